@@ -1,0 +1,173 @@
+/*
+ * nnp.h - C ABI of the MI355X (gfx950) neural-network-potential library.
+ *
+ * The library evaluates an ANI-style high-dimensional neural network
+ * potential (Deep-HP paper, arXiv 2207.14276): the total energy is the sum
+ * of atomic energies, each produced by the network of the atom's element from
+ * its atomic environment vector (AEV) (section "Neural Network Potentials",
+ * energy-decomposition equation); the AEV is built from radial and angular
+ * symmetry functions with a cosine cutoff (section "ANI models", cutoff,
+ * radial and angular equations) over a cell-list neighbour search
+ * (section "Massive Parallelism within Tinker-HP"); forces are the analytic
+ * negative gradient of the energy.  Device data crosses this boundary as raw
+ * addresses with no copies (section "A General Machine Learning Platform").
+ *
+ * Conventions for every call:
+ *   - All functions return NNP_OK (0) on success and a negative NNP_E* code on
+ *     failure; none throws.  nnp_last_error() then holds a message for the
+ *     calling thread.
+ *   - "DEVICE" pointers are HIP device allocations on the model's device
+ *     (e.g. torch tensors' data_ptr()); "HOST" pointers are host memory that
+ *     the call reads before it returns.
+ *   - Work is enqueued on `stream` (a hipStream_t; NULL = default stream) and
+ *     the call returns without waiting for it; outputs are valid once the
+ *     stream reaches that point.  The caller keeps every device buffer alive
+ *     until then.
+ *   - A model is used by one host thread at a time.
+ */
+#ifndef NNP_H
+#define NNP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  NNP_OK = 0,
+  NNP_EINVAL = -1,       /* bad argument (null pointer, bad offsets, ...) */
+  NNP_ENOMEM = -2,       /* device or pinned host allocation failed */
+  NNP_ECAPACITY = -3,    /* a neighbour list overflowed its capacity */
+  NNP_EDEVICE = -4,      /* a HIP runtime error; message carries its text */
+  NNP_ESPECIES = -5,     /* an atom's species index is outside the model */
+  NNP_EUNSUPPORTED = -6  /* a valid description this build does not run */
+};
+
+enum { NNP_FP32 = 0, NNP_BF16 = 1 };
+
+typedef struct nnp_model nnp_model; /* opaque, library-owned */
+
+/* AEV hyper-parameters (section "ANI models").  The radial term of
+ * neighbour j at distance R is radial_scale * exp(-eta_rad (R - Rs)^2) fc(R)
+ * with fc(R) = 0.5 cos(pi R / rc) + 0.5 for R < rc, else 0.  The angular term
+ * of an unordered neighbour pair {j, k} inside rc_ang is
+ * 2^(1-zeta) (1 + cos(theta_ijk - theta_s))^zeta
+ *   * exp(-eta_ang ((R_ij + R_ik)/2 - Rs)^2) fc(R_ij) fc(R_ik).
+ * Feature layout: radial block of neighbour species s at s*n_shf_rad + m;
+ * angular block of the species pair (a <= b), numbered row by row through the
+ * upper triangle, at n_species*n_shf_rad + pair*(n_shf_ang*n_shf_z)
+ * + r*n_shf_z + z.  Host arrays, copied at creation.
+ * This build runs n_shf_rad = 16, n_shf_ang = 4, n_shf_z = 8, n_species <= 7
+ * and rc_ang <= rc_rad; other values give NNP_EUNSUPPORTED. */
+typedef struct {
+  int n_species;
+  float rc_rad, eta_rad;
+  int n_shf_rad;
+  const float *shf_rad;
+  float rc_ang, eta_ang, zeta;
+  int n_shf_ang;
+  const float *shf_ang;
+  int n_shf_z;
+  const float *shf_z; /* angle shifts theta_s, radians */
+  float radial_scale;
+} nnp_aev_params;
+
+/* A set of element networks (section "Neural Network Potentials").  Each
+ * species s has n_layers[s] fully connected layers; hidden layers apply
+ * CELU(z) = max(0, z) + min(0, alpha (exp(z / alpha) - 1)); the last layer
+ * has one output, the atomic energy.  With n_ensemble > 1 the atomic energy
+ * is the mean over the ensemble members.
+ *   widths:  per species, n_layers[s] + 1 widths, concatenated; the first is
+ *            the AEV length, the last is 1.  All species must have the same
+ *            number of layers in this build.
+ *   weights: float32, concatenated over (member, species, layer), each layer
+ *            as W[out][in] row-major followed by b[out].
+ * All arrays are HOST memory, copied by nnp_create (the caller may free them
+ * afterwards).  precision = NNP_FP32 runs the dense layers in float32;
+ * NNP_BF16 rounds their operands to bfloat16 and accumulates in float32; AEV,
+ * forces and per-atom energies stay float32 and the per-system energy and
+ * virial sums are float64 in both. */
+typedef struct {
+  nnp_aev_params aev;
+  int n_ensemble;
+  const int *n_layers;
+  const int *widths;
+  const float *weights;
+  float celu_alpha;
+  int precision;
+} nnp_model_desc;
+
+/* Builds a model on the current HIP device. *out receives the handle. */
+int nnp_create(const nnp_model_desc *desc, nnp_model **out);
+void nnp_destroy(nnp_model *model);
+
+/* Pre-sizes the library workspace (the paper's bounded up-front buffer,
+ * section "Massive Parallelism within Tinker-HP") for calls of up to
+ * max_atoms atoms and max_systems systems, and sets the per-atom neighbour
+ * list capacity (0 keeps the current one; default 256).  Without it the
+ * workspace grows on demand, which synchronizes the device. */
+int nnp_reserve(nnp_model *model, int64_t max_atoms, int max_systems, int nbr_capacity);
+
+/* Energy and forces of a batch of independent systems.
+ *   n_systems      >= 1
+ *   batch_offsets  HOST int64[n_systems + 1]; offsets[0] = 0, non-decreasing;
+ *                  system s owns atoms [offsets[s], offsets[s+1]).
+ *   coords         DEVICE float32[N][3], Angstrom, N = offsets[n_systems].
+ *   species        DEVICE int32[N], slot index < n_species.  An index outside
+ *                  the model sets a device flag that nnp_status reports as
+ *                  NNP_ESPECIES; that call's outputs are then undefined.
+ *   box            HOST float32[n_systems][3]: orthorhombic box lengths of a
+ *                  periodic system, or 0,0,0 for a non-periodic one.  Every
+ *                  periodic image inside the cutoff is a neighbour, so boxes
+ *                  smaller than twice the cutoff are valid.
+ *   energy         DEVICE float64[n_systems] out, kcal/mol.
+ *   forces         DEVICE float32[N][3] out, kcal/mol/A, or NULL for energy
+ *                  only (skips the backward pass).
+ *   virial         DEVICE float64[n_systems][9] out, row-major
+ *                  W = -sum over neighbour terms of d (x) dE/dd (equal to
+ *                  sum_i r_i (x) F_i for a non-periodic system), or NULL.
+ *                  Requires forces != NULL.
+ *   atom_energy    DEVICE float32[N] out (ensemble-mean atomic energies), or
+ *                  NULL.
+ * Neighbour-list overflow sets a device flag (nnp_status -> NNP_ECAPACITY). */
+int nnp_energy_forces(nnp_model *model, int n_systems, const int64_t *batch_offsets,
+                      const float *coords, const int32_t *species, const float *box,
+                      double *energy, float *forces, double *virial, float *atom_energy,
+                      void *stream);
+
+/* Same inputs; writes the AEV of every atom, DEVICE float32[N][aev_dim],
+ * atom order.  For tests and inspection. */
+int nnp_debug_aev(nnp_model *model, int n_systems, const int64_t *batch_offsets,
+                  const float *coords, const int32_t *species, const float *box,
+                  float *aev_out, void *stream);
+
+/* Same inputs; writes the neighbour lists the last build produced:
+ * DEVICE int32[N] counts and DEVICE int32[N][capacity][4] entries
+ * (j, image x, image y, image z), up to `capacity` per atom.  For tests. */
+int nnp_debug_neighbors(nnp_model *model, int n_systems, const int64_t *batch_offsets,
+                        const float *coords, const int32_t *species, const float *box,
+                        int32_t *counts, int32_t *entries, int capacity, void *stream);
+
+/* Waits for `stream` and returns the device flags raised since the last
+ * nnp_status call (NNP_ECAPACITY, NNP_ESPECIES) or NNP_OK; clears them.
+ * *max_neighbors (nullable) receives the largest neighbour count seen. */
+int nnp_status(nnp_model *model, void *stream, int *max_neighbors);
+
+/* AEV length of the model (1008 for 7 species). */
+int nnp_aev_dim(const nnp_model *model);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *nnp_last_error(void);
+
+/* Enables per-stage timing (HIP events; adds a wait in nnp_stage_timings).
+ * nnp_stage_timings writes up to n stage durations of the last call in ms
+ * and their names, returns the number of stages. */
+int nnp_set_timing(nnp_model *model, int enable);
+int nnp_stage_timings(nnp_model *model, float *ms_out, const char **names_out, int n);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NNP_H */

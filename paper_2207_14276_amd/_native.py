@@ -1,0 +1,97 @@
+"""ctypes binding of libnnp.so (include/nnp.h), argument marshalling only.
+
+The functions here carry the C names.  Every step of the computation runs in
+the HIP library; there is no CPU fallback: if the library is missing this
+module raises on first use.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "lib", "libnnp.so")
+
+NNP_OK = 0
+NNP_EINVAL = -1
+NNP_ENOMEM = -2
+NNP_ECAPACITY = -3
+NNP_EDEVICE = -4
+NNP_ESPECIES = -5
+NNP_EUNSUPPORTED = -6
+NNP_FP32 = 0
+NNP_BF16 = 1
+
+_ERR_NAMES = {NNP_EINVAL: "EINVAL", NNP_ENOMEM: "ENOMEM", NNP_ECAPACITY: "ECAPACITY",
+              NNP_EDEVICE: "EDEVICE", NNP_ESPECIES: "ESPECIES",
+              NNP_EUNSUPPORTED: "EUNSUPPORTED"}
+
+
+class NNPError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"nnp error {_ERR_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class nnp_aev_params(C.Structure):
+    _fields_ = [("n_species", C.c_int),
+                ("rc_rad", C.c_float), ("eta_rad", C.c_float),
+                ("n_shf_rad", C.c_int), ("shf_rad", C.POINTER(C.c_float)),
+                ("rc_ang", C.c_float), ("eta_ang", C.c_float), ("zeta", C.c_float),
+                ("n_shf_ang", C.c_int), ("shf_ang", C.POINTER(C.c_float)),
+                ("n_shf_z", C.c_int), ("shf_z", C.POINTER(C.c_float)),
+                ("radial_scale", C.c_float)]
+
+
+class nnp_model_desc(C.Structure):
+    _fields_ = [("aev", nnp_aev_params),
+                ("n_ensemble", C.c_int),
+                ("n_layers", C.POINTER(C.c_int)),
+                ("widths", C.POINTER(C.c_int)),
+                ("weights", C.POINTER(C.c_float)),
+                ("celu_alpha", C.c_float),
+                ("precision", C.c_int)]
+
+
+EXPORTS = ["nnp_create", "nnp_destroy", "nnp_reserve", "nnp_energy_forces", "nnp_debug_aev",
+           "nnp_debug_neighbors", "nnp_status", "nnp_aev_dim", "nnp_last_error",
+           "nnp_set_timing", "nnp_stage_timings"]
+
+_lib = None
+
+
+def load():
+    """Loads libnnp.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                           "`python -m paper_2207_14276_amd.build` (there is no fallback path)")
+    lib = C.CDLL(LIB_PATH)
+    vp, i64p = C.c_void_p, C.POINTER(C.c_int64)
+    fp = C.POINTER(C.c_float)
+    lib.nnp_create.argtypes = [C.POINTER(nnp_model_desc), C.POINTER(C.c_void_p)]
+    lib.nnp_destroy.argtypes = [vp]
+    lib.nnp_destroy.restype = None
+    lib.nnp_reserve.argtypes = [vp, C.c_int64, C.c_int, C.c_int]
+    lib.nnp_energy_forces.argtypes = [vp, C.c_int, i64p, vp, vp, fp, vp, vp, vp, vp, vp]
+    lib.nnp_debug_aev.argtypes = [vp, C.c_int, i64p, vp, vp, fp, vp, vp]
+    lib.nnp_debug_neighbors.argtypes = [vp, C.c_int, i64p, vp, vp, fp, vp, vp, C.c_int, vp]
+    lib.nnp_status.argtypes = [vp, vp, C.POINTER(C.c_int)]
+    lib.nnp_aev_dim.argtypes = [vp]
+    lib.nnp_last_error.restype = C.c_char_p
+    lib.nnp_set_timing.argtypes = [vp, C.c_int]
+    lib.nnp_stage_timings.argtypes = [vp, fp, C.POINTER(C.c_char_p), C.c_int]
+    _lib = lib
+    return lib
+
+
+def check(rc):
+    if rc < 0:
+        raise NNPError(rc, load().nnp_last_error().decode())
+    return rc
+
+
+def last_error() -> str:
+    return load().nnp_last_error().decode()

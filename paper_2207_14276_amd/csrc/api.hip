@@ -1,0 +1,631 @@
+// C ABI (include/nnp.h): model creation, workspace, and the stage order of
+// one energy/force evaluation.  Host code only orchestrates: every step of
+// the path runs in the library's kernels on the caller's stream.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/nnp.h"
+#include "internal.h"
+
+using namespace nnp;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                   \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return fail(NNP_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));          \
+  } while (0)
+
+// A device buffer that only grows.
+struct DevBuf {
+  void *p = nullptr;
+  size_t bytes = 0;
+  int ensure(size_t need) {
+    if (need <= bytes) return NNP_OK;
+    if (p) {
+      hipError_t e = hipFree(p);
+      if (e != hipSuccess) return fail(NNP_EDEVICE, "hipFree: %s", hipGetErrorString(e));
+      p = nullptr;
+      bytes = 0;
+    }
+    size_t nb = need + need / 4 + 256;
+    hipError_t e = hipMalloc(&p, nb);
+    if (e != hipSuccess) {
+      p = nullptr;
+      (void)hipGetLastError();
+      return fail(NNP_ENOMEM, "hipMalloc(%zu) failed: %s", nb, hipGetErrorString(e));
+    }
+    bytes = nb;
+    return NNP_OK;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  template <class T> T *as() const { return (T *)p; }
+};
+
+constexpr int kStages = 8;
+const char *kStageNames[kStages] = {"ingest", "cells", "neighbours", "buckets",
+                                    "aev_fwd", "mlp", "aev_bwd", "reduce"};
+
+}  // namespace
+
+struct LayerW {
+  float *W = nullptr;       // [out][in] float32
+  float *Wt = nullptr;      // [in][out] float32
+  uint16_t *Wb = nullptr;   // [out][in] bf16
+  uint16_t *Wtb = nullptr;  // [in][out] bf16
+  float *b = nullptr;
+  int n_in = 0, n_out = 0;
+};
+
+struct nnp_model {
+  int device = 0;
+  int S = 0, M = 1, L = 1;
+  int precision = NNP_FP32;
+  float alpha = 0.1f;
+  AevConst aev{};
+  std::vector<std::vector<int>> widths;  // [S][L+1]
+  std::vector<int> ldH;                  // [L-1] max width of hidden layer l
+  std::vector<LayerW> layers;            // [(M * S + s) * L + l]
+  std::vector<void *> weight_allocs;
+  int cap = 256;                         // neighbour capacity per atom
+
+  // workspace
+  DevBuf pos, sys_of, atom_cell, atom_slot, cell_count, cell_start, cell_atoms, nbr, nbr_cnt;
+  DevBuf block_counts, bucket_off, bucket_cnt, perm, row_of_atom, G, dG, e_atom, W_atom, partial;
+  DevBuf sysdesc, chunk_sys, chunk_begin, sys_chunk_off, status;
+  std::vector<DevBuf> H, Gd;
+  // host staging (pinned) for per-call descriptors
+  void *stage = nullptr;
+  size_t stage_bytes = 0;
+  hipEvent_t stage_done = nullptr;
+  bool stage_pending = false;
+  // timing
+  bool timing = false;
+  hipEvent_t ev[kStages + 1] = {};
+  int last_stages = 0;
+
+  LayerW &layer(int m, int s, int l) { return layers[((size_t)m * S + s) * L + l]; }
+};
+
+static void round_bf16_host(const float *src, uint16_t *dst, size_t n) {
+  for (size_t i = 0; i < n; ++i) {
+    uint32_t u;
+    memcpy(&u, &src[i], 4);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    dst[i] = (uint16_t)(u >> 16);
+  }
+}
+
+static int upload(nnp_model *m, const void *host, size_t bytes, void **dev) {
+  HIP_TRY(hipMalloc(dev, bytes));
+  m->weight_allocs.push_back(*dev);
+  HIP_TRY(hipMemcpy(*dev, host, bytes, hipMemcpyHostToDevice));
+  return NNP_OK;
+}
+
+extern "C" const char *nnp_last_error(void) { return g_err.c_str(); }
+
+extern "C" void nnp_destroy(nnp_model *m) {
+  if (!m) return;
+  (void)hipSetDevice(m->device);
+  (void)hipDeviceSynchronize();
+  for (void *p : m->weight_allocs) (void)hipFree(p);
+  DevBuf *bufs[] = {&m->pos, &m->sys_of, &m->atom_cell, &m->atom_slot, &m->cell_count,
+                    &m->cell_start, &m->cell_atoms, &m->nbr, &m->nbr_cnt, &m->block_counts,
+                    &m->bucket_off, &m->bucket_cnt, &m->perm, &m->row_of_atom, &m->G, &m->dG,
+                    &m->e_atom, &m->W_atom, &m->partial, &m->sysdesc, &m->chunk_sys,
+                    &m->chunk_begin, &m->sys_chunk_off, &m->status};
+  for (DevBuf *b : bufs) b->release();
+  for (auto &b : m->H) b.release();
+  for (auto &b : m->Gd) b.release();
+  if (m->stage) (void)hipHostFree(m->stage);
+  if (m->stage_done) (void)hipEventDestroy(m->stage_done);
+  for (auto &e : m->ev)
+    if (e) (void)hipEventDestroy(e);
+  delete m;
+}
+
+static int create_impl(const nnp_model_desc *d, nnp_model *m) {
+  const nnp_aev_params &a = d->aev;
+  if (a.n_species < 1 || a.n_species > kMaxSpecies)
+    return fail(NNP_EUNSUPPORTED, "n_species must be in 1..%d (got %d)", kMaxSpecies, a.n_species);
+  if (a.n_shf_rad != kNShfRad || a.n_shf_ang != kNShfAng || a.n_shf_z != kNShfZ)
+    return fail(NNP_EUNSUPPORTED, "this build runs 16 radial, 4 angular-radial and 8 angle shifts");
+  if (!a.shf_rad || !a.shf_ang || !a.shf_z) return fail(NNP_EINVAL, "null shift array");
+  if (!(a.rc_rad > 0.f) || !(a.rc_ang > 0.f) || a.rc_ang > a.rc_rad)
+    return fail(NNP_EUNSUPPORTED, "need 0 < rc_ang <= rc_rad");
+  if (!(a.zeta >= 1.f)) return fail(NNP_EUNSUPPORTED, "zeta must be >= 1");
+  if (d->n_ensemble < 1) return fail(NNP_EINVAL, "n_ensemble must be >= 1");
+  if (!d->n_layers || !d->widths || !d->weights) return fail(NNP_EINVAL, "null network array");
+  if (d->precision != NNP_FP32 && d->precision != NNP_BF16) return fail(NNP_EINVAL, "bad precision");
+  if (!(d->celu_alpha > 0.f)) return fail(NNP_EINVAL, "celu_alpha must be > 0");
+  const int S = a.n_species;
+  m->S = S;
+  m->M = d->n_ensemble;
+  m->precision = d->precision;
+  m->alpha = d->celu_alpha;
+  AevConst &c = m->aev;
+  c.rc_r = a.rc_rad; c.eta_r = a.eta_rad; c.rc_a = a.rc_ang; c.eta_a = a.eta_ang;
+  c.zeta = a.zeta; c.scale = a.radial_scale;
+  for (int k = 0; k < kNShfRad; ++k) c.shf_r[k] = a.shf_rad[k];
+  for (int k = 0; k < kNShfAng; ++k) c.shf_a[k] = a.shf_ang[k];
+  for (int k = 0; k < kNShfZ; ++k) {
+    c.cz[k] = (float)std::cos((double)a.shf_z[k]);
+    c.sz[k] = (float)std::sin((double)a.shf_z[k]);
+  }
+  c.S = S;
+  c.rad_len = S * kNShfRad;
+  c.D = c.rad_len + S * (S + 1) / 2 * kAngBlock;
+  const int L = d->n_layers[0];
+  if (L < 1) return fail(NNP_EINVAL, "n_layers must be >= 1");
+  for (int s = 0; s < S; ++s)
+    if (d->n_layers[s] != L)
+      return fail(NNP_EUNSUPPORTED, "all species must have the same number of layers");
+  m->L = L;
+  m->widths.assign(S, std::vector<int>(L + 1));
+  for (int s = 0; s < S; ++s)
+    for (int l = 0; l <= L; ++l) {
+      int w = d->widths[s * (L + 1) + l];
+      if (w < 1) return fail(NNP_EINVAL, "width must be >= 1");
+      if (l > 0 && l < L && w % 8 != 0)
+        return fail(NNP_EUNSUPPORTED, "hidden widths must be multiples of 8");
+      m->widths[s][l] = w;
+    }
+  for (int s = 0; s < S; ++s) {
+    if (m->widths[s][0] != c.D) return fail(NNP_EINVAL, "first width must be the AEV length %d", c.D);
+    if (m->widths[s][L] != 1) return fail(NNP_EINVAL, "last width must be 1");
+  }
+  m->ldH.assign(std::max(L - 1, 0), 0);
+  for (int l = 0; l + 1 < L; ++l)
+    for (int s = 0; s < S; ++s) m->ldH[l] = std::max(m->ldH[l], m->widths[s][l + 1]);
+  m->H.resize(std::max(L - 1, 0));
+  m->Gd.resize(std::max(L - 1, 0));
+
+  HIP_TRY(hipGetDevice(&m->device));
+  m->layers.resize((size_t)m->M * S * L);
+  const float *wp = d->weights;
+  std::vector<float> tmp;
+  std::vector<uint16_t> tb;
+  for (int mb = 0; mb < m->M; ++mb)
+    for (int s = 0; s < S; ++s)
+      for (int l = 0; l < L; ++l) {
+        LayerW &lw = m->layer(mb, s, l);
+        lw.n_in = m->widths[s][l];
+        lw.n_out = m->widths[s][l + 1];
+        size_t nw = (size_t)lw.n_in * lw.n_out;
+        int rc;
+        if ((rc = upload(m, wp, nw * 4, (void **)&lw.W))) return rc;
+        tmp.resize(nw);
+        for (int o = 0; o < lw.n_out; ++o)
+          for (int k = 0; k < lw.n_in; ++k) tmp[(size_t)k * lw.n_out + o] = wp[(size_t)o * lw.n_in + k];
+        if ((rc = upload(m, tmp.data(), nw * 4, (void **)&lw.Wt))) return rc;
+        if (m->precision == NNP_BF16) {
+          tb.resize(nw);
+          round_bf16_host(wp, tb.data(), nw);
+          if ((rc = upload(m, tb.data(), nw * 2, (void **)&lw.Wb))) return rc;
+          round_bf16_host(tmp.data(), tb.data(), nw);
+          if ((rc = upload(m, tb.data(), nw * 2, (void **)&lw.Wtb))) return rc;
+        }
+        wp += nw;
+        if ((rc = upload(m, wp, (size_t)lw.n_out * 4, (void **)&lw.b))) return rc;
+        wp += lw.n_out;
+      }
+  HIP_TRY(hipEventCreateWithFlags(&m->stage_done, hipEventDisableTiming));
+  for (auto &e : m->ev) HIP_TRY(hipEventCreate(&e));
+  int rc = m->status.ensure(2 * sizeof(int));
+  if (rc) return rc;
+  HIP_TRY(hipMemset(m->status.p, 0, 2 * sizeof(int)));
+  return NNP_OK;
+}
+
+extern "C" int nnp_create(const nnp_model_desc *d, nnp_model **out) {
+  if (!d || !out) return fail(NNP_EINVAL, "null argument");
+  *out = nullptr;
+  nnp_model *m = new nnp_model();
+  int rc = create_impl(d, m);
+  if (rc != NNP_OK) {
+    nnp_destroy(m);
+    return rc;
+  }
+  *out = m;
+  return NNP_OK;
+}
+
+extern "C" int nnp_aev_dim(const nnp_model *m) { return m ? m->aev.D : NNP_EINVAL; }
+
+// Buffers for a call of N atoms, S systems, C cells and n_chunks chunks.
+static int ensure_ws(nnp_model *m, int64_t N, int S, int64_t C, int n_chunks) {
+  const int64_t rows = (N + kTileM - 1) / kTileM * kTileM + (int64_t)m->S * kTileM;
+  const int nblk = (int)((N + 1023) / 1024);
+  int rc;
+#define ENS(buf, bytes) if ((rc = (buf).ensure((size_t)(bytes)))) return rc
+  ENS(m->pos, N * 16);
+  ENS(m->sys_of, N * 4);
+  ENS(m->atom_cell, N * 4);
+  ENS(m->atom_slot, N * 4);
+  ENS(m->cell_count, C * 4 + 4);
+  ENS(m->cell_start, C * 4 + 8);
+  ENS(m->cell_atoms, N * 4);
+  ENS(m->nbr, N * (int64_t)m->cap * 8);
+  ENS(m->nbr_cnt, N * 4);
+  ENS(m->block_counts, (int64_t)std::max(nblk, 1) * kMaxSpecies * 4);
+  ENS(m->bucket_off, (kMaxSpecies + 1) * 4);
+  ENS(m->bucket_cnt, kMaxSpecies * 4);
+  ENS(m->perm, rows * 4);
+  ENS(m->row_of_atom, N * 4);
+  ENS(m->G, rows * m->aev.D * 4);
+  ENS(m->dG, rows * m->aev.D * 4);
+  ENS(m->e_atom, N * 4);
+  ENS(m->W_atom, N * 36);
+  ENS(m->partial, (int64_t)n_chunks * 80 + 80);
+  ENS(m->sysdesc, (int64_t)S * sizeof(SysDesc));
+  ENS(m->chunk_sys, (int64_t)n_chunks * 4 + 4);
+  ENS(m->chunk_begin, (int64_t)n_chunks * 4 + 4);
+  ENS(m->sys_chunk_off, (int64_t)(S + 1) * 4);
+  for (int l = 0; l + 1 < m->L; ++l) {
+    ENS(m->H[l], rows * m->ldH[l] * 4);
+    ENS(m->Gd[l], rows * m->ldH[l] * 4);
+  }
+#undef ENS
+  return NNP_OK;
+}
+
+extern "C" int nnp_reserve(nnp_model *m, int64_t max_atoms, int max_systems, int nbr_capacity) {
+  if (!m || max_atoms < 0 || max_systems < 0 || nbr_capacity < 0)
+    return fail(NNP_EINVAL, "bad reserve arguments");
+  HIP_TRY(hipSetDevice(m->device));
+  if (nbr_capacity > 0) {
+    if (nbr_capacity > 1024) return fail(NNP_EUNSUPPORTED, "neighbour capacity above 1024");
+    int cap = (nbr_capacity + 3) / 4 * 4;
+    if (cap != m->cap) {
+      m->cap = cap;
+      m->nbr.release();
+    }
+  }
+  // cells: at most one per atom for non-periodic systems; periodic grids are
+  // sized per call
+  int n_chunks = (int)(max_atoms / 4096) + max_systems + 1;
+  return ensure_ws(m, max_atoms, std::max(max_systems, 1), max_atoms + max_systems, n_chunks);
+}
+
+extern "C" int nnp_set_timing(nnp_model *m, int enable) {
+  if (!m) return fail(NNP_EINVAL, "null model");
+  m->timing = enable != 0;
+  return NNP_OK;
+}
+
+extern "C" int nnp_stage_timings(nnp_model *m, float *ms, const char **names, int n) {
+  if (!m) return fail(NNP_EINVAL, "null model");
+  if (!m->timing || m->last_stages == 0) return 0;
+  HIP_TRY(hipEventSynchronize(m->ev[m->last_stages]));
+  int k = std::min(n, m->last_stages);
+  for (int q = 0; q < k; ++q) {
+    if (ms) HIP_TRY(hipEventElapsedTime(&ms[q], m->ev[q], m->ev[q + 1]));
+    if (names) names[q] = kStageNames[q];
+  }
+  return k;
+}
+
+extern "C" int nnp_status(nnp_model *m, void *stream, int *max_nbr) {
+  if (!m) return fail(NNP_EINVAL, "null model");
+  hipStream_t st = (hipStream_t)stream;
+  HIP_TRY(hipSetDevice(m->device));
+  HIP_TRY(hipStreamSynchronize(st));
+  int h[2] = {0, 0};
+  HIP_TRY(hipMemcpy(h, m->status.p, sizeof h, hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemset(m->status.p, 0, sizeof h));
+  if (max_nbr) *max_nbr = h[1];
+  if (h[0] & kStatBadSpecies) return fail(NNP_ESPECIES, "an atom's species index is outside the model");
+  if (h[0] & kStatOverflow)
+    return fail(NNP_ECAPACITY, "neighbour list overflow: %d neighbours, capacity %d", h[1], m->cap);
+  return NNP_OK;
+}
+
+enum Mode { kFull = 0, kAev = 1, kNbr = 2 };
+
+struct CallOut {
+  double *energy = nullptr;
+  float *forces = nullptr;
+  double *virial = nullptr;
+  float *atom_energy = nullptr;
+  float *aev = nullptr;
+  int *nb_counts = nullptr;
+  int *nb_entries = nullptr;
+  int nb_cap = 0;
+};
+
+static int run(nnp_model *m, int n_sys, const int64_t *offs, const float *coords,
+               const int32_t *species, const float *box, const CallOut &o, hipStream_t st, Mode mode) {
+  if (!m) return fail(NNP_EINVAL, "null model");
+  if (n_sys < 1) return fail(NNP_EINVAL, "n_systems must be >= 1");
+  if (!offs || !box) return fail(NNP_EINVAL, "null host array (batch_offsets / box)");
+  if (offs[0] != 0) return fail(NNP_EINVAL, "batch_offsets[0] must be 0");
+  for (int s = 0; s < n_sys; ++s)
+    if (offs[s + 1] < offs[s]) return fail(NNP_EINVAL, "batch_offsets must be non-decreasing");
+  const int64_t N64 = offs[n_sys];
+  if (N64 > (int64_t)1 << 28) return fail(NNP_EUNSUPPORTED, "more than 2^28 atoms in one call");
+  const int N = (int)N64;
+  if (N > 0 && (!coords || !species)) return fail(NNP_EINVAL, "null coords / species");
+  if (mode == kFull && !o.energy) return fail(NNP_EINVAL, "null energy");
+  if (mode == kFull && o.virial && !o.forces) return fail(NNP_EINVAL, "virial needs forces");
+  HIP_TRY(hipSetDevice(m->device));
+
+  const float rc_list = m->aev.rc_r;
+  const float rc_cell = rc_list * (1.0f + 1e-5f);
+  std::vector<SysDesc> sd(n_sys);
+  int64_t C = 0;
+  std::vector<int> ch_sys, ch_begin, sys_ch(n_sys + 1);
+  for (int s = 0; s < n_sys; ++s) {
+    SysDesc &d = sd[s];
+    memset(&d, 0, sizeof d);
+    const float *b = box + 3 * s;
+    bool per = b[0] > 0.f || b[1] > 0.f || b[2] > 0.f;
+    if (!(b[0] >= 0.f && b[1] >= 0.f && b[2] >= 0.f) || (per && !(b[0] > 0.f && b[1] > 0.f && b[2] > 0.f)))
+      return fail(NNP_EINVAL, "system %d: box must be three positive lengths or all zero", s);
+    d.atom_off = (int)offs[s];
+    d.n = (int)(offs[s + 1] - offs[s]);
+    d.periodic = per ? 1 : 0;
+    d.cell_off = (int)C;
+    if (per && (b[0] < 0.25f * rc_list || b[1] < 0.25f * rc_list || b[2] < 0.25f * rc_list))
+      return fail(NNP_EUNSUPPORTED, "system %d: periodic box edge below a quarter of the cutoff", s);
+    if (per) {
+      int64_t cells = 1;
+      for (int k = 0; k < 3; ++k) {
+        d.L[k] = b[k];
+        int nc = std::max(1, (int)std::floor(b[k] / rc_cell));
+        nc = std::min(nc, 1024);
+        d.nc[k] = nc;
+        d.edge[k] = b[k] / nc;
+        d.origin[k] = 0.f;
+        cells *= nc;
+      }
+      if (cells > ((int64_t)1 << 26)) return fail(NNP_EUNSUPPORTED, "system %d: too many cells", s);
+      d.cell_cap = (int)cells;
+    } else {
+      d.cell_cap = std::max(1, d.n);
+    }
+    C += d.cell_cap;
+    sys_ch[s] = (int)ch_sys.size();
+    for (int b0 = d.atom_off; b0 < d.atom_off + d.n; b0 += 4096) {
+      ch_sys.push_back(s);
+      ch_begin.push_back(b0);
+    }
+  }
+  sys_ch[n_sys] = (int)ch_sys.size();
+  const int n_chunks = (int)ch_sys.size();
+  if (C > ((int64_t)1 << 28)) return fail(NNP_EUNSUPPORTED, "too many cells");
+  int rc = ensure_ws(m, N, n_sys, C, n_chunks);
+  if (rc) return rc;
+
+  // stage the per-call descriptors through pinned memory
+  size_t off_sd = 0, off_cs = off_sd + sizeof(SysDesc) * n_sys;
+  size_t off_cb = off_cs + 4 * (size_t)n_chunks, off_so = off_cb + 4 * (size_t)n_chunks;
+  size_t total = off_so + 4 * (size_t)(n_sys + 1);
+  if (m->stage_pending) {
+    HIP_TRY(hipEventSynchronize(m->stage_done));
+    m->stage_pending = false;
+  }
+  if (total > m->stage_bytes) {
+    if (m->stage) HIP_TRY(hipHostFree(m->stage));
+    m->stage = nullptr;
+    size_t nb = total + total / 2 + 4096;
+    HIP_TRY(hipHostMalloc(&m->stage, nb, hipHostMallocDefault));
+    m->stage_bytes = nb;
+  }
+  char *hs = (char *)m->stage;
+  memcpy(hs + off_sd, sd.data(), sizeof(SysDesc) * n_sys);
+  if (n_chunks) {
+    memcpy(hs + off_cs, ch_sys.data(), 4 * (size_t)n_chunks);
+    memcpy(hs + off_cb, ch_begin.data(), 4 * (size_t)n_chunks);
+  }
+  memcpy(hs + off_so, sys_ch.data(), 4 * (size_t)(n_sys + 1));
+  HIP_TRY(hipMemcpyAsync(m->sysdesc.p, hs + off_sd, sizeof(SysDesc) * n_sys, hipMemcpyHostToDevice, st));
+  if (n_chunks) {
+    HIP_TRY(hipMemcpyAsync(m->chunk_sys.p, hs + off_cs, 4 * (size_t)n_chunks, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(m->chunk_begin.p, hs + off_cb, 4 * (size_t)n_chunks, hipMemcpyHostToDevice, st));
+  }
+  HIP_TRY(hipMemcpyAsync(m->sys_chunk_off.p, hs + off_so, 4 * (size_t)(n_sys + 1), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipEventRecord(m->stage_done, st));
+  m->stage_pending = true;
+
+  int stage = 0;
+  auto mark = [&]() {
+    if (m->timing && mode == kFull) (void)hipEventRecord(m->ev[stage++], st);
+  };
+  mark();
+  SysDesc *dsys = m->sysdesc.as<SysDesc>();
+  int *status = m->status.as<int>();
+  float4 *pos = m->pos.as<float4>();
+  launch_ingest(coords, species, dsys, n_sys, N, m->S, pos, m->sys_of.as<int>(), status, st);
+  mark();
+  launch_grid(dsys, n_sys, pos, m->cell_count.as<int>(), rc_list, st);
+  launch_cell_count(pos, m->sys_of.as<int>(), dsys, N, m->cell_count.as<int>(), m->atom_cell.as<int>(),
+                    m->atom_slot.as<int>(), st);
+  launch_scan(m->cell_count.as<int>(), m->cell_start.as<int>(), (int)C, st);
+  launch_cell_scatter(m->atom_cell.as<int>(), m->atom_slot.as<int>(), m->cell_start.as<int>(), N,
+                      m->cell_atoms.as<int>(), st);
+  launch_cell_sort(m->cell_start.as<int>(), (int)C, m->cell_atoms.as<int>(), st);
+  mark();
+  launch_nbr_build(pos, m->sys_of.as<int>(), dsys, m->cell_start.as<int>(), m->cell_atoms.as<int>(), N,
+                   rc_list, m->cap, m->nbr.as<int2>(), m->nbr_cnt.as<int>(), status, st);
+  if (mode == kNbr) {
+    launch_export_nbr(m->nbr.as<int2>(), m->nbr_cnt.as<int>(), m->cap, N, o.nb_counts, o.nb_entries,
+                      o.nb_cap, st);
+    HIP_TRY(hipGetLastError());
+    return NNP_OK;
+  }
+  mark();
+  const int nblk = (N + 1023) / 1024;
+  const int rows = (N + kTileM - 1) / kTileM * kTileM + m->S * kTileM;
+  launch_species_bucket(pos, N, m->S, m->block_counts.as<int>(), nblk, m->bucket_off.as<int>(),
+                        m->bucket_cnt.as<int>(), m->perm.as<int>(), m->row_of_atom.as<int>(), rows, st);
+  mark();
+  const int D = m->aev.D;
+  launch_aev_fwd(pos, m->sys_of.as<int>(), dsys, m->nbr.as<int2>(), m->nbr_cnt.as<int>(), m->cap,
+                 m->row_of_atom.as<int>(), m->G.as<float>(), D, N, m->aev, st);
+  if (mode == kAev) {
+    launch_gather_rows(m->G.as<float>(), D, m->row_of_atom.as<int>(), N, D, o.aev, st);
+    HIP_TRY(hipGetLastError());
+    return NNP_OK;
+  }
+  mark();
+
+  // element networks: forward, output layer, backward to dE/dG
+  const bool want_grad = o.forces != nullptr;
+  const bool bf16 = m->precision == NNP_BF16;
+  const int row_tiles = rows / kTileM;
+  const int L = m->L;
+  for (int mb = 0; mb < m->M; ++mb) {
+    for (int l = 0; l + 1 < L; ++l) {
+      GemmLaunch gl{};
+      gl.A = l == 0 ? m->G.as<float>() : m->H[l - 1].as<float>();
+      gl.lda = l == 0 ? D : m->ldH[l - 1];
+      gl.C = m->H[l].as<float>();
+      gl.ldc = m->ldH[l];
+      gl.bucket_off = m->bucket_off.as<int>();
+      gl.n_groups = m->S;
+      gl.alpha = m->alpha;
+      gl.scale = 1.f;
+      for (int s = 0; s < m->S; ++s) {
+        LayerW &lw = m->layer(mb, s, l);
+        gl.g[s].B = bf16 ? (const void *)lw.Wb : (const void *)lw.W;
+        gl.g[s].bias = lw.b;
+        gl.g[s].n_out = lw.n_out;
+        gl.g[s].K = lw.n_in;
+      }
+      launch_gemm(kEpiFwd, bf16, gl, row_tiles, m->ldH[l], st);
+    }
+    EnergyLaunch el{};
+    el.Hin = L >= 2 ? m->H[L - 2].as<float>() : m->G.as<float>();
+    el.ldh = L >= 2 ? m->ldH[L - 2] : D;
+    el.Gout = L >= 2 ? m->Gd[L - 2].as<float>() : m->dG.as<float>();
+    el.ldg = L >= 2 ? m->ldH[L - 2] : D;
+    for (int s = 0; s < m->S; ++s) {
+      LayerW &lw = m->layer(mb, s, L - 1);
+      el.w[s] = lw.W;
+      el.b[s] = lw.b;
+      el.K[s] = lw.n_in;
+    }
+    el.perm = m->perm.as<int>();
+    el.bucket_off = m->bucket_off.as<int>();
+    el.n_groups = m->S;
+    el.e_atom = m->e_atom.as<float>();
+    el.inv_m = 1.0f / (float)m->M;
+    el.alpha = m->alpha;
+    el.first = mb == 0;
+    el.hidden = L >= 2;
+    el.want_grad = want_grad;
+    el.accumulate_grad = L == 1 && mb > 0;
+    launch_energy(el, rows, st);
+    if (!want_grad) continue;
+    for (int l = L - 2; l >= 1; --l) {
+      GemmLaunch gl{};
+      gl.A = m->Gd[l].as<float>();
+      gl.lda = m->ldH[l];
+      gl.C = m->Gd[l - 1].as<float>();
+      gl.ldc = m->ldH[l - 1];
+      gl.H = m->H[l - 1].as<float>();
+      gl.ldh = m->ldH[l - 1];
+      gl.bucket_off = m->bucket_off.as<int>();
+      gl.n_groups = m->S;
+      gl.alpha = m->alpha;
+      gl.scale = 1.f;
+      for (int s = 0; s < m->S; ++s) {
+        LayerW &lw = m->layer(mb, s, l);
+        gl.g[s].B = bf16 ? (const void *)lw.Wtb : (const void *)lw.Wt;
+        gl.g[s].n_out = lw.n_in;
+        gl.g[s].K = lw.n_out;
+      }
+      launch_gemm(kEpiBwd, bf16, gl, row_tiles, m->ldH[l - 1], st);
+    }
+    if (L >= 2) {
+      GemmLaunch gl{};
+      gl.A = m->Gd[0].as<float>();
+      gl.lda = m->ldH[0];
+      gl.C = m->dG.as<float>();
+      gl.ldc = D;
+      gl.bucket_off = m->bucket_off.as<int>();
+      gl.n_groups = m->S;
+      gl.alpha = m->alpha;
+      gl.scale = 1.f;
+      gl.accumulate = mb > 0;
+      for (int s = 0; s < m->S; ++s) {
+        LayerW &lw = m->layer(mb, s, 0);
+        gl.g[s].B = bf16 ? (const void *)lw.Wtb : (const void *)lw.Wt;
+        gl.g[s].n_out = lw.n_in;
+        gl.g[s].K = lw.n_out;
+      }
+      launch_gemm(kEpiOut, bf16, gl, row_tiles, D, st);
+    }
+  }
+  mark();
+  if (want_grad) {
+    launch_fill(o.forces, (size_t)3 * N, 0.f, st);
+    launch_aev_bwd(pos, m->sys_of.as<int>(), dsys, m->nbr.as<int2>(), m->nbr_cnt.as<int>(), m->cap,
+                   m->row_of_atom.as<int>(), m->dG.as<float>(), D, N, m->aev, o.forces,
+                   m->W_atom.as<float>(), st);
+  }
+  mark();
+  launch_reduce(m->e_atom.as<float>(), want_grad ? m->W_atom.as<float>() : nullptr, dsys, n_sys,
+                m->chunk_sys.as<int>(), m->chunk_begin.as<int>(), n_chunks, m->sys_chunk_off.as<int>(),
+                m->partial.as<double>(), o.energy, o.virial, st);
+  if (o.atom_energy && N > 0)
+    HIP_TRY(hipMemcpyAsync(o.atom_energy, m->e_atom.p, (size_t)N * 4, hipMemcpyDeviceToDevice, st));
+  mark();
+  if (m->timing) m->last_stages = stage - 1;
+  HIP_TRY(hipGetLastError());
+  return NNP_OK;
+}
+
+extern "C" int nnp_energy_forces(nnp_model *m, int n_systems, const int64_t *offs, const float *coords,
+                                 const int32_t *species, const float *box, double *energy,
+                                 float *forces, double *virial, float *atom_energy, void *stream) {
+  CallOut o;
+  o.energy = energy;
+  o.forces = forces;
+  o.virial = virial;
+  o.atom_energy = atom_energy;
+  return run(m, n_systems, offs, coords, species, box, o, (hipStream_t)stream, kFull);
+}
+
+extern "C" int nnp_debug_aev(nnp_model *m, int n_systems, const int64_t *offs, const float *coords,
+                             const int32_t *species, const float *box, float *aev_out, void *stream) {
+  if (!aev_out) return fail(NNP_EINVAL, "null aev_out");
+  CallOut o;
+  o.aev = aev_out;
+  return run(m, n_systems, offs, coords, species, box, o, (hipStream_t)stream, kAev);
+}
+
+extern "C" int nnp_debug_neighbors(nnp_model *m, int n_systems, const int64_t *offs,
+                                   const float *coords, const int32_t *species, const float *box,
+                                   int32_t *counts, int32_t *entries, int capacity, void *stream) {
+  if (!counts || !entries || capacity < 1) return fail(NNP_EINVAL, "null neighbour outputs");
+  CallOut o;
+  o.nb_counts = counts;
+  o.nb_entries = entries;
+  o.nb_cap = capacity;
+  return run(m, n_systems, offs, coords, species, box, o, (hipStream_t)stream, kNbr);
+}

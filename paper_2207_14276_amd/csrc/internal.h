@@ -1,0 +1,130 @@
+// Internal declarations shared by the library's translation units.
+// gfx950 only: wave64, MFMA, 160 KB LDS per CU.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace nnp {
+
+constexpr int kWave = 64;
+constexpr int kMaxSpecies = 7;
+constexpr int kNShfRad = 16;
+constexpr int kNShfAng = 4;
+constexpr int kNShfZ = 8;
+constexpr int kAngBlock = kNShfAng * kNShfZ;  // 32 features per species pair
+constexpr int kTileM = 128;                   // MLP row tile; buckets pad to it
+
+// Device status word bits.
+enum : int { kStatOverflow = 1, kStatBadSpecies = 2 };
+
+// One system of a batch, as the kernels see it.  Filled on the host except
+// the non-periodic cell grid (origin/edge/nc), which a kernel derives from
+// the system's bounding box.
+struct SysDesc {
+  float L[3];        // box lengths (periodic) or 0
+  int periodic;
+  int atom_off, n;   // atoms [atom_off, atom_off + n)
+  int cell_off;      // first cell of this system in the global cell arrays
+  int cell_cap;      // cells reserved for this system
+  float origin[3];
+  float edge[3];
+  int nc[3];
+  int pad_;
+};
+
+// AEV hyper-parameters, passed by value to the AEV kernels.
+struct AevConst {
+  float rc_r, eta_r, rc_a, eta_a, zeta, scale;
+  float shf_r[kNShfRad];
+  float shf_a[kNShfAng];
+  float cz[kNShfZ], sz[kNShfZ];  // cos / sin of the angle shifts
+  int S;        // species
+  int D;        // AEV length
+  int rad_len;  // S * 16
+};
+
+// Neighbour entry: j and a packed lattice image (10 bits per axis, +512).
+__host__ __device__ inline int pack_image(int x, int y, int z) {
+  return (x + 512) | ((y + 512) << 10) | ((z + 512) << 20);
+}
+__host__ __device__ inline void unpack_image(int c, int &x, int &y, int &z) {
+  x = (c & 1023) - 512;
+  y = ((c >> 10) & 1023) - 512;
+  z = ((c >> 20) & 1023) - 512;
+}
+
+// ---- dense layers
+struct GemmGroup {
+  const void *B;      // [n_out][K] row-major, float or bf16
+  const float *bias;  // [n_out] (forward only)
+  int n_out, K;
+};
+
+struct GemmLaunch {
+  const float *A; int lda;   // [rows][>=K] float32 activations
+  float *C; int ldc;         // [rows][>=n_out]
+  const float *H; int ldh;   // backward: layer input activations for CELU'
+  const int *bucket_off;     // [n_groups + 1] padded row offsets (device)
+  int n_groups;
+  GemmGroup g[kMaxSpecies];
+  float alpha;               // CELU alpha
+  float scale;
+  int accumulate;
+};
+
+enum { kEpiFwd = 0, kEpiBwd = 1, kEpiOut = 2 };
+
+struct EnergyLaunch {
+  const float *Hin; int ldh;  // input of the last layer
+  float *Gout; int ldg;       // dE/d(input), scaled by inv_m
+  const float *w[kMaxSpecies];
+  const float *b[kMaxSpecies];
+  int K[kMaxSpecies];
+  const int *perm;            // row -> atom (-1 padding)
+  const int *bucket_off;
+  int n_groups;
+  float *e_atom;
+  float inv_m, alpha;
+  int first, hidden, want_grad, accumulate_grad;
+};
+
+// ---- launchers (stream-ordered, no host sync)
+void launch_ingest(const float *coords, const int *species, const SysDesc *sys, int n_sys,
+                   int N, int S, float4 *pos, int *sys_of, int *status, hipStream_t st);
+void launch_grid(SysDesc *sys, int n_sys, const float4 *pos, int *cell_count, float rc_list,
+                 hipStream_t st);
+void launch_cell_count(const float4 *pos, const int *sys_of, const SysDesc *sys, int N,
+                       int *cell_count, int *atom_cell, int *atom_slot, hipStream_t st);
+void launch_scan(const int *in, int *out, int n, hipStream_t st);
+void launch_cell_scatter(const int *atom_cell, const int *atom_slot, const int *cell_start,
+                         int N, int *cell_atoms, hipStream_t st);
+void launch_cell_sort(const int *cell_start, int n_cells, int *cell_atoms, hipStream_t st);
+void launch_nbr_build(const float4 *pos, const int *sys_of, const SysDesc *sys,
+                      const int *cell_start, const int *cell_atoms, int N, float rc_list,
+                      int cap, int2 *nbr, int *nbr_cnt, int *status, hipStream_t st);
+void launch_species_bucket(const float4 *pos, int N, int S, int *block_counts, int n_blocks,
+                           int *bucket_off, int *bucket_cnt, int *perm, int *row_of_atom,
+                           int rows_cap, hipStream_t st);
+void launch_aev_fwd(const float4 *pos, const int *sys_of, const SysDesc *sys, const int2 *nbr,
+                    const int *nbr_cnt, int cap, const int *row_of_atom, float *G, int ldg,
+                    int N, const AevConst &c, hipStream_t st);
+void launch_aev_bwd(const float4 *pos, const int *sys_of, const SysDesc *sys, const int2 *nbr,
+                    const int *nbr_cnt, int cap, const int *row_of_atom, const float *dG,
+                    int ldg, int N, const AevConst &c, float *F, float *W_atom, hipStream_t st);
+void launch_gemm(int epi, bool bf16, const GemmLaunch &gl, int row_tiles, int max_n_out,
+                 hipStream_t st);
+void launch_energy(const EnergyLaunch &el, int rows, hipStream_t st);
+void launch_fill(float *p, size_t n, float v, hipStream_t st);
+void launch_fill_i32(int *p, size_t n, int v, hipStream_t st);
+void launch_reduce(const float *e_atom, const float *W_atom, const SysDesc *sys, int n_sys,
+                   const int *chunk_sys, const int *chunk_begin, int n_chunks,
+                   const int *sys_chunk_off, double *partial, double *energy, double *virial,
+                   hipStream_t st);
+void launch_gather_rows(const float *src, int ld, const int *row_of_atom, int N, int D,
+                        float *dst, hipStream_t st);
+void launch_export_nbr(const int2 *nbr, const int *nbr_cnt, int cap, int N, int *counts,
+                       int *entries, int out_cap, hipStream_t st);
+void launch_f32_to_bf16(const float *src, uint16_t *dst, size_t n, hipStream_t st);
+
+}  // namespace nnp

@@ -1,0 +1,452 @@
+// Ingest, cell list and neighbour list (linked-cell search, section
+// "Massive Parallelism within Tinker-HP"), species buckets, small utilities.
+#include "internal.h"
+
+namespace nnp {
+
+// ------------------------------------------------------------------ ingest
+// Caller AoS float32[N][3] -> packed 16-byte atom records {x, y, z, species}
+// with periodic coordinates wrapped into [0, L).  One 16-byte load per
+// neighbour gather in the AEV kernels.
+__global__ void k_ingest(const float *__restrict__ coords, const int *__restrict__ species,
+                         const SysDesc *__restrict__ sys, int n_sys, int N, int S,
+                         float4 *__restrict__ pos, int *__restrict__ sys_of,
+                         int *__restrict__ status) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  // system of atom i: last s with atom_off <= i (binary search)
+  int lo = 0, hi = n_sys - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (sys[mid].atom_off <= i) lo = mid; else hi = mid - 1;
+  }
+  // skip empty systems that share the offset
+  while (lo + 1 < n_sys && sys[lo + 1].atom_off <= i) ++lo;
+  const SysDesc &d = sys[lo];
+  float x = coords[3 * i], y = coords[3 * i + 1], z = coords[3 * i + 2];
+  if (d.periodic) {
+    x -= floorf(x / d.L[0]) * d.L[0];
+    y -= floorf(y / d.L[1]) * d.L[1];
+    z -= floorf(z / d.L[2]) * d.L[2];
+    if (x >= d.L[0]) x -= d.L[0];
+    if (y >= d.L[1]) y -= d.L[1];
+    if (z >= d.L[2]) z -= d.L[2];
+    x = fmaxf(x, 0.f); y = fmaxf(y, 0.f); z = fmaxf(z, 0.f);
+  }
+  int s = species[i];
+  if (s < 0 || s >= S) {
+    atomicOr(status, kStatBadSpecies);
+    s = 0;
+  }
+  pos[i] = make_float4(x, y, z, __int_as_float(s));
+  sys_of[i] = lo;
+}
+
+void launch_ingest(const float *coords, const int *species, const SysDesc *sys, int n_sys,
+                   int N, int S, float4 *pos, int *sys_of, int *status, hipStream_t st) {
+  if (N <= 0) return;
+  k_ingest<<<(N + 255) / 256, 256, 0, st>>>(coords, species, sys, n_sys, N, S, pos, sys_of,
+                                            status);
+}
+
+// -------------------------------------------------------------- cell grids
+// One wave per system.  Periodic: the host already set nc/edge.  Non-periodic:
+// cells of edge >= rc_list over the bounding box, at most cell_cap cells.
+// Also clears the system's cell counters.
+__global__ void k_grid(SysDesc *__restrict__ sys, int n_sys, const float4 *__restrict__ pos,
+                       int *__restrict__ cell_count, float rc_list) {
+  int s = blockIdx.x;
+  if (s >= n_sys) return;
+  int lane = threadIdx.x;
+  SysDesc d = sys[s];
+  if (!d.periodic) {
+    float mn[3] = {3.4e38f, 3.4e38f, 3.4e38f}, mx[3] = {-3.4e38f, -3.4e38f, -3.4e38f};
+    for (int a = lane; a < d.n; a += kWave) {
+      float4 p = pos[d.atom_off + a];
+      mn[0] = fminf(mn[0], p.x); mx[0] = fmaxf(mx[0], p.x);
+      mn[1] = fminf(mn[1], p.y); mx[1] = fmaxf(mx[1], p.y);
+      mn[2] = fminf(mn[2], p.z); mx[2] = fmaxf(mx[2], p.z);
+    }
+    for (int off = 32; off >= 1; off >>= 1)
+      for (int k = 0; k < 3; ++k) {
+        mn[k] = fminf(mn[k], __shfl_xor(mn[k], off));
+        mx[k] = fmaxf(mx[k], __shfl_xor(mx[k], off));
+      }
+    if (lane == 0) {
+      const float rc = rc_list * (1.0f + 1e-5f);
+      int nc[3];
+      float ext[3];
+      for (int k = 0; k < 3; ++k) {
+        if (d.n == 0) { mn[k] = 0.f; mx[k] = 0.f; }
+        ext[k] = fmaxf(mx[k] - mn[k], 0.f);
+        nc[k] = max(1, (int)floorf(ext[k] / rc));
+        nc[k] = min(nc[k], 1024);
+      }
+      // keep the product within the reserved cells: widen the largest axis' cells
+      while ((long long)nc[0] * nc[1] * nc[2] > d.cell_cap) {
+        int k = (nc[0] >= nc[1] && nc[0] >= nc[2]) ? 0 : (nc[1] >= nc[2] ? 1 : 2);
+        nc[k] = max(1, nc[k] - 1);
+      }
+      for (int k = 0; k < 3; ++k) {
+        d.origin[k] = mn[k];
+        d.nc[k] = nc[k];
+        d.edge[k] = nc[k] > 1 ? ext[k] / nc[k] : fmaxf(ext[k], rc);
+        // guard the edge so floor((x - origin) / edge) of the max lands in-grid
+        d.edge[k] = fmaxf(d.edge[k], rc);
+      }
+      sys[s] = d;
+    }
+  }
+  for (int c = lane; c < d.cell_cap; c += kWave) cell_count[d.cell_off + c] = 0;
+}
+
+void launch_grid(SysDesc *sys, int n_sys, const float4 *pos, int *cell_count, float rc_list,
+                 hipStream_t st) {
+  if (n_sys <= 0) return;
+  k_grid<<<n_sys, kWave, 0, st>>>(sys, n_sys, pos, cell_count, rc_list);
+}
+
+__device__ inline int cell_coord(float x, float o, float e, int nc) {
+  int c = (int)floorf((x - o) / e);
+  return min(max(c, 0), nc - 1);
+}
+
+__global__ void k_cell_count(const float4 *__restrict__ pos, const int *__restrict__ sys_of,
+                             const SysDesc *__restrict__ sys, int N, int *__restrict__ cell_count,
+                             int *__restrict__ atom_cell, int *__restrict__ atom_slot) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const SysDesc &d = sys[sys_of[i]];
+  float4 p = pos[i];
+  int cx = cell_coord(p.x, d.origin[0], d.edge[0], d.nc[0]);
+  int cy = cell_coord(p.y, d.origin[1], d.edge[1], d.nc[1]);
+  int cz = cell_coord(p.z, d.origin[2], d.edge[2], d.nc[2]);
+  int c = d.cell_off + (cx * d.nc[1] + cy) * d.nc[2] + cz;
+  atom_cell[i] = c;
+  atom_slot[i] = atomicAdd(&cell_count[c], 1);
+}
+
+void launch_cell_count(const float4 *pos, const int *sys_of, const SysDesc *sys, int N,
+                       int *cell_count, int *atom_cell, int *atom_slot, hipStream_t st) {
+  if (N <= 0) return;
+  k_cell_count<<<(N + 255) / 256, 256, 0, st>>>(pos, sys_of, sys, N, cell_count, atom_cell,
+                                                atom_slot);
+}
+
+// Exclusive prefix sum, out[0..n]; one workgroup of 1024 threads, each thread
+// owning a contiguous run.  n is at most a few hundred thousand cells.
+__global__ void __launch_bounds__(1024) k_scan(const int *__restrict__ in, int *__restrict__ out,
+                                               int n) {
+  __shared__ int part[1024];
+  int t = threadIdx.x;
+  int per = (n + 1023) / 1024;
+  int b = t * per, e = min(n, b + per);
+  int s = 0;
+  for (int k = b; k < e; ++k) s += in[k];
+  part[t] = s;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    int v = t >= off ? part[t - off] : 0;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  int run = part[t] - s;
+  for (int k = b; k < e; ++k) {
+    out[k] = run;
+    run += in[k];
+  }
+  if (t == 1023) out[n] = part[1023];
+}
+
+void launch_scan(const int *in, int *out, int n, hipStream_t st) {
+  k_scan<<<1, 1024, 0, st>>>(in, out, n);
+}
+
+__global__ void k_cell_scatter(const int *__restrict__ atom_cell, const int *__restrict__ atom_slot,
+                               const int *__restrict__ cell_start, int N,
+                               int *__restrict__ cell_atoms) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  cell_atoms[cell_start[atom_cell[i]] + atom_slot[i]] = i;
+}
+
+void launch_cell_scatter(const int *atom_cell, const int *atom_slot, const int *cell_start, int N,
+                         int *cell_atoms, hipStream_t st) {
+  if (N <= 0) return;
+  k_cell_scatter<<<(N + 255) / 256, 256, 0, st>>>(atom_cell, atom_slot, cell_start, N,
+                                                  cell_atoms);
+}
+
+// Sorts each cell's atoms by index so neighbour lists (and every sum over
+// them) come out in the same order on every call.
+__global__ void k_cell_sort(const int *__restrict__ cell_start, int n_cells,
+                            int *__restrict__ cell_atoms) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n_cells) return;
+  int b = cell_start[c], e = cell_start[c + 1];
+  for (int k = b + 1; k < e; ++k) {
+    int v = cell_atoms[k];
+    int q = k - 1;
+    while (q >= b && cell_atoms[q] > v) {
+      cell_atoms[q + 1] = cell_atoms[q];
+      --q;
+    }
+    cell_atoms[q + 1] = v;
+  }
+}
+
+void launch_cell_sort(const int *cell_start, int n_cells, int *cell_atoms, hipStream_t st) {
+  if (n_cells <= 0) return;
+  k_cell_sort<<<(n_cells + 255) / 256, 256, 0, st>>>(cell_start, n_cells, cell_atoms);
+}
+
+// ----------------------------------------------------------- neighbour list
+// Thread per atom: scan the stencil of cells around the atom's cell (every
+// periodic image through the wrap of the cell index) and keep each (j, image)
+// with |d| < rc_list, excluding the atom itself in the home image.
+__global__ void k_nbr_build(const float4 *__restrict__ pos, const int *__restrict__ sys_of,
+                            const SysDesc *__restrict__ sys, const int *__restrict__ cell_start,
+                            const int *__restrict__ cell_atoms, int N, float rc_list, int cap,
+                            int2 *__restrict__ nbr, int *__restrict__ nbr_cnt,
+                            int *__restrict__ status) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const SysDesc d = sys[sys_of[i]];
+  const float4 p = pos[i];
+  const float rc2 = rc_list * rc_list;
+  int c[3], k[3];
+  const float pc[3] = {p.x, p.y, p.z};
+  for (int a = 0; a < 3; ++a) {
+    c[a] = cell_coord(pc[a], d.origin[a], d.edge[a], d.nc[a]);
+    k[a] = d.periodic ? (int)ceilf(rc_list / d.edge[a]) : 1;
+  }
+  int cnt = 0;
+  int2 *out = nbr + (size_t)i * cap;
+  for (int ox = -k[0]; ox <= k[0]; ++ox) {
+    int ux = c[0] + ox, wx, sx;
+    if (d.periodic) {
+      sx = ux >= 0 ? ux / d.nc[0] : -((-ux + d.nc[0] - 1) / d.nc[0]);
+      wx = ux - sx * d.nc[0];
+    } else {
+      if (ux < 0 || ux >= d.nc[0]) continue;
+      wx = ux; sx = 0;
+    }
+    for (int oy = -k[1]; oy <= k[1]; ++oy) {
+      int uy = c[1] + oy, wy, sy;
+      if (d.periodic) {
+        sy = uy >= 0 ? uy / d.nc[1] : -((-uy + d.nc[1] - 1) / d.nc[1]);
+        wy = uy - sy * d.nc[1];
+      } else {
+        if (uy < 0 || uy >= d.nc[1]) continue;
+        wy = uy; sy = 0;
+      }
+      for (int oz = -k[2]; oz <= k[2]; ++oz) {
+        int uz = c[2] + oz, wz, sz;
+        if (d.periodic) {
+          sz = uz >= 0 ? uz / d.nc[2] : -((-uz + d.nc[2] - 1) / d.nc[2]);
+          wz = uz - sz * d.nc[2];
+        } else {
+          if (uz < 0 || uz >= d.nc[2]) continue;
+          wz = uz; sz = 0;
+        }
+        const float shx = sx * d.L[0], shy = sy * d.L[1], shz = sz * d.L[2];
+        const bool home = (sx | sy | sz) == 0;
+        const int cell = d.cell_off + (wx * d.nc[1] + wy) * d.nc[2] + wz;
+        const int qb = cell_start[cell], qe = cell_start[cell + 1];
+        for (int q = qb; q < qe; ++q) {
+          int j = cell_atoms[q];
+          if (home && j == i) continue;
+          float4 pj = pos[j];
+          float dx = (pj.x - p.x) + shx, dy = (pj.y - p.y) + shy, dz = (pj.z - p.z) + shz;
+          float r2 = dx * dx + dy * dy + dz * dz;
+          if (r2 < rc2) {
+            if (cnt < cap) out[cnt] = make_int2(j, pack_image(sx, sy, sz));
+            ++cnt;
+          }
+        }
+      }
+    }
+  }
+  nbr_cnt[i] = cnt;
+  if (cnt > cap) atomicOr(status, kStatOverflow);
+  atomicMax(status + 1, cnt);
+}
+
+void launch_nbr_build(const float4 *pos, const int *sys_of, const SysDesc *sys,
+                      const int *cell_start, const int *cell_atoms, int N, float rc_list, int cap,
+                      int2 *nbr, int *nbr_cnt, int *status, hipStream_t st) {
+  if (N <= 0) return;
+  k_nbr_build<<<(N + 127) / 128, 128, 0, st>>>(pos, sys_of, sys, cell_start, cell_atoms, N,
+                                               rc_list, cap, nbr, nbr_cnt, status);
+}
+
+// ----------------------------------------------------------- species buckets
+// Stable counting sort of atoms by species into row ranges padded to the MLP
+// row tile, so one dense-layer tile never mixes element networks
+// (section "Neural Network Potentials": one network per element).
+constexpr int kBucketBlock = 1024;
+
+__global__ void __launch_bounds__(kBucketBlock)
+k_species_count(const float4 *__restrict__ pos, int N, int S, int *__restrict__ block_counts) {
+  __shared__ int cnt[kMaxSpecies];
+  if (threadIdx.x < kMaxSpecies) cnt[threadIdx.x] = 0;
+  __syncthreads();
+  int i = blockIdx.x * kBucketBlock + threadIdx.x;
+  if (i < N) atomicAdd(&cnt[__float_as_int(pos[i].w)], 1);
+  __syncthreads();
+  if (threadIdx.x < kMaxSpecies) block_counts[blockIdx.x * kMaxSpecies + threadIdx.x] = cnt[threadIdx.x];
+}
+
+// One workgroup: per-species exclusive scan over blocks, padded bucket
+// offsets, and -1 in the padding rows.
+__global__ void __launch_bounds__(256)
+k_species_scan(int *__restrict__ block_counts, int n_blocks, int S, int *__restrict__ bucket_off,
+               int *__restrict__ bucket_cnt, int *__restrict__ perm) {
+  __shared__ int tot[kMaxSpecies];
+  __shared__ int off[kMaxSpecies + 1];
+  int t = threadIdx.x;
+  if (t < S) {
+    int run = 0;
+    for (int b = 0; b < n_blocks; ++b) {
+      int v = block_counts[b * kMaxSpecies + t];
+      block_counts[b * kMaxSpecies + t] = run;
+      run += v;
+    }
+    tot[t] = run;
+  }
+  __syncthreads();
+  if (t == 0) {
+    int o = 0;
+    for (int s = 0; s < S; ++s) {
+      off[s] = o;
+      o += (tot[s] + kTileM - 1) / kTileM * kTileM;
+    }
+    off[S] = o;
+    for (int s = 0; s <= S; ++s) bucket_off[s] = off[s];
+    for (int s = 0; s < S; ++s) bucket_cnt[s] = tot[s];
+  }
+  __syncthreads();
+  for (int s = 0; s < S; ++s)
+    for (int r = off[s] + tot[s] + t; r < off[s + 1]; r += blockDim.x) perm[r] = -1;
+}
+
+__global__ void __launch_bounds__(kBucketBlock)
+k_species_scatter(const float4 *__restrict__ pos, int N, const int *__restrict__ block_base,
+                  const int *__restrict__ bucket_off, int *__restrict__ perm,
+                  int *__restrict__ row_of_atom) {
+  __shared__ int wave_cnt[kBucketBlock / kWave][kMaxSpecies];
+  int i = blockIdx.x * kBucketBlock + threadIdx.x;
+  int w = threadIdx.x / kWave;
+  int s = i < N ? __float_as_int(pos[i].w) : -1;
+  int rank_in_wave = 0;
+  for (int q = 0; q < kMaxSpecies; ++q) {
+    unsigned long long m = __ballot(s == q);
+    if (s == q)
+      rank_in_wave = __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
+                                               __builtin_amdgcn_mbcnt_lo((unsigned)m, 0));
+    if ((threadIdx.x & (kWave - 1)) == 0) wave_cnt[w][q] = __popcll(m);
+  }
+  __syncthreads();
+  if (s >= 0) {
+    int before = 0;
+    for (int v = 0; v < w; ++v) before += wave_cnt[v][s];
+    int row = bucket_off[s] + block_base[blockIdx.x * kMaxSpecies + s] + before + rank_in_wave;
+    perm[row] = i;
+    row_of_atom[i] = row;
+  }
+}
+
+void launch_species_bucket(const float4 *pos, int N, int S, int *block_counts, int n_blocks,
+                           int *bucket_off, int *bucket_cnt, int *perm, int *row_of_atom,
+                           int rows_cap, hipStream_t st) {
+  (void)rows_cap;
+  if (N > 0) k_species_count<<<n_blocks, kBucketBlock, 0, st>>>(pos, N, S, block_counts);
+  k_species_scan<<<1, 256, 0, st>>>(block_counts, N > 0 ? n_blocks : 0, S, bucket_off,
+                                    bucket_cnt, perm);
+  if (N > 0)
+    k_species_scatter<<<n_blocks, kBucketBlock, 0, st>>>(pos, N, block_counts, bucket_off, perm,
+                                                         row_of_atom);
+}
+
+// ----------------------------------------------------------------- utilities
+__global__ void k_fill(float *__restrict__ p, size_t n, float v) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) p[i] = v;
+}
+
+void launch_fill(float *p, size_t n, float v, hipStream_t st) {
+  if (n == 0) return;
+  size_t blocks = (n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  k_fill<<<(unsigned)blocks, 256, 0, st>>>(p, n, v);
+}
+
+__global__ void k_fill_i32(int *__restrict__ p, size_t n, int v) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) p[i] = v;
+}
+
+void launch_fill_i32(int *p, size_t n, int v, hipStream_t st) {
+  if (n == 0) return;
+  size_t blocks = (n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  k_fill_i32<<<(unsigned)blocks, 256, 0, st>>>(p, n, v);
+}
+
+__global__ void k_gather_rows(const float *__restrict__ src, int ld, const int *__restrict__ row_of_atom,
+                              int N, int D, float *__restrict__ dst) {
+  int i = blockIdx.x;
+  if (i >= N) return;
+  const float *s = src + (size_t)row_of_atom[i] * ld;
+  float *d = dst + (size_t)i * D;
+  for (int k = threadIdx.x; k < D; k += blockDim.x) d[k] = s[k];
+}
+
+void launch_gather_rows(const float *src, int ld, const int *row_of_atom, int N, int D, float *dst,
+                        hipStream_t st) {
+  if (N <= 0) return;
+  k_gather_rows<<<N, 256, 0, st>>>(src, ld, row_of_atom, N, D, dst);
+}
+
+__global__ void k_export_nbr(const int2 *__restrict__ nbr, const int *__restrict__ nbr_cnt, int cap,
+                             int N, int *__restrict__ counts, int *__restrict__ entries,
+                             int out_cap) {
+  int i = blockIdx.x;
+  if (i >= N) return;
+  int n = nbr_cnt[i];
+  if (threadIdx.x == 0) counts[i] = n;
+  int w = min(min(n, cap), out_cap);
+  for (int e = threadIdx.x; e < w; e += blockDim.x) {
+    int2 v = nbr[(size_t)i * cap + e];
+    int x, y, z;
+    unpack_image(v.y, x, y, z);
+    int *o = entries + ((size_t)i * out_cap + e) * 4;
+    o[0] = v.x; o[1] = x; o[2] = y; o[3] = z;
+  }
+}
+
+void launch_export_nbr(const int2 *nbr, const int *nbr_cnt, int cap, int N, int *counts,
+                       int *entries, int out_cap, hipStream_t st) {
+  if (N <= 0) return;
+  k_export_nbr<<<N, 64, 0, st>>>(nbr, nbr_cnt, cap, N, counts, entries, out_cap);
+}
+
+__global__ void k_f32_to_bf16(const float *__restrict__ src, uint16_t *__restrict__ dst, size_t n) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  // round to nearest even
+  unsigned u = __float_as_uint(src[i]);
+  unsigned lsb = (u >> 16) & 1u;
+  u += 0x7fffu + lsb;
+  dst[i] = (uint16_t)(u >> 16);
+}
+
+void launch_f32_to_bf16(const float *src, uint16_t *dst, size_t n, hipStream_t st) {
+  if (n == 0) return;
+  k_f32_to_bf16<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(src, dst, n);
+}
+
+}  // namespace nnp
