@@ -1,0 +1,318 @@
+"""Throughput benchmark of the energy+force path on one MI355X.
+
+Default workload: the ragged batch of 512 independent non-periodic solutes
+(10-120 atoms, H/C/N/O/S/F/Cl), evaluated in one call per step with the
+dense layers in bfloat16 (float32 accumulate).  Beside it the same batch is
+run the plain way: float32 dense layers, one system per call, sequentially
+on one stream.  One atom-eval = energy + forces of one atom.
+
+Prints one JSON line (see the measurement section of the design doc).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP32_VALU_TFLOPS = 157.3
+PEAK_BF16_MFMA_TFLOPS = 2500.0
+PEAK_FP32_MFMA_TFLOPS = 157.3
+PEAK_HBM_GBS = 8000.0
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=20)
+    p.add_argument("--warmup", type=int, default=5)
+    p.add_argument("--workload", default="ragged512",
+                   choices=["ragged512", "water2001", "protein100k", "cluster24"])
+    p.add_argument("--precision", default="bf16", choices=["bf16", "fp32"])
+    p.add_argument("--no-plain", action="store_true")
+    p.add_argument("--no-cpu", action="store_true")
+    p.add_argument("--plain-passes", type=int, default=2)
+    p.add_argument("--cpu-seconds", type=float, default=15.0)
+    p.add_argument("--quiet", action="store_true")
+    return p.parse_args()
+
+
+def say(args, *a):
+    if not args.quiet:
+        print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def workload(name):
+    import synth
+    if name == "ragged512":
+        return synth.config2(), synth.make_model(0), "ragged batch: 512 non-periodic solutes, 10-120 atoms"
+    if name == "water2001":
+        return synth.make_batch([synth.config1()]), synth.make_model(0), "periodic water box, 2001 atoms, L=27.1 A"
+    if name == "protein100k":
+        return (synth.make_batch([synth.config3()]), synth.make_model(3, n_ensemble=8),
+                "periodic solvated-protein-like box, 100,002 atoms, L=101 A, ensemble of 8 networks")
+    return synth.make_batch([synth.config0()]), synth.make_model(0), "24-atom cluster"
+
+
+def pair_triplet_counts(model, batch, c, s):
+    """Radial pairs and angular triplets of the batch, from the library's own
+    neighbour lists (distances recomputed here in float64)."""
+    cnt, ent = model.neighbors(c, s, batch.boxes, batch.offsets, capacity=model_cap(model))
+    cnt = cnt.cpu().numpy()
+    ent = ent.cpu().numpy()
+    sys_of = np.repeat(np.arange(batch.n_systems), np.diff(batch.offsets))
+    x = batch.coords.astype(np.float64)
+    rc_r, rc_a = model.spec.aev["rc_rad"], model.spec.aev["rc_ang"]
+    n_pairs = 0
+    n_trip = 0
+    for i in range(batch.n_atoms):
+        e = ent[i, :min(cnt[i], ent.shape[1])]
+        if len(e) == 0:
+            continue
+        L = batch.boxes[sys_of[i]].astype(np.float64)
+        d = x[e[:, 0]] + e[:, 1:4] * L - x[i]
+        r = np.sqrt((d * d).sum(1))
+        n_pairs += int((r < rc_r).sum())
+        na = int((r < rc_a).sum())
+        n_trip += na * (na - 1) // 2
+    return n_pairs, n_trip
+
+
+def size_capacity(model, batch, c, sp, N, S):
+    """Neighbour capacity = largest neighbour count, rounded up (LDS use of
+    the AEV kernels scales with it)."""
+    model.reserve(N, S, 1024)
+    model.energy_forces(c, sp, batch.boxes, batch.offsets, forces=False)
+    mx = model.status()
+    cap = min(1024, (mx + 8 + 31) // 32 * 32)
+    model.reserve(N, S, cap)
+    model._bench_cap = cap
+    return cap
+
+
+def model_cap(model):
+    return getattr(model, "_bench_cap", 256)
+
+
+# Algorithmic work of the AEV stages, counted from the formulas (flops of the
+# float32 vector unit; a transcendental (exp, log, sin/cos, sqrt, reciprocal)
+# counts 4, its issue cost relative to an add or multiply):
+#   radial pair:  per shift  (R - Rs), square, * eta, exp, * fc, accumulate
+#                 = 5 + 4 = 9; x16 shifts = 144; + distance (8 + sqrt 4) and
+#                 cutoff (2 + cos 4) = 18                      -> 162
+#   triplet:      geometry (dot 5, cross 9 + sqrt, 1/(RjRk), cos/sin 2) = 25;
+#                 per angle shift: cos(theta - theta_s) 3, 1 + c 1, log 4,
+#                 * zeta + const 2, exp2 4 = 14, x8 = 112;
+#                 per radial shift: Rbar - Rs, square, * eta, exp 4 = 7, x4 = 28;
+#                 fc_j fc_k 1; per (a, r) product and accumulate 2, x32 = 64
+#                                                               -> 230
+# The backward pass differentiates the same terms: radial 2x, triplet ~2.2x
+# (see the design doc), i.e. 324 and 510.
+FLOP_RADIAL_FWD = 162
+FLOP_TRIPLET_FWD = 230
+FLOP_RADIAL_BWD = 324
+FLOP_TRIPLET_BWD = 510
+
+
+def mlp_flops(spec, species):
+    """2 * MACs of forward and backward (input gradient) dense layers."""
+    per = []
+    for w in spec.widths:
+        macs = sum(w[l] * w[l + 1] for l in range(len(w) - 1))
+        per.append(macs)
+    per = np.array(per, dtype=np.float64)
+    fwd = 2.0 * per[species].sum() * spec.n_ensemble
+    bwd = 2.0 * (per[species] - np.array([w[-2] for w in spec.widths])[species]).sum() * spec.n_ensemble
+    return fwd, bwd
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only; the energy/force path "
+                          "is not sharded across GPUs in this build (see DESIGN.md)",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+    import synth
+    from paper_2207_14276_amd import NNPModel
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    batch, spec, desc = workload(args.workload)
+    N, S = batch.n_atoms, batch.n_systems
+    say(args, f"workload {args.workload}: N={N} S={S}")
+    c = torch.as_tensor(batch.coords, device=dev)
+    sp = torch.as_tensor(batch.species, device=dev)
+
+    model = NNPModel(spec, args.precision)
+    cap = size_capacity(model, batch, c, sp, N, S)
+    res = model.energy_forces(c, sp, batch.boxes, batch.offsets, forces=True, virial=True,
+                              atom_energy=True, check=True)
+    for _ in range(args.warmup):
+        model.energy_forces(c, sp, batch.boxes, batch.offsets, out=res)
+    torch.cuda.synchronize()
+
+    st = torch.cuda.current_stream()
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        starts[k].record(st)
+        model.energy_forces(c, sp, batch.boxes, batch.offsets, out=res)
+        ends[k].record(st)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    model.status()
+    wall = t1 - t0
+    lat = np.array([starts[k].elapsed_time(ends[k]) for k in range(args.steps)])
+    value = N * args.steps / wall
+    say(args, f"headline {args.precision}: {wall / args.steps * 1e3:.3f} ms/step, {value:.3e} atom-evals/s")
+
+    # per-stage device times (HIP events around each stage, same stream)
+    model.set_timing(True)
+    stage_acc = {}
+    n_t = max(3, min(args.steps, 10))
+    for _ in range(n_t):
+        model.energy_forces(c, sp, batch.boxes, batch.offsets, out=res)
+        for k, v in model.stage_timings().items():
+            stage_acc[k] = stage_acc.get(k, 0.0) + v
+    model.set_timing(False)
+    stages = {k: v / n_t for k, v in stage_acc.items()}
+    say(args, "stages ms:", {k: round(v, 4) for k, v in stages.items()})
+
+    # algorithmic work
+    n_pairs, n_trip = pair_triplet_counts(model, batch, c, sp)
+    fwd_f, bwd_f = mlp_flops(spec, batch.species)
+    aev_fwd_flop = FLOP_RADIAL_FWD * n_pairs + FLOP_TRIPLET_FWD * n_trip
+    aev_bwd_flop = FLOP_RADIAL_BWD * n_pairs + FLOP_TRIPLET_BWD * n_trip
+    mlp_flop = fwd_f + bwd_f
+    cand = {
+        "aev_fwd": ("alu", aev_fwd_flop, PEAK_FP32_VALU_TFLOPS),
+        "aev_bwd": ("alu", aev_bwd_flop, PEAK_FP32_VALU_TFLOPS),
+        "mlp": ("mfma", mlp_flop,
+                PEAK_BF16_MFMA_TFLOPS if args.precision == "bf16" else PEAK_FP32_MFMA_TFLOPS),
+    }
+    dom = max(cand, key=lambda k: stages.get(k, 0.0))
+    bound, work, peak = cand[dom]
+    t_dom = stages[dom] * 1e-3
+    achieved = work / t_dom / 1e12
+    roof = {"kernel": {"aev_fwd": "k_aev_fwd", "aev_bwd": "k_aev_bwd", "mlp": "k_gemm (all dense layers)"}[dom],
+            "bound": bound, "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+            "frac": round(achieved / peak, 4), "traffic": None,
+            "work_per_launch_flop": work, "avg_launch_ms": round(stages[dom], 4),
+            "pairs": n_pairs, "triplets": n_trip}
+
+    out = {
+        "metric": "energy+force atom-evals/s",
+        "value": round(value, 1),
+        "unit": "atom-evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall / args.steps * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16-mlp/f32-aev" if args.precision == "bf16" else "f32",
+        "data": "synthetic",
+        "config": {"workload": desc, "n_atoms": N, "n_systems": S, "nbr_capacity": cap,
+                   "form": f"batched, one call per step, {args.precision} dense layers",
+                   "parallelism": "single GPU"},
+        "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 4),
+                       "p99": round(float(np.percentile(lat, 99)), 4)},
+        "stages_ms": {k: round(v, 4) for k, v in stages.items()},
+        "roofline": roof,
+        "mlp_tflops": round(mlp_flop / (stages["mlp"] * 1e-3) / 1e12, 2),
+    }
+
+    # plain form: float32, one system per call, sequential on one stream
+    if not args.no_plain and S > 1:
+        plain = NNPModel(spec, "fp32")
+        plain.reserve(int(np.diff(batch.offsets).max()), 1, cap)
+        offs = batch.offsets
+        per_sys = []
+        for k in range(S):
+            a, e = int(offs[k]), int(offs[k + 1])
+            per_sys.append((c[a:e], sp[a:e], batch.boxes[k:k + 1], np.array([0, e - a], np.int64)))
+        outs = [plain.energy_forces(*p, forces=True) for p in per_sys]
+        torch.cuda.synchronize()
+        plain.status()
+        tp = []
+        for _ in range(max(1, args.plain_passes)):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for p, o in zip(per_sys, outs):
+                plain.energy_forces(*p, out=o)
+            torch.cuda.synchronize()
+            tp.append(time.perf_counter() - t0)
+        tplain = min(tp)
+        out["plain_fp32_per_system"] = {"value": round(N / tplain, 1), "unit": "atom-evals/s",
+                                        "ms_per_pass": round(tplain * 1e3, 3),
+                                        "calls_per_pass": S}
+        out["speedup_vs_plain"] = round(value / (N / tplain), 2)
+        say(args, f"plain fp32 per-system: {tplain * 1e3:.2f} ms/pass, {N / tplain:.3e} atom-evals/s")
+
+    # error of each form against the oracle on a seeded sample of systems
+    if not args.no_cpu:
+        import oracle
+        om = oracle.OracleModel(spec)
+        rng = np.random.default_rng(0)
+        pick = sorted(rng.choice(S, min(S, 8), replace=False).tolist()) if S > 1 else [0]
+        if args.workload == "protein100k":
+            tgt = np.sort(rng.choice(N, 8, replace=False))
+            e_ref, f_ref = oracle.sampled(batch.coords, batch.species, batch.boxes[0], om, tgt)
+            f_err = float(np.abs(res.forces.cpu().numpy()[tgt] - f_ref).max())
+            e_err = float(np.abs(res.atom_energy.cpu().numpy()[tgt] - e_ref).max())
+            out["error_vs_oracle"] = {"sample": "8 atoms", "max_abs_dE_atom": e_err, "max_abs_dF": f_err}
+        else:
+            ref = oracle.batch_energy_forces(batch, om, systems=pick)
+            F = res.forces.cpu().numpy()
+            E = res.energy.cpu().numpy()
+            fe, ee = 0.0, 0.0
+            for q, k in enumerate(pick):
+                a, e = int(batch.offsets[k]), int(batch.offsets[k + 1])
+                fe = max(fe, float(np.abs(F[a:e] - ref["forces"][q]).max()))
+                ee = max(ee, abs(E[k] - ref["energy"][q]) / (e - a))
+            out["error_vs_oracle"] = {"sample": f"{len(pick)} systems", "max_abs_dF": fe,
+                                      "max_abs_dE_per_atom": ee}
+
+        # CPU baseline: the oracle on a bounded sample of the same workload
+        t_budget = args.cpu_seconds
+        if args.workload == "protein100k":
+            tgt = np.arange(0, N, N // 16)[:16]
+            t0 = time.perf_counter()
+            oracle.sampled(batch.coords, batch.species, batch.boxes[0], om, tgt)
+            dt = time.perf_counter() - t0
+            cpu_rate, sample = len(tgt) / dt, f"{len(tgt)} atoms of the 100k box, local evaluation"
+        else:
+            done_atoms, k, t0 = 0, 0, time.perf_counter()
+            order = np.random.default_rng(1).permutation(S)
+            while k < S and time.perf_counter() - t0 < t_budget:
+                q = int(order[k])
+                a, e = int(batch.offsets[q]), int(batch.offsets[q + 1])
+                oracle.energy_forces(batch.coords[a:e], batch.species[a:e], batch.boxes[q], om)
+                done_atoms += e - a
+                k += 1
+            dt = time.perf_counter() - t0
+            cpu_rate = done_atoms / dt
+            sample = f"{k} of {S} systems ({done_atoms} atoms), seeded order"
+        out["cpu_baseline"] = {"value": round(cpu_rate, 2), "unit": "atom-evals/s",
+                               "cores": oracle.threads(), "kind": "oracle", "sample": sample,
+                               "seconds": round(dt, 2)}
+        say(args, f"cpu oracle: {cpu_rate:.3e} atom-evals/s on {oracle.threads()} threads")
+
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -2,17 +2,25 @@
 // cosine cutoff, radial and angular symmetry functions).
 //
 // One wavefront per centre atom.  The centre's neighbour entries are
-// re-derived from the packed atom records, sorted by neighbour species into
-// LDS with wave ballots, and then
+// re-derived from the packed atom records and sorted by neighbour species into
+// LDS with wave ballots.  Then
 //   radial:  lanes = 16 radial shifts x 4 neighbour slots, one species block
 //            at a time, reduced across the 4 slots with lane shuffles;
-//   angular: lanes = 8 angle shifts x 8 neighbour pairs, one species-pair
-//            block at a time.  Each lane evaluates the cosine power for its
-//            own angle shift and one of the 4 radial Gaussians, which the
-//            8 lanes of a pair then exchange; the 4 radial-shift accumulators
-//            are reduced across the 8 pairs at the end of the block.
-// The backward kernel walks the same blocks with dE/dG, accumulates
-// dE/dd per neighbour entry in LDS and scatters forces with float atomics.
+//   angular (forward): one species-pair block at a time, in passes of 64
+//            neighbour pairs:
+//            (A) lane per pair: the pair geometry (cos and sin of the angle,
+//                cutoff product, the 4 radial Gaussians of the mean distance)
+//                is computed once and staged in a per-wave LDS scratch;
+//            (B) lanes = 8 angle shifts x 8 pairs: each lane evaluates the
+//                cosine power of its angle shift for a pair and accumulates
+//                the 4 radial-shift products; accumulators are reduced across
+//                the 8 pairs at the end of the block.
+//   angular (backward): the pairs of all species-pair blocks form one
+//            stream, one pair per lane; a lane evaluates all 8 angle shifts
+//            of its pair against the block's dE/dG values (staged in LDS),
+//            differentiates through cos, sin, R_j and R_k, and accumulates
+//            dE/dd_j and dE/dd_k per neighbour entry in LDS.  Forces are then
+//            scattered with float atomics.
 #include "internal.h"
 
 namespace nnp {
@@ -56,28 +64,56 @@ __device__ inline float4 entry_vec(const float4 &pi, const float4 &pj, int code,
   return make_float4(dx, dy, dz, sqrtf(dx * dx + dy * dy + dz * dz));
 }
 
-// LDS layout of one wave's lists (cap entries each).
+// LDS layout of one wave's lists (cap entries each), pair-block table and
+// pair scratch.
+constexpr int kPairPass = kWave;  // neighbour pairs staged per pass
+constexpr int kMaxBlocks = kMaxSpecies * (kMaxSpecies + 1) / 2;
+constexpr int kMaxAng = kMaxBlocks * kAngBlock;  // 896 angular features
+
+// Non-empty species-pair block q of the centre's pair stream.
+struct PairBlock {
+  int start;   // first pair of the block in the stream
+  int p;       // feature block index (upper-triangle order of (sa, sb))
+  int oa, ob;  // offsets of the two species in the angular list
+  int na, nb;  // their counts
+  int same;    // sa == sb
+  int pad;
+};
+
 struct WaveLds {
-  float4 *rD;   // radial: d vector and R
-  float *rFc;   // radial: fc_rad(R)
-  float *rDfc;  // radial: fc_rad'(R)         (backward)
-  int *rJ;      // radial: neighbour index     (backward)
-  float *rG;    // radial: dE/dd accumulators  (backward, 3 per entry)
-  int *aIdx;    // angular: position in the radial arrays
-  float *aFc;   // angular: fc_ang(R)
-  float *aDfc;  // angular: fc_ang'(R)         (backward)
+  float4 *tGeo;    // pair scratch: cos, sin, fc_j fc_k, -      (forward)
+  float4 *tF2;     // pair scratch: radial Gaussians of Rbar     (forward)
+  PairBlock *blk;  // [kMaxBlocks + 1] pair-block table           (backward)
+  float *gAng;     // angular part of the centre's dE/dG row      (backward)
+  float4 *rD;      // radial: d vector and R
+  float *rFc;      // radial: fc_rad(R)
+  float *rDfc;     // radial: fc_rad'(R)         (backward)
+  int *rJ;         // radial: neighbour index     (backward)
+  float *rG;       // radial: dE/dd accumulators  (backward, 3 per entry)
+  int *aIdx;       // angular: position in the radial arrays
+  float *aFc;      // angular: fc_ang(R)
+  float *aDfc;     // angular: fc_ang'(R)         (backward)
 };
 
 template <bool BWD>
 __host__ __device__ inline size_t wave_lds_bytes(int cap) {
-  return (size_t)cap * (BWD ? 16 + 4 + 4 + 4 + 12 + 4 + 4 + 4 : 16 + 4 + 4 + 4);
+  return BWD ? (size_t)kMaxAng * 4 + sizeof(PairBlock) * (kMaxBlocks + 1) +
+                   (size_t)cap * (16 + 4 + 4 + 4 + 12 + 4 + 4 + 4)
+             : (size_t)kPairPass * 16 * 2 + (size_t)cap * (16 + 4 + 4 + 4);
 }
 
 template <bool BWD>
 __device__ inline WaveLds carve(char *base, int cap) {
   WaveLds w{};
-  w.rD = (float4 *)base;
-  char *p = base + (size_t)cap * 16;
+  char *p = base;
+  if (BWD) {
+    w.gAng = (float *)p; p += (size_t)kMaxAng * 4;
+    w.blk = (PairBlock *)p; p += sizeof(PairBlock) * (kMaxBlocks + 1);
+  } else {
+    w.tGeo = (float4 *)p; p += (size_t)kPairPass * 16;
+    w.tF2 = (float4 *)p; p += (size_t)kPairPass * 16;
+  }
+  w.rD = (float4 *)p; p += (size_t)cap * 16;
   w.rFc = (float *)p; p += (size_t)cap * 4;
   w.aIdx = (int *)p; p += (size_t)cap * 4;
   w.aFc = (float *)p; p += (size_t)cap * 4;
@@ -88,6 +124,56 @@ __device__ inline WaveLds carve(char *base, int cap) {
     w.aDfc = (float *)p; p += (size_t)cap * 4;
   }
   return w;
+}
+
+// Builds the table of non-empty species-pair blocks of the angular list
+// (wave-uniform values; lane 0 writes); returns the number of pairs.
+__device__ inline int build_blocks(int lane, const Lists &ls, int S, WaveLds &w, int &nblk) {
+  int q = 0, start = 0, p = 0;
+  for (int sa = 0; sa < S; ++sa)
+    for (int sb = sa; sb < S; ++sb, ++p) {
+      const int na = ls.cA[sa], nb = ls.cA[sb];
+      const int T = sa == sb ? na * (na - 1) / 2 : na * nb;
+      if (T == 0) continue;
+      if (lane == 0) {
+        PairBlock b;
+        b.start = start; b.p = p; b.oa = ls.oA[sa]; b.ob = ls.oA[sb];
+        b.na = na; b.nb = nb; b.same = sa == sb; b.pad = 0;
+        w.blk[q] = b;
+      }
+      ++q;
+      start += T;
+    }
+  if (lane == 0) w.blk[q].start = start;  // sentinel
+  nblk = q;
+  return start;
+}
+
+// Pair t of the stream -> its block (searched from the wave-uniform block
+// index qb of the pass), the positions of j and k in the angular list, and
+// the feature block index.
+__device__ inline void locate_pair(int t, int qb, int nblk, int pass_end, const WaveLds &w,
+                                   int &aj, int &ak, int &p) {
+  int q = qb;
+  for (int r = qb + 1; r < nblk && w.blk[r].start < pass_end; ++r)
+    if (t >= w.blk[r].start) q = r;
+  const PairBlock b = w.blk[q];
+  const int u = t - b.start;
+  int j, k;
+  if (b.same) unrank_upper(u, b.na, j, k);
+  else { j = u / b.nb; k = u - j * b.nb; }
+  aj = b.oa + j;
+  ak = b.ob + k;
+  p = b.p;
+}
+
+// Orders this wave's LDS writes before its later LDS reads by other lanes
+// (LDS requests of one wave are served in order; this only stops the
+// compiler from moving accesses across it).
+__device__ inline void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // Builds the species-sorted radial list (R < rc_r) and angular list
@@ -166,12 +252,22 @@ __device__ inline void fill_lists(int lane, int n, const int2 *__restrict__ ent,
   }
 }
 
-template <int WPB>
+// One AEV feature out, float32 or rounded to bfloat16 (nearest even) for the
+// bfloat16 dense layers that consume it.
+template <bool BF16> __device__ inline void put(void *row, int k, float v);
+template <> __device__ inline void put<false>(void *row, int k, float v) { ((float *)row)[k] = v; }
+template <> __device__ inline void put<true>(void *row, int k, float v) {
+  uint32_t u = __float_as_uint(v);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  ((uint16_t *)row)[k] = (uint16_t)(u >> 16);
+}
+
+template <int WPB, bool BF16>
 __global__ void __launch_bounds__(WPB * kWave)
 k_aev_fwd(const float4 *__restrict__ pos, const int *__restrict__ sys_of,
           const SysDesc *__restrict__ sys, const int2 *__restrict__ nbr,
           const int *__restrict__ nbr_cnt, int cap, const int *__restrict__ row_of_atom,
-          float *__restrict__ G, int ldg, int N, AevConst c) {
+          void *__restrict__ G, int ldg, int N, AevConst c) {
   extern __shared__ float4 lds4[];
   const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
   const int i = blockIdx.x * WPB + wave;
@@ -190,7 +286,7 @@ k_aev_fwd(const float4 *__restrict__ pos, const int *__restrict__ sys_of,
   fill_lists<false>(lane, n, nbr + (size_t)(live ? i : 0) * cap, pos, pi, L, c, w, ls);
   __syncthreads();
   if (!live) return;
-  float *Grow = G + (size_t)row_of_atom[i] * ldg;
+  void *Grow = (char *)G + (size_t)row_of_atom[i] * ldg * (BF16 ? 2 : 4);
 
   // radial: G[16 s + m] = scale * sum_j exp(-eta (R - Rs_m)^2) fc(R)
   {
@@ -206,46 +302,60 @@ k_aev_fwd(const float4 *__restrict__ pos, const int *__restrict__ sys_of,
       }
       acc += __shfl_xor(acc, 16);
       acc += __shfl_xor(acc, 32);
-      if (slot == 0) Grow[s * kNShfRad + m] = acc * c.scale;
+      if (slot == 0) put<BF16>(Grow, s * kNShfRad + m, acc * c.scale);
     }
   }
 
-  // angular
+  // angular: G[rad_len + 32 p + 8 r + a] = sum over pairs {j, k} of
+  //   2^(1-zeta) (1 + cos(theta - theta_a))^zeta exp(-eta (Rbar - Rs_r)^2) fc_j fc_k
   {
-    const int a = lane & 7, t0 = lane >> 3, grp = lane & ~7;
-    const float cza = c.cz[a], sza = c.sz[a], shf_own = c.shf_a[a & 3];
+    const int a = lane & 7, t0 = lane >> 3;
+    const float cza = c.cz[a], sza = c.sz[a];
     const float pre = 1.0f - c.zeta;
+    const float keta = -c.eta_a * 1.4426950408889634f;
     int p = 0;
     for (int sa = 0; sa < c.S; ++sa) {
       for (int sb = sa; sb < c.S; ++sb, ++p) {
         const int na = ls.cA[sa], nb = ls.cA[sb];
         const int T = sa == sb ? na * (na - 1) / 2 : na * nb;
         float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f, acc3 = 0.f;
-        for (int base = 0; base < T; base += 8) {
-          const int t = base + t0;
-          const bool valid = t < T;
-          const int tt = valid ? t : T - 1;
-          int j, k;
-          if (sa == sb) unrank_upper(tt, na, j, k);
-          else { j = tt / nb; k = tt - j * nb; }
-          const int qj = ls.oA[sa] + j, qk = ls.oA[sb] + k;
-          const float4 dj = w.rD[w.aIdx[qj]], dk = w.rD[w.aIdx[qk]];
-          const float fj = w.aFc[qj], fk = w.aFc[qk];
-          const float dot = dj.x * dk.x + dj.y * dk.y + dj.z * dk.z;
-          const float cx = dj.y * dk.z - dj.z * dk.y;
-          const float cy = dj.z * dk.x - dj.x * dk.z;
-          const float cz = dj.x * dk.y - dj.y * dk.x;
-          const float cr = sqrtf(cx * cx + cy * cy + cz * cz);
-          const float inv = 1.0f / (dj.w * dk.w);
-          const float cc = (dot * cza + cr * sza) * inv;  // cos(theta - theta_s)
-          const float x = fmaxf(1.0f + cc, 0.f);
-          const float f1 = fast_exp2(c.zeta * fast_log2(x) + pre);
-          const float u = 0.5f * (dj.w + dk.w) - shf_own;
-          const float f2 = fast_exp(-c.eta_a * u * u);
-          const float f20 = __shfl(f2, grp | 0), f21 = __shfl(f2, grp | 1);
-          const float f22 = __shfl(f2, grp | 2), f23 = __shfl(f2, grp | 3);
-          const float v = valid ? f1 * fj * fk : 0.f;
-          acc0 += v * f20; acc1 += v * f21; acc2 += v * f22; acc3 += v * f23;
+        for (int base = 0; base < T; base += kPairPass) {
+          // (A) lane per pair
+          {
+            const int t = base + lane;
+            const bool valid = t < T;
+            const int tt = valid ? t : T - 1;
+            int j, k;
+            if (sa == sb) unrank_upper(tt, na, j, k);
+            else { j = tt / nb; k = tt - j * nb; }
+            const int qj = ls.oA[sa] + j, qk = ls.oA[sb] + k;
+            const float4 dj = w.rD[w.aIdx[qj]], dk = w.rD[w.aIdx[qk]];
+            const float dot = dj.x * dk.x + dj.y * dk.y + dj.z * dk.z;
+            const float cx = dj.y * dk.z - dj.z * dk.y;
+            const float cy = dj.z * dk.x - dj.x * dk.z;
+            const float cz = dj.x * dk.y - dj.y * dk.x;
+            const float cr = sqrtf(cx * cx + cy * cy + cz * cz);
+            const float inv = 1.0f / (dj.w * dk.w);
+            const float fcc = valid ? w.aFc[qj] * w.aFc[qk] : 0.f;
+            const float Rbar = 0.5f * (dj.w + dk.w);
+            const float u0 = Rbar - c.shf_a[0], u1 = Rbar - c.shf_a[1];
+            const float u2 = Rbar - c.shf_a[2], u3 = Rbar - c.shf_a[3];
+            w.tGeo[lane] = make_float4(dot * inv, cr * inv, fcc, 0.f);
+            w.tF2[lane] = make_float4(fast_exp2(keta * u0 * u0), fast_exp2(keta * u1 * u1),
+                                      fast_exp2(keta * u2 * u2), fast_exp2(keta * u3 * u3));
+          }
+          wave_lds_sync();
+          // (B) lanes = 8 angle shifts x 8 pairs
+          const int cnt = min(kPairPass, T - base);
+          for (int sub = 0; sub < cnt; sub += 8) {
+            const int q = sub + t0;
+            const float4 geo = w.tGeo[q];
+            const float4 f2 = w.tF2[q];
+            const float x = fmaxf(1.0f + geo.x * cza + geo.y * sza, 0.f);
+            const float v = q < cnt ? fast_exp2(c.zeta * fast_log2(x) + pre) * geo.z : 0.f;
+            acc0 += v * f2.x; acc1 += v * f2.y; acc2 += v * f2.z; acc3 += v * f2.w;
+          }
+          wave_lds_sync();
         }
         for (int off = 8; off < kWave; off <<= 1) {
           acc0 += __shfl_xor(acc0, off);
@@ -254,8 +364,11 @@ k_aev_fwd(const float4 *__restrict__ pos, const int *__restrict__ sys_of,
           acc3 += __shfl_xor(acc3, off);
         }
         if (t0 == 0) {
-          float *o = Grow + c.rad_len + p * kAngBlock + a;
-          o[0] = acc0; o[kNShfZ] = acc1; o[2 * kNShfZ] = acc2; o[3 * kNShfZ] = acc3;
+          const int o = c.rad_len + p * kAngBlock + a;
+          put<BF16>(Grow, o, acc0);
+          put<BF16>(Grow, o + kNShfZ, acc1);
+          put<BF16>(Grow, o + 2 * kNShfZ, acc2);
+          put<BF16>(Grow, o + 3 * kNShfZ, acc3);
         }
       }
     }
@@ -314,83 +427,100 @@ k_aev_bwd(const float4 *__restrict__ pos, const int *__restrict__ sys_of,
     }
   }
 
-  // angular
+  wave_lds_sync();
+
+  // angular: lane per neighbour pair over the pair stream of all blocks
   {
-    const int a = lane & 7, t0 = lane >> 3, grp = lane & ~7;
-    const float cza = c.cz[a], sza = c.sz[a], shf_own = c.shf_a[a & 3];
+    const int nang = (c.S * (c.S + 1) / 2) * kAngBlock;
+    for (int k = lane; k < nang; k += kWave) w.gAng[k] = g[c.rad_len + k];
+    int nblk;
+    const int P = build_blocks(lane, ls, c.S, w, nblk);
+    wave_lds_sync();
     const float pre = 1.0f - c.zeta;
+    const float keta = -c.eta_a * 1.4426950408889634f;
     const float m2eta = -2.0f * c.eta_a;
-    int p = 0;
-    for (int sa = 0; sa < c.S; ++sa) {
-      for (int sb = sa; sb < c.S; ++sb, ++p) {
-        const int na = ls.cA[sa], nb = ls.cA[sb];
-        const int T = sa == sb ? na * (na - 1) / 2 : na * nb;
-        if (T == 0) continue;
-        const float *gp = g + c.rad_len + p * kAngBlock + a;
-        const float g0 = gp[0], g1 = gp[kNShfZ], g2 = gp[2 * kNShfZ], g3 = gp[3 * kNShfZ];
-        for (int base = 0; base < T; base += 8) {
-          const int t = base + t0;
-          const bool valid = t < T;
-          const int tt = valid ? t : T - 1;
-          int j, k;
-          if (sa == sb) unrank_upper(tt, na, j, k);
-          else { j = tt / nb; k = tt - j * nb; }
-          const int aj = ls.oA[sa] + j, ak = ls.oA[sb] + k;
-          const int qj = w.aIdx[aj], qk = w.aIdx[ak];
-          const float4 dj = w.rD[qj], dk = w.rD[qk];
-          const float fj = w.aFc[aj], fk = w.aFc[ak];
-          const float dfj = w.aDfc[aj], dfk = w.aDfc[ak];
-          const float dot = dj.x * dk.x + dj.y * dk.y + dj.z * dk.z;
-          const float cx = dj.y * dk.z - dj.z * dk.y;
-          const float cy = dj.z * dk.x - dj.x * dk.z;
-          const float cz = dj.x * dk.y - dj.y * dk.x;
-          const float cr = sqrtf(cx * cx + cy * cy + cz * cz);
-          const float RR = dj.w * dk.w;
-          const float invRR = 1.0f / RR;
-          const float cosv = dot * invRR, sinv = cr * invRR;
-          const float x = fmaxf(1.0f + cosv * cza + sinv * sza, 0.f);
+    int qb = 0;
+    for (int base = 0; base < P; base += kPairPass) {
+      while (qb + 1 < nblk && w.blk[qb + 1].start <= base) ++qb;
+      const bool valid = base + lane < P;
+      int aj, ak, p;
+      locate_pair(min(base + lane, P - 1), qb, nblk, base + kPairPass, w, aj, ak, p);
+      const int qj = w.aIdx[aj], qk = w.aIdx[ak];
+      const float4 dj = w.rD[qj], dk = w.rD[qk];
+      const float fj = w.aFc[aj], fk = w.aFc[ak];
+      const float dot = dj.x * dk.x + dj.y * dk.y + dj.z * dk.z;
+      const float cx = dj.y * dk.z - dj.z * dk.y;
+      const float cy = dj.z * dk.x - dj.x * dk.z;
+      const float cz = dj.x * dk.y - dj.y * dk.x;
+      const float cr = sqrtf(cx * cx + cy * cy + cz * cz);
+      const float RR = dj.w * dk.w;
+      const float invRR = 1.0f / RR;
+      const float cosv = dot * invRR, sinv = cr * invRR;
+      const float Rbar = 0.5f * (dj.w + dk.w);
+      float f2[kNShfAng], df2[kNShfAng];
+#pragma unroll
+      for (int r = 0; r < kNShfAng; ++r) {
+        const float u = Rbar - c.shf_a[r];
+        f2[r] = fast_exp2(keta * u * u);
+        df2[r] = m2eta * u * f2[r];
+      }
+      // dE/dG of this block: gv[r][a] at gAng[32 p + 8 r + a]
+      const float4 *gv = (const float4 *)(w.gAng + p * kAngBlock);
+      float dcos = 0.f, dsin = 0.f, dbar = 0.f, dfc = 0.f;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        float gq[kNShfAng][4];
+#pragma unroll
+        for (int r = 0; r < kNShfAng; ++r) {
+          const float4 v = gv[2 * r + h];
+          gq[r][0] = v.x; gq[r][1] = v.y; gq[r][2] = v.z; gq[r][3] = v.w;
+        }
+#pragma unroll
+        for (int aa = 0; aa < 4; ++aa) {
+          const int a = 4 * h + aa;
+          const float x = fmaxf(1.0f + cosv * c.cz[a] + sinv * c.sz[a], 0.f);
           // p1 = 2^(1-zeta) x^(zeta-1); f1 = p1 x; df1/dx = zeta p1
           const float p1 = fast_exp2((c.zeta - 1.0f) * fast_log2(x) + pre);
-          const float f1 = p1 * x, df1 = c.zeta * p1;
-          const float Rbar = 0.5f * (dj.w + dk.w);
-          const float u = Rbar - shf_own;
-          const float f2 = fast_exp(-c.eta_a * u * u);
-          const float f20 = __shfl(f2, grp | 0), f21 = __shfl(f2, grp | 1);
-          const float f22 = __shfl(f2, grp | 2), f23 = __shfl(f2, grp | 3);
-          const float A = g0 * f20 + g1 * f21 + g2 * f22 + g3 * f23;
-          const float B = m2eta * (g0 * (Rbar - c.shf_a[0]) * f20 + g1 * (Rbar - c.shf_a[1]) * f21 +
-                                   g2 * (Rbar - c.shf_a[2]) * f22 + g3 * (Rbar - c.shf_a[3]) * f23);
-          const float fcc = fj * fk;
-          const float dVdc = valid ? df1 * A * fcc : 0.f;
-          float dcos = dVdc * cza, dsin = dVdc * sza;
-          float dRj = valid ? f1 * (0.5f * B * fcc + A * dfj * fk) : 0.f;
-          float dRk = valid ? f1 * (0.5f * B * fcc + A * fj * dfk) : 0.f;
-          for (int off = 1; off < 8; off <<= 1) {
-            dcos += __shfl_xor(dcos, off);
-            dsin += __shfl_xor(dsin, off);
-            dRj += __shfl_xor(dRj, off);
-            dRk += __shfl_xor(dRk, off);
+          const float f1 = p1 * x;
+          float A = 0.f, B = 0.f;
+#pragma unroll
+          for (int r = 0; r < kNShfAng; ++r) {
+            A += gq[r][aa] * f2[r];
+            B += gq[r][aa] * df2[r];
           }
-          // lanes 0-2 of the pair own dE/dd_j (x,y,z), lanes 3-5 own dE/dd_k
-          if (valid && a < 6) {
-            const bool isj = a < 3;
-            const int comp = isj ? a : a - 3;
-            const float4 da = isj ? dj : dk, db = isj ? dk : dj;
-            const float Ra = da.w, Rb = db.w;
-            const float dac = comp == 0 ? da.x : (comp == 1 ? da.y : da.z);
-            const float dbc = comp == 0 ? db.x : (comp == 1 ? db.y : db.z);
-            const float invRa2 = 1.0f / (Ra * Ra);
-            const float inv_cr = cr > 1e-12f * RR ? 1.0f / cr : 0.f;
-            const float dcos_d = dbc * invRR - cosv * dac * invRa2;
-            const float dsin_d = inv_cr != 0.f
-                                     ? (Rb * Rb * dac - dot * dbc) * inv_cr * invRR - sinv * dac * invRa2
-                                     : 0.f;
-            const float val = dcos * dcos_d + dsin * dsin_d + (isj ? dRj : dRk) * dac / Ra;
-            atomicAdd(&w.rG[3 * (isj ? qj : qk) + comp], val);
-          }
+          const float s1 = c.zeta * p1 * A;
+          dcos += s1 * c.cz[a];
+          dsin += s1 * c.sz[a];
+          dbar += f1 * B;
+          dfc += f1 * A;
         }
       }
+      if (valid) {
+        const float fcc = fj * fk;
+        dcos *= fcc;
+        dsin *= fcc;
+        dbar *= 0.5f * fcc;  // via Rbar, for each of R_j and R_k
+        const float dRj = dbar + dfc * w.aDfc[aj] * fk;
+        const float dRk = dbar + dfc * fj * w.aDfc[ak];
+        const float inv_cr = cr > 1e-12f * RR ? 1.0f / cr : 0.f;
+        const float invj2 = 1.0f / (dj.w * dj.w), invk2 = 1.0f / (dk.w * dk.w);
+        const float aj_ = dcos * invRR, ak_ = dsin * inv_cr * invRR;
+        // d cos / d dj = dk / RR - cos dj / Rj^2 ; d sin / d dj =
+        // (Rk^2 dj - dot dk) / (|dj x dk| RR) - sin dj / Rj^2
+        const float cj = -(dcos * cosv + dsin * sinv) * invj2 + dRj / dj.w;
+        const float ck = -(dcos * cosv + dsin * sinv) * invk2 + dRk / dk.w;
+        const float sjj = ak_ * dk.w * dk.w, sjk = -ak_ * dot;
+        const float skk = ak_ * dj.w * dj.w, skj = -ak_ * dot;
+        float *gj = w.rG + 3 * qj, *gk = w.rG + 3 * qk;
+        atomicAdd(gj + 0, aj_ * dk.x + sjj * dj.x + sjk * dk.x + cj * dj.x);
+        atomicAdd(gj + 1, aj_ * dk.y + sjj * dj.y + sjk * dk.y + cj * dj.y);
+        atomicAdd(gj + 2, aj_ * dk.z + sjj * dj.z + sjk * dk.z + cj * dj.z);
+        atomicAdd(gk + 0, aj_ * dj.x + skk * dk.x + skj * dj.x + ck * dk.x);
+        atomicAdd(gk + 1, aj_ * dj.y + skk * dk.y + skj * dj.y + ck * dk.y);
+        atomicAdd(gk + 2, aj_ * dj.z + skk * dk.z + skj * dj.z + ck * dk.z);
+      }
     }
+    wave_lds_sync();
   }
 
   // scatter: F_i += dE/dd, F_j -= dE/dd, per-centre virial -sum d (x) dE/dd
@@ -439,19 +569,27 @@ static int waves_for_cap(int cap) {
   return 1;
 }
 
-void launch_aev_fwd(const float4 *pos, const int *sys_of, const SysDesc *sys, const int2 *nbr,
-                    const int *nbr_cnt, int cap, const int *row_of_atom, float *G, int ldg, int N,
-                    const AevConst &c, hipStream_t st) {
-  if (N <= 0) return;
+template <bool BF16>
+static void aev_fwd_t(const float4 *pos, const int *sys_of, const SysDesc *sys, const int2 *nbr,
+                      const int *nbr_cnt, int cap, const int *row_of_atom, void *G, int ldg, int N,
+                      const AevConst &c, hipStream_t st) {
   int wpb = waves_for_cap<false>(cap);
   size_t lds = wave_lds_bytes<false>(cap) * wpb;
   unsigned grid = (unsigned)((N + wpb - 1) / wpb);
   if (wpb == 4)
-    k_aev_fwd<4><<<grid, 4 * kWave, lds, st>>>(pos, sys_of, sys, nbr, nbr_cnt, cap, row_of_atom, G, ldg, N, c);
+    k_aev_fwd<4, BF16><<<grid, 4 * kWave, lds, st>>>(pos, sys_of, sys, nbr, nbr_cnt, cap, row_of_atom, G, ldg, N, c);
   else if (wpb == 2)
-    k_aev_fwd<2><<<grid, 2 * kWave, lds, st>>>(pos, sys_of, sys, nbr, nbr_cnt, cap, row_of_atom, G, ldg, N, c);
+    k_aev_fwd<2, BF16><<<grid, 2 * kWave, lds, st>>>(pos, sys_of, sys, nbr, nbr_cnt, cap, row_of_atom, G, ldg, N, c);
   else
-    k_aev_fwd<1><<<grid, kWave, lds, st>>>(pos, sys_of, sys, nbr, nbr_cnt, cap, row_of_atom, G, ldg, N, c);
+    k_aev_fwd<1, BF16><<<grid, kWave, lds, st>>>(pos, sys_of, sys, nbr, nbr_cnt, cap, row_of_atom, G, ldg, N, c);
+}
+
+void launch_aev_fwd(const float4 *pos, const int *sys_of, const SysDesc *sys, const int2 *nbr,
+                    const int *nbr_cnt, int cap, const int *row_of_atom, void *G, bool g_bf16,
+                    int ldg, int N, const AevConst &c, hipStream_t st) {
+  if (N <= 0) return;
+  if (g_bf16) aev_fwd_t<true>(pos, sys_of, sys, nbr, nbr_cnt, cap, row_of_atom, G, ldg, N, c, st);
+  else aev_fwd_t<false>(pos, sys_of, sys, nbr, nbr_cnt, cap, row_of_atom, G, ldg, N, c, st);
 }
 
 void launch_aev_bwd(const float4 *pos, const int *sys_of, const SysDesc *sys, const int2 *nbr,

@@ -89,6 +89,9 @@ struct nnp_model {
   std::vector<std::vector<int>> widths;  // [S][L+1]
   std::vector<int> ldH;                  // [L-1] max width of hidden layer l
   std::vector<LayerW> layers;            // [(M * S + s) * L + l]
+  // per species: [D][M * n1] = members' first-layer W^T side by side (dE/dG)
+  std::vector<float *> Wdg;
+  std::vector<uint16_t *> Wdg_b;
   std::vector<void *> weight_allocs;
   int cap = 256;                         // neighbour capacity per atom
 
@@ -159,6 +162,7 @@ static int create_impl(const nnp_model_desc *d, nnp_model *m) {
     return fail(NNP_EUNSUPPORTED, "need 0 < rc_ang <= rc_rad");
   if (!(a.zeta >= 1.f)) return fail(NNP_EUNSUPPORTED, "zeta must be >= 1");
   if (d->n_ensemble < 1) return fail(NNP_EINVAL, "n_ensemble must be >= 1");
+  if (d->n_ensemble > kMaxMembers) return fail(NNP_EUNSUPPORTED, "at most %d ensemble members", kMaxMembers);
   if (!d->n_layers || !d->widths || !d->weights) return fail(NNP_EINVAL, "null network array");
   if (d->precision != NNP_FP32 && d->precision != NNP_BF16) return fail(NNP_EINVAL, "bad precision");
   if (!(d->celu_alpha > 0.f)) return fail(NNP_EINVAL, "celu_alpha must be > 0");
@@ -233,6 +237,35 @@ static int create_impl(const nnp_model_desc *d, nnp_model *m) {
         if ((rc = upload(m, wp, (size_t)lw.n_out * 4, (void **)&lw.b))) return rc;
         wp += lw.n_out;
       }
+  if (L >= 2) {
+    m->Wdg.assign(S, nullptr);
+    m->Wdg_b.assign(S, nullptr);
+    const float *base = d->weights;
+    // offsets of (member, species) first layers in the flat weight array
+    std::vector<size_t> off((size_t)m->M * S);
+    size_t o = 0;
+    for (int mb = 0; mb < m->M; ++mb)
+      for (int s = 0; s < S; ++s) {
+        off[(size_t)mb * S + s] = o;
+        for (int l = 0; l < L; ++l) o += (size_t)m->widths[s][l] * m->widths[s][l + 1] + m->widths[s][l + 1];
+      }
+    for (int s = 0; s < S; ++s) {
+      const int D = m->widths[s][0], n1 = m->widths[s][1], MK = m->M * n1;
+      std::vector<float> cat((size_t)D * MK);
+      for (int mb = 0; mb < m->M; ++mb) {
+        const float *W0 = base + off[(size_t)mb * S + s];  // [n1][D]
+        for (int k = 0; k < n1; ++k)
+          for (int dd = 0; dd < D; ++dd) cat[(size_t)dd * MK + (size_t)mb * n1 + k] = W0[(size_t)k * D + dd];
+      }
+      int rc;
+      if ((rc = upload(m, cat.data(), cat.size() * 4, (void **)&m->Wdg[s]))) return rc;
+      if (m->precision == NNP_BF16) {
+        std::vector<uint16_t> cb(cat.size());
+        round_bf16_host(cat.data(), cb.data(), cat.size());
+        if ((rc = upload(m, cb.data(), cb.size() * 2, (void **)&m->Wdg_b[s]))) return rc;
+      }
+    }
+  }
   HIP_TRY(hipEventCreateWithFlags(&m->stage_done, hipEventDisableTiming));
   for (auto &e : m->ev) HIP_TRY(hipEventCreate(&e));
   int rc = m->status.ensure(2 * sizeof(int));
@@ -276,7 +309,8 @@ static int ensure_ws(nnp_model *m, int64_t N, int S, int64_t C, int n_chunks) {
   ENS(m->bucket_cnt, kMaxSpecies * 4);
   ENS(m->perm, rows * 4);
   ENS(m->row_of_atom, N * 4);
-  ENS(m->G, rows * m->aev.D * 4);
+  const int esz = m->precision == NNP_BF16 ? 2 : 4;  // activation element size
+  ENS(m->G, rows * m->aev.D * esz);
   ENS(m->dG, rows * m->aev.D * 4);
   ENS(m->e_atom, N * 4);
   ENS(m->W_atom, N * 36);
@@ -286,8 +320,8 @@ static int ensure_ws(nnp_model *m, int64_t N, int S, int64_t C, int n_chunks) {
   ENS(m->chunk_begin, (int64_t)n_chunks * 4 + 4);
   ENS(m->sys_chunk_off, (int64_t)(S + 1) * 4);
   for (int l = 0; l + 1 < m->L; ++l) {
-    ENS(m->H[l], rows * m->ldH[l] * 4);
-    ENS(m->Gd[l], rows * m->ldH[l] * 4);
+    ENS(m->H[l], rows * m->ldH[l] * m->M * esz);
+    ENS(m->Gd[l], rows * m->ldH[l] * m->M * esz);
   }
 #undef ENS
   return NNP_OK;
@@ -405,7 +439,9 @@ static int run(nnp_model *m, int n_sys, const int64_t *offs, const float *coords
       if (cells > ((int64_t)1 << 26)) return fail(NNP_EUNSUPPORTED, "system %d: too many cells", s);
       d.cell_cap = (int)cells;
     } else {
-      d.cell_cap = std::max(1, d.n);
+      // bounding-box grid of cells >= rc; a cell holds ~10-80 atoms at the
+      // densities of molecular systems, so a quarter of the atom count bounds it
+      d.cell_cap = std::max(1, d.n / 4);
     }
     C += d.cell_cap;
     sys_ch[s] = (int)ch_sys.size();
@@ -482,108 +518,127 @@ static int run(nnp_model *m, int n_sys, const int64_t *offs, const float *coords
   const int rows = (N + kTileM - 1) / kTileM * kTileM + m->S * kTileM;
   launch_species_bucket(pos, N, m->S, m->block_counts.as<int>(), nblk, m->bucket_off.as<int>(),
                         m->bucket_cnt.as<int>(), m->perm.as<int>(), m->row_of_atom.as<int>(), rows, st);
+  if (mode == kFull && o.forces) launch_fill(o.forces, (size_t)3 * N, 0.f, st);
   mark();
   const int D = m->aev.D;
-  launch_aev_fwd(pos, m->sys_of.as<int>(), dsys, m->nbr.as<int2>(), m->nbr_cnt.as<int>(), m->cap,
-                 m->row_of_atom.as<int>(), m->G.as<float>(), D, N, m->aev, st);
+  const bool bf16 = m->precision == NNP_BF16;
   if (mode == kAev) {
-    launch_gather_rows(m->G.as<float>(), D, m->row_of_atom.as<int>(), N, D, o.aev, st);
+    // float32 AEV into the (float32) dE/dG buffer, then back to atom order
+    launch_aev_fwd(pos, m->sys_of.as<int>(), dsys, m->nbr.as<int2>(), m->nbr_cnt.as<int>(), m->cap,
+                   m->row_of_atom.as<int>(), m->dG.p, false, D, N, m->aev, st);
+    launch_gather_rows(m->dG.as<float>(), D, m->row_of_atom.as<int>(), N, D, o.aev, st);
     HIP_TRY(hipGetLastError());
     return NNP_OK;
   }
+  launch_aev_fwd(pos, m->sys_of.as<int>(), dsys, m->nbr.as<int2>(), m->nbr_cnt.as<int>(), m->cap,
+                 m->row_of_atom.as<int>(), m->G.p, bf16, D, N, m->aev, st);
   mark();
 
-  // element networks: forward, output layer, backward to dE/dG
+  // element networks: forward, output layer, backward to dE/dG; every launch
+  // covers all species and all ensemble members of one layer index
   const bool want_grad = o.forces != nullptr;
-  const bool bf16 = m->precision == NNP_BF16;
   const int row_tiles = rows / kTileM;
-  const int L = m->L;
-  for (int mb = 0; mb < m->M; ++mb) {
-    for (int l = 0; l + 1 < L; ++l) {
-      GemmLaunch gl{};
-      gl.A = l == 0 ? m->G.as<float>() : m->H[l - 1].as<float>();
-      gl.lda = l == 0 ? D : m->ldH[l - 1];
-      gl.C = m->H[l].as<float>();
-      gl.ldc = m->ldH[l];
-      gl.bucket_off = m->bucket_off.as<int>();
-      gl.n_groups = m->S;
-      gl.alpha = m->alpha;
-      gl.scale = 1.f;
-      for (int s = 0; s < m->S; ++s) {
+  const int L = m->L, M = m->M, S = m->S;
+  auto common = [&](GemmLaunch &gl) {
+    gl.bucket_off = m->bucket_off.as<int>();
+    gl.n_groups = S;
+    gl.alpha = m->alpha;
+    gl.scale = 1.f;
+    gl.n_members = M;
+    gl.n_seg = 1;
+  };
+  for (int l = 0; l + 1 < L; ++l) {
+    GemmLaunch gl{};
+    common(gl);
+    gl.A = l == 0 ? m->G.p : m->H[l - 1].p;
+    gl.lda = l == 0 ? D : M * m->ldH[l - 1];
+    gl.a_member_stride = l == 0 ? 0 : m->ldH[l - 1];
+    gl.C = m->H[l].p;
+    gl.ldc = M * m->ldH[l];
+    gl.c_member_stride = m->ldH[l];
+    for (int mb = 0; mb < M; ++mb)
+      for (int s = 0; s < S; ++s) {
         LayerW &lw = m->layer(mb, s, l);
-        gl.g[s].B = bf16 ? (const void *)lw.Wb : (const void *)lw.W;
-        gl.g[s].bias = lw.b;
-        gl.g[s].n_out = lw.n_out;
-        gl.g[s].K = lw.n_in;
+        GemmGroup &g = gl.g[mb * S + s];
+        g.B = bf16 ? (const void *)lw.Wb : (const void *)lw.W;
+        g.bias = lw.b;
+        g.n_out = lw.n_out;
+        g.K = lw.n_in;
       }
-      launch_gemm(kEpiFwd, bf16, gl, row_tiles, m->ldH[l], st);
-    }
+    launch_gemm(kEpiFwd, bf16, gl, row_tiles, m->ldH[l], st);
+  }
+  {
     EnergyLaunch el{};
-    el.Hin = L >= 2 ? m->H[L - 2].as<float>() : m->G.as<float>();
-    el.ldh = L >= 2 ? m->ldH[L - 2] : D;
-    el.Gout = L >= 2 ? m->Gd[L - 2].as<float>() : m->dG.as<float>();
-    el.ldg = L >= 2 ? m->ldH[L - 2] : D;
-    for (int s = 0; s < m->S; ++s) {
-      LayerW &lw = m->layer(mb, s, L - 1);
-      el.w[s] = lw.W;
-      el.b[s] = lw.b;
-      el.K[s] = lw.n_in;
-    }
+    el.Hin = L >= 2 ? m->H[L - 2].p : m->G.p;
+    el.ldh = L >= 2 ? M * m->ldH[L - 2] : D;
+    el.h_member_stride = L >= 2 ? m->ldH[L - 2] : 0;
+    el.Gout = L >= 2 ? m->Gd[L - 2].p : m->dG.p;
+    el.ldg = L >= 2 ? M * m->ldH[L - 2] : D;
+    el.g_member_stride = L >= 2 ? m->ldH[L - 2] : 0;
+    for (int mb = 0; mb < M; ++mb)
+      for (int s = 0; s < S; ++s) {
+        LayerW &lw = m->layer(mb, s, L - 1);
+        el.w[mb * S + s] = lw.W;
+        el.b[mb * S + s] = lw.b;
+        el.K[s] = lw.n_in;
+      }
     el.perm = m->perm.as<int>();
     el.bucket_off = m->bucket_off.as<int>();
-    el.n_groups = m->S;
+    el.n_groups = S;
+    el.n_members = M;
     el.e_atom = m->e_atom.as<float>();
-    el.inv_m = 1.0f / (float)m->M;
+    el.inv_m = 1.0f / (float)M;
     el.alpha = m->alpha;
-    el.first = mb == 0;
     el.hidden = L >= 2;
     el.want_grad = want_grad;
-    el.accumulate_grad = L == 1 && mb > 0;
-    launch_energy(el, rows, st);
-    if (!want_grad) continue;
+    // the no-hidden-layer form reads float32 AEVs and writes float32 dE/dG
+    launch_energy(el, bf16, rows, st);
+  }
+  if (want_grad) {
     for (int l = L - 2; l >= 1; --l) {
       GemmLaunch gl{};
-      gl.A = m->Gd[l].as<float>();
-      gl.lda = m->ldH[l];
-      gl.C = m->Gd[l - 1].as<float>();
-      gl.ldc = m->ldH[l - 1];
-      gl.H = m->H[l - 1].as<float>();
-      gl.ldh = m->ldH[l - 1];
-      gl.bucket_off = m->bucket_off.as<int>();
-      gl.n_groups = m->S;
-      gl.alpha = m->alpha;
-      gl.scale = 1.f;
-      for (int s = 0; s < m->S; ++s) {
-        LayerW &lw = m->layer(mb, s, l);
-        gl.g[s].B = bf16 ? (const void *)lw.Wtb : (const void *)lw.Wt;
-        gl.g[s].n_out = lw.n_in;
-        gl.g[s].K = lw.n_out;
-      }
+      common(gl);
+      gl.A = m->Gd[l].p;
+      gl.lda = M * m->ldH[l];
+      gl.a_member_stride = m->ldH[l];
+      gl.C = m->Gd[l - 1].p;
+      gl.ldc = M * m->ldH[l - 1];
+      gl.c_member_stride = m->ldH[l - 1];
+      gl.H = m->H[l - 1].p;
+      gl.ldh = M * m->ldH[l - 1];
+      gl.h_member_stride = m->ldH[l - 1];
+      for (int mb = 0; mb < M; ++mb)
+        for (int s = 0; s < S; ++s) {
+          LayerW &lw = m->layer(mb, s, l);
+          GemmGroup &g = gl.g[mb * S + s];
+          g.B = bf16 ? (const void *)lw.Wtb : (const void *)lw.Wt;
+          g.n_out = lw.n_in;
+          g.K = lw.n_out;
+        }
       launch_gemm(kEpiBwd, bf16, gl, row_tiles, m->ldH[l - 1], st);
     }
     if (L >= 2) {
+      // dE/dG = sum over members of delta_0^m W_0^m: members are K segments
       GemmLaunch gl{};
-      gl.A = m->Gd[0].as<float>();
-      gl.lda = m->ldH[0];
-      gl.C = m->dG.as<float>();
+      common(gl);
+      gl.n_members = 1;
+      gl.n_seg = M;
+      gl.A = m->Gd[0].p;
+      gl.lda = M * m->ldH[0];
+      gl.a_seg_stride = m->ldH[0];
+      gl.C = m->dG.p;
       gl.ldc = D;
-      gl.bucket_off = m->bucket_off.as<int>();
-      gl.n_groups = m->S;
-      gl.alpha = m->alpha;
-      gl.scale = 1.f;
-      gl.accumulate = mb > 0;
-      for (int s = 0; s < m->S; ++s) {
-        LayerW &lw = m->layer(mb, s, 0);
-        gl.g[s].B = bf16 ? (const void *)lw.Wtb : (const void *)lw.Wt;
-        gl.g[s].n_out = lw.n_in;
-        gl.g[s].K = lw.n_out;
+      for (int s = 0; s < S; ++s) {
+        GemmGroup &g = gl.g[s];
+        g.B = bf16 ? (const void *)m->Wdg_b[s] : (const void *)m->Wdg[s];
+        g.n_out = D;
+        g.K = m->widths[s][1];
       }
       launch_gemm(kEpiOut, bf16, gl, row_tiles, D, st);
     }
   }
   mark();
   if (want_grad) {
-    launch_fill(o.forces, (size_t)3 * N, 0.f, st);
     launch_aev_bwd(pos, m->sys_of.as<int>(), dsys, m->nbr.as<int2>(), m->nbr_cnt.as<int>(), m->cap,
                    m->row_of_atom.as<int>(), m->dG.as<float>(), D, N, m->aev, o.forces,
                    m->W_atom.as<float>(), st);

@@ -55,38 +55,46 @@ __host__ __device__ inline void unpack_image(int c, int &x, int &y, int &z) {
 }
 
 // ---- dense layers
+constexpr int kMaxMembers = 8;  // ensemble members
+
 struct GemmGroup {
-  const void *B;      // [n_out][K] row-major, float or bf16
+  const void *B;      // [n_out][n_seg * K] row-major, float or bf16
   const float *bias;  // [n_out] (forward only)
-  int n_out, K;
+  int n_out, K;       // K per segment
 };
 
 struct GemmLaunch {
-  const float *A; int lda;   // [rows][>=K] float32 activations
-  float *C; int ldc;         // [rows][>=n_out]
-  const float *H; int ldh;   // backward: layer input activations for CELU'
-  const int *bucket_off;     // [n_groups + 1] padded row offsets (device)
-  int n_groups;
-  GemmGroup g[kMaxSpecies];
-  float alpha;               // CELU alpha
+  const void *A; int lda;      // [rows][...] activations (operand type)
+  int a_member_stride;         // column offset of member m's input
+  int a_seg_stride;            // column offset of K segment q
+  void *C; int ldc;            // output
+  int c_member_stride;
+  const void *H; int ldh;      // backward: layer input activations for CELU'
+  int h_member_stride;
+  const int *bucket_off;       // [n_groups + 1] padded row offsets (device)
+  int n_groups;                // species
+  int n_members;               // grid dimension over ensemble members
+  int n_seg;                   // K segments summed into one output
+  int col_tiles;               // set by the launcher
+  GemmGroup g[kMaxMembers * kMaxSpecies];  // [member][species]
+  float alpha;                 // CELU alpha
   float scale;
-  int accumulate;
 };
 
 enum { kEpiFwd = 0, kEpiBwd = 1, kEpiOut = 2 };
 
 struct EnergyLaunch {
-  const float *Hin; int ldh;  // input of the last layer
-  float *Gout; int ldg;       // dE/d(input), scaled by inv_m
-  const float *w[kMaxSpecies];
-  const float *b[kMaxSpecies];
+  const void *Hin; int ldh; int h_member_stride;  // input of the last layer
+  void *Gout; int ldg; int g_member_stride;       // dE/d(input), scaled by inv_m
+  const float *w[kMaxMembers * kMaxSpecies];
+  const float *b[kMaxMembers * kMaxSpecies];
   int K[kMaxSpecies];
   const int *perm;            // row -> atom (-1 padding)
   const int *bucket_off;
-  int n_groups;
+  int n_groups, n_members;
   float *e_atom;
   float inv_m, alpha;
-  int first, hidden, want_grad, accumulate_grad;
+  int hidden, want_grad;
 };
 
 // ---- launchers (stream-ordered, no host sync)
@@ -107,14 +115,13 @@ void launch_species_bucket(const float4 *pos, int N, int S, int *block_counts, i
                            int *bucket_off, int *bucket_cnt, int *perm, int *row_of_atom,
                            int rows_cap, hipStream_t st);
 void launch_aev_fwd(const float4 *pos, const int *sys_of, const SysDesc *sys, const int2 *nbr,
-                    const int *nbr_cnt, int cap, const int *row_of_atom, float *G, int ldg,
-                    int N, const AevConst &c, hipStream_t st);
+                    const int *nbr_cnt, int cap, const int *row_of_atom, void *G, bool g_bf16,
+                    int ldg, int N, const AevConst &c, hipStream_t st);
 void launch_aev_bwd(const float4 *pos, const int *sys_of, const SysDesc *sys, const int2 *nbr,
                     const int *nbr_cnt, int cap, const int *row_of_atom, const float *dG,
                     int ldg, int N, const AevConst &c, float *F, float *W_atom, hipStream_t st);
-void launch_gemm(int epi, bool bf16, const GemmLaunch &gl, int row_tiles, int max_n_out,
-                 hipStream_t st);
-void launch_energy(const EnergyLaunch &el, int rows, hipStream_t st);
+void launch_gemm(int epi, bool bf16, GemmLaunch gl, int row_tiles, int max_n_out, hipStream_t st);
+void launch_energy(const EnergyLaunch &el, bool bf16, int rows, hipStream_t st);
 void launch_fill(float *p, size_t n, float v, hipStream_t st);
 void launch_fill_i32(int *p, size_t n, int v, hipStream_t st);
 void launch_reduce(const float *e_atom, const float *W_atom, const SysDesc *sys, int n_sys,

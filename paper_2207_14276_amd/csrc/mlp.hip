@@ -4,15 +4,20 @@
 //
 // Dense layers are grouped GEMMs over species buckets: rows of one species
 // are contiguous and padded to 128, so a 128-row tile always belongs to one
-// network and every launch covers all species of one layer index.
-//   C[rows, n_out] = A[rows, 0:K] . B[n_out, 0:K]^T  with a fused epilogue:
-//     forward:  CELU(acc + bias)                    -> hidden activations
-//     backward: acc * CELU'(layer input)            -> input gradient
-//     output:   (C +=) acc * scale                  -> dE/dG
-// MFMA: v_mfma_f32_32x32x2_f32 (float32 form) or v_mfma_f32_32x32x16_bf16
-// (bfloat16 operands, float32 accumulate).  A workgroup of 4 waves computes a
-// 128 x 64 tile; each wave a 32 x 64 strip as two 32x32 MFMA blocks that
-// share the A fragment.
+// network, and one launch covers all species and all ensemble members of one
+// layer index (members side by side in the activation buffers).
+//   C[rows, n_out] = sum over K segments of A[rows, seg] . B[n_out, seg]^T
+// with a fused epilogue:
+//     forward:  CELU(acc + bias)              -> hidden activations
+//     backward: acc * CELU'(layer input)      -> input gradient
+//     output:   acc * scale (float32)         -> dE/dG, ensemble summed along K
+// Activations are stored in the operand type: float32 for the float32 model
+// (v_mfma_f32_32x32x2_f32), bfloat16 for the bfloat16 model
+// (v_mfma_f32_32x32x16_bf16, float32 accumulate).
+// A workgroup of 4 waves computes a 128 x TN tile (TN = 128: 2 x 2 waves of
+// 64 x 64, TN = 64: 4 x 1 waves of 32 x 64), K staged through double-buffered
+// LDS.  Blocks are renumbered so that consecutive logical blocks (which share
+// an A row tile) run on the same XCD and hit the same L2.
 #include "internal.h"
 
 namespace nnp {
@@ -20,169 +25,241 @@ namespace nnp {
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
-constexpr int kTN = 64;
-
 __device__ inline uint32_t bf16_bits_rne(float f) {
   uint32_t u = __float_as_uint(f);
   u += 0x7fffu + ((u >> 16) & 1u);
   return u >> 16;
 }
+__device__ inline float bf16_to_f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
-__device__ inline uint2 pack4_bf16(float4 v) {
-  uint2 r;
-  r.x = bf16_bits_rne(v.x) | (bf16_bits_rne(v.y) << 16);
-  r.y = bf16_bits_rne(v.z) | (bf16_bits_rne(v.w) << 16);
-  return r;
-}
+template <bool BF16> struct Op;
+template <> struct Op<false> {
+  typedef float T;
+  static __device__ inline float load(const float *p) { return *p; }
+  static __device__ inline void store(float *p, float v) { *p = v; }
+};
+template <> struct Op<true> {
+  typedef uint16_t T;
+  static __device__ inline float load(const uint16_t *p) { return bf16_to_f(*p); }
+  static __device__ inline void store(uint16_t *p, float v) { *p = (uint16_t)bf16_bits_rne(v); }
+};
 
 __device__ inline float celu(float z, float alpha) { return z > 0.f ? z : alpha * expm1f(z / alpha); }
 
 // CELU'(z) from h = CELU(z): 1 for h > 0, else exp(z / alpha) = 1 + h / alpha.
 __device__ inline float dcelu_from_h(float h, float alpha) { return h > 0.f ? 1.f : 1.f + h / alpha; }
 
-template <int EPI, bool BF16>
-__global__ void __launch_bounds__(256) k_gemm(GemmLaunch gl) {
-  constexpr int TM = kTileM, TN = kTN;
-  constexpr int TK = BF16 ? 64 : 32;
-  constexpr int PADF = 1;   // float32 row padding (words)
-  constexpr int PADH = 8;   // bf16 row padding (halves)
-  constexpr int LDA = BF16 ? TK + PADH : TK + PADF;
-  __shared__ __attribute__((aligned(16))) char smem[BF16 ? (TM + TN) * LDA * 2 : (TM + TN) * LDA * 4];
+// Workgroups are dispatched round-robin over the 8 XCDs; map them so that
+// each XCD walks a contiguous range of logical block numbers.
+__device__ inline int xcd_logical(int bid, int nb) {
+  constexpr int X = 8;
+  const int q = nb / X, r = nb % X;
+  const int x = bid % X, k = bid / X;
+  return x * q + min(x, r) + k;
+}
 
-  const int r0 = blockIdx.x * TM;
+template <int EPI, bool BF16, int TN>
+__global__ void __launch_bounds__(256) k_gemm(GemmLaunch gl) {
+  typedef typename Op<BF16>::T T;
+  constexpr int TM = kTileM;
+  constexpr int TK = BF16 ? 32 : 16;
+  constexpr int PAD = BF16 ? 8 : 1;          // row padding in elements
+  constexpr int LD = TK + PAD;
+  constexpr int WM = TN == 128 ? 64 : 32;    // wave tile rows
+  constexpr int WN = 64;                     // wave tile cols
+  constexpr int WAVES_N = TN / WN;
+  constexpr int BM = WM / 32, BN = WN / 32;  // 32x32 MFMA blocks per wave
+  constexpr int EPV = 16 / sizeof(T);        // elements per 16-byte vector
+  constexpr int A_VEC = TM * TK / EPV / 256; // 16-byte loads per thread
+  constexpr int B_VEC = TN * TK / EPV / 256;
+  static_assert(A_VEC >= 1 && B_VEC >= 1, "tile too small");
+  __shared__ __attribute__((aligned(16))) T smem[2][(TM + TN) * LD];
+
+  // logical block -> (row tile, member, col tile); columns fastest
+  const int nb = gridDim.x;
+  const int lb = xcd_logical(blockIdx.x, nb);
+  const int n_ct = gl.col_tiles;
+  const int ct = lb % n_ct;
+  const int mb = (lb / n_ct) % gl.n_members;
+  const int rt = lb / (n_ct * gl.n_members);
+  const int r0 = rt * TM;
   int s = -1;
   for (int q = 0; q < gl.n_groups; ++q)
     if (r0 >= gl.bucket_off[q] && r0 < gl.bucket_off[q + 1]) s = q;
   if (s < 0) return;
-  const GemmGroup grp = gl.g[s];
-  const int c0 = blockIdx.y * TN;
+  const GemmGroup grp = gl.g[mb * gl.n_groups + s];
+  const int c0 = ct * TN;
   if (c0 >= grp.n_out) return;
-  const int K = grp.K;
+  const int K = grp.K;                 // per segment
+  const int nseg = gl.n_seg;
+  const int nk = (K + TK - 1) / TK;    // chunks per segment
+  const int total = nk * nseg;
+
   const int tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
   const int l32 = lane & 31, hi = lane >> 5;
+  const int wr = wave / WAVES_N, wc = wave % WAVES_N;
 
-  floatx16 acc0 = {}, acc1 = {};
-  const float *A = gl.A + (size_t)r0 * gl.lda;
+  const T *A = (const T *)gl.A + (size_t)r0 * gl.lda + (size_t)mb * gl.a_member_stride;
+  const T *B = (const T *)grp.B;
+  const size_t ldb = (size_t)K * nseg;
 
-  for (int k0 = 0; k0 < K; k0 += TK) {
-    if (BF16) {
-      uint16_t *As = (uint16_t *)smem;
-      uint16_t *Bs = As + TM * LDA;
-      // A: TM x TK floats -> bf16
+  uint4 ra[A_VEC], rb[B_VEC];
+  auto load_chunk = [&](int c) {
+    const int seg = c / nk, k0 = (c % nk) * TK;
 #pragma unroll
-      for (int q = 0; q < (TM * TK / 4) / 256; ++q) {
-        int idx = q * 256 + tid;
-        int row = idx / (TK / 4), c4 = idx % (TK / 4);
-        int k = k0 + c4 * 4;
-        float4 v = k < K ? *(const float4 *)(A + (size_t)row * gl.lda + k) : make_float4(0.f, 0.f, 0.f, 0.f);
-        *(uint2 *)(As + row * LDA + c4 * 4) = pack4_bf16(v);
-      }
-      // B: TN x TK bf16, 8 per load
-      const uint16_t *B = (const uint16_t *)grp.B;
+    for (int q = 0; q < A_VEC; ++q) {
+      const int idx = q * 256 + tid;
+      const int row = idx / (TK / EPV), cv = idx % (TK / EPV);
+      const int k = k0 + cv * EPV;
+      ra[q] = k < K ? *(const uint4 *)(A + (size_t)row * gl.lda + (size_t)seg * gl.a_seg_stride + k)
+                    : make_uint4(0u, 0u, 0u, 0u);
+    }
 #pragma unroll
-      for (int q = 0; q < (TN * TK / 8) / 256; ++q) {
-        int idx = q * 256 + tid;
-        int row = idx / (TK / 8), c8 = idx % (TK / 8);
-        int k = k0 + c8 * 8, col = c0 + row;
-        uint4 v = (k < K && col < grp.n_out) ? *(const uint4 *)(B + (size_t)col * K + k)
-                                             : make_uint4(0u, 0u, 0u, 0u);
-        *(uint4 *)(Bs + row * LDA + c8 * 8) = v;
-      }
-    } else {
-      float *As = (float *)smem;
-      float *Bs = As + TM * LDA;
+    for (int q = 0; q < B_VEC; ++q) {
+      const int idx = q * 256 + tid;
+      const int row = idx / (TK / EPV), cv = idx % (TK / EPV);
+      const int k = k0 + cv * EPV, col = c0 + row;
+      rb[q] = (k < K && col < grp.n_out) ? *(const uint4 *)(B + (size_t)col * ldb + (size_t)seg * K + k)
+                                         : make_uint4(0u, 0u, 0u, 0u);
+    }
+  };
+  auto store_chunk = [&](int buf) {
+    T *As = smem[buf];
+    T *Bs = As + TM * LD;
 #pragma unroll
-      for (int q = 0; q < (TM * TK / 4) / 256; ++q) {
-        int idx = q * 256 + tid;
-        int row = idx / (TK / 4), c4 = idx % (TK / 4);
-        int k = k0 + c4 * 4;
-        float4 v = k < K ? *(const float4 *)(A + (size_t)row * gl.lda + k) : make_float4(0.f, 0.f, 0.f, 0.f);
-        float *d = As + row * LDA + c4 * 4;
-        d[0] = v.x; d[1] = v.y; d[2] = v.z; d[3] = v.w;
-      }
-      const float *B = (const float *)grp.B;
-#pragma unroll
-      for (int q = 0; q < (TN * TK / 4) / 256; ++q) {
-        int idx = q * 256 + tid;
-        int row = idx / (TK / 4), c4 = idx % (TK / 4);
-        int k = k0 + c4 * 4, col = c0 + row;
-        float4 v = (k < K && col < grp.n_out) ? *(const float4 *)(B + (size_t)col * K + k)
-                                              : make_float4(0.f, 0.f, 0.f, 0.f);
-        float *d = Bs + row * LDA + c4 * 4;
-        d[0] = v.x; d[1] = v.y; d[2] = v.z; d[3] = v.w;
+    for (int q = 0; q < A_VEC; ++q) {
+      const int idx = q * 256 + tid;
+      const int row = idx / (TK / EPV), cv = idx % (TK / EPV);
+      if (BF16) {
+        *(uint4 *)(As + row * LD + cv * EPV) = ra[q];
+      } else {
+        float *d = (float *)(As + row * LD + cv * EPV);
+        d[0] = __uint_as_float(ra[q].x); d[1] = __uint_as_float(ra[q].y);
+        d[2] = __uint_as_float(ra[q].z); d[3] = __uint_as_float(ra[q].w);
       }
     }
-    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < B_VEC; ++q) {
+      const int idx = q * 256 + tid;
+      const int row = idx / (TK / EPV), cv = idx % (TK / EPV);
+      if (BF16) {
+        *(uint4 *)(Bs + row * LD + cv * EPV) = rb[q];
+      } else {
+        float *d = (float *)(Bs + row * LD + cv * EPV);
+        d[0] = __uint_as_float(rb[q].x); d[1] = __uint_as_float(rb[q].y);
+        d[2] = __uint_as_float(rb[q].z); d[3] = __uint_as_float(rb[q].w);
+      }
+    }
+  };
+
+  floatx16 acc[BM][BN];
+#pragma unroll
+  for (int i = 0; i < BM; ++i)
+#pragma unroll
+    for (int j = 0; j < BN; ++j) acc[i][j] = floatx16{};
+
+  load_chunk(0);
+  store_chunk(0);
+  __syncthreads();
+  for (int c = 0; c < total; ++c) {
+    const int cur = c & 1;
+    if (c + 1 < total) load_chunk(c + 1);
+    const T *As = smem[cur];
+    const T *Bs = As + TM * LD;
     if (BF16) {
-      const uint16_t *As = (const uint16_t *)smem;
-      const uint16_t *Bs = As + TM * LDA;
 #pragma unroll
       for (int kk = 0; kk < TK; kk += 16) {
-        bf16x8 a = __builtin_bit_cast(bf16x8, *(const uint4 *)(As + (wave * 32 + l32) * LDA + kk + 8 * hi));
-        bf16x8 b0 = __builtin_bit_cast(bf16x8, *(const uint4 *)(Bs + l32 * LDA + kk + 8 * hi));
-        bf16x8 b1 = __builtin_bit_cast(bf16x8, *(const uint4 *)(Bs + (32 + l32) * LDA + kk + 8 * hi));
-        acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b0, acc0, 0, 0, 0);
-        acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b1, acc1, 0, 0, 0);
+        bf16x8 a[BM], b[BN];
+#pragma unroll
+        for (int i = 0; i < BM; ++i)
+          a[i] = __builtin_bit_cast(bf16x8, *(const uint4 *)(As + (wr * WM + i * 32 + l32) * LD + kk + 8 * hi));
+#pragma unroll
+        for (int j = 0; j < BN; ++j)
+          b[j] = __builtin_bit_cast(bf16x8, *(const uint4 *)(Bs + (wc * WN + j * 32 + l32) * LD + kk + 8 * hi));
+#pragma unroll
+        for (int i = 0; i < BM; ++i)
+#pragma unroll
+          for (int j = 0; j < BN; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
       }
     } else {
-      const float *As = (const float *)smem;
-      const float *Bs = As + TM * LDA;
 #pragma unroll
       for (int kk = 0; kk < TK; kk += 2) {
-        float a = As[(wave * 32 + l32) * LDA + kk + hi];
-        float b0 = Bs[l32 * LDA + kk + hi];
-        float b1 = Bs[(32 + l32) * LDA + kk + hi];
-        acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b0, acc0, 0, 0, 0);
-        acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b1, acc1, 0, 0, 0);
+        float a[BM], b[BN];
+#pragma unroll
+        for (int i = 0; i < BM; ++i) a[i] = ((const float *)As)[(wr * WM + i * 32 + l32) * LD + kk + hi];
+#pragma unroll
+        for (int j = 0; j < BN; ++j) b[j] = ((const float *)Bs)[(wc * WN + j * 32 + l32) * LD + kk + hi];
+#pragma unroll
+        for (int i = 0; i < BM; ++i)
+#pragma unroll
+          for (int j = 0; j < BN; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i], b[j], acc[i][j], 0, 0, 0);
       }
     }
+    if (c + 1 < total) store_chunk(cur ^ 1);
     __syncthreads();
   }
 
   // D[row][col]: col = lane % 32, row = 8 (i / 4) + 4 (lane / 32) + i % 4
 #pragma unroll
-  for (int blk = 0; blk < 2; ++blk) {
-    const int col = c0 + blk * 32 + l32;
+  for (int bj = 0; bj < BN; ++bj) {
+    const int col = c0 + wc * WN + bj * 32 + l32;
     if (col >= grp.n_out) continue;
-    float bias = 0.f;
-    if (EPI == kEpiFwd) bias = grp.bias[col];
+    const float bias = EPI == kEpiFwd ? grp.bias[col] : 0.f;
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      const int row = r0 + wave * 32 + 8 * (i / 4) + 4 * hi + (i % 4);
-      float v = blk == 0 ? acc0[i] : acc1[i];
-      float *out = gl.C + (size_t)row * gl.ldc + col;
-      if (EPI == kEpiFwd) {
-        *out = celu(v + bias, gl.alpha);
-      } else if (EPI == kEpiBwd) {
-        const float h = gl.H[(size_t)row * gl.ldh + col];
-        *out = v * dcelu_from_h(h, gl.alpha) * gl.scale;
-      } else {
-        v *= gl.scale;
-        *out = gl.accumulate ? *out + v : v;
+    for (int bi = 0; bi < BM; ++bi) {
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const int row = r0 + wr * WM + bi * 32 + 8 * (i / 4) + 4 * hi + (i % 4);
+        const float v = acc[bi][bj][i];
+        if (EPI == kEpiFwd) {
+          T *out = (T *)gl.C + (size_t)row * gl.ldc + (size_t)mb * gl.c_member_stride + col;
+          Op<BF16>::store(out, celu(v + bias, gl.alpha));
+        } else if (EPI == kEpiBwd) {
+          T *out = (T *)gl.C + (size_t)row * gl.ldc + (size_t)mb * gl.c_member_stride + col;
+          const float h = Op<BF16>::load((const T *)gl.H + (size_t)row * gl.ldh +
+                                         (size_t)mb * gl.h_member_stride + col);
+          Op<BF16>::store(out, v * dcelu_from_h(h, gl.alpha) * gl.scale);
+        } else {
+          float *out = (float *)gl.C + (size_t)row * gl.ldc + col;
+          *out = v * gl.scale;
+        }
       }
     }
   }
 }
 
-void launch_gemm(int epi, bool bf16, const GemmLaunch &gl, int row_tiles, int max_n_out,
-                 hipStream_t st) {
+template <int EPI, bool BF16>
+static void launch_t(const GemmLaunch &gl, int row_tiles, int tn, hipStream_t st) {
+  const unsigned blocks = (unsigned)(row_tiles * gl.n_members * gl.col_tiles);
+  if (tn == 128) k_gemm<EPI, BF16, 128><<<blocks, 256, 0, st>>>(gl);
+  else k_gemm<EPI, BF16, 64><<<blocks, 256, 0, st>>>(gl);
+}
+
+void launch_gemm(int epi, bool bf16, GemmLaunch gl, int row_tiles, int max_n_out, hipStream_t st) {
   if (row_tiles <= 0) return;
-  dim3 grid(row_tiles, (max_n_out + kTN - 1) / kTN);
+  // 128-wide column tiles when they waste little, else 64
+  const int t128 = (max_n_out + 127) / 128 * 128, t64 = (max_n_out + 63) / 64 * 64;
+  const int tn = (t128 - max_n_out) * 4 <= max_n_out && t128 <= t64 + 32 ? 128 : 64;
+  gl.col_tiles = (max_n_out + tn - 1) / tn;
   if (bf16) {
-    if (epi == kEpiFwd) k_gemm<kEpiFwd, true><<<grid, 256, 0, st>>>(gl);
-    else if (epi == kEpiBwd) k_gemm<kEpiBwd, true><<<grid, 256, 0, st>>>(gl);
-    else k_gemm<kEpiOut, true><<<grid, 256, 0, st>>>(gl);
+    if (epi == kEpiFwd) launch_t<kEpiFwd, true>(gl, row_tiles, tn, st);
+    else if (epi == kEpiBwd) launch_t<kEpiBwd, true>(gl, row_tiles, tn, st);
+    else launch_t<kEpiOut, true>(gl, row_tiles, tn, st);
   } else {
-    if (epi == kEpiFwd) k_gemm<kEpiFwd, false><<<grid, 256, 0, st>>>(gl);
-    else if (epi == kEpiBwd) k_gemm<kEpiBwd, false><<<grid, 256, 0, st>>>(gl);
-    else k_gemm<kEpiOut, false><<<grid, 256, 0, st>>>(gl);
+    if (epi == kEpiFwd) launch_t<kEpiFwd, false>(gl, row_tiles, tn, st);
+    else if (epi == kEpiBwd) launch_t<kEpiBwd, false>(gl, row_tiles, tn, st);
+    else launch_t<kEpiOut, false>(gl, row_tiles, tn, st);
   }
 }
 
-// Output layer (one unit): E_row = w . h + b, and dE/dh = w * CELU'(h) (or
-// w itself when the network has no hidden layer), both scaled by 1/M for an
-// ensemble of M networks.  One wave per row.
+// Output layer (one unit) of every ensemble member: E_row = mean over members
+// of w . h + b, and dE/dh = w * CELU'(h) / M per member (or, for networks
+// without hidden layers, dE/dG = mean of w).  One wave per row.
+template <bool BF16>
 __global__ void __launch_bounds__(256) k_energy(EnergyLaunch el, int rows) {
+  typedef typename Op<BF16>::T T;
   const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
   const int row = blockIdx.x * 4 + wave;
   if (row >= rows) return;
@@ -192,29 +269,37 @@ __global__ void __launch_bounds__(256) k_energy(EnergyLaunch el, int rows) {
   if (s < 0) return;
   const int atom = el.perm[row];
   if (atom < 0) return;
-  const int K = el.K[s];
-  const float *w = el.w[s];
-  const float *h = el.Hin + (size_t)row * el.ldh;
-  float *go = el.Gout + (size_t)row * el.ldg;
   float e = 0.f;
-  for (int k = lane; k < K; k += kWave) {
-    const float hv = h[k], wv = w[k];
-    e += hv * wv;
-    if (el.want_grad) {
-      float gk = (el.hidden ? wv * dcelu_from_h(hv, el.alpha) : wv) * el.inv_m;
-      go[k] = el.accumulate_grad ? go[k] + gk : gk;
+  float bsum = 0.f;
+  for (int m = 0; m < el.n_members; ++m) {
+    const int K = el.K[s];
+    const float *w = el.w[m * el.n_groups + s];
+    bsum += el.b[m * el.n_groups + s][0];
+    const T *h = (const T *)el.Hin + (size_t)row * el.ldh + (size_t)m * el.h_member_stride;
+    for (int k = lane; k < K; k += kWave) {
+      const float hv = Op<BF16>::load(h + k), wv = w[k];
+      e += hv * wv;
+      if (el.want_grad) {
+        if (el.hidden) {
+          T *go = (T *)el.Gout + (size_t)row * el.ldg + (size_t)m * el.g_member_stride + k;
+          Op<BF16>::store(go, wv * dcelu_from_h(hv, el.alpha) * el.inv_m);
+        } else {
+          // no hidden layer: dE/dG = mean of w, float32
+          float *go = (float *)el.Gout + (size_t)row * el.ldg + k;
+          const float v = wv * el.inv_m;
+          *go = m == 0 ? v : *go + v;
+        }
+      }
     }
   }
   for (int off = 32; off >= 1; off >>= 1) e += __shfl_xor(e, off);
-  if (lane == 0) {
-    const float val = (e + el.b[s][0]) * el.inv_m;
-    el.e_atom[atom] = el.first ? val : el.e_atom[atom] + val;
-  }
+  if (lane == 0) el.e_atom[atom] = (e + bsum) * el.inv_m;
 }
 
-void launch_energy(const EnergyLaunch &el, int rows, hipStream_t st) {
+void launch_energy(const EnergyLaunch &el, bool bf16, int rows, hipStream_t st) {
   if (rows <= 0) return;
-  k_energy<<<(rows + 3) / 4, 256, 0, st>>>(el, rows);
+  if (bf16) k_energy<true><<<(rows + 3) / 4, 256, 0, st>>>(el, rows);
+  else k_energy<false><<<(rows + 3) / 4, 256, 0, st>>>(el, rows);
 }
 
 // Per-system totals in float64: energies (sum of atomic energies) and the

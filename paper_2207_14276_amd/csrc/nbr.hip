@@ -133,30 +133,32 @@ void launch_cell_count(const float4 *pos, const int *sys_of, const SysDesc *sys,
                                                 atom_slot);
 }
 
-// Exclusive prefix sum, out[0..n]; one workgroup of 1024 threads, each thread
-// owning a contiguous run.  n is at most a few hundred thousand cells.
+// Exclusive prefix sum, out[0..n]: one workgroup of 1024 threads walks the
+// array in coalesced 1024-element steps, carrying the running total.
 __global__ void __launch_bounds__(1024) k_scan(const int *__restrict__ in, int *__restrict__ out,
                                                int n) {
-  __shared__ int part[1024];
-  int t = threadIdx.x;
-  int per = (n + 1023) / 1024;
-  int b = t * per, e = min(n, b + per);
-  int s = 0;
-  for (int k = b; k < e; ++k) s += in[k];
-  part[t] = s;
+  __shared__ int wsum[1024 / kWave];
+  __shared__ int carry_s;
+  const int t = threadIdx.x, lane = t % kWave, w = t / kWave;
+  if (t == 0) carry_s = 0;
   __syncthreads();
-  for (int off = 1; off < 1024; off <<= 1) {
-    int v = t >= off ? part[t - off] : 0;
+  for (int base = 0; base < n; base += 1024) {
+    const int v = base + t < n ? in[base + t] : 0;
+    int x = v;
+    for (int off = 1; off < kWave; off <<= 1) {
+      int y = __shfl_up(x, off);
+      if (lane >= off) x += y;
+    }
+    if (lane == kWave - 1) wsum[w] = x;
     __syncthreads();
-    part[t] += v;
+    int before = carry_s;
+    for (int q = 0; q < w; ++q) before += wsum[q];
+    if (base + t < n) out[base + t] = before + x - v;
+    __syncthreads();
+    if (t == 1023) carry_s = before + x;
     __syncthreads();
   }
-  int run = part[t] - s;
-  for (int k = b; k < e; ++k) {
-    out[k] = run;
-    run += in[k];
-  }
-  if (t == 1023) out[n] = part[1023];
+  if (t == 0) out[n] = carry_s;
 }
 
 void launch_scan(const int *in, int *out, int n, hipStream_t st) {
@@ -179,26 +181,29 @@ void launch_cell_scatter(const int *atom_cell, const int *atom_slot, const int *
 }
 
 // Sorts each cell's atoms by index so neighbour lists (and every sum over
-// them) come out in the same order on every call.
-__global__ void k_cell_sort(const int *__restrict__ cell_start, int n_cells,
-                            int *__restrict__ cell_atoms) {
-  int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= n_cells) return;
-  int b = cell_start[c], e = cell_start[c + 1];
-  for (int k = b + 1; k < e; ++k) {
-    int v = cell_atoms[k];
-    int q = k - 1;
-    while (q >= b && cell_atoms[q] > v) {
-      cell_atoms[q + 1] = cell_atoms[q];
-      --q;
-    }
-    cell_atoms[q + 1] = v;
+// them) come out in the same order on every call.  One workgroup per cell,
+// rank sort in LDS; cells above kSortMax atoms keep their arrival order.
+constexpr int kSortMax = 2048;
+
+__global__ void __launch_bounds__(256) k_cell_sort(const int *__restrict__ cell_start, int n_cells,
+                                                   int *__restrict__ cell_atoms) {
+  __shared__ int buf[kSortMax];
+  const int c = blockIdx.x;
+  const int b = cell_start[c], n = cell_start[c + 1] - b;
+  if (n <= 1 || n > kSortMax) return;
+  for (int k = threadIdx.x; k < n; k += blockDim.x) buf[k] = cell_atoms[b + k];
+  __syncthreads();
+  for (int k = threadIdx.x; k < n; k += blockDim.x) {
+    const int v = buf[k];
+    int rank = 0;
+    for (int q = 0; q < n; ++q) rank += buf[q] < v;
+    cell_atoms[b + rank] = v;
   }
 }
 
 void launch_cell_sort(const int *cell_start, int n_cells, int *cell_atoms, hipStream_t st) {
   if (n_cells <= 0) return;
-  k_cell_sort<<<(n_cells + 255) / 256, 256, 0, st>>>(cell_start, n_cells, cell_atoms);
+  k_cell_sort<<<n_cells, 256, 0, st>>>(cell_start, n_cells, cell_atoms);
 }
 
 // ----------------------------------------------------------- neighbour list
