@@ -136,6 +136,37 @@ int nnp_energy_forces(nnp_model *model, int n_systems, const int64_t *batch_offs
                       double *energy, float *forces, double *virial, float *atom_energy,
                       void *stream);
 
+/* Persistent neighbour lists (device-resident state for repeated calls on
+ * slowly moving systems, e.g. successive MD steps).  A pool holds `slots`
+ * atom slots; each system of a call occupies a caller-chosen range of slots
+ * for as long as it lives, wherever its atoms sit in that call's batch.  A
+ * system's list is built with cutoff rc_rad + skin and reused until one of
+ * its atoms has moved more than skin / 2 from where it was at the last build
+ * (checked on the device every call), so no neighbour can enter the cutoff
+ * unseen.  Periodic coordinates are not re-wrapped while a list is reused.
+ * nnp_nlist_create allocates device memory (slots * capacity * 8 bytes plus
+ * 36 bytes per slot); capacity <= 1024. */
+typedef struct nnp_nlist nnp_nlist;
+int nnp_nlist_create(nnp_model *model, int64_t slots, int capacity, float skin, nnp_nlist **out);
+void nnp_nlist_destroy(nnp_nlist *list);
+
+/* As nnp_energy_forces, with the neighbour lists kept in `list`:
+ *   slots    HOST int64[n_systems]: first pool slot of each system; the ranges
+ *            [slots[s], slots[s] + n_s) lie inside the pool and do not
+ *            overlap (NNP_EINVAL otherwise).
+ *   rebuild  HOST int32[n_systems] or NULL: nonzero forces a fresh list for
+ *            that system (set it the first time a system uses its slots, or
+ *            after its atoms were renumbered). */
+int nnp_energy_forces_nlist(nnp_model *model, nnp_nlist *list, int n_systems,
+                            const int64_t *batch_offsets, const int64_t *slots,
+                            const int32_t *rebuild, const float *coords, const int32_t *species,
+                            const float *box, double *energy, float *forces, double *virial,
+                            float *atom_energy, void *stream);
+
+/* Waits for `stream`; *builds = number of system lists built in the pool so
+ * far (forced and skin-triggered). */
+int nnp_nlist_builds(nnp_nlist *list, void *stream, int64_t *builds);
+
 /* Same inputs; writes the AEV of every atom, DEVICE float32[N][aev_dim],
  * atom order.  For tests and inspection. */
 int nnp_debug_aev(nnp_model *model, int n_systems, const int64_t *batch_offsets,

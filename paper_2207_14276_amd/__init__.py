@@ -2,4 +2,4 @@
 network potential (Deep-HP, arXiv 2207.14276): HIP kernels behind the C ABI
 of include/nnp.h, with a thin ctypes binding and a torch.autograd.Function."""
 from ._native import NNPError, load  # noqa: F401
-from .model import NNPFunction, NNPModel, Result  # noqa: F401
+from .model import NeighborPool, NNPFunction, NNPModel, Result  # noqa: F401

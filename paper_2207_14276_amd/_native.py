@@ -55,7 +55,8 @@ class nnp_model_desc(C.Structure):
 
 EXPORTS = ["nnp_create", "nnp_destroy", "nnp_reserve", "nnp_energy_forces", "nnp_debug_aev",
            "nnp_debug_neighbors", "nnp_status", "nnp_aev_dim", "nnp_last_error",
-           "nnp_set_timing", "nnp_stage_timings"]
+           "nnp_set_timing", "nnp_stage_timings", "nnp_nlist_create", "nnp_nlist_destroy",
+           "nnp_energy_forces_nlist", "nnp_nlist_builds"]
 
 _lib = None
 
@@ -83,6 +84,12 @@ def load():
     lib.nnp_last_error.restype = C.c_char_p
     lib.nnp_set_timing.argtypes = [vp, C.c_int]
     lib.nnp_stage_timings.argtypes = [vp, fp, C.POINTER(C.c_char_p), C.c_int]
+    lib.nnp_nlist_create.argtypes = [vp, C.c_int64, C.c_int, C.c_float, C.POINTER(C.c_void_p)]
+    lib.nnp_nlist_destroy.argtypes = [vp]
+    lib.nnp_nlist_destroy.restype = None
+    lib.nnp_energy_forces_nlist.argtypes = [vp, vp, C.c_int, i64p, i64p, C.POINTER(C.c_int32), vp,
+                                            vp, fp, vp, vp, vp, vp, vp]
+    lib.nnp_nlist_builds.argtypes = [vp, vp, i64p]
     _lib = lib
     return lib
 

@@ -34,18 +34,18 @@ __device__ inline unsigned lanes_below(unsigned long long m) {
 __device__ inline float fast_exp(float x) { return __builtin_amdgcn_exp2f(x * 1.4426950408889634f); }
 __device__ inline float fast_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
 __device__ inline float fast_log2(float x) { return __builtin_amdgcn_logf(x); }
+// Hardware reciprocal and square root (about 1 ulp), in place of the
+// correctly rounded division and square-root sequences.
+__device__ inline float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ inline float fast_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 
-// Pair (j < k) of the same-species block with n entries from its rank t in
-// row-major order over the strict upper triangle.
-__device__ inline void unrank_upper(int t, int n, int &j, int &k) {
-  float fn = (float)(2 * n - 1);
-  int jj = (int)((fn - sqrtf(fmaxf(fn * fn - 8.0f * (float)t, 0.f))) * 0.5f);
-  jj = max(0, min(jj, n - 2));
-  auto start = [n](int r) { return r * (2 * n - r - 1) / 2; };
-  while (jj > 0 && start(jj) > t) --jj;
-  while (jj < n - 2 && start(jj + 1) <= t) ++jj;
-  j = jj;
-  k = t - start(jj) + jj + 1;
+// q = u / n and r = u mod n for 0 <= u < 2^24 through a float reciprocal
+// (rn = 1/n), corrected to the exact integer result.
+__device__ inline int fdivmod(int u, int n, float rn, int &r) {
+  int q = (int)((float)u * rn);
+  r = u - q * n;
+  if (r >= n) { ++q; r -= n; } else if (r < 0) { --q; r += n; }
+  return q;
 }
 
 // Wave-uniform per-species counts and offsets of the sorted lists.
@@ -61,7 +61,7 @@ __device__ inline float4 entry_vec(const float4 &pi, const float4 &pj, int code,
   float dx = (pj.x - pi.x) + (float)ix * L[0];
   float dy = (pj.y - pi.y) + (float)iy * L[1];
   float dz = (pj.z - pi.z) + (float)iz * L[2];
-  return make_float4(dx, dy, dz, sqrtf(dx * dx + dy * dy + dz * dz));
+  return make_float4(dx, dy, dz, fast_sqrt(dx * dx + dy * dy + dz * dz));
 }
 
 // LDS layout of one wave's lists (cap entries each), pair-block table and
@@ -72,13 +72,24 @@ constexpr int kMaxAng = kMaxBlocks * kAngBlock;  // 896 angular features
 
 // Non-empty species-pair block q of the centre's pair stream.
 struct PairBlock {
-  int start;   // first pair of the block in the stream
-  int p;       // feature block index (upper-triangle order of (sa, sb))
-  int oa, ob;  // offsets of the two species in the angular list
-  int na, nb;  // their counts
-  int same;    // sa == sb
-  int pad;
+  int start;    // first pair of the block in the stream
+  int p;        // feature block index (upper-triangle order of (sa, sb))
+  int oa, ob;   // offsets of the two species in the angular list
+  int na, nb;   // their counts
+  int same;     // sa == sb
+  float r_hi;   // 1 / max(na, nb)
+  float r_lo;   // 1 / min(na, nb)
+  int pad[3];
 };
+
+__device__ inline PairBlock make_block(int start, int p, int oa, int ob, int na, int nb, bool same) {
+  PairBlock b;
+  b.start = start; b.p = p; b.oa = oa; b.ob = ob; b.na = na; b.nb = nb; b.same = same;
+  b.r_hi = 1.0f / (float)max(max(na, nb), 1);
+  b.r_lo = 1.0f / (float)max(min(na, nb), 1);
+  b.pad[0] = b.pad[1] = b.pad[2] = 0;
+  return b;
+}
 
 struct WaveLds {
   float4 *tGeo;    // pair scratch: cos, sin, fc_j fc_k, -      (forward)
@@ -135,18 +146,50 @@ __device__ inline int build_blocks(int lane, const Lists &ls, int S, WaveLds &w,
       const int na = ls.cA[sa], nb = ls.cA[sb];
       const int T = sa == sb ? na * (na - 1) / 2 : na * nb;
       if (T == 0) continue;
-      if (lane == 0) {
-        PairBlock b;
-        b.start = start; b.p = p; b.oa = ls.oA[sa]; b.ob = ls.oA[sb];
-        b.na = na; b.nb = nb; b.same = sa == sb; b.pad = 0;
-        w.blk[q] = b;
-      }
+      if (lane == 0) w.blk[q] = make_block(start, p, ls.oA[sa], ls.oA[sb], na, nb, sa == sb);
       ++q;
       start += T;
     }
   if (lane == 0) w.blk[q].start = start;  // sentinel
   nblk = q;
   return start;
+}
+
+// Pair u of a block, enumerated by diagonals so that consecutive pairs (the
+// lanes of one pass) mostly touch different neighbour entries:
+//   same species, n entries: pairs (j, j + d mod n) for d = 1, 2, ...; when n
+//   is even the last diagonal d = n/2 holds n/2 pairs;
+//   two species (na, nb): the longer list runs fastest, the other index is
+//   shifted by the diagonal number.
+__device__ inline void unrank_diag(int u, const PairBlock &b, int &j, int &k) {
+  if (b.same) {
+    const int n = b.na;
+    const int full = (n & 1) ? n * (n - 1) / 2 : n * (n / 2 - 1);
+    if (u < full) {
+      int r;
+      const int dd = fdivmod(u, n, b.r_hi, r) + 1;
+      j = r;
+      k = j + dd;
+      if (k >= n) k -= n;
+    } else {
+      j = u - full;
+      k = j + n / 2;
+    }
+  } else if (b.na >= b.nb) {
+    int r;
+    const int row = fdivmod(u, b.na, b.r_hi, r);
+    j = r;
+    int m;
+    fdivmod(row + j, b.nb, b.r_lo, m);
+    k = m;
+  } else {
+    int r;
+    const int row = fdivmod(u, b.nb, b.r_hi, r);
+    k = r;
+    int m;
+    fdivmod(row + k, b.na, b.r_lo, m);
+    j = m;
+  }
 }
 
 // Pair t of the stream -> its block (searched from the wave-uniform block
@@ -158,10 +201,8 @@ __device__ inline void locate_pair(int t, int qb, int nblk, int pass_end, const 
   for (int r = qb + 1; r < nblk && w.blk[r].start < pass_end; ++r)
     if (t >= w.blk[r].start) q = r;
   const PairBlock b = w.blk[q];
-  const int u = t - b.start;
   int j, k;
-  if (b.same) unrank_upper(u, b.na, j, k);
-  else { j = u / b.nb; k = u - j * b.nb; }
+  unrank_diag(t - b.start, b, j, k);
   aj = b.oa + j;
   ak = b.ob + k;
   p = b.p;
@@ -179,20 +220,23 @@ __device__ inline void wave_lds_sync() {
 // Builds the species-sorted radial list (R < rc_r) and angular list
 // (R < rc_a, a subset) of centre i in LDS.  Two passes over the entries:
 // per-species counts by ballot, then placement.
+// Entries whose stored atom index is not below n_sys (a reused list applied
+// to a different system) are skipped, never dereferenced.
 template <bool BWD>
-__device__ inline void fill_lists(int lane, int n, const int2 *__restrict__ ent,
+__device__ inline void fill_lists(int lane, int n, const int2 *__restrict__ ent, int j0, int n_sys,
                                   const float4 *__restrict__ pos, const float4 &pi,
                                   const float L[3], const AevConst &c, WaveLds &w, Lists &ls) {
   const int S = c.S;
   for (int s = 0; s < kMaxSpecies; ++s) { ls.cR[s] = 0; ls.cA[s] = 0; }
   for (int b = 0; b < n; b += kWave) {
     int e = b + lane;
-    bool v = e < n;
+    int2 en = make_int2(0, 0);
+    if (e < n) en = ent[e];
+    bool v = e < n && (unsigned)en.x < (unsigned)n_sys;
     int sj = -1;
     float R = 1e30f;
     if (v) {
-      int2 en = ent[e];
-      float4 pj = pos[en.x];
+      float4 pj = pos[j0 + en.x];
       R = entry_vec(pi, pj, en.y, L).w;
       sj = __float_as_int(pj.w);
     }
@@ -212,15 +256,16 @@ __device__ inline void fill_lists(int lane, int n, const int2 *__restrict__ ent,
   const float kr = kPi / c.rc_r, ka = kPi / c.rc_a;
   for (int b = 0; b < n; b += kWave) {
     int e = b + lane;
-    bool v = e < n;
+    int2 en = make_int2(0, 0);
+    if (e < n) en = ent[e];
+    bool v = e < n && (unsigned)en.x < (unsigned)n_sys;
     int sj = -1, j = 0;
     float4 d = make_float4(0.f, 0.f, 0.f, 1e30f);
     if (v) {
-      int2 en = ent[e];
-      float4 pj = pos[en.x];
+      j = j0 + en.x;
+      float4 pj = pos[j];
       d = entry_vec(pi, pj, en.y, L);
       sj = __float_as_int(pj.w);
-      j = en.x;
     }
     bool inR = v && d.w < c.rc_r, inA = v && d.w < c.rc_a;
     for (int s = 0; s < S; ++s) {
@@ -276,14 +321,18 @@ k_aev_fwd(const float4 *__restrict__ pos, const int *__restrict__ sys_of,
   Lists ls;
   float4 pi = make_float4(0.f, 0.f, 0.f, 0.f);
   float L[3] = {0.f, 0.f, 0.f};
-  int n = 0;
+  int n = 0, j0 = 0, n_sys = 0;
+  const int2 *row = nbr;
   if (live) {
-    n = min(nbr_cnt[i], cap);
-    pi = pos[i];
     const SysDesc &d = sys[sys_of[i]];
+    n_sys = d.n;
+    n = min(nbr_cnt[d.state_off + (i - d.atom_off)], cap);
+    pi = pos[i];
     L[0] = d.L[0]; L[1] = d.L[1]; L[2] = d.L[2];
+    j0 = d.atom_off;
+    row = nbr + nbr_row(d, i, cap);
   }
-  fill_lists<false>(lane, n, nbr + (size_t)(live ? i : 0) * cap, pos, pi, L, c, w, ls);
+  fill_lists<false>(lane, n, row, j0, n_sys, pos, pi, L, c, w, ls);
   __syncthreads();
   if (!live) return;
   void *Grow = (char *)G + (size_t)row_of_atom[i] * ldg * (BF16 ? 2 : 4);
@@ -318,6 +367,7 @@ k_aev_fwd(const float4 *__restrict__ pos, const int *__restrict__ sys_of,
       for (int sb = sa; sb < c.S; ++sb, ++p) {
         const int na = ls.cA[sa], nb = ls.cA[sb];
         const int T = sa == sb ? na * (na - 1) / 2 : na * nb;
+        const PairBlock blk = make_block(0, p, 0, 0, na, nb, sa == sb);
         float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f, acc3 = 0.f;
         for (int base = 0; base < T; base += kPairPass) {
           // (A) lane per pair
@@ -326,16 +376,15 @@ k_aev_fwd(const float4 *__restrict__ pos, const int *__restrict__ sys_of,
             const bool valid = t < T;
             const int tt = valid ? t : T - 1;
             int j, k;
-            if (sa == sb) unrank_upper(tt, na, j, k);
-            else { j = tt / nb; k = tt - j * nb; }
+            unrank_diag(tt, blk, j, k);
             const int qj = ls.oA[sa] + j, qk = ls.oA[sb] + k;
             const float4 dj = w.rD[w.aIdx[qj]], dk = w.rD[w.aIdx[qk]];
             const float dot = dj.x * dk.x + dj.y * dk.y + dj.z * dk.z;
             const float cx = dj.y * dk.z - dj.z * dk.y;
             const float cy = dj.z * dk.x - dj.x * dk.z;
             const float cz = dj.x * dk.y - dj.y * dk.x;
-            const float cr = sqrtf(cx * cx + cy * cy + cz * cz);
-            const float inv = 1.0f / (dj.w * dk.w);
+            const float cr = fast_sqrt(cx * cx + cy * cy + cz * cz);
+            const float inv = fast_rcp(dj.w * dk.w);
             const float fcc = valid ? w.aFc[qj] * w.aFc[qk] : 0.f;
             const float Rbar = 0.5f * (dj.w + dk.w);
             const float u0 = Rbar - c.shf_a[0], u1 = Rbar - c.shf_a[1];
@@ -390,14 +439,18 @@ k_aev_bwd(const float4 *__restrict__ pos, const int *__restrict__ sys_of,
   Lists ls;
   float4 pi = make_float4(0.f, 0.f, 0.f, 0.f);
   float L[3] = {0.f, 0.f, 0.f};
-  int n = 0;
+  int n = 0, j0 = 0, n_sys = 0;
+  const int2 *row = nbr;
   if (live) {
-    n = min(nbr_cnt[i], cap);
-    pi = pos[i];
     const SysDesc &d = sys[sys_of[i]];
+    n_sys = d.n;
+    n = min(nbr_cnt[d.state_off + (i - d.atom_off)], cap);
+    pi = pos[i];
     L[0] = d.L[0]; L[1] = d.L[1]; L[2] = d.L[2];
+    j0 = d.atom_off;
+    row = nbr + nbr_row(d, i, cap);
   }
-  fill_lists<true>(lane, n, nbr + (size_t)(live ? i : 0) * cap, pos, pi, L, c, w, ls);
+  fill_lists<true>(lane, n, row, j0, n_sys, pos, pi, L, c, w, ls);
   __syncthreads();
   if (!live) return;
   const float *g = dG + (size_t)row_of_atom[i] * ldg;
@@ -419,7 +472,7 @@ k_aev_bwd(const float4 *__restrict__ pos, const int *__restrict__ sys_of,
         term += __shfl_xor(term, 4);
         term += __shfl_xor(term, 8);
         if (m == 0) {
-          const float q = term / d.w;
+          const float q = term * fast_rcp(d.w);
           float *gg = w.rG + 3 * (o + e);
           gg[0] = q * d.x; gg[1] = q * d.y; gg[2] = q * d.z;
         }
@@ -452,9 +505,9 @@ k_aev_bwd(const float4 *__restrict__ pos, const int *__restrict__ sys_of,
       const float cx = dj.y * dk.z - dj.z * dk.y;
       const float cy = dj.z * dk.x - dj.x * dk.z;
       const float cz = dj.x * dk.y - dj.y * dk.x;
-      const float cr = sqrtf(cx * cx + cy * cy + cz * cz);
+      const float cr = fast_sqrt(cx * cx + cy * cy + cz * cz);
       const float RR = dj.w * dk.w;
-      const float invRR = 1.0f / RR;
+      const float invRR = fast_rcp(RR);
       const float cosv = dot * invRR, sinv = cr * invRR;
       const float Rbar = 0.5f * (dj.w + dk.w);
       float f2[kNShfAng], df2[kNShfAng];
@@ -502,13 +555,14 @@ k_aev_bwd(const float4 *__restrict__ pos, const int *__restrict__ sys_of,
         dbar *= 0.5f * fcc;  // via Rbar, for each of R_j and R_k
         const float dRj = dbar + dfc * w.aDfc[aj] * fk;
         const float dRk = dbar + dfc * fj * w.aDfc[ak];
-        const float inv_cr = cr > 1e-12f * RR ? 1.0f / cr : 0.f;
-        const float invj2 = 1.0f / (dj.w * dj.w), invk2 = 1.0f / (dk.w * dk.w);
+        const float inv_cr = cr > 1e-12f * RR ? fast_rcp(cr) : 0.f;
+        const float invj = fast_rcp(dj.w), invk = fast_rcp(dk.w);
         const float aj_ = dcos * invRR, ak_ = dsin * inv_cr * invRR;
         // d cos / d dj = dk / RR - cos dj / Rj^2 ; d sin / d dj =
         // (Rk^2 dj - dot dk) / (|dj x dk| RR) - sin dj / Rj^2
-        const float cj = -(dcos * cosv + dsin * sinv) * invj2 + dRj / dj.w;
-        const float ck = -(dcos * cosv + dsin * sinv) * invk2 + dRk / dk.w;
+        const float cs = dcos * cosv + dsin * sinv;
+        const float cj = (dRj - cs * invj) * invj;
+        const float ck = (dRk - cs * invk) * invk;
         const float sjj = ak_ * dk.w * dk.w, sjk = -ak_ * dot;
         const float skk = ak_ * dj.w * dj.w, skj = -ak_ * dot;
         float *gj = w.rG + 3 * qj, *gk = w.rG + 3 * qk;

@@ -98,7 +98,7 @@ struct nnp_model {
   // workspace
   DevBuf pos, sys_of, atom_cell, atom_slot, cell_count, cell_start, cell_atoms, nbr, nbr_cnt;
   DevBuf block_counts, bucket_off, bucket_cnt, perm, row_of_atom, G, dG, e_atom, W_atom, partial;
-  DevBuf sysdesc, chunk_sys, chunk_begin, sys_chunk_off, status;
+  DevBuf sysdesc, chunk_sys, chunk_begin, sys_chunk_off, status, state;
   std::vector<DevBuf> H, Gd;
   // host staging (pinned) for per-call descriptors
   void *stage = nullptr;
@@ -111,6 +111,17 @@ struct nnp_model {
   int last_stages = 0;
 
   LayerW &layer(int m, int s, int l) { return layers[((size_t)m * S + s) * L + l]; }
+};
+
+// A persistent pool of neighbour lists: each system of a call owns a range of
+// slots (one per atom) for its rows, counts and per-atom state, so its list is
+// reused across calls until an atom has moved more than half the skin.
+struct nnp_nlist {
+  int device = 0;
+  int64_t slots = 0;
+  int cap = 0;
+  float skin = 0.f;
+  DevBuf nbr, cnt, state, stats;
 };
 
 static void round_bf16_host(const float *src, uint16_t *dst, size_t n) {
@@ -140,7 +151,7 @@ extern "C" void nnp_destroy(nnp_model *m) {
                     &m->cell_start, &m->cell_atoms, &m->nbr, &m->nbr_cnt, &m->block_counts,
                     &m->bucket_off, &m->bucket_cnt, &m->perm, &m->row_of_atom, &m->G, &m->dG,
                     &m->e_atom, &m->W_atom, &m->partial, &m->sysdesc, &m->chunk_sys,
-                    &m->chunk_begin, &m->sys_chunk_off, &m->status};
+                    &m->chunk_begin, &m->sys_chunk_off, &m->status, &m->state};
   for (DevBuf *b : bufs) b->release();
   for (auto &b : m->H) b.release();
   for (auto &b : m->Gd) b.release();
@@ -304,6 +315,7 @@ static int ensure_ws(nnp_model *m, int64_t N, int S, int64_t C, int n_chunks) {
   ENS(m->cell_atoms, N * 4);
   ENS(m->nbr, N * (int64_t)m->cap * 8);
   ENS(m->nbr_cnt, N * 4);
+  ENS(m->state, N * (int64_t)sizeof(AtomState));
   ENS(m->block_counts, (int64_t)std::max(nblk, 1) * kMaxSpecies * 4);
   ENS(m->bucket_off, (kMaxSpecies + 1) * 4);
   ENS(m->bucket_cnt, kMaxSpecies * 4);
@@ -391,8 +403,17 @@ struct CallOut {
   int nb_cap = 0;
 };
 
+// Where a call's neighbour lists live: the model's own per-call pool (every
+// list rebuilt, no skin) or a persistent nnp_nlist.
+struct ListPool {
+  nnp_nlist *nl = nullptr;       // null: the model's workspace
+  const int64_t *slots = nullptr;  // nl: first slot of each system
+  const int32_t *rebuild = nullptr;  // nl: caller-forced rebuilds (nullable)
+};
+
 static int run(nnp_model *m, int n_sys, const int64_t *offs, const float *coords,
-               const int32_t *species, const float *box, const CallOut &o, hipStream_t st, Mode mode) {
+               const int32_t *species, const float *box, const CallOut &o, hipStream_t st, Mode mode,
+               const ListPool &lp = ListPool()) {
   if (!m) return fail(NNP_EINVAL, "null model");
   if (n_sys < 1) return fail(NNP_EINVAL, "n_systems must be >= 1");
   if (!offs || !box) return fail(NNP_EINVAL, "null host array (batch_offsets / box)");
@@ -407,7 +428,23 @@ static int run(nnp_model *m, int n_sys, const int64_t *offs, const float *coords
   if (mode == kFull && o.virial && !o.forces) return fail(NNP_EINVAL, "virial needs forces");
   HIP_TRY(hipSetDevice(m->device));
 
-  const float rc_list = m->aev.rc_r;
+  nnp_nlist *nl = lp.nl;
+  if (nl) {
+    if (!lp.slots) return fail(NNP_EINVAL, "null slot offsets");
+    if (nl->device != m->device) return fail(NNP_EINVAL, "neighbour-list pool on another device");
+    // slot ranges must lie in the pool and must not overlap
+    std::vector<std::pair<int64_t, int64_t>> r;
+    for (int s = 0; s < n_sys; ++s) {
+      const int64_t a = lp.slots[s], n = offs[s + 1] - offs[s];
+      if (a < 0 || a + n > nl->slots) return fail(NNP_EINVAL, "system %d: slots outside the pool", s);
+      if (n > 0) r.push_back({a, a + n});
+    }
+    std::sort(r.begin(), r.end());
+    for (size_t q = 1; q < r.size(); ++q)
+      if (r[q].first < r[q - 1].second) return fail(NNP_EINVAL, "overlapping slot ranges");
+  }
+  const int cap = nl ? nl->cap : m->cap;
+  const float rc_list = m->aev.rc_r + (nl ? nl->skin : 0.f);
   const float rc_cell = rc_list * (1.0f + 1e-5f);
   std::vector<SysDesc> sd(n_sys);
   int64_t C = 0;
@@ -423,6 +460,15 @@ static int run(nnp_model *m, int n_sys, const int64_t *offs, const float *coords
     d.n = (int)(offs[s + 1] - offs[s]);
     d.periodic = per ? 1 : 0;
     d.cell_off = (int)C;
+    if (nl) {
+      d.state_off = lp.slots[s];
+      d.list_off = lp.slots[s] * (int64_t)cap;
+      d.rebuild = lp.rebuild ? (lp.rebuild[s] != 0) : 0;
+    } else {
+      d.state_off = offs[s];
+      d.list_off = offs[s] * (int64_t)cap;
+      d.rebuild = 1;
+    }
     if (per && (b[0] < 0.25f * rc_list || b[1] < 0.25f * rc_list || b[2] < 0.25f * rc_list))
       return fail(NNP_EUNSUPPORTED, "system %d: periodic box edge below a quarter of the cutoff", s);
     if (per) {
@@ -495,7 +541,11 @@ static int run(nnp_model *m, int n_sys, const int64_t *offs, const float *coords
   SysDesc *dsys = m->sysdesc.as<SysDesc>();
   int *status = m->status.as<int>();
   float4 *pos = m->pos.as<float4>();
-  launch_ingest(coords, species, dsys, n_sys, N, m->S, pos, m->sys_of.as<int>(), status, st);
+  int2 *pool_nbr = nl ? nl->nbr.as<int2>() : m->nbr.as<int2>();
+  int *pool_cnt = nl ? nl->cnt.as<int>() : m->nbr_cnt.as<int>();
+  AtomState *pool_state = nl ? nl->state.as<AtomState>() : m->state.as<AtomState>();
+  if (nl) launch_skin_check(coords, dsys, n_sys, pool_state, 0.5f * nl->skin, nl->stats.as<int>(), st);
+  launch_ingest(coords, species, dsys, n_sys, N, m->S, pos, m->sys_of.as<int>(), pool_state, status, st);
   mark();
   launch_grid(dsys, n_sys, pos, m->cell_count.as<int>(), rc_list, st);
   launch_cell_count(pos, m->sys_of.as<int>(), dsys, N, m->cell_count.as<int>(), m->atom_cell.as<int>(),
@@ -506,10 +556,10 @@ static int run(nnp_model *m, int n_sys, const int64_t *offs, const float *coords
   launch_cell_sort(m->cell_start.as<int>(), (int)C, m->cell_atoms.as<int>(), st);
   mark();
   launch_nbr_build(pos, m->sys_of.as<int>(), dsys, m->cell_start.as<int>(), m->cell_atoms.as<int>(), N,
-                   rc_list, m->cap, m->nbr.as<int2>(), m->nbr_cnt.as<int>(), status, st);
+                   rc_list, cap, pool_nbr, pool_cnt, status, st);
   if (mode == kNbr) {
-    launch_export_nbr(m->nbr.as<int2>(), m->nbr_cnt.as<int>(), m->cap, N, o.nb_counts, o.nb_entries,
-                      o.nb_cap, st);
+    launch_export_nbr(pool_nbr, pool_cnt, cap, dsys, m->sys_of.as<int>(), N, o.nb_counts,
+                      o.nb_entries, o.nb_cap, st);
     HIP_TRY(hipGetLastError());
     return NNP_OK;
   }
@@ -524,13 +574,13 @@ static int run(nnp_model *m, int n_sys, const int64_t *offs, const float *coords
   const bool bf16 = m->precision == NNP_BF16;
   if (mode == kAev) {
     // float32 AEV into the (float32) dE/dG buffer, then back to atom order
-    launch_aev_fwd(pos, m->sys_of.as<int>(), dsys, m->nbr.as<int2>(), m->nbr_cnt.as<int>(), m->cap,
+    launch_aev_fwd(pos, m->sys_of.as<int>(), dsys, pool_nbr, pool_cnt, cap,
                    m->row_of_atom.as<int>(), m->dG.p, false, D, N, m->aev, st);
     launch_gather_rows(m->dG.as<float>(), D, m->row_of_atom.as<int>(), N, D, o.aev, st);
     HIP_TRY(hipGetLastError());
     return NNP_OK;
   }
-  launch_aev_fwd(pos, m->sys_of.as<int>(), dsys, m->nbr.as<int2>(), m->nbr_cnt.as<int>(), m->cap,
+  launch_aev_fwd(pos, m->sys_of.as<int>(), dsys, pool_nbr, pool_cnt, cap,
                  m->row_of_atom.as<int>(), m->G.p, bf16, D, N, m->aev, st);
   mark();
 
@@ -639,7 +689,7 @@ static int run(nnp_model *m, int n_sys, const int64_t *offs, const float *coords
   }
   mark();
   if (want_grad) {
-    launch_aev_bwd(pos, m->sys_of.as<int>(), dsys, m->nbr.as<int2>(), m->nbr_cnt.as<int>(), m->cap,
+    launch_aev_bwd(pos, m->sys_of.as<int>(), dsys, pool_nbr, pool_cnt, cap,
                    m->row_of_atom.as<int>(), m->dG.as<float>(), D, N, m->aev, o.forces,
                    m->W_atom.as<float>(), st);
   }
@@ -683,4 +733,68 @@ extern "C" int nnp_debug_neighbors(nnp_model *m, int n_systems, const int64_t *o
   o.nb_entries = entries;
   o.nb_cap = capacity;
   return run(m, n_systems, offs, coords, species, box, o, (hipStream_t)stream, kNbr);
+}
+
+extern "C" int nnp_nlist_create(nnp_model *m, int64_t slots, int capacity, float skin, nnp_nlist **out) {
+  if (!m || !out) return fail(NNP_EINVAL, "null argument");
+  *out = nullptr;
+  if (slots < 1 || capacity < 1 || !(skin >= 0.f)) return fail(NNP_EINVAL, "bad pool size, capacity or skin");
+  if (capacity > 1024) return fail(NNP_EUNSUPPORTED, "neighbour capacity above 1024");
+  HIP_TRY(hipSetDevice(m->device));
+  nnp_nlist *nl = new nnp_nlist();
+  nl->device = m->device;
+  nl->slots = slots;
+  nl->cap = (capacity + 3) / 4 * 4;
+  nl->skin = skin;
+  int rc;
+  if ((rc = nl->nbr.ensure((size_t)slots * nl->cap * 8)) || (rc = nl->cnt.ensure((size_t)slots * 4)) ||
+      (rc = nl->state.ensure((size_t)slots * sizeof(AtomState))) || (rc = nl->stats.ensure(16))) {
+    nnp_nlist_destroy(nl);
+    return rc;
+  }
+  hipError_t e = hipMemset(nl->stats.p, 0, 16);
+  if (e != hipSuccess) {
+    nnp_nlist_destroy(nl);
+    return fail(NNP_EDEVICE, "hipMemset: %s", hipGetErrorString(e));
+  }
+  *out = nl;
+  return NNP_OK;
+}
+
+extern "C" void nnp_nlist_destroy(nnp_nlist *nl) {
+  if (!nl) return;
+  (void)hipSetDevice(nl->device);
+  (void)hipDeviceSynchronize();
+  nl->nbr.release();
+  nl->cnt.release();
+  nl->state.release();
+  nl->stats.release();
+  delete nl;
+}
+
+extern "C" int nnp_nlist_builds(nnp_nlist *nl, void *stream, int64_t *builds) {
+  if (!nl || !builds) return fail(NNP_EINVAL, "null argument");
+  HIP_TRY(hipSetDevice(nl->device));
+  HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+  int h = 0;
+  HIP_TRY(hipMemcpy(&h, nl->stats.p, sizeof h, hipMemcpyDeviceToHost));
+  *builds = h;
+  return NNP_OK;
+}
+
+extern "C" int nnp_energy_forces_nlist(nnp_model *m, nnp_nlist *nl, int n_systems, const int64_t *offs,
+                                       const int64_t *slots, const int32_t *rebuild, const float *coords,
+                                       const int32_t *species, const float *box, double *energy,
+                                       float *forces, double *virial, float *atom_energy, void *stream) {
+  if (!nl) return fail(NNP_EINVAL, "null neighbour-list pool");
+  CallOut o;
+  o.energy = energy;
+  o.forces = forces;
+  o.virial = virial;
+  o.atom_energy = atom_energy;
+  ListPool lp;
+  lp.nl = nl;
+  lp.slots = slots;
+  lp.rebuild = rebuild;
+  return run(m, n_systems, offs, coords, species, box, o, (hipStream_t)stream, kFull, lp);
 }

@@ -30,8 +30,22 @@ struct SysDesc {
   float origin[3];
   float edge[3];
   int nc[3];
-  int pad_;
+  int rebuild;       // nonzero: build this system's neighbour list in this call
+  long long list_off;   // first neighbour row of the system in the list pool
+  long long state_off;  // first per-atom state slot (reference position, wrap)
 };
+
+// Persistent per-atom state of a neighbour list: the caller's coordinates at
+// the last build (w unused) and the periodic wrap applied then (in box units).
+struct AtomState {
+  float4 ref;
+  float4 wrap;
+};
+
+// Neighbour row of atom i (cap entries): entries hold (j - atom_off, image).
+__host__ __device__ inline size_t nbr_row(const SysDesc &d, int i, int cap) {
+  return (size_t)d.list_off + (size_t)(i - d.atom_off) * (size_t)cap;
+}
 
 // AEV hyper-parameters, passed by value to the AEV kernels.
 struct AevConst {
@@ -98,8 +112,11 @@ struct EnergyLaunch {
 };
 
 // ---- launchers (stream-ordered, no host sync)
+void launch_skin_check(const float *coords, SysDesc *sys, int n_sys, const AtomState *state,
+                       float half_skin, int *stats, hipStream_t st);
 void launch_ingest(const float *coords, const int *species, const SysDesc *sys, int n_sys,
-                   int N, int S, float4 *pos, int *sys_of, int *status, hipStream_t st);
+                   int N, int S, float4 *pos, int *sys_of, AtomState *state, int *status,
+                   hipStream_t st);
 void launch_grid(SysDesc *sys, int n_sys, const float4 *pos, int *cell_count, float rc_list,
                  hipStream_t st);
 void launch_cell_count(const float4 *pos, const int *sys_of, const SysDesc *sys, int N,
@@ -130,8 +147,9 @@ void launch_reduce(const float *e_atom, const float *W_atom, const SysDesc *sys,
                    hipStream_t st);
 void launch_gather_rows(const float *src, int ld, const int *row_of_atom, int N, int D,
                         float *dst, hipStream_t st);
-void launch_export_nbr(const int2 *nbr, const int *nbr_cnt, int cap, int N, int *counts,
-                       int *entries, int out_cap, hipStream_t st);
+void launch_export_nbr(const int2 *nbr, const int *nbr_cnt, int cap, const SysDesc *sys,
+                       const int *sys_of, int N, int *counts, int *entries, int out_cap,
+                       hipStream_t st);
 void launch_f32_to_bf16(const float *src, uint16_t *dst, size_t n, hipStream_t st);
 
 }  // namespace nnp

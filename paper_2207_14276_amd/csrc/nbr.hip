@@ -5,13 +5,15 @@
 namespace nnp {
 
 // ------------------------------------------------------------------ ingest
-// Caller AoS float32[N][3] -> packed 16-byte atom records {x, y, z, species}
-// with periodic coordinates wrapped into [0, L).  One 16-byte load per
-// neighbour gather in the AEV kernels.
+// Caller AoS float32[N][3] -> packed 16-byte atom records {x, y, z, species}.
+// A system whose neighbour list is (re)built in this call has its periodic
+// coordinates wrapped into [0, L) and the wrap and the caller's coordinates
+// recorded; a system that reuses its list applies the recorded wrap instead,
+// so neighbour vectors stay consistent with the stored lattice images.
 __global__ void k_ingest(const float *__restrict__ coords, const int *__restrict__ species,
                          const SysDesc *__restrict__ sys, int n_sys, int N, int S,
                          float4 *__restrict__ pos, int *__restrict__ sys_of,
-                         int *__restrict__ status) {
+                         AtomState *__restrict__ state, int *__restrict__ status) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= N) return;
   // system of atom i: last s with atom_off <= i (binary search)
@@ -23,16 +25,29 @@ __global__ void k_ingest(const float *__restrict__ coords, const int *__restrict
   // skip empty systems that share the offset
   while (lo + 1 < n_sys && sys[lo + 1].atom_off <= i) ++lo;
   const SysDesc &d = sys[lo];
-  float x = coords[3 * i], y = coords[3 * i + 1], z = coords[3 * i + 2];
+  const float cx = coords[3 * i], cy = coords[3 * i + 1], cz = coords[3 * i + 2];
+  float x = cx, y = cy, z = cz;
+  AtomState &a = state[d.state_off + (i - d.atom_off)];
   if (d.periodic) {
-    x -= floorf(x / d.L[0]) * d.L[0];
-    y -= floorf(y / d.L[1]) * d.L[1];
-    z -= floorf(z / d.L[2]) * d.L[2];
-    if (x >= d.L[0]) x -= d.L[0];
-    if (y >= d.L[1]) y -= d.L[1];
-    if (z >= d.L[2]) z -= d.L[2];
-    x = fmaxf(x, 0.f); y = fmaxf(y, 0.f); z = fmaxf(z, 0.f);
+    float wx, wy, wz;
+    if (d.rebuild) {
+      wx = floorf(cx / d.L[0]); wy = floorf(cy / d.L[1]); wz = floorf(cz / d.L[2]);
+    } else {
+      const float4 w = a.wrap;
+      wx = w.x; wy = w.y; wz = w.z;
+    }
+    x = cx - wx * d.L[0];
+    y = cy - wy * d.L[1];
+    z = cz - wz * d.L[2];
+    if (d.rebuild) {
+      // rounding can land exactly on L: fold into the cell grid's range
+      if (x >= d.L[0]) { x -= d.L[0]; wx += 1.f; }
+      if (y >= d.L[1]) { y -= d.L[1]; wy += 1.f; }
+      if (z >= d.L[2]) { z -= d.L[2]; wz += 1.f; }
+      a.wrap = make_float4(wx, wy, wz, 0.f);
+    }
   }
+  if (d.rebuild) a.ref = make_float4(cx, cy, cz, 0.f);
   int s = species[i];
   if (s < 0 || s >= S) {
     atomicOr(status, kStatBadSpecies);
@@ -43,10 +58,45 @@ __global__ void k_ingest(const float *__restrict__ coords, const int *__restrict
 }
 
 void launch_ingest(const float *coords, const int *species, const SysDesc *sys, int n_sys,
-                   int N, int S, float4 *pos, int *sys_of, int *status, hipStream_t st) {
+                   int N, int S, float4 *pos, int *sys_of, AtomState *state, int *status,
+                   hipStream_t st) {
   if (N <= 0) return;
   k_ingest<<<(N + 255) / 256, 256, 0, st>>>(coords, species, sys, n_sys, N, S, pos, sys_of,
-                                            status);
+                                            state, status);
+}
+
+// One wave per system: a system that keeps its neighbour list is rebuilt
+// once any atom has moved more than half the skin since the last build
+// (then no pair can have entered the cutoff unseen).  stats[0] counts builds.
+__global__ void k_skin_check(const float *__restrict__ coords, SysDesc *__restrict__ sys, int n_sys,
+                             const AtomState *__restrict__ state, float half_skin,
+                             int *__restrict__ stats) {
+  const int s = blockIdx.x;
+  if (s >= n_sys) return;
+  const int lane = threadIdx.x;
+  const SysDesc d = sys[s];
+  int rebuild = d.rebuild;
+  if (!rebuild) {
+    float mx = 0.f;
+    for (int a = lane; a < d.n; a += kWave) {
+      const int i = d.atom_off + a;
+      const float4 r = state[d.state_off + a].ref;
+      const float dx = coords[3 * i] - r.x, dy = coords[3 * i + 1] - r.y, dz = coords[3 * i + 2] - r.z;
+      mx = fmaxf(mx, dx * dx + dy * dy + dz * dz);
+    }
+    for (int off = 32; off >= 1; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off));
+    rebuild = mx > half_skin * half_skin;
+  }
+  if (lane == 0) {
+    sys[s].rebuild = rebuild;
+    if (rebuild && d.n > 0) atomicAdd(stats, 1);
+  }
+}
+
+void launch_skin_check(const float *coords, SysDesc *sys, int n_sys, const AtomState *state,
+                       float half_skin, int *stats, hipStream_t st) {
+  if (n_sys <= 0) return;
+  k_skin_check<<<n_sys, kWave, 0, st>>>(coords, sys, n_sys, state, half_skin, stats);
 }
 
 // -------------------------------------------------------------- cell grids
@@ -207,17 +257,33 @@ void launch_cell_sort(const int *cell_start, int n_cells, int *cell_atoms, hipSt
 }
 
 // ----------------------------------------------------------- neighbour list
-// Thread per atom: scan the stencil of cells around the atom's cell (every
-// periodic image through the wrap of the cell index) and keep each (j, image)
-// with |d| < rc_list, excluding the atom itself in the home image.
-__global__ void k_nbr_build(const float4 *__restrict__ pos, const int *__restrict__ sys_of,
-                            const SysDesc *__restrict__ sys, const int *__restrict__ cell_start,
-                            const int *__restrict__ cell_atoms, int N, float rc_list, int cap,
-                            int2 *__restrict__ nbr, int *__restrict__ nbr_cnt,
-                            int *__restrict__ status) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
+// One wave per atom: walk the stencil of cells around the atom's cell (every
+// periodic image through the wrap of the cell index), the lanes splitting each
+// cell's atoms, and keep each (j, image) with |d| < rc_list except the atom
+// itself in the home image.  Entries are appended in cell order and, within a
+// cell, in sorted atom order (ballot prefix), so the list is deterministic.
+__device__ inline void wrap_cell(int u, int nc, bool periodic, int &w, int &shift, bool &ok) {
+  if (periodic) {
+    shift = u >= 0 ? u / nc : -((-u + nc - 1) / nc);
+    w = u - shift * nc;
+    ok = true;
+  } else {
+    ok = u >= 0 && u < nc;
+    w = u;
+    shift = 0;
+  }
+}
+
+__global__ void __launch_bounds__(256)
+k_nbr_build(const float4 *__restrict__ pos, const int *__restrict__ sys_of,
+            const SysDesc *__restrict__ sys, const int *__restrict__ cell_start,
+            const int *__restrict__ cell_atoms, int N, float rc_list, int cap,
+            int2 *__restrict__ nbr, int *__restrict__ nbr_cnt, int *__restrict__ status) {
+  const int lane = threadIdx.x % kWave;
+  const int i = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
   if (i >= N) return;
   const SysDesc d = sys[sys_of[i]];
+  if (!d.rebuild) return;
   const float4 p = pos[i];
   const float rc2 = rc_list * rc_list;
   int c[3], k[3];
@@ -227,63 +293,58 @@ __global__ void k_nbr_build(const float4 *__restrict__ pos, const int *__restric
     k[a] = d.periodic ? (int)ceilf(rc_list / d.edge[a]) : 1;
   }
   int cnt = 0;
-  int2 *out = nbr + (size_t)i * cap;
+  int2 *out = nbr + nbr_row(d, i, cap);
   for (int ox = -k[0]; ox <= k[0]; ++ox) {
-    int ux = c[0] + ox, wx, sx;
-    if (d.periodic) {
-      sx = ux >= 0 ? ux / d.nc[0] : -((-ux + d.nc[0] - 1) / d.nc[0]);
-      wx = ux - sx * d.nc[0];
-    } else {
-      if (ux < 0 || ux >= d.nc[0]) continue;
-      wx = ux; sx = 0;
-    }
+    int wx, sx; bool okx;
+    wrap_cell(c[0] + ox, d.nc[0], d.periodic, wx, sx, okx);
+    if (!okx) continue;
     for (int oy = -k[1]; oy <= k[1]; ++oy) {
-      int uy = c[1] + oy, wy, sy;
-      if (d.periodic) {
-        sy = uy >= 0 ? uy / d.nc[1] : -((-uy + d.nc[1] - 1) / d.nc[1]);
-        wy = uy - sy * d.nc[1];
-      } else {
-        if (uy < 0 || uy >= d.nc[1]) continue;
-        wy = uy; sy = 0;
-      }
+      int wy, sy; bool oky;
+      wrap_cell(c[1] + oy, d.nc[1], d.periodic, wy, sy, oky);
+      if (!oky) continue;
       for (int oz = -k[2]; oz <= k[2]; ++oz) {
-        int uz = c[2] + oz, wz, sz;
-        if (d.periodic) {
-          sz = uz >= 0 ? uz / d.nc[2] : -((-uz + d.nc[2] - 1) / d.nc[2]);
-          wz = uz - sz * d.nc[2];
-        } else {
-          if (uz < 0 || uz >= d.nc[2]) continue;
-          wz = uz; sz = 0;
-        }
+        int wz, sz; bool okz;
+        wrap_cell(c[2] + oz, d.nc[2], d.periodic, wz, sz, okz);
+        if (!okz) continue;
         const float shx = sx * d.L[0], shy = sy * d.L[1], shz = sz * d.L[2];
         const bool home = (sx | sy | sz) == 0;
+        const int code = pack_image(sx, sy, sz);
         const int cell = d.cell_off + (wx * d.nc[1] + wy) * d.nc[2] + wz;
         const int qb = cell_start[cell], qe = cell_start[cell + 1];
-        for (int q = qb; q < qe; ++q) {
-          int j = cell_atoms[q];
-          if (home && j == i) continue;
-          float4 pj = pos[j];
-          float dx = (pj.x - p.x) + shx, dy = (pj.y - p.y) + shy, dz = (pj.z - p.z) + shz;
-          float r2 = dx * dx + dy * dy + dz * dz;
-          if (r2 < rc2) {
-            if (cnt < cap) out[cnt] = make_int2(j, pack_image(sx, sy, sz));
-            ++cnt;
+        for (int base = qb; base < qe; base += kWave) {
+          const int q = base + lane;
+          bool inside = false;
+          int j = 0;
+          if (q < qe) {
+            j = cell_atoms[q];
+            const float4 pj = pos[j];
+            const float dx = (pj.x - p.x) + shx, dy = (pj.y - p.y) + shy, dz = (pj.z - p.z) + shz;
+            inside = dx * dx + dy * dy + dz * dz < rc2 && !(home && j == i);
           }
+          const unsigned long long m = __ballot(inside);
+          const int at = cnt + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
+                                                               __builtin_amdgcn_mbcnt_lo((unsigned)m, 0));
+          if (inside && at < cap) out[at] = make_int2(j - d.atom_off, code);
+          cnt += __popcll(m);
         }
       }
     }
   }
-  nbr_cnt[i] = cnt;
-  if (cnt > cap) atomicOr(status, kStatOverflow);
-  atomicMax(status + 1, cnt);
+  if (lane == 0) {
+    nbr_cnt[d.state_off + (i - d.atom_off)] = cnt;
+    if (cnt > cap) atomicOr(status, kStatOverflow);
+    // most waves do not raise the maximum: read before the atomic
+    if (cnt > __hip_atomic_load(status + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+      atomicMax(status + 1, cnt);
+  }
 }
 
 void launch_nbr_build(const float4 *pos, const int *sys_of, const SysDesc *sys,
                       const int *cell_start, const int *cell_atoms, int N, float rc_list, int cap,
                       int2 *nbr, int *nbr_cnt, int *status, hipStream_t st) {
   if (N <= 0) return;
-  k_nbr_build<<<(N + 127) / 128, 128, 0, st>>>(pos, sys_of, sys, cell_start, cell_atoms, N,
-                                               rc_list, cap, nbr, nbr_cnt, status);
+  k_nbr_build<<<(N + 3) / 4, 256, 0, st>>>(pos, sys_of, sys, cell_start, cell_atoms, N, rc_list,
+                                           cap, nbr, nbr_cnt, status);
 }
 
 // ----------------------------------------------------------- species buckets
@@ -417,26 +478,29 @@ void launch_gather_rows(const float *src, int ld, const int *row_of_atom, int N,
 }
 
 __global__ void k_export_nbr(const int2 *__restrict__ nbr, const int *__restrict__ nbr_cnt, int cap,
-                             int N, int *__restrict__ counts, int *__restrict__ entries,
-                             int out_cap) {
+                             const SysDesc *__restrict__ sys, const int *__restrict__ sys_of, int N,
+                             int *__restrict__ counts, int *__restrict__ entries, int out_cap) {
   int i = blockIdx.x;
   if (i >= N) return;
-  int n = nbr_cnt[i];
+  const SysDesc d = sys[sys_of[i]];
+  int n = nbr_cnt[d.state_off + (i - d.atom_off)];
   if (threadIdx.x == 0) counts[i] = n;
   int w = min(min(n, cap), out_cap);
+  const int2 *row = nbr + nbr_row(d, i, cap);
   for (int e = threadIdx.x; e < w; e += blockDim.x) {
-    int2 v = nbr[(size_t)i * cap + e];
+    int2 v = row[e];
     int x, y, z;
     unpack_image(v.y, x, y, z);
     int *o = entries + ((size_t)i * out_cap + e) * 4;
-    o[0] = v.x; o[1] = x; o[2] = y; o[3] = z;
+    o[0] = v.x + d.atom_off; o[1] = x; o[2] = y; o[3] = z;
   }
 }
 
-void launch_export_nbr(const int2 *nbr, const int *nbr_cnt, int cap, int N, int *counts,
-                       int *entries, int out_cap, hipStream_t st) {
+void launch_export_nbr(const int2 *nbr, const int *nbr_cnt, int cap, const SysDesc *sys,
+                       const int *sys_of, int N, int *counts, int *entries, int out_cap,
+                       hipStream_t st) {
   if (N <= 0) return;
-  k_export_nbr<<<N, 64, 0, st>>>(nbr, nbr_cnt, cap, N, counts, entries, out_cap);
+  k_export_nbr<<<N, 64, 0, st>>>(nbr, nbr_cnt, cap, sys, sys_of, N, counts, entries, out_cap);
 }
 
 __global__ void k_f32_to_bf16(const float *__restrict__ src, uint16_t *__restrict__ dst, size_t n) {

@@ -182,6 +182,68 @@ class NNPModel:
         return {names[q].decode(): float(ms[q]) for q in range(k)}
 
 
+class NeighborPool:
+    """Persistent device-resident neighbour lists (nnp_nlist): `slots` atom
+    slots, lists built with cutoff rc_rad + skin and reused until an atom of
+    the system has moved more than skin / 2 since its last build."""
+
+    def __init__(self, model: NNPModel, slots: int, capacity: int = 256, skin: float = 1.0):
+        self.model = model
+        self.slots = int(slots)
+        self.capacity = int(capacity)
+        self.skin = float(skin)
+        h = C.c_void_p()
+        with torch.cuda.device(model.device):
+            nat.check(nat.load().nnp_nlist_create(model.handle, self.slots, self.capacity,
+                                                  self.skin, C.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            nat.load().nnp_nlist_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def builds(self) -> int:
+        b = C.c_int64()
+        with torch.cuda.device(self.model.device):
+            nat.check(nat.load().nnp_nlist_builds(self._h, _stream_handle(self.model.device), C.byref(b)))
+        return int(b.value)
+
+    def energy_forces(self, coords, species, boxes, offsets, slots, rebuild=None,
+                      forces: bool = True, virial: bool = False, atom_energy: bool = False,
+                      out: Result | None = None) -> Result:
+        """Energies (and forces) of a batch whose system s keeps its list in
+        pool slots [slots[s], slots[s] + n_s); rebuild[s] != 0 forces a fresh list."""
+        m = self.model
+        coords, species, bx, offs, S = m._inputs(coords, species, boxes, offsets)
+        N = int(offs[-1])
+        sl = np.ascontiguousarray(np.asarray(slots, dtype=np.int64))
+        rb = None if rebuild is None else np.ascontiguousarray(np.asarray(rebuild, dtype=np.int32))
+        if out is None:
+            out = Result(energy=torch.empty(S, dtype=torch.float64, device=m.device))
+            if forces:
+                out.forces = torch.empty((N, 3), dtype=torch.float32, device=m.device)
+            if virial:
+                out.virial = torch.empty((S, 3, 3), dtype=torch.float64, device=m.device)
+            if atom_energy:
+                out.atom_energy = torch.empty(N, dtype=torch.float32, device=m.device)
+        ptr = lambda t: C.c_void_p(t.data_ptr()) if t is not None else None
+        with torch.cuda.device(m.device):
+            nat.check(nat.load().nnp_energy_forces_nlist(
+                m.handle, self._h, S, offs.ctypes.data_as(C.POINTER(C.c_int64)),
+                sl.ctypes.data_as(C.POINTER(C.c_int64)),
+                rb.ctypes.data_as(C.POINTER(C.c_int32)) if rb is not None else None,
+                ptr(coords), ptr(species), _fptr(bx), ptr(out.energy), ptr(out.forces),
+                ptr(out.virial), ptr(out.atom_energy), _stream_handle(m.device)))
+        return out
+
+
 class NNPFunction(torch.autograd.Function):
     """E = NNPFunction.apply(coords, species, boxes, offsets, model) -> [S] float64.
 
