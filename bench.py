@@ -33,13 +33,17 @@ def parse():
     p.add_argument("--steps", type=int, default=20)
     p.add_argument("--warmup", type=int, default=5)
     p.add_argument("--workload", default="ragged512",
-                   choices=["ragged512", "water2001", "protein100k", "cluster24"])
+                   choices=["ragged512", "water2001", "protein100k", "cluster24", "serve", "copy"])
     p.add_argument("--precision", default="bf16", choices=["bf16", "fp32"])
     p.add_argument("--no-plain", action="store_true")
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--plain-passes", type=int, default=2)
     p.add_argument("--cpu-seconds", type=float, default=15.0)
     p.add_argument("--quiet", action="store_true")
+    p.add_argument("--requests", type=int, default=200, help="serving: requests in the trace")
+    p.add_argument("--rate", type=float, default=2000.0, help="serving: Poisson arrival rate (1/s)")
+    p.add_argument("--req-steps", type=int, default=50, help="serving: steps per request")
+    p.add_argument("--plain-requests", type=int, default=12, help="serving: sample for the plain path")
     return p.parse_args()
 
 
@@ -132,6 +136,129 @@ def mlp_flops(spec, species):
     return fwd, bwd
 
 
+def copy_probe(args):
+    """A plain device-to-device copy of 1 GiB: the known-size reference for
+    the HBM byte counters (FETCH_SIZE, WRITE_SIZE) of rocprofv3."""
+    import torch
+    n = 1 << 28  # float32 elements = 1 GiB
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(max(1, args.steps)):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n,
+                      "launches": max(1, args.steps)}), flush=True)
+
+
+def serve_bench(args):
+    """Serving: a Poisson stream of requests (log-uniform 20-5000 atoms, half
+    periodic water boxes, half dense solutes), each a random walk of
+    `req_steps` steps, through the continuous-batching server (bfloat16 dense
+    layers, persistent neighbour lists with a 1 A skin); beside it a seeded
+    sample of the same requests through the plain path (float32, one request
+    and one step per call, fresh lists)."""
+    import torch
+    import synth
+    from paper_2207_14276_amd import NNPModel
+    from paper_2207_14276_amd.serve import GpuExecutor, Job, Scheduler, SystemPayload, serve
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    spec = synth.make_model(0)
+    say(args, f"generating {args.requests} requests")
+    trace = synth.request_trace(args.requests, seed=4, rate=args.rate, n_steps=args.req_steps)
+    sizes = np.array([r.system.n for r in trace])
+    cap = 640   # dense 5000-atom solutes: ~550 neighbours within rc + skin
+    model = NNPModel(spec, "bf16")
+    slots = int(sizes.sum()) + 1024
+    max_batch = int(min(slots, 400000))
+    model.reserve(max_batch, len(trace), cap)
+
+    def jobs():
+        out = []
+        for rid, r in enumerate(trace):
+            p = SystemPayload(r.system.coords, r.system.species, r.system.box, seed=r.seed, sigma=0.01)
+            out.append((r.arrival, Job(rid, r.system.n, args.req_steps, 0.0, payload=p)))
+        return out
+
+    # warm-up pass on a few requests (kernel loading, workspace growth)
+    ex = GpuExecutor(model, slots=slots, capacity=cap, skin=1.0)
+    warm = Scheduler(slots=slots, max_batch_atoms=max_batch)
+    serve(ex, warm, [(0.0, j) for _, j in jobs()[:8]], sync=torch.cuda.synchronize, max_iterations=5)
+    torch.cuda.synchronize()
+
+    ex = GpuExecutor(model, slots=slots, capacity=cap, skin=1.0)
+    sched = Scheduler(slots=slots, max_batch_atoms=max_batch)
+    say(args, "serving")
+    wall = serve(ex, sched, jobs(), sync=torch.cuda.synchronize)
+    model.status()
+    lat = sched.latencies(skip=len(trace) // 10) * 1e3
+    value = sched.atom_evals / wall
+    builds = ex.builds()
+
+    # plain: float32, one request at a time, one step per call, fresh lists
+    plain = NNPModel(spec, "fp32")
+    plain.reserve(int(sizes.max()), 1, cap)
+    rng = np.random.default_rng(7)
+    pick = sorted(rng.choice(len(trace), min(args.plain_requests, len(trace)), replace=False).tolist())
+    p_atoms, p_time, p_lat = 0, 0.0, []
+    for k in pick:
+        r = trace[k]
+        c = torch.as_tensor(r.system.coords, device=dev)
+        s = torch.as_tensor(r.system.species, device=dev)
+        box = r.system.box[None, :]
+        offs = np.array([0, r.system.n], np.int64)
+        g = torch.Generator(device=dev)
+        g.manual_seed(int(r.seed))
+        out = plain.energy_forces(c, s, box, offs)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.req_steps):
+            plain.energy_forces(c, s, box, offs, out=out)
+            torch.cuda.synchronize()
+            c.add_(torch.randn(c.shape, generator=g, device=dev) * 0.01)
+        dt = time.perf_counter() - t0
+        p_time += dt
+        p_atoms += r.system.n * args.req_steps
+        p_lat.append(dt * 1e3)
+    plain.status()
+    plain_rate = p_atoms / p_time
+    offered = args.rate * args.req_steps * float(sizes.mean())
+    out = {
+        "metric": "energy+force atom-evals/s (serving)",
+        "value": round(value, 1),
+        "unit": "atom-evals/s",
+        "n_gpus": 1,
+        "steps": int(sched.iterations),
+        "warmup": 5,
+        "ms_per_step": round(wall / max(sched.iterations, 1) * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16-mlp/f32-aev",
+        "data": "synthetic",
+        "config": {"workload": f"serving: {len(trace)} requests, Poisson {args.rate:g}/s, "
+                               f"log-uniform 20-5000 atoms (half water boxes, half solutes), "
+                               f"{args.req_steps} random-walk steps each",
+                   "mean_atoms": round(float(sizes.mean()), 1),
+                   "offered_atom_evals_per_s": round(offered, 1),
+                   "form": "continuous batching, persistent lists (1 A skin)",
+                   "parallelism": "single GPU"},
+        "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3),
+                       "p99": round(float(np.percentile(lat, 99)), 3),
+                       "requests": int(len(lat)), "excluded_warmup_requests": len(trace) // 10},
+        "wall_s": round(wall, 3),
+        "neighbour_list_builds": builds,
+        "plain_fp32_sequential": {"value": round(plain_rate, 1), "unit": "atom-evals/s",
+                                  "sample": f"{len(pick)} requests x {args.req_steps} steps",
+                                  "service_ms_p50": round(float(np.percentile(p_lat, 50)), 3),
+                                  "note": "service time only; at the offered load its queue grows "
+                                          "without bound"},
+        "speedup_vs_plain": round(value / plain_rate, 2),
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -145,6 +272,12 @@ def main():
     import synth
     from paper_2207_14276_amd import NNPModel
 
+    if args.workload == "serve":
+        serve_bench(args)
+        return
+    if args.workload == "copy":
+        copy_probe(args)
+        return
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
     batch, spec, desc = workload(args.workload)

@@ -19,8 +19,9 @@
 //            stream, one pair per lane; a lane evaluates all 8 angle shifts
 //            of its pair against the block's dE/dG values (staged in LDS),
 //            differentiates through cos, sin, R_j and R_k, and accumulates
-//            dE/dd_j and dE/dd_k per neighbour entry in LDS.  Forces are then
-//            scattered with float atomics.
+//            dE/dd_j and dE/dd_k per neighbour entry in LDS (64-bit fixed
+//            point, integer atomics).  Forces are then scattered with float
+//            atomics.
 #include "internal.h"
 
 namespace nnp {
@@ -38,6 +39,14 @@ __device__ inline float fast_log2(float x) { return __builtin_amdgcn_logf(x); }
 // correctly rounded division and square-root sequences.
 __device__ inline float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ inline float fast_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+
+// dE/dd accumulators in LDS are 64-bit fixed point with 2^-32 resolution:
+// integer LDS atomics are fast on this hardware where float LDS atomics are
+// not, and integer sums are exact and independent of the order of the adds.
+constexpr float kFix = 4294967296.0f;         // 2^32
+constexpr float kUnfix = 2.3283064365386963e-10f;  // 2^-32
+__device__ inline long long to_fix(float v) { return (long long)(v * kFix); }
+__device__ inline float from_fix(long long v) { return (float)v * kUnfix; }
 
 // q = u / n and r = u mod n for 0 <= u < 2^24 through a float reciprocal
 // (rn = 1/n), corrected to the exact integer result.
@@ -100,7 +109,7 @@ struct WaveLds {
   float *rFc;      // radial: fc_rad(R)
   float *rDfc;     // radial: fc_rad'(R)         (backward)
   int *rJ;         // radial: neighbour index     (backward)
-  float *rG;       // radial: dE/dd accumulators  (backward, 3 per entry)
+  long long *rG;   // radial: dE/dd accumulators, fixed point (backward, 3 per entry)
   int *aIdx;       // angular: position in the radial arrays
   float *aFc;      // angular: fc_ang(R)
   float *aDfc;     // angular: fc_ang'(R)         (backward)
@@ -109,8 +118,9 @@ struct WaveLds {
 template <bool BWD>
 __host__ __device__ inline size_t wave_lds_bytes(int cap) {
   return BWD ? (size_t)kMaxAng * 4 + sizeof(PairBlock) * (kMaxBlocks + 1) +
-                   (size_t)cap * (16 + 4 + 4 + 4 + 12 + 4 + 4 + 4)
+                   (size_t)cap * (16 + 4 + 4 + 4 + 24 + 4 + 4 + 4)
              : (size_t)kPairPass * 16 * 2 + (size_t)cap * (16 + 4 + 4 + 4);
+  // backward entry: rD 16, rFc 4, aIdx 4, aFc 4, rDfc 4, rJ 4, rG 24, aDfc 4
 }
 
 template <bool BWD>
@@ -131,10 +141,38 @@ __device__ inline WaveLds carve(char *base, int cap) {
   if (BWD) {
     w.rDfc = (float *)p; p += (size_t)cap * 4;
     w.rJ = (int *)p; p += (size_t)cap * 4;
-    w.rG = (float *)p; p += (size_t)cap * 12;
+    w.rG = (long long *)p; p += (size_t)cap * 24;
     w.aDfc = (float *)p; p += (size_t)cap * 4;
   }
   return w;
+}
+
+// Lane reductions on the VALU (DPP) rather than through the LDS crossbar.
+template <int CTRL, int ROWS = 0xF> __device__ inline float dpp(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWS, 0xF, false));
+}
+// sum over aligned groups of 4 / 8 / 16 lanes, result in every lane of the group
+__device__ inline float sum4(float v) {
+  v += dpp<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp<0x4E>(v);   // quad_perm [2,3,0,1]
+  return v;
+}
+__device__ inline float sum8(float v) {
+  v = sum4(v);
+  v += dpp<0x141>(v);  // row_half_mirror: quads 0 <-> 1 of each half-row
+  return v;
+}
+__device__ inline float sum16(float v) {
+  v = sum8(v);
+  v += dpp<0x140>(v);  // row_mirror: halves 0 <-> 1 of each row
+  return v;
+}
+// sum over the whole wave, returned in every lane
+__device__ inline float wave_sum(float v) {
+  v = sum16(v);
+  v += dpp<0x142, 0xA>(v);  // row_bcast15 into rows 1 and 3
+  v += dpp<0x143, 0xC>(v);  // row_bcast31 into rows 2 and 3
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
 }
 
 // Builds the table of non-empty species-pair blocks of the angular list
@@ -280,7 +318,7 @@ __device__ inline void fill_lists(int lane, int n, const int2 *__restrict__ ent,
         if (BWD) {
           w.rDfc[q] = -0.5f * kr * sn;
           w.rJ[q] = j;
-          w.rG[3 * q] = 0.f; w.rG[3 * q + 1] = 0.f; w.rG[3 * q + 2] = 0.f;
+          w.rG[3 * q] = 0; w.rG[3 * q + 1] = 0; w.rG[3 * q + 2] = 0;
         }
       }
       if (inA && sj == s) {
@@ -338,19 +376,23 @@ k_aev_fwd(const float4 *__restrict__ pos, const int *__restrict__ sys_of,
   void *Grow = (char *)G + (size_t)row_of_atom[i] * ldg * (BF16 ? 2 : 4);
 
   // radial: G[16 s + m] = scale * sum_j exp(-eta (R - Rs_m)^2) fc(R)
+  // lanes = 16 shifts x 4 neighbour slots (slot fastest)
   {
-    const int m = lane & 15, slot = lane >> 4;
+    const int m = lane >> 2, slot = lane & 3;
     const float shf = c.shf_r[m];
     for (int s = 0; s < c.S; ++s) {
       float acc = 0.f;
       const int o = ls.oR[s];
-      for (int e = slot; e < ls.cR[s]; e += 4) {
-        float R = w.rD[o + e].w;
-        float t = R - shf;
-        acc += fast_exp(-c.eta_r * t * t) * w.rFc[o + e];
+      const int cnt = ls.cR[s];
+      for (int e0 = 0; e0 < cnt; e0 += 4) {
+        const int e = e0 + slot;
+        if (e < cnt) {
+          float R = w.rD[o + e].w;
+          float t = R - shf;
+          acc += fast_exp(-c.eta_r * t * t) * w.rFc[o + e];
+        }
       }
-      acc += __shfl_xor(acc, 16);
-      acc += __shfl_xor(acc, 32);
+      acc = sum4(acc);
       if (slot == 0) put<BF16>(Grow, s * kNShfRad + m, acc * c.scale);
     }
   }
@@ -358,7 +400,7 @@ k_aev_fwd(const float4 *__restrict__ pos, const int *__restrict__ sys_of,
   // angular: G[rad_len + 32 p + 8 r + a] = sum over pairs {j, k} of
   //   2^(1-zeta) (1 + cos(theta - theta_a))^zeta exp(-eta (Rbar - Rs_r)^2) fc_j fc_k
   {
-    const int a = lane & 7, t0 = lane >> 3;
+    const int a = lane >> 3, t0 = lane & 7;  // 8 angle shifts x 8 pairs (pair fastest)
     const float cza = c.cz[a], sza = c.sz[a];
     const float pre = 1.0f - c.zeta;
     const float keta = -c.eta_a * 1.4426950408889634f;
@@ -406,12 +448,10 @@ k_aev_fwd(const float4 *__restrict__ pos, const int *__restrict__ sys_of,
           }
           wave_lds_sync();
         }
-        for (int off = 8; off < kWave; off <<= 1) {
-          acc0 += __shfl_xor(acc0, off);
-          acc1 += __shfl_xor(acc1, off);
-          acc2 += __shfl_xor(acc2, off);
-          acc3 += __shfl_xor(acc3, off);
-        }
+        acc0 = sum8(acc0);
+        acc1 = sum8(acc1);
+        acc2 = sum8(acc2);
+        acc3 = sum8(acc3);
         if (t0 == 0) {
           const int o = c.rad_len + p * kAngBlock + a;
           put<BF16>(Grow, o, acc0);
@@ -466,15 +506,11 @@ k_aev_bwd(const float4 *__restrict__ pos, const int *__restrict__ sys_of,
         const float4 d = w.rD[o + e];
         const float t = d.w - shf;
         const float ex = fast_exp(-c.eta_r * t * t);
-        float term = gm * ex * (-2.0f * c.eta_r * t * w.rFc[o + e] + w.rDfc[o + e]);
-        term += __shfl_xor(term, 1);
-        term += __shfl_xor(term, 2);
-        term += __shfl_xor(term, 4);
-        term += __shfl_xor(term, 8);
+        float term = sum16(gm * ex * (-2.0f * c.eta_r * t * w.rFc[o + e] + w.rDfc[o + e]));
         if (m == 0) {
           const float q = term * fast_rcp(d.w);
-          float *gg = w.rG + 3 * (o + e);
-          gg[0] = q * d.x; gg[1] = q * d.y; gg[2] = q * d.z;
+          long long *gg = w.rG + 3 * (o + e);
+          gg[0] = to_fix(q * d.x); gg[1] = to_fix(q * d.y); gg[2] = to_fix(q * d.z);
         }
       }
     }
@@ -565,13 +601,14 @@ k_aev_bwd(const float4 *__restrict__ pos, const int *__restrict__ sys_of,
         const float ck = (dRk - cs * invk) * invk;
         const float sjj = ak_ * dk.w * dk.w, sjk = -ak_ * dot;
         const float skk = ak_ * dj.w * dj.w, skj = -ak_ * dot;
-        float *gj = w.rG + 3 * qj, *gk = w.rG + 3 * qk;
-        atomicAdd(gj + 0, aj_ * dk.x + sjj * dj.x + sjk * dk.x + cj * dj.x);
-        atomicAdd(gj + 1, aj_ * dk.y + sjj * dj.y + sjk * dk.y + cj * dj.y);
-        atomicAdd(gj + 2, aj_ * dk.z + sjj * dj.z + sjk * dk.z + cj * dj.z);
-        atomicAdd(gk + 0, aj_ * dj.x + skk * dk.x + skj * dj.x + ck * dk.x);
-        atomicAdd(gk + 1, aj_ * dj.y + skk * dk.y + skj * dj.y + ck * dk.y);
-        atomicAdd(gk + 2, aj_ * dj.z + skk * dk.z + skj * dj.z + ck * dk.z);
+        unsigned long long *gj = (unsigned long long *)(w.rG + 3 * qj);
+        unsigned long long *gk = (unsigned long long *)(w.rG + 3 * qk);
+        atomicAdd(gj + 0, (unsigned long long)to_fix(aj_ * dk.x + sjj * dj.x + sjk * dk.x + cj * dj.x));
+        atomicAdd(gj + 1, (unsigned long long)to_fix(aj_ * dk.y + sjj * dj.y + sjk * dk.y + cj * dj.y));
+        atomicAdd(gj + 2, (unsigned long long)to_fix(aj_ * dk.z + sjj * dj.z + sjk * dk.z + cj * dj.z));
+        atomicAdd(gk + 0, (unsigned long long)to_fix(aj_ * dj.x + skk * dk.x + skj * dj.x + ck * dk.x));
+        atomicAdd(gk + 1, (unsigned long long)to_fix(aj_ * dj.y + skk * dk.y + skj * dj.y + ck * dk.y));
+        atomicAdd(gk + 2, (unsigned long long)to_fix(aj_ * dj.z + skk * dk.z + skj * dj.z + ck * dk.z));
       }
     }
     wave_lds_sync();
@@ -586,7 +623,7 @@ k_aev_bwd(const float4 *__restrict__ pos, const int *__restrict__ sys_of,
     for (int q = 0; q < 9; ++q) vir[q] = 0.f;
     for (int e = lane; e < nR; e += kWave) {
       const float4 d = w.rD[e];
-      const float gx = w.rG[3 * e], gy = w.rG[3 * e + 1], gz = w.rG[3 * e + 2];
+      const float gx = from_fix(w.rG[3 * e]), gy = from_fix(w.rG[3 * e + 1]), gz = from_fix(w.rG[3 * e + 2]);
       const int j = w.rJ[e];
       fi0 += gx; fi1 += gy; fi2 += gz;
       atomicAdd(&F[3 * j], -gx);
@@ -596,12 +633,10 @@ k_aev_bwd(const float4 *__restrict__ pos, const int *__restrict__ sys_of,
       vir[3] -= d.y * gx; vir[4] -= d.y * gy; vir[5] -= d.y * gz;
       vir[6] -= d.z * gx; vir[7] -= d.z * gy; vir[8] -= d.z * gz;
     }
-    for (int off = 32; off >= 1; off >>= 1) {
-      fi0 += __shfl_xor(fi0, off);
-      fi1 += __shfl_xor(fi1, off);
-      fi2 += __shfl_xor(fi2, off);
-      for (int q = 0; q < 9; ++q) vir[q] += __shfl_xor(vir[q], off);
-    }
+    fi0 = wave_sum(fi0);
+    fi1 = wave_sum(fi1);
+    fi2 = wave_sum(fi2);
+    for (int q = 0; q < 9; ++q) vir[q] = wave_sum(vir[q]);
     if (lane == 0) {
       atomicAdd(&F[3 * i], fi0);
       atomicAdd(&F[3 * i + 1], fi1);

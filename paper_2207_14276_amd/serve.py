@@ -208,6 +208,11 @@ class GpuExecutor:
     def builds(self) -> int:
         return self.pool.builds()
 
+    def check(self):
+        """Waits for the device and raises on a device flag (neighbour
+        capacity overflow, bad species) of the calls so far."""
+        self.model.status()
+
 
 def serve(executor, sched: Scheduler, arrivals, clock=time.perf_counter, sync=None,
           max_iterations: int | None = None):
@@ -232,6 +237,8 @@ def serve(executor, sched: Scheduler, arrivals, clock=time.perf_counter, sync=No
         executor.evaluate(batch)
         if sync is not None:
             sync()
+            if hasattr(executor, "check"):
+                executor.check()
         fin = sched.complete(batch, clock())
         executor.advance(batch, fin)
         it += 1

@@ -101,7 +101,8 @@ def _requests(n, seed, nmin=20, nmax=400, steps=6, record=()):
 
 def _run(model, jobs, spacing=0.0):
     from paper_2207_14276_amd.serve import GpuExecutor, Scheduler, serve
-    ex = GpuExecutor(model, slots=20000, capacity=256, skin=1.0)
+    # dense solutes reach ~550 neighbours inside rc + skin
+    ex = GpuExecutor(model, slots=20000, capacity=640, skin=1.0)
     sched = Scheduler(slots=20000, max_batch_atoms=20000)
     arrivals = [(k * spacing, j) for k, j in enumerate(jobs)]
     wall = serve(ex, sched, arrivals, sync=torch.cuda.synchronize)
