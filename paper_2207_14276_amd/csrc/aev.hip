@@ -59,8 +59,8 @@ __device__ inline int fdivmod(int u, int n, float rn, int &r) {
 
 // Wave-uniform per-species counts and offsets of the sorted lists.
 struct Lists {
-  int cR[kMaxSpecies], oR[kMaxSpecies];
-  int cA[kMaxSpecies], oA[kMaxSpecies];
+  int cR[8], oR[8];
+  int cA[8], oA[8];
 };
 
 // Neighbour vector d = r_j + image * L - r_i of entry e of centre i.
@@ -101,6 +101,8 @@ __device__ inline PairBlock make_block(int start, int p, int oa, int ob, int na,
 }
 
 struct WaveLds {
+  Lists *ls;       // per-species counts and offsets (wave-uniform)
+  float *xp;       // 32-feature block being written out              (forward)
   float4 *tGeo;    // pair scratch: cos, sin, fc_j fc_k, -      (forward)
   float4 *tF2;     // pair scratch: radial Gaussians of Rbar     (forward)
   PairBlock *blk;  // [kMaxBlocks + 1] pair-block table           (backward)
@@ -117,9 +119,9 @@ struct WaveLds {
 
 template <bool BWD>
 __host__ __device__ inline size_t wave_lds_bytes(int cap) {
-  return BWD ? (size_t)kMaxAng * 4 + sizeof(PairBlock) * (kMaxBlocks + 1) +
+  return sizeof(Lists) + (BWD ? (size_t)kMaxAng * 4 + sizeof(PairBlock) * (kMaxBlocks + 1) +
                    (size_t)cap * (16 + 4 + 4 + 4 + 24 + 4 + 4 + 4)
-             : (size_t)kPairPass * 16 * 2 + (size_t)cap * (16 + 4 + 4 + 4);
+             : (size_t)kAngBlock * 4 + (size_t)kPairPass * 16 * 2 + (size_t)cap * (16 + 4 + 4 + 4));
   // backward entry: rD 16, rFc 4, aIdx 4, aFc 4, rDfc 4, rJ 4, rG 24, aDfc 4
 }
 
@@ -127,10 +129,12 @@ template <bool BWD>
 __device__ inline WaveLds carve(char *base, int cap) {
   WaveLds w{};
   char *p = base;
+  w.ls = (Lists *)p; p += sizeof(Lists);
   if (BWD) {
     w.gAng = (float *)p; p += (size_t)kMaxAng * 4;
     w.blk = (PairBlock *)p; p += sizeof(PairBlock) * (kMaxBlocks + 1);
   } else {
+    w.xp = (float *)p; p += (size_t)kAngBlock * 4;
     w.tGeo = (float4 *)p; p += (size_t)kPairPass * 16;
     w.tF2 = (float4 *)p; p += (size_t)kPairPass * 16;
   }
@@ -259,13 +263,17 @@ __device__ inline void wave_lds_sync() {
 // (R < rc_a, a subset) of centre i in LDS.  Two passes over the entries:
 // per-species counts by ballot, then placement.
 // Entries whose stored atom index is not below n_sys (a reused list applied
-// to a different system) are skipped, never dereferenced.
+// to a different system) are skipped, never dereferenced.  Per-species tallies
+// live in registers (loops over the species slots are fully unrolled) and the
+// wave-uniform result is published in LDS.
 template <bool BWD>
 __device__ inline void fill_lists(int lane, int n, const int2 *__restrict__ ent, int j0, int n_sys,
                                   const float4 *__restrict__ pos, const float4 &pi,
-                                  const float L[3], const AevConst &c, WaveLds &w, Lists &ls) {
+                                  const float L[3], const AevConst &c, WaveLds &w) {
   const int S = c.S;
-  for (int s = 0; s < kMaxSpecies; ++s) { ls.cR[s] = 0; ls.cA[s] = 0; }
+  int cR[kMaxSpecies], cA[kMaxSpecies];
+#pragma unroll
+  for (int s = 0; s < kMaxSpecies; ++s) { cR[s] = 0; cA[s] = 0; }
   for (int b = 0; b < n; b += kWave) {
     int e = b + lane;
     int2 en = make_int2(0, 0);
@@ -279,18 +287,28 @@ __device__ inline void fill_lists(int lane, int n, const int2 *__restrict__ ent,
       sj = __float_as_int(pj.w);
     }
     bool inR = v && R < c.rc_r, inA = v && R < c.rc_a;
-    for (int s = 0; s < S; ++s) {
-      ls.cR[s] += __popcll(__ballot(inR && sj == s));
-      ls.cA[s] += __popcll(__ballot(inA && sj == s));
+#pragma unroll
+    for (int s = 0; s < kMaxSpecies; ++s) {
+      cR[s] += __popcll(__ballot(inR && sj == s));
+      cA[s] += __popcll(__ballot(inA && sj == s));
     }
   }
-  int oR = 0, oA = 0;
-  for (int s = 0; s < S; ++s) {
-    ls.oR[s] = oR; oR += ls.cR[s];
-    ls.oA[s] = oA; oA += ls.cA[s];
-  }
   int pR[kMaxSpecies], pA[kMaxSpecies];
-  for (int s = 0; s < S; ++s) { pR[s] = ls.oR[s]; pA[s] = ls.oA[s]; }
+  {
+    int oR = 0, oA = 0;
+#pragma unroll
+    for (int s = 0; s < kMaxSpecies; ++s) {
+      pR[s] = oR; oR += cR[s];
+      pA[s] = oA; oA += cA[s];
+    }
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int s = 0; s < kMaxSpecies; ++s) {
+      w.ls->cR[s] = s < S ? cR[s] : 0; w.ls->oR[s] = pR[s];
+      w.ls->cA[s] = s < S ? cA[s] : 0; w.ls->oA[s] = pA[s];
+    }
+  }
   const float kr = kPi / c.rc_r, ka = kPi / c.rc_a;
   for (int b = 0; b < n; b += kWave) {
     int e = b + lane;
@@ -306,7 +324,8 @@ __device__ inline void fill_lists(int lane, int n, const int2 *__restrict__ ent,
       sj = __float_as_int(pj.w);
     }
     bool inR = v && d.w < c.rc_r, inA = v && d.w < c.rc_a;
-    for (int s = 0; s < S; ++s) {
+#pragma unroll
+    for (int s = 0; s < kMaxSpecies; ++s) {
       unsigned long long mR = __ballot(inR && sj == s);
       unsigned long long mA = __ballot(inA && sj == s);
       int q = pR[s] + (int)lanes_below(mR);
@@ -335,14 +354,35 @@ __device__ inline void fill_lists(int lane, int n, const int2 *__restrict__ ent,
   }
 }
 
-// One AEV feature out, float32 or rounded to bfloat16 (nearest even) for the
-// bfloat16 dense layers that consume it.
-template <bool BF16> __device__ inline void put(void *row, int k, float v);
-template <> __device__ inline void put<false>(void *row, int k, float v) { ((float *)row)[k] = v; }
-template <> __device__ inline void put<true>(void *row, int k, float v) {
-  uint32_t u = __float_as_uint(v);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  ((uint16_t *)row)[k] = (uint16_t)(u >> 16);
+// Element k of a small constant table for a lane-dependent k, by selects
+// (a dynamically indexed kernel argument would go through scratch memory).
+template <int N> __device__ inline float pick(const float (&t)[N], int k) {
+  float v = t[0];
+#pragma unroll
+  for (int q = 1; q < N; ++q) v = k == q ? t[q] : v;
+  return v;
+}
+
+__device__ inline uint32_t bf16_pair(float lo, float hi) {
+  uint32_t a = __float_as_uint(lo), b = __float_as_uint(hi);
+  a += 0x7fffu + ((a >> 16) & 1u);
+  b += 0x7fffu + ((b >> 16) & 1u);
+  return (a >> 16) | (b & 0xffff0000u);
+}
+
+// Eight consecutive features (row offset k, a multiple of 8) from LDS to the
+// feature row in one 16-byte (bfloat16) or two 16-byte (float32) stores.
+template <bool BF16> __device__ inline void store8(void *row, int k, const float *v);
+template <> __device__ inline void store8<true>(void *row, int k, const float *v) {
+  uint4 o;
+  o.x = bf16_pair(v[0], v[1]); o.y = bf16_pair(v[2], v[3]);
+  o.z = bf16_pair(v[4], v[5]); o.w = bf16_pair(v[6], v[7]);
+  *(uint4 *)((uint16_t *)row + k) = o;
+}
+template <> __device__ inline void store8<false>(void *row, int k, const float *v) {
+  float4 *d = (float4 *)((float *)row + k);
+  d[0] = make_float4(v[0], v[1], v[2], v[3]);
+  d[1] = make_float4(v[4], v[5], v[6], v[7]);
 }
 
 template <int WPB, bool BF16>
@@ -356,7 +396,6 @@ k_aev_fwd(const float4 *__restrict__ pos, const int *__restrict__ sys_of,
   const int i = blockIdx.x * WPB + wave;
   const bool live = i < N;
   WaveLds w = carve<false>((char *)lds4 + wave * wave_lds_bytes<false>(cap), cap);
-  Lists ls;
   float4 pi = make_float4(0.f, 0.f, 0.f, 0.f);
   float L[3] = {0.f, 0.f, 0.f};
   int n = 0, j0 = 0, n_sys = 0;
@@ -370,16 +409,17 @@ k_aev_fwd(const float4 *__restrict__ pos, const int *__restrict__ sys_of,
     j0 = d.atom_off;
     row = nbr + nbr_row(d, i, cap);
   }
-  fill_lists<false>(lane, n, row, j0, n_sys, pos, pi, L, c, w, ls);
+  fill_lists<false>(lane, n, row, j0, n_sys, pos, pi, L, c, w);
   __syncthreads();
   if (!live) return;
+  const Lists &ls = *w.ls;
   void *Grow = (char *)G + (size_t)row_of_atom[i] * ldg * (BF16 ? 2 : 4);
 
   // radial: G[16 s + m] = scale * sum_j exp(-eta (R - Rs_m)^2) fc(R)
   // lanes = 16 shifts x 4 neighbour slots (slot fastest)
   {
     const int m = lane >> 2, slot = lane & 3;
-    const float shf = c.shf_r[m];
+    const float shf = pick(c.shf_r, m);
     for (int s = 0; s < c.S; ++s) {
       float acc = 0.f;
       const int o = ls.oR[s];
@@ -393,7 +433,10 @@ k_aev_fwd(const float4 *__restrict__ pos, const int *__restrict__ sys_of,
         }
       }
       acc = sum4(acc);
-      if (slot == 0) put<BF16>(Grow, s * kNShfRad + m, acc * c.scale);
+      if (slot == 0) w.xp[m] = acc * c.scale;
+      wave_lds_sync();
+      if (lane < kNShfRad / 8) store8<BF16>(Grow, s * kNShfRad + 8 * lane, w.xp + 8 * lane);
+      wave_lds_sync();
     }
   }
 
@@ -401,7 +444,7 @@ k_aev_fwd(const float4 *__restrict__ pos, const int *__restrict__ sys_of,
   //   2^(1-zeta) (1 + cos(theta - theta_a))^zeta exp(-eta (Rbar - Rs_r)^2) fc_j fc_k
   {
     const int a = lane >> 3, t0 = lane & 7;  // 8 angle shifts x 8 pairs (pair fastest)
-    const float cza = c.cz[a], sza = c.sz[a];
+    const float cza = pick(c.cz, a), sza = pick(c.sz, a);
     const float pre = 1.0f - c.zeta;
     const float keta = -c.eta_a * 1.4426950408889634f;
     int p = 0;
@@ -452,13 +495,11 @@ k_aev_fwd(const float4 *__restrict__ pos, const int *__restrict__ sys_of,
         acc1 = sum8(acc1);
         acc2 = sum8(acc2);
         acc3 = sum8(acc3);
-        if (t0 == 0) {
-          const int o = c.rad_len + p * kAngBlock + a;
-          put<BF16>(Grow, o, acc0);
-          put<BF16>(Grow, o + kNShfZ, acc1);
-          put<BF16>(Grow, o + 2 * kNShfZ, acc2);
-          put<BF16>(Grow, o + 3 * kNShfZ, acc3);
-        }
+        // block [r][a] transposed through LDS, written as 4 x 8 features
+        if (t0 < kNShfAng) w.xp[kNShfZ * t0 + a] = t0 == 0 ? acc0 : t0 == 1 ? acc1 : t0 == 2 ? acc2 : acc3;
+        wave_lds_sync();
+        if (lane < kNShfAng) store8<BF16>(Grow, c.rad_len + p * kAngBlock + 8 * lane, w.xp + 8 * lane);
+        wave_lds_sync();
       }
     }
   }
@@ -476,7 +517,6 @@ k_aev_bwd(const float4 *__restrict__ pos, const int *__restrict__ sys_of,
   const int i = blockIdx.x * WPB + wave;
   const bool live = i < N;
   WaveLds w = carve<true>((char *)lds4 + wave * wave_lds_bytes<true>(cap), cap);
-  Lists ls;
   float4 pi = make_float4(0.f, 0.f, 0.f, 0.f);
   float L[3] = {0.f, 0.f, 0.f};
   int n = 0, j0 = 0, n_sys = 0;
@@ -490,15 +530,16 @@ k_aev_bwd(const float4 *__restrict__ pos, const int *__restrict__ sys_of,
     j0 = d.atom_off;
     row = nbr + nbr_row(d, i, cap);
   }
-  fill_lists<true>(lane, n, row, j0, n_sys, pos, pi, L, c, w, ls);
+  fill_lists<true>(lane, n, row, j0, n_sys, pos, pi, L, c, w);
   __syncthreads();
   if (!live) return;
+  const Lists &ls = *w.ls;
   const float *g = dG + (size_t)row_of_atom[i] * ldg;
 
   // radial: dE/dR = scale * sum_m g_m d/dR[exp(-eta (R - Rs_m)^2) fc(R)]
   {
     const int m = lane & 15, slot = lane >> 4;
-    const float shf = c.shf_r[m];
+    const float shf = pick(c.shf_r, m);
     for (int s = 0; s < c.S; ++s) {
       const float gm = g[s * kNShfRad + m] * c.scale;
       const int o = ls.oR[s];
