@@ -136,6 +136,49 @@ def mlp_flops(spec, species):
     return fwd, bwd
 
 
+# Kernel sources whose hash a counter summary records: the HBM byte counts
+# it holds describe the kernel as it was built from exactly these files.
+KERNEL_SOURCES = {
+    "k_aev_fwd": ["paper_2207_14276_amd/csrc/aev.hip", "paper_2207_14276_amd/csrc/internal.h"],
+    "k_aev_bwd": ["paper_2207_14276_amd/csrc/aev.hip", "paper_2207_14276_amd/csrc/internal.h"],
+    "k_gemm": ["paper_2207_14276_amd/csrc/mlp.hip", "paper_2207_14276_amd/csrc/internal.h"],
+}
+
+
+def kernel_source_hash(kernel):
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES[kernel]:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def read_summary(path):
+    """`key: value` lines of a counter summary (other lines ignored)."""
+    out = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith((" ", "#", "|")):
+                k, v = line.split(":", 1)
+                out[k.strip()] = v.strip()
+    return out
+
+
+def measured_traffic(kernel, workload, precision):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE per dispatch, each scaled by what the
+    counter reads for a plain 1 GiB copy); None when there is no summary or
+    the kernel's source has changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_{precision}_hbm.txt")
+    if not os.path.exists(path):
+        return None
+    d = read_summary(path)
+    if d.get("source_sha256") != kernel_source_hash(kernel):
+        return None
+    return int(float(d["traffic_bytes_per_launch"]))
+
+
 def copy_probe(args):
     """A plain device-to-device copy of 1 GiB: the known-size reference for
     the HBM byte counters (FETCH_SIZE, WRITE_SIZE) of rocprofv3."""
@@ -153,14 +196,15 @@ def copy_probe(args):
 def serve_bench(args):
     """Serving: a Poisson stream of requests (log-uniform 20-5000 atoms, half
     periodic water boxes, half dense solutes), each a random walk of
-    `req_steps` steps, through the continuous-batching server (bfloat16 dense
-    layers, persistent neighbour lists with a 1 A skin); beside it a seeded
-    sample of the same requests through the plain path (float32, one request
-    and one step per call, fresh lists)."""
+    `req_steps` steps, through the library's continuous-batching server
+    (bfloat16 dense layers, persistent neighbour lists with a 1 A skin,
+    memory-bound admission); beside it a seeded sample of the same requests
+    through the plain path (float32, one request and one step per call,
+    fresh lists)."""
     import torch
     import synth
     from paper_2207_14276_amd import NNPModel
-    from paper_2207_14276_amd.serve import GpuExecutor, Job, Scheduler, SystemPayload, serve
+    from paper_2207_14276_amd.serve import Request, Server, replay
 
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
@@ -171,30 +215,25 @@ def serve_bench(args):
     cap = 640   # dense 5000-atom solutes: ~550 neighbours within rc + skin
     model = NNPModel(spec, "bf16")
     slots = int(sizes.sum()) + 1024
-    max_batch = int(min(slots, 400000))
-    model.reserve(max_batch, len(trace), cap)
 
-    def jobs():
-        out = []
-        for rid, r in enumerate(trace):
-            p = SystemPayload(r.system.coords, r.system.species, r.system.box, seed=r.seed, sigma=0.01)
-            out.append((r.arrival, Job(rid, r.system.n, args.req_steps, 0.0, payload=p)))
-        return out
+    def reqs():
+        return [(r.arrival, Request(r.system.coords, r.system.species, r.system.box,
+                                    args.req_steps, 0.01, seed=r.seed)) for r in trace]
 
-    # warm-up pass on a few requests (kernel loading, workspace growth)
-    ex = GpuExecutor(model, slots=slots, capacity=cap, skin=1.0)
-    warm = Scheduler(slots=slots, max_batch_atoms=max_batch)
-    serve(ex, warm, [(0.0, j) for _, j in jobs()[:8]], sync=torch.cuda.synchronize, max_iterations=5)
+    # warm-up on a few requests (kernel loading, first-touch of the workspace)
+    srv = Server(model, slots=slots, capacity=cap, skin=1.0)
+    replay(srv, [(0.0, q) for _, q in reqs()[:8]])
+    srv.close()
     torch.cuda.synchronize()
 
-    ex = GpuExecutor(model, slots=slots, capacity=cap, skin=1.0)
-    sched = Scheduler(slots=slots, max_batch_atoms=max_batch)
+    srv = Server(model, slots=slots, capacity=cap, skin=1.0)
     say(args, "serving")
-    wall = serve(ex, sched, jobs(), sync=torch.cuda.synchronize)
-    model.status()
-    lat = sched.latencies(skip=len(trace) // 10) * 1e3
-    value = sched.atom_evals / wall
-    builds = ex.builds()
+    rep = replay(srv, reqs())
+    st = srv.stats()
+    srv.close()
+    skip = len(trace) // 10
+    lat = rep.latencies(skip=skip) * 1e3
+    value = st.atom_evals / rep.wall
 
     # plain: float32, one request at a time, one step per call, fresh lists
     plain = NNPModel(spec, "fp32")
@@ -229,9 +268,9 @@ def serve_bench(args):
         "value": round(value, 1),
         "unit": "atom-evals/s",
         "n_gpus": 1,
-        "steps": int(sched.iterations),
-        "warmup": 5,
-        "ms_per_step": round(wall / max(sched.iterations, 1) * 1e3, 4),
+        "steps": int(st.iterations),
+        "warmup": 8,
+        "ms_per_step": round(rep.wall / max(st.iterations, 1) * 1e3, 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -242,13 +281,16 @@ def serve_bench(args):
                                f"{args.req_steps} random-walk steps each",
                    "mean_atoms": round(float(sizes.mean()), 1),
                    "offered_atom_evals_per_s": round(offered, 1),
-                   "form": "continuous batching, persistent lists (1 A skin)",
+                   "form": "native continuous batching, persistent lists (1 A skin), "
+                           "two iterations in flight",
                    "parallelism": "single GPU"},
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3),
                        "p99": round(float(np.percentile(lat, 99)), 3),
-                       "requests": int(len(lat)), "excluded_warmup_requests": len(trace) // 10},
-        "wall_s": round(wall, 3),
-        "neighbour_list_builds": builds,
+                       "requests": int(len(lat)), "excluded_warmup_requests": skip},
+        "wall_s": round(rep.wall, 3),
+        "server": {"iterations": st.iterations, "atom_evals": st.atom_evals,
+                   "max_batch_seen": st.max_batch_seen, "batch_budget": st.max_batch_atoms,
+                   "device_bytes": st.device_bytes, "neighbour_list_builds": st.list_builds},
         "plain_fp32_sequential": {"value": round(plain_rate, 1), "unit": "atom-evals/s",
                                   "sample": f"{len(pick)} requests x {args.req_steps} steps",
                                   "service_ms_p50": round(float(np.percentile(p_lat, 50)), 3),
@@ -294,9 +336,13 @@ def main():
         model.energy_forces(c, sp, batch.boxes, batch.offsets, out=res)
     torch.cuda.synchronize()
 
+    # The library records HIP events at its stage boundaries on the stream it
+    # launches on (torch's current stream) during the timed steps; the stage
+    # times below are means over exactly these steps.
     st = torch.cuda.current_stream()
     starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
     ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    model.set_timing(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
@@ -305,22 +351,13 @@ def main():
         ends[k].record(st)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    stages = model.stage_timings()
+    model.set_timing(False)
     model.status()
     wall = t1 - t0
     lat = np.array([starts[k].elapsed_time(ends[k]) for k in range(args.steps)])
     value = N * args.steps / wall
     say(args, f"headline {args.precision}: {wall / args.steps * 1e3:.3f} ms/step, {value:.3e} atom-evals/s")
-
-    # per-stage device times (HIP events around each stage, same stream)
-    model.set_timing(True)
-    stage_acc = {}
-    n_t = max(3, min(args.steps, 10))
-    for _ in range(n_t):
-        model.energy_forces(c, sp, batch.boxes, batch.offsets, out=res)
-        for k, v in model.stage_timings().items():
-            stage_acc[k] = stage_acc.get(k, 0.0) + v
-    model.set_timing(False)
-    stages = {k: v / n_t for k, v in stage_acc.items()}
     say(args, "stages ms:", {k: round(v, 4) for k, v in stages.items()})
 
     # algorithmic work
@@ -339,9 +376,11 @@ def main():
     bound, work, peak = cand[dom]
     t_dom = stages[dom] * 1e-3
     achieved = work / t_dom / 1e12
-    roof = {"kernel": {"aev_fwd": "k_aev_fwd", "aev_bwd": "k_aev_bwd", "mlp": "k_gemm (all dense layers)"}[dom],
+    kname = {"aev_fwd": "k_aev_fwd", "aev_bwd": "k_aev_bwd", "mlp": "k_gemm"}[dom]
+    roof = {"kernel": kname if dom != "mlp" else "k_gemm (all dense layers)",
             "bound": bound, "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
-            "frac": round(achieved / peak, 4), "traffic": None,
+            "frac": round(achieved / peak, 4),
+            "traffic": measured_traffic(kname, args.workload, args.precision),
             "work_per_launch_flop": work, "avg_launch_ms": round(stages[dom], 4),
             "pairs": n_pairs, "triplets": n_trip}
 

@@ -180,6 +180,122 @@ int nnp_debug_neighbors(nnp_model *model, int n_systems, const int64_t *batch_of
                         const float *coords, const int32_t *species, const float *box,
                         int32_t *counts, int32_t *entries, int capacity, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Serving: continuous batching of energy/force requests (a request is one
+ * system and a number of successive evaluations, as an MD client or a
+ * free-energy window produces them).
+ *
+ * Every admitted request keeps its coordinates, species and persistent
+ * neighbour list (cutoff rc_rad + skin, rebuilt when an atom has moved more
+ * than skin / 2) on the device.  Each nnp_server_step admits queued requests
+ * first-come first-served (a contiguous range of `slots` of the request's
+ * size must be free, the atoms of one iteration stay within the batch budget
+ * and the requests in flight within max_active) and enqueues one iteration:
+ * the next step of every request in flight in one batched evaluation,
+ * followed by the built-in client's move of each continuing request, a random
+ * walk x += sigma * z per coordinate with z ~ N(0, 1) drawn from Philox4x32-10
+ * (Salmon et al., SC 2011; counter = (atom index in the request, step + 1,
+ * 0, 0), key = seed) and the Box-Muller transform, so a request's trajectory
+ * and results do not depend on what it is batched with.  Two iterations are
+ * kept in flight; results are filed when an iteration's work has completed.
+ *
+ * Memory: the server allocates its coordinate store and list pool for
+ * `slots` atoms, batch buffers, and grows the model's workspace once, for the
+ * largest per-iteration atom count that fits `hbm_budget` bytes (0 = 90% of
+ * the device memory free at creation) and max_batch_atoms (0 = no limit
+ * beyond the budget and the slots).  Requests that do not fit wait in the
+ * queue; a request larger than the pool or the batch budget is refused.
+ * The server uses the model exclusively while it lives (same host thread).
+ * ---------------------------------------------------------------------- */
+typedef struct nnp_server nnp_server;
+
+typedef struct {
+  int64_t slots;            /* atom slots (coordinate store and list pool) */
+  int nbr_capacity;         /* neighbour entries per atom in the pool, <= 1024 */
+  float skin;               /* list skin, Angstrom */
+  int64_t max_batch_atoms;  /* atoms per iteration at most, 0 = memory-bound */
+  int max_active;           /* requests in flight at most, >= 1 */
+  uint64_t hbm_budget;      /* device bytes granted to the server, 0 = 90% of free */
+} nnp_server_opts;
+
+typedef struct {
+  int n_atoms;
+  const float *coords;     /* HOST float32[n_atoms][3], copied by the call */
+  const int32_t *species;  /* HOST int32[n_atoms], copied by the call */
+  float box[3];            /* orthorhombic box lengths or 0,0,0 */
+  int n_steps;             /* evaluations requested, >= 1 */
+  float sigma;             /* random-walk step per coordinate, Angstrom */
+  uint64_t seed;           /* random-walk key */
+} nnp_request;
+
+typedef struct {
+  int64_t iterations;       /* iterations launched */
+  int64_t atom_evals;       /* sum over iterations of the atoms evaluated */
+  int64_t queued, active;   /* requests waiting / in flight */
+  int64_t max_batch_atoms;  /* the per-iteration atom budget in force */
+  int64_t max_batch_seen;   /* largest iteration so far */
+  uint64_t device_bytes;    /* device memory granted at creation (estimate) */
+  int64_t list_builds;      /* neighbour lists built (waits for the device) */
+} nnp_server_counters;
+
+/* NNP_ENOMEM when the slots or a batch of one atom do not fit the budget;
+ * waits for the device and fails with the flag's code if the model has a
+ * device flag raised (see nnp_status). */
+int nnp_server_create(nnp_model *model, const nnp_server_opts *opts, nnp_server **out);
+/* Waits for the work in flight, then frees everything. */
+void nnp_server_destroy(nnp_server *server);
+/* Seconds on the server's monotonic clock (0 at creation). */
+double nnp_server_clock(const nnp_server *server);
+/* Queues a request; t_arrival on the server clock (< 0: now).  *id receives
+ * its handle (ids count up from 0).  NNP_EINVAL if it can never run. */
+int nnp_server_submit(nnp_server *server, const nnp_request *req, double t_arrival, int64_t *id);
+/* Admits, launches one iteration on `stream` if any request is in flight,
+ * and files the results of completed iterations (waiting while two are in
+ * flight).  *pending (nullable) = requests queued or in flight plus
+ * iterations not yet filed; 0 means everything submitted is finished.
+ * A device flag (neighbour capacity, bad species) makes this and every later
+ * step fail with NNP_ECAPACITY / NNP_ESPECIES. */
+int nnp_server_step(nnp_server *server, void *stream, int64_t *pending);
+/* Waits for every launched iteration and files its results. */
+int nnp_server_drain(nnp_server *server);
+/* Ids of up to max finished requests not yet reported; *n = how many. */
+int nnp_server_poll(nnp_server *server, int64_t *ids, int max, int *n);
+/* Results of a finished request, each output nullable: energies HOST
+ * float64[n_steps] (kcal/mol, one per step), coords and forces HOST
+ * float32[n_atoms][3] of the last step (coordinates evaluated, kcal/mol/A),
+ * times HOST float64[3] = arrival, admission, completion (server clock; the
+ * completion time is when the host saw the last step's results).  Releases
+ * the request's record: a second call fails with NNP_EINVAL. */
+int nnp_server_result(nnp_server *server, int64_t id, double *energies, float *coords, float *forces,
+                      double *times);
+int nnp_server_stats(nnp_server *server, nnp_server_counters *out);
+
+/* The server's admission logic on its own, host only (no device use): for
+ * callers that drive their own evaluation, and for tests.
+ *   submit   NNP_EINVAL if the request can never run or the id is in use.
+ *   admit    admits from the head of the queue; ids/slots (nullable) get the
+ *            admitted requests and their first slots, at most max.
+ *   launch   one step of every request in flight, in admission order: ids,
+ *            slots, n_atoms, steps (0-based step index), each nullable, at
+ *            most max.  A request whose last step is launched leaves the
+ *            flight and frees its slots.
+ *   complete results of one launched step of id are back at time `now`;
+ *            *finished = 1 when it was the last.
+ *   job      times[3] = arrival, admission, completion (-1 = not yet), first
+ *            slot and steps completed of a known request.
+ *   info     info[6] = queued, in flight, atoms in flight, free slots,
+ *            iterations, atom-evals. */
+typedef struct nnp_sched nnp_sched;
+int nnp_sched_create(int64_t slots, int64_t max_batch_atoms, int max_active, nnp_sched **out);
+void nnp_sched_destroy(nnp_sched *sched);
+int nnp_sched_submit(nnp_sched *sched, int64_t id, int n_atoms, int n_steps, double t_arrival);
+int nnp_sched_admit(nnp_sched *sched, double now, int64_t *ids, int64_t *slots, int max, int *n);
+int nnp_sched_launch(nnp_sched *sched, int64_t *ids, int64_t *slots, int32_t *n_atoms, int32_t *steps,
+                     int max, int *n);
+int nnp_sched_complete(nnp_sched *sched, int64_t id, double now, int *finished);
+int nnp_sched_job(nnp_sched *sched, int64_t id, double *times, int64_t *slot, int32_t *steps_done);
+int nnp_sched_info(nnp_sched *sched, int64_t *info);
+
 /* Waits for `stream` and returns the device flags raised since the last
  * nnp_status call (NNP_ECAPACITY, NNP_ESPECIES) or NNP_OK; clears them.
  * *max_neighbors (nullable) receives the largest neighbour count seen. */
@@ -191,9 +307,15 @@ int nnp_aev_dim(const nnp_model *model);
 /* Message of the last failed call on this thread ("" if none). */
 const char *nnp_last_error(void);
 
-/* Enables per-stage timing (HIP events; adds a wait in nnp_stage_timings).
- * nnp_stage_timings writes up to n stage durations of the last call in ms
- * and their names, returns the number of stages. */
+/* Per-stage timing with HIP events recorded on the call's stream.
+ * nnp_set_timing(model, 1) turns it on and clears what was recorded; every
+ * later nnp_energy_forces / nnp_energy_forces_nlist call records one set of
+ * stage-boundary events (up to 4096 calls between two reads; calls beyond
+ * that are not timed).  nnp_stage_timings waits for the last recorded call,
+ * writes up to n stage durations in ms, each the mean over the calls recorded
+ * since the previous read, with the stage names (static strings), clears the
+ * record and returns the number of stages (0 when nothing was recorded).
+ * The recording adds no wait to the calls themselves. */
 int nnp_set_timing(nnp_model *model, int enable);
 int nnp_stage_timings(nnp_model *model, float *ms_out, const char **names_out, int n);
 

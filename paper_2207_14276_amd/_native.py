@@ -53,10 +53,34 @@ class nnp_model_desc(C.Structure):
                 ("precision", C.c_int)]
 
 
+class nnp_server_opts(C.Structure):
+    _fields_ = [("slots", C.c_int64), ("nbr_capacity", C.c_int), ("skin", C.c_float),
+                ("max_batch_atoms", C.c_int64), ("max_active", C.c_int),
+                ("hbm_budget", C.c_uint64)]
+
+
+class nnp_request(C.Structure):
+    _fields_ = [("n_atoms", C.c_int), ("coords", C.POINTER(C.c_float)),
+                ("species", C.POINTER(C.c_int32)), ("box", C.c_float * 3),
+                ("n_steps", C.c_int), ("sigma", C.c_float), ("seed", C.c_uint64)]
+
+
+class nnp_server_counters(C.Structure):
+    _fields_ = [("iterations", C.c_int64), ("atom_evals", C.c_int64), ("queued", C.c_int64),
+                ("active", C.c_int64), ("max_batch_atoms", C.c_int64),
+                ("max_batch_seen", C.c_int64), ("device_bytes", C.c_uint64),
+                ("list_builds", C.c_int64)]
+
+
 EXPORTS = ["nnp_create", "nnp_destroy", "nnp_reserve", "nnp_energy_forces", "nnp_debug_aev",
            "nnp_debug_neighbors", "nnp_status", "nnp_aev_dim", "nnp_last_error",
            "nnp_set_timing", "nnp_stage_timings", "nnp_nlist_create", "nnp_nlist_destroy",
-           "nnp_energy_forces_nlist", "nnp_nlist_builds"]
+           "nnp_energy_forces_nlist", "nnp_nlist_builds",
+           "nnp_server_create", "nnp_server_destroy", "nnp_server_clock", "nnp_server_submit",
+           "nnp_server_step", "nnp_server_drain", "nnp_server_poll", "nnp_server_result",
+           "nnp_server_stats",
+           "nnp_sched_create", "nnp_sched_destroy", "nnp_sched_submit", "nnp_sched_admit",
+           "nnp_sched_launch", "nnp_sched_complete", "nnp_sched_job", "nnp_sched_info"]
 
 _lib = None
 
@@ -90,6 +114,27 @@ def load():
     lib.nnp_energy_forces_nlist.argtypes = [vp, vp, C.c_int, i64p, i64p, C.POINTER(C.c_int32), vp,
                                             vp, fp, vp, vp, vp, vp, vp]
     lib.nnp_nlist_builds.argtypes = [vp, vp, i64p]
+    dp, i32p, ip = C.POINTER(C.c_double), C.POINTER(C.c_int32), C.POINTER(C.c_int)
+    lib.nnp_server_create.argtypes = [vp, C.POINTER(nnp_server_opts), C.POINTER(C.c_void_p)]
+    lib.nnp_server_destroy.argtypes = [vp]
+    lib.nnp_server_destroy.restype = None
+    lib.nnp_server_clock.argtypes = [vp]
+    lib.nnp_server_clock.restype = C.c_double
+    lib.nnp_server_submit.argtypes = [vp, C.POINTER(nnp_request), C.c_double, i64p]
+    lib.nnp_server_step.argtypes = [vp, vp, i64p]
+    lib.nnp_server_drain.argtypes = [vp]
+    lib.nnp_server_poll.argtypes = [vp, i64p, C.c_int, ip]
+    lib.nnp_server_result.argtypes = [vp, C.c_int64, dp, fp, fp, dp]
+    lib.nnp_server_stats.argtypes = [vp, C.POINTER(nnp_server_counters)]
+    lib.nnp_sched_create.argtypes = [C.c_int64, C.c_int64, C.c_int, C.POINTER(C.c_void_p)]
+    lib.nnp_sched_destroy.argtypes = [vp]
+    lib.nnp_sched_destroy.restype = None
+    lib.nnp_sched_submit.argtypes = [vp, C.c_int64, C.c_int, C.c_int, C.c_double]
+    lib.nnp_sched_admit.argtypes = [vp, C.c_double, i64p, i64p, C.c_int, ip]
+    lib.nnp_sched_launch.argtypes = [vp, i64p, i64p, i32p, i32p, C.c_int, ip]
+    lib.nnp_sched_complete.argtypes = [vp, C.c_int64, C.c_double, ip]
+    lib.nnp_sched_job.argtypes = [vp, C.c_int64, dp, i64p, i32p]
+    lib.nnp_sched_info.argtypes = [vp, i64p]
     _lib = lib
     return lib
 

@@ -2,6 +2,7 @@
 // one energy/force evaluation.  Host code only orchestrates: every step of
 // the path runs in the library's kernels on the caller's stream.
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -10,11 +11,12 @@
 #include <vector>
 
 #include "../../include/nnp.h"
+
 #include "internal.h"
 
 using namespace nnp;
 
-namespace {
+namespace nnp {
 
 thread_local std::string g_err;
 
@@ -27,6 +29,10 @@ int fail(int code, const char *fmt, ...) {
   g_err = buf;
   return code;
 }
+
+}  // namespace nnp
+
+namespace {
 
 #define HIP_TRY(expr)                                                                   \
   do {                                                                                  \
@@ -66,6 +72,7 @@ struct DevBuf {
 };
 
 constexpr int kStages = 8;
+constexpr int kMaxTimedCalls = 4096;  // timed calls held between two reads
 const char *kStageNames[kStages] = {"ingest", "cells", "neighbours", "buckets",
                                     "aev_fwd", "mlp", "aev_bwd", "reduce"};
 
@@ -105,9 +112,10 @@ struct nnp_model {
   size_t stage_bytes = 0;
   hipEvent_t stage_done = nullptr;
   bool stage_pending = false;
-  // timing
+  // timing: one set of stage-boundary events per timed call, kept until read
   bool timing = false;
-  hipEvent_t ev[kStages + 1] = {};
+  std::vector<std::array<hipEvent_t, kStages + 1>> evsets;
+  int ev_used = 0;       // sets recorded since the last read
   int last_stages = 0;
 
   LayerW &layer(int m, int s, int l) { return layers[((size_t)m * S + s) * L + l]; }
@@ -157,8 +165,9 @@ extern "C" void nnp_destroy(nnp_model *m) {
   for (auto &b : m->Gd) b.release();
   if (m->stage) (void)hipHostFree(m->stage);
   if (m->stage_done) (void)hipEventDestroy(m->stage_done);
-  for (auto &e : m->ev)
-    if (e) (void)hipEventDestroy(e);
+  for (auto &set : m->evsets)
+    for (auto &e : set)
+      if (e) (void)hipEventDestroy(e);
   delete m;
 }
 
@@ -278,7 +287,6 @@ static int create_impl(const nnp_model_desc *d, nnp_model *m) {
     }
   }
   HIP_TRY(hipEventCreateWithFlags(&m->stage_done, hipEventDisableTiming));
-  for (auto &e : m->ev) HIP_TRY(hipEventCreate(&e));
   int rc = m->status.ensure(2 * sizeof(int));
   if (rc) return rc;
   HIP_TRY(hipMemset(m->status.p, 0, 2 * sizeof(int)));
@@ -301,11 +309,16 @@ extern "C" int nnp_create(const nnp_model_desc *d, nnp_model **out) {
 extern "C" int nnp_aev_dim(const nnp_model *m) { return m ? m->aev.D : NNP_EINVAL; }
 
 // Buffers for a call of N atoms, S systems, C cells and n_chunks chunks.
-static int ensure_ws(nnp_model *m, int64_t N, int S, int64_t C, int n_chunks) {
+// Workspace of a call with N atoms, S systems, C cells and n_chunks
+// reduction chunks: f(buffer, bytes) is applied to every buffer (grow it, or
+// add up its size).  With pooled lists the neighbour rows, counts and
+// per-atom list state live in the pool, not here.
+template <class F>
+static int for_each_ws(nnp_model *m, int64_t N, int S, int64_t C, int n_chunks, bool pooled, F &&f) {
   const int64_t rows = (N + kTileM - 1) / kTileM * kTileM + (int64_t)m->S * kTileM;
   const int nblk = (int)((N + 1023) / 1024);
   int rc;
-#define ENS(buf, bytes) if ((rc = (buf).ensure((size_t)(bytes)))) return rc
+#define ENS(buf, bytes) if ((rc = f((buf), (size_t)(bytes)))) return rc
   ENS(m->pos, N * 16);
   ENS(m->sys_of, N * 4);
   ENS(m->atom_cell, N * 4);
@@ -313,9 +326,11 @@ static int ensure_ws(nnp_model *m, int64_t N, int S, int64_t C, int n_chunks) {
   ENS(m->cell_count, C * 4 + 4);
   ENS(m->cell_start, C * 4 + 8);
   ENS(m->cell_atoms, N * 4);
-  ENS(m->nbr, N * (int64_t)m->cap * 8);
-  ENS(m->nbr_cnt, N * 4);
-  ENS(m->state, N * (int64_t)sizeof(AtomState));
+  if (!pooled) {
+    ENS(m->nbr, N * (int64_t)m->cap * 8);
+    ENS(m->nbr_cnt, N * 4);
+    ENS(m->state, N * (int64_t)sizeof(AtomState));
+  }
   ENS(m->block_counts, (int64_t)std::max(nblk, 1) * kMaxSpecies * 4);
   ENS(m->bucket_off, (kMaxSpecies + 1) * 4);
   ENS(m->bucket_cnt, kMaxSpecies * 4);
@@ -339,6 +354,18 @@ static int ensure_ws(nnp_model *m, int64_t N, int S, int64_t C, int n_chunks) {
   return NNP_OK;
 }
 
+static int ensure_ws(nnp_model *m, int64_t N, int S, int64_t C, int n_chunks, bool pooled = false) {
+  return for_each_ws(m, N, S, C, n_chunks, pooled, [](DevBuf &b, size_t n) { return b.ensure(n); });
+}
+
+// Cells and reduction chunks reserved for up to max_atoms atoms in
+// max_systems systems (non-periodic grids hold at most one cell per atom;
+// periodic grids are sized per call).
+static int64_t reserve_cells(int64_t max_atoms, int max_systems) { return max_atoms + max_systems; }
+static int reserve_chunks(int64_t max_atoms, int max_systems) {
+  return (int)(max_atoms / 4096) + max_systems + 1;
+}
+
 extern "C" int nnp_reserve(nnp_model *m, int64_t max_atoms, int max_systems, int nbr_capacity) {
   if (!m || max_atoms < 0 || max_systems < 0 || nbr_capacity < 0)
     return fail(NNP_EINVAL, "bad reserve arguments");
@@ -351,27 +378,76 @@ extern "C" int nnp_reserve(nnp_model *m, int64_t max_atoms, int max_systems, int
       m->nbr.release();
     }
   }
-  // cells: at most one per atom for non-periodic systems; periodic grids are
-  // sized per call
-  int n_chunks = (int)(max_atoms / 4096) + max_systems + 1;
-  return ensure_ws(m, max_atoms, std::max(max_systems, 1), max_atoms + max_systems, n_chunks);
+  max_systems = std::max(max_systems, 1);
+  return ensure_ws(m, max_atoms, max_systems, reserve_cells(max_atoms, max_systems),
+                   reserve_chunks(max_atoms, max_systems));
 }
+
+// Hooks for the serving layer (same library).
+namespace nnp {
+
+size_t model_workspace_bytes(nnp_model *m, int64_t max_atoms, int max_systems, bool pooled) {
+  size_t total = 0;
+  max_systems = std::max(max_systems, 1);
+  for_each_ws(m, max_atoms, max_systems, reserve_cells(max_atoms, max_systems),
+              reserve_chunks(max_atoms, max_systems), pooled, [&](DevBuf &b, size_t n) {
+                if (n > b.bytes) total += n + n / 4 + 256;  // what DevBuf::ensure would allocate
+                return 0;
+              });
+  return total;
+}
+
+int model_reserve_pooled(nnp_model *m, int64_t max_atoms, int max_systems) {
+  HIP_TRY(hipSetDevice(m->device));
+  max_systems = std::max(max_systems, 1);
+  return ensure_ws(m, max_atoms, max_systems, reserve_cells(max_atoms, max_systems),
+                   reserve_chunks(max_atoms, max_systems), true);
+}
+
+const int *model_status_word(const nnp_model *m) { return m->status.as<int>(); }
+int model_device(const nnp_model *m) { return m->device; }
+int model_precision(const nnp_model *m) { return m->precision; }
+
+}  // namespace nnp
 
 extern "C" int nnp_set_timing(nnp_model *m, int enable) {
   if (!m) return fail(NNP_EINVAL, "null model");
   m->timing = enable != 0;
+  m->ev_used = 0;
+  m->last_stages = 0;
+  return NNP_OK;
+}
+
+// Event set for the next timed call (created on first use, then reused).
+static int next_evset(nnp_model *m, hipEvent_t **out) {
+  *out = nullptr;
+  if (m->ev_used >= kMaxTimedCalls) return NNP_OK;  // beyond the limit: untimed
+  if (m->ev_used == (int)m->evsets.size()) {
+    std::array<hipEvent_t, kStages + 1> set{};
+    for (auto &e : set) HIP_TRY(hipEventCreate(&e));
+    m->evsets.push_back(set);
+  }
+  *out = m->evsets[m->ev_used++].data();
   return NNP_OK;
 }
 
 extern "C" int nnp_stage_timings(nnp_model *m, float *ms, const char **names, int n) {
   if (!m) return fail(NNP_EINVAL, "null model");
-  if (!m->timing || m->last_stages == 0) return 0;
-  HIP_TRY(hipEventSynchronize(m->ev[m->last_stages]));
-  int k = std::min(n, m->last_stages);
+  if (!m->timing || m->last_stages == 0 || m->ev_used == 0) return 0;
+  const int k = std::min(n, m->last_stages);
+  const int used = m->ev_used;
+  HIP_TRY(hipEventSynchronize(m->evsets[used - 1][m->last_stages]));
   for (int q = 0; q < k; ++q) {
-    if (ms) HIP_TRY(hipEventElapsedTime(&ms[q], m->ev[q], m->ev[q + 1]));
+    double acc = 0.0;
+    for (int c = 0; c < used; ++c) {
+      float t = 0.f;
+      HIP_TRY(hipEventElapsedTime(&t, m->evsets[c][q], m->evsets[c][q + 1]));
+      acc += t;
+    }
+    if (ms) ms[q] = (float)(acc / used);
     if (names) names[q] = kStageNames[q];
   }
+  m->ev_used = 0;
   return k;
 }
 
@@ -499,7 +575,7 @@ static int run(nnp_model *m, int n_sys, const int64_t *offs, const float *coords
   sys_ch[n_sys] = (int)ch_sys.size();
   const int n_chunks = (int)ch_sys.size();
   if (C > ((int64_t)1 << 28)) return fail(NNP_EUNSUPPORTED, "too many cells");
-  int rc = ensure_ws(m, N, n_sys, C, n_chunks);
+  int rc = ensure_ws(m, N, n_sys, C, n_chunks, nl != nullptr);
   if (rc) return rc;
 
   // stage the per-call descriptors through pinned memory
@@ -534,8 +610,13 @@ static int run(nnp_model *m, int n_sys, const int64_t *offs, const float *coords
   m->stage_pending = true;
 
   int stage = 0;
+  hipEvent_t *ev = nullptr;
+  if (m->timing && mode == kFull) {
+    rc = next_evset(m, &ev);
+    if (rc) return rc;
+  }
   auto mark = [&]() {
-    if (m->timing && mode == kFull) (void)hipEventRecord(m->ev[stage++], st);
+    if (ev) (void)hipEventRecord(ev[stage++], st);
   };
   mark();
   SysDesc *dsys = m->sysdesc.as<SysDesc>();
@@ -700,7 +781,7 @@ static int run(nnp_model *m, int n_sys, const int64_t *offs, const float *coords
   if (o.atom_energy && N > 0)
     HIP_TRY(hipMemcpyAsync(o.atom_energy, m->e_atom.p, (size_t)N * 4, hipMemcpyDeviceToDevice, st));
   mark();
-  if (m->timing) m->last_stages = stage - 1;
+  if (ev) m->last_stages = stage - 1;
   HIP_TRY(hipGetLastError());
   return NNP_OK;
 }

@@ -5,7 +5,19 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+struct nnp_model;
+
 namespace nnp {
+
+// Sets the calling thread's error message (nnp_last_error) and returns code.
+int fail(int code, const char *fmt, ...);
+
+// Model internals used by the serving layer.
+size_t model_workspace_bytes(nnp_model *m, int64_t max_atoms, int max_systems, bool pooled);
+int model_reserve_pooled(nnp_model *m, int64_t max_atoms, int max_systems);
+const int *model_status_word(const nnp_model *m);
+int model_device(const nnp_model *m);
+int model_precision(const nnp_model *m);
 
 constexpr int kWave = 64;
 constexpr int kMaxSpecies = 7;

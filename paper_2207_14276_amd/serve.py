@@ -1,247 +1,255 @@
-"""Continuous batching of energy+force requests on one GPU.
+"""Continuous batching of energy+force requests: bindings of the library's
+native server (`nnp_server_*`) and of its host-only scheduler
+(`nnp_sched_*`), plus a driver that replays a timed request trace.
 
-A request is one system plus a number of successive steps (an MD client that
-moves the atoms a little between steps and needs energy and forces each
-time).  The server keeps every in-flight request's coordinates, species and
-neighbour list on the device; each iteration it evaluates the next step of
-every in-flight request in one batched library call, then advances each
-request (its client moves the atoms on the device).  Requests that arrive
-meanwhile wait in a queue and are admitted as soon as neighbour-list slots
-and the atom budget of one batch allow, so new work joins the running batch
-at the next iteration.
-
-Scheduling (queue, admission, slots, latency bookkeeping) is host logic in
-`Scheduler`, independent of the GPU so it can be tested on its own;
-`GpuExecutor` owns the device state and issues the library calls.
+A request is one system plus a number of successive evaluations (an MD-like
+client whose atoms take a small random step between evaluations).  The
+server keeps every admitted request's coordinates and neighbour list on the
+device, evaluates the next step of all requests in flight in one batched
+call per iteration, and admits waiting requests as slots and the memory
+budget allow; see include/nnp.h for the exact semantics.
 """
 from __future__ import annotations
 
+import ctypes as C
 import time
-from collections import deque
 from dataclasses import dataclass, field
 
 import numpy as np
 
-
-@dataclass
-class Job:
-    """One request: a system and the number of steps its client asks for."""
-    rid: int
-    n_atoms: int
-    n_steps: int
-    arrival: float
-    payload: object = None       # executor-specific (coordinates, species, box, seed)
-    slot: int = -1               # first neighbour-list slot
-    admitted: float = -1.0
-    steps_done: int = 0
-    done_time: float = -1.0
-    fresh: bool = True           # next evaluation must build its neighbour list
-
-
-class SlotAllocator:
-    """First-fit allocator of contiguous slot ranges in [0, total)."""
-
-    def __init__(self, total: int):
-        self.total = int(total)
-        self.free = [(0, self.total)]  # sorted (start, length)
-
-    def alloc(self, n: int):
-        for k, (s, ln) in enumerate(self.free):
-            if ln >= n:
-                if ln == n:
-                    self.free.pop(k)
-                else:
-                    self.free[k] = (s + n, ln - n)
-                return s
-        return None
-
-    def release(self, start: int, n: int):
-        self.free.append((start, n))
-        self.free.sort()
-        merged = []
-        for s, ln in self.free:
-            if merged and merged[-1][0] + merged[-1][1] == s:
-                merged[-1] = (merged[-1][0], merged[-1][1] + ln)
-            else:
-                merged.append((s, ln))
-        self.free = merged
-
-    @property
-    def free_slots(self) -> int:
-        return sum(ln for _, ln in self.free)
+from . import _native as nat
 
 
 class Scheduler:
-    """Queue, admission and step accounting.
+    """The server's admission and step bookkeeping on its own (host only)."""
 
-    Admission is first-come first-served: the head of the queue is admitted
-    when a contiguous slot range of its size is free and the batch stays within
-    `max_batch_atoms`; otherwise it (and everything behind it) waits.  A job
-    larger than either limit can never run and is rejected at submission.
-    """
+    def __init__(self, slots: int, max_batch_atoms: int, max_active: int = 1 << 30):
+        lib = nat.load()
+        h = C.c_void_p()
+        nat.check(lib.nnp_sched_create(int(slots), int(max_batch_atoms), int(max_active), C.byref(h)))
+        self._h = h
+        self._lib = lib
 
-    def __init__(self, slots: int, max_batch_atoms: int, clock=time.perf_counter):
-        self.alloc = SlotAllocator(slots)
-        self.max_batch_atoms = int(max_batch_atoms)
-        self.clock = clock
-        self.queue: deque[Job] = deque()
-        self.active: list[Job] = []
-        self.finished: list[Job] = []
-        self.atom_evals = 0
-        self.iterations = 0
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.nnp_sched_destroy(self._h)
+            self._h = None
 
-    def submit(self, job: Job):
-        if job.n_atoms > self.alloc.total or job.n_atoms > self.max_batch_atoms:
-            raise ValueError(f"request of {job.n_atoms} atoms exceeds the server's capacity")
-        self.queue.append(job)
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
-    @property
-    def active_atoms(self) -> int:
-        return sum(j.n_atoms for j in self.active)
+    def submit(self, rid: int, n_atoms: int, n_steps: int, t_arrival: float = 0.0):
+        nat.check(self._lib.nnp_sched_submit(self._h, int(rid), int(n_atoms), int(n_steps),
+                                             float(t_arrival)))
 
-    def admit(self) -> list[Job]:
-        out = []
-        while self.queue:
-            j = self.queue[0]
-            if self.active_atoms + j.n_atoms > self.max_batch_atoms:
-                break
-            s = self.alloc.alloc(j.n_atoms)
-            if s is None:
-                break
-            self.queue.popleft()
-            j.slot = s
-            j.admitted = self.clock()
-            j.fresh = True
-            self.active.append(j)
-            out.append(j)
-        return out
+    def admit(self, now: float, max_n: int = 4096):
+        ids = (C.c_int64 * max_n)()
+        slots = (C.c_int64 * max_n)()
+        n = C.c_int()
+        nat.check(self._lib.nnp_sched_admit(self._h, float(now), ids, slots, max_n, C.byref(n)))
+        return [(ids[k], slots[k]) for k in range(n.value)]
 
-    def batch(self) -> list[Job]:
-        """Jobs evaluated in the next iteration: every in-flight job."""
-        return list(self.active)
+    def launch(self):
+        """One step of every request in flight: [(id, slot, n_atoms, step)]."""
+        m = max(1, self.info()["active"])
+        ids, slots = (C.c_int64 * m)(), (C.c_int64 * m)()
+        na, st = (C.c_int32 * m)(), (C.c_int32 * m)()
+        n = C.c_int()
+        nat.check(self._lib.nnp_sched_launch(self._h, ids, slots, na, st, m, C.byref(n)))
+        return [(ids[k], slots[k], na[k], st[k]) for k in range(n.value)]
 
-    def complete(self, batch: list[Job], t_done: float) -> list[Job]:
-        """Marks one step of every job in `batch` done; returns jobs that finished."""
-        self.iterations += 1
-        fin = []
-        for j in batch:
-            self.atom_evals += j.n_atoms
-            j.steps_done += 1
-            j.fresh = False
-            if j.steps_done >= j.n_steps:
-                j.done_time = t_done
-                fin.append(j)
-        for j in fin:
-            self.active.remove(j)
-            self.alloc.release(j.slot, j.n_atoms)
-            self.finished.append(j)
-        return fin
+    def complete(self, rid: int, now: float) -> bool:
+        fin = C.c_int()
+        nat.check(self._lib.nnp_sched_complete(self._h, int(rid), float(now), C.byref(fin)))
+        return bool(fin.value)
 
-    def latencies(self, skip: int = 0) -> np.ndarray:
-        done = sorted(self.finished, key=lambda j: j.arrival)[skip:]
-        return np.array([j.done_time - j.arrival for j in done])
+    def job(self, rid: int) -> dict:
+        t = (C.c_double * 3)()
+        slot = C.c_int64()
+        done = C.c_int32()
+        nat.check(self._lib.nnp_sched_job(self._h, int(rid), t, C.byref(slot), C.byref(done)))
+        return {"arrival": t[0], "admitted": t[1], "done": t[2], "slot": slot.value,
+                "steps_done": done.value}
+
+    def info(self) -> dict:
+        v = (C.c_int64 * 6)()
+        nat.check(self._lib.nnp_sched_info(self._h, v))
+        return dict(zip(["queued", "active", "active_atoms", "free_slots", "iterations",
+                         "atom_evals"], list(v)))
 
 
 @dataclass
-class SystemPayload:
-    coords: np.ndarray
-    species: np.ndarray
-    box: np.ndarray
-    seed: int
-    sigma: float = 0.01
-    record: bool = False           # keep every step's inputs and outputs (tests)
-    trace: list = field(default_factory=list)
+class Request:
+    coords: np.ndarray        # [n, 3] float32, Angstrom
+    species: np.ndarray       # [n] int32 slot indices
+    box: np.ndarray           # [3] float32 (0,0,0 = non-periodic)
+    n_steps: int
+    sigma: float = 0.01       # random-walk step per coordinate, Angstrom
+    seed: int = 0
+
+    @property
+    def n_atoms(self) -> int:
+        return int(len(self.species))
 
 
-class GpuExecutor:
-    """Device state of the in-flight jobs and the batched library calls."""
+@dataclass
+class Result:
+    rid: int
+    energies: np.ndarray      # [n_steps] float64, kcal/mol
+    coords: np.ndarray        # [n, 3] float32, last step's coordinates
+    forces: np.ndarray        # [n, 3] float32, last step's forces
+    arrival: float
+    admitted: float
+    done: float
 
-    def __init__(self, model, slots: int, capacity: int = 256, skin: float = 1.0):
+    @property
+    def latency(self) -> float:
+        return self.done - self.arrival
+
+
+@dataclass
+class ServerStats:
+    iterations: int
+    atom_evals: int
+    queued: int
+    active: int
+    max_batch_atoms: int
+    max_batch_seen: int
+    device_bytes: int
+    list_builds: int
+
+
+class Server:
+    """The library's continuous-batching server on one model (which it then
+    uses exclusively).  `hbm_budget` bytes of device memory (0 = 90% of what
+    is free) bound the per-iteration batch; see nnp_server_create."""
+
+    def __init__(self, model, slots: int, capacity: int = 256, skin: float = 1.0,
+                 max_batch_atoms: int = 0, max_active: int = 4096, hbm_budget: int = 0):
         import torch
-        from .model import NeighborPool
         self.torch = torch
         self.model = model
-        self.pool = NeighborPool(model, slots, capacity, skin)
-        self.dev = model.device
-        self.state = {}  # rid -> (coords tensor, species tensor, box, generator)
+        self._lib = nat.load()
+        opts = nat.nnp_server_opts(int(slots), int(capacity), float(skin), int(max_batch_atoms),
+                                   int(max_active), int(hbm_budget))
+        h = C.c_void_p()
+        with torch.cuda.device(model.device):
+            nat.check(self._lib.nnp_server_create(model.handle, C.byref(opts), C.byref(h)))
+        self._h = h
+        self.n_atoms = {}
+        self.n_steps = {}
 
-    def admit(self, job: Job):
-        t = self.torch
-        p: SystemPayload = job.payload
-        c = t.as_tensor(p.coords, dtype=t.float32, device=self.dev).contiguous()
-        s = t.as_tensor(p.species, dtype=t.int32, device=self.dev).contiguous()
-        g = t.Generator(device=self.dev)
-        g.manual_seed(int(p.seed))
-        self.state[job.rid] = (c, s, np.asarray(p.box, np.float32), g)
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            with self.torch.cuda.device(self.model.device):
+                self._lib.nnp_server_destroy(self._h)
+            self._h = None
 
-    def evaluate(self, batch: list[Job]):
-        """Enqueues one batched evaluation; returns the result (device tensors)."""
-        t = self.torch
-        coords = t.cat([self.state[j.rid][0] for j in batch])
-        species = t.cat([self.state[j.rid][1] for j in batch])
-        boxes = np.stack([self.state[j.rid][2] for j in batch])
-        offs = np.zeros(len(batch) + 1, np.int64)
-        offs[1:] = np.cumsum([j.n_atoms for j in batch])
-        slots = np.array([j.slot for j in batch], np.int64)
-        rebuild = np.array([1 if j.fresh else 0 for j in batch], np.int32)
-        res = self.pool.energy_forces(coords, species, boxes, offs, slots, rebuild, forces=True)
-        for k, j in enumerate(batch):
-            p: SystemPayload = j.payload
-            if p.record:
-                a, e = int(offs[k]), int(offs[k + 1])
-                p.trace.append((coords[a:e].clone(), res.energy[k:k + 1].clone(),
-                                res.forces[a:e].clone()))
-        return res
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
-    def advance(self, batch: list[Job], finished: list[Job]):
-        """The clients take their step: each continuing system moves by
-        N(0, sigma) per coordinate (a random walk, on the device)."""
-        t = self.torch
-        done = {j.rid for j in finished}
-        for j in batch:
-            c, s, b, g = self.state[j.rid]
-            if j.rid in done:
-                del self.state[j.rid]
-                continue
-            c.add_(t.randn(c.shape, generator=g, device=self.dev) * j.payload.sigma)
+    def clock(self) -> float:
+        return float(self._lib.nnp_server_clock(self._h))
 
-    def builds(self) -> int:
-        return self.pool.builds()
+    def submit(self, req: Request, t_arrival: float = -1.0) -> int:
+        x = np.ascontiguousarray(req.coords, dtype=np.float32).reshape(-1, 3)
+        s = np.ascontiguousarray(req.species, dtype=np.int32)
+        if len(x) != len(s):
+            raise ValueError("coords and species differ in length")
+        r = nat.nnp_request(len(s), x.ctypes.data_as(C.POINTER(C.c_float)),
+                            s.ctypes.data_as(C.POINTER(C.c_int32)),
+                            (C.c_float * 3)(*[float(v) for v in np.asarray(req.box).reshape(3)]),
+                            int(req.n_steps), float(req.sigma), int(req.seed) & ((1 << 64) - 1))
+        rid = C.c_int64()
+        nat.check(self._lib.nnp_server_submit(self._h, C.byref(r), float(t_arrival), C.byref(rid)))
+        self.n_atoms[rid.value] = len(s)
+        self.n_steps[rid.value] = int(req.n_steps)
+        return rid.value
 
-    def check(self):
-        """Waits for the device and raises on a device flag (neighbour
-        capacity overflow, bad species) of the calls so far."""
-        self.model.status()
+    def step(self) -> int:
+        """One iteration on torch's current stream; returns the number of
+        requests queued or in flight plus iterations not yet filed."""
+        torch = self.torch
+        pend = C.c_int64()
+        with torch.cuda.device(self.model.device):
+            st = C.c_void_p(torch.cuda.current_stream(self.model.device).cuda_stream)
+            nat.check(self._lib.nnp_server_step(self._h, st, C.byref(pend)))
+        return int(pend.value)
+
+    def drain(self):
+        nat.check(self._lib.nnp_server_drain(self._h))
+
+    def poll(self, max_n: int = 4096):
+        ids = (C.c_int64 * max_n)()
+        n = C.c_int()
+        nat.check(self._lib.nnp_server_poll(self._h, ids, max_n, C.byref(n)))
+        return [ids[k] for k in range(n.value)]
+
+    def result(self, rid: int) -> Result:
+        n, k = self.n_atoms.pop(rid), self.n_steps.pop(rid)
+        e = np.empty(k, np.float64)
+        x = np.empty((n, 3), np.float32)
+        f = np.empty((n, 3), np.float32)
+        t = np.empty(3, np.float64)
+        dp = C.POINTER(C.c_double)
+        fp = C.POINTER(C.c_float)
+        nat.check(self._lib.nnp_server_result(self._h, int(rid), e.ctypes.data_as(dp),
+                                              x.ctypes.data_as(fp), f.ctypes.data_as(fp),
+                                              t.ctypes.data_as(dp)))
+        return Result(rid, e, x, f, float(t[0]), float(t[1]), float(t[2]))
+
+    def stats(self) -> ServerStats:
+        c = nat.nnp_server_counters()
+        nat.check(self._lib.nnp_server_stats(self._h, C.byref(c)))
+        return ServerStats(*[int(getattr(c, f)) for f, _ in nat.nnp_server_counters._fields_])
 
 
-def serve(executor, sched: Scheduler, arrivals, clock=time.perf_counter, sync=None,
-          max_iterations: int | None = None):
-    """Replays `arrivals` (list of (t_arrival, Job), sorted, times relative to
-    the start) through the scheduler; returns when every job has finished."""
-    pending = deque(arrivals)
-    t0 = clock()
-    it = 0
-    while pending or sched.queue or sched.active:
-        now = clock() - t0
-        while pending and pending[0][0] <= now:
-            ta, job = pending.popleft()
-            job.arrival = t0 + ta
-            sched.submit(job)
-        for j in sched.admit():
-            executor.admit(j)
-        if not sched.active:
-            if pending:
-                time.sleep(max(0.0, pending[0][0] - (clock() - t0)))
+@dataclass
+class Replay:
+    results: dict = field(default_factory=dict)   # rid -> Result
+    order: list = field(default_factory=list)     # rids in trace order
+    wall: float = 0.0                             # first arrival -> last completion, s
+    steps: int = 0                                # nnp_server_step calls
+
+    def latencies(self, skip: int = 0) -> np.ndarray:
+        return np.array([self.results[r].latency for r in self.order[skip:]])
+
+
+def replay(server: Server, arrivals, max_steps: int | None = None) -> Replay:
+    """Feeds `arrivals` ([(t, Request)] sorted by t, seconds from the start)
+    to the server on its own clock: each request is submitted once its time
+    has come (stamped with its scheduled arrival), and the server is stepped
+    until everything submitted has finished."""
+    out = Replay()
+    pending = list(arrivals)
+    k = 0
+    t0 = server.clock()
+    busy = 0
+    while k < len(pending) or busy:
+        now = server.clock() - t0
+        while k < len(pending) and pending[k][0] <= now:
+            t, req = pending[k]
+            out.order.append(server.submit(req, t0 + t))
+            k += 1
+        if not busy and k < len(pending) and pending[k][0] > now:
+            # idle until the next arrival
+            time.sleep(max(0.0, pending[k][0] - (server.clock() - t0)))
             continue
-        batch = sched.batch()
-        executor.evaluate(batch)
-        if sync is not None:
-            sync()
-            if hasattr(executor, "check"):
-                executor.check()
-        fin = sched.complete(batch, clock())
-        executor.advance(batch, fin)
-        it += 1
-        if max_iterations is not None and it >= max_iterations:
+        busy = server.step()
+        out.steps += 1
+        for rid in server.poll():
+            out.results[rid] = server.result(rid)
+        if max_steps is not None and out.steps >= max_steps:
             break
-    return clock() - t0
+    server.drain()
+    for rid in server.poll():
+        out.results[rid] = server.result(rid)
+    if out.results:
+        out.wall = max(r.done for r in out.results.values()) - (t0 + pending[0][0])
+    return out

@@ -1,10 +1,11 @@
-"""Device-resident neighbour lists and the continuous-batching server, on the
-GPU through the C ABI.
+"""Device-resident neighbour lists and the native continuous-batching
+server, on the GPU through the C ABI.
 
 Persistent lists (built with rc + skin, reused until an atom moved more than
 skin/2) must give the results of fresh lists at every step of a random walk;
 a request served inside a changing mix must give the same per-step results
-as when served alone, and those match the oracle at the float32 tolerances.
+as when served alone, and those match the oracle at the float32 tolerances;
+memory and batch budgets make requests wait without changing any result.
 """
 import numpy as np
 import pytest
@@ -82,10 +83,10 @@ def test_pool_rejects_bad_slot_ranges(m32):
         pool.energy_forces(c, sp, b.boxes, b.offsets, [0, 300, 390], [1, 1, 1])
 
 
-def _requests(n, seed, nmin=20, nmax=400, steps=6, record=()):
-    from paper_2207_14276_amd.serve import Job, SystemPayload
+def _requests(n, seed, nmin=20, nmax=400, steps=6, sigma=0.01):
+    from paper_2207_14276_amd.serve import Request
     rng = np.random.default_rng(seed)
-    jobs = []
+    reqs = []
     for rid in range(n):
         size = int(rng.integers(nmin, nmax))
         if rid % 2 == 0:
@@ -93,60 +94,123 @@ def _requests(n, seed, nmin=20, nmax=400, steps=6, record=()):
         else:
             s = synth.random_solute(np.random.default_rng(2000 + rid), size,
                                     1.2 * size ** (1 / 3), synth.CONFIG2_PROBS)
-        p = SystemPayload(s.coords, s.species, s.box, seed=3000 + rid, sigma=0.01,
-                          record=rid in record)
-        jobs.append(Job(rid, s.n, steps, 0.0, payload=p))
-    return jobs
+        reqs.append(Request(s.coords, s.species, s.box, steps, sigma, seed=3000 + rid))
+    return reqs
 
 
-def _run(model, jobs, spacing=0.0):
-    from paper_2207_14276_amd.serve import GpuExecutor, Scheduler, serve
+def _server(model, **kw):
+    from paper_2207_14276_amd.serve import Server
     # dense solutes reach ~550 neighbours inside rc + skin
-    ex = GpuExecutor(model, slots=20000, capacity=640, skin=1.0)
-    sched = Scheduler(slots=20000, max_batch_atoms=20000)
-    arrivals = [(k * spacing, j) for k, j in enumerate(jobs)]
-    wall = serve(ex, sched, arrivals, sync=torch.cuda.synchronize)
-    return sched, ex, wall
+    opts = dict(slots=20000, capacity=640, skin=1.0)
+    opts.update(kw)
+    return Server(model, **opts)
+
+
+def _run(model, reqs, spacing=0.0, **kw):
+    from paper_2207_14276_amd.serve import replay
+    srv = _server(model, **kw)
+    rep = replay(srv, [(k * spacing, r) for k, r in enumerate(reqs)])
+    stats = srv.stats()
+    srv.close()
+    return rep, stats
 
 
 def test_served_alone_equals_served_in_mix(m32, oracle_lib, spec):
-    jobs = _requests(10, seed=5, record=(3, 6))
-    # staggered arrivals: the mix around the tracked jobs changes every few steps
-    sched, ex, wall = _run(m32, jobs, spacing=0.002)
-    assert len(sched.finished) == 10
-    mixed = {j.rid: j.payload.trace for j in jobs if j.rid in (3, 6)}
+    reqs = _requests(10, seed=5)
+    # staggered arrivals: the mix around the tracked requests changes every few steps
+    mixed, _ = _run(m32, reqs, spacing=0.002)
+    assert len(mixed.results) == 10
     for rid in (3, 6):
-        alone = _requests(10, seed=5, record=(rid,))[rid]
-        _run(m32, [alone])
-        t_mix, t_alone = mixed[rid], alone.payload.trace
-        assert len(t_mix) == len(t_alone) == alone.n_steps
-        worst_e = worst_f = 0.0
-        for (cm, em, fm), (ca, ea, fa) in zip(t_mix, t_alone):
-            assert torch.equal(cm, ca)          # the client's walk is the same
-            worst_e = max(worst_e, abs(float(em[0]) - float(ea[0])))
-            worst_f = max(worst_f, float((fm - fa).abs().max()))
-        log(f"[alone-vs-mix rid={rid}] max|dE|={worst_e:.3e} max|dF|={worst_f:.3e}")
-        assert worst_e <= 1e-9 * alone.n_atoms + 1e-12
-        assert worst_f <= 1e-5
-        # and the served result matches the oracle on the last step's coordinates
-        p = alone.payload
-        x, e, f = t_alone[-1]
+        alone, _ = _run(m32, [reqs[rid]])
+        a, m = alone.results[0], mixed.results[rid]
+        assert np.array_equal(a.coords, m.coords)        # the client's walk is the same
+        de = float(np.abs(a.energies - m.energies).max())
+        df = float(np.abs(a.forces - m.forces).max())
+        log(f"[alone-vs-mix rid={rid}] max|dE|={de:.3e} max|dF|={df:.3e}")
+        assert de <= 1e-9 * reqs[rid].n_atoms + 1e-12
+        assert df <= 1e-5
+        # the last step's results match the oracle at the coordinates evaluated
         om = oracle_lib.OracleModel(spec)
-        E, ea, F, _ = oracle_lib.energy_forces(x.cpu().numpy(), p.species, p.box, om)
-        de = abs(float(e[0]) - E) / alone.n_atoms
-        df = float(np.abs(f.cpu().numpy() - F).max())
+        E, ea, F, _ = oracle_lib.energy_forces(a.coords, reqs[rid].species, reqs[rid].box, om)
+        de = abs(float(a.energies[-1]) - E) / reqs[rid].n_atoms
+        df = float(np.abs(a.forces - F).max())
         log(f"[served vs oracle rid={rid}] |dE|/N={de:.3e} max|dF|={df:.3e}")
         assert de <= FP32_E_ATOM
         assert df <= FP32_F
 
 
 def test_server_drains_a_burst(m32):
-    jobs = _requests(24, seed=9, nmin=20, nmax=600, steps=5)
-    sched, ex, wall = _run(m32, jobs, spacing=0.0005)
-    lat = sched.latencies()
-    assert len(lat) == 24
-    log(f"[serve burst] {sched.atom_evals / wall:.3e} atom-evals/s, iterations={sched.iterations}, "
+    reqs = _requests(24, seed=9, nmin=20, nmax=600, steps=5)
+    rep, st = _run(m32, reqs, spacing=0.0005)
+    lat = rep.latencies()
+    assert len(lat) == 24 and np.all(lat > 0)
+    log(f"[serve burst] {st.atom_evals / rep.wall:.3e} atom-evals/s, iterations={st.iterations}, "
         f"p50={np.percentile(lat, 50) * 1e3:.2f} ms p99={np.percentile(lat, 99) * 1e3:.2f} ms, "
-        f"list builds={ex.builds()}")
-    # every job was admitted at once (budget large enough): one build each
-    assert ex.builds() == 24
+        f"list builds={st.list_builds}")
+    assert st.atom_evals == sum(r.n_atoms * r.n_steps for r in reqs)
+    # sigma = 0.01 A over 5 steps never moves an atom skin/2: one build per request
+    assert st.list_builds == 24
+    for r in rep.results.values():
+        assert r.admitted >= r.arrival - 1e-9 and r.done > r.admitted
+
+
+def test_batch_budget_queues_without_changing_results(m32):
+    reqs = _requests(8, seed=21, nmin=100, nmax=250, steps=4)
+    free, _ = _run(m32, reqs)
+    tight, st = _run(m32, reqs, max_batch_atoms=300)
+    log(f"[batch budget 300] iterations={st.iterations} max batch seen={st.max_batch_seen}")
+    assert st.max_batch_atoms == 300 and st.max_batch_seen <= 300
+    assert st.iterations > 4       # the requests could not all run side by side
+    for rid in range(8):
+        a, b = free.results[rid], tight.results[rid]
+        assert np.array_equal(a.coords, b.coords)
+        assert np.abs(a.energies - b.energies).max() <= 1e-9 * reqs[rid].n_atoms + 1e-12
+        assert np.abs(a.forces - b.forces).max() <= 1e-5
+
+
+def test_memory_budget_bounds_the_batch(spec):
+    from paper_2207_14276_amd import NNPError, NNPModel
+    from paper_2207_14276_amd.serve import replay
+    # a fresh model: the budget covers the memory the server adds, and a model
+    # that already holds a large workspace would need none
+    model = NNPModel(spec, "fp32")
+    budget = 64 << 20
+    srv = _server(model, slots=4000, hbm_budget=budget)
+    st = srv.stats()
+    log(f"[hbm budget 64 MiB] batch budget={st.max_batch_atoms} atoms, granted={st.device_bytes} B")
+    assert 0 < st.max_batch_atoms < 4000
+    assert st.device_bytes <= budget
+    big = _requests(1, seed=3, nmin=3000, nmax=3001)[0]
+    if big.n_atoms > st.max_batch_atoms:
+        with pytest.raises(NNPError):
+            srv.submit(big)
+    small = [r for r in _requests(12, seed=4, nmin=50, nmax=300, steps=3)
+             if r.n_atoms <= st.max_batch_atoms]
+    rep = replay(srv, [(0.0, r) for r in small])
+    assert len(rep.results) == len(small)
+    assert srv.stats().max_batch_seen <= st.max_batch_atoms
+    srv.close()
+    model.close()
+
+
+def test_random_walk_statistics(m32):
+    from paper_2207_14276_amd.serve import Request
+    s = synth.water_box(300, seed=77)
+    sigma, steps = 0.01, 9
+    rep, _ = _run(m32, [Request(s.coords, s.species, s.box, steps, sigma, seed=123)])
+    d = (rep.results[0].coords.astype(np.float64) - s.coords).ravel()
+    var = d.var() / (sigma ** 2 * (steps - 1))
+    log(f"[walk] n={d.size} mean={d.mean():.2e} var ratio={var:.3f}")
+    assert abs(d.mean()) < 5 * sigma * np.sqrt(steps - 1) / np.sqrt(d.size)
+    assert 0.9 < var < 1.1
+
+
+def test_capacity_overflow_is_reported(m32):
+    from paper_2207_14276_amd import NNPError
+    from paper_2207_14276_amd.serve import replay
+    srv = _server(m32, slots=5000, capacity=16)
+    with pytest.raises(NNPError, match="ECAPACITY"):
+        replay(srv, [(0.0, r) for r in _requests(2, seed=5, steps=2)])
+    srv.close()
+    with pytest.raises(NNPError, match="ECAPACITY"):
+        m32.status()    # reports the flag and clears it for the tests after this one

@@ -1,101 +1,154 @@
-"""Host logic of the serving loop, against a mock executor (no GPU):
-slot allocation, first-come first-served admission under slot and batch
-budgets, continuous joining of new requests, step accounting and latencies."""
+"""Host logic of the serving layer through the C ABI, without a GPU: the
+native scheduler's first-fit slot ranges, first-come first-served admission
+under the slot, batch-atom and in-flight limits, continuous joining of new
+requests, step accounting and latencies (driven with explicit times)."""
 import numpy as np
 import pytest
 
-from paper_2207_14276_amd.serve import Job, Scheduler, SlotAllocator, serve
+from paper_2207_14276_amd import NNPError
+from paper_2207_14276_amd.serve import Scheduler
 
 
-def test_slot_allocator_first_fit_and_merge():
-    a = SlotAllocator(100)
-    s1 = a.alloc(30)
-    s2 = a.alloc(30)
-    s3 = a.alloc(30)
-    assert (s1, s2, s3) == (0, 30, 60)
-    assert a.alloc(20) is None            # only 10 free
-    a.release(s2, 30)
-    assert a.alloc(35) is None            # the hole is 30 wide
-    assert a.alloc(25) == 30
-    a.release(s1, 30)
-    a.release(30, 25)
-    assert a.free == [(0, 60), (90, 10)]  # merged
-    assert a.free_slots == 70
+def run_to_completion(s, arrivals, dt=1.0):
+    """Replays [(t_arrival, rid, n_atoms, n_steps)] with one iteration per
+    `dt` of time; returns the batches (lists of ids) launched."""
+    t, k, batches = 0.0, 0, []
+    arrivals = sorted(arrivals)
+    while True:
+        while k < len(arrivals) and arrivals[k][0] <= t:
+            ta, rid, n, st = arrivals[k]
+            s.submit(rid, n, st, ta)
+            k += 1
+        s.admit(t)
+        items = s.launch()
+        if not items:
+            if k == len(arrivals) and s.info()["queued"] == 0:
+                return batches
+            t = arrivals[k][0] if k < len(arrivals) else t + dt
+            continue
+        batches.append([it[0] for it in items])
+        t += dt
+        for it in items:
+            s.complete(it[0], t)
 
 
-class FakeClock:
-    def __init__(self):
-        self.t = 0.0
-
-    def __call__(self):
-        return self.t
-
-
-class MockExecutor:
-    """Stands in for the GPU: each evaluation takes `dt` of fake time."""
-
-    def __init__(self, clock, dt=1.0):
-        self.clock, self.dt = clock, dt
-        self.batches = []
-        self.admitted = []
-
-    def admit(self, job):
-        self.admitted.append(job.rid)
-
-    def evaluate(self, batch):
-        self.batches.append([j.rid for j in batch])
-        self.clock.t += self.dt
-
-    def advance(self, batch, finished):
-        pass
+def test_first_fit_slots_and_merge():
+    s = Scheduler(slots=100, max_batch_atoms=1000)
+    for rid, (n, steps) in enumerate([(30, 3), (30, 1), (30, 3)]):
+        s.submit(rid, n, steps)
+    assert s.admit(0.0) == [(0, 0), (1, 30), (2, 60)]
+    s.launch()                      # request 1 launches its only step: slots 30..59 free
+    assert s.info()["free_slots"] == 40
+    s.submit(3, 35, 1)              # the 30-slot hole and the 10 at the end do not fit 35
+    s.submit(4, 25, 1)              # first come first served: 4 waits behind 3
+    assert s.admit(1.0) == []
+    s.launch()
+    s.launch()                      # requests 0 and 2 finish: everything merges back
+    assert s.info()["free_slots"] == 100
+    assert s.admit(2.0) == [(3, 0), (4, 35)]
 
 
-def test_fcfs_admission_respects_both_budgets():
-    clk = FakeClock()
-    s = Scheduler(slots=100, max_batch_atoms=80, clock=clk)
+def test_fcfs_admission_respects_slot_and_batch_budgets():
+    s = Scheduler(slots=100, max_batch_atoms=80)
     for rid, n in enumerate([50, 40, 20, 10]):
-        s.submit(Job(rid, n, n_steps=2, arrival=0.0))
-    got = s.admit()
+        s.submit(rid, n, 2, 0.0)
     # 50 fits; 40 would exceed the 80-atom batch budget; 20 and 10 wait behind it
-    assert [j.rid for j in got] == [0]
-    s.complete(s.batch(), 1.0)
-    assert s.admit() == []
-    s.complete(s.batch(), 2.0)           # job 0 finishes after 2 steps
-    assert [j.rid for j in s.finished] == [0]
-    assert [j.rid for j in s.admit()] == [1, 2, 3]
+    assert [r for r, _ in s.admit(0.0)] == [0]
+    s.launch()
+    assert s.admit(1.0) == []
+    s.launch()                      # request 0 launches its last step
+    assert [r for r, _ in s.admit(2.0)] == [1, 2, 3]
 
 
-def test_oversized_request_is_rejected():
+def test_in_flight_limit():
+    s = Scheduler(slots=1000, max_batch_atoms=1000, max_active=2)
+    for rid in range(4):
+        s.submit(rid, 10, 1)
+    assert [r for r, _ in s.admit(0.0)] == [0, 1]
+    s.launch()
+    assert [r for r, _ in s.admit(1.0)] == [2, 3]
+
+
+def test_requests_that_can_never_run_are_refused():
     s = Scheduler(slots=100, max_batch_atoms=50)
-    with pytest.raises(ValueError):
-        s.submit(Job(0, 60, 1, 0.0))
+    with pytest.raises(NNPError):
+        s.submit(0, 60, 1)          # above the batch budget
+    with pytest.raises(NNPError):
+        s.submit(1, 10, 0)          # no steps
+    s.submit(2, 10, 1)
+    with pytest.raises(NNPError):
+        s.submit(2, 10, 1)          # id in use
+    s2 = Scheduler(slots=40, max_batch_atoms=1000)
+    with pytest.raises(NNPError):
+        s2.submit(0, 41, 1)         # above the pool
 
 
 def test_continuous_batching_joins_new_requests_mid_flight():
-    clk = FakeClock()
-    ex = MockExecutor(clk, dt=1.0)
-    s = Scheduler(slots=1000, max_batch_atoms=1000, clock=clk)
-    arrivals = [(0.0, Job(0, 10, 5, 0.0)), (2.5, Job(1, 20, 2, 0.0)), (2.5, Job(2, 5, 1, 0.0))]
-    serve(ex, s, arrivals, clock=clk)
-    # job 0 runs alone for three iterations, then 1 and 2 join the batch
-    assert ex.batches[:3] == [[0], [0], [0]]
-    assert ex.batches[3] == [0, 1, 2]
-    assert ex.batches[4] == [0, 1]
-    assert len(s.finished) == 3
-    lat = {j.rid: j.done_time - j.arrival for j in s.finished}
+    s = Scheduler(slots=1000, max_batch_atoms=1000)
+    batches = run_to_completion(s, [(0.0, 0, 10, 5), (2.5, 1, 20, 2), (2.5, 2, 5, 1)])
+    # request 0 runs alone for three iterations, then 1 and 2 join the batch
+    assert batches == [[0], [0], [0], [0, 1, 2], [0, 1]]
+    lat = {r: s.job(r)["done"] - s.job(r)["arrival"] for r in range(3)}
     assert lat[0] == pytest.approx(5.0)
+    assert lat[1] == pytest.approx(2.5)
     assert lat[2] == pytest.approx(1.5)
-    assert s.atom_evals == 10 * 5 + 20 * 2 + 5 * 1
+    assert s.info()["atom_evals"] == 10 * 5 + 20 * 2 + 5 * 1
+    assert s.info()["iterations"] == 5
 
 
 def test_queue_waits_for_slots_then_drains():
-    clk = FakeClock()
-    ex = MockExecutor(clk, dt=1.0)
-    s = Scheduler(slots=30, max_batch_atoms=1000, clock=clk)
-    arrivals = [(0.0, Job(k, 20, 3, 0.0)) for k in range(4)]
-    serve(ex, s, arrivals, clock=clk)
-    # one 20-atom job fits the 30 slots at a time: strictly sequential, none lost
-    assert all(len(b) == 1 for b in ex.batches)
-    assert sorted(j.rid for j in s.finished) == [0, 1, 2, 3]
-    lat = s.latencies()
-    np.testing.assert_allclose(sorted(lat), [3, 6, 9, 12])
+    s = Scheduler(slots=30, max_batch_atoms=1000)
+    batches = run_to_completion(s, [(0.0, k, 20, 3) for k in range(4)])
+    # one 20-atom request fits the 30 slots at a time: strictly sequential
+    assert all(len(b) == 1 for b in batches)
+    lat = sorted(s.job(r)["done"] - s.job(r)["arrival"] for r in range(4))
+    np.testing.assert_allclose(lat, [3, 6, 9, 12])
+
+
+def test_complete_without_a_launched_step_is_an_error():
+    s = Scheduler(slots=10, max_batch_atoms=10)
+    s.submit(0, 5, 2)
+    s.admit(0.0)
+    with pytest.raises(NNPError):
+        s.complete(0, 0.0)
+    s.launch()
+    assert s.complete(0, 1.0) is False
+    s.launch()
+    assert s.complete(0, 2.0) is True
+    assert s.job(0)["steps_done"] == 2
+
+
+def test_randomized_invariants():
+    """Random arrivals and sizes: slot ranges of requests in flight never
+    overlap, the batch budget holds every iteration, every request runs
+    exactly its steps, and admission order is arrival order."""
+    rng = np.random.default_rng(0)
+    slots, budget = 500, 300
+    s = Scheduler(slots=slots, max_batch_atoms=budget, max_active=16)
+    n_req = 200
+    sizes = rng.integers(1, 120, n_req)
+    steps = rng.integers(1, 6, n_req)
+    t, k, admitted_order, live = 0.0, 0, [], {}
+    launched = {r: 0 for r in range(n_req)}
+    while k < n_req or s.info()["queued"] or s.info()["active"]:
+        for _ in range(int(rng.integers(0, 4))):
+            if k < n_req:
+                s.submit(k, int(sizes[k]), int(steps[k]), t)
+                k += 1
+        for rid, slot in s.admit(t):
+            admitted_order.append(rid)
+            live[rid] = (slot, int(sizes[rid]))
+        ranges = sorted(live.values())
+        for (a0, n0), (a1, _) in zip(ranges, ranges[1:]):
+            assert a0 + n0 <= a1
+        assert all(0 <= a and a + n <= slots for a, n in ranges)
+        items = s.launch()
+        assert sum(it[2] for it in items) <= budget
+        t += 1.0
+        for rid, slot, n, st in items:
+            assert st == launched[rid]
+            launched[rid] += 1
+            if s.complete(rid, t):
+                del live[rid]
+    assert admitted_order == list(range(n_req))
+    assert all(launched[r] == steps[r] for r in range(n_req))
