@@ -26,7 +26,7 @@
 
 #include "../../include/nnp.h"
 #include "internal.h"
-#include "sched.h"
+#include "scheduler.h"
 
 using namespace nnp;
 
