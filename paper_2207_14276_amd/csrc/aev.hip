@@ -15,13 +15,18 @@
 //                cosine power of its angle shift for a pair and accumulates
 //                the 4 radial-shift products; accumulators are reduced across
 //                the 8 pairs at the end of the block.
+//            Blocks without a pair are written as zeros directly.
 //   angular (backward): the pairs of all species-pair blocks form one
 //            stream, one pair per lane; a lane evaluates all 8 angle shifts
-//            of its pair against the block's dE/dG values (staged in LDS),
-//            differentiates through cos, sin, R_j and R_k, and accumulates
-//            dE/dd_j and dE/dd_k per neighbour entry in LDS (64-bit fixed
-//            point, integer atomics).  Forces are then scattered with float
-//            atomics.
+//            of its pair against the block's dE/dG values (read from the
+//            centre's row, which stays in the L1/L2 caches), recomputes the
+//            angular cutoff of both legs, differentiates through cos, sin,
+//            R_j and R_k, and accumulates dE/dd_j and dE/dd_k per neighbour
+//            entry in LDS (64-bit fixed point, integer atomics).  Forces are
+//            then scattered with float atomics.
+// The backward keeps its LDS per wave near 8 KB (5 waves per SIMD at a
+// neighbour capacity of 128): the kernel is latency-bound, so occupancy
+// matters more than avoiding recomputation.
 #include "internal.h"
 
 namespace nnp {
@@ -45,7 +50,13 @@ __device__ inline float fast_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 // not, and integer sums are exact and independent of the order of the adds.
 constexpr float kFix = 4294967296.0f;         // 2^32
 constexpr float kUnfix = 2.3283064365386963e-10f;  // 2^-32
-__device__ inline long long to_fix(float v) { return (long long)(v * kFix); }
+// floor(v * 2^32) as a 64-bit integer, built from its two 32-bit halves:
+// hi = floor(v), lo = (v - hi) * 2^32 in [0, 2^32) (both steps exact).
+__device__ inline long long to_fix(float v) {
+  const float hi = floorf(v);
+  const unsigned lo = (unsigned)((v - hi) * kFix);
+  return (long long)(((unsigned long long)(unsigned)(int)hi << 32) | lo);
+}
 __device__ inline float from_fix(long long v) { return (float)v * kUnfix; }
 
 // q = u / n and r = u mod n for 0 <= u < 2^24 through a float reciprocal
@@ -81,24 +92,30 @@ constexpr int kMaxAng = kMaxBlocks * kAngBlock;  // 896 angular features
 
 // Non-empty species-pair block q of the centre's pair stream.
 struct PairBlock {
-  int start;    // first pair of the block in the stream
-  int p;        // feature block index (upper-triangle order of (sa, sb))
-  int oa, ob;   // offsets of the two species in the angular list
-  int na, nb;   // their counts
-  int same;     // sa == sb
-  float r_hi;   // 1 / max(na, nb)
-  float r_lo;   // 1 / min(na, nb)
-  int pad[3];
+  int start;                   // first pair of the block in the stream
+  unsigned short oa, ob;       // offsets of the two species in the angular list
+  unsigned short na, nb;       // their counts
+  unsigned char p;             // feature block index (upper-triangle order of (sa, sb))
+  unsigned char same;          // sa == sb
+  unsigned char pad0, pad1;
+  float r_hi;                  // 1 / max(na, nb)
+  float r_lo;                  // 1 / min(na, nb)
 };
+static_assert(sizeof(PairBlock) == 24, "pair-block table entry");
 
 __device__ inline PairBlock make_block(int start, int p, int oa, int ob, int na, int nb, bool same) {
   PairBlock b;
-  b.start = start; b.p = p; b.oa = oa; b.ob = ob; b.na = na; b.nb = nb; b.same = same;
+  b.start = start;
+  b.oa = (unsigned short)oa; b.ob = (unsigned short)ob;
+  b.na = (unsigned short)na; b.nb = (unsigned short)nb;
+  b.p = (unsigned char)p; b.same = same ? 1 : 0;
+  b.pad0 = b.pad1 = 0;
   b.r_hi = 1.0f / (float)max(max(na, nb), 1);
   b.r_lo = 1.0f / (float)max(min(na, nb), 1);
-  b.pad[0] = b.pad[1] = b.pad[2] = 0;
   return b;
 }
+// the table of one wave, padded to a multiple of 16 bytes
+constexpr size_t kBlkTableBytes = (sizeof(PairBlock) * (kMaxBlocks + 1) + 15) / 16 * 16;
 
 struct WaveLds {
   Lists *ls;       // per-species counts and offsets (wave-uniform)
@@ -106,23 +123,25 @@ struct WaveLds {
   float4 *tGeo;    // pair scratch: cos, sin, fc_j fc_k, -      (forward)
   float4 *tF2;     // pair scratch: radial Gaussians of Rbar     (forward)
   PairBlock *blk;  // [kMaxBlocks + 1] pair-block table           (backward)
-  float *gAng;     // angular part of the centre's dE/dG row      (backward)
   float4 *rD;      // radial: d vector and R
   float *rFc;      // radial: fc_rad(R)
   float *rDfc;     // radial: fc_rad'(R)         (backward)
   int *rJ;         // radial: neighbour index     (backward)
   long long *rG;   // radial: dE/dd accumulators, fixed point (backward, 3 per entry)
   int *aIdx;       // angular: position in the radial arrays
-  float *aFc;      // angular: fc_ang(R)
-  float *aDfc;     // angular: fc_ang'(R)         (backward)
+  float *aFc;      // angular: fc_ang(R)          (forward)
 };
 
+// Per-wave LDS bytes (a multiple of 16).  Forward entry: rD 16, rFc 4,
+// aIdx 4, aFc 4.  Backward entry: rD 16, rG 24, rFc 4, rDfc 4, rJ 4, aIdx 4;
+// the backward reads the centre's dE/dG row from global memory (it stays in
+// the L1/L2 caches) and recomputes the angular cutoff per pair, which keeps
+// its LDS per wave near 8 KB (5 waves per SIMD at a capacity of 128).
 template <bool BWD>
 __host__ __device__ inline size_t wave_lds_bytes(int cap) {
-  return sizeof(Lists) + (BWD ? (size_t)kMaxAng * 4 + sizeof(PairBlock) * (kMaxBlocks + 1) +
-                   (size_t)cap * (16 + 4 + 4 + 4 + 24 + 4 + 4 + 4)
-             : (size_t)kAngBlock * 4 + (size_t)kPairPass * 16 * 2 + (size_t)cap * (16 + 4 + 4 + 4));
-  // backward entry: rD 16, rFc 4, aIdx 4, aFc 4, rDfc 4, rJ 4, rG 24, aDfc 4
+  return sizeof(Lists) + (BWD ? kBlkTableBytes + (size_t)cap * (16 + 24 + 4 + 4 + 4 + 4)
+                              : (size_t)kAngBlock * 4 + (size_t)kPairPass * 16 * 2 +
+                                    (size_t)cap * (16 + 4 + 4 + 4));
 }
 
 template <bool BWD>
@@ -131,22 +150,21 @@ __device__ inline WaveLds carve(char *base, int cap) {
   char *p = base;
   w.ls = (Lists *)p; p += sizeof(Lists);
   if (BWD) {
-    w.gAng = (float *)p; p += (size_t)kMaxAng * 4;
-    w.blk = (PairBlock *)p; p += sizeof(PairBlock) * (kMaxBlocks + 1);
+    w.rD = (float4 *)p; p += (size_t)cap * 16;
+    w.rG = (long long *)p; p += (size_t)cap * 24;
+    w.blk = (PairBlock *)p; p += kBlkTableBytes;
+    w.rFc = (float *)p; p += (size_t)cap * 4;
+    w.rDfc = (float *)p; p += (size_t)cap * 4;
+    w.rJ = (int *)p; p += (size_t)cap * 4;
+    w.aIdx = (int *)p; p += (size_t)cap * 4;
   } else {
     w.xp = (float *)p; p += (size_t)kAngBlock * 4;
     w.tGeo = (float4 *)p; p += (size_t)kPairPass * 16;
     w.tF2 = (float4 *)p; p += (size_t)kPairPass * 16;
-  }
-  w.rD = (float4 *)p; p += (size_t)cap * 16;
-  w.rFc = (float *)p; p += (size_t)cap * 4;
-  w.aIdx = (int *)p; p += (size_t)cap * 4;
-  w.aFc = (float *)p; p += (size_t)cap * 4;
-  if (BWD) {
-    w.rDfc = (float *)p; p += (size_t)cap * 4;
-    w.rJ = (int *)p; p += (size_t)cap * 4;
-    w.rG = (long long *)p; p += (size_t)cap * 24;
-    w.aDfc = (float *)p; p += (size_t)cap * 4;
+    w.rD = (float4 *)p; p += (size_t)cap * 16;
+    w.rFc = (float *)p; p += (size_t)cap * 4;
+    w.aIdx = (int *)p; p += (size_t)cap * 4;
+    w.aFc = (float *)p; p += (size_t)cap * 4;
   }
   return w;
 }
@@ -310,6 +328,7 @@ __device__ inline void fill_lists(int lane, int n, const int2 *__restrict__ ent,
     }
   }
   const float kr = kPi / c.rc_r, ka = kPi / c.rc_a;
+  (void)ka;
   for (int b = 0; b < n; b += kWave) {
     int e = b + lane;
     int2 en = make_int2(0, 0);
@@ -341,12 +360,9 @@ __device__ inline void fill_lists(int lane, int n, const int2 *__restrict__ ent,
         }
       }
       if (inA && sj == s) {
-        int qa = pA[s] + (int)lanes_below(mA);
-        float sn, cs;
-        __sincosf(ka * d.w, &sn, &cs);
+        const int qa = pA[s] + (int)lanes_below(mA);
         w.aIdx[qa] = q;
-        w.aFc[qa] = 0.5f * cs + 0.5f;
-        if (BWD) w.aDfc[qa] = -0.5f * ka * sn;
+        if (!BWD) w.aFc[qa] = 0.5f * __cosf(ka * d.w) + 0.5f;
       }
       pR[s] += __popcll(mR);
       pA[s] += __popcll(mA);
@@ -452,6 +468,14 @@ k_aev_fwd(const float4 *__restrict__ pos, const int *__restrict__ sys_of,
       for (int sb = sa; sb < c.S; ++sb, ++p) {
         const int na = ls.cA[sa], nb = ls.cA[sb];
         const int T = sa == sb ? na * (na - 1) / 2 : na * nb;
+        if (T == 0) {
+          // no pair of these species: the block is zero
+          if (lane < kNShfAng) {
+            const float z[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+            store8<BF16>(Grow, c.rad_len + p * kAngBlock + 8 * lane, z);
+          }
+          continue;
+        }
         const PairBlock blk = make_block(0, p, 0, 0, na, nb, sa == sb);
         float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f, acc3 = 0.f;
         for (int base = 0; base < T; base += kPairPass) {
@@ -479,14 +503,30 @@ k_aev_fwd(const float4 *__restrict__ pos, const int *__restrict__ sys_of,
                                       fast_exp2(keta * u2 * u2), fast_exp2(keta * u3 * u3));
           }
           wave_lds_sync();
-          // (B) lanes = 8 angle shifts x 8 pairs
-          const int cnt = min(kPairPass, T - base);
-          for (int sub = 0; sub < cnt; sub += 8) {
-            const int q = sub + t0;
+          // (B) lanes = 8 angle shifts x 8 pairs.  Slots past the last pair
+          // hold a zero cutoff product (phase A), so they add nothing and need
+          // no test; groups of 8 pairs are taken two at a time.
+          const int groups = (min(kPairPass, T - base) + 7) >> 3;
+          int g8 = 0;
+          for (; g8 + 2 <= groups; g8 += 2) {
+            const int q0 = 8 * g8 + t0, q1 = q0 + 8;
+            const float4 geo0 = w.tGeo[q0], geo1 = w.tGeo[q1];
+            const float4 f20 = w.tF2[q0], f21 = w.tF2[q1];
+            const float x0 = fmaxf(1.0f + geo0.x * cza + geo0.y * sza, 0.f);
+            const float x1 = fmaxf(1.0f + geo1.x * cza + geo1.y * sza, 0.f);
+            const float v0 = fast_exp2(c.zeta * fast_log2(x0) + pre) * geo0.z;
+            const float v1 = fast_exp2(c.zeta * fast_log2(x1) + pre) * geo1.z;
+            acc0 += v0 * f20.x + v1 * f21.x;
+            acc1 += v0 * f20.y + v1 * f21.y;
+            acc2 += v0 * f20.z + v1 * f21.z;
+            acc3 += v0 * f20.w + v1 * f21.w;
+          }
+          if (g8 < groups) {
+            const int q = 8 * g8 + t0;
             const float4 geo = w.tGeo[q];
             const float4 f2 = w.tF2[q];
             const float x = fmaxf(1.0f + geo.x * cza + geo.y * sza, 0.f);
-            const float v = q < cnt ? fast_exp2(c.zeta * fast_log2(x) + pre) * geo.z : 0.f;
+            const float v = fast_exp2(c.zeta * fast_log2(x) + pre) * geo.z;
             acc0 += v * f2.x; acc1 += v * f2.y; acc2 += v * f2.z; acc3 += v * f2.w;
           }
           wave_lds_sync();
@@ -530,18 +570,25 @@ k_aev_bwd(const float4 *__restrict__ pos, const int *__restrict__ sys_of,
     j0 = d.atom_off;
     row = nbr + nbr_row(d, i, cap);
   }
+  // this lane's radial dE/dG values (shift m = lane % 16 of every species),
+  // loaded now so that their latency overlaps the list construction
+  const float *g = dG + (size_t)(live ? row_of_atom[i] : 0) * ldg;
+  float gR[kMaxSpecies];
+#pragma unroll
+  for (int s = 0; s < kMaxSpecies; ++s) gR[s] = live && s < c.S ? g[s * kNShfRad + (lane & 15)] : 0.f;
   fill_lists<true>(lane, n, row, j0, n_sys, pos, pi, L, c, w);
   __syncthreads();
   if (!live) return;
   const Lists &ls = *w.ls;
-  const float *g = dG + (size_t)row_of_atom[i] * ldg;
 
   // radial: dE/dR = scale * sum_m g_m d/dR[exp(-eta (R - Rs_m)^2) fc(R)]
   {
     const int m = lane & 15, slot = lane >> 4;
     const float shf = pick(c.shf_r, m);
-    for (int s = 0; s < c.S; ++s) {
-      const float gm = g[s * kNShfRad + m] * c.scale;
+#pragma unroll
+    for (int s = 0; s < kMaxSpecies; ++s) {
+      if (s >= c.S) break;
+      const float gm = gR[s] * c.scale;
       const int o = ls.oR[s];
       for (int e = slot; e < ls.cR[s]; e += 4) {
         const float4 d = w.rD[o + e];
@@ -561,8 +608,8 @@ k_aev_bwd(const float4 *__restrict__ pos, const int *__restrict__ sys_of,
 
   // angular: lane per neighbour pair over the pair stream of all blocks
   {
-    const int nang = (c.S * (c.S + 1) / 2) * kAngBlock;
-    for (int k = lane; k < nang; k += kWave) w.gAng[k] = g[c.rad_len + k];
+    const float *gA = g + c.rad_len;
+    const float ka = kPi / c.rc_a;
     int nblk;
     const int P = build_blocks(lane, ls, c.S, w, nblk);
     wave_lds_sync();
@@ -577,7 +624,10 @@ k_aev_bwd(const float4 *__restrict__ pos, const int *__restrict__ sys_of,
       locate_pair(min(base + lane, P - 1), qb, nblk, base + kPairPass, w, aj, ak, p);
       const int qj = w.aIdx[aj], qk = w.aIdx[ak];
       const float4 dj = w.rD[qj], dk = w.rD[qk];
-      const float fj = w.aFc[aj], fk = w.aFc[ak];
+      float sj_, cj_, sk_, ck_;
+      __sincosf(ka * dj.w, &sj_, &cj_);
+      __sincosf(ka * dk.w, &sk_, &ck_);
+      const float fj = 0.5f * cj_ + 0.5f, fk = 0.5f * ck_ + 0.5f;
       const float dot = dj.x * dk.x + dj.y * dk.y + dj.z * dk.z;
       const float cx = dj.y * dk.z - dj.z * dk.y;
       const float cy = dj.z * dk.x - dj.x * dk.z;
@@ -594,8 +644,8 @@ k_aev_bwd(const float4 *__restrict__ pos, const int *__restrict__ sys_of,
         f2[r] = fast_exp2(keta * u * u);
         df2[r] = m2eta * u * f2[r];
       }
-      // dE/dG of this block: gv[r][a] at gAng[32 p + 8 r + a]
-      const float4 *gv = (const float4 *)(w.gAng + p * kAngBlock);
+      // dE/dG of this block: gv[r][a] at gA[32 p + 8 r + a] (global, cached)
+      const float4 *gv = (const float4 *)(gA + p * kAngBlock);
       float dcos = 0.f, dsin = 0.f, dbar = 0.f, dfc = 0.f;
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
@@ -630,8 +680,8 @@ k_aev_bwd(const float4 *__restrict__ pos, const int *__restrict__ sys_of,
         dcos *= fcc;
         dsin *= fcc;
         dbar *= 0.5f * fcc;  // via Rbar, for each of R_j and R_k
-        const float dRj = dbar + dfc * w.aDfc[aj] * fk;
-        const float dRk = dbar + dfc * fj * w.aDfc[ak];
+        const float dRj = dbar + dfc * (-0.5f * ka * sj_) * fk;
+        const float dRk = dbar + dfc * fj * (-0.5f * ka * sk_);
         const float inv_cr = cr > 1e-12f * RR ? fast_rcp(cr) : 0.f;
         const float invj = fast_rcp(dj.w), invk = fast_rcp(dk.w);
         const float aj_ = dcos * invRR, ak_ = dsin * inv_cr * invRR;
