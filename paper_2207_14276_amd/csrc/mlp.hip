@@ -256,50 +256,93 @@ void launch_gemm(int epi, bool bf16, GemmLaunch gl, int row_tiles, int max_n_out
 
 // Output layer (one unit) of every ensemble member: E_row = mean over members
 // of w . h + b, and dE/dh = w * CELU'(h) / M per member (or, for networks
-// without hidden layers, dE/dG = mean of w).  One wave per row.
+// without hidden layers, dE/dG = mean of w).  One half-wave (32 lanes) per
+// row; a lane takes 8 consecutive inputs at a time (one 16-byte bfloat16 or
+// two 16-byte float32 accesses).  Hidden widths and the AEV length are
+// multiples of 8, so a lane's 8 inputs never straddle a member's slice.
+template <bool BF16> struct Vec8;
+template <> struct Vec8<true> {
+  static __device__ inline void load(const uint16_t *p, float v[8]) {
+    const uint4 u = *(const uint4 *)p;
+    const uint32_t w[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      v[2 * q] = __uint_as_float(w[q] << 16);
+      v[2 * q + 1] = __uint_as_float(w[q] & 0xffff0000u);
+    }
+  }
+  static __device__ inline void store(uint16_t *p, const float v[8]) {
+    uint4 u;
+    u.x = bf16_bits_rne(v[0]) | (bf16_bits_rne(v[1]) << 16);
+    u.y = bf16_bits_rne(v[2]) | (bf16_bits_rne(v[3]) << 16);
+    u.z = bf16_bits_rne(v[4]) | (bf16_bits_rne(v[5]) << 16);
+    u.w = bf16_bits_rne(v[6]) | (bf16_bits_rne(v[7]) << 16);
+    *(uint4 *)p = u;
+  }
+};
+template <> struct Vec8<false> {
+  static __device__ inline void load(const float *p, float v[8]) {
+    const float4 a = *(const float4 *)p, b = *(const float4 *)(p + 4);
+    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+    v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+  }
+  static __device__ inline void store(float *p, const float v[8]) {
+    *(float4 *)p = make_float4(v[0], v[1], v[2], v[3]);
+    *(float4 *)(p + 4) = make_float4(v[4], v[5], v[6], v[7]);
+  }
+};
+
 template <bool BF16>
 __global__ void __launch_bounds__(256) k_energy(EnergyLaunch el, int rows) {
   typedef typename Op<BF16>::T T;
-  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-  const int row = blockIdx.x * 4 + wave;
-  if (row >= rows) return;
+  const int half = threadIdx.x >> 5, l32 = threadIdx.x & 31;
+  const int row = blockIdx.x * 8 + half;
   int s = -1;
-  for (int q = 0; q < el.n_groups; ++q)
-    if (row >= el.bucket_off[q] && row < el.bucket_off[q + 1]) s = q;
-  if (s < 0) return;
-  const int atom = el.perm[row];
-  if (atom < 0) return;
-  float e = 0.f;
-  float bsum = 0.f;
-  for (int m = 0; m < el.n_members; ++m) {
+  if (row < rows)
+    for (int q = 0; q < el.n_groups; ++q)
+      if (row >= el.bucket_off[q] && row < el.bucket_off[q + 1]) s = q;
+  const int atom = s >= 0 ? el.perm[row] : -1;
+  const bool active = atom >= 0;   // uniform over the half-wave
+  float e = 0.f, bsum = 0.f;
+  if (active) {
     const int K = el.K[s];
-    const float *w = el.w[m * el.n_groups + s];
-    bsum += el.b[m * el.n_groups + s][0];
-    const T *h = (const T *)el.Hin + (size_t)row * el.ldh + (size_t)m * el.h_member_stride;
-    for (int k = lane; k < K; k += kWave) {
-      const float hv = Op<BF16>::load(h + k), wv = w[k];
-      e += hv * wv;
-      if (el.want_grad) {
-        if (el.hidden) {
-          T *go = (T *)el.Gout + (size_t)row * el.ldg + (size_t)m * el.g_member_stride + k;
-          Op<BF16>::store(go, wv * dcelu_from_h(hv, el.alpha) * el.inv_m);
-        } else {
-          // no hidden layer: dE/dG = mean of w, float32
-          float *go = (float *)el.Gout + (size_t)row * el.ldg + k;
-          const float v = wv * el.inv_m;
-          *go = m == 0 ? v : *go + v;
+    for (int m = 0; m < el.n_members; ++m) {
+      const float *w = el.w[m * el.n_groups + s];
+      bsum += el.b[m * el.n_groups + s][0];
+      const T *h = (const T *)el.Hin + (size_t)row * el.ldh + (size_t)m * el.h_member_stride;
+      for (int k0 = 8 * l32; k0 < K; k0 += 256) {
+        float hv[8], wv[8];
+        Vec8<BF16>::load(h + k0, hv);
+        Vec8<false>::load(w + k0, wv);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) e += hv[q] * wv[q];
+        if (el.want_grad) {
+          if (el.hidden) {
+            float gv[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) gv[q] = wv[q] * dcelu_from_h(hv[q], el.alpha) * el.inv_m;
+            Vec8<BF16>::store((T *)el.Gout + (size_t)row * el.ldg + (size_t)m * el.g_member_stride + k0, gv);
+          } else {
+            // no hidden layer: dE/dG = mean of w, float32
+            float *go = (float *)el.Gout + (size_t)row * el.ldg + k0;
+            float gv[8];
+            if (m > 0) Vec8<false>::load(go, gv);
+#pragma unroll
+            for (int q = 0; q < 8; ++q) gv[q] = (m == 0 ? 0.f : gv[q]) + wv[q] * el.inv_m;
+            Vec8<false>::store(go, gv);
+          }
         }
       }
     }
   }
-  for (int off = 32; off >= 1; off >>= 1) e += __shfl_xor(e, off);
-  if (lane == 0) el.e_atom[atom] = (e + bsum) * el.inv_m;
+  for (int off = 16; off >= 1; off >>= 1) e += __shfl_xor(e, off, 32);
+  if (active && l32 == 0) el.e_atom[atom] = (e + bsum) * el.inv_m;
 }
 
 void launch_energy(const EnergyLaunch &el, bool bf16, int rows, hipStream_t st) {
   if (rows <= 0) return;
-  if (bf16) k_energy<true><<<(rows + 3) / 4, 256, 0, st>>>(el, rows);
-  else k_energy<false><<<(rows + 3) / 4, 256, 0, st>>>(el, rows);
+  if (bf16) k_energy<true><<<(rows + 7) / 8, 256, 0, st>>>(el, rows);
+  else k_energy<false><<<(rows + 7) / 8, 256, 0, st>>>(el, rows);
 }
 
 // Per-system totals in float64: energies (sum of atomic energies) and the
