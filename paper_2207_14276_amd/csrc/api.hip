@@ -101,6 +101,9 @@ struct nnp_model {
   std::vector<uint16_t *> Wdg_b;
   std::vector<void *> weight_allocs;
   int cap = 256;                         // neighbour capacity per atom
+  int ldG = 0;                           // row stride of the AEV buffer G: the AEV length
+                                         // rounded up to 32; columns past it stay zero
+  size_t G_zeroed = 0;                   // bytes of G cleared since its last growth
 
   // workspace
   DevBuf pos, sys_of, atom_cell, atom_slot, cell_count, cell_start, cell_atoms, nbr, nbr_cnt;
@@ -222,6 +225,7 @@ static int create_impl(const nnp_model_desc *d, nnp_model *m) {
     if (m->widths[s][0] != c.D) return fail(NNP_EINVAL, "first width must be the AEV length %d", c.D);
     if (m->widths[s][L] != 1) return fail(NNP_EINVAL, "last width must be 1");
   }
+  m->ldG = (c.D + 31) / 32 * 32;
   m->ldH.assign(std::max(L - 1, 0), 0);
   for (int l = 0; l + 1 < L; ++l)
     for (int s = 0; s < S; ++s) m->ldH[l] = std::max(m->ldH[l], m->widths[s][l + 1]);
@@ -248,8 +252,16 @@ static int create_impl(const nnp_model_desc *d, nnp_model *m) {
         if ((rc = upload(m, tmp.data(), nw * 4, (void **)&lw.Wt))) return rc;
         if (m->precision == NNP_BF16) {
           tb.resize(nw);
-          round_bf16_host(wp, tb.data(), nw);
-          if ((rc = upload(m, tb.data(), nw * 2, (void **)&lw.Wb))) return rc;
+          if (l == 0) {
+            // first layer: rows padded with zeros to the stride of G
+            std::vector<uint16_t> pad((size_t)lw.n_out * m->ldG, 0);
+            for (int o = 0; o < lw.n_out; ++o)
+              round_bf16_host(wp + (size_t)o * lw.n_in, pad.data() + (size_t)o * m->ldG, lw.n_in);
+            if ((rc = upload(m, pad.data(), pad.size() * 2, (void **)&lw.Wb))) return rc;
+          } else {
+            round_bf16_host(wp, tb.data(), nw);
+            if ((rc = upload(m, tb.data(), nw * 2, (void **)&lw.Wb))) return rc;
+          }
           round_bf16_host(tmp.data(), tb.data(), nw);
           if ((rc = upload(m, tb.data(), nw * 2, (void **)&lw.Wtb))) return rc;
         }
@@ -337,7 +349,7 @@ static int for_each_ws(nnp_model *m, int64_t N, int S, int64_t C, int n_chunks, 
   ENS(m->perm, rows * 4);
   ENS(m->row_of_atom, N * 4);
   const int esz = m->precision == NNP_BF16 ? 2 : 4;  // activation element size
-  ENS(m->G, rows * m->aev.D * esz);
+  ENS(m->G, rows * m->ldG * esz);
   ENS(m->dG, rows * m->aev.D * 4);
   ENS(m->e_atom, N * 4);
   ENS(m->W_atom, N * 36);
@@ -577,6 +589,12 @@ static int run(nnp_model *m, int n_sys, const int64_t *offs, const float *coords
   if (C > ((int64_t)1 << 28)) return fail(NNP_EUNSUPPORTED, "too many cells");
   int rc = ensure_ws(m, N, n_sys, C, n_chunks, nl != nullptr);
   if (rc) return rc;
+  if (m->G.bytes != m->G_zeroed) {
+    // a newly allocated G: clear it once so that the columns past the AEV
+    // length (never written) read as zeros in the first-layer GEMM
+    HIP_TRY(hipMemsetAsync(m->G.p, 0, m->G.bytes, st));
+    m->G_zeroed = m->G.bytes;
+  }
 
   // stage the per-call descriptors through pinned memory
   size_t off_sd = 0, off_cs = off_sd + sizeof(SysDesc) * n_sys;
@@ -662,7 +680,7 @@ static int run(nnp_model *m, int n_sys, const int64_t *offs, const float *coords
     return NNP_OK;
   }
   launch_aev_fwd(pos, m->sys_of.as<int>(), dsys, pool_nbr, pool_cnt, cap,
-                 m->row_of_atom.as<int>(), m->G.p, bf16, D, N, m->aev, st);
+                 m->row_of_atom.as<int>(), m->G.p, bf16, m->ldG, N, m->aev, st);
   mark();
 
   // element networks: forward, output layer, backward to dE/dG; every launch
@@ -682,7 +700,7 @@ static int run(nnp_model *m, int n_sys, const int64_t *offs, const float *coords
     GemmLaunch gl{};
     common(gl);
     gl.A = l == 0 ? m->G.p : m->H[l - 1].p;
-    gl.lda = l == 0 ? D : M * m->ldH[l - 1];
+    gl.lda = l == 0 ? m->ldG : M * m->ldH[l - 1];
     gl.a_member_stride = l == 0 ? 0 : m->ldH[l - 1];
     gl.C = m->H[l].p;
     gl.ldc = M * m->ldH[l];
@@ -695,13 +713,14 @@ static int run(nnp_model *m, int n_sys, const int64_t *offs, const float *coords
         g.bias = lw.b;
         g.n_out = lw.n_out;
         g.K = lw.n_in;
+        if (l == 0 && bf16) g.K = g.ldb = m->ldG;  // zero-padded columns on both sides
       }
     launch_gemm(kEpiFwd, bf16, gl, row_tiles, m->ldH[l], st);
   }
   {
     EnergyLaunch el{};
     el.Hin = L >= 2 ? m->H[L - 2].p : m->G.p;
-    el.ldh = L >= 2 ? M * m->ldH[L - 2] : D;
+    el.ldh = L >= 2 ? M * m->ldH[L - 2] : m->ldG;
     el.h_member_stride = L >= 2 ? m->ldH[L - 2] : 0;
     el.Gout = L >= 2 ? m->Gd[L - 2].p : m->dG.p;
     el.ldg = L >= 2 ? M * m->ldH[L - 2] : D;

@@ -84,9 +84,11 @@ __host__ __device__ inline void unpack_image(int c, int &x, int &y, int &z) {
 constexpr int kMaxMembers = 8;  // ensemble members
 
 struct GemmGroup {
-  const void *B;      // [n_out][n_seg * K] row-major, float or bf16
+  const void *B;      // [n_out][ldb] row-major, float or bf16; segment q at column q * K
   const float *bias;  // [n_out] (forward only)
   int n_out, K;       // K per segment
+  int ldb;            // row stride of B in elements (0: n_seg * K)
+  int pad;
 };
 
 struct GemmLaunch {
@@ -102,6 +104,7 @@ struct GemmLaunch {
   int n_members;               // grid dimension over ensemble members
   int n_seg;                   // K segments summed into one output
   int col_tiles;               // set by the launcher
+  int k32;                     // every K and stride allows 32-wide K chunks (direct-to-LDS kernel)
   GemmGroup g[kMaxMembers * kMaxSpecies];  // [member][species]
   float alpha;                 // CELU alpha
   float scale;

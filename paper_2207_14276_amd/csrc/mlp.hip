@@ -101,7 +101,7 @@ __global__ void __launch_bounds__(256) k_gemm(GemmLaunch gl) {
 
   const T *A = (const T *)gl.A + (size_t)r0 * gl.lda + (size_t)mb * gl.a_member_stride;
   const T *B = (const T *)grp.B;
-  const size_t ldb = (size_t)K * nseg;
+  const size_t ldb = grp.ldb ? (size_t)grp.ldb : (size_t)K * nseg;
 
   uint4 ra[A_VEC], rb[B_VEC];
   auto load_chunk = [&](int c) {
@@ -230,15 +230,193 @@ __global__ void __launch_bounds__(256) k_gemm(GemmLaunch gl) {
   }
 }
 
+// bfloat16 GEMM fed by direct global -> LDS loads (global_load_lds_dwordx4):
+// no staging registers and no LDS store instructions, so a three-stage ring
+// fits in the register budget of the two-stage kernel above.  Each 128 x 32
+// (or TN x 32) operand tile is 16-byte slots, row r's 4 K-chunks at slots
+// 4 r + (chunk ^ swz(r)); a wave's load instruction fills 64 consecutive
+// slots, and the XOR swizzle keeps the MFMA operand reads free of bank
+// conflicts for both 8- and 16-lane LDS phases.  Requires every K (per
+// segment), lda, ldb and the segment and member offsets to be multiples of
+// 32 elements (gl.k32); column tiles past n_out read a clamped, valid row and
+// their results are discarded.
+__device__ inline int lds_swz(int r) { return ((r >> 1) ^ (r >> 3)) & 3; }
+
+template <int EPI, int TN>
+__global__ void __launch_bounds__(256) k_gemm_dl(GemmLaunch gl) {
+  typedef uint16_t T;
+  constexpr int TM = kTileM;
+  constexpr int TK = 32;
+  constexpr int STAGES = 3;
+  constexpr int WM = TN == 128 ? 64 : 32;
+  constexpr int WN = 64;
+  constexpr int WAVES_N = TN / WN;
+  constexpr int BM = WM / 32, BN = WN / 32;
+  constexpr int A_SLOTS = TM * 4, B_SLOTS = TN * 4;  // 16-byte slots per stage
+  constexpr int A_LD = A_SLOTS / 256, B_LD = B_SLOTS / 256;
+  constexpr int LOADS = A_LD + B_LD;                  // load instructions per chunk and thread
+  static_assert(A_LD >= 1 && B_LD >= 1, "tile too small");
+  __shared__ __attribute__((aligned(16))) uint4 smem[STAGES][A_SLOTS + B_SLOTS];
+
+  const int nb = gridDim.x;
+  const int lb = xcd_logical(blockIdx.x, nb);
+  const int n_ct = gl.col_tiles;
+  const int ct = lb % n_ct;
+  const int mb = (lb / n_ct) % gl.n_members;
+  const int rt = lb / (n_ct * gl.n_members);
+  const int r0 = rt * TM;
+  int s = -1;
+  for (int q = 0; q < gl.n_groups; ++q)
+    if (r0 >= gl.bucket_off[q] && r0 < gl.bucket_off[q + 1]) s = q;
+  if (s < 0) return;
+  const GemmGroup grp = gl.g[mb * gl.n_groups + s];
+  const int c0 = ct * TN;
+  if (c0 >= grp.n_out) return;
+  const int K = grp.K;
+  const int nseg = gl.n_seg;
+  const int nk = K / TK;
+  const int total = nk * nseg;
+
+  const int tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
+  const int l32 = lane & 31, hi = lane >> 5;
+  const int wr = wave / WAVES_N, wc = wave % WAVES_N;
+
+  const T *A = (const T *)gl.A + (size_t)r0 * gl.lda + (size_t)mb * gl.a_member_stride;
+  const T *B = (const T *)grp.B;
+  const size_t ldb = grp.ldb ? (size_t)grp.ldb : (size_t)K * nseg;
+
+  // this thread's source rows and chunks (fixed over the K loop)
+  const T *asrc[A_LD];
+  const T *bsrc[B_LD];
+#pragma unroll
+  for (int q = 0; q < A_LD; ++q) {
+    const int sl = q * 256 + tid, row = sl >> 2, kc = (sl & 3) ^ lds_swz(row);
+    asrc[q] = A + (size_t)row * gl.lda + kc * 8;
+  }
+#pragma unroll
+  for (int q = 0; q < B_LD; ++q) {
+    const int sl = q * 256 + tid, row = sl >> 2, kc = (sl & 3) ^ lds_swz(row);
+    const int col = min(c0 + row, grp.n_out - 1);
+    bsrc[q] = B + (size_t)col * ldb + kc * 8;
+  }
+  auto issue = [&](int c, int stage) {
+    const int seg = c / nk, k0 = (c % nk) * TK;
+    const size_t ao = (size_t)seg * gl.a_seg_stride + k0, bo = (size_t)seg * K + k0;
+#pragma unroll
+    for (int q = 0; q < A_LD; ++q)
+      __builtin_amdgcn_global_load_lds((const void *)(asrc[q] + ao),
+                                       (__attribute__((address_space(3))) void *)&smem[stage][q * 256 + wave * kWave],
+                                       16, 0, 0);
+#pragma unroll
+    for (int q = 0; q < B_LD; ++q)
+      __builtin_amdgcn_global_load_lds((const void *)(bsrc[q] + bo),
+                                       (__attribute__((address_space(3))) void *)&smem[stage][A_SLOTS + q * 256 + wave * kWave],
+                                       16, 0, 0);
+  };
+
+  floatx16 acc[BM][BN];
+#pragma unroll
+  for (int i = 0; i < BM; ++i)
+#pragma unroll
+    for (int j = 0; j < BN; ++j) acc[i][j] = floatx16{};
+
+  issue(0, 0);
+  if (total > 1) issue(1, 1);
+  for (int c = 0; c < total; ++c) {
+    // this wave's loads of chunk c are done once at most chunk c+1's remain
+    // (vmcnt in the low bits; expcnt and lgkmcnt left at their maxima)
+    if (c + 1 < total) __builtin_amdgcn_s_waitcnt(0xF70 | LOADS);
+    else __builtin_amdgcn_s_waitcnt(0xF70);
+    // a plain barrier: LDS is coherent within the workgroup, every wave has
+    // waited for its own part of chunk c above, and its reads of the stage
+    // overwritten next were consumed (by MFMAs) before it got here; a full
+    // __syncthreads() would also wait for the loads of chunk c + 1
+    __builtin_amdgcn_s_barrier();
+    // stage (c + 2) % 3 was last read for chunk c - 1, which every wave has
+    // finished (barrier above)
+    if (c + 2 < total) issue(c + 2, (c + 2) % STAGES);
+    const uint4 *As = smem[c % STAGES];
+    const uint4 *Bs = As + A_SLOTS;
+#pragma unroll
+    for (int kk = 0; kk < TK; kk += 16) {
+      const int ch = kk / 8 + hi;
+      bf16x8 a[BM], b[BN];
+#pragma unroll
+      for (int i = 0; i < BM; ++i) {
+        const int r = wr * WM + i * 32 + l32;
+        a[i] = __builtin_bit_cast(bf16x8, As[4 * r + (ch ^ lds_swz(r))]);
+      }
+#pragma unroll
+      for (int j = 0; j < BN; ++j) {
+        const int r = wc * WN + j * 32 + l32;
+        b[j] = __builtin_bit_cast(bf16x8, Bs[4 * r + (ch ^ lds_swz(r))]);
+      }
+#pragma unroll
+      for (int i = 0; i < BM; ++i)
+#pragma unroll
+        for (int j = 0; j < BN; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+  }
+
+  // D[row][col]: col = lane % 32, row = 8 (i / 4) + 4 (lane / 32) + i % 4
+#pragma unroll
+  for (int bj = 0; bj < BN; ++bj) {
+    const int col = c0 + wc * WN + bj * 32 + l32;
+    if (col >= grp.n_out) continue;
+    const float bias = EPI == kEpiFwd ? grp.bias[col] : 0.f;
+#pragma unroll
+    for (int bi = 0; bi < BM; ++bi) {
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const int row = r0 + wr * WM + bi * 32 + 8 * (i / 4) + 4 * hi + (i % 4);
+        const float v = acc[bi][bj][i];
+        if (EPI == kEpiFwd) {
+          T *out = (T *)gl.C + (size_t)row * gl.ldc + (size_t)mb * gl.c_member_stride + col;
+          Op<true>::store(out, celu(v + bias, gl.alpha));
+        } else if (EPI == kEpiBwd) {
+          T *out = (T *)gl.C + (size_t)row * gl.ldc + (size_t)mb * gl.c_member_stride + col;
+          const float h = Op<true>::load((const T *)gl.H + (size_t)row * gl.ldh +
+                                         (size_t)mb * gl.h_member_stride + col);
+          Op<true>::store(out, v * dcelu_from_h(h, gl.alpha) * gl.scale);
+        } else {
+          float *out = (float *)gl.C + (size_t)row * gl.ldc + col;
+          *out = v * gl.scale;
+        }
+      }
+    }
+  }
+}
+
 template <int EPI, bool BF16>
 static void launch_t(const GemmLaunch &gl, int row_tiles, int tn, hipStream_t st) {
   const unsigned blocks = (unsigned)(row_tiles * gl.n_members * gl.col_tiles);
+  if (BF16 && gl.k32) {
+    if (tn == 128) k_gemm_dl<EPI, 128><<<blocks, 256, 0, st>>>(gl);
+    else k_gemm_dl<EPI, 64><<<blocks, 256, 0, st>>>(gl);
+    return;
+  }
   if (tn == 128) k_gemm<EPI, BF16, 128><<<blocks, 256, 0, st>>>(gl);
   else k_gemm<EPI, BF16, 64><<<blocks, 256, 0, st>>>(gl);
 }
 
+// Whether every K chunk of 32 elements and every operand row start is
+// 16-byte aligned and inside its row, as the direct-to-LDS kernel needs.
+static bool gemm_k32(const GemmLaunch &gl) {
+  auto m32 = [](long long v) { return v % 32 == 0; };
+  if (!m32(gl.lda) || !m32(gl.a_member_stride) || !m32(gl.a_seg_stride)) return false;
+  for (int q = 0; q < gl.n_members * gl.n_groups; ++q) {
+    const GemmGroup &g = gl.g[q];
+    if (!g.B) continue;
+    const long long ldb = g.ldb ? g.ldb : (long long)g.K * gl.n_seg;
+    if (!m32(g.K) || !m32(ldb) || g.K < 32) return false;
+  }
+  return true;
+}
+
 void launch_gemm(int epi, bool bf16, GemmLaunch gl, int row_tiles, int max_n_out, hipStream_t st) {
   if (row_tiles <= 0) return;
+  gl.k32 = bf16 && gemm_k32(gl) ? 1 : 0;
   // 128-wide column tiles when they waste little, else 64
   const int t128 = (max_n_out + 127) / 128 * 128, t64 = (max_n_out + 63) / 64 * 64;
   const int tn = (t128 - max_n_out) * 4 <= max_n_out && t128 <= t64 + 32 ? 128 : 64;
