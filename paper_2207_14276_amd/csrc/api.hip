@@ -654,7 +654,7 @@ static int run(nnp_model *m, int n_sys, const int64_t *offs, const float *coords
                       m->cell_atoms.as<int>(), st);
   launch_cell_sort(m->cell_start.as<int>(), (int)C, m->cell_atoms.as<int>(), st);
   mark();
-  launch_nbr_build(pos, m->sys_of.as<int>(), dsys, m->cell_start.as<int>(), m->cell_atoms.as<int>(), N,
+  launch_nbr_build(pos, m->sys_of.as<int>(), dsys, n_sys, (int)C, m->cell_start.as<int>(), m->cell_atoms.as<int>(), N,
                    rc_list, cap, pool_nbr, pool_cnt, status, st);
   if (mode == kNbr) {
     launch_export_nbr(pool_nbr, pool_cnt, cap, dsys, m->sys_of.as<int>(), N, o.nb_counts,

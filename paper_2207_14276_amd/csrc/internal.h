@@ -140,9 +140,9 @@ void launch_scan(const int *in, int *out, int n, hipStream_t st);
 void launch_cell_scatter(const int *atom_cell, const int *atom_slot, const int *cell_start,
                          int N, int *cell_atoms, hipStream_t st);
 void launch_cell_sort(const int *cell_start, int n_cells, int *cell_atoms, hipStream_t st);
-void launch_nbr_build(const float4 *pos, const int *sys_of, const SysDesc *sys,
-                      const int *cell_start, const int *cell_atoms, int N, float rc_list,
-                      int cap, int2 *nbr, int *nbr_cnt, int *status, hipStream_t st);
+void launch_nbr_build(const float4 *pos, const int *sys_of, const SysDesc *sys, int n_sys, int n_cells,
+                      const int *cell_start, const int *cell_atoms, int N, float rc_list, int cap,
+                      int2 *nbr, int *nbr_cnt, int *status, hipStream_t st);
 void launch_species_bucket(const float4 *pos, int N, int S, int *block_counts, int n_blocks,
                            int *bucket_off, int *bucket_cnt, int *perm, int *row_of_atom,
                            int rows_cap, hipStream_t st);

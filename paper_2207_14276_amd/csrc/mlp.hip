@@ -230,6 +230,40 @@ __global__ void __launch_bounds__(256) k_gemm(GemmLaunch gl) {
   }
 }
 
+// Eight consecutive elements in one 16-byte (bfloat16) or two 16-byte
+// (float32) accesses; p is 16-byte aligned.
+template <bool BF16> struct Vec8;
+template <> struct Vec8<true> {
+  static __device__ inline void load(const uint16_t *p, float v[8]) {
+    const uint4 u = *(const uint4 *)p;
+    const uint32_t w[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      v[2 * q] = __uint_as_float(w[q] << 16);
+      v[2 * q + 1] = __uint_as_float(w[q] & 0xffff0000u);
+    }
+  }
+  static __device__ inline void store(uint16_t *p, const float v[8]) {
+    uint4 u;
+    u.x = bf16_bits_rne(v[0]) | (bf16_bits_rne(v[1]) << 16);
+    u.y = bf16_bits_rne(v[2]) | (bf16_bits_rne(v[3]) << 16);
+    u.z = bf16_bits_rne(v[4]) | (bf16_bits_rne(v[5]) << 16);
+    u.w = bf16_bits_rne(v[6]) | (bf16_bits_rne(v[7]) << 16);
+    *(uint4 *)p = u;
+  }
+};
+template <> struct Vec8<false> {
+  static __device__ inline void load(const float *p, float v[8]) {
+    const float4 a = *(const float4 *)p, b = *(const float4 *)(p + 4);
+    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+    v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+  }
+  static __device__ inline void store(float *p, const float v[8]) {
+    *(float4 *)p = make_float4(v[0], v[1], v[2], v[3]);
+    *(float4 *)(p + 4) = make_float4(v[4], v[5], v[6], v[7]);
+  }
+};
+
 // bfloat16 GEMM fed by direct global -> LDS loads (global_load_lds_dwordx4):
 // no staging registers and no LDS store instructions, so a three-stage ring
 // fits in the register budget of the two-stage kernel above.  Each 128 x 32
@@ -359,31 +393,57 @@ __global__ void __launch_bounds__(256) k_gemm_dl(GemmLaunch gl) {
     }
   }
 
-  // D[row][col]: col = lane % 32, row = 8 (i / 4) + 4 (lane / 32) + i % 4
+  // Epilogue through LDS: each 32 x 32 accumulator block is written to a
+  // per-wave LDS tile in the MFMA layout (col = lane % 32, row = 8 (i / 4) +
+  // 4 (lane / 32) + i % 4) and read back by rows, so that every global access
+  // moves 8 consecutive elements (16-byte bfloat16 rows, 2 x 16-byte float32
+  // rows).  Output widths are multiples of 8: an 8-column chunk is either
+  // wholly inside n_out or wholly outside.
+  constexpr int EP_LD = 36;                     // floats per LDS row (16-byte aligned)
+  __syncthreads();                              // every wave is done with the operand tiles
+  float *ep = (float *)smem + wave * 32 * EP_LD;
 #pragma unroll
-  for (int bj = 0; bj < BN; ++bj) {
-    const int col = c0 + wc * WN + bj * 32 + l32;
-    if (col >= grp.n_out) continue;
-    const float bias = EPI == kEpiFwd ? grp.bias[col] : 0.f;
+  for (int bi = 0; bi < BM; ++bi) {
 #pragma unroll
-    for (int bi = 0; bi < BM; ++bi) {
+    for (int bj = 0; bj < BN; ++bj) {
 #pragma unroll
-      for (int i = 0; i < 16; ++i) {
-        const int row = r0 + wr * WM + bi * 32 + 8 * (i / 4) + 4 * hi + (i % 4);
-        const float v = acc[bi][bj][i];
+      for (int i = 0; i < 16; ++i) ep[(8 * (i / 4) + 4 * hi + (i % 4)) * EP_LD + l32] = acc[bi][bj][i];
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const int chunk = q * kWave + lane;     // 128 chunks of 8: 32 rows x 4
+        const int rr = chunk >> 2, cc = (chunk & 3) * 8;
+        const int row = r0 + wr * WM + bi * 32 + rr;
+        const int col = c0 + wc * WN + bj * 32 + cc;
+        if (col >= grp.n_out) continue;
+        float v[8];
+        const float4 v0 = *(const float4 *)(ep + rr * EP_LD + cc);
+        const float4 v1 = *(const float4 *)(ep + rr * EP_LD + cc + 4);
+        v[0] = v0.x; v[1] = v0.y; v[2] = v0.z; v[3] = v0.w;
+        v[4] = v1.x; v[5] = v1.y; v[6] = v1.z; v[7] = v1.w;
         if (EPI == kEpiFwd) {
-          T *out = (T *)gl.C + (size_t)row * gl.ldc + (size_t)mb * gl.c_member_stride + col;
-          Op<true>::store(out, celu(v + bias, gl.alpha));
+          float b[8];
+          Vec8<false>::load(grp.bias + col, b);
+#pragma unroll
+          for (int e = 0; e < 8; ++e) v[e] = celu(v[e] + b[e], gl.alpha);
+          Vec8<true>::store((T *)gl.C + (size_t)row * gl.ldc + (size_t)mb * gl.c_member_stride + col, v);
         } else if (EPI == kEpiBwd) {
-          T *out = (T *)gl.C + (size_t)row * gl.ldc + (size_t)mb * gl.c_member_stride + col;
-          const float h = Op<true>::load((const T *)gl.H + (size_t)row * gl.ldh +
-                                         (size_t)mb * gl.h_member_stride + col);
-          Op<true>::store(out, v * dcelu_from_h(h, gl.alpha) * gl.scale);
+          float h[8];
+          Vec8<true>::load((const T *)gl.H + (size_t)row * gl.ldh + (size_t)mb * gl.h_member_stride + col, h);
+#pragma unroll
+          for (int e = 0; e < 8; ++e) v[e] = v[e] * dcelu_from_h(h[e], gl.alpha) * gl.scale;
+          Vec8<true>::store((T *)gl.C + (size_t)row * gl.ldc + (size_t)mb * gl.c_member_stride + col, v);
         } else {
-          float *out = (float *)gl.C + (size_t)row * gl.ldc + col;
-          *out = v * gl.scale;
+#pragma unroll
+          for (int e = 0; e < 8; ++e) v[e] *= gl.scale;
+          Vec8<false>::store((float *)gl.C + (size_t)row * gl.ldc + col, v);
         }
       }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
   }
 }
@@ -438,38 +498,6 @@ void launch_gemm(int epi, bool bf16, GemmLaunch gl, int row_tiles, int max_n_out
 // row; a lane takes 8 consecutive inputs at a time (one 16-byte bfloat16 or
 // two 16-byte float32 accesses).  Hidden widths and the AEV length are
 // multiples of 8, so a lane's 8 inputs never straddle a member's slice.
-template <bool BF16> struct Vec8;
-template <> struct Vec8<true> {
-  static __device__ inline void load(const uint16_t *p, float v[8]) {
-    const uint4 u = *(const uint4 *)p;
-    const uint32_t w[4] = {u.x, u.y, u.z, u.w};
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      v[2 * q] = __uint_as_float(w[q] << 16);
-      v[2 * q + 1] = __uint_as_float(w[q] & 0xffff0000u);
-    }
-  }
-  static __device__ inline void store(uint16_t *p, const float v[8]) {
-    uint4 u;
-    u.x = bf16_bits_rne(v[0]) | (bf16_bits_rne(v[1]) << 16);
-    u.y = bf16_bits_rne(v[2]) | (bf16_bits_rne(v[3]) << 16);
-    u.z = bf16_bits_rne(v[4]) | (bf16_bits_rne(v[5]) << 16);
-    u.w = bf16_bits_rne(v[6]) | (bf16_bits_rne(v[7]) << 16);
-    *(uint4 *)p = u;
-  }
-};
-template <> struct Vec8<false> {
-  static __device__ inline void load(const float *p, float v[8]) {
-    const float4 a = *(const float4 *)p, b = *(const float4 *)(p + 4);
-    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
-    v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
-  }
-  static __device__ inline void store(float *p, const float v[8]) {
-    *(float4 *)p = make_float4(v[0], v[1], v[2], v[3]);
-    *(float4 *)(p + 4) = make_float4(v[4], v[5], v[6], v[7]);
-  }
-};
-
 template <bool BF16>
 __global__ void __launch_bounds__(256) k_energy(EnergyLaunch el, int rows) {
   typedef typename Op<BF16>::T T;

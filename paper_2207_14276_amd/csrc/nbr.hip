@@ -339,10 +339,160 @@ k_nbr_build(const float4 *__restrict__ pos, const int *__restrict__ sys_of,
   }
 }
 
-void launch_nbr_build(const float4 *pos, const int *sys_of, const SysDesc *sys,
+// The same lists, built one cell per workgroup: the atoms of the cell's
+// stencil of neighbour cells (with their lattice images) are staged in LDS,
+// in chunks, once for all atoms of the cell, instead of every atom walking
+// the stencil through global memory.  Candidates are taken in stencil order
+// (x offset outermost) and cell order, and each atom's entries in candidate
+// order, so a row is identical to k_nbr_build's; the distance test uses the
+// same arithmetic, (r_j - r_i) + image * L.
+constexpr int kCandChunk = 1024;  // candidates staged at a time
+constexpr int kHomeChunk = 256;   // atoms of the home cell handled at a time
+
+__global__ void __launch_bounds__(256)
+k_nbr_cell(const float4 *__restrict__ pos, const SysDesc *__restrict__ sys, int n_sys,
+           const int *__restrict__ cell_start, const int *__restrict__ cell_atoms, float rc_list,
+           int cap, int2 *__restrict__ nbr, int *__restrict__ nbr_cnt, int *__restrict__ status) {
+  __shared__ float4 cpos[kCandChunk];   // candidate r_j (w: j as int bits)
+  __shared__ int ccode[kCandChunk];     // candidate image code
+  __shared__ int st_cell[kWave], st_code[kWave], st_pre[kWave + 1];
+  __shared__ float4 hpos[kHomeChunk];
+  __shared__ int hidx[kHomeChunk], hcnt[kHomeChunk];
+  const int tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
+  const int cell = blockIdx.x;
+  // the system owning this cell: last s with cell_off <= cell
+  int lo = 0, hi = n_sys - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (sys[mid].cell_off <= cell) lo = mid; else hi = mid - 1;
+  }
+  const SysDesc &d = sys[lo];
+  if (!d.rebuild || cell >= d.cell_off + d.cell_cap) return;
+  const int hb = cell_start[cell], he = cell_start[cell + 1];
+  if (hb >= he) return;
+  const int local = cell - d.cell_off;
+  const int hc[3] = {local / (d.nc[1] * d.nc[2]), (local / d.nc[2]) % d.nc[1], local % d.nc[2]};
+  int k[3], n1[3];
+  for (int a = 0; a < 3; ++a) {
+    k[a] = d.periodic ? (int)ceilf(rc_list / d.edge[a]) : 1;
+    n1[a] = 2 * k[a] + 1;
+  }
+  const int nst = n1[0] * n1[1] * n1[2];
+  const float rc2 = rc_list * rc_list;
+  const int home_code = pack_image(0, 0, 0);
+
+  for (int hb0 = hb; hb0 < he; hb0 += kHomeChunk) {
+    const int nh = min(kHomeChunk, he - hb0);
+    for (int t = tid; t < nh; t += blockDim.x) {
+      const int i = cell_atoms[hb0 + t];
+      hidx[t] = i;
+      hpos[t] = pos[i];
+      hcnt[t] = 0;
+    }
+    for (int sc0 = 0; sc0 < nst; sc0 += kWave) {
+      __syncthreads();
+      if (wave == 0) {
+        // stencil cells sc0 .. sc0 + 63: cell index, image and atom count
+        const int e = sc0 + lane;
+        int cnt = 0, cidx = 0, code = 0;
+        if (e < nst) {
+          const int o[3] = {e / (n1[1] * n1[2]) - k[0], (e / n1[2]) % n1[1] - k[1], e % n1[2] - k[2]};
+          int w[3], sh[3];
+          bool ok = true;
+          for (int a = 0; a < 3; ++a) {
+            bool oka;
+            wrap_cell(hc[a] + o[a], d.nc[a], d.periodic, w[a], sh[a], oka);
+            ok = ok && oka;
+          }
+          if (ok) {
+            cidx = d.cell_off + (w[0] * d.nc[1] + w[1]) * d.nc[2] + w[2];
+            code = pack_image(sh[0], sh[1], sh[2]);
+            cnt = cell_start[cidx + 1] - cell_start[cidx];
+          }
+        }
+        // inclusive scan over the wave
+        int incl = cnt;
+        for (int off = 1; off < kWave; off <<= 1) {
+          const int v = __shfl_up(incl, off);
+          if (lane >= off) incl += v;
+        }
+        st_cell[lane] = cidx;
+        st_code[lane] = code;
+        st_pre[lane + 1] = incl;
+        if (lane == 0) st_pre[0] = 0;
+      }
+      __syncthreads();
+      const int total = st_pre[kWave];
+      for (int t0 = 0; t0 < total; t0 += kCandChunk) {
+        const int nc = min(kCandChunk, total - t0);
+        if (t0 > 0) __syncthreads();   // the previous chunk has been scanned
+        for (int u = tid; u < nc; u += blockDim.x) {
+          const int t = t0 + u;
+          int a = 0, b = kWave - 1;    // stencil entry holding candidate t
+          while (a < b) {
+            const int mid = (a + b + 1) >> 1;
+            if (st_pre[mid] <= t) a = mid; else b = mid - 1;
+          }
+          const int j = cell_atoms[cell_start[st_cell[a]] + (t - st_pre[a])];
+          float4 pj = pos[j];
+          pj.w = __int_as_float(j);
+          cpos[u] = pj;
+          ccode[u] = st_code[a];
+        }
+        __syncthreads();
+        for (int h = wave; h < nh; h += blockDim.x / kWave) {
+          const int i = hidx[h];
+          const float4 p = hpos[h];
+          int cnt = hcnt[h];
+          int2 *out = nbr + nbr_row(d, i, cap);
+          for (int b0 = 0; b0 < nc; b0 += kWave) {
+            const int u = b0 + lane;
+            bool inside = false;
+            int j = 0, code = 0;
+            if (u < nc) {
+              const float4 pj = cpos[u];
+              j = __float_as_int(pj.w);
+              code = ccode[u];
+              int ix, iy, iz;
+              unpack_image(code, ix, iy, iz);
+              const float dx = (pj.x - p.x) + (float)ix * d.L[0];
+              const float dy = (pj.y - p.y) + (float)iy * d.L[1];
+              const float dz = (pj.z - p.z) + (float)iz * d.L[2];
+              inside = dx * dx + dy * dy + dz * dz < rc2 && !(code == home_code && j == i);
+            }
+            const unsigned long long m = __ballot(inside);
+            const int at = cnt + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
+                                                                 __builtin_amdgcn_mbcnt_lo((unsigned)m, 0));
+            if (inside && at < cap) out[at] = make_int2(j - d.atom_off, code);
+            cnt += __popcll(m);
+          }
+          if (lane == 0) hcnt[h] = cnt;
+        }
+      }
+    }
+    __syncthreads();
+    for (int t = tid; t < nh; t += blockDim.x) {
+      const int i = hidx[t], cnt = hcnt[t];
+      nbr_cnt[d.state_off + (i - d.atom_off)] = cnt;
+      if (cnt > cap) atomicOr(status, kStatOverflow);
+      if (cnt > __hip_atomic_load(status + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+        atomicMax(status + 1, cnt);
+    }
+    __syncthreads();   // hidx / hcnt are reused by the next group of home atoms
+  }
+}
+
+void launch_nbr_build(const float4 *pos, const int *sys_of, const SysDesc *sys, int n_sys, int n_cells,
                       const int *cell_start, const int *cell_atoms, int N, float rc_list, int cap,
                       int2 *nbr, int *nbr_cnt, int *status, hipStream_t st) {
   if (N <= 0) return;
+  // staging a cell's stencil pays off once cells hold several atoms (dense
+  // boxes); sparse grids of small solutes are faster with a wave per atom
+  if (n_cells > 0 && N >= 8 * (long long)n_cells) {
+    k_nbr_cell<<<n_cells, 256, 0, st>>>(pos, sys, n_sys, cell_start, cell_atoms, rc_list, cap, nbr,
+                                        nbr_cnt, status);
+    return;
+  }
   k_nbr_build<<<(N + 3) / 4, 256, 0, st>>>(pos, sys_of, sys, cell_start, cell_atoms, N, rc_list,
                                            cap, nbr, nbr_cnt, status);
 }

@@ -44,6 +44,8 @@ def small_systems():
         "cluster24": synth.make_batch([synth.config0()]),
         "water8_small_box": synth.make_batch([synth.water_box(8, seed=5)]),
         "water2_tiny_box": synth.make_batch([synth.water_box(2, seed=6)]),
+        # one cell of ~4.5 A with 9 atoms: two images deep in every direction
+        "water3_tiny_box": synth.make_batch([synth.water_box(3, seed=7)]),
         "ragged16": synth.ragged_solutes(16, seed=12),
         "water667": synth.make_batch([synth.config1()]),
     }
