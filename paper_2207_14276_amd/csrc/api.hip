@@ -108,8 +108,13 @@ struct nnp_model {
   // workspace
   DevBuf pos, sys_of, atom_cell, atom_slot, cell_count, cell_start, cell_atoms, nbr, nbr_cnt;
   DevBuf block_counts, bucket_off, bucket_cnt, perm, row_of_atom, G, dG, e_atom, W_atom, partial;
-  DevBuf sysdesc, chunk_sys, chunk_begin, sys_chunk_off, status, state;
+  DevBuf sysdesc, chunk_sys, chunk_begin, sys_chunk_off, status, state, e_mem;
   std::vector<DevBuf> H, Gd;
+  // fused hidden-layer chain (bfloat16 models whose hidden widths allow it)
+  bool chain = false;
+  DevBuf chain_nets;                     // [member][species] ChainNet
+  ChainLaunch chain_proto{};             // strides and LDS layout, filled at creation
+  size_t chain_lds = 0;
   // host staging (pinned) for per-call descriptors
   void *stage = nullptr;
   size_t stage_bytes = 0;
@@ -162,7 +167,8 @@ extern "C" void nnp_destroy(nnp_model *m) {
                     &m->cell_start, &m->cell_atoms, &m->nbr, &m->nbr_cnt, &m->block_counts,
                     &m->bucket_off, &m->bucket_cnt, &m->perm, &m->row_of_atom, &m->G, &m->dG,
                     &m->e_atom, &m->W_atom, &m->partial, &m->sysdesc, &m->chunk_sys,
-                    &m->chunk_begin, &m->sys_chunk_off, &m->status, &m->state};
+                    &m->chunk_begin, &m->sys_chunk_off, &m->status, &m->state, &m->e_mem,
+                    &m->chain_nets};
   for (DevBuf *b : bufs) b->release();
   for (auto &b : m->H) b.release();
   for (auto &b : m->Gd) b.release();
@@ -298,6 +304,48 @@ static int create_impl(const nnp_model_desc *d, nnp_model *m) {
       }
     }
   }
+  // fused chain: bfloat16, 2..4 hidden layers after the first, widths that are
+  // multiples of 32 and at most 256, activation tiles within 64 KB of LDS
+  if (m->precision == NNP_BF16 && L >= 3 && L - 2 <= kChainMax) {
+    bool ok = true;
+    size_t lds = 0;
+    ChainLaunch &cp = m->chain_proto;
+    for (int l = 0; l + 1 < L; ++l) {
+      for (int s = 0; s < S; ++s) {
+        const int w = m->widths[s][l + 1];
+        ok = ok && w % 32 == 0 && w <= 256;
+      }
+      if (l <= kChainMax) {
+        cp.lds_off[l] = (int)lds;
+        cp.lds_ld[l] = m->ldH[l] + 8;
+        lds += (size_t)kChainRows * (m->ldH[l] + 8) * 2;
+      }
+    }
+    ok = ok && lds <= 64 * 1024;
+    if (ok) {
+      std::vector<ChainNet> nets((size_t)m->M * S);
+      for (int mb = 0; mb < m->M; ++mb)
+        for (int s = 0; s < S; ++s) {
+          ChainNet &n = nets[(size_t)mb * S + s];
+          memset(&n, 0, sizeof n);
+          for (int l = 1; l <= L - 2; ++l) {
+            LayerW &lw = m->layer(mb, s, l);
+            n.W[l - 1] = lw.Wb;
+            n.Wt[l - 1] = lw.Wtb;
+            n.b[l - 1] = lw.b;
+          }
+          LayerW &lo = m->layer(mb, s, L - 1);
+          n.w_out = lo.W;
+          HIP_TRY(hipMemcpy(&n.b_out, lo.b, sizeof(float), hipMemcpyDeviceToHost));
+          for (int l = 0; l <= L - 2; ++l) n.width[l] = m->widths[s][l + 1];
+        }
+      int rc = m->chain_nets.ensure(nets.size() * sizeof(ChainNet));
+      if (rc) return rc;
+      HIP_TRY(hipMemcpy(m->chain_nets.p, nets.data(), nets.size() * sizeof(ChainNet), hipMemcpyHostToDevice));
+      m->chain = true;
+      m->chain_lds = lds;
+    }
+  }
   HIP_TRY(hipEventCreateWithFlags(&m->stage_done, hipEventDisableTiming));
   int rc = m->status.ensure(2 * sizeof(int));
   if (rc) return rc;
@@ -352,6 +400,7 @@ static int for_each_ws(nnp_model *m, int64_t N, int S, int64_t C, int n_chunks, 
   ENS(m->G, rows * m->ldG * esz);
   ENS(m->dG, rows * m->aev.D * 4);
   ENS(m->e_atom, N * 4);
+  if (m->chain) ENS(m->e_mem, rows * m->M * 4);
   ENS(m->W_atom, N * 36);
   ENS(m->partial, (int64_t)n_chunks * 80 + 80);
   ENS(m->sysdesc, (int64_t)S * sizeof(SysDesc));
@@ -696,7 +745,9 @@ static int run(nnp_model *m, int n_sys, const int64_t *offs, const float *coords
     gl.n_members = M;
     gl.n_seg = 1;
   };
-  for (int l = 0; l + 1 < L; ++l) {
+  // with the fused chain only the first layer runs as a separate GEMM
+  const bool use_chain = m->chain && bf16;
+  for (int l = 0; l + 1 < (use_chain ? 2 : L); ++l) {
     GemmLaunch gl{};
     common(gl);
     gl.A = l == 0 ? m->G.p : m->H[l - 1].p;
@@ -717,7 +768,25 @@ static int run(nnp_model *m, int n_sys, const int64_t *offs, const float *coords
       }
     launch_gemm(kEpiFwd, bf16, gl, row_tiles, m->ldH[l], st);
   }
-  {
+  if (use_chain) {
+    ChainLaunch cl = m->chain_proto;
+    cl.H0 = (const uint16_t *)m->H[0].p;
+    cl.ldh = M * m->ldH[0];
+    cl.h_member_stride = m->ldH[0];
+    cl.D0 = (uint16_t *)m->Gd[0].p;
+    cl.ldd = M * m->ldH[0];
+    cl.d_member_stride = m->ldH[0];
+    cl.nets = m->chain_nets.as<ChainNet>();
+    cl.bucket_off = m->bucket_off.as<int>();
+    cl.n_groups = S;
+    cl.n_members = M;
+    cl.alpha = m->alpha;
+    cl.inv_m = 1.0f / (float)M;
+    cl.e_mem = m->e_mem.as<float>();
+    cl.perm = m->perm.as<int>();
+    cl.e_atom = m->e_atom.as<float>();
+    launch_chain(cl, L - 2, want_grad, rows, m->chain_lds, st);
+  } else {
     EnergyLaunch el{};
     el.Hin = L >= 2 ? m->H[L - 2].p : m->G.p;
     el.ldh = L >= 2 ? M * m->ldH[L - 2] : m->ldG;
@@ -745,7 +814,7 @@ static int run(nnp_model *m, int n_sys, const int64_t *offs, const float *coords
     launch_energy(el, bf16, rows, st);
   }
   if (want_grad) {
-    for (int l = L - 2; l >= 1; --l) {
+    for (int l = L - 2; l >= 1 && !use_chain; --l) {
       GemmLaunch gl{};
       common(gl);
       gl.A = m->Gd[l].p;

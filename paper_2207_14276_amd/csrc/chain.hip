@@ -1,0 +1,220 @@
+// Fused hidden-layer chain of the element networks (section "Neural Network
+// Potentials": one feed-forward network per element, atomic energies summed).
+//
+// After the first dense layer (a large GEMM over the AEV), the remaining
+// layers of a network are narrow (<= 256 wide): run as separate GEMMs their
+// activations make several round trips through HBM.  Here one workgroup
+// takes 32 rows of one species bucket for one ensemble member and runs the
+// rest of the network on chip:
+//   forward   h_l = CELU(h_{l-1} W_l^T + b_l) for the hidden layers l >= 1,
+//             E = h_last . w_out + b_out, d_last = w_out * CELU'(h_last) / M;
+//   backward  d_{l-1} = (d_l W_l) * CELU'(h_{l-1}) down to d_0,
+// keeping every h_l / d_l tile in LDS (bfloat16, rows padded by 8 elements)
+// and writing only d_0 (the input gradient the AEV-gradient GEMM needs) and
+// the member's energy per row.  The products use v_mfma_f32_16x16x32_bf16:
+// each wave owns every 4th 16-column block of a layer's output, and loads
+// that block's B fragments (weights, L2-resident) for the whole K before its
+// MFMAs.  Activations are rounded to bfloat16 exactly where the unfused path
+// stores them, so both paths give the same results.
+#include "internal.h"
+
+namespace nnp {
+
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float floatx4_t __attribute__((ext_vector_type(4)));
+
+__device__ inline uint16_t to_bf16(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__device__ inline float from_bf16(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+__device__ inline float celu_f(float z, float alpha) { return z > 0.f ? z : alpha * expm1f(z / alpha); }
+__device__ inline float dcelu_h(float h, float alpha) { return h > 0.f ? 1.f : 1.f + h / alpha; }
+
+// Sum over aligned groups of 16 lanes (DPP), result in every lane of the group.
+__device__ inline float sum16_dpp(float v) {
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, false));
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x4E, 0xF, 0xF, false));
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x141, 0xF, 0xF, false));
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x140, 0xF, 0xF, false));
+  return v;
+}
+
+// C[32 x N] = A[32 x K] (LDS, bfloat16, row stride lda) . B^T with B[N][K]
+// (global, bfloat16, row stride ldb); K a multiple of 32 (<= 256), N of 16.
+// For every 16-column block owned by this wave, epi(cb, acc0, acc1) gets the
+// accumulators of rows 0-15 and 16-31: lane l holds column 16 cb + l % 16,
+// rows 4 (l / 16) + j (j = 0..3) of each half.
+template <class Epi>
+__device__ inline void chain_gemm(const uint16_t *A, int lda, int K, const uint16_t *__restrict__ B, int ldb,
+                                  int N, int wave, int lane, Epi &&epi) {
+  const int l16 = lane & 15, kq = lane >> 4;
+  const int nkb = K / 32;
+  for (int cb = wave; cb < N / 16; cb += 4) {
+    uint4 bf[8];
+    const uint16_t *bp = B + (size_t)(cb * 16 + l16) * ldb + 8 * kq;
+#pragma unroll
+    for (int kb = 0; kb < 8; ++kb)
+      if (kb < nkb) bf[kb] = *(const uint4 *)(bp + kb * 32);
+    floatx4_t acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kb = 0; kb < 8; ++kb) {
+      if (kb < nkb) {
+        const uint4 a0 = *(const uint4 *)(A + l16 * lda + kb * 32 + 8 * kq);
+        const uint4 a1 = *(const uint4 *)(A + (16 + l16) * lda + kb * 32 + 8 * kq);
+        const bf16x8_t b = __builtin_bit_cast(bf16x8_t, bf[kb]);
+        acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, a0), b, acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, a1), b, acc1, 0, 0, 0);
+      }
+    }
+    epi(cb, acc0, acc1);
+  }
+}
+
+template <int NL, bool GRAD>
+__global__ void __launch_bounds__(256) k_chain(ChainLaunch cl) {
+  extern __shared__ uint4 chain_lds[];
+  __shared__ float e_red[4][kChainRows];
+  const int tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
+  const int l16 = lane & 15, kq = lane >> 4;
+  // consecutive blocks are the members of one row tile (they share its h0 rows in L2)
+  const int mb = blockIdx.x % cl.n_members;
+  const int r0 = (blockIdx.x / cl.n_members) * kChainRows;
+  int s = -1;
+  for (int q = 0; q < cl.n_groups; ++q)
+    if (r0 >= cl.bucket_off[q] && r0 < cl.bucket_off[q + 1]) s = q;
+  if (s < 0) return;
+  const ChainNet &net = cl.nets[mb * cl.n_groups + s];
+  uint16_t *act[NL + 1];
+#pragma unroll
+  for (int l = 0; l <= NL; ++l) act[l] = (uint16_t *)((char *)chain_lds + cl.lds_off[l]);
+
+  // h_0 tile (this member's slice of the first layer's output) into LDS
+  {
+    const int w0 = net.width[0], cpr = w0 / 8;
+    const uint16_t *src = cl.H0 + (size_t)r0 * cl.ldh + (size_t)mb * cl.h_member_stride;
+    for (int idx = tid; idx < kChainRows * cpr; idx += blockDim.x) {
+      const int row = idx / cpr, ch = idx % cpr;
+      *(uint4 *)(act[0] + row * cl.lds_ld[0] + ch * 8) = *(const uint4 *)(src + (size_t)row * cl.ldh + ch * 8);
+    }
+  }
+  __syncthreads();
+
+  float ep[2][4] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};  // energy partials (last layer)
+#pragma unroll
+  for (int l = 1; l <= NL; ++l) {
+    const int K = net.width[l - 1], N = net.width[l];
+    const float *bias = net.b[l - 1];
+    uint16_t *out = act[l];
+    const int ldo = cl.lds_ld[l];
+    if (l < NL) {
+      chain_gemm(act[l - 1], cl.lds_ld[l - 1], K, net.W[l - 1], K, N, wave, lane,
+                 [&](int cb, floatx4_t a0, floatx4_t a1) {
+                   const int col = cb * 16 + l16;
+                   const float bc = bias[col];
+#pragma unroll
+                   for (int j = 0; j < 4; ++j) {
+                     out[(4 * kq + j) * ldo + col] = to_bf16(celu_f(a0[j] + bc, cl.alpha));
+                     out[(16 + 4 * kq + j) * ldo + col] = to_bf16(celu_f(a1[j] + bc, cl.alpha));
+                   }
+                 });
+    } else {
+      // last hidden layer: energy partials and d_last = w_out CELU'(h) / M
+      chain_gemm(act[l - 1], cl.lds_ld[l - 1], K, net.W[l - 1], K, N, wave, lane,
+                 [&](int cb, floatx4_t a0, floatx4_t a1) {
+                   const int col = cb * 16 + l16;
+                   const float bc = bias[col], wo = net.w_out[col];
+#pragma unroll
+                   for (int j = 0; j < 4; ++j) {
+                     const float h0 = from_bf16(to_bf16(celu_f(a0[j] + bc, cl.alpha)));
+                     const float h1 = from_bf16(to_bf16(celu_f(a1[j] + bc, cl.alpha)));
+                     ep[0][j] += h0 * wo;
+                     ep[1][j] += h1 * wo;
+                     if (GRAD) {
+                       out[(4 * kq + j) * ldo + col] = to_bf16(wo * dcelu_h(h0, cl.alpha) * cl.inv_m);
+                       out[(16 + 4 * kq + j) * ldo + col] = to_bf16(wo * dcelu_h(h1, cl.alpha) * cl.inv_m);
+                     }
+                   }
+                 });
+    }
+    __syncthreads();
+  }
+
+  // the member's energy of each row: reduce over columns (lanes, then waves)
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const float v = sum16_dpp(ep[h][j]);
+      if (l16 == 0) e_red[wave][16 * h + 4 * kq + j] = v;
+    }
+  __syncthreads();
+  if (tid < kChainRows)
+    cl.e_mem[(size_t)(r0 + tid) * cl.n_members + mb] =
+        e_red[0][tid] + e_red[1][tid] + e_red[2][tid] + e_red[3][tid] + net.b_out;
+  if (!GRAD) return;
+
+  // backward: d_{l-1} = (d_l W_l) * CELU'(h_{l-1}), in place over h_{l-1}
+#pragma unroll
+  for (int l = NL; l >= 1; --l) {
+    const int K = net.width[l], N = net.width[l - 1];
+    uint16_t *hd = act[l - 1];
+    const int ldo = cl.lds_ld[l - 1];
+    chain_gemm(act[l], cl.lds_ld[l], K, net.Wt[l - 1], K, N, wave, lane,
+               [&](int cb, floatx4_t a0, floatx4_t a1) {
+                 const int col = cb * 16 + l16;
+#pragma unroll
+                 for (int j = 0; j < 4; ++j) {
+                   uint16_t *p0 = hd + (4 * kq + j) * ldo + col;
+                   uint16_t *p1 = hd + (16 + 4 * kq + j) * ldo + col;
+                   *p0 = to_bf16(a0[j] * dcelu_h(from_bf16(*p0), cl.alpha));
+                   *p1 = to_bf16(a1[j] * dcelu_h(from_bf16(*p1), cl.alpha));
+                 }
+               });
+    __syncthreads();
+  }
+
+  // d_0 tile to global (16-byte stores)
+  {
+    const int w0 = net.width[0], cpr = w0 / 8;
+    uint16_t *dst = cl.D0 + (size_t)r0 * cl.ldd + (size_t)mb * cl.d_member_stride;
+    for (int idx = tid; idx < kChainRows * cpr; idx += blockDim.x) {
+      const int row = idx / cpr, ch = idx % cpr;
+      *(uint4 *)(dst + (size_t)row * cl.ldd + ch * 8) = *(const uint4 *)(act[0] + row * cl.lds_ld[0] + ch * 8);
+    }
+  }
+}
+
+// Atomic energies: mean over the members' energies of each row.  Rows past
+// the last species bucket carry no atom (and no permutation entry).
+__global__ void k_chain_mean(const float *__restrict__ e_mem, int M, const int *__restrict__ perm,
+                             const int *__restrict__ bucket_off, int n_groups, int rows, float inv_m,
+                             float *__restrict__ e_atom) {
+  const int row = blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= rows || row >= bucket_off[n_groups]) return;
+  const int atom = perm[row];
+  if (atom < 0) return;
+  float e = 0.f;
+  for (int m = 0; m < M; ++m) e += e_mem[(size_t)row * M + m];
+  e_atom[atom] = e * inv_m;
+}
+
+void launch_chain(const ChainLaunch &cl, int n_hidden, bool grad, int rows, size_t lds_bytes, hipStream_t st) {
+  const unsigned blocks = (unsigned)(rows / kChainRows * cl.n_members);
+  if (blocks == 0) return;
+  if (n_hidden == 1) {
+    if (grad) k_chain<1, true><<<blocks, 256, lds_bytes, st>>>(cl);
+    else k_chain<1, false><<<blocks, 256, lds_bytes, st>>>(cl);
+  } else if (n_hidden == 2) {
+    if (grad) k_chain<2, true><<<blocks, 256, lds_bytes, st>>>(cl);
+    else k_chain<2, false><<<blocks, 256, lds_bytes, st>>>(cl);
+  } else {
+    if (grad) k_chain<3, true><<<blocks, 256, lds_bytes, st>>>(cl);
+    else k_chain<3, false><<<blocks, 256, lds_bytes, st>>>(cl);
+  }
+  k_chain_mean<<<(rows + 255) / 256, 256, 0, st>>>(cl.e_mem, cl.n_members, cl.perm, cl.bucket_off, cl.n_groups,
+                                                    rows, cl.inv_m, cl.e_atom);
+}
+
+}  // namespace nnp

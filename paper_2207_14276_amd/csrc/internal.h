@@ -112,6 +112,30 @@ struct GemmLaunch {
 
 enum { kEpiFwd = 0, kEpiBwd = 1, kEpiOut = 2 };
 
+// Fused hidden-layer chain (bfloat16 models): layers 1 .. L-2 and the output
+// layer of one (member, species) network, forward and input gradient.
+constexpr int kChainRows = 32;   // rows per workgroup
+constexpr int kChainMax = 3;     // hidden layers after the first, at most
+struct ChainNet {
+  const uint16_t *W[kChainMax];   // layer l: bfloat16 [width[l]][width[l-1]]
+  const uint16_t *Wt[kChainMax];  // its transpose [width[l-1]][width[l]]
+  const float *b[kChainMax];      // [width[l]]
+  const float *w_out;             // output layer weights [width[NL]]
+  float b_out;                    // output layer bias
+  int width[kChainMax + 1];       // width of h_0 .. h_NL
+};
+struct ChainLaunch {
+  const uint16_t *H0; int ldh; int h_member_stride;  // h_0 (first layer output)
+  uint16_t *D0; int ldd; int d_member_stride;        // d_0 = dE/dz_0 out
+  const ChainNet *nets;                               // device [member][species]
+  const int *bucket_off; int n_groups; int n_members;
+  int lds_off[kChainMax + 1];                         // byte offset of the h_l tile
+  int lds_ld[kChainMax + 1];                          // its row stride (elements)
+  float alpha, inv_m;
+  float *e_mem;                                       // [rows][members] energies
+  const int *perm; float *e_atom;
+};
+
 struct EnergyLaunch {
   const void *Hin; int ldh; int h_member_stride;  // input of the last layer
   void *Gout; int ldg; int g_member_stride;       // dE/d(input), scaled by inv_m
@@ -154,6 +178,7 @@ void launch_aev_bwd(const float4 *pos, const int *sys_of, const SysDesc *sys, co
                     int ldg, int N, const AevConst &c, float *F, float *W_atom, hipStream_t st);
 void launch_gemm(int epi, bool bf16, GemmLaunch gl, int row_tiles, int max_n_out, hipStream_t st);
 void launch_energy(const EnergyLaunch &el, bool bf16, int rows, hipStream_t st);
+void launch_chain(const ChainLaunch &cl, int n_hidden, bool grad, int rows, size_t lds_bytes, hipStream_t st);
 void launch_fill(float *p, size_t n, float v, hipStream_t st);
 void launch_fill_i32(int *p, size_t n, int v, hipStream_t st);
 void launch_reduce(const float *e_atom, const float *W_atom, const SysDesc *sys, int n_sys,
