@@ -12,9 +12,9 @@
 // keeping every h_l / d_l tile in LDS (bfloat16, rows padded by 8 elements)
 // and writing only d_0 (the input gradient the AEV-gradient GEMM needs) and
 // the member's energy per row.  The products use v_mfma_f32_16x16x32_bf16:
-// each wave owns every 4th 16-column block of a layer's output, and loads
-// that block's B fragments (weights, L2-resident) for the whole K before its
-// MFMAs.  Activations are rounded to bfloat16 exactly where the unfused path
+// each wave owns every 4th 16-column block of a layer's output; it reads
+// the A fragments of a K step from LDS once for all its blocks and loads the
+// next step's B fragments (weights, L2-resident) during the current MFMAs.  Activations are rounded to bfloat16 exactly where the unfused path
 // stores them, so both paths give the same results.
 #include "internal.h"
 
@@ -50,26 +50,44 @@ template <class Epi>
 __device__ inline void chain_gemm(const uint16_t *A, int lda, int K, const uint16_t *__restrict__ B, int ldb,
                                   int N, int wave, int lane, Epi &&epi) {
   const int l16 = lane & 15, kq = lane >> 4;
-  const int nkb = K / 32;
-  for (int cb = wave; cb < N / 16; cb += 4) {
-    uint4 bf[8];
-    const uint16_t *bp = B + (size_t)(cb * 16 + l16) * ldb + 8 * kq;
+  const int nkb = K / 32, ncb = N / 16;
+  // this wave's blocks: wave + 4 q, q < nq (N <= 256: at most 4).  K-step
+  // outer, blocks inner: the A fragments of a K step are read from LDS once
+  // for all of the wave's blocks, and the next step's B fragments are loaded
+  // while the current step's MFMAs run.
+  const int nq = ncb > wave ? (ncb - wave + 3) / 4 : 0;
+  if (nq == 0) return;
+  floatx4_t acc[4][2];
 #pragma unroll
-    for (int kb = 0; kb < 8; ++kb)
-      if (kb < nkb) bf[kb] = *(const uint4 *)(bp + kb * 32);
-    floatx4_t acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+  for (int q = 0; q < 4; ++q) acc[q][0] = acc[q][1] = floatx4_t{0.f, 0.f, 0.f, 0.f};
+  const uint16_t *bp = B + (size_t)(wave * 16 + l16) * ldb + 8 * kq;
+  const size_t bstep = (size_t)64 * ldb;          // 4 blocks of 16 rows
+  uint4 bc[4], bn[4];
 #pragma unroll
-    for (int kb = 0; kb < 8; ++kb) {
-      if (kb < nkb) {
-        const uint4 a0 = *(const uint4 *)(A + l16 * lda + kb * 32 + 8 * kq);
-        const uint4 a1 = *(const uint4 *)(A + (16 + l16) * lda + kb * 32 + 8 * kq);
-        const bf16x8_t b = __builtin_bit_cast(bf16x8_t, bf[kb]);
-        acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, a0), b, acc0, 0, 0, 0);
-        acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, a1), b, acc1, 0, 0, 0);
+  for (int q = 0; q < 4; ++q)
+    if (q < nq) bc[q] = *(const uint4 *)(bp + q * bstep);
+  for (int kb = 0; kb < nkb; ++kb) {
+    if (kb + 1 < nkb) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (q < nq) bn[q] = *(const uint4 *)(bp + q * bstep + (kb + 1) * 32);
+    }
+    const bf16x8_t a0 = __builtin_bit_cast(bf16x8_t, *(const uint4 *)(A + l16 * lda + kb * 32 + 8 * kq));
+    const bf16x8_t a1 = __builtin_bit_cast(bf16x8_t, *(const uint4 *)(A + (16 + l16) * lda + kb * 32 + 8 * kq));
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (q < nq) {
+        const bf16x8_t b = __builtin_bit_cast(bf16x8_t, bc[q]);
+        acc[q][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b, acc[q][0], 0, 0, 0);
+        acc[q][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b, acc[q][1], 0, 0, 0);
       }
     }
-    epi(cb, acc0, acc1);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) bc[q] = bn[q];
   }
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+    if (q < nq) epi(wave + 4 * q, acc[q][0], acc[q][1]);
 }
 
 template <int NL, bool GRAD>
@@ -78,9 +96,13 @@ __global__ void __launch_bounds__(256) k_chain(ChainLaunch cl) {
   __shared__ float e_red[4][kChainRows];
   const int tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
   const int l16 = lane & 15, kq = lane >> 4;
-  // consecutive blocks are the members of one row tile (they share its h0 rows in L2)
-  const int mb = blockIdx.x % cl.n_members;
-  const int r0 = (blockIdx.x / cl.n_members) * kChainRows;
+  // member-major logical order, contiguous per XCD: an XCD works through the
+  // row tiles of one or two (member, species) networks at a time, whose
+  // weights then stay in its L2
+  const int n_rt = gridDim.x / cl.n_members;
+  const int lb = xcd_logical(blockIdx.x, gridDim.x);
+  const int mb = lb / n_rt;
+  const int r0 = (lb % n_rt) * kChainRows;
   int s = -1;
   for (int q = 0; q < cl.n_groups; ++q)
     if (r0 >= cl.bucket_off[q] && r0 < cl.bucket_off[q + 1]) s = q;

@@ -27,6 +27,16 @@ constexpr int kNShfZ = 8;
 constexpr int kAngBlock = kNShfAng * kNShfZ;  // 32 features per species pair
 constexpr int kTileM = 128;                   // MLP row tile; buckets pad to it
 
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own
+// L2): logical block of dispatch slot bid, so that each XCD walks a
+// contiguous range of logical blocks.
+__device__ inline int xcd_logical(int bid, int nb) {
+  constexpr int X = 8;
+  const int q = nb / X, r = nb % X;
+  const int x = bid % X, k = bid / X;
+  return x * q + min(x, r) + k;
+}
+
 // Device status word bits.
 enum : int { kStatOverflow = 1, kStatBadSpecies = 2 };
 

@@ -49,14 +49,6 @@ __device__ inline float celu(float z, float alpha) { return z > 0.f ? z : alpha 
 // CELU'(z) from h = CELU(z): 1 for h > 0, else exp(z / alpha) = 1 + h / alpha.
 __device__ inline float dcelu_from_h(float h, float alpha) { return h > 0.f ? 1.f : 1.f + h / alpha; }
 
-// Workgroups are dispatched round-robin over the 8 XCDs; map them so that
-// each XCD walks a contiguous range of logical block numbers.
-__device__ inline int xcd_logical(int bid, int nb) {
-  constexpr int X = 8;
-  const int q = nb / X, r = nb % X;
-  const int x = bid % X, k = bid / X;
-  return x * q + min(x, r) + k;
-}
 
 template <int EPI, bool BF16, int TN>
 __global__ void __launch_bounds__(256) k_gemm(GemmLaunch gl) {

@@ -159,6 +159,23 @@ def test_ensemble_mean(oracle_lib):
                              FP32_E_ATOM, FP32_F, f"fp32 ensemble3 {name}")
 
 
+@pytest.mark.parametrize("hidden", [(72, 40), (96, 64), (128, 96, 64, 32)],
+                         ids=["unfused-widths-72-40", "chain-1-layer", "chain-3-layers"])
+def test_bf16_network_shapes(oracle_lib, hidden):
+    """bfloat16 networks of other shapes, 2 members: hidden widths that are
+    not multiples of 32 run the layer-by-layer GEMMs (register-staged tiles,
+    element output layer); the others run the fused hidden-layer chain with
+    one and with three layers after the first."""
+    from paper_2207_14276_amd import NNPModel
+    spec = synth.make_model(11, n_ensemble=2, hidden=[hidden] * 7)
+    m = NNPModel(spec, "bf16")
+    om = oracle_lib.OracleModel(spec)
+    for name in ("cluster24", "water8_small_box", "ragged16"):
+        b = SYSTEMS[name]
+        _check_energy_forces(m, oracle_lib, om, b, list(range(b.n_systems)), None,
+                             BF16_E_PER_ATOM, BF16_F, f"bf16 {hidden} {name}")
+
+
 def test_linear_readout_model(oracle_lib):
     """Networks without hidden layers: energy linear in the AEV, so energy
     and force errors come from the AEV and its gradient alone."""
