@@ -296,6 +296,26 @@ int nnp_sched_complete(nnp_sched *sched, int64_t id, double now, int *finished);
 int nnp_sched_job(nnp_sched *sched, int64_t id, double *times, int64_t *slot, int32_t *steps_done);
 int nnp_sched_info(nnp_sched *sched, int64_t *info);
 
+/* Tile-shape tuning for a representative batch (section "Massive Parallelism
+ * within Tinker-HP" reports the kernel time split that makes these choices
+ * matter).  Runs the batch (inputs as for nnp_energy_forces, energies and
+ * forces computed into the call's own scratch) once per candidate round and
+ * keeps, for every tunable launch ("site"), the fastest candidate measured
+ * with HIP events on `stream`:
+ *   site 0, 1        AEV forward / backward: waves per workgroup 1, 2 or 4
+ *                    (candidates whose LDS does not fit are skipped);
+ *   site 2 + l       dense layer l forward GEMM: column-tile width 64 or 128;
+ *   site 10 + l      dense layer l input-gradient GEMM: width 64 or 128;
+ *   site 18          the dE/dG GEMM: width 64 or 128.
+ * The choices stay with the model for all later calls (no call changes any
+ * result: tile shapes change no per-element arithmetic order); sites that did
+ * not run keep their default (0).  Waits for the stream; allocates. */
+int nnp_autotune(nnp_model *model, int n_systems, const int64_t *batch_offsets, const float *coords,
+                 const int32_t *species, const float *box, void *stream);
+/* Copies up to n tuned site values (0 = default shape) into values; returns
+ * the number of sites (19). */
+int nnp_tuning(const nnp_model *model, int *values, int n);
+
 /* Waits for `stream` and returns the device flags raised since the last
  * nnp_status call (NNP_ECAPACITY, NNP_ESPECIES) or NNP_OK; clears them.
  * *max_neighbors (nullable) receives the largest neighbour count seen. */

@@ -69,6 +69,8 @@ def _load():
         lib.orc_net_energy.argtypes = [C.POINTER(_Model), C.c_int, C.c_int, dp, dp]
         lib.orc_net_energy.restype = C.c_double
         lib.orc_threads.restype = C.c_int
+        lib.orc_set_threads.argtypes = [C.c_int]
+        lib.orc_set_threads.restype = C.c_int
         _lib = lib
     return _lib
 
@@ -113,6 +115,11 @@ class OracleModel:
 
 def threads() -> int:
     return int(_load().orc_threads())
+
+
+def set_threads(n: int) -> int:
+    """Threads for later calls (timing only); returns the previous count."""
+    return int(_load().orc_set_threads(int(n)))
 
 
 def _sys_arrays(coords, species, box):

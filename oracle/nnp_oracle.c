@@ -83,6 +83,18 @@ static int orc_omp_threads(void) {
 
 int orc_threads(void) { return orc_omp_threads(); }
 
+/* Threads used by later calls (n >= 1); returns the previous count.  Only
+ * the timing of the baseline depends on it, never a result. */
+int orc_set_threads(int n) {
+  const int prev = orc_omp_threads();
+#ifdef _OPENMP
+  if (n >= 1) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+  return prev;
+}
+
 int orc_aev_dim(const orc_aev_params *p) {
   int s = p->n_species;
   return s * p->n_shf_rad + (s * (s + 1) / 2) * p->n_shf_ang * p->n_shf_z;

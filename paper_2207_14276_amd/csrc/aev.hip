@@ -741,9 +741,12 @@ k_aev_bwd(const float4 *__restrict__ pos, const int *__restrict__ sys_of,
   }
 }
 
+// Waves per workgroup: the preference (1, 2 or 4) when its LDS fits in
+// 64 KB, else the most that fit.
 template <bool BWD>
-static int waves_for_cap(int cap) {
-  size_t per = wave_lds_bytes<BWD>(cap);
+static int waves_for_cap(int cap, int pref) {
+  const size_t per = wave_lds_bytes<BWD>(cap);
+  if ((pref == 1 || pref == 2 || pref == 4) && per * pref <= 64 * 1024) return pref;
   if (per * 4 <= 64 * 1024) return 4;
   if (per * 2 <= 64 * 1024) return 2;
   return 1;
@@ -752,8 +755,8 @@ static int waves_for_cap(int cap) {
 template <bool BF16>
 static void aev_fwd_t(const float4 *pos, const int *sys_of, const SysDesc *sys, const int2 *nbr,
                       const int *nbr_cnt, int cap, const int *row_of_atom, void *G, int ldg, int N,
-                      const AevConst &c, hipStream_t st) {
-  int wpb = waves_for_cap<false>(cap);
+                      const AevConst &c, int wpb_pref, hipStream_t st) {
+  int wpb = waves_for_cap<false>(cap, wpb_pref);
   size_t lds = wave_lds_bytes<false>(cap) * wpb;
   unsigned grid = (unsigned)((N + wpb - 1) / wpb);
   if (wpb == 4)
@@ -766,17 +769,17 @@ static void aev_fwd_t(const float4 *pos, const int *sys_of, const SysDesc *sys, 
 
 void launch_aev_fwd(const float4 *pos, const int *sys_of, const SysDesc *sys, const int2 *nbr,
                     const int *nbr_cnt, int cap, const int *row_of_atom, void *G, bool g_bf16,
-                    int ldg, int N, const AevConst &c, hipStream_t st) {
+                    int ldg, int N, const AevConst &c, int wpb_pref, hipStream_t st) {
   if (N <= 0) return;
-  if (g_bf16) aev_fwd_t<true>(pos, sys_of, sys, nbr, nbr_cnt, cap, row_of_atom, G, ldg, N, c, st);
-  else aev_fwd_t<false>(pos, sys_of, sys, nbr, nbr_cnt, cap, row_of_atom, G, ldg, N, c, st);
+  if (g_bf16) aev_fwd_t<true>(pos, sys_of, sys, nbr, nbr_cnt, cap, row_of_atom, G, ldg, N, c, wpb_pref, st);
+  else aev_fwd_t<false>(pos, sys_of, sys, nbr, nbr_cnt, cap, row_of_atom, G, ldg, N, c, wpb_pref, st);
 }
 
 void launch_aev_bwd(const float4 *pos, const int *sys_of, const SysDesc *sys, const int2 *nbr,
                     const int *nbr_cnt, int cap, const int *row_of_atom, const float *dG, int ldg,
-                    int N, const AevConst &c, float *F, float *W_atom, hipStream_t st) {
+                    int N, const AevConst &c, float *F, float *W_atom, int wpb_pref, hipStream_t st) {
   if (N <= 0) return;
-  int wpb = waves_for_cap<true>(cap);
+  int wpb = waves_for_cap<true>(cap, wpb_pref);
   size_t lds = wave_lds_bytes<true>(cap) * wpb;
   unsigned grid = (unsigned)((N + wpb - 1) / wpb);
   if (wpb == 4)

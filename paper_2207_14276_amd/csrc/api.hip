@@ -72,6 +72,10 @@ struct DevBuf {
 };
 
 constexpr int kStages = 8;
+// Tunable launch shapes ("sites"): waves per workgroup of the AEV forward and
+// backward kernels, column-tile width of each dense-layer GEMM.
+enum { kSiteAevFwd = 0, kSiteAevBwd = 1, kSiteGemmFwd = 2, kSiteGemmBwd = 10, kSiteGemmOut = 18,
+       kTuneSites = 19 };
 constexpr int kMaxTimedCalls = 4096;  // timed calls held between two reads
 const char *kStageNames[kStages] = {"ingest", "cells", "neighbours", "buckets",
                                     "aev_fwd", "mlp", "aev_bwd", "reduce"};
@@ -120,6 +124,11 @@ struct nnp_model {
   size_t stage_bytes = 0;
   hipEvent_t stage_done = nullptr;
   bool stage_pending = false;
+  // tuned launch shapes (0: default) and the per-site events of a tuning run
+  int tune_val[kTuneSites] = {};
+  bool tuning = false;
+  bool tune_hit[kTuneSites] = {};
+  hipEvent_t tune_ev[kTuneSites][2] = {};
   // timing: one set of stage-boundary events per timed call, kept until read
   bool timing = false;
   std::vector<std::array<hipEvent_t, kStages + 1>> evsets;
@@ -177,6 +186,9 @@ extern "C" void nnp_destroy(nnp_model *m) {
   for (auto &set : m->evsets)
     for (auto &e : set)
       if (e) (void)hipEventDestroy(e);
+  for (auto &pair : m->tune_ev)
+    for (auto &e : pair)
+      if (e) (void)hipEventDestroy(e);
   delete m;
 }
 
@@ -214,6 +226,7 @@ static int create_impl(const nnp_model_desc *d, nnp_model *m) {
   c.D = c.rad_len + S * (S + 1) / 2 * kAngBlock;
   const int L = d->n_layers[0];
   if (L < 1) return fail(NNP_EINVAL, "n_layers must be >= 1");
+  if (L > 9) return fail(NNP_EUNSUPPORTED, "at most 9 layers per network");
   for (int s = 0; s < S; ++s)
     if (d->n_layers[s] != L)
       return fail(NNP_EUNSUPPORTED, "all species must have the same number of layers");
@@ -685,6 +698,17 @@ static int run(nnp_model *m, int n_sys, const int64_t *offs, const float *coords
   auto mark = [&]() {
     if (ev) (void)hipEventRecord(ev[stage++], st);
   };
+  // per-site events while tuning (every site launches at most once per call)
+  const bool tuning = m->tuning && mode == kFull;
+  auto site_begin = [&](int site) {
+    if (tuning) {
+      (void)hipEventRecord(m->tune_ev[site][0], st);
+      m->tune_hit[site] = true;
+    }
+  };
+  auto site_end = [&](int site) {
+    if (tuning) (void)hipEventRecord(m->tune_ev[site][1], st);
+  };
   mark();
   SysDesc *dsys = m->sysdesc.as<SysDesc>();
   int *status = m->status.as<int>();
@@ -723,13 +747,15 @@ static int run(nnp_model *m, int n_sys, const int64_t *offs, const float *coords
   if (mode == kAev) {
     // float32 AEV into the (float32) dE/dG buffer, then back to atom order
     launch_aev_fwd(pos, m->sys_of.as<int>(), dsys, pool_nbr, pool_cnt, cap,
-                   m->row_of_atom.as<int>(), m->dG.p, false, D, N, m->aev, st);
+                   m->row_of_atom.as<int>(), m->dG.p, false, D, N, m->aev, 0, st);
     launch_gather_rows(m->dG.as<float>(), D, m->row_of_atom.as<int>(), N, D, o.aev, st);
     HIP_TRY(hipGetLastError());
     return NNP_OK;
   }
+  site_begin(kSiteAevFwd);
   launch_aev_fwd(pos, m->sys_of.as<int>(), dsys, pool_nbr, pool_cnt, cap,
-                 m->row_of_atom.as<int>(), m->G.p, bf16, m->ldG, N, m->aev, st);
+                 m->row_of_atom.as<int>(), m->G.p, bf16, m->ldG, N, m->aev, m->tune_val[kSiteAevFwd], st);
+  site_end(kSiteAevFwd);
   mark();
 
   // element networks: forward, output layer, backward to dE/dG; every launch
@@ -766,7 +792,9 @@ static int run(nnp_model *m, int n_sys, const int64_t *offs, const float *coords
         g.K = lw.n_in;
         if (l == 0 && bf16) g.K = g.ldb = m->ldG;  // zero-padded columns on both sides
       }
-    launch_gemm(kEpiFwd, bf16, gl, row_tiles, m->ldH[l], st);
+    site_begin(kSiteGemmFwd + l);
+    launch_gemm(kEpiFwd, bf16, gl, row_tiles, m->ldH[l], m->tune_val[kSiteGemmFwd + l], st);
+    site_end(kSiteGemmFwd + l);
   }
   if (use_chain) {
     ChainLaunch cl = m->chain_proto;
@@ -834,7 +862,9 @@ static int run(nnp_model *m, int n_sys, const int64_t *offs, const float *coords
           g.n_out = lw.n_in;
           g.K = lw.n_out;
         }
-      launch_gemm(kEpiBwd, bf16, gl, row_tiles, m->ldH[l - 1], st);
+      site_begin(kSiteGemmBwd + l);
+      launch_gemm(kEpiBwd, bf16, gl, row_tiles, m->ldH[l - 1], m->tune_val[kSiteGemmBwd + l], st);
+      site_end(kSiteGemmBwd + l);
     }
     if (L >= 2) {
       // dE/dG = sum over members of delta_0^m W_0^m: members are K segments
@@ -853,14 +883,18 @@ static int run(nnp_model *m, int n_sys, const int64_t *offs, const float *coords
         g.n_out = D;
         g.K = m->widths[s][1];
       }
-      launch_gemm(kEpiOut, bf16, gl, row_tiles, D, st);
+      site_begin(kSiteGemmOut);
+      launch_gemm(kEpiOut, bf16, gl, row_tiles, D, m->tune_val[kSiteGemmOut], st);
+      site_end(kSiteGemmOut);
     }
   }
   mark();
   if (want_grad) {
+    site_begin(kSiteAevBwd);
     launch_aev_bwd(pos, m->sys_of.as<int>(), dsys, pool_nbr, pool_cnt, cap,
                    m->row_of_atom.as<int>(), m->dG.as<float>(), D, N, m->aev, o.forces,
-                   m->W_atom.as<float>(), st);
+                   m->W_atom.as<float>(), m->tune_val[kSiteAevBwd], st);
+    site_end(kSiteAevBwd);
   }
   mark();
   launch_reduce(m->e_atom.as<float>(), want_grad ? m->W_atom.as<float>() : nullptr, dsys, n_sys,
@@ -902,6 +936,75 @@ extern "C" int nnp_debug_neighbors(nnp_model *m, int n_systems, const int64_t *o
   o.nb_entries = entries;
   o.nb_cap = capacity;
   return run(m, n_systems, offs, coords, species, box, o, (hipStream_t)stream, kNbr);
+}
+
+extern "C" int nnp_autotune(nnp_model *m, int n_systems, const int64_t *offs, const float *coords,
+                            const int32_t *species, const float *box, void *stream) {
+  if (!m) return fail(NNP_EINVAL, "null model");
+  if (n_systems < 1 || !offs) return fail(NNP_EINVAL, "bad batch");
+  HIP_TRY(hipSetDevice(m->device));
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t N = offs[n_systems];
+  if (N < 1) return fail(NNP_EINVAL, "empty batch");
+  for (auto &pair : m->tune_ev)
+    for (auto &e : pair)
+      if (!e) HIP_TRY(hipEventCreate(&e));
+  double *energy = nullptr;
+  float *forces = nullptr;
+  if (hipMalloc(&energy, sizeof(double) * n_systems) != hipSuccess ||
+      hipMalloc(&forces, sizeof(float) * 3 * (size_t)N) != hipSuccess) {
+    (void)hipGetLastError();
+    if (energy) (void)hipFree(energy);
+    return fail(NNP_ENOMEM, "tuning outputs");
+  }
+  CallOut o;
+  o.energy = energy;
+  o.forces = forces;
+  // candidates: round r sets every GEMM site to kTn[r] and both AEV sites to kWpb[r]
+  constexpr int kRounds = 3, kReps = 3;
+  const int kTn[kRounds] = {64, 128, 64}, kWpb[kRounds] = {1, 2, 4};
+  double t[kTuneSites][kRounds] = {};
+  bool hit[kTuneSites] = {};
+  int rc = NNP_OK;
+  for (int r = 0; r < kRounds && rc == NNP_OK; ++r) {
+    for (int q = 0; q < kTuneSites; ++q) m->tune_val[q] = q < kSiteGemmFwd ? kWpb[r] : kTn[r];
+    rc = run(m, n_systems, offs, coords, species, box, o, st, kFull);  // warm-up
+    for (int k = 0; k < kReps && rc == NNP_OK; ++k) {
+      m->tuning = true;
+      for (bool &h : m->tune_hit) h = false;
+      rc = run(m, n_systems, offs, coords, species, box, o, st, kFull);
+      m->tuning = false;
+      if (rc) break;
+      if (hipStreamSynchronize(st) != hipSuccess) { rc = fail(NNP_EDEVICE, "tuning run failed"); break; }
+      for (int q = 0; q < kTuneSites; ++q)
+        if (m->tune_hit[q]) {
+          float ms = 0.f;
+          if (hipEventElapsedTime(&ms, m->tune_ev[q][0], m->tune_ev[q][1]) == hipSuccess) t[q][r] += ms;
+          hit[q] = true;
+        }
+    }
+  }
+  // the fastest candidate of each site that ran (GEMM widths: best of the two 64 rounds)
+  for (int q = 0; q < kTuneSites; ++q) {
+    m->tune_val[q] = 0;
+    if (!hit[q] || rc) continue;
+    if (q < kSiteGemmFwd) {
+      int best = 0;
+      for (int r = 1; r < kRounds; ++r) if (t[q][r] < t[q][best]) best = r;
+      m->tune_val[q] = kWpb[best];
+    } else {
+      m->tune_val[q] = std::min(t[q][0], t[q][2]) <= t[q][1] ? 64 : 128;
+    }
+  }
+  (void)hipFree(energy);
+  (void)hipFree(forces);
+  return rc;
+}
+
+extern "C" int nnp_tuning(const nnp_model *m, int *values, int n) {
+  if (!m) return fail(NNP_EINVAL, "null model");
+  for (int q = 0; q < std::min(n, (int)kTuneSites); ++q) values[q] = m->tune_val[q];
+  return kTuneSites;
 }
 
 extern "C" int nnp_nlist_create(nnp_model *m, int64_t slots, int capacity, float skin, nnp_nlist **out) {

@@ -182,11 +182,13 @@ void launch_species_bucket(const float4 *pos, int N, int S, int *block_counts, i
                            int rows_cap, hipStream_t st);
 void launch_aev_fwd(const float4 *pos, const int *sys_of, const SysDesc *sys, const int2 *nbr,
                     const int *nbr_cnt, int cap, const int *row_of_atom, void *G, bool g_bf16,
-                    int ldg, int N, const AevConst &c, hipStream_t st);
+                    int ldg, int N, const AevConst &c, int wpb_pref, hipStream_t st);
 void launch_aev_bwd(const float4 *pos, const int *sys_of, const SysDesc *sys, const int2 *nbr,
                     const int *nbr_cnt, int cap, const int *row_of_atom, const float *dG,
-                    int ldg, int N, const AevConst &c, float *F, float *W_atom, hipStream_t st);
-void launch_gemm(int epi, bool bf16, GemmLaunch gl, int row_tiles, int max_n_out, hipStream_t st);
+                    int ldg, int N, const AevConst &c, float *F, float *W_atom, int wpb_pref, hipStream_t st);
+// tn_pref: column-tile width 64 or 128 (anything else: the width heuristic);
+// wpb_pref below: waves per workgroup 1, 2 or 4 when the LDS fits (else the default).
+void launch_gemm(int epi, bool bf16, GemmLaunch gl, int row_tiles, int max_n_out, int tn_pref, hipStream_t st);
 void launch_energy(const EnergyLaunch &el, bool bf16, int rows, hipStream_t st);
 void launch_chain(const ChainLaunch &cl, int n_hidden, bool grad, int rows, size_t lds_bytes, hipStream_t st);
 void launch_fill(float *p, size_t n, float v, hipStream_t st);

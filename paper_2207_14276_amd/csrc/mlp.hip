@@ -466,12 +466,13 @@ static bool gemm_k32(const GemmLaunch &gl) {
   return true;
 }
 
-void launch_gemm(int epi, bool bf16, GemmLaunch gl, int row_tiles, int max_n_out, hipStream_t st) {
+void launch_gemm(int epi, bool bf16, GemmLaunch gl, int row_tiles, int max_n_out, int tn_pref, hipStream_t st) {
   if (row_tiles <= 0) return;
   gl.k32 = bf16 && gemm_k32(gl) ? 1 : 0;
-  // 128-wide column tiles when they waste little, else 64
+  // the tuned width, else 128-wide column tiles when they waste little, else 64
   const int t128 = (max_n_out + 127) / 128 * 128, t64 = (max_n_out + 63) / 64 * 64;
-  const int tn = (t128 - max_n_out) * 4 <= max_n_out && t128 <= t64 + 32 ? 128 : 64;
+  const int tn = tn_pref == 64 || tn_pref == 128 ? tn_pref
+               : (t128 - max_n_out) * 4 <= max_n_out && t128 <= t64 + 32 ? 128 : 64;
   gl.col_tiles = (max_n_out + tn - 1) / tn;
   if (bf16) {
     if (epi == kEpiFwd) launch_t<kEpiFwd, true>(gl, row_tiles, tn, st);

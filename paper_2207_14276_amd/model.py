@@ -141,6 +141,28 @@ class NNPModel:
                 break
         return out
 
+    def autotune(self, coords, species, boxes, offsets) -> dict:
+        """Picks the launch shapes (AEV waves per workgroup, GEMM column-tile
+        widths) that run this batch fastest; they stay with the model.
+        Returns {site: value} for the sites that were tuned."""
+        coords, species, bx, offs, S = self._inputs(coords, species, boxes, offsets)
+        with torch.cuda.device(self.device):
+            nat.check(nat.load().nnp_autotune(
+                self._h, S, offs.ctypes.data_as(C.POINTER(C.c_int64)), C.c_void_p(coords.data_ptr()),
+                C.c_void_p(species.data_ptr()), _fptr(bx), _stream_handle(self.device)))
+        return self.tuning()
+
+    def tuning(self) -> dict:
+        vals = (C.c_int * 32)()
+        n = nat.check(nat.load().nnp_tuning(self._h, vals, 32))
+        names = {0: "aev_fwd_waves", 1: "aev_bwd_waves", 18: "gemm_dEdG_tn"}
+        out = {}
+        for q in range(n):
+            if vals[q]:
+                name = names.get(q) or (f"gemm_fwd{q - 2}_tn" if q < 10 else f"gemm_bwd{q - 10}_tn")
+                out[name] = int(vals[q])
+        return out
+
     def status(self):
         mx = C.c_int()
         with torch.cuda.device(self.device):

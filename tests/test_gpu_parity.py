@@ -327,3 +327,25 @@ def test_autograd_function_gives_minus_forces(m32):
     r = m32.energy_forces(c.detach(), s, bx, o, check=True)
     g = torch.repeat_interleave(w.float(), torch.as_tensor(np.diff(b.offsets), device=c.device))
     torch.testing.assert_close(c.grad, -g[:, None] * r.forces, rtol=1e-5, atol=1e-6)
+
+
+def test_autotune_changes_no_result(oracle_lib):
+    """Tuning the launch shapes on a batch picks valid shapes and leaves every
+    result as it was (tile shapes change no per-element arithmetic)."""
+    from paper_2207_14276_amd import NNPModel
+    spec = synth.make_model(0)
+    b = synth.ragged_solutes(24, seed=31)
+    for prec in ("fp32", "bf16"):
+        m = NNPModel(spec, prec)
+        c, sp, bx, o = to_dev(b)
+        r0 = m.energy_forces(c, sp, bx, o, check=True)
+        e0, f0 = r0.energy.cpu().numpy(), r0.forces.cpu().numpy()
+        tuned = m.autotune(c, sp, bx, o)
+        log(f"[autotune {prec}] {tuned}")
+        assert tuned, "no site was tuned"
+        for k, v in tuned.items():
+            assert v in ((1, 2, 4) if k.startswith("aev") else (64, 128)), (k, v)
+        r1 = m.energy_forces(c, sp, bx, o, check=True)
+        assert np.array_equal(r1.energy.cpu().numpy(), e0)
+        assert float(np.abs(r1.forces.cpu().numpy() - f0).max()) <= 1e-5
+        m.close()
