@@ -237,8 +237,9 @@ def replay(server: Server, arrivals, max_steps: int | None = None) -> Replay:
             t, req = pending[k]
             out.order.append(server.submit(req, t0 + t))
             k += 1
-        if not busy and k < len(pending) and pending[k][0] > now:
-            # idle until the next arrival
+            busy = max(busy, 1)   # a submitted request is work for the next step
+        if not busy:
+            # nothing queued or in flight: idle until the next arrival
             time.sleep(max(0.0, pending[k][0] - (server.clock() - t0)))
             continue
         busy = server.step()

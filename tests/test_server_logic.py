@@ -152,3 +152,76 @@ def test_randomized_invariants():
                 del live[rid]
     assert admitted_order == list(range(n_req))
     assert all(launched[r] == steps[r] for r in range(n_req))
+
+
+class _FakeServer:
+    """Stand-in for serve.Server on a virtual clock: every step advances the
+    clock by `dt` and moves each request in flight on by one evaluation."""
+
+    def __init__(self, dt):
+        self.t, self.dt = 0.0, dt
+        self.active, self.done, self.next_id = {}, [], 0
+        self.batches, self.finished = [], {}
+
+    def clock(self):
+        return self.t
+
+    def submit(self, req, t_arrival):
+        rid = self.next_id
+        self.next_id += 1
+        self.active[rid] = [req, t_arrival]
+        return rid
+
+    def step(self):
+        self.batches.append(sorted(self.active))
+        self.t += self.dt
+        for rid in list(self.active):
+            self.active[rid][0] -= 1
+            if self.active[rid][0] == 0:
+                t_arr = self.active.pop(rid)[1]
+                self.done.append(rid)
+                self.finished[rid] = (t_arr, self.t)
+        return len(self.active)
+
+    def poll(self):
+        out, self.done = self.done, []
+        return out
+
+    def result(self, rid):
+        from types import SimpleNamespace
+        t_arr, t_done = self.finished[rid]
+        return SimpleNamespace(done=t_done, latency=t_done - t_arr)
+
+    def drain(self):
+        pass
+
+
+def test_replay_steps_while_requests_arrive(monkeypatch):
+    """A request is served from the first step after its arrival, not held
+    back until the rest of the trace has arrived: with arrivals 10 steps
+    apart and 3 evaluations each, no batch ever holds two requests, and each
+    request's latency is its own 3 steps."""
+    from paper_2207_14276_amd import serve
+    fake = _FakeServer(dt=1.0)
+    monkeypatch.setattr(serve.time, "sleep", lambda s: setattr(fake, "t", fake.t + s))
+    arrivals = [(10.0 * q, 3) for q in range(5)]
+    rep = serve.replay(fake, arrivals)
+    assert len(rep.results) == 5
+    assert all(len(b) == 1 for b in fake.batches)
+    assert len(fake.batches) == 15
+    np.testing.assert_allclose(rep.latencies(), 3.0)
+
+
+def test_replay_joins_arrivals_into_running_batch(monkeypatch):
+    """Requests arriving while others are in flight join the next step
+    (continuous batching), and the replay runs until the last one is done."""
+    from paper_2207_14276_amd import serve
+    fake = _FakeServer(dt=1.0)
+    monkeypatch.setattr(serve.time, "sleep", lambda s: setattr(fake, "t", fake.t + s))
+    arrivals = [(0.0, 4), (1.5, 4), (2.5, 1)]
+    rep = serve.replay(fake, arrivals)
+    assert fake.batches[0] == [0]
+    assert fake.batches[2] == [0, 1]
+    assert fake.batches[3] == [0, 1, 2]
+    assert sorted(rep.results) == [0, 1, 2]
+    assert rep.wall == pytest.approx(max(r.done for r in rep.results.values()))
