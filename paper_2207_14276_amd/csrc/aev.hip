@@ -59,12 +59,14 @@ __device__ inline long long to_fix(float v) {
 }
 __device__ inline float from_fix(long long v) { return (float)v * kUnfix; }
 
-// q = u / n and r = u mod n for 0 <= u < 2^24 through a float reciprocal
-// (rn = 1/n), corrected to the exact integer result.
+// q = u / n and r = u mod n for 0 <= u < 2^23 through a float reciprocal
+// (rn = 1/n): the estimate is off by at most one, corrected by selects.
 __device__ inline int fdivmod(int u, int n, float rn, int &r) {
   int q = (int)((float)u * rn);
-  r = u - q * n;
-  if (r >= n) { ++q; r -= n; } else if (r < 0) { --q; r += n; }
+  int m = u - q * n;
+  const bool hi = m >= n, lo = m < 0;
+  q = hi ? q + 1 : (lo ? q - 1 : q);
+  r = hi ? m - n : (lo ? m + n : m);
   return q;
 }
 
@@ -90,28 +92,32 @@ constexpr int kPairPass = kWave;  // neighbour pairs staged per pass
 constexpr int kMaxBlocks = kMaxSpecies * (kMaxSpecies + 1) / 2;
 constexpr int kMaxAng = kMaxBlocks * kAngBlock;  // 896 angular features
 
-// Non-empty species-pair block q of the centre's pair stream.
+// Non-empty species-pair block q of the centre's pair stream.  A pair is
+// addressed as (x, y): x in the longer species list (length n1), y in the
+// shorter one (n2); for a same-species block both are the one list.  The
+// angular term is symmetric in its two neighbours, so which of the two
+// species is called j does not matter.
 struct PairBlock {
   int start;                   // first pair of the block in the stream
-  unsigned short oa, ob;       // offsets of the two species in the angular list
-  unsigned short na, nb;       // their counts
+  unsigned short ox, oy;       // angular-list offsets of the x and y lists
+  unsigned short n1, n2;       // their counts (n1 >= n2)
+  float r1, r2;                // 1 / n1, 1 / n2
   unsigned char p;             // feature block index (upper-triangle order of (sa, sb))
   unsigned char same;          // sa == sb
   unsigned char pad0, pad1;
-  float r_hi;                  // 1 / max(na, nb)
-  float r_lo;                  // 1 / min(na, nb)
 };
 static_assert(sizeof(PairBlock) == 24, "pair-block table entry");
 
 __device__ inline PairBlock make_block(int start, int p, int oa, int ob, int na, int nb, bool same) {
   PairBlock b;
+  const bool a_long = na >= nb;
   b.start = start;
-  b.oa = (unsigned short)oa; b.ob = (unsigned short)ob;
-  b.na = (unsigned short)na; b.nb = (unsigned short)nb;
+  b.ox = (unsigned short)(a_long ? oa : ob); b.oy = (unsigned short)(a_long ? ob : oa);
+  b.n1 = (unsigned short)max(na, nb); b.n2 = (unsigned short)min(na, nb);
+  b.r1 = 1.0f / (float)max((int)b.n1, 1);
+  b.r2 = 1.0f / (float)max((int)b.n2, 1);
   b.p = (unsigned char)p; b.same = same ? 1 : 0;
   b.pad0 = b.pad1 = 0;
-  b.r_hi = 1.0f / (float)max(max(na, nb), 1);
-  b.r_lo = 1.0f / (float)max(min(na, nb), 1);
   return b;
 }
 // the table of one wave, padded to a multiple of 16 bytes
@@ -124,8 +130,9 @@ struct WaveLds {
   float4 *tF2;     // pair scratch: radial Gaussians of Rbar     (forward)
   PairBlock *blk;  // [kMaxBlocks + 1] pair-block table           (backward)
   float4 *rD;      // radial: d vector and R
-  float *rFc;      // radial: fc_rad(R)
-  float *rDfc;     // radial: fc_rad'(R)         (backward)
+  float *rFc;      // radial: fc_rad(R)          (forward)
+  float2 *rF2;     // fc(R) and fc'(R): radial cutoff, then (angular entries)
+                   // the angular cutoff once the radial stage is done (backward)
   int *rJ;         // radial: neighbour index     (backward)
   long long *rG;   // radial: dE/dd accumulators, fixed point (backward, 3 per entry)
   int *aIdx;       // angular: position in the radial arrays
@@ -133,10 +140,11 @@ struct WaveLds {
 };
 
 // Per-wave LDS bytes (a multiple of 16).  Forward entry: rD 16, rFc 4,
-// aIdx 4, aFc 4.  Backward entry: rD 16, rG 24, rFc 4, rDfc 4, rJ 4, aIdx 4;
-// the backward reads the centre's dE/dG row from global memory (it stays in
-// the L1/L2 caches) and recomputes the angular cutoff per pair, which keeps
-// its LDS per wave near 8 KB (5 waves per SIMD at a capacity of 128).
+// aIdx 4, aFc 4.  Backward entry: rD 16, rG 24, rF2 8, rJ 4, aIdx 4; the
+// backward reads the centre's dE/dG row from global memory (it stays in the
+// L1/L2 caches) and keeps the angular cutoff in the radial cutoff's slots,
+// which keeps its LDS per wave near 8 KB (5 waves per SIMD at a capacity of
+// 128).
 template <bool BWD>
 __host__ __device__ inline size_t wave_lds_bytes(int cap) {
   return sizeof(Lists) + (BWD ? kBlkTableBytes + (size_t)cap * (16 + 24 + 4 + 4 + 4 + 4)
@@ -153,8 +161,7 @@ __device__ inline WaveLds carve(char *base, int cap) {
     w.rD = (float4 *)p; p += (size_t)cap * 16;
     w.rG = (long long *)p; p += (size_t)cap * 24;
     w.blk = (PairBlock *)p; p += kBlkTableBytes;
-    w.rFc = (float *)p; p += (size_t)cap * 4;
-    w.rDfc = (float *)p; p += (size_t)cap * 4;
+    w.rF2 = (float2 *)p; p += (size_t)cap * 8;
     w.rJ = (int *)p; p += (size_t)cap * 4;
     w.aIdx = (int *)p; p += (size_t)cap * 4;
   } else {
@@ -217,54 +224,32 @@ __device__ inline int build_blocks(int lane, const Lists &ls, int S, WaveLds &w,
 
 // Pair u of a block, enumerated by diagonals so that consecutive pairs (the
 // lanes of one pass) mostly touch different neighbour entries:
-//   same species, n entries: pairs (j, j + d mod n) for d = 1, 2, ...; when n
-//   is even the last diagonal d = n/2 holds n/2 pairs;
-//   two species (na, nb): the longer list runs fastest, the other index is
-//   shifted by the diagonal number.
-__device__ inline void unrank_diag(int u, const PairBlock &b, int &j, int &k) {
-  if (b.same) {
-    const int n = b.na;
-    const int full = (n & 1) ? n * (n - 1) / 2 : n * (n / 2 - 1);
-    if (u < full) {
-      int r;
-      const int dd = fdivmod(u, n, b.r_hi, r) + 1;
-      j = r;
-      k = j + dd;
-      if (k >= n) k -= n;
-    } else {
-      j = u - full;
-      k = j + n / 2;
-    }
-  } else if (b.na >= b.nb) {
-    int r;
-    const int row = fdivmod(u, b.na, b.r_hi, r);
-    j = r;
-    int m;
-    fdivmod(row + j, b.nb, b.r_lo, m);
-    k = m;
-  } else {
-    int r;
-    const int row = fdivmod(u, b.nb, b.r_hi, r);
-    k = r;
-    int m;
-    fdivmod(row + k, b.na, b.r_lo, m);
-    j = m;
-  }
+//   x = u mod n1 runs fastest, the diagonal number q = u div n1 shifts the
+//   partner: y = (x + q + same) mod n2.
+// Same species (n1 = n2 = n): diagonals d = q + 1 = 1, 2, ... give the pairs
+// (x, x + d mod n) once each; when n is even the last diagonal d = n/2 holds
+// only its first n/2 pairs, which is where u stops (u < n(n-1)/2).
+// Two species: q < n2 and every (x, y) occurs exactly once.
+// No branch depends on the block, so lanes of one pass in different blocks
+// do not diverge.
+__device__ inline void unrank(int u, const PairBlock &b, int &ax, int &ay) {
+  int x, y;
+  const int q = fdivmod(u, b.n1, b.r1, x);
+  fdivmod(x + q + b.same, b.n2, b.r2, y);
+  ax = b.ox + x;
+  ay = b.oy + y;
 }
 
 // Pair t of the stream -> its block (searched from the wave-uniform block
-// index qb of the pass), the positions of j and k in the angular list, and
-// the feature block index.
+// index qb of the pass), the positions of its two entries in the angular
+// list, and the feature block index.
 __device__ inline void locate_pair(int t, int qb, int nblk, int pass_end, const WaveLds &w,
                                    int &aj, int &ak, int &p) {
   int q = qb;
   for (int r = qb + 1; r < nblk && w.blk[r].start < pass_end; ++r)
     if (t >= w.blk[r].start) q = r;
   const PairBlock b = w.blk[q];
-  int j, k;
-  unrank_diag(t - b.start, b, j, k);
-  aj = b.oa + j;
-  ak = b.ob + k;
+  unrank(t - b.start, b, aj, ak);
   p = b.p;
 }
 
@@ -352,9 +337,9 @@ __device__ inline void fill_lists(int lane, int n, const int2 *__restrict__ ent,
         float sn, cs;
         __sincosf(kr * d.w, &sn, &cs);
         w.rD[q] = d;
-        w.rFc[q] = 0.5f * cs + 0.5f;
+        if (!BWD) w.rFc[q] = 0.5f * cs + 0.5f;
         if (BWD) {
-          w.rDfc[q] = -0.5f * kr * sn;
+          w.rF2[q] = make_float2(0.5f * cs + 0.5f, -0.5f * kr * sn);
           w.rJ[q] = j;
           w.rG[3 * q] = 0; w.rG[3 * q + 1] = 0; w.rG[3 * q + 2] = 0;
         }
@@ -408,7 +393,9 @@ k_aev_fwd(const float4 *__restrict__ pos, const int *__restrict__ sys_of,
           const int *__restrict__ nbr_cnt, int cap, const int *__restrict__ row_of_atom,
           void *__restrict__ G, int ldg, int N, AevConst c) {
   extern __shared__ float4 lds4[];
-  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  // the wave index is uniform across the wave: keep it (and the centre's
+  // index, descriptors and row pointers) in scalar registers
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave), lane = threadIdx.x % kWave;
   const int i = blockIdx.x * WPB + wave;
   const bool live = i < N;
   WaveLds w = carve<false>((char *)lds4 + wave * wave_lds_bytes<false>(cap), cap);
@@ -476,7 +463,7 @@ k_aev_fwd(const float4 *__restrict__ pos, const int *__restrict__ sys_of,
           }
           continue;
         }
-        const PairBlock blk = make_block(0, p, 0, 0, na, nb, sa == sb);
+        const PairBlock blk = make_block(0, p, ls.oA[sa], ls.oA[sb], na, nb, sa == sb);
         float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f, acc3 = 0.f;
         for (int base = 0; base < T; base += kPairPass) {
           // (A) lane per pair
@@ -484,9 +471,8 @@ k_aev_fwd(const float4 *__restrict__ pos, const int *__restrict__ sys_of,
             const int t = base + lane;
             const bool valid = t < T;
             const int tt = valid ? t : T - 1;
-            int j, k;
-            unrank_diag(tt, blk, j, k);
-            const int qj = ls.oA[sa] + j, qk = ls.oA[sb] + k;
+            int qj, qk;
+            unrank(tt, blk, qj, qk);
             const float4 dj = w.rD[w.aIdx[qj]], dk = w.rD[w.aIdx[qk]];
             const float dot = dj.x * dk.x + dj.y * dk.y + dj.z * dk.z;
             const float cx = dj.y * dk.z - dj.z * dk.y;
@@ -545,15 +531,20 @@ k_aev_fwd(const float4 *__restrict__ pos, const int *__restrict__ sys_of,
   }
 }
 
-template <int WPB>
-__global__ void __launch_bounds__(WPB * kWave)
+// OCC: waves per SIMD the register allocation must allow (0: no bound).
+// With a small neighbour capacity the LDS leaves room for 6 waves per
+// SIMD; the kernel is then held to 80 registers so that they fit.
+template <int WPB, int OCC>
+__global__ void __launch_bounds__(WPB * kWave) __attribute__((amdgpu_waves_per_eu(OCC)))
 k_aev_bwd(const float4 *__restrict__ pos, const int *__restrict__ sys_of,
           const SysDesc *__restrict__ sys, const int2 *__restrict__ nbr,
           const int *__restrict__ nbr_cnt, int cap, const int *__restrict__ row_of_atom,
           const float *__restrict__ dG, int ldg, int N, AevConst c, float *__restrict__ F,
           float *__restrict__ W_atom) {
   extern __shared__ float4 lds4[];
-  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  // the wave index is uniform across the wave: keep it (and the centre's
+  // index, descriptors and row pointers) in scalar registers
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave), lane = threadIdx.x % kWave;
   const int i = blockIdx.x * WPB + wave;
   const bool live = i < N;
   WaveLds w = carve<true>((char *)lds4 + wave * wave_lds_bytes<true>(cap), cap);
@@ -592,9 +583,10 @@ k_aev_bwd(const float4 *__restrict__ pos, const int *__restrict__ sys_of,
       const int o = ls.oR[s];
       for (int e = slot; e < ls.cR[s]; e += 4) {
         const float4 d = w.rD[o + e];
+        const float2 fc = w.rF2[o + e];
         const float t = d.w - shf;
         const float ex = fast_exp(-c.eta_r * t * t);
-        float term = sum16(gm * ex * (-2.0f * c.eta_r * t * w.rFc[o + e] + w.rDfc[o + e]));
+        float term = sum16(gm * ex * (-2.0f * c.eta_r * t * fc.x + fc.y));
         if (m == 0) {
           const float q = term * fast_rcp(d.w);
           long long *gg = w.rG + 3 * (o + e);
@@ -606,14 +598,29 @@ k_aev_bwd(const float4 *__restrict__ pos, const int *__restrict__ sys_of,
 
   wave_lds_sync();
 
+  // angular cutoff of every angular entry, into its radial cutoff slot (the
+  // radial stage above was the last reader of those)
+  {
+    const float ka = kPi / c.rc_a;
+    int nA = 0;
+    for (int s = 0; s < c.S; ++s) nA += ls.cA[s];
+    for (int e = lane; e < nA; e += kWave) {
+      const int q = w.aIdx[e];
+      float sn, cs;
+      __sincosf(ka * w.rD[q].w, &sn, &cs);
+      w.rF2[q] = make_float2(0.5f * cs + 0.5f, -0.5f * ka * sn);
+    }
+  }
+  wave_lds_sync();
+
   // angular: lane per neighbour pair over the pair stream of all blocks
   {
     const float *gA = g + c.rad_len;
-    const float ka = kPi / c.rc_a;
     int nblk;
     const int P = build_blocks(lane, ls, c.S, w, nblk);
     wave_lds_sync();
     const float pre = 1.0f - c.zeta;
+    const float zm1 = c.zeta - 1.0f;
     const float keta = -c.eta_a * 1.4426950408889634f;
     const float m2eta = -2.0f * c.eta_a;
     int qb = 0;
@@ -624,29 +631,30 @@ k_aev_bwd(const float4 *__restrict__ pos, const int *__restrict__ sys_of,
       locate_pair(min(base + lane, P - 1), qb, nblk, base + kPairPass, w, aj, ak, p);
       const int qj = w.aIdx[aj], qk = w.aIdx[ak];
       const float4 dj = w.rD[qj], dk = w.rD[qk];
-      float sj_, cj_, sk_, ck_;
-      __sincosf(ka * dj.w, &sj_, &cj_);
-      __sincosf(ka * dk.w, &sk_, &ck_);
-      const float fj = 0.5f * cj_ + 0.5f, fk = 0.5f * ck_ + 0.5f;
+      const float2 cj2 = w.rF2[qj], ck2 = w.rF2[qk];  // angular fc and fc'
       const float dot = dj.x * dk.x + dj.y * dk.y + dj.z * dk.z;
       const float cx = dj.y * dk.z - dj.z * dk.y;
       const float cy = dj.z * dk.x - dj.x * dk.z;
       const float cz = dj.x * dk.y - dj.y * dk.x;
       const float cr = fast_sqrt(cx * cx + cy * cy + cz * cz);
-      const float RR = dj.w * dk.w;
-      const float invRR = fast_rcp(RR);
+      const float invj = fast_rcp(dj.w), invk = fast_rcp(dk.w);
+      const float invRR = invj * invk;
       const float cosv = dot * invRR, sinv = cr * invRR;
       const float Rbar = 0.5f * (dj.w + dk.w);
-      float f2[kNShfAng], df2[kNShfAng];
+      float f2[kNShfAng], ur[kNShfAng];
 #pragma unroll
       for (int r = 0; r < kNShfAng; ++r) {
-        const float u = Rbar - c.shf_a[r];
-        f2[r] = fast_exp2(keta * u * u);
-        df2[r] = m2eta * u * f2[r];
+        ur[r] = Rbar - c.shf_a[r];
+        f2[r] = fast_exp2(keta * ur[r] * ur[r]);
       }
-      // dE/dG of this block: gv[r][a] at gA[32 p + 8 r + a] (global, cached)
+      // dE/dG of this block: gv[r][a] at gA[32 p + 8 r + a] (global, cached).
+      // With p1 = 2^(1-zeta) x^(zeta-1) and f1 = p1 x (x = 1 + cos(theta -
+      // theta_a)), the pair's terms are f1 f2[r] fc_j fc_k, so
+      //   dE/dx_a   = zeta p1 A_a fc_j fc_k,  A_a = sum_r gv[r][a] f2[r]
+      //   dE/dRbar  = sum_r f2'[r] H_r fc_j fc_k,  dE/d(fc_j fc_k) = sum_r f2[r] H_r,
+      //   H_r = sum_a gv[r][a] f1_a.
       const float4 *gv = (const float4 *)(gA + p * kAngBlock);
-      float dcos = 0.f, dsin = 0.f, dbar = 0.f, dfc = 0.f;
+      float dcos = 0.f, dsin = 0.f, H[kNShfAng] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
         float gq[kNShfAng][4];
@@ -659,31 +667,35 @@ k_aev_bwd(const float4 *__restrict__ pos, const int *__restrict__ sys_of,
         for (int aa = 0; aa < 4; ++aa) {
           const int a = 4 * h + aa;
           const float x = fmaxf(1.0f + cosv * c.cz[a] + sinv * c.sz[a], 0.f);
-          // p1 = 2^(1-zeta) x^(zeta-1); f1 = p1 x; df1/dx = zeta p1
-          const float p1 = fast_exp2((c.zeta - 1.0f) * fast_log2(x) + pre);
-          const float f1 = p1 * x;
-          float A = 0.f, B = 0.f;
+          const float p1 = fast_exp2(zm1 * fast_log2(x) + pre);
+          float A = gq[0][aa] * f2[0];
 #pragma unroll
-          for (int r = 0; r < kNShfAng; ++r) {
-            A += gq[r][aa] * f2[r];
-            B += gq[r][aa] * df2[r];
-          }
-          const float s1 = c.zeta * p1 * A;
+          for (int r = 1; r < kNShfAng; ++r) A += gq[r][aa] * f2[r];
+          const float s1 = p1 * A;
           dcos += s1 * c.cz[a];
           dsin += s1 * c.sz[a];
-          dbar += f1 * B;
-          dfc += f1 * A;
+          const float f1 = p1 * x;
+#pragma unroll
+          for (int r = 0; r < kNShfAng; ++r) H[r] += gq[r][aa] * f1;
         }
       }
       if (valid) {
+        float dfc = 0.f, dbar = 0.f;
+#pragma unroll
+        for (int r = 0; r < kNShfAng; ++r) {
+          const float t = f2[r] * H[r];
+          dfc += t;
+          dbar += ur[r] * t;
+        }
+        const float fj = cj2.x, fk = ck2.x;
         const float fcc = fj * fk;
-        dcos *= fcc;
-        dsin *= fcc;
-        dbar *= 0.5f * fcc;  // via Rbar, for each of R_j and R_k
-        const float dRj = dbar + dfc * (-0.5f * ka * sj_) * fk;
-        const float dRk = dbar + dfc * fj * (-0.5f * ka * sk_);
-        const float inv_cr = cr > 1e-12f * RR ? fast_rcp(cr) : 0.f;
-        const float invj = fast_rcp(dj.w), invk = fast_rcp(dk.w);
+        const float zf = c.zeta * fcc;
+        dcos *= zf;
+        dsin *= zf;
+        dbar *= 0.5f * m2eta * fcc;  // via Rbar, for each of R_j and R_k
+        const float dRj = dbar + dfc * cj2.y * fk;
+        const float dRk = dbar + dfc * fj * ck2.y;
+        const float inv_cr = cr > 1e-12f * dj.w * dk.w ? fast_rcp(cr) : 0.f;
         const float aj_ = dcos * invRR, ak_ = dsin * inv_cr * invRR;
         // d cos / d dj = dk / RR - cos dj / Rj^2 ; d sin / d dj =
         // (Rk^2 dj - dot dk) / (|dj x dk| RR) - sin dj / Rj^2
@@ -775,19 +787,32 @@ void launch_aev_fwd(const float4 *pos, const int *sys_of, const SysDesc *sys, co
   else aev_fwd_t<false>(pos, sys_of, sys, nbr, nbr_cnt, cap, row_of_atom, G, ldg, N, c, wpb_pref, st);
 }
 
+template <int OCC>
+static void aev_bwd_t(const float4 *pos, const int *sys_of, const SysDesc *sys, const int2 *nbr,
+                      const int *nbr_cnt, int cap, const int *row_of_atom, const float *dG, int ldg,
+                      int N, const AevConst &c, float *F, float *W_atom, int wpb, hipStream_t st) {
+  size_t lds = wave_lds_bytes<true>(cap) * wpb;
+  unsigned grid = (unsigned)((N + wpb - 1) / wpb);
+  if (wpb == 4)
+    k_aev_bwd<4, OCC><<<grid, 4 * kWave, lds, st>>>(pos, sys_of, sys, nbr, nbr_cnt, cap, row_of_atom, dG, ldg, N, c, F, W_atom);
+  else if (wpb == 2)
+    k_aev_bwd<2, OCC><<<grid, 2 * kWave, lds, st>>>(pos, sys_of, sys, nbr, nbr_cnt, cap, row_of_atom, dG, ldg, N, c, F, W_atom);
+  else
+    k_aev_bwd<1, OCC><<<grid, kWave, lds, st>>>(pos, sys_of, sys, nbr, nbr_cnt, cap, row_of_atom, dG, ldg, N, c, F, W_atom);
+}
+
 void launch_aev_bwd(const float4 *pos, const int *sys_of, const SysDesc *sys, const int2 *nbr,
                     const int *nbr_cnt, int cap, const int *row_of_atom, const float *dG, int ldg,
                     int N, const AevConst &c, float *F, float *W_atom, int wpb_pref, hipStream_t st) {
   if (N <= 0) return;
-  int wpb = waves_for_cap<true>(cap, wpb_pref);
-  size_t lds = wave_lds_bytes<true>(cap) * wpb;
-  unsigned grid = (unsigned)((N + wpb - 1) / wpb);
-  if (wpb == 4)
-    k_aev_bwd<4><<<grid, 4 * kWave, lds, st>>>(pos, sys_of, sys, nbr, nbr_cnt, cap, row_of_atom, dG, ldg, N, c, F, W_atom);
-  else if (wpb == 2)
-    k_aev_bwd<2><<<grid, 2 * kWave, lds, st>>>(pos, sys_of, sys, nbr, nbr_cnt, cap, row_of_atom, dG, ldg, N, c, F, W_atom);
+  const int wpb = waves_for_cap<true>(cap, wpb_pref);
+  // waves per SIMD the LDS allows (160 KB per compute unit, 4 SIMDs)
+  const size_t per_wg = wave_lds_bytes<true>(cap) * wpb;
+  const int lds_waves = (int)(160 * 1024 / per_wg) * wpb / 4;
+  if (lds_waves >= 6)
+    aev_bwd_t<6>(pos, sys_of, sys, nbr, nbr_cnt, cap, row_of_atom, dG, ldg, N, c, F, W_atom, wpb, st);
   else
-    k_aev_bwd<1><<<grid, kWave, lds, st>>>(pos, sys_of, sys, nbr, nbr_cnt, cap, row_of_atom, dG, ldg, N, c, F, W_atom);
+    aev_bwd_t<0>(pos, sys_of, sys, nbr, nbr_cnt, cap, row_of_atom, dG, ldg, N, c, F, W_atom, wpb, st);
 }
 
 }  // namespace nnp

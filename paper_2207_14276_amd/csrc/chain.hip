@@ -94,7 +94,7 @@ template <int NL, bool GRAD>
 __global__ void __launch_bounds__(256) k_chain(ChainLaunch cl) {
   extern __shared__ uint4 chain_lds[];
   __shared__ float e_red[4][kChainRows];
-  const int tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
+  const int tid = threadIdx.x, wave = __builtin_amdgcn_readfirstlane(tid / kWave), lane = tid % kWave;
   const int l16 = lane & 15, kq = lane >> 4;
   // member-major logical order, contiguous per XCD: an XCD works through the
   // row tiles of one or two (member, species) networks at a time, whose

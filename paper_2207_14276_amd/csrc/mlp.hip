@@ -87,7 +87,7 @@ __global__ void __launch_bounds__(256) k_gemm(GemmLaunch gl) {
   const int nk = (K + TK - 1) / TK;    // chunks per segment
   const int total = nk * nseg;
 
-  const int tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
+  const int tid = threadIdx.x, wave = __builtin_amdgcn_readfirstlane(tid / kWave), lane = tid % kWave;
   const int l32 = lane & 31, hi = lane >> 5;
   const int wr = wave / WAVES_N, wc = wave % WAVES_N;
 
@@ -303,7 +303,7 @@ __global__ void __launch_bounds__(256) k_gemm_dl(GemmLaunch gl) {
   const int nk = K / TK;
   const int total = nk * nseg;
 
-  const int tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
+  const int tid = threadIdx.x, wave = __builtin_amdgcn_readfirstlane(tid / kWave), lane = tid % kWave;
   const int l32 = lane & 31, hi = lane >> 5;
   const int wr = wave / WAVES_N, wc = wave % WAVES_N;
 
