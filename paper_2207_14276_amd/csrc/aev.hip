@@ -328,29 +328,33 @@ __device__ inline void fill_lists(int lane, int n, const int2 *__restrict__ ent,
       sj = __float_as_int(pj.w);
     }
     bool inR = v && d.w < c.rc_r, inA = v && d.w < c.rc_a;
+    // slots of this lane's entry in the two lists (selects per species;
+    // the stores below are then issued once, not once per species)
+    int q = 0, qa = 0;
 #pragma unroll
     for (int s = 0; s < kMaxSpecies; ++s) {
       unsigned long long mR = __ballot(inR && sj == s);
       unsigned long long mA = __ballot(inA && sj == s);
-      int q = pR[s] + (int)lanes_below(mR);
-      if (inR && sj == s) {
-        float sn, cs;
-        __sincosf(kr * d.w, &sn, &cs);
-        w.rD[q] = d;
-        if (!BWD) w.rFc[q] = 0.5f * cs + 0.5f;
-        if (BWD) {
-          w.rF2[q] = make_float2(0.5f * cs + 0.5f, -0.5f * kr * sn);
-          w.rJ[q] = j;
-          w.rG[3 * q] = 0; w.rG[3 * q + 1] = 0; w.rG[3 * q + 2] = 0;
-        }
-      }
-      if (inA && sj == s) {
-        const int qa = pA[s] + (int)lanes_below(mA);
-        w.aIdx[qa] = q;
-        if (!BWD) w.aFc[qa] = 0.5f * __cosf(ka * d.w) + 0.5f;
+      if (sj == s) {
+        q = pR[s] + (int)lanes_below(mR);
+        qa = pA[s] + (int)lanes_below(mA);
       }
       pR[s] += __popcll(mR);
       pA[s] += __popcll(mA);
+    }
+    if (inR) {
+      float sn, cs;
+      __sincosf(kr * d.w, &sn, &cs);
+      w.rD[q] = d;
+      if (!BWD) w.rFc[q] = 0.5f * cs + 0.5f;
+      if (BWD) {
+        w.rF2[q] = make_float2(0.5f * cs + 0.5f, -0.5f * kr * sn);
+        w.rJ[q] = j;
+      }
+    }
+    if (inA) {
+      w.aIdx[qa] = q;
+      if (!BWD) w.aFc[qa] = 0.5f * __cosf(ka * d.w) + 0.5f;
     }
   }
 }
@@ -502,10 +506,10 @@ k_aev_fwd(const float4 *__restrict__ pos, const int *__restrict__ sys_of,
             const float x1 = fmaxf(1.0f + geo1.x * cza + geo1.y * sza, 0.f);
             const float v0 = fast_exp2(c.zeta * fast_log2(x0) + pre) * geo0.z;
             const float v1 = fast_exp2(c.zeta * fast_log2(x1) + pre) * geo1.z;
-            acc0 += v0 * f20.x + v1 * f21.x;
-            acc1 += v0 * f20.y + v1 * f21.y;
-            acc2 += v0 * f20.z + v1 * f21.z;
-            acc3 += v0 * f20.w + v1 * f21.w;
+            acc0 += v0 * f20.x; acc0 += v1 * f21.x;
+            acc1 += v0 * f20.y; acc1 += v1 * f21.y;
+            acc2 += v0 * f20.z; acc2 += v1 * f21.z;
+            acc3 += v0 * f20.w; acc3 += v1 * f21.w;
           }
           if (g8 < groups) {
             const int q = 8 * g8 + t0;
@@ -561,41 +565,46 @@ k_aev_bwd(const float4 *__restrict__ pos, const int *__restrict__ sys_of,
     j0 = d.atom_off;
     row = nbr + nbr_row(d, i, cap);
   }
-  // this lane's radial dE/dG values (shift m = lane % 16 of every species),
-  // loaded now so that their latency overlaps the list construction
-  const float *g = dG + (size_t)(live ? row_of_atom[i] : 0) * ldg;
-  float gR[kMaxSpecies];
-#pragma unroll
-  for (int s = 0; s < kMaxSpecies; ++s) gR[s] = live && s < c.S ? g[s * kNShfRad + (lane & 15)] : 0.f;
   fill_lists<true>(lane, n, row, j0, n_sys, pos, pi, L, c, w);
   __syncthreads();
   if (!live) return;
   const Lists &ls = *w.ls;
+  const float *g = dG + (size_t)row_of_atom[i] * ldg;
+  int nR = 0;
+  for (int s = 0; s < c.S; ++s) nR += ls.cR[s];
 
-  // radial: dE/dR = scale * sum_m g_m d/dR[exp(-eta (R - Rs_m)^2) fc(R)]
+  // radial, lane per neighbour entry: with t_m = R - Rs_m and
+  // e_m = exp(-eta t_m^2), dE/dR = scale (fc' sum_m g_m e_m - 2 eta fc
+  // sum_m g_m e_m t_m), g being the dE/dG values of the entry's species.
+  // This stage is the first writer of the dE/dd accumulators.
   {
-    const int m = lane & 15, slot = lane >> 4;
-    const float shf = pick(c.shf_r, m);
+    const float keta = -c.eta_r * 1.4426950408889634f;
+    for (int e = lane; e < nR; e += kWave) {
+      int sp = 0;
 #pragma unroll
-    for (int s = 0; s < kMaxSpecies; ++s) {
-      if (s >= c.S) break;
-      const float gm = gR[s] * c.scale;
-      const int o = ls.oR[s];
-      for (int e = slot; e < ls.cR[s]; e += 4) {
-        const float4 d = w.rD[o + e];
-        const float2 fc = w.rF2[o + e];
-        const float t = d.w - shf;
-        const float ex = fast_exp(-c.eta_r * t * t);
-        float term = sum16(gm * ex * (-2.0f * c.eta_r * t * fc.x + fc.y));
-        if (m == 0) {
-          const float q = term * fast_rcp(d.w);
-          long long *gg = w.rG + 3 * (o + e);
-          gg[0] = to_fix(q * d.x); gg[1] = to_fix(q * d.y); gg[2] = to_fix(q * d.z);
+      for (int s = 1; s < kMaxSpecies; ++s) sp += e >= ls.oR[s] ? 1 : 0;
+      const float4 d = w.rD[e];
+      const float2 fc = w.rF2[e];
+      const float4 *gs = (const float4 *)(g + sp * kNShfRad);
+      float A = 0.f, B = 0.f;
+#pragma unroll
+      for (int h = 0; h < kNShfRad / 4; ++h) {
+        const float4 gv = gs[h];
+        const float gm[4] = {gv.x, gv.y, gv.z, gv.w};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const float t = d.w - c.shf_r[4 * h + k];
+          const float ge = gm[k] * fast_exp2(keta * t * t);
+          A += ge;
+          B += ge * t;
         }
       }
+      const float dEdR = c.scale * (fc.y * A - 2.0f * c.eta_r * fc.x * B);
+      const float q = dEdR * fast_rcp(d.w);
+      long long *gg = w.rG + 3 * e;
+      gg[0] = to_fix(q * d.x); gg[1] = to_fix(q * d.y); gg[2] = to_fix(q * d.z);
     }
   }
-
   wave_lds_sync();
 
   // angular cutoff of every angular entry, into its radial cutoff slot (the
@@ -719,8 +728,6 @@ k_aev_bwd(const float4 *__restrict__ pos, const int *__restrict__ sys_of,
 
   // scatter: F_i += dE/dd, F_j -= dE/dd, per-centre virial -sum d (x) dE/dd
   {
-    int nR = 0;
-    for (int s = 0; s < c.S; ++s) nR += ls.cR[s];
     float fi0 = 0.f, fi1 = 0.f, fi2 = 0.f;
     float vir[9];
     for (int q = 0; q < 9; ++q) vir[q] = 0.f;
