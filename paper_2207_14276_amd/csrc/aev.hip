@@ -60,7 +60,8 @@ __device__ inline long long to_fix(float v) {
 __device__ inline float from_fix(long long v) { return (float)v * kUnfix; }
 
 // q = u / n and r = u mod n for 0 <= u < 2^23 through a float reciprocal
-// (rn = 1/n): the estimate is off by at most one, corrected by selects.
+// (rn within an ulp of 1/n): the estimate is off by at most one, corrected
+// by selects.
 __device__ inline int fdivmod(int u, int n, float rn, int &r) {
   int q = (int)((float)u * rn);
   int m = u - q * n;
@@ -114,8 +115,9 @@ __device__ inline PairBlock make_block(int start, int p, int oa, int ob, int na,
   b.start = start;
   b.ox = (unsigned short)(a_long ? oa : ob); b.oy = (unsigned short)(a_long ? ob : oa);
   b.n1 = (unsigned short)max(na, nb); b.n2 = (unsigned short)min(na, nb);
-  b.r1 = 1.0f / (float)max((int)b.n1, 1);
-  b.r2 = 1.0f / (float)max((int)b.n2, 1);
+  // hardware reciprocals (within an ulp): fdivmod corrects the quotient
+  b.r1 = fast_rcp((float)max((int)b.n1, 1));
+  b.r2 = fast_rcp((float)max((int)b.n2, 1));
   b.p = (unsigned char)p; b.same = same ? 1 : 0;
   b.pad0 = b.pad1 = 0;
   return b;
@@ -125,7 +127,6 @@ constexpr size_t kBlkTableBytes = (sizeof(PairBlock) * (kMaxBlocks + 1) + 15) / 
 
 struct WaveLds {
   Lists *ls;       // per-species counts and offsets (wave-uniform)
-  float *xp;       // 32-feature block being written out              (forward)
   float4 *tGeo;    // pair scratch: cos, sin, fc_j fc_k, -      (forward)
   float4 *tF2;     // pair scratch: radial Gaussians of Rbar     (forward)
   PairBlock *blk;  // [kMaxBlocks + 1] pair-block table           (backward)
@@ -148,7 +149,7 @@ struct WaveLds {
 template <bool BWD>
 __host__ __device__ inline size_t wave_lds_bytes(int cap) {
   return sizeof(Lists) + (BWD ? kBlkTableBytes + (size_t)cap * (16 + 24 + 4 + 4 + 4 + 4)
-                              : (size_t)kAngBlock * 4 + (size_t)kPairPass * 16 * 2 +
+                              : (size_t)kPairPass * 16 * 2 +
                                     (size_t)cap * (16 + 4 + 4 + 4));
 }
 
@@ -165,7 +166,6 @@ __device__ inline WaveLds carve(char *base, int cap) {
     w.rJ = (int *)p; p += (size_t)cap * 4;
     w.aIdx = (int *)p; p += (size_t)cap * 4;
   } else {
-    w.xp = (float *)p; p += (size_t)kAngBlock * 4;
     w.tGeo = (float4 *)p; p += (size_t)kPairPass * 16;
     w.tF2 = (float4 *)p; p += (size_t)kPairPass * 16;
     w.rD = (float4 *)p; p += (size_t)cap * 16;
@@ -390,6 +390,17 @@ template <> __device__ inline void store8<false>(void *row, int k, const float *
   d[1] = make_float4(v[4], v[5], v[6], v[7]);
 }
 
+// One feature (row offset k) to the feature row, rounded to bfloat16 the
+// same way as bf16_pair.  The lanes of a wave that store together cover
+// contiguous features, so the stores combine into full segments.
+template <bool BF16> __device__ inline void store1(void *row, int k, float v);
+template <> __device__ inline void store1<true>(void *row, int k, float v) {
+  uint32_t a = __float_as_uint(v);
+  a += 0x7fffu + ((a >> 16) & 1u);
+  ((uint16_t *)row)[k] = (uint16_t)(a >> 16);
+}
+template <> __device__ inline void store1<false>(void *row, int k, float v) { ((float *)row)[k] = v; }
+
 template <int WPB, bool BF16>
 __global__ void __launch_bounds__(WPB * kWave)
 k_aev_fwd(const float4 *__restrict__ pos, const int *__restrict__ sys_of,
@@ -440,10 +451,7 @@ k_aev_fwd(const float4 *__restrict__ pos, const int *__restrict__ sys_of,
         }
       }
       acc = sum4(acc);
-      if (slot == 0) w.xp[m] = acc * c.scale;
-      wave_lds_sync();
-      if (lane < kNShfRad / 8) store8<BF16>(Grow, s * kNShfRad + 8 * lane, w.xp + 8 * lane);
-      wave_lds_sync();
+      if (slot == 0) store1<BF16>(Grow, s * kNShfRad + m, acc * c.scale);
     }
   }
 
@@ -454,19 +462,27 @@ k_aev_fwd(const float4 *__restrict__ pos, const int *__restrict__ sys_of,
     const float cza = pick(c.cz, a), sza = pick(c.sz, a);
     const float pre = 1.0f - c.zeta;
     const float keta = -c.eta_a * 1.4426950408889634f;
+    // blocks without a pair of their two species are zero: written in one
+    // pass of 16-byte stores over the angular part of the row
+    {
+      unsigned long long nonempty = 0;  // up to 36 blocks
+      int q = 0;
+      for (int sa = 0; sa < c.S; ++sa)
+        for (int sb = sa; sb < c.S; ++sb, ++q) {
+          const int na = ls.cA[sa], nb = ls.cA[sb];
+          if ((sa == sb ? na * (na - 1) / 2 : na * nb) > 0) nonempty |= 1ull << q;
+        }
+      constexpr int kChunksPerBlock = kAngBlock * (BF16 ? 2 : 4) / 16;
+      uint4 *ang = (uint4 *)((char *)Grow + (size_t)c.rad_len * (BF16 ? 2 : 4));
+      for (int k = lane; k < q * kChunksPerBlock; k += kWave)
+        if (!((nonempty >> (k / kChunksPerBlock)) & 1ull)) ang[k] = make_uint4(0u, 0u, 0u, 0u);
+    }
     int p = 0;
     for (int sa = 0; sa < c.S; ++sa) {
       for (int sb = sa; sb < c.S; ++sb, ++p) {
         const int na = ls.cA[sa], nb = ls.cA[sb];
         const int T = sa == sb ? na * (na - 1) / 2 : na * nb;
-        if (T == 0) {
-          // no pair of these species: the block is zero
-          if (lane < kNShfAng) {
-            const float z[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-            store8<BF16>(Grow, c.rad_len + p * kAngBlock + 8 * lane, z);
-          }
-          continue;
-        }
+        if (T == 0) continue;
         const PairBlock blk = make_block(0, p, ls.oA[sa], ls.oA[sb], na, nb, sa == sb);
         float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f, acc3 = 0.f;
         for (int base = 0; base < T; base += kPairPass) {
@@ -525,11 +541,10 @@ k_aev_fwd(const float4 *__restrict__ pos, const int *__restrict__ sys_of,
         acc1 = sum8(acc1);
         acc2 = sum8(acc2);
         acc3 = sum8(acc3);
-        // block [r][a] transposed through LDS, written as 4 x 8 features
-        if (t0 < kNShfAng) w.xp[kNShfZ * t0 + a] = t0 == 0 ? acc0 : t0 == 1 ? acc1 : t0 == 2 ? acc2 : acc3;
-        wave_lds_sync();
-        if (lane < kNShfAng) store8<BF16>(Grow, c.rad_len + p * kAngBlock + 8 * lane, w.xp + 8 * lane);
-        wave_lds_sync();
+        // feature [r][a] of the block from lane (a, t0 = r)
+        if (t0 < kNShfAng)
+          store1<BF16>(Grow, c.rad_len + p * kAngBlock + kNShfZ * t0 + a,
+                       t0 == 0 ? acc0 : t0 == 1 ? acc1 : t0 == 2 ? acc2 : acc3);
       }
     }
   }
@@ -761,13 +776,13 @@ k_aev_bwd(const float4 *__restrict__ pos, const int *__restrict__ sys_of,
 }
 
 // Waves per workgroup: the preference (1, 2 or 4) when its LDS fits in
-// 64 KB, else the most that fit.
+// 64 KB, else one.  One is the default: each wave works on its own centre,
+// and single-wave workgroups pack the compute units most freely (it was the
+// fastest shape on most measured batches).
 template <bool BWD>
 static int waves_for_cap(int cap, int pref) {
   const size_t per = wave_lds_bytes<BWD>(cap);
   if ((pref == 1 || pref == 2 || pref == 4) && per * pref <= 64 * 1024) return pref;
-  if (per * 4 <= 64 * 1024) return 4;
-  if (per * 2 <= 64 * 1024) return 2;
   return 1;
 }
 

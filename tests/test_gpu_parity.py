@@ -96,6 +96,30 @@ def test_aev_matches_oracle(m32, oracle_lib, name):
     assert worst < 2e-5
 
 
+def test_aev_rows_rewritten_whole(spec, oracle_lib):
+    """Every call rewrites each feature row whole: after a batch with many
+    species, a water box (H and O only) reuses the same rows, and the blocks
+    of species pairs with no pair around a centre read exactly zero, in
+    float32 and in bfloat16 feature rows."""
+    from paper_2207_14276_amd import NNPModel
+    first = synth.ragged_solutes(16, seed=12)
+    second = synth.make_batch([synth.config1()])
+    ref = oracle_lib.aev(second.coords, second.species, second.boxes[0], spec.aev)
+    zero_cols = np.all(ref == 0.0, axis=0)
+    assert zero_cols.sum() > 0
+    for prec, tol in (("fp32", 2e-5), ("bf16", 4e-3)):
+        m = NNPModel(spec, prec)
+        c, s, bx, o = to_dev(first)
+        m.aev(c, s, bx, o)
+        c, s, bx, o = to_dev(second)
+        G = m.aev(c, s, bx, o).cpu().numpy().astype(np.float64)
+        err = np.abs(G - ref) / (1.0 + np.abs(ref))
+        log(f"[aev reuse] {prec}: max |dG|/(1+|G|) = {err.max():.3e}, zero columns = {int(zero_cols.sum())}")
+        assert err.max() < tol
+        assert np.all(G[:, zero_cols] == 0.0)
+        m.close()
+
+
 def _check_energy_forces(model, oracle_lib, om, b, systems, e_atom_tol, e_sys_tol, f_tol, label):
     gpu = run_gpu(model, b)
     ora = oracle_lib.batch_energy_forces(b, om, systems=systems)
