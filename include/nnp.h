@@ -306,14 +306,15 @@ int nnp_sched_info(nnp_sched *sched, int64_t *info);
  *                    (candidates whose LDS does not fit are skipped);
  *   site 2 + l       dense layer l forward GEMM: column-tile width 64 or 128;
  *   site 10 + l      dense layer l input-gradient GEMM: width 64 or 128;
- *   site 18          the dE/dG GEMM: width 64 or 128.
+ *   site 18          the dE/dG GEMM: width 64 or 128;
+ *   site 19          the fused hidden-layer chain: 4 or 8 waves per workgroup.
  * The choices stay with the model for all later calls (no call changes any
  * result: tile shapes change no per-element arithmetic order); sites that did
  * not run keep their default (0).  Waits for the stream; allocates. */
 int nnp_autotune(nnp_model *model, int n_systems, const int64_t *batch_offsets, const float *coords,
                  const int32_t *species, const float *box, void *stream);
 /* Copies up to n tuned site values (0 = default shape) into values; returns
- * the number of sites (19). */
+ * the number of sites (20). */
 int nnp_tuning(const nnp_model *model, int *values, int n);
 
 /* Waits for `stream` and returns the device flags raised since the last

@@ -75,7 +75,7 @@ constexpr int kStages = 8;
 // Tunable launch shapes ("sites"): waves per workgroup of the AEV forward and
 // backward kernels, column-tile width of each dense-layer GEMM.
 enum { kSiteAevFwd = 0, kSiteAevBwd = 1, kSiteGemmFwd = 2, kSiteGemmBwd = 10, kSiteGemmOut = 18,
-       kTuneSites = 19 };
+       kSiteChain = 19, kTuneSites = 20 };
 constexpr int kMaxTimedCalls = 4096;  // timed calls held between two reads
 const char *kStageNames[kStages] = {"ingest", "cells", "neighbours", "buckets",
                                     "aev_fwd", "mlp", "aev_bwd", "reduce"};
@@ -813,7 +813,9 @@ static int run(nnp_model *m, int n_sys, const int64_t *offs, const float *coords
     cl.e_mem = m->e_mem.as<float>();
     cl.perm = m->perm.as<int>();
     cl.e_atom = m->e_atom.as<float>();
-    launch_chain(cl, L - 2, want_grad, rows, m->chain_lds, st);
+    site_begin(kSiteChain);
+    launch_chain(cl, L - 2, want_grad, rows, m->chain_lds, m->tune_val[kSiteChain] == 4 ? 4 : 8, st);
+    site_end(kSiteChain);
   } else {
     EnergyLaunch el{};
     el.Hin = L >= 2 ? m->H[L - 2].p : m->G.p;
@@ -960,14 +962,16 @@ extern "C" int nnp_autotune(nnp_model *m, int n_systems, const int64_t *offs, co
   CallOut o;
   o.energy = energy;
   o.forces = forces;
-  // candidates: round r sets every GEMM site to kTn[r] and both AEV sites to kWpb[r]
+  // candidates: round r sets every GEMM site to kTn[r], both AEV sites to
+  // kWpb[r] and the fused chain to kChainW[r] waves per workgroup
   constexpr int kRounds = 3, kReps = 3;
-  const int kTn[kRounds] = {64, 128, 64}, kWpb[kRounds] = {1, 2, 4};
+  const int kTn[kRounds] = {64, 128, 64}, kWpb[kRounds] = {1, 2, 4}, kChainW[kRounds] = {8, 4, 8};
   double t[kTuneSites][kRounds] = {};
   bool hit[kTuneSites] = {};
   int rc = NNP_OK;
   for (int r = 0; r < kRounds && rc == NNP_OK; ++r) {
-    for (int q = 0; q < kTuneSites; ++q) m->tune_val[q] = q < kSiteGemmFwd ? kWpb[r] : kTn[r];
+    for (int q = 0; q < kTuneSites; ++q)
+      m->tune_val[q] = q < kSiteGemmFwd ? kWpb[r] : q == kSiteChain ? kChainW[r] : kTn[r];
     rc = run(m, n_systems, offs, coords, species, box, o, st, kFull);  // warm-up
     for (int k = 0; k < kReps && rc == NNP_OK; ++k) {
       m->tuning = true;
@@ -992,6 +996,8 @@ extern "C" int nnp_autotune(nnp_model *m, int n_systems, const int64_t *offs, co
       int best = 0;
       for (int r = 1; r < kRounds; ++r) if (t[q][r] < t[q][best]) best = r;
       m->tune_val[q] = kWpb[best];
+    } else if (q == kSiteChain) {
+      m->tune_val[q] = std::min(t[q][0], t[q][2]) <= t[q][1] ? 8 : 4;
     } else {
       m->tune_val[q] = std::min(t[q][0], t[q][2]) <= t[q][1] ? 64 : 128;
     }

@@ -12,10 +12,11 @@
 // keeping every h_l / d_l tile in LDS (bfloat16, rows padded by 8 elements)
 // and writing only d_0 (the input gradient the AEV-gradient GEMM needs) and
 // the member's energy per row.  The products use v_mfma_f32_16x16x32_bf16:
-// each wave owns every 4th 16-column block of a layer's output; it reads
-// the A fragments of a K step from LDS once for all its blocks and loads the
-// next step's B fragments (weights, L2-resident) during the current MFMAs.  Activations are rounded to bfloat16 exactly where the unfused path
-// stores them, so both paths give the same results.
+// with W waves per workgroup (4 or 8, a tuned launch shape) each wave owns
+// every W-th 16-column block of a layer's output; it reads the A fragments
+// of a K step from LDS once for all its blocks and loads the next step's B
+// fragments (weights, L2-resident) during the current MFMAs.  Activations
+// are rounded to bfloat16 exactly where the unfused path stores them.
 #include "internal.h"
 
 namespace nnp {
@@ -32,12 +33,11 @@ __device__ inline float from_bf16(uint16_t h) { return __uint_as_float((uint32_t
 __device__ inline float celu_f(float z, float alpha) { return z > 0.f ? z : alpha * expm1f(z / alpha); }
 __device__ inline float dcelu_h(float h, float alpha) { return h > 0.f ? 1.f : 1.f + h / alpha; }
 
-// Sum over aligned groups of 16 lanes (DPP), result in every lane of the group.
-__device__ inline float sum16_dpp(float v) {
+// Sum over aligned groups of 8 lanes (DPP), result in every lane of the group.
+__device__ inline float sum8_dpp(float v) {
   v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, false));
   v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x4E, 0xF, 0xF, false));
   v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x141, 0xF, 0xF, false));
-  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x140, 0xF, 0xF, false));
   return v;
 }
 
@@ -46,36 +46,37 @@ __device__ inline float sum16_dpp(float v) {
 // For every 16-column block owned by this wave, epi(cb, acc0, acc1) gets the
 // accumulators of rows 0-15 and 16-31: lane l holds column 16 cb + l % 16,
 // rows 4 (l / 16) + j (j = 0..3) of each half.
-template <class Epi>
+template <int W, class Epi>
 __device__ inline void chain_gemm(const uint16_t *A, int lda, int K, const uint16_t *__restrict__ B, int ldb,
                                   int N, int wave, int lane, Epi &&epi) {
+  constexpr int QM = 16 / W;                      // blocks per wave at N = 256
   const int l16 = lane & 15, kq = lane >> 4;
   const int nkb = K / 32, ncb = N / 16;
-  // this wave's blocks: wave + 4 q, q < nq (N <= 256: at most 4).  K-step
-  // outer, blocks inner: the A fragments of a K step are read from LDS once
-  // for all of the wave's blocks, and the next step's B fragments are loaded
-  // while the current step's MFMAs run.
-  const int nq = ncb > wave ? (ncb - wave + 3) / 4 : 0;
+  // this wave's blocks: wave + W q, q < nq (N <= 256: at most 16 / W).
+  // K-step outer, blocks inner: the A fragments of a K step are read from
+  // LDS once for all of the wave's blocks, and the next step's B fragments
+  // are loaded while the current step's MFMAs run.
+  const int nq = ncb > wave ? (ncb - wave + W - 1) / W : 0;
   if (nq == 0) return;
-  floatx4_t acc[4][2];
+  floatx4_t acc[QM][2];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) acc[q][0] = acc[q][1] = floatx4_t{0.f, 0.f, 0.f, 0.f};
+  for (int q = 0; q < QM; ++q) acc[q][0] = acc[q][1] = floatx4_t{0.f, 0.f, 0.f, 0.f};
   const uint16_t *bp = B + (size_t)(wave * 16 + l16) * ldb + 8 * kq;
-  const size_t bstep = (size_t)64 * ldb;          // 4 blocks of 16 rows
-  uint4 bc[4], bn[4];
+  const size_t bstep = (size_t)16 * W * ldb;      // W blocks of 16 rows
+  uint4 bc[QM], bn[QM];
 #pragma unroll
-  for (int q = 0; q < 4; ++q)
+  for (int q = 0; q < QM; ++q)
     if (q < nq) bc[q] = *(const uint4 *)(bp + q * bstep);
   for (int kb = 0; kb < nkb; ++kb) {
     if (kb + 1 < nkb) {
 #pragma unroll
-      for (int q = 0; q < 4; ++q)
+      for (int q = 0; q < QM; ++q)
         if (q < nq) bn[q] = *(const uint4 *)(bp + q * bstep + (kb + 1) * 32);
     }
     const bf16x8_t a0 = __builtin_bit_cast(bf16x8_t, *(const uint4 *)(A + l16 * lda + kb * 32 + 8 * kq));
     const bf16x8_t a1 = __builtin_bit_cast(bf16x8_t, *(const uint4 *)(A + (16 + l16) * lda + kb * 32 + 8 * kq));
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < QM; ++q) {
       if (q < nq) {
         const bf16x8_t b = __builtin_bit_cast(bf16x8_t, bc[q]);
         acc[q][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b, acc[q][0], 0, 0, 0);
@@ -83,17 +84,16 @@ __device__ inline void chain_gemm(const uint16_t *A, int lda, int K, const uint1
       }
     }
 #pragma unroll
-    for (int q = 0; q < 4; ++q) bc[q] = bn[q];
+    for (int q = 0; q < QM; ++q) bc[q] = bn[q];
   }
 #pragma unroll
-  for (int q = 0; q < 4; ++q)
-    if (q < nq) epi(wave + 4 * q, acc[q][0], acc[q][1]);
+  for (int q = 0; q < QM; ++q)
+    if (q < nq) epi(wave + W * q, acc[q][0], acc[q][1]);
 }
 
-template <int NL, bool GRAD>
-__global__ void __launch_bounds__(256) k_chain(ChainLaunch cl) {
+template <int NL, bool GRAD, int W>
+__global__ void __launch_bounds__(W * kWave) k_chain(ChainLaunch cl) {
   extern __shared__ uint4 chain_lds[];
-  __shared__ float e_red[4][kChainRows];
   const int tid = threadIdx.x, wave = __builtin_amdgcn_readfirstlane(tid / kWave), lane = tid % kWave;
   const int l16 = lane & 15, kq = lane >> 4;
   // member-major logical order, contiguous per XCD: an XCD works through the
@@ -123,7 +123,6 @@ __global__ void __launch_bounds__(256) k_chain(ChainLaunch cl) {
   }
   __syncthreads();
 
-  float ep[2][4] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};  // energy partials (last layer)
 #pragma unroll
   for (int l = 1; l <= NL; ++l) {
     const int K = net.width[l - 1], N = net.width[l];
@@ -131,7 +130,7 @@ __global__ void __launch_bounds__(256) k_chain(ChainLaunch cl) {
     uint16_t *out = act[l];
     const int ldo = cl.lds_ld[l];
     if (l < NL) {
-      chain_gemm(act[l - 1], cl.lds_ld[l - 1], K, net.W[l - 1], K, N, wave, lane,
+      chain_gemm<W>(act[l - 1], cl.lds_ld[l - 1], K, net.W[l - 1], K, N, wave, lane,
                  [&](int cb, floatx4_t a0, floatx4_t a1) {
                    const int col = cb * 16 + l16;
                    const float bc = bias[col];
@@ -142,39 +141,51 @@ __global__ void __launch_bounds__(256) k_chain(ChainLaunch cl) {
                    }
                  });
     } else {
-      // last hidden layer: energy partials and d_last = w_out CELU'(h) / M
-      chain_gemm(act[l - 1], cl.lds_ld[l - 1], K, net.W[l - 1], K, N, wave, lane,
+      // last hidden layer: h_last (bfloat16) into its tile
+      chain_gemm<W>(act[l - 1], cl.lds_ld[l - 1], K, net.W[l - 1], K, N, wave, lane,
                  [&](int cb, floatx4_t a0, floatx4_t a1) {
                    const int col = cb * 16 + l16;
-                   const float bc = bias[col], wo = net.w_out[col];
+                   const float bc = bias[col];
 #pragma unroll
                    for (int j = 0; j < 4; ++j) {
-                     const float h0 = from_bf16(to_bf16(celu_f(a0[j] + bc, cl.alpha)));
-                     const float h1 = from_bf16(to_bf16(celu_f(a1[j] + bc, cl.alpha)));
-                     ep[0][j] += h0 * wo;
-                     ep[1][j] += h1 * wo;
-                     if (GRAD) {
-                       out[(4 * kq + j) * ldo + col] = to_bf16(wo * dcelu_h(h0, cl.alpha) * cl.inv_m);
-                       out[(16 + 4 * kq + j) * ldo + col] = to_bf16(wo * dcelu_h(h1, cl.alpha) * cl.inv_m);
-                     }
+                     out[(4 * kq + j) * ldo + col] = to_bf16(celu_f(a0[j] + bc, cl.alpha));
+                     out[(16 + 4 * kq + j) * ldo + col] = to_bf16(celu_f(a1[j] + bc, cl.alpha));
                    }
                  });
     }
     __syncthreads();
   }
 
-  // the member's energy of each row: reduce over columns (lanes, then waves)
+  // the member's energy of each row, E = h_last . w_out + b_out, and (for
+  // forces) d_last = w_out CELU'(h_last) / M in place of h_last.  Eight
+  // threads per row, each over the 8-column chunks seg, seg + 8, ..., then
+  // summed over the eight: a fixed order, whatever the workgroup's shape.
+  {
+    const int N = net.width[NL], nch = N / 8, ldo = cl.lds_ld[NL];
+    uint16_t *hl = act[NL];
+    if (tid < kChainRows * 8) {
+      const int row = tid >> 3, seg = tid & 7;
+      float e = 0.f;
+      for (int ch = seg; ch < nch; ch += 8) {
+        uint4 u = *(const uint4 *)(hl + row * ldo + ch * 8);
+        const float4 w0 = *(const float4 *)(net.w_out + ch * 8);
+        const float4 w1 = *(const float4 *)(net.w_out + ch * 8 + 4);
+        const float wv[8] = {w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, w1.w};
+        uint16_t hv[8];
+        *(uint4 *)hv = u;
 #pragma unroll
-  for (int h = 0; h < 2; ++h)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const float v = sum16_dpp(ep[h][j]);
-      if (l16 == 0) e_red[wave][16 * h + 4 * kq + j] = v;
+        for (int k = 0; k < 8; ++k) {
+          const float h = from_bf16(hv[k]);
+          e += h * wv[k];
+          hv[k] = to_bf16(wv[k] * dcelu_h(h, cl.alpha) * cl.inv_m);
+        }
+        if (GRAD) *(uint4 *)(hl + row * ldo + ch * 8) = *(const uint4 *)hv;
+      }
+      e = sum8_dpp(e);
+      if (seg == 0) cl.e_mem[(size_t)(r0 + row) * cl.n_members + mb] = e + net.b_out;
     }
-  __syncthreads();
-  if (tid < kChainRows)
-    cl.e_mem[(size_t)(r0 + tid) * cl.n_members + mb] =
-        e_red[0][tid] + e_red[1][tid] + e_red[2][tid] + e_red[3][tid] + net.b_out;
+    __syncthreads();
+  }
   if (!GRAD) return;
 
   // backward: d_{l-1} = (d_l W_l) * CELU'(h_{l-1}), in place over h_{l-1}
@@ -183,7 +194,7 @@ __global__ void __launch_bounds__(256) k_chain(ChainLaunch cl) {
     const int K = net.width[l], N = net.width[l - 1];
     uint16_t *hd = act[l - 1];
     const int ldo = cl.lds_ld[l - 1];
-    chain_gemm(act[l], cl.lds_ld[l], K, net.Wt[l - 1], K, N, wave, lane,
+    chain_gemm<W>(act[l], cl.lds_ld[l], K, net.Wt[l - 1], K, N, wave, lane,
                [&](int cb, floatx4_t a0, floatx4_t a1) {
                  const int col = cb * 16 + l16;
 #pragma unroll
@@ -222,19 +233,27 @@ __global__ void k_chain_mean(const float *__restrict__ e_mem, int M, const int *
   e_atom[atom] = e * inv_m;
 }
 
-void launch_chain(const ChainLaunch &cl, int n_hidden, bool grad, int rows, size_t lds_bytes, hipStream_t st) {
+template <int W>
+static void chain_t(const ChainLaunch &cl, int n_hidden, bool grad, unsigned blocks, size_t lds_bytes,
+                    hipStream_t st) {
+  if (n_hidden == 1) {
+    if (grad) k_chain<1, true, W><<<blocks, W * kWave, lds_bytes, st>>>(cl);
+    else k_chain<1, false, W><<<blocks, W * kWave, lds_bytes, st>>>(cl);
+  } else if (n_hidden == 2) {
+    if (grad) k_chain<2, true, W><<<blocks, W * kWave, lds_bytes, st>>>(cl);
+    else k_chain<2, false, W><<<blocks, W * kWave, lds_bytes, st>>>(cl);
+  } else {
+    if (grad) k_chain<3, true, W><<<blocks, W * kWave, lds_bytes, st>>>(cl);
+    else k_chain<3, false, W><<<blocks, W * kWave, lds_bytes, st>>>(cl);
+  }
+}
+
+void launch_chain(const ChainLaunch &cl, int n_hidden, bool grad, int rows, size_t lds_bytes, int waves,
+                  hipStream_t st) {
   const unsigned blocks = (unsigned)(rows / kChainRows * cl.n_members);
   if (blocks == 0) return;
-  if (n_hidden == 1) {
-    if (grad) k_chain<1, true><<<blocks, 256, lds_bytes, st>>>(cl);
-    else k_chain<1, false><<<blocks, 256, lds_bytes, st>>>(cl);
-  } else if (n_hidden == 2) {
-    if (grad) k_chain<2, true><<<blocks, 256, lds_bytes, st>>>(cl);
-    else k_chain<2, false><<<blocks, 256, lds_bytes, st>>>(cl);
-  } else {
-    if (grad) k_chain<3, true><<<blocks, 256, lds_bytes, st>>>(cl);
-    else k_chain<3, false><<<blocks, 256, lds_bytes, st>>>(cl);
-  }
+  if (waves == 4) chain_t<4>(cl, n_hidden, grad, blocks, lds_bytes, st);
+  else chain_t<8>(cl, n_hidden, grad, blocks, lds_bytes, st);
   k_chain_mean<<<(rows + 255) / 256, 256, 0, st>>>(cl.e_mem, cl.n_members, cl.perm, cl.bucket_off, cl.n_groups,
                                                     rows, cl.inv_m, cl.e_atom);
 }

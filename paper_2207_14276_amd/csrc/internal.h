@@ -190,7 +190,8 @@ void launch_aev_bwd(const float4 *pos, const int *sys_of, const SysDesc *sys, co
 // wpb_pref below: waves per workgroup 1, 2 or 4 when the LDS fits (else the default).
 void launch_gemm(int epi, bool bf16, GemmLaunch gl, int row_tiles, int max_n_out, int tn_pref, hipStream_t st);
 void launch_energy(const EnergyLaunch &el, bool bf16, int rows, hipStream_t st);
-void launch_chain(const ChainLaunch &cl, int n_hidden, bool grad, int rows, size_t lds_bytes, hipStream_t st);
+void launch_chain(const ChainLaunch &cl, int n_hidden, bool grad, int rows, size_t lds_bytes, int waves,
+                  hipStream_t st);
 void launch_fill(float *p, size_t n, float v, hipStream_t st);
 void launch_fill_i32(int *p, size_t n, int v, hipStream_t st);
 void launch_reduce(const float *e_atom, const float *W_atom, const SysDesc *sys, int n_sys,

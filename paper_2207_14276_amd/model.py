@@ -155,7 +155,7 @@ class NNPModel:
     def tuning(self) -> dict:
         vals = (C.c_int * 32)()
         n = nat.check(nat.load().nnp_tuning(self._h, vals, 32))
-        names = {0: "aev_fwd_waves", 1: "aev_bwd_waves", 18: "gemm_dEdG_tn"}
+        names = {0: "aev_fwd_waves", 1: "aev_bwd_waves", 18: "gemm_dEdG_tn", 19: "chain_waves"}
         out = {}
         for q in range(n):
             if vals[q]:
