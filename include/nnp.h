@@ -304,9 +304,11 @@ int nnp_sched_info(nnp_sched *sched, int64_t *info);
  * with HIP events on `stream`:
  *   site 0, 1        AEV forward / backward: waves per workgroup 1, 2 or 4
  *                    (candidates whose LDS does not fit are skipped);
- *   site 2 + l       dense layer l forward GEMM: column-tile width 64 or 128;
- *   site 10 + l      dense layer l input-gradient GEMM: width 64 or 128;
- *   site 18          the dE/dG GEMM: width 64 or 128;
+ *   site 2 + l       dense layer l forward GEMM: column-tile width 64, 128
+ *                    or 256 (256: for a layer whose members share the input,
+ *                    the members' columns side by side in one tile space);
+ *   site 10 + l      dense layer l input-gradient GEMM: width 64, 128 or 256;
+ *   site 18          the dE/dG GEMM: width 64, 128 or 256;
  *   site 19          the fused hidden-layer chain: 4 or 8 waves per workgroup.
  * The choices stay with the model for all later calls (no call changes any
  * result: tile shapes change no per-element arithmetic order); sites that did

@@ -965,7 +965,7 @@ extern "C" int nnp_autotune(nnp_model *m, int n_systems, const int64_t *offs, co
   // candidates: round r sets every GEMM site to kTn[r], both AEV sites to
   // kWpb[r] and the fused chain to kChainW[r] waves per workgroup
   constexpr int kRounds = 3, kReps = 3;
-  const int kTn[kRounds] = {64, 128, 64}, kWpb[kRounds] = {1, 2, 4}, kChainW[kRounds] = {8, 4, 8};
+  const int kTn[kRounds] = {64, 128, 256}, kWpb[kRounds] = {1, 2, 4}, kChainW[kRounds] = {8, 4, 8};
   double t[kTuneSites][kRounds] = {};
   bool hit[kTuneSites] = {};
   int rc = NNP_OK;
@@ -992,14 +992,12 @@ extern "C" int nnp_autotune(nnp_model *m, int n_systems, const int64_t *offs, co
   for (int q = 0; q < kTuneSites; ++q) {
     m->tune_val[q] = 0;
     if (!hit[q] || rc) continue;
-    if (q < kSiteGemmFwd) {
-      int best = 0;
-      for (int r = 1; r < kRounds; ++r) if (t[q][r] < t[q][best]) best = r;
-      m->tune_val[q] = kWpb[best];
-    } else if (q == kSiteChain) {
+    if (q == kSiteChain) {
       m->tune_val[q] = std::min(t[q][0], t[q][2]) <= t[q][1] ? 8 : 4;
     } else {
-      m->tune_val[q] = std::min(t[q][0], t[q][2]) <= t[q][1] ? 64 : 128;
+      int best = 0;
+      for (int r = 1; r < kRounds; ++r) if (t[q][r] < t[q][best]) best = r;
+      m->tune_val[q] = q < kSiteGemmFwd ? kWpb[best] : kTn[best];
     }
   }
   (void)hipFree(energy);

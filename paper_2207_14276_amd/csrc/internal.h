@@ -115,6 +115,7 @@ struct GemmLaunch {
   int n_seg;                   // K segments summed into one output
   int col_tiles;               // set by the launcher
   int k32;                     // every K and stride allows 32-wide K chunks (direct-to-LDS kernel)
+  int span;                    // set by the launcher: members' columns side by side
   GemmGroup g[kMaxMembers * kMaxSpecies];  // [member][species]
   float alpha;                 // CELU alpha
   float scale;

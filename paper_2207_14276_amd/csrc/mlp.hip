@@ -20,6 +20,8 @@
 // an A row tile) run on the same XCD and hit the same L2.
 #include "internal.h"
 
+#include <algorithm>
+
 namespace nnp {
 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
@@ -268,14 +270,17 @@ template <> struct Vec8<false> {
 // their results are discarded.
 __device__ inline int lds_swz(int r) { return ((r >> 1) ^ (r >> 3)) & 3; }
 
-template <int EPI, int TN>
-__global__ void __launch_bounds__(256) k_gemm_dl(GemmLaunch gl) {
+// 256-wide tiles hold 128 accumulator registers per lane; the kernel is
+// held to 256 registers in all so that two workgroups share a compute unit.
+template <int EPI, int TN, bool SPAN>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TN == 256 ? 2 : 1)))
+k_gemm_dl(GemmLaunch gl) {
   typedef uint16_t T;
   constexpr int TM = kTileM;
   constexpr int TK = 32;
   constexpr int STAGES = 3;
-  constexpr int WM = TN == 128 ? 64 : 32;
-  constexpr int WN = 64;
+  constexpr int WM = TN == 64 ? 32 : 64;
+  constexpr int WN = TN == 256 ? 128 : 64;
   constexpr int WAVES_N = TN / WN;
   constexpr int BM = WM / 32, BN = WN / 32;
   constexpr int A_SLOTS = TM * 4, B_SLOTS = TN * 4;  // 16-byte slots per stage
@@ -288,16 +293,19 @@ __global__ void __launch_bounds__(256) k_gemm_dl(GemmLaunch gl) {
   const int lb = xcd_logical(blockIdx.x, nb);
   const int n_ct = gl.col_tiles;
   const int ct = lb % n_ct;
-  const int mb = (lb / n_ct) % gl.n_members;
-  const int rt = lb / (n_ct * gl.n_members);
+  // SPAN: the output columns of all members side by side (member-major), one
+  // column space of n_members * n_out; every member reads the same A
+  const int mb = SPAN ? 0 : (lb / n_ct) % gl.n_members;
+  const int rt = SPAN ? lb / n_ct : lb / (n_ct * gl.n_members);
   const int r0 = rt * TM;
   int s = -1;
   for (int q = 0; q < gl.n_groups; ++q)
     if (r0 >= gl.bucket_off[q] && r0 < gl.bucket_off[q + 1]) s = q;
   if (s < 0) return;
   const GemmGroup grp = gl.g[mb * gl.n_groups + s];
+  const int n_cols = SPAN ? grp.n_out * gl.n_members : grp.n_out;
   const int c0 = ct * TN;
-  if (c0 >= grp.n_out) return;
+  if (c0 >= n_cols) return;
   const int K = grp.K;
   const int nseg = gl.n_seg;
   const int nk = K / TK;
@@ -322,8 +330,13 @@ __global__ void __launch_bounds__(256) k_gemm_dl(GemmLaunch gl) {
 #pragma unroll
   for (int q = 0; q < B_LD; ++q) {
     const int sl = q * 256 + tid, row = sl >> 2, kc = (sl & 3) ^ lds_swz(row);
-    const int col = min(c0 + row, grp.n_out - 1);
-    bsrc[q] = B + (size_t)col * ldb + kc * 8;
+    const int col = min(c0 + row, n_cols - 1);
+    if (SPAN) {
+      const int m = col / grp.n_out;
+      bsrc[q] = (const T *)gl.g[m * gl.n_groups + s].B + (size_t)(col - m * grp.n_out) * ldb + kc * 8;
+    } else {
+      bsrc[q] = B + (size_t)col * ldb + kc * 8;
+    }
   }
   auto issue = [&](int c, int stage) {
     const int seg = c / nk, k0 = (c % nk) * TK;
@@ -408,8 +421,12 @@ __global__ void __launch_bounds__(256) k_gemm_dl(GemmLaunch gl) {
         const int chunk = q * kWave + lane;     // 128 chunks of 8: 32 rows x 4
         const int rr = chunk >> 2, cc = (chunk & 3) * 8;
         const int row = r0 + wr * WM + bi * 32 + rr;
-        const int col = c0 + wc * WN + bj * 32 + cc;
-        if (col >= grp.n_out) continue;
+        const int vcol = c0 + wc * WN + bj * 32 + cc;
+        if (vcol >= n_cols) continue;
+        // the member and its column (8-column chunks never straddle members:
+        // output widths are multiples of 8)
+        const int om = SPAN ? vcol / grp.n_out : mb;
+        const int col = SPAN ? vcol - om * grp.n_out : vcol;
         float v[8];
         const float4 v0 = *(const float4 *)(ep + rr * EP_LD + cc);
         const float4 v1 = *(const float4 *)(ep + rr * EP_LD + cc + 4);
@@ -417,10 +434,10 @@ __global__ void __launch_bounds__(256) k_gemm_dl(GemmLaunch gl) {
         v[4] = v1.x; v[5] = v1.y; v[6] = v1.z; v[7] = v1.w;
         if (EPI == kEpiFwd) {
           float b[8];
-          Vec8<false>::load(grp.bias + col, b);
+          Vec8<false>::load((SPAN ? gl.g[om * gl.n_groups + s].bias : grp.bias) + col, b);
 #pragma unroll
           for (int e = 0; e < 8; ++e) v[e] = celu(v[e] + b[e], gl.alpha);
-          Vec8<true>::store((T *)gl.C + (size_t)row * gl.ldc + (size_t)mb * gl.c_member_stride + col, v);
+          Vec8<true>::store((T *)gl.C + (size_t)row * gl.ldc + (size_t)om * gl.c_member_stride + col, v);
         } else if (EPI == kEpiBwd) {
           float h[8];
           Vec8<true>::load((const T *)gl.H + (size_t)row * gl.ldh + (size_t)mb * gl.h_member_stride + col, h);
@@ -442,14 +459,35 @@ __global__ void __launch_bounds__(256) k_gemm_dl(GemmLaunch gl) {
 
 template <int EPI, bool BF16>
 static void launch_t(const GemmLaunch &gl, int row_tiles, int tn, hipStream_t st) {
-  const unsigned blocks = (unsigned)(row_tiles * gl.n_members * gl.col_tiles);
+  const unsigned blocks = (unsigned)(row_tiles * (gl.span ? 1 : gl.n_members) * gl.col_tiles);
   if (BF16 && gl.k32) {
-    if (tn == 128) k_gemm_dl<EPI, 128><<<blocks, 256, 0, st>>>(gl);
-    else k_gemm_dl<EPI, 64><<<blocks, 256, 0, st>>>(gl);
+    if constexpr (EPI == kEpiFwd) {
+      if (gl.span) {
+        k_gemm_dl<EPI, 256, true><<<blocks, 256, 0, st>>>(gl);
+        return;
+      }
+    }
+    if (tn == 256) k_gemm_dl<EPI, 256, false><<<blocks, 256, 0, st>>>(gl);
+    else if (tn == 128) k_gemm_dl<EPI, 128, false><<<blocks, 256, 0, st>>>(gl);
+    else k_gemm_dl<EPI, 64, false><<<blocks, 256, 0, st>>>(gl);
     return;
   }
+  if (tn == 256) tn = 128;
   if (tn == 128) k_gemm<EPI, BF16, 128><<<blocks, 256, 0, st>>>(gl);
   else k_gemm<EPI, BF16, 64><<<blocks, 256, 0, st>>>(gl);
+}
+
+// Whether every member of a species group has the same output width, K and
+// B row stride (the members-side-by-side tiling needs it).
+static bool gemm_span_uniform(const GemmLaunch &gl) {
+  for (int s = 0; s < gl.n_groups; ++s) {
+    const GemmGroup &g0 = gl.g[s];
+    for (int m = 1; m < gl.n_members; ++m) {
+      const GemmGroup &g = gl.g[m * gl.n_groups + s];
+      if (g.n_out != g0.n_out || g.K != g0.K || g.ldb != g0.ldb || !g.B != !g0.B) return false;
+    }
+  }
+  return true;
 }
 
 // Whether every K chunk of 32 elements and every operand row start is
@@ -469,11 +507,26 @@ static bool gemm_k32(const GemmLaunch &gl) {
 void launch_gemm(int epi, bool bf16, GemmLaunch gl, int row_tiles, int max_n_out, int tn_pref, hipStream_t st) {
   if (row_tiles <= 0) return;
   gl.k32 = bf16 && gemm_k32(gl) ? 1 : 0;
-  // the tuned width, else 128-wide column tiles when they waste little, else 64
+  // 256-wide tiles (direct-to-LDS kernel only); for a forward layer whose
+  // members all read the same input, the members' columns side by side
+  const bool wide_ok = gl.k32 && max_n_out >= 160;
+  const bool span_ok = wide_ok && epi == kEpiFwd && gl.a_member_stride == 0 && gemm_span_uniform(gl);
+  // the tuned width, else: 256 for the AEV-gradient GEMM when that still
+  // gives several workgroups per compute unit; 128-wide column tiles when
+  // they waste little; else 64
   const int t128 = (max_n_out + 127) / 128 * 128, t64 = (max_n_out + 63) / 64 * 64;
-  const int tn = tn_pref == 64 || tn_pref == 128 ? tn_pref
-               : (t128 - max_n_out) * 4 <= max_n_out && t128 <= t64 + 32 ? 128 : 64;
-  gl.col_tiles = (max_n_out + tn - 1) / tn;
+  int tn = tn_pref == 64 || tn_pref == 128 || tn_pref == 256 ? tn_pref
+         : wide_ok && epi == kEpiOut && row_tiles * ((max_n_out + 255) / 256) >= 2048 ? 256
+         : (t128 - max_n_out) * 4 <= max_n_out && t128 <= t64 + 32 ? 128 : 64;
+  if (tn == 256 && !wide_ok) tn = 128;
+  gl.span = tn == 256 && span_ok ? 1 : 0;
+  int cols = max_n_out;
+  if (gl.span) {
+    cols = 0;
+    for (int s = 0; s < gl.n_groups; ++s)
+      if (gl.g[s].B) cols = std::max(cols, gl.g[s].n_out * gl.n_members);
+  }
+  gl.col_tiles = (cols + tn - 1) / tn;
   if (bf16) {
     if (epi == kEpiFwd) launch_t<kEpiFwd, true>(gl, row_tiles, tn, st);
     else if (epi == kEpiBwd) launch_t<kEpiBwd, true>(gl, row_tiles, tn, st);
