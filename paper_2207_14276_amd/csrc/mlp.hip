@@ -270,15 +270,30 @@ template <> struct Vec8<false> {
 // their results are discarded.
 __device__ inline int lds_swz(int r) { return ((r >> 1) ^ (r >> 3)) & 3; }
 
+// s_waitcnt immediate: vmcnt = n (bits 3:0 and 15:14), expcnt and lgkmcnt
+// left at their maxima.
+constexpr int vm_imm(int n) { return 0xF70 | (n & 15) | ((n >> 4) << 14); }
+
+// Waits until at most `ahead` chunks' worth of this wave's loads (LOADS
+// instructions per chunk) are outstanding; ahead is wave-uniform.
+template <int LOADS, int MAXA>
+__device__ inline void wait_chunks(int ahead) {
+  if (MAXA >= 3 && ahead >= 3) __builtin_amdgcn_s_waitcnt(vm_imm(3 * LOADS));
+  else if (MAXA >= 2 && ahead >= 2) __builtin_amdgcn_s_waitcnt(vm_imm(2 * LOADS));
+  else if (MAXA >= 1 && ahead >= 1) __builtin_amdgcn_s_waitcnt(vm_imm(LOADS));
+  else __builtin_amdgcn_s_waitcnt(vm_imm(0));
+}
+
 // 256-wide tiles hold 128 accumulator registers per lane; the kernel is
 // held to 256 registers in all so that two workgroups share a compute unit.
-template <int EPI, int TN, bool SPAN>
+// STAGES: depth of the operand ring; loads run STAGES - 1 chunks ahead.
+template <int EPI, int TN, bool SPAN, int STAGES>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TN == 256 ? 2 : 1)))
 k_gemm_dl(GemmLaunch gl) {
   typedef uint16_t T;
   constexpr int TM = kTileM;
   constexpr int TK = 32;
-  constexpr int STAGES = 3;
+  static_assert(STAGES >= 3 && STAGES <= 5, "ring depth");
   constexpr int WM = TN == 64 ? 32 : 64;
   constexpr int WN = TN == 256 ? 128 : 64;
   constexpr int WAVES_N = TN / WN;
@@ -359,21 +374,21 @@ k_gemm_dl(GemmLaunch gl) {
 #pragma unroll
     for (int j = 0; j < BN; ++j) acc[i][j] = floatx16{};
 
-  issue(0, 0);
-  if (total > 1) issue(1, 1);
+#pragma unroll
+  for (int q = 0; q < STAGES - 1; ++q)
+    if (q < total) issue(q, q);
   for (int c = 0; c < total; ++c) {
-    // this wave's loads of chunk c are done once at most chunk c+1's remain
-    // (vmcnt in the low bits; expcnt and lgkmcnt left at their maxima)
-    if (c + 1 < total) __builtin_amdgcn_s_waitcnt(0xF70 | LOADS);
-    else __builtin_amdgcn_s_waitcnt(0xF70);
+    // this wave's loads of chunk c are done once at most those of the
+    // chunks issued after it remain
+    wait_chunks<LOADS, STAGES - 2>(min(total - 1 - c, STAGES - 2));
     // a plain barrier: LDS is coherent within the workgroup, every wave has
     // waited for its own part of chunk c above, and its reads of the stage
     // overwritten next were consumed (by MFMAs) before it got here; a full
-    // __syncthreads() would also wait for the loads of chunk c + 1
+    // __syncthreads() would also wait for the loads of later chunks
     __builtin_amdgcn_s_barrier();
-    // stage (c + 2) % 3 was last read for chunk c - 1, which every wave has
-    // finished (barrier above)
-    if (c + 2 < total) issue(c + 2, (c + 2) % STAGES);
+    // stage (c + STAGES - 1) % STAGES was last read for chunk c - 1, which
+    // every wave has finished (barrier above)
+    if (c + STAGES - 1 < total) issue(c + STAGES - 1, (c + STAGES - 1) % STAGES);
     const uint4 *As = smem[c % STAGES];
     const uint4 *Bs = As + A_SLOTS;
 #pragma unroll
@@ -457,19 +472,22 @@ k_gemm_dl(GemmLaunch gl) {
   }
 }
 
+// operand ring depth per tile width
+constexpr int kStages128 = 3, kStages256 = 3;
+
 template <int EPI, bool BF16>
 static void launch_t(const GemmLaunch &gl, int row_tiles, int tn, hipStream_t st) {
   const unsigned blocks = (unsigned)(row_tiles * (gl.span ? 1 : gl.n_members) * gl.col_tiles);
   if (BF16 && gl.k32) {
     if constexpr (EPI == kEpiFwd) {
       if (gl.span) {
-        k_gemm_dl<EPI, 256, true><<<blocks, 256, 0, st>>>(gl);
+        k_gemm_dl<EPI, 256, true, kStages256><<<blocks, 256, 0, st>>>(gl);
         return;
       }
     }
-    if (tn == 256) k_gemm_dl<EPI, 256, false><<<blocks, 256, 0, st>>>(gl);
-    else if (tn == 128) k_gemm_dl<EPI, 128, false><<<blocks, 256, 0, st>>>(gl);
-    else k_gemm_dl<EPI, 64, false><<<blocks, 256, 0, st>>>(gl);
+    if (tn == 256) k_gemm_dl<EPI, 256, false, kStages256><<<blocks, 256, 0, st>>>(gl);
+    else if (tn == 128) k_gemm_dl<EPI, 128, false, kStages128><<<blocks, 256, 0, st>>>(gl);
+    else k_gemm_dl<EPI, 64, false, 3><<<blocks, 256, 0, st>>>(gl);
     return;
   }
   if (tn == 256) tn = 128;
