@@ -33,7 +33,8 @@ def parse():
     p.add_argument("--steps", type=int, default=20)
     p.add_argument("--warmup", type=int, default=5)
     p.add_argument("--workload", default="ragged512",
-                   choices=["ragged512", "water2001", "protein100k", "cluster24", "serve", "copy"])
+                   choices=["ragged512", "water2001", "protein100k", "cluster24", "serve", "copy",
+                            "hybrid"])
     p.add_argument("--precision", default="bf16", choices=["bf16", "fp32"])
     p.add_argument("--no-plain", action="store_true")
     p.add_argument("--no-cpu", action="store_true")
@@ -301,6 +302,127 @@ def serve_bench(args):
     print(json.dumps(out), flush=True)
 
 
+def hybrid_bench(args):
+    """The pair-list entry point on the 100k-atom solvated-protein box: the
+    ML region is the 30,000-atom protein (V_ML(P) of the hybrid potential,
+    8 networks), the caller's list is a full list of the whole box (every
+    neighbour pair within the radial cutoff, built once by the library's own
+    search and handed over as plain pairs).  Beside it: the same region as a
+    system of its own through the library's cell search."""
+    import torch
+    import synth
+    from paper_2207_14276_amd import NNPModel
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    full = synth.config3()
+    spec = synth.make_model(3, n_ensemble=8)
+    N = len(full.species)
+    n_ml = 30000
+    c = torch.as_tensor(full.coords, device=dev)
+    sp = torch.as_tensor(full.species, device=dev)
+    mask = torch.zeros(N, dtype=torch.uint8, device=dev)
+    mask[:n_ml] = 1
+    sub = synth.make_batch([synth.System(full.coords[:n_ml], full.species[:n_ml], full.box)])
+    cs, ss = c[:n_ml].contiguous(), sp[:n_ml].contiguous()
+
+    model = NNPModel(spec, args.precision)
+    cap = size_capacity(model, sub, cs, ss, n_ml, 1)
+    tuned = model.autotune(cs, ss, sub.boxes, sub.offsets)
+    # the caller's list: every (i, j, image) of the whole box within 5.1 A
+    model.reserve(N, 1, 128)
+    cnt, ent = model.neighbors(c, sp, full.box[None, :], np.array([0, N], np.int64), capacity=128)
+    model.reserve(N, 1, cap)
+    valid = torch.arange(128, device=dev)[None, :] < cnt.clamp(max=128)[:, None]
+    ii = torch.arange(N, device=dev, dtype=torch.int32)[:, None].expand(N, 128)[valid]
+    pairs = torch.stack([ii, ent[..., 0][valid]], 1).contiguous()
+    shifts = ent[..., 1:4][valid].contiguous()
+    say(args, f"hybrid: N={N} region={n_ml} caller pairs={pairs.shape[0]} capacity={cap}")
+
+    res = model.energy_forces_pairs(c, sp, full.box, pairs, shifts, mask, half=False, virial=True,
+                                    atom_energy=True, check=True)
+    for _ in range(args.warmup):
+        model.energy_forces_pairs(c, sp, full.box, pairs, shifts, mask, half=False, out=res)
+    st = torch.cuda.current_stream()
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    model.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        starts[k].record(st)
+        model.energy_forces_pairs(c, sp, full.box, pairs, shifts, mask, half=False, out=res)
+        ends[k].record(st)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    stages = model.stage_timings()
+    model.set_timing(False)
+    model.status()
+    lat = np.array([starts[k].elapsed_time(ends[k]) for k in range(args.steps)])
+    value = n_ml * args.steps / wall
+
+    # the same region through the library's own cell search
+    r2 = model.energy_forces(cs, ss, sub.boxes, sub.offsets, check=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        model.energy_forces(cs, ss, sub.boxes, sub.offsets, out=r2)
+    torch.cuda.synchronize()
+    own = n_ml * args.steps / (time.perf_counter() - t0)
+
+    n_pairs, n_trip = pair_triplet_counts(model, sub, cs, ss)
+    aev_fwd_flop = FLOP_RADIAL_FWD * n_pairs + FLOP_TRIPLET_FWD * n_trip
+    aev_bwd_flop = FLOP_RADIAL_BWD * n_pairs + FLOP_TRIPLET_BWD * n_trip
+    fwd_f, bwd_f = mlp_flops(spec, sub.species)
+    cand = {"aev_fwd": ("alu", aev_fwd_flop, PEAK_FP32_VALU_TFLOPS),
+            "aev_bwd": ("alu", aev_bwd_flop, PEAK_FP32_VALU_TFLOPS),
+            "mlp": ("mfma", fwd_f + bwd_f,
+                    PEAK_BF16_MFMA_TFLOPS if args.precision == "bf16" else PEAK_FP32_MFMA_TFLOPS)}
+    dom = max(cand, key=lambda k: stages.get(k, 0.0))
+    bound, work, peak = cand[dom]
+    achieved = work / (stages[dom] * 1e-3) / 1e12
+    kname = {"aev_fwd": "k_aev_fwd", "aev_bwd": "k_aev_bwd", "mlp": "k_gemm"}[dom]
+    out = {
+        "metric": "energy+force atom-evals/s (pair-list entry point, ML region)",
+        "value": round(value, 1),
+        "unit": "atom-evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall / args.steps * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16-mlp/f32-aev" if args.precision == "bf16" else "f32",
+        "data": "synthetic",
+        "config": {"workload": "hybrid: 30,000-atom protein region (8 networks) of the 100,002-atom "
+                               "solvated box, caller's full pair list of the whole box",
+                   "n_atoms": N, "n_region": n_ml, "caller_pairs": int(pairs.shape[0]),
+                   "nbr_capacity": cap, "tuned_shapes": tuned, "parallelism": "single GPU"},
+        "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 4),
+                       "p99": round(float(np.percentile(lat, 99)), 4)},
+        "stages_ms": {k: round(v, 4) for k, v in stages.items()},
+        "roofline": {"kernel": kname if dom != "mlp" else "k_gemm (all dense layers)", "bound": bound,
+                     "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+                     "frac": round(achieved / peak, 4), "traffic": None,
+                     "work_per_launch_flop": work, "avg_launch_ms": round(stages[dom], 4),
+                     "pairs": n_pairs, "triplets": n_trip},
+        "own_cell_search_same_region": {"value": round(own, 1), "unit": "atom-evals/s"},
+    }
+    if not args.no_cpu:
+        import oracle
+        om = oracle.OracleModel(spec)
+        tgt = np.sort(np.random.default_rng(0).choice(n_ml, 8, replace=False))
+        e_ref, f_ref = oracle.sampled(sub.coords, sub.species, sub.boxes[0], om, tgt)
+        F = res.forces.cpu().numpy()
+        out["error_vs_oracle"] = {
+            "sample": "8 atoms of the region (local evaluation of the region alone)",
+            "max_abs_dF": float(np.abs(F[tgt] - f_ref).max()),
+            "max_abs_dE_atom": float(np.abs(res.atom_energy.cpu().numpy()[tgt] - e_ref).max()),
+            "max_abs_F_outside_region": float(np.abs(F[n_ml:]).max())}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -319,6 +441,9 @@ def main():
         return
     if args.workload == "copy":
         copy_probe(args)
+        return
+    if args.workload == "hybrid":
+        hybrid_bench(args)
         return
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)

@@ -163,6 +163,45 @@ int nnp_energy_forces_nlist(nnp_model *model, nnp_nlist *list, int n_systems,
                             const float *box, double *energy, float *forces, double *virial,
                             float *atom_energy, void *stream);
 
+/* Energy and forces of one system from the caller's own pair list, over an
+ * ML region (section "A General Machine Learning Platform": the host MD code
+ * keeps the neighbour list and passes positions and pairs; section "Hybrid
+ * Model: Neural Network Solutes in AMOEBA Polarizable Solvent/Protein": the
+ * network sees only the solute P, whose environments contain solute atoms
+ * only, giving V_ML(P) of the hybrid potential).
+ *   n_atoms   atoms of the system (N).
+ *   coords    DEVICE float32[N][3], species DEVICE int32[N] (as above; the
+ *             species of every atom, inside the region or not, must be a
+ *             valid slot).
+ *   box       HOST float32[3]: lengths that scale the lattice shifts (0 for a
+ *             non-periodic system).  Coordinates are used as given (no
+ *             wrapping): a shift is relative to them.
+ *   pairs     DEVICE int32[n_pairs][2] (i, j): atom j moved by the lattice
+ *             vector shifts[p] * box is a neighbour of atom i.  half_list = 1:
+ *             each unordered pair appears once and both directions are used;
+ *             half_list = 0: each direction appears.  Pairs at a distance
+ *             >= rc_rad are ignored, so a list built with a larger cutoff
+ *             (and skin) may be passed.  A pair inside the cutoff listed
+ *             twice, an index outside [0, N), i == j with a zero shift, or a
+ *             shift component beyond +-511 sets a device flag (nnp_status ->
+ *             NNP_EINVAL).
+ *   shifts    DEVICE int32[n_pairs][3] or NULL (all zero).
+ *   ml_mask   DEVICE uint8[N] or NULL (every atom): atoms with a zero entry
+ *             are outside the ML region; pairs touching them are ignored,
+ *             they contribute no energy and receive zero force.
+ *   energy    DEVICE float64[1]: E_ML = sum of the atomic energies of the
+ *             region.  forces / virial / atom_energy as in nnp_energy_forces
+ *             (virial: -sum over pairs d (x) dE/dd with the image vectors).
+ * More than `capacity` neighbours of one atom inside the cutoff set the
+ * overflow flag (nnp_status -> NNP_ECAPACITY, with the largest count); the
+ * capacity is the model's (nnp_reserve).  Enqueues on `stream`; no host
+ * synchronization. */
+int nnp_energy_forces_pairs(nnp_model *model, int64_t n_atoms, const float *coords,
+                            const int32_t *species, const float *box, int64_t n_pairs,
+                            const int32_t *pairs, const int32_t *shifts, int half_list,
+                            const uint8_t *ml_mask, double *energy, float *forces, double *virial,
+                            float *atom_energy, void *stream);
+
 /* Waits for `stream`; *builds = number of system lists built in the pool so
  * far (forced and skin-triggered). */
 int nnp_nlist_builds(nnp_nlist *list, void *stream, int64_t *builds);

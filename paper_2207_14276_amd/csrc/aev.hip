@@ -412,7 +412,8 @@ k_aev_fwd(const float4 *__restrict__ pos, const int *__restrict__ sys_of,
   // index, descriptors and row pointers) in scalar registers
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave), lane = threadIdx.x % kWave;
   const int i = blockIdx.x * WPB + wave;
-  const bool live = i < N;
+  // an atom without a network row (outside a caller's mask) is skipped
+  const bool live = i < N && row_of_atom[i] >= 0;
   WaveLds w = carve<false>((char *)lds4 + wave * wave_lds_bytes<false>(cap), cap);
   float4 pi = make_float4(0.f, 0.f, 0.f, 0.f);
   float L[3] = {0.f, 0.f, 0.f};
@@ -565,7 +566,11 @@ k_aev_bwd(const float4 *__restrict__ pos, const int *__restrict__ sys_of,
   // index, descriptors and row pointers) in scalar registers
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave), lane = threadIdx.x % kWave;
   const int i = blockIdx.x * WPB + wave;
-  const bool live = i < N;
+  // an atom without a network row (outside a caller's mask) is skipped; its
+  // virial share is zero
+  const bool has_row = i < N && row_of_atom[i] >= 0;
+  const bool live = has_row;
+  if (i < N && !has_row && lane < 9) W_atom[(size_t)9 * i + lane] = 0.f;
   WaveLds w = carve<true>((char *)lds4 + wave * wave_lds_bytes<true>(cap), cap);
   float4 pi = make_float4(0.f, 0.f, 0.f, 0.f);
   float L[3] = {0.f, 0.f, 0.f};

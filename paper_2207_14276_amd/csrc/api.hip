@@ -535,6 +535,9 @@ extern "C" int nnp_status(nnp_model *m, void *stream, int *max_nbr) {
   HIP_TRY(hipMemset(m->status.p, 0, sizeof h));
   if (max_nbr) *max_nbr = h[1];
   if (h[0] & kStatBadSpecies) return fail(NNP_ESPECIES, "an atom's species index is outside the model");
+  if (h[0] & kStatBadPairs)
+    return fail(NNP_EINVAL, "pair list: an index outside the atoms, a self pair without shift, "
+                            "a shift beyond 511 boxes, or a pair listed twice");
   if (h[0] & kStatOverflow)
     return fail(NNP_ECAPACITY, "neighbour list overflow: %d neighbours, capacity %d", h[1], m->cap);
   return NNP_OK;
@@ -561,9 +564,19 @@ struct ListPool {
   const int32_t *rebuild = nullptr;  // nl: caller-forced rebuilds (nullable)
 };
 
+// A caller's pair list (nnp_energy_forces_pairs): one system whose
+// neighbour rows come from the list instead of the cell search.
+struct PairIn {
+  long long n = -1;                 // number of pairs; -1: not the pair-list entry point
+  const int32_t *pairs = nullptr;   // DEVICE [n][2]
+  const int32_t *shifts = nullptr;  // DEVICE [n][3] lattice shifts, or null (all zero)
+  const uint8_t *mask = nullptr;    // DEVICE [N] ML region, or null (every atom)
+  int half = 1;                     // 1: each unordered pair once; 0: each direction
+};
+
 static int run(nnp_model *m, int n_sys, const int64_t *offs, const float *coords,
                const int32_t *species, const float *box, const CallOut &o, hipStream_t st, Mode mode,
-               const ListPool &lp = ListPool()) {
+               const ListPool &lp = ListPool(), const PairIn &pin = PairIn()) {
   if (!m) return fail(NNP_EINVAL, "null model");
   if (n_sys < 1) return fail(NNP_EINVAL, "n_systems must be >= 1");
   if (!offs || !box) return fail(NNP_EINVAL, "null host array (batch_offsets / box)");
@@ -579,6 +592,11 @@ static int run(nnp_model *m, int n_sys, const int64_t *offs, const float *coords
   HIP_TRY(hipSetDevice(m->device));
 
   nnp_nlist *nl = lp.nl;
+  const bool pairs = pin.n >= 0;
+  if (pairs) {
+    if (n_sys != 1 || nl) return fail(NNP_EINVAL, "a pair list describes one system");
+    if (pin.n > 0 && !pin.pairs) return fail(NNP_EINVAL, "null pair list");
+  }
   if (nl) {
     if (!lp.slots) return fail(NNP_EINVAL, "null slot offsets");
     if (nl->device != m->device) return fail(NNP_EINVAL, "neighbour-list pool on another device");
@@ -610,6 +628,23 @@ static int run(nnp_model *m, int n_sys, const int64_t *offs, const float *coords
     d.n = (int)(offs[s + 1] - offs[s]);
     d.periodic = per ? 1 : 0;
     d.cell_off = (int)C;
+    if (pairs) {
+      // the caller's shifts refer to its own coordinates: no wrapping, no
+      // cells; the box lengths only scale the image vectors
+      d.periodic = 0;
+      for (int k = 0; k < 3; ++k) d.L[k] = b[k];
+      d.state_off = 0;
+      d.list_off = 0;
+      d.rebuild = 1;
+      d.cell_cap = 1;
+      C += 1;
+      sys_ch[s] = (int)ch_sys.size();
+      for (int b0 = d.atom_off; b0 < d.atom_off + d.n; b0 += 4096) {
+        ch_sys.push_back(s);
+        ch_begin.push_back(b0);
+      }
+      continue;
+    }
     if (nl) {
       d.state_off = lp.slots[s];
       d.list_off = lp.slots[s] * (int64_t)cap;
@@ -717,18 +752,26 @@ static int run(nnp_model *m, int n_sys, const int64_t *offs, const float *coords
   int *pool_cnt = nl ? nl->cnt.as<int>() : m->nbr_cnt.as<int>();
   AtomState *pool_state = nl ? nl->state.as<AtomState>() : m->state.as<AtomState>();
   if (nl) launch_skin_check(coords, dsys, n_sys, pool_state, 0.5f * nl->skin, nl->stats.as<int>(), st);
-  launch_ingest(coords, species, dsys, n_sys, N, m->S, pos, m->sys_of.as<int>(), pool_state, status, st);
+  launch_ingest(coords, species, pin.mask, dsys, n_sys, N, m->S, pos, m->sys_of.as<int>(), pool_state,
+                status, st);
   mark();
-  launch_grid(dsys, n_sys, pos, m->cell_count.as<int>(), rc_list, st);
-  launch_cell_count(pos, m->sys_of.as<int>(), dsys, N, m->cell_count.as<int>(), m->atom_cell.as<int>(),
-                    m->atom_slot.as<int>(), st);
-  launch_scan(m->cell_count.as<int>(), m->cell_start.as<int>(), (int)C, st);
-  launch_cell_scatter(m->atom_cell.as<int>(), m->atom_slot.as<int>(), m->cell_start.as<int>(), N,
-                      m->cell_atoms.as<int>(), st);
-  launch_cell_sort(m->cell_start.as<int>(), (int)C, m->cell_atoms.as<int>(), st);
-  mark();
-  launch_nbr_build(pos, m->sys_of.as<int>(), dsys, n_sys, (int)C, m->cell_start.as<int>(), m->cell_atoms.as<int>(), N,
-                   rc_list, cap, pool_nbr, pool_cnt, status, st);
+  if (pairs) {
+    // the caller's list replaces the cell search (stage "cells" stays empty)
+    mark();
+    launch_pairs_to_rows(pin.pairs, pin.shifts, pin.n, pin.half, pin.mask, pos, N, sd[0].L, rc_list, cap,
+                         pool_nbr, pool_cnt, status, st);
+  } else {
+    launch_grid(dsys, n_sys, pos, m->cell_count.as<int>(), rc_list, st);
+    launch_cell_count(pos, m->sys_of.as<int>(), dsys, N, m->cell_count.as<int>(), m->atom_cell.as<int>(),
+                      m->atom_slot.as<int>(), st);
+    launch_scan(m->cell_count.as<int>(), m->cell_start.as<int>(), (int)C, st);
+    launch_cell_scatter(m->atom_cell.as<int>(), m->atom_slot.as<int>(), m->cell_start.as<int>(), N,
+                        m->cell_atoms.as<int>(), st);
+    launch_cell_sort(m->cell_start.as<int>(), (int)C, m->cell_atoms.as<int>(), st);
+    mark();
+    launch_nbr_build(pos, m->sys_of.as<int>(), dsys, n_sys, (int)C, m->cell_start.as<int>(),
+                     m->cell_atoms.as<int>(), N, rc_list, cap, pool_nbr, pool_cnt, status, st);
+  }
   if (mode == kNbr) {
     launch_export_nbr(pool_nbr, pool_cnt, cap, dsys, m->sys_of.as<int>(), N, o.nb_counts,
                       o.nb_entries, o.nb_cap, st);
@@ -741,6 +784,8 @@ static int run(nnp_model *m, int n_sys, const int64_t *offs, const float *coords
   launch_species_bucket(pos, N, m->S, m->block_counts.as<int>(), nblk, m->bucket_off.as<int>(),
                         m->bucket_cnt.as<int>(), m->perm.as<int>(), m->row_of_atom.as<int>(), rows, st);
   if (mode == kFull && o.forces) launch_fill(o.forces, (size_t)3 * N, 0.f, st);
+  // atoms outside a caller's mask have no network: zero atomic energy
+  if (pin.mask) launch_fill(m->e_atom.as<float>(), (size_t)N, 0.f, st);
   mark();
   const int D = m->aev.D;
   const bool bf16 = m->precision == NNP_BF16;
@@ -919,6 +964,30 @@ extern "C" int nnp_energy_forces(nnp_model *m, int n_systems, const int64_t *off
   o.virial = virial;
   o.atom_energy = atom_energy;
   return run(m, n_systems, offs, coords, species, box, o, (hipStream_t)stream, kFull);
+}
+
+extern "C" int nnp_energy_forces_pairs(nnp_model *m, int64_t n_atoms, const float *coords,
+                                       const int32_t *species, const float *box, int64_t n_pairs,
+                                       const int32_t *pairs, const int32_t *shifts, int half_list,
+                                       const uint8_t *ml_mask, double *energy, float *forces,
+                                       double *virial, float *atom_energy, void *stream) {
+  if (n_atoms < 0) return fail(NNP_EINVAL, "n_atoms must be >= 0");
+  if (n_pairs < 0) return fail(NNP_EINVAL, "n_pairs must be >= 0");
+  if (n_pairs > ((int64_t)1 << 40)) return fail(NNP_EUNSUPPORTED, "more than 2^40 pairs");
+  if (half_list != 0 && half_list != 1) return fail(NNP_EINVAL, "half_list must be 0 or 1");
+  const int64_t offs[2] = {0, n_atoms};
+  CallOut o;
+  o.energy = energy;
+  o.forces = forces;
+  o.virial = virial;
+  o.atom_energy = atom_energy;
+  PairIn pin;
+  pin.n = n_pairs;
+  pin.pairs = pairs;
+  pin.shifts = shifts;
+  pin.mask = ml_mask;
+  pin.half = half_list;
+  return run(m, 1, offs, coords, species, box, o, (hipStream_t)stream, kFull, ListPool(), pin);
 }
 
 extern "C" int nnp_debug_aev(nnp_model *m, int n_systems, const int64_t *offs, const float *coords,

@@ -96,11 +96,12 @@ __global__ void __launch_bounds__(W * kWave) k_chain(ChainLaunch cl) {
   extern __shared__ uint4 chain_lds[];
   const int tid = threadIdx.x, wave = __builtin_amdgcn_readfirstlane(tid / kWave), lane = tid % kWave;
   const int l16 = lane & 15, kq = lane >> 4;
-  // member-major logical order, contiguous per XCD: an XCD works through the
-  // row tiles of one or two (member, species) networks at a time, whose
-  // weights then stay in its L2
-  const int n_rt = gridDim.x / cl.n_members;
-  const int lb = xcd_logical(blockIdx.x, gridDim.x);
+  // member-major logical order in chunks of row tiles per XCD: an XCD works
+  // through a run of row tiles of one (member, species) network at a time,
+  // whose weights then stay in its L2
+  const int lb = xcd_chunked(blockIdx.x, cl.xcd_chunk);
+  if (lb >= cl.n_blocks) return;
+  const int n_rt = cl.n_blocks / cl.n_members;
   const int mb = lb / n_rt;
   const int r0 = (lb % n_rt) * kChainRows;
   int s = -1;
@@ -236,6 +237,7 @@ __global__ void k_chain_mean(const float *__restrict__ e_mem, int M, const int *
 template <int W>
 static void chain_t(const ChainLaunch &cl, int n_hidden, bool grad, unsigned blocks, size_t lds_bytes,
                     hipStream_t st) {
+  blocks = xcd_grid(blocks, cl.xcd_chunk);
   if (n_hidden == 1) {
     if (grad) k_chain<1, true, W><<<blocks, W * kWave, lds_bytes, st>>>(cl);
     else k_chain<1, false, W><<<blocks, W * kWave, lds_bytes, st>>>(cl);
@@ -248,10 +250,12 @@ static void chain_t(const ChainLaunch &cl, int n_hidden, bool grad, unsigned blo
   }
 }
 
-void launch_chain(const ChainLaunch &cl, int n_hidden, bool grad, int rows, size_t lds_bytes, int waves,
+void launch_chain(ChainLaunch cl, int n_hidden, bool grad, int rows, size_t lds_bytes, int waves,
                   hipStream_t st) {
   const unsigned blocks = (unsigned)(rows / kChainRows * cl.n_members);
   if (blocks == 0) return;
+  cl.n_blocks = (int)blocks;
+  cl.xcd_chunk = 16;   // 512 rows of one network per chunk
   if (waves == 4) chain_t<4>(cl, n_hidden, grad, blocks, lds_bytes, st);
   else chain_t<8>(cl, n_hidden, grad, blocks, lds_bytes, st);
   k_chain_mean<<<(rows + 255) / 256, 256, 0, st>>>(cl.e_mem, cl.n_members, cl.perm, cl.bucket_off, cl.n_groups,

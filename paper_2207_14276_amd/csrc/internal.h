@@ -28,17 +28,24 @@ constexpr int kAngBlock = kNShfAng * kNShfZ;  // 32 features per species pair
 constexpr int kTileM = 128;                   // MLP row tile; buckets pad to it
 
 // Workgroups are dispatched round-robin over the 8 XCDs (each with its own
-// L2): logical block of dispatch slot bid, so that each XCD walks a
-// contiguous range of logical blocks.
-__device__ inline int xcd_logical(int bid, int nb) {
-  constexpr int X = 8;
-  const int q = nb / X, r = nb % X;
-  const int x = bid % X, k = bid / X;
-  return x * q + min(x, r) + k;
+// L2): block b runs on XCD b % 8.  Logical block of dispatch slot bid when
+// chunks of C consecutive logical blocks go to the XCDs in turn: the blocks
+// of one chunk (those that share an operand tile) run on one XCD and hit the
+// same L2, and any prefix of the logical blocks (the part of a grid sized
+// for more rows than a call has) is spread evenly over all eight XCDs.  The
+// grid must be a multiple of 8 C (xcd_grid); logical blocks past the real
+// count exit at once.
+__device__ inline int xcd_chunked(int bid, int C) {
+  const int x = bid % 8, k = bid / 8;
+  return ((k / C) * 8 + x) * C + (k % C);
+}
+__host__ inline unsigned xcd_grid(unsigned blocks, int C) {
+  const unsigned g = 8u * (unsigned)C;
+  return (blocks + g - 1) / g * g;
 }
 
 // Device status word bits.
-enum : int { kStatOverflow = 1, kStatBadSpecies = 2 };
+enum : int { kStatOverflow = 1, kStatBadSpecies = 2, kStatBadPairs = 4 };
 
 // One system of a batch, as the kernels see it.  Filled on the host except
 // the non-periodic cell grid (origin/edge/nc), which a kernel derives from
@@ -116,6 +123,8 @@ struct GemmLaunch {
   int col_tiles;               // set by the launcher
   int k32;                     // every K and stride allows 32-wide K chunks (direct-to-LDS kernel)
   int span;                    // set by the launcher: members' columns side by side
+  int n_blocks;                // set by the launcher: real blocks (the grid is padded)
+  int xcd_chunk;               // set by the launcher: logical blocks per XCD chunk
   GemmGroup g[kMaxMembers * kMaxSpecies];  // [member][species]
   float alpha;                 // CELU alpha
   float scale;
@@ -144,6 +153,7 @@ struct ChainLaunch {
   int lds_ld[kChainMax + 1];                          // its row stride (elements)
   float alpha, inv_m;
   float *e_mem;                                       // [rows][members] energies
+  int n_blocks, xcd_chunk;                            // set by the launcher
   const int *perm; float *e_atom;
 };
 
@@ -164,9 +174,12 @@ struct EnergyLaunch {
 // ---- launchers (stream-ordered, no host sync)
 void launch_skin_check(const float *coords, SysDesc *sys, int n_sys, const AtomState *state,
                        float half_skin, int *stats, hipStream_t st);
-void launch_ingest(const float *coords, const int *species, const SysDesc *sys, int n_sys,
-                   int N, int S, float4 *pos, int *sys_of, AtomState *state, int *status,
-                   hipStream_t st);
+void launch_ingest(const float *coords, const int *species, const unsigned char *mask,
+                   const SysDesc *sys, int n_sys, int N, int S, float4 *pos, int *sys_of,
+                   AtomState *state, int *status, hipStream_t st);
+void launch_pairs_to_rows(const int *pairs, const int *shifts, long long n_pairs, int half,
+                          const unsigned char *mask, const float4 *pos, int N, const float L[3],
+                          float rc, int cap, int2 *nbr, int *nbr_cnt, int *status, hipStream_t st);
 void launch_grid(SysDesc *sys, int n_sys, const float4 *pos, int *cell_count, float rc_list,
                  hipStream_t st);
 void launch_cell_count(const float4 *pos, const int *sys_of, const SysDesc *sys, int N,
@@ -191,7 +204,7 @@ void launch_aev_bwd(const float4 *pos, const int *sys_of, const SysDesc *sys, co
 // wpb_pref below: waves per workgroup 1, 2 or 4 when the LDS fits (else the default).
 void launch_gemm(int epi, bool bf16, GemmLaunch gl, int row_tiles, int max_n_out, int tn_pref, hipStream_t st);
 void launch_energy(const EnergyLaunch &el, bool bf16, int rows, hipStream_t st);
-void launch_chain(const ChainLaunch &cl, int n_hidden, bool grad, int rows, size_t lds_bytes, int waves,
+void launch_chain(ChainLaunch cl, int n_hidden, bool grad, int rows, size_t lds_bytes, int waves,
                   hipStream_t st);
 void launch_fill(float *p, size_t n, float v, hipStream_t st);
 void launch_fill_i32(int *p, size_t n, int v, hipStream_t st);

@@ -70,8 +70,8 @@ __global__ void __launch_bounds__(256) k_gemm(GemmLaunch gl) {
   __shared__ __attribute__((aligned(16))) T smem[2][(TM + TN) * LD];
 
   // logical block -> (row tile, member, col tile); columns fastest
-  const int nb = gridDim.x;
-  const int lb = xcd_logical(blockIdx.x, nb);
+  const int lb = xcd_chunked(blockIdx.x, gl.xcd_chunk);
+  if (lb >= gl.n_blocks) return;
   const int n_ct = gl.col_tiles;
   const int ct = lb % n_ct;
   const int mb = (lb / n_ct) % gl.n_members;
@@ -304,8 +304,8 @@ k_gemm_dl(GemmLaunch gl) {
   static_assert(A_LD >= 1 && B_LD >= 1, "tile too small");
   __shared__ __attribute__((aligned(16))) uint4 smem[STAGES][A_SLOTS + B_SLOTS];
 
-  const int nb = gridDim.x;
-  const int lb = xcd_logical(blockIdx.x, nb);
+  const int lb = xcd_chunked(blockIdx.x, gl.xcd_chunk);
+  if (lb >= gl.n_blocks) return;
   const int n_ct = gl.col_tiles;
   const int ct = lb % n_ct;
   // SPAN: the output columns of all members side by side (member-major), one
@@ -476,8 +476,11 @@ k_gemm_dl(GemmLaunch gl) {
 constexpr int kStages128 = 3, kStages256 = 3;
 
 template <int EPI, bool BF16>
-static void launch_t(const GemmLaunch &gl, int row_tiles, int tn, hipStream_t st) {
-  const unsigned blocks = (unsigned)(row_tiles * (gl.span ? 1 : gl.n_members) * gl.col_tiles);
+static void launch_t(GemmLaunch gl, int row_tiles, int tn, hipStream_t st) {
+  // the blocks of one row tile (every column tile and member) form a chunk
+  gl.xcd_chunk = (gl.span ? 1 : gl.n_members) * gl.col_tiles;
+  gl.n_blocks = row_tiles * gl.xcd_chunk;
+  const unsigned blocks = xcd_grid((unsigned)gl.n_blocks, gl.xcd_chunk);
   if (BF16 && gl.k32) {
     if constexpr (EPI == kEpiFwd) {
       if (gl.span) {

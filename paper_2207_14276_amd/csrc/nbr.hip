@@ -11,6 +11,7 @@ namespace nnp {
 // recorded; a system that reuses its list applies the recorded wrap instead,
 // so neighbour vectors stay consistent with the stored lattice images.
 __global__ void k_ingest(const float *__restrict__ coords, const int *__restrict__ species,
+                         const unsigned char *__restrict__ mask,
                          const SysDesc *__restrict__ sys, int n_sys, int N, int S,
                          float4 *__restrict__ pos, int *__restrict__ sys_of,
                          AtomState *__restrict__ state, int *__restrict__ status) {
@@ -53,15 +54,17 @@ __global__ void k_ingest(const float *__restrict__ coords, const int *__restrict
     atomicOr(status, kStatBadSpecies);
     s = 0;
   }
+  // an atom outside the caller's mask has no network (species slot -1)
+  if (mask && !mask[i]) s = -1;
   pos[i] = make_float4(x, y, z, __int_as_float(s));
   sys_of[i] = lo;
 }
 
-void launch_ingest(const float *coords, const int *species, const SysDesc *sys, int n_sys,
-                   int N, int S, float4 *pos, int *sys_of, AtomState *state, int *status,
-                   hipStream_t st) {
+void launch_ingest(const float *coords, const int *species, const unsigned char *mask,
+                   const SysDesc *sys, int n_sys, int N, int S, float4 *pos, int *sys_of,
+                   AtomState *state, int *status, hipStream_t st) {
   if (N <= 0) return;
-  k_ingest<<<(N + 255) / 256, 256, 0, st>>>(coords, species, sys, n_sys, N, S, pos, sys_of,
+  k_ingest<<<(N + 255) / 256, 256, 0, st>>>(coords, species, mask, sys, n_sys, N, S, pos, sys_of,
                                             state, status);
 }
 
@@ -509,7 +512,10 @@ k_species_count(const float4 *__restrict__ pos, int N, int S, int *__restrict__ 
   if (threadIdx.x < kMaxSpecies) cnt[threadIdx.x] = 0;
   __syncthreads();
   int i = blockIdx.x * kBucketBlock + threadIdx.x;
-  if (i < N) atomicAdd(&cnt[__float_as_int(pos[i].w)], 1);
+  if (i < N) {
+    const int s = __float_as_int(pos[i].w);
+    if (s >= 0) atomicAdd(&cnt[s], 1);   // slot -1: outside the caller's mask
+  }
   __syncthreads();
   if (threadIdx.x < kMaxSpecies) block_counts[blockIdx.x * kMaxSpecies + threadIdx.x] = cnt[threadIdx.x];
 }
@@ -570,6 +576,8 @@ k_species_scatter(const float4 *__restrict__ pos, int N, const int *__restrict__
     int row = bucket_off[s] + block_base[blockIdx.x * kMaxSpecies + s] + before + rank_in_wave;
     perm[row] = i;
     row_of_atom[i] = row;
+  } else if (i < N) {
+    row_of_atom[i] = -1;   // no network row: the AEV kernels skip the atom
   }
 }
 
@@ -616,8 +624,13 @@ __global__ void k_gather_rows(const float *__restrict__ src, int ld, const int *
                               int N, int D, float *__restrict__ dst) {
   int i = blockIdx.x;
   if (i >= N) return;
-  const float *s = src + (size_t)row_of_atom[i] * ld;
+  const int r = row_of_atom[i];
   float *d = dst + (size_t)i * D;
+  if (r < 0) {   // no network row: no features
+    for (int k = threadIdx.x; k < D; k += blockDim.x) d[k] = 0.f;
+    return;
+  }
+  const float *s = src + (size_t)r * ld;
   for (int k = threadIdx.x; k < D; k += blockDim.x) d[k] = s[k];
 }
 
@@ -666,6 +679,125 @@ __global__ void k_f32_to_bf16(const float *__restrict__ src, uint16_t *__restric
 void launch_f32_to_bf16(const float *src, uint16_t *dst, size_t n, hipStream_t st) {
   if (n == 0) return;
   k_f32_to_bf16<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(src, dst, n);
+}
+
+
+// ---- caller pair lists (the pair-list entry point)
+//
+// A host program that keeps its own neighbour list (the paper's platform
+// hands the network positions and a pair list) passes it as pairs (i, j)
+// with integer lattice shifts n: r_j + n * L is a neighbour of i.  A half
+// list names each unordered pair once and both directions are added; a
+// full list names each direction.  Pairs with an atom outside the mask, or
+// at a distance at or beyond the cutoff, are dropped here (the AEV kernels
+// apply the cutoff again with their own arithmetic).
+__global__ void k_pairs_append(const int *__restrict__ pairs, const int *__restrict__ shifts,
+                               long long n_pairs, int half, const unsigned char *__restrict__ mask,
+                               const float4 *__restrict__ pos, int N, float L0, float L1, float L2,
+                               float rc2, int cap, int2 *__restrict__ nbr, int *__restrict__ nbr_cnt,
+                               int *__restrict__ status) {
+  const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x % kWave;
+  bool keep = false;
+  int i = 0, j = 0, nx = 0, ny = 0, nz = 0;
+  if (p < n_pairs) {
+    i = pairs[2 * p];
+    j = pairs[2 * p + 1];
+    if (shifts) { nx = shifts[3 * p]; ny = shifts[3 * p + 1]; nz = shifts[3 * p + 2]; }
+    const bool bad = (unsigned)i >= (unsigned)N || (unsigned)j >= (unsigned)N ||
+                     (i == j && nx == 0 && ny == 0 && nz == 0) ||
+                     nx < -511 || nx > 511 || ny < -511 || ny > 511 || nz < -511 || nz > 511;
+    if (bad) {
+      atomicOr(status, kStatBadPairs);
+    } else if (!mask || (mask[i] && mask[j])) {
+      const float4 pi = pos[i], pj = pos[j];
+      const float dx = (pj.x - pi.x) + (float)nx * L0;
+      const float dy = (pj.y - pi.y) + (float)ny * L1;
+      const float dz = (pj.z - pi.z) + (float)nz * L2;
+      keep = dx * dx + dy * dy + dz * dz < rc2;
+    }
+  }
+  // slots in row i.  Lists usually come grouped by i, so many lanes of a
+  // wave add to one counter: lanes sharing the first remaining lane's i take
+  // their slots with one atomic; once such groups become small, the rest
+  // add one by one.
+  unsigned long long act = __ballot(keep);
+  int a = -1;
+  while (act) {
+    const int leader = __ffsll((long long)act) - 1;
+    const int key = __shfl(i, leader);
+    const unsigned long long grp = __ballot(keep && i == key) & act;
+    const int n = __popcll(grp);
+    if (n < 4) break;
+    int base = 0;
+    if (lane == leader) base = atomicAdd(&nbr_cnt[key], n);
+    base = __shfl(base, leader);
+    if ((grp >> lane) & 1ull)
+      a = base + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(grp >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)grp, 0));
+    act &= ~grp;
+  }
+  if ((act >> lane) & 1ull) a = atomicAdd(&nbr_cnt[i], 1);
+  if (!keep) return;
+  if (a < cap) nbr[(size_t)i * cap + a] = make_int2(j, pack_image(nx, ny, nz));
+  if (half) {
+    const int b = atomicAdd(&nbr_cnt[j], 1);
+    if (b < cap) nbr[(size_t)j * cap + b] = make_int2(i, pack_image(-nx, -ny, -nz));
+  }
+}
+
+// One wave per atom: each row, filled in arbitrary (atomic) order, is put in
+// (j, image) order so that results do not depend on it; a repeated entry
+// (a pair listed twice) raises kStatBadPairs; a row past the capacity raises
+// kStatOverflow and the largest count is kept for the caller's retry.
+__global__ void __launch_bounds__(256)
+k_pairs_rows(int N, int cap, int2 *__restrict__ nbr, const int *__restrict__ nbr_cnt,
+             int *__restrict__ status) {
+  extern __shared__ unsigned long long row_keys[];
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave), lane = threadIdx.x % kWave;
+  const int i = blockIdx.x * (blockDim.x / kWave) + wave;
+  if (i >= N) return;
+  unsigned long long *K = row_keys + (size_t)wave * cap;
+  const int cnt = nbr_cnt[i];
+  if (lane == 0 && cnt > cap) {
+    atomicOr(status, kStatOverflow);
+    if (cnt > __hip_atomic_load(status + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+      atomicMax(status + 1, cnt);
+  }
+  const int n = min(cnt, cap);
+  int2 *row = nbr + (size_t)i * cap;
+  for (int e = lane; e < n; e += kWave) {
+    const int2 v = row[e];
+    K[e] = ((unsigned long long)(unsigned)v.x << 32) | (unsigned)v.y;
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  bool dup = false;
+  for (int e = lane; e < n; e += kWave) {
+    const unsigned long long k = K[e];
+    int r = 0;
+    for (int t = 0; t < n; ++t) {
+      const unsigned long long kt = K[t];
+      r += kt < k ? 1 : 0;
+      dup |= kt == k && t != e;
+    }
+    row[r] = make_int2((int)(k >> 32), (int)(unsigned)k);
+  }
+  if (__ballot(dup) != 0ull && lane == 0) atomicOr(status, kStatBadPairs);
+}
+
+void launch_pairs_to_rows(const int *pairs, const int *shifts, long long n_pairs, int half,
+                          const unsigned char *mask, const float4 *pos, int N, const float L[3],
+                          float rc, int cap, int2 *nbr, int *nbr_cnt, int *status, hipStream_t st) {
+  if (N <= 0) return;
+  launch_fill_i32(nbr_cnt, (size_t)N, 0, st);
+  if (n_pairs > 0) {
+    const float rc2 = rc * rc * (1.0f + 1e-5f);
+    k_pairs_append<<<(unsigned)((n_pairs + 255) / 256), 256, 0, st>>>(
+        pairs, shifts, n_pairs, half, mask, pos, N, L[0], L[1], L[2], rc2, cap, nbr, nbr_cnt, status);
+  }
+  k_pairs_rows<<<(N + 3) / 4, 256, (size_t)4 * cap * sizeof(unsigned long long), st>>>(N, cap, nbr, nbr_cnt,
+                                                                                      status);
 }
 
 }  // namespace nnp

@@ -141,6 +141,62 @@ class NNPModel:
                 break
         return out
 
+    def energy_forces_pairs(self, coords, species, box, pairs, shifts=None, mask=None,
+                            half: bool = True, forces: bool = True, virial: bool = False,
+                            atom_energy: bool = False, check: bool = False,
+                            out: Result | None = None) -> Result:
+        """One system from the caller's pair list (nnp_energy_forces_pairs):
+        `pairs` [P, 2] int32 (i, j), `shifts` [P, 3] int32 lattice shifts or
+        None, `mask` [N] bool/uint8 ML region or None (all atoms), `box` [3]
+        (zeros: non-periodic).  Energy [1] float64, forces [N, 3], virial
+        [1, 3, 3], atomic energies [N] as in energy_forces.  check=True waits
+        and raises on a device flag (a neighbour overflow retries once with a
+        larger capacity)."""
+        coords = coords.to(self.device, torch.float32).contiguous()
+        species = species.to(self.device, torch.int32).contiguous()
+        N = int(coords.shape[0])
+        pairs = pairs.to(self.device, torch.int32).contiguous()
+        P = int(pairs.shape[0])
+        if pairs.dim() != 2 or pairs.shape[1] != 2:
+            raise ValueError("pairs must be [P, 2]")
+        if shifts is not None:
+            shifts = shifts.to(self.device, torch.int32).contiguous()
+            if tuple(shifts.shape) != (P, 3):
+                raise ValueError("shifts must be [P, 3]")
+        if mask is not None:
+            mask = mask.to(self.device, torch.uint8).contiguous()
+            if tuple(mask.shape) != (N,):
+                raise ValueError("mask must be [N]")
+        bx = box.detach().cpu().numpy() if torch.is_tensor(box) else np.asarray(box)
+        bx = np.ascontiguousarray(bx, dtype=np.float32).reshape(3)
+        if out is None:
+            out = Result(energy=torch.empty(1, dtype=torch.float64, device=self.device))
+            if forces:
+                out.forces = torch.empty((N, 3), dtype=torch.float32, device=self.device)
+            if virial:
+                out.virial = torch.empty((1, 3, 3), dtype=torch.float64, device=self.device)
+            if atom_energy:
+                out.atom_energy = torch.empty(N, dtype=torch.float32, device=self.device)
+        lib = nat.load()
+        ptr = lambda t: C.c_void_p(t.data_ptr()) if t is not None else None
+        with torch.cuda.device(self.device):
+            st = _stream_handle(self.device)
+            for attempt in range(2):
+                nat.check(lib.nnp_energy_forces_pairs(
+                    self._h, N, ptr(coords), ptr(species), _fptr(bx), P, ptr(pairs), ptr(shifts),
+                    1 if half else 0, ptr(mask), ptr(out.energy), ptr(out.forces), ptr(out.virial),
+                    ptr(out.atom_energy), st))
+                if not check:
+                    break
+                mx = C.c_int()
+                rc = lib.nnp_status(self._h, st, C.byref(mx))
+                if rc == nat.NNP_ECAPACITY and attempt == 0:
+                    self.reserve(N, 1, min(1024, max(int(mx.value * 1.25) + 4, 64)))
+                    continue
+                nat.check(rc)
+                break
+        return out
+
     def autotune(self, coords, species, boxes, offsets) -> dict:
         """Picks the launch shapes (AEV waves per workgroup, GEMM column-tile
         widths) that run this batch fastest; they stay with the model.

@@ -1,0 +1,221 @@
+"""The pair-list entry point (nnp_energy_forces_pairs) against the FP64
+oracle: the caller passes its own neighbour pairs (with lattice shifts) and
+an ML region; the network sees only the region's atoms, so the result is the
+oracle's energy and forces of the region taken as a system of its own, with
+zero force on every other atom.
+
+Bars as in test_gpu_parity: float32 |dE|/N <= 1e-5 and |dF| <= 1e-3,
+bfloat16 dense layers |dE|/N <= 1e-2 and |dF| <= 5e-2.  The caller's list is
+built here by brute force with a 6 A cutoff (wider than the 5.1 A radial
+cutoff, so that out-of-range pairs must be dropped).
+"""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from paper_2207_14276_amd import NNPError
+from tests.gpu_util import BF16_E_PER_ATOM, BF16_F, FP32_E_ATOM, FP32_F, log
+
+pytestmark = pytest.mark.gpu
+
+LIST_RC = 6.0
+
+
+def brute_pairs(coords, box, rc=LIST_RC):
+    """Half list of every unordered pair {i, j + n} with |d| < rc: i < j with
+    any shift, and i == j with a lexicographically positive shift."""
+    x = np.asarray(coords, np.float64)
+    L = np.asarray(box, np.float64)
+    per = L > 0
+    k = [int(np.ceil(rc / L[a])) if per[a] else 0 for a in range(3)]
+    shifts = np.array([(a, b, c) for a in range(-k[0], k[0] + 1) for b in range(-k[1], k[1] + 1)
+                       for c in range(-k[2], k[2] + 1)], np.int64)
+    out_p, out_s = [], []
+    n = len(x)
+    for i in range(n):
+        d = x[None, :, :] + shifts[:, None, :] * L - x[i]          # [images, n, 3]
+        r = np.sqrt((d * d).sum(-1))
+        img, j = np.nonzero(r < rc)
+        sh = shifts[img]
+        pos_shift = (sh[:, 0] > 0) | ((sh[:, 0] == 0) & ((sh[:, 1] > 0) | ((sh[:, 1] == 0) & (sh[:, 2] > 0))))
+        keep = (j > i) | ((j == i) & pos_shift)
+        out_p.append(np.stack([np.full(keep.sum(), i), j[keep]], 1))
+        out_s.append(sh[keep])
+    return np.concatenate(out_p).astype(np.int32), np.concatenate(out_s).astype(np.int32)
+
+
+@pytest.fixture(scope="module")
+def spec():
+    return synth.make_model(0)
+
+
+@pytest.fixture(scope="module")
+def om(oracle_lib, spec):
+    return oracle_lib.OracleModel(spec)
+
+
+def solute_in_water(seed=21):
+    """A 60-atom solute (species H/C/N/O/F/S/Cl) inside a periodic 2,001-atom
+    water box: the region is the solute plus the waters within 4 A of it."""
+    water = synth.config1()
+    rng = np.random.default_rng(seed)
+    sol = synth.random_solute(rng, 60, 1.2 * 60 ** (1 / 3), synth.CONFIG2_PROBS)
+    centre = water.box / 2
+    sc = sol.coords - sol.coords.mean(0) + centre
+    # drop waters that overlap the solute (keep whole molecules: O, H, H)
+    w = water.coords.reshape(-1, 3, 3)
+    ws = water.species.reshape(-1, 3)
+    dmin = np.sqrt(((w[:, :, None, :] - sc[None, None, :, :]) ** 2).sum(-1)).min(axis=(1, 2))
+    keep = dmin > 2.0
+    coords = np.concatenate([sc, w[keep].reshape(-1, 3)]).astype(np.float32)
+    species = np.concatenate([sol.species, ws[keep].reshape(-1)]).astype(np.int32)
+    near = np.sqrt(((coords[:, None, :] - sc[None, :, :]) ** 2).sum(-1)).min(1) < 4.0
+    mask = near.copy()
+    mask[:60] = True
+    return coords, species, water.box.astype(np.float32), mask
+
+
+def oracle_region(oracle_lib, om, coords, species, box, mask):
+    E, e_atom, F, W = oracle_lib.energy_forces(coords[mask], species[mask], box, om)
+    Ffull = np.zeros((len(coords), 3))
+    Ffull[mask] = F
+    return E, Ffull, W
+
+
+def run_pairs(m, coords, species, box, pairs, shifts, mask=None, half=True, virial=True):
+    dev = "cuda"
+    r = m.energy_forces_pairs(torch.as_tensor(coords, device=dev), torch.as_tensor(species, device=dev), box,
+                              torch.as_tensor(pairs, device=dev),
+                              None if shifts is None else torch.as_tensor(shifts, device=dev),
+                              None if mask is None else torch.as_tensor(mask.astype(np.uint8), device=dev),
+                              half=half, virial=virial, check=True)
+    torch.cuda.synchronize()
+    return (float(r.energy.cpu().numpy()[0]), r.forces.cpu().numpy().astype(np.float64),
+            None if r.virial is None else r.virial.cpu().numpy()[0])
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_region_matches_oracle(spec, om, oracle_lib, prec):
+    from paper_2207_14276_amd import NNPModel
+    coords, species, box, mask = solute_in_water()
+    pairs, shifts = brute_pairs(coords, box)
+    m = NNPModel(spec, prec)
+    E, F, W = run_pairs(m, coords, species, box, pairs, shifts, mask)
+    m.close()
+    Eo, Fo, Wo = oracle_region(oracle_lib, om, coords, species, box, mask)
+    n = int(mask.sum())
+    de, df = abs(E - Eo) / n, float(np.abs(F - Fo).max())
+    dw = float(np.abs(W - Wo).max()) / n
+    log(f"[pairs {prec}] atoms={len(coords)} region={n} pairs={len(pairs)} |dE|/N={de:.3e} "
+        f"|dF|={df:.3e} |dW|/N={dw:.3e}")
+    e_tol, f_tol = (FP32_E_ATOM, FP32_F) if prec == "fp32" else (BF16_E_PER_ATOM, BF16_F)
+    assert de <= e_tol
+    assert df <= f_tol
+    assert dw <= 50 * f_tol
+    assert np.all(F[~mask] == 0.0)
+
+
+def test_whole_system_matches_cell_search(spec, oracle_lib, om):
+    """Without a mask the caller's list and the library's own cell search
+    give the same energy and forces (entries reach the AEV kernels in a
+    different order: float32 rounding only), and both match the oracle."""
+    from paper_2207_14276_amd import NNPModel
+    b = synth.make_batch([synth.config1()])
+    pairs, shifts = brute_pairs(b.coords, b.boxes[0])
+    m = NNPModel(spec, "fp32")
+    E, F, _ = run_pairs(m, b.coords, b.species, b.boxes[0], pairs, shifts)
+    dev = "cuda"
+    r = m.energy_forces(torch.as_tensor(b.coords, device=dev), torch.as_tensor(b.species, device=dev),
+                        b.boxes, b.offsets, check=True)
+    E2, F2 = float(r.energy.cpu().numpy()[0]), r.forces.cpu().numpy().astype(np.float64)
+    m.close()
+    Eo, _, Fo, _ = oracle_lib.energy_forces(b.coords, b.species, b.boxes[0], om)
+    n = b.n_atoms
+    log(f"[pairs whole] |E-E_cells|/N={abs(E - E2) / n:.3e} |F-F_cells|={np.abs(F - F2).max():.3e} "
+        f"|E-E_oracle|/N={abs(E - Eo) / n:.3e}")
+    assert abs(E - E2) / n <= FP32_E_ATOM
+    assert np.abs(F - F2).max() <= 1e-4
+    assert abs(E - Eo) / n <= FP32_E_ATOM
+    assert np.abs(F - Fo).max() <= FP32_F
+
+
+def test_list_form_and_order_do_not_matter(spec):
+    """A half list, the same list shuffled with i and j swapped (shift
+    negated), and the full list give bit-identical energies: every neighbour
+    row is put in a canonical order before use."""
+    from paper_2207_14276_amd import NNPModel
+    coords, species, box, mask = solute_in_water(seed=22)
+    pairs, shifts = brute_pairs(coords, box)
+    rng = np.random.default_rng(5)
+    perm = rng.permutation(len(pairs))
+    p2, s2 = pairs[perm].copy(), shifts[perm].copy()
+    sw = rng.random(len(pairs)) < 0.5
+    p2[sw] = p2[sw][:, ::-1]
+    s2[sw] = -s2[sw]
+    pf = np.concatenate([pairs, pairs[:, ::-1]])
+    sf = np.concatenate([shifts, -shifts])
+    m = NNPModel(spec, "bf16")
+    ea, fa, _ = run_pairs(m, coords, species, box, pairs, shifts, mask)
+    eb, fb, _ = run_pairs(m, coords, species, box, p2, s2, mask)
+    ec, fc, _ = run_pairs(m, coords, species, box, pf, sf, mask, half=False)
+    m.close()
+    assert ea == eb == ec
+    np.testing.assert_allclose(fa, fb, rtol=1e-5, atol=1e-5)
+    np.testing.assert_allclose(fa, fc, rtol=1e-5, atol=1e-5)
+
+
+def test_non_periodic_solute_without_shifts(spec, om, oracle_lib):
+    from paper_2207_14276_amd import NNPModel
+    sys_ = synth.config0()
+    box = np.zeros(3, np.float32)
+    pairs, _ = brute_pairs(sys_.coords, box)
+    m = NNPModel(spec, "fp32")
+    E, F, W = run_pairs(m, sys_.coords, sys_.species, box, pairs, None)
+    m.close()
+    Eo, _, Fo, Wo = oracle_lib.energy_forces(sys_.coords, sys_.species, box, om)
+    assert abs(E - Eo) / len(sys_.species) <= FP32_E_ATOM
+    assert np.abs(F - Fo).max() <= FP32_F
+    assert np.abs(W - Wo).max() <= 50 * FP32_F
+
+
+def test_bad_lists_are_reported(spec):
+    """A pair inside the cutoff listed twice, an index past the atoms and a
+    self pair without shift each raise NNPError (NNP_EINVAL) from the device
+    check; a row past the capacity is retried with a larger capacity and then
+    succeeds."""
+    from paper_2207_14276_amd import NNPModel
+    sys_ = synth.config0()
+    box = np.zeros(3, np.float32)
+    pairs, _ = brute_pairs(sys_.coords, box)
+    x = sys_.coords.astype(np.float64)
+    r = np.linalg.norm(x[pairs[:, 1]] - x[pairs[:, 0]], axis=1)
+    inside = pairs[r < 5.0][:1]
+    m = NNPModel(spec, "fp32")
+    for bad in (np.concatenate([pairs, inside]),
+                np.concatenate([pairs, np.array([[0, len(sys_.species)]], np.int32)]),
+                np.concatenate([pairs, np.array([[3, 3]], np.int32)])):
+        with pytest.raises(NNPError):
+            run_pairs(m, sys_.coords, sys_.species, box, bad, None, virial=False)
+    # after the errors the model still works
+    E_ok, _, _ = run_pairs(m, sys_.coords, sys_.species, box, pairs, None, virial=False)
+    m.reserve(len(sys_.species), 1, 4)
+    E_small, _, _ = run_pairs(m, sys_.coords, sys_.species, box, pairs, None, virial=False)
+    m.close()
+    assert E_small == E_ok
+
+
+def test_empty_region_and_empty_list(spec):
+    """No pairs: every atom of the region is isolated (its energy is the
+    network's value at a zero AEV); an empty region: zero energy and force."""
+    from paper_2207_14276_amd import NNPModel
+    sys_ = synth.config0()
+    box = np.zeros(3, np.float32)
+    pairs, _ = brute_pairs(sys_.coords, box)
+    m = NNPModel(spec, "fp32")
+    E0, F0, _ = run_pairs(m, sys_.coords, sys_.species, box, np.zeros((0, 2), np.int32), None, virial=False)
+    assert np.all(F0 == 0.0) and np.isfinite(E0)
+    none = np.zeros(len(sys_.species), bool)
+    E1, F1, _ = run_pairs(m, sys_.coords, sys_.species, box, pairs, None, none, virial=False)
+    m.close()
+    assert E1 == 0.0 and np.all(F1 == 0.0)
