@@ -34,7 +34,7 @@ def parse():
     p.add_argument("--warmup", type=int, default=5)
     p.add_argument("--workload", default="ragged512",
                    choices=["ragged512", "water2001", "protein100k", "cluster24", "serve", "copy",
-                            "hybrid"])
+                            "hybrid", "snapshots"])
     p.add_argument("--precision", default="bf16", choices=["bf16", "fp32"])
     p.add_argument("--no-plain", action="store_true")
     p.add_argument("--no-cpu", action="store_true")
@@ -423,6 +423,135 @@ def hybrid_bench(args):
     print(json.dumps(out), flush=True)
 
 
+def snapshots_bench(args):
+    """Energy-only throughput for reweighting stored snapshots: 4,096
+    snapshots of one 40-atom solute (two harmonic reference states of 2,048
+    each), evaluated in one batched call per step without forces (the
+    input-gradient and AEV-backward stages are skipped); beside it the same
+    batch with forces, the plain float32 form (one snapshot per call, energy
+    only) and the host BAR estimate on the energies."""
+    import torch
+    import synth
+    from paper_2207_14276_amd import NNPModel
+    from paper_2207_14276_amd.bar import bar_reweighted, beta_at
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    spec = synth.make_model(0)
+    rng = np.random.default_rng(8)
+    n_atoms, n_per = 40, 2048
+    ref = synth.random_solute(rng, n_atoms, 1.2 * n_atoms ** (1 / 3), synth.CONFIG2_PROBS)
+    beta = beta_at(300.0)
+    ks = (20.0, 40.0)
+    systems, state = [], []
+    for si, k in enumerate(ks):
+        sd = 1.0 / np.sqrt(beta * k)
+        for _ in range(n_per):
+            x = ref.coords + rng.normal(0.0, sd, size=ref.coords.shape)
+            systems.append(synth.System(x.astype(np.float32), ref.species, np.zeros(3, np.float32)))
+            state.append(si)
+    batch = synth.make_batch(systems)
+    state = np.array(state)
+    N, S = batch.n_atoms, batch.n_systems
+    c = torch.as_tensor(batch.coords, device=dev)
+    sp = torch.as_tensor(batch.species, device=dev)
+    model = NNPModel(spec, args.precision)
+    cap = size_capacity(model, batch, c, sp, N, S)
+    tuned = model.autotune(c, sp, batch.boxes, batch.offsets)
+
+    def timed(forces):
+        r = model.energy_forces(c, sp, batch.boxes, batch.offsets, forces=forces, check=True)
+        for _ in range(args.warmup):
+            model.energy_forces(c, sp, batch.boxes, batch.offsets, forces=forces, out=r)
+        st = torch.cuda.current_stream()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(args.steps)]
+        model.set_timing(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for a, b in ev:
+            a.record(st)
+            model.energy_forces(c, sp, batch.boxes, batch.offsets, forces=forces, out=r)
+            b.record(st)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        stages = model.stage_timings()
+        model.set_timing(False)
+        lat = np.array([a.elapsed_time(b) for a, b in ev])
+        return r, wall, stages, lat
+
+    r_e, wall_e, stages_e, lat_e = timed(False)
+    _, wall_f, _, _ = timed(True)
+    value = N * args.steps / wall_e
+    e = r_e.energy.cpu().numpy().astype(np.float64)
+
+    # plain: float32, one snapshot per call, energy only, sequential
+    plain = NNPModel(spec, "fp32")
+    plain.reserve(n_atoms, 1, cap)
+    pick = list(range(0, S, S // 256))
+    per = [(c[int(batch.offsets[k]):int(batch.offsets[k + 1])], sp[int(batch.offsets[k]):int(batch.offsets[k + 1])],
+            batch.boxes[k:k + 1], np.array([0, n_atoms], np.int64)) for k in pick]
+    outs = [plain.energy_forces(*q, forces=False) for q in per]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for q, o in zip(per, outs):
+        plain.energy_forces(*q, forces=False, out=o)
+    torch.cuda.synchronize()
+    plain_rate = len(pick) * n_atoms / (time.perf_counter() - t0)
+
+    # host BAR on the energies (target = reference restraint + network energy)
+    x_ref = ref.coords.astype(np.float64)
+    Ur = np.array([[0.5 * k * ((sy.coords - x_ref) ** 2).sum() for k in ks] for sy in systems])
+    ee = e - e.mean()
+    a_, b_ = state == 0, state == 1
+    t0 = time.perf_counter()
+    dF, sF = bar_reweighted(Ur[a_, 0], Ur[a_, 1], Ur[b_, 0], Ur[b_, 1],
+                            Ur[a_, 0] + ee[a_], Ur[a_, 1] + ee[a_], Ur[b_, 0] + ee[b_], Ur[b_, 1] + ee[b_],
+                            beta)
+    t_bar = time.perf_counter() - t0
+
+    fwd_f, _ = mlp_flops(spec, batch.species)
+    n_pairs, n_trip = pair_triplet_counts(model, batch, c, sp)
+    cand = {"aev_fwd": ("alu", FLOP_RADIAL_FWD * n_pairs + FLOP_TRIPLET_FWD * n_trip, PEAK_FP32_VALU_TFLOPS),
+            "mlp": ("mfma", fwd_f,
+                    PEAK_BF16_MFMA_TFLOPS if args.precision == "bf16" else PEAK_FP32_MFMA_TFLOPS)}
+    dom = max(cand, key=lambda k: stages_e.get(k, 0.0))
+    bound, work, peak = cand[dom]
+    achieved = work / (stages_e[dom] * 1e-3) / 1e12
+    out = {
+        "metric": "energy-only atom-evals/s (stored snapshots)",
+        "value": round(value, 1),
+        "unit": "atom-evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall_e / args.steps * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16-mlp/f32-aev" if args.precision == "bf16" else "f32",
+        "data": "synthetic",
+        "config": {"workload": "4,096 snapshots of a 40-atom solute (two harmonic reference states), "
+                               "one batched energy-only call per step",
+                   "n_atoms": N, "n_systems": S, "nbr_capacity": cap, "tuned_shapes": tuned,
+                   "parallelism": "single GPU"},
+        "latency_ms": {"p50": round(float(np.percentile(lat_e, 50)), 4),
+                       "p99": round(float(np.percentile(lat_e, 99)), 4)},
+        "stages_ms": {k: round(v, 4) for k, v in stages_e.items()},
+        "roofline": {"kernel": "k_aev_fwd" if dom == "aev_fwd" else "k_gemm (dense layers, forward)",
+                     "bound": bound, "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+                     "frac": round(achieved / peak, 4), "traffic": None, "work_per_launch_flop": work,
+                     "avg_launch_ms": round(stages_e[dom], 4), "pairs": n_pairs, "triplets": n_trip},
+        "with_forces": {"value": round(N * args.steps / wall_f, 1), "unit": "atom-evals/s"},
+        "plain_fp32_per_snapshot_energy_only": {"value": round(plain_rate, 1), "unit": "atom-evals/s",
+                                                "sample": f"{len(pick)} snapshots"},
+        "speedup_vs_plain": round(value / plain_rate, 2),
+        "bar": {"dF_kcal_mol": round(dF, 5), "sigma": round(sF, 5), "host_seconds": round(t_bar, 4),
+                "note": "target = reference restraint + network energy, 2,048 snapshots per state"},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -444,6 +573,9 @@ def main():
         return
     if args.workload == "hybrid":
         hybrid_bench(args)
+        return
+    if args.workload == "snapshots":
+        snapshots_bench(args)
         return
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)

@@ -358,6 +358,25 @@ int nnp_autotune(nnp_model *model, int n_systems, const int64_t *batch_offsets, 
  * the number of sites (20). */
 int nnp_tuning(const nnp_model *model, int *values, int n);
 
+/* Bennett acceptance ratio estimate of a free-energy difference between two
+ * states, host only (section "Accelerating Hybrid Simulations: an
+ * Alternative Reweighting Strategy" and its supplementary section: stored
+ * snapshots of a reference ensemble U are re-evaluated with the network's
+ * energies (nnp_energy_forces with forces = NULL) and reweighted to the
+ * hybrid potential U').  Reduced units (energies times beta):
+ *   u[n0]   HOST float64: beta (U_1 - U_0) on the samples of state 0;
+ *   v[n1]   HOST float64: beta (U_0 - U_1) on the samples of state 1;
+ *   lw0, lw1  HOST float64 log weights of the samples, or NULL (unweighted):
+ *           -beta (U'_s - U_s) to reweight samples of ensemble U to U';
+ *           u and v are then differences of U'.
+ *   delta   out: beta (F_1 - F_0), the root of Bennett's self-consistent
+ *           equation with the variance-minimizing constant (sample sizes
+ *           n1/n0, or Kish effective sizes when weighted);
+ *   sigma   out (or NULL): its asymptotic standard deviation.
+ * NNP_EINVAL for empty or non-finite samples, or no overlap. */
+int nnp_bar(int64_t n0, const double *u, const double *lw0, int64_t n1, const double *v,
+            const double *lw1, double *delta, double *sigma);
+
 /* Waits for `stream` and returns the device flags raised since the last
  * nnp_status call (NNP_ECAPACITY, NNP_ESPECIES) or NNP_OK; clears them.
  * *max_neighbors (nullable) receives the largest neighbour count seen. */

@@ -76,7 +76,7 @@ EXPORTS = ["nnp_create", "nnp_destroy", "nnp_reserve", "nnp_energy_forces", "nnp
            "nnp_debug_neighbors", "nnp_status", "nnp_aev_dim", "nnp_last_error",
            "nnp_set_timing", "nnp_stage_timings", "nnp_nlist_create", "nnp_nlist_destroy",
            "nnp_energy_forces_nlist", "nnp_nlist_builds", "nnp_autotune", "nnp_tuning",
-           "nnp_energy_forces_pairs",
+           "nnp_energy_forces_pairs", "nnp_bar",
            "nnp_server_create", "nnp_server_destroy", "nnp_server_clock", "nnp_server_submit",
            "nnp_server_step", "nnp_server_drain", "nnp_server_poll", "nnp_server_result",
            "nnp_server_stats",
@@ -115,6 +115,8 @@ def load():
     lib.nnp_energy_forces_nlist.argtypes = [vp, vp, C.c_int, i64p, i64p, C.POINTER(C.c_int32), vp,
                                             vp, fp, vp, vp, vp, vp, vp]
     lib.nnp_nlist_builds.argtypes = [vp, vp, i64p]
+    dpp = C.POINTER(C.c_double)
+    lib.nnp_bar.argtypes = [C.c_int64, dpp, dpp, C.c_int64, dpp, dpp, dpp, dpp]
     lib.nnp_energy_forces_pairs.argtypes = [vp, C.c_int64, vp, vp, fp, C.c_int64, vp, vp, C.c_int, vp,
                                             vp, vp, vp, vp, vp]
     lib.nnp_autotune.argtypes = [vp, C.c_int, i64p, vp, vp, fp, vp]
