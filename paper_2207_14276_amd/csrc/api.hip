@@ -498,7 +498,9 @@ static int next_evset(nnp_model *m, hipEvent_t **out) {
   if (m->ev_used >= kMaxTimedCalls) return NNP_OK;  // beyond the limit: untimed
   if (m->ev_used == (int)m->evsets.size()) {
     std::array<hipEvent_t, kStages + 1> set{};
-    for (auto &e : set) HIP_TRY(hipEventCreate(&e));
+    // timing only: no system-scope fence at each record (the times are read
+    // after the stream has completed)
+    for (auto &e : set) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
     m->evsets.push_back(set);
   }
   *out = m->evsets[m->ev_used++].data();
@@ -755,11 +757,17 @@ static int run(nnp_model *m, int n_sys, const int64_t *offs, const float *coords
   launch_ingest(coords, species, pin.mask, dsys, n_sys, N, m->S, pos, m->sys_of.as<int>(), pool_state,
                 status, st);
   mark();
+  // every system small and without a box: a direct scan per system
+  bool all_small = !pairs && N > 0;
+  for (int s = 0; s < n_sys && all_small; ++s) all_small = !sd[s].periodic && sd[s].n <= kSmallSystem;
   if (pairs) {
     // the caller's list replaces the cell search (stage "cells" stays empty)
     mark();
     launch_pairs_to_rows(pin.pairs, pin.shifts, pin.n, pin.half, pin.mask, pos, N, sd[0].L, rc_list, cap,
                          pool_nbr, pool_cnt, status, st);
+  } else if (all_small) {
+    mark();
+    launch_nbr_small(pos, m->sys_of.as<int>(), dsys, N, rc_list, cap, pool_nbr, pool_cnt, status, st);
   } else {
     launch_grid(dsys, n_sys, pos, m->cell_count.as<int>(), rc_list, st);
     launch_cell_count(pos, m->sys_of.as<int>(), dsys, N, m->cell_count.as<int>(), m->atom_cell.as<int>(),
@@ -1019,7 +1027,7 @@ extern "C" int nnp_autotune(nnp_model *m, int n_systems, const int64_t *offs, co
   if (N < 1) return fail(NNP_EINVAL, "empty batch");
   for (auto &pair : m->tune_ev)
     for (auto &e : pair)
-      if (!e) HIP_TRY(hipEventCreate(&e));
+      if (!e) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
   double *energy = nullptr;
   float *forces = nullptr;
   if (hipMalloc(&energy, sizeof(double) * n_systems) != hipSuccess ||

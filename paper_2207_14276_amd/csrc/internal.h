@@ -177,6 +177,9 @@ void launch_skin_check(const float *coords, SysDesc *sys, int n_sys, const AtomS
 void launch_ingest(const float *coords, const int *species, const unsigned char *mask,
                    const SysDesc *sys, int n_sys, int N, int S, float4 *pos, int *sys_of,
                    AtomState *state, int *status, hipStream_t st);
+constexpr int kSmallSystem = 512;   // largest non-periodic system of the small-system search
+void launch_nbr_small(const float4 *pos, const int *sys_of, const SysDesc *sys, int N, float rc_list,
+                      int cap, int2 *nbr, int *nbr_cnt, int *status, hipStream_t st);
 void launch_pairs_to_rows(const int *pairs, const int *shifts, long long n_pairs, int half,
                           const unsigned char *mask, const float4 *pos, int N, const float L[3],
                           float rc, int cap, int2 *nbr, int *nbr_cnt, int *status, hipStream_t st);

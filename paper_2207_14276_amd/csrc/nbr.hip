@@ -485,6 +485,53 @@ k_nbr_cell(const float4 *__restrict__ pos, const SysDesc *__restrict__ sys, int 
   }
 }
 
+// Small non-periodic systems (every system of the call at most kSmallSystem
+// atoms, no box): one wave per atom scans its whole system in j order, in
+// place of the cell grid, its scan and sort and the stencil walk.  The
+// distance test is the one the cell walk uses; rows list neighbours in
+// increasing j.
+__global__ void __launch_bounds__(256)
+k_nbr_small(const float4 *__restrict__ pos, const int *__restrict__ sys_of,
+            const SysDesc *__restrict__ sys, int N, float rc_list, int cap,
+            int2 *__restrict__ nbr, int *__restrict__ nbr_cnt, int *__restrict__ status) {
+  const int lane = threadIdx.x % kWave;
+  const int i = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+  if (i >= N) return;
+  const SysDesc d = sys[sys_of[i]];
+  if (!d.rebuild) return;
+  const float4 p = pos[i];
+  const float rc2 = rc_list * rc_list;
+  const int code = pack_image(0, 0, 0);
+  int cnt = 0;
+  int2 *out = nbr + nbr_row(d, i, cap);
+  for (int base = d.atom_off; base < d.atom_off + d.n; base += kWave) {
+    const int j = base + lane;
+    bool inside = false;
+    if (j < d.atom_off + d.n && j != i) {
+      const float4 pj = pos[j];
+      const float dx = pj.x - p.x, dy = pj.y - p.y, dz = pj.z - p.z;
+      inside = dx * dx + dy * dy + dz * dz < rc2;
+    }
+    const unsigned long long m = __ballot(inside);
+    const int at = cnt + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
+                                                         __builtin_amdgcn_mbcnt_lo((unsigned)m, 0));
+    if (inside && at < cap) out[at] = make_int2(j - d.atom_off, code);
+    cnt += __popcll(m);
+  }
+  if (lane == 0) {
+    nbr_cnt[d.state_off + (i - d.atom_off)] = cnt;
+    if (cnt > cap) atomicOr(status, kStatOverflow);
+    if (cnt > __hip_atomic_load(status + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+      atomicMax(status + 1, cnt);
+  }
+}
+
+void launch_nbr_small(const float4 *pos, const int *sys_of, const SysDesc *sys, int N, float rc_list,
+                      int cap, int2 *nbr, int *nbr_cnt, int *status, hipStream_t st) {
+  if (N <= 0) return;
+  k_nbr_small<<<(N + 3) / 4, 256, 0, st>>>(pos, sys_of, sys, N, rc_list, cap, nbr, nbr_cnt, status);
+}
+
 void launch_nbr_build(const float4 *pos, const int *sys_of, const SysDesc *sys, int n_sys, int n_cells,
                       const int *cell_start, const int *cell_atoms, int N, float rc_list, int cap,
                       int2 *nbr, int *nbr_cnt, int *status, hipStream_t st) {
