@@ -42,13 +42,19 @@ class _AevParams(C.Structure):
                 ("radial_scale", C.c_double)]
 
 
+class _DpParams(C.Structure):
+    _fields_ = [("n_species", C.c_int), ("rc", C.c_double), ("sel", C.POINTER(C.c_int))]
+
+
 class _Model(C.Structure):
     _fields_ = [("aev", _AevParams),
                 ("n_ensemble", C.c_int),
                 ("n_layers", C.POINTER(C.c_int)),
                 ("widths", C.POINTER(C.c_int)),
                 ("weights", C.POINTER(C.c_double)),
-                ("celu_alpha", C.c_double)]
+                ("celu_alpha", C.c_double),
+                ("kind", C.c_int),
+                ("dp", _DpParams)]
 
 
 _lib = None
@@ -66,6 +72,8 @@ def _load():
         lib.orc_neighbours.argtypes = [C.c_int, dp, dp, C.c_double, C.c_int, C.c_int, ip, ip]
         lib.orc_energy_forces.argtypes = [C.c_int, dp, ip, dp, C.POINTER(_Model), dp, dp, dp, dp]
         lib.orc_sampled.argtypes = [C.c_int, dp, ip, dp, C.POINTER(_Model), C.c_int, ip, dp, dp]
+        lib.orc_dp_dim.argtypes = [C.POINTER(_DpParams)]
+        lib.orc_dp_descriptor.argtypes = [C.c_int, dp, ip, dp, C.POINTER(_DpParams), dp]
         lib.orc_net_energy.argtypes = [C.POINTER(_Model), C.c_int, C.c_int, dp, dp]
         lib.orc_net_energy.restype = C.c_double
         lib.orc_threads.restype = C.c_int
@@ -98,19 +106,34 @@ def _aev_struct(p: dict, keep: _Keep) -> _AevParams:
                       float(p.get("radial_scale", 0.25)))
 
 
+def _dp_struct(p: dict, keep: _Keep) -> _DpParams:
+    keep.sel = np.ascontiguousarray(p["sel"], dtype=np.int32)
+    return _DpParams(int(p["n_species"]), float(p["rc"]), _ip(keep.sel))
+
+
 class OracleModel:
-    """float64 copy of a ModelSpec laid out for the C oracle."""
+    """float64 copy of a ModelSpec laid out for the C oracle (AEV or
+    DeepPot-style descriptor, by spec.aev["kind"])."""
 
     def __init__(self, spec):
         self.spec = spec
         self._keep = _Keep()
-        self.aev_params = _aev_struct(spec.aev, self._keep)
+        is_dp = spec.aev.get("kind") == "dp"
+        if is_dp:
+            self.aev_params = _AevParams()
+            self.aev_params.n_species = int(spec.aev["n_species"])
+            self.dp_params = _dp_struct(spec.aev, self._keep)
+        else:
+            self.aev_params = _aev_struct(spec.aev, self._keep)
+            self.dp_params = _DpParams()
         self.n_layers = np.array([len(w) - 1 for w in spec.widths], dtype=np.int32)
         self.widths = np.concatenate([np.array(w, dtype=np.int32) for w in spec.widths])
         self.weights = np.ascontiguousarray(spec.weights, dtype=np.float64)
         self.struct = _Model(self.aev_params, int(spec.n_ensemble), _ip(self.n_layers),
-                             _ip(self.widths), _dp(self.weights), float(spec.celu_alpha))
-        self.dim = _load().orc_aev_dim(C.byref(self.aev_params))
+                             _ip(self.widths), _dp(self.weights), float(spec.celu_alpha),
+                             1 if is_dp else 0, self.dp_params)
+        lib = _load()
+        self.dim = lib.orc_dp_dim(C.byref(self.dp_params)) if is_dp else lib.orc_aev_dim(C.byref(self.aev_params))
 
 
 def threads() -> int:
@@ -215,3 +238,16 @@ def net_energy(model: OracleModel, member: int, species: int, G):
     g = np.zeros(model.dim, np.float64)
     E = lib.orc_net_energy(C.byref(model.struct), int(member), int(species), _dp(G), _dp(g))
     return float(E), g
+
+
+def dp_descriptor(coords, species, box, p: dict):
+    """DeepPot-style descriptor of every atom: float64 [n, 4 * sum(sel)]."""
+    lib = _load()
+    x, s, b = _sys_arrays(coords, species, box)
+    keep = _Keep()
+    st = _dp_struct(p, keep)
+    D = lib.orc_dp_dim(C.byref(st))
+    out = np.zeros((len(s), D), np.float64)
+    if len(s):
+        assert lib.orc_dp_descriptor(len(s), _dp(x), _ip(s), _dp(b), C.byref(st), _dp(out)) == 0
+    return out

@@ -23,6 +23,9 @@
  *   6. the total energy as the sum of atomic energies (energy-decomposition
  *      equation);
  *   7. forces and virial as the exact analytic gradient of that total.
+ * A second descriptor kind replaces steps 2-4 with the DeepPot local-frame
+ * environment of section "DeePMD Models" (species-sorted neighbours, local
+ * axes, {1/R, x/R, y/R, z/R}); steps 1 and 5-7 are shared.
  *
  * Readings where the paper is silent (each is also listed in the design
  * notes): the radial term carries a 0.25 prefactor; the angular sum runs over
@@ -55,13 +58,27 @@ typedef struct {
   double radial_scale;
 } orc_aev_params;
 
+/* DeepPot-style descriptor (section "DeePMD Models"): neighbours inside rc,
+ * grouped by species and ordered nearest first, at most sel[s] of species s
+ * kept; each kept neighbour contributes {1/R, x/R, y/R, z/R} in the centre's
+ * local frame. */
 typedef struct {
-  orc_aev_params aev;
+  int n_species;
+  double rc;
+  const int *sel;        /* [n_species] neighbours kept per species */
+} orc_dp_params;
+
+enum { ORC_ANI = 0, ORC_DP = 1 };
+
+typedef struct {
+  orc_aev_params aev;    /* descriptor of kind ORC_ANI */
   int n_ensemble;
   const int *n_layers;   /* [n_species] linear layers per network */
   const int *widths;     /* per species: n_layers + 1 widths, concatenated */
   const double *weights; /* (member, species, layer): W[out][in] then b[out] */
   double celu_alpha;
+  int kind;              /* ORC_ANI or ORC_DP */
+  orc_dp_params dp;      /* descriptor of kind ORC_DP */
 } orc_model;
 
 typedef struct {
@@ -258,7 +275,207 @@ int orc_aev(int n, const double *xyz, const int *species, const double *box,
   return bad ? -1 : 0;
 }
 
+/* ------------------------------------- 2'-4'. the DeepPot descriptor of a centre
+ *
+ * Section "DeePMD Models".  Readings where the paper is silent:
+ *   - "sorted by species and inverse distance": species ascending, then
+ *     inverse distance descending (nearest first); exact distance ties are
+ *     broken by neighbour index, then by lattice image (x, y, z) ascending;
+ *     the distance is compared through R^2 = (dx dx + dy dy) + dz dz in
+ *     float64, d = (r_j - r_i) + n L;
+ *   - at most sel[s] neighbours of species s are kept (the nearest ones);
+ *     their features fill slots sel[0] + ... + sel[s-1] + rank, slots past
+ *     the last neighbour of a species stay zero;
+ *   - the local frame: e_x along the nearest neighbour a, e_y along the
+ *     part of the second-nearest neighbour b orthogonal to e_x, and
+ *     e_z = e_x x e_y; with a single neighbour, or when b is collinear with
+ *     a (|u|^2 <= 1e-12 |d_b|^2), e_y = e_z = 0;
+ *   - no smoothing function at the cutoff (the paper gives none), so the
+ *     energy is continuous only away from the cutoff and from changes of
+ *     the neighbour order. */
+
+typedef struct {
+  const orc_nbr *e;
+  double r2;
+  int s;
+} dp_item;
+
+typedef struct {
+  int a, b;                    /* nb indices of the axis neighbours, or -1 */
+  double ex[3], ey[3], ez[3];  /* local axes (e_y = e_z = 0 when undefined) */
+  double ra;                   /* |d_a| */
+  double nu;                   /* |u|, u = d_b - (d_b . e_x) e_x; 0: e_y undefined */
+} dp_frame;
+
+int orc_dp_dim(const orc_dp_params *p) {
+  int k = 0;
+  for (int s = 0; s < p->n_species; ++s) k += p->sel[s];
+  return 4 * k;
+}
+
+static double dp_r2(const orc_nbr *e) {
+  return e->d[0] * e->d[0] + e->d[1] * e->d[1] + e->d[2] * e->d[2];
+}
+
+/* distance order: R^2, then neighbour index, then image */
+static int dp_cmp_dist(const dp_item *a, const dp_item *b) {
+  if (a->r2 != b->r2) return a->r2 < b->r2 ? -1 : 1;
+  if (a->e->j != b->e->j) return a->e->j < b->e->j ? -1 : 1;
+  for (int k = 0; k < 3; ++k)
+    if (a->e->n[k] != b->e->n[k]) return a->e->n[k] < b->e->n[k] ? -1 : 1;
+  return 0;
+}
+
+static int dp_cmp_species(const void *pa, const void *pb) {
+  const dp_item *a = (const dp_item *)pa, *b = (const dp_item *)pb;
+  if (a->s != b->s) return a->s < b->s ? -1 : 1;
+  return dp_cmp_dist(a, b);
+}
+
+static double dot3(const double *a, const double *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+
+static void cross3(const double *a, const double *b, double *c) {
+  c[0] = a[1] * b[2] - a[2] * b[1];
+  c[1] = a[2] * b[0] - a[0] * b[2];
+  c[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+static void dp_axes(const orc_nbr *nb, dp_frame *f) {
+  memset(f->ex, 0, sizeof f->ex);
+  memset(f->ey, 0, sizeof f->ey);
+  memset(f->ez, 0, sizeof f->ez);
+  f->ra = 0.0;
+  f->nu = 0.0;
+  if (f->a < 0) return;
+  const double *da = nb[f->a].d;
+  f->ra = nb[f->a].r;
+  for (int k = 0; k < 3; ++k) f->ex[k] = da[k] / f->ra;
+  if (f->b < 0) return;
+  const double *db = nb[f->b].d;
+  const double t = dot3(db, f->ex);
+  double u[3];
+  for (int k = 0; k < 3; ++k) u[k] = db[k] - t * f->ex[k];
+  const double uu = dot3(u, u);
+  if (!(uu > 1e-12 * dot3(db, db))) return;   /* collinear: e_y, e_z undefined */
+  f->nu = sqrt(uu);
+  for (int k = 0; k < 3; ++k) f->ey[k] = u[k] / f->nu;
+  cross3(f->ex, f->ey, f->ez);
+}
+
+/* Descriptor G[4 * sum(sel)] of one centre; slot[e] receives the slot of
+ * neighbour entry e (-1: not kept) and *fr the local frame. */
+static void centre_dp(const orc_nbr *nb, int nn, const int *species, const orc_dp_params *p,
+                      double *G, int *slot, dp_frame *fr) {
+  memset(G, 0, sizeof(double) * orc_dp_dim(p));
+  dp_item *it = (dp_item *)malloc(sizeof(dp_item) * (nn > 0 ? nn : 1));
+  for (int e = 0; e < nn; ++e) {
+    it[e].e = &nb[e];
+    it[e].r2 = dp_r2(&nb[e]);
+    it[e].s = species[nb[e].j];
+    slot[e] = -1;
+  }
+  /* the frame: the two nearest neighbours in distance order */
+  fr->a = fr->b = -1;
+  for (int e = 0; e < nn; ++e) {
+    if (fr->a < 0 || dp_cmp_dist(&it[e], &it[fr->a]) < 0) {
+      fr->b = fr->a;
+      fr->a = e;
+    } else if (fr->b < 0 || dp_cmp_dist(&it[e], &it[fr->b]) < 0) {
+      fr->b = e;
+    }
+  }
+  dp_axes(nb, fr);
+  /* species blocks, nearest first; the first sel[s] of species s are kept */
+  qsort(it, (size_t)nn, sizeof(dp_item), dp_cmp_species);
+  int first_slot = 0, prev_s = -1, rank = 0;
+  for (int k = 0; k < nn; ++k) {
+    const int s = it[k].s;
+    if (s != prev_s) {
+      first_slot = 0;
+      for (int q = 0; q < s; ++q) first_slot += p->sel[q];
+      rank = 0;
+      prev_s = s;
+    }
+    if (rank < p->sel[s]) {
+      const int e = (int)(it[k].e - nb);
+      const double *d = nb[e].d, R = nb[e].r;
+      const int q = first_slot + rank;
+      slot[e] = q;
+      G[4 * q + 0] = 1.0 / R;
+      G[4 * q + 1] = dot3(d, fr->ex) / R;
+      G[4 * q + 2] = dot3(d, fr->ey) / R;
+      G[4 * q + 3] = dot3(d, fr->ez) / R;
+    }
+    ++rank;
+  }
+  free(it);
+}
+
+/* Given g = dE/dG of the centre, writes gd[e] = dE/dd_e for each neighbour:
+ * the explicit dependence of a kept neighbour's four features on its own
+ * vector, plus the dependence of every x, y, z on the frame, which reaches
+ * the axis neighbours a and b (e_x = d_a / |d_a|, e_y = u / |u| with
+ * u = (I - e_x e_x^T) d_b, e_z = e_x x e_y). */
+static void centre_dp_grad(const orc_nbr *nb, int nn, const int *slot, const dp_frame *fr,
+                           const double *g, double (*gd)[3]) {
+  double A[3][3] = {{0}};  /* A[c] = dE/de_c with the other axes fixed */
+  for (int e = 0; e < nn; ++e) {
+    gd[e][0] = gd[e][1] = gd[e][2] = 0.0;
+    if (slot[e] < 0) continue;
+    const double *gs = g + 4 * slot[e], *d = nb[e].d, R = nb[e].r;
+    const double c[3] = {dot3(d, fr->ex), dot3(d, fr->ey), dot3(d, fr->ez)};
+    /* d(1/R)/dd = -d/R^3; d(c/R)/dd = e_c/R - c d/R^3 */
+    const double s = gs[0] + gs[1] * c[0] + gs[2] * c[1] + gs[3] * c[2];
+    for (int k = 0; k < 3; ++k) {
+      gd[e][k] += -s * d[k] / (R * R * R) + (gs[1] * fr->ex[k] + gs[2] * fr->ey[k] + gs[3] * fr->ez[k]) / R;
+      for (int q = 0; q < 3; ++q) A[q][k] += gs[1 + q] * d[k] / R;
+    }
+  }
+  if (fr->a < 0) return;
+  double Bx[3] = {A[0][0], A[0][1], A[0][2]};
+  if (fr->nu > 0.0) {
+    double By[3] = {A[1][0], A[1][1], A[1][2]}, t[3];
+    cross3(fr->ey, A[2], t);               /* e_z = e_x x e_y, through e_x */
+    for (int k = 0; k < 3; ++k) Bx[k] += t[k];
+    cross3(A[2], fr->ex, t);               /* ... and through e_y */
+    for (int k = 0; k < 3; ++k) By[k] += t[k];
+    const double *db = nb[fr->b].d;
+    const double byy = dot3(By, fr->ey);
+    double C[3];                            /* dE/du */
+    for (int k = 0; k < 3; ++k) C[k] = (By[k] - byy * fr->ey[k]) / fr->nu;
+    const double cx = dot3(C, fr->ex), bx = dot3(db, fr->ex);
+    for (int k = 0; k < 3; ++k) {
+      gd[fr->b][k] += C[k] - cx * fr->ex[k];
+      Bx[k] += -cx * db[k] - bx * C[k];     /* u depends on e_x too */
+    }
+  }
+  const double bxx = dot3(Bx, fr->ex);
+  for (int k = 0; k < 3; ++k) gd[fr->a][k] += (Bx[k] - bxx * fr->ex[k]) / fr->ra;
+}
+
+int orc_dp_descriptor(int n, const double *xyz, const int *species, const double *box,
+                      const orc_dp_params *p, double *out) {
+  const int D = orc_dp_dim(p);
+  int bad = 0;
+  #pragma omp parallel for schedule(dynamic, 4) reduction(| : bad)
+  for (int i = 0; i < n; ++i) {
+    int nn;
+    orc_nbr *nb = neighbours_alloc(n, xyz, box, i, p->rc, &nn);
+    int *slot = (int *)malloc(sizeof(int) * (nn > 0 ? nn : 1));
+    dp_frame fr;
+    centre_dp(nb, nn, species, p, out + (size_t)i * D, slot, &fr);
+    free(slot);
+    free(nb);
+  }
+  return bad ? -1 : 0;
+}
+
 /* ----------------------------------------------------- 5. element networks */
+
+/* Descriptor of either kind: species count, length and cutoff. */
+static int model_species(const orc_model *m) { return m->kind == ORC_DP ? m->dp.n_species : m->aev.n_species; }
+static int model_dim(const orc_model *m) { return m->kind == ORC_DP ? orc_dp_dim(&m->dp) : orc_aev_dim(&m->aev); }
+static double model_rc(const orc_model *m) { return m->kind == ORC_DP ? m->dp.rc : m->aev.rc_rad; }
 
 static double celu(double z, double alpha) {
   return z > 0.0 ? z : alpha * (exp(z / alpha) - 1.0);
@@ -272,7 +489,7 @@ static double dcelu(double z, double alpha) {
 static size_t net_offset(const orc_model *m, int member, int species) {
   size_t per_member = 0, off_s = 0;
   int wo = 0;
-  for (int s = 0; s < m->aev.n_species; ++s) {
+  for (int s = 0; s < model_species(m); ++s) {
     size_t cnt = 0;
     for (int l = 0; l < m->n_layers[s]; ++l)
       cnt += (size_t)m->widths[wo + l] * m->widths[wo + l + 1] + m->widths[wo + l + 1];
@@ -345,7 +562,7 @@ static double net_energy(const orc_model *m, int member, int species,
 
 /* Ensemble-averaged atomic energy and (optionally) its AEV gradient. */
 static double atom_energy(const orc_model *m, int species, const double *G, double *dEdG) {
-  const int D = orc_aev_dim(&m->aev);
+  const int D = model_dim(m);
   if (dEdG) memset(dEdG, 0, sizeof(double) * D);
   double E = 0.0;
   const double inv = 1.0 / m->n_ensemble;
@@ -357,7 +574,7 @@ static double atom_energy(const orc_model *m, int species, const double *G, doub
 /* Exported for tests: one network (member, species) on one AEV. */
 double orc_net_energy(const orc_model *m, int member, int species,
                       const double *G, double *dEdG) {
-  if (dEdG) memset(dEdG, 0, sizeof(double) * orc_aev_dim(&m->aev));
+  if (dEdG) memset(dEdG, 0, sizeof(double) * model_dim(m));
   return net_energy(m, member, species, G, dEdG, 1.0);
 }
 
@@ -438,6 +655,21 @@ static void centre_aev_grad(const orc_nbr *nb, int nn, const int *species,
   }
 }
 
+/* One centre's descriptor and its gradient, for either kind.  slot and fr
+ * carry the DeepPot slot assignment and frame from the forward to the
+ * gradient (unused for the AEV). */
+static void centre_desc(const orc_model *m, const orc_nbr *nb, int nn, const int *species,
+                        double *G, int *slot, dp_frame *fr) {
+  if (m->kind == ORC_DP) centre_dp(nb, nn, species, &m->dp, G, slot, fr);
+  else centre_aev(nb, nn, species, &m->aev, G);
+}
+
+static void centre_desc_grad(const orc_model *m, const orc_nbr *nb, int nn, const int *species,
+                             const int *slot, const dp_frame *fr, const double *g, double (*gd)[3]) {
+  if (m->kind == ORC_DP) centre_dp_grad(nb, nn, slot, fr, g, gd);
+  else centre_aev_grad(nb, nn, species, &m->aev, g, gd);
+}
+
 /* -------------------------------------- 6-7. energy, forces, virial of a system */
 
 /* e_atom[n]: ensemble-mean atomic energies; forces[n][3] (nullable);
@@ -447,7 +679,7 @@ static void centre_aev_grad(const orc_nbr *nb, int nn, const int *species,
 int orc_energy_forces(int n, const double *xyz, const int *species,
                       const double *box, const orc_model *m, double *e_atom,
                       double *energy, double *forces, double *virial) {
-  const int D = orc_aev_dim(&m->aev);
+  const int D = model_dim(m);
   const int T = orc_omp_threads();
   const int need_grad = forces != NULL || virial != NULL;
   double *Fth = need_grad ? (double *)calloc((size_t)T * n * 3, sizeof(double)) : NULL;
@@ -464,12 +696,14 @@ int orc_energy_forces(int n, const double *xyz, const int *species,
     #pragma omp for schedule(static)
     for (int i = 0; i < n; ++i) {
       int nn;
-      orc_nbr *nb = neighbours_alloc(n, xyz, box, i, m->aev.rc_rad, &nn);
-      centre_aev(nb, nn, species, &m->aev, G);
+      orc_nbr *nb = neighbours_alloc(n, xyz, box, i, model_rc(m), &nn);
+      int *slot = (int *)malloc(sizeof(int) * (nn > 0 ? nn : 1));
+      dp_frame fr;
+      centre_desc(m, nb, nn, species, G, slot, &fr);
       e_atom[i] = atom_energy(m, species[i], G, g);
       if (need_grad) {
         double (*gd)[3] = (double (*)[3])malloc(sizeof(double) * 3 * (nn > 0 ? nn : 1));
-        centre_aev_grad(nb, nn, species, &m->aev, g, gd);
+        centre_desc_grad(m, nb, nn, species, slot, &fr, g, gd);
         double *F = Fth + (size_t)t * n * 3;
         double *W = Wth + (size_t)t * 9;
         for (int e = 0; e < nn; ++e) {
@@ -481,6 +715,7 @@ int orc_energy_forces(int n, const double *xyz, const int *species,
         }
         free(gd);
       }
+      free(slot);
       free(nb);
     }
     free(G);
@@ -510,13 +745,14 @@ int orc_energy_forces(int n, const double *xyz, const int *species,
  *
  * The force on atom t collects the derivative of every atomic energy whose
  * environment contains t: its own, and that of every centre c having some
- * image of t inside the radial cutoff.  Each such centre is evaluated from
+ * image of t inside the descriptor's cutoff.  Each such centre is evaluated from
  * scratch, so the cost is independent of system size apart from the
  * brute-force neighbour scans.  e_t[nt], f_t[nt][3]. */
 int orc_sampled(int n, const double *xyz, const int *species, const double *box,
                 const orc_model *m, int nt, const int *targets, double *e_t,
                 double *f_t) {
-  const int D = orc_aev_dim(&m->aev);
+  const int D = model_dim(m);
+  const double rc = model_rc(m);
   int bad = 0;
   #pragma omp parallel for schedule(dynamic, 1) reduction(| : bad)
   for (int q = 0; q < nt; ++q) {
@@ -524,7 +760,7 @@ int orc_sampled(int n, const double *xyz, const int *species, const double *box,
     double *G = (double *)malloc(sizeof(double) * D);
     double *g = (double *)malloc(sizeof(double) * D);
     int nt_nb;
-    orc_nbr *tn = neighbours_alloc(n, xyz, box, t, m->aev.rc_rad, &nt_nb);
+    orc_nbr *tn = neighbours_alloc(n, xyz, box, t, rc, &nt_nb);
     /* unique centre list: t first, then every distinct neighbour index */
     int *centres = (int *)malloc(sizeof(int) * (nt_nb + 1));
     int nc = 0;
@@ -537,12 +773,14 @@ int orc_sampled(int n, const double *xyz, const int *species, const double *box,
     double F[3] = {0.0, 0.0, 0.0};
     for (int k = 0; k < nc; ++k) {
       int c = centres[k], nn;
-      orc_nbr *nb = neighbours_alloc(n, xyz, box, c, m->aev.rc_rad, &nn);
-      centre_aev(nb, nn, species, &m->aev, G);
+      orc_nbr *nb = neighbours_alloc(n, xyz, box, c, rc, &nn);
+      int *slot = (int *)malloc(sizeof(int) * (nn > 0 ? nn : 1));
+      dp_frame fr;
+      centre_desc(m, nb, nn, species, G, slot, &fr);
       double E = atom_energy(m, species[c], G, g);
       if (c == t) e_t[q] = E;
       double (*gd)[3] = (double (*)[3])malloc(sizeof(double) * 3 * (nn > 0 ? nn : 1));
-      centre_aev_grad(nb, nn, species, &m->aev, g, gd);
+      centre_desc_grad(m, nb, nn, species, slot, &fr, g, gd);
       for (int e = 0; e < nn; ++e) {
         for (int a = 0; a < 3; ++a) {
           if (c == t) F[a] += gd[e][a];
@@ -550,6 +788,7 @@ int orc_sampled(int n, const double *xyz, const int *species, const double *box,
         }
       }
       free(gd);
+      free(slot);
       free(nb);
     }
     for (int a = 0; a < 3; ++a) f_t[3 * q + a] = F[a];

@@ -52,7 +52,22 @@ def aev_params() -> dict:
     )
 
 
+# DeepPot-style descriptor (section "DeePMD Models"): neighbours kept per
+# species slot, nearest first.  Within 6 A of an atom of water or a solvated
+# protein sit about 60 H, 30 O and (protein) 15 C / 4 N.
+DP_SEL = (48, 24, 8, 24, 4, 4, 8)
+
+
+def dp_params(rc: float = 6.0, sel=DP_SEL) -> dict:
+    """DeepPot-style descriptor hyper-parameters: cutoff 6 A, at most sel[s]
+    neighbours of species s (120 slots, 4 features each -> 480 features)."""
+    return dict(kind="dp", n_species=len(sel), rc=float(rc), sel=tuple(int(x) for x in sel))
+
+
 def aev_dim(p: dict) -> int:
+    """Descriptor length of either kind (AEV or DeepPot-style)."""
+    if p.get("kind") == "dp":
+        return 4 * sum(p["sel"])
     s = p["n_species"]
     return s * len(p["shf_rad"]) + (s * (s + 1) // 2) * len(p["shf_ang"]) * len(p["shf_z"])
 
@@ -85,6 +100,11 @@ class ModelSpec:
     @property
     def n_species(self) -> int:
         return len(self.widths)
+
+    @property
+    def kind(self) -> str:
+        """Descriptor kind: "ani" (AEV) or "dp" (DeepPot-style)."""
+        return self.aev.get("kind", "ani")
 
     def layer_slices(self):
         """Yield (member, species, layer, W_slice, b_slice, n_out, n_in)."""
@@ -138,6 +158,13 @@ def make_model(seed: int = 0, n_ensemble: int = 1, hidden=None, aev=None,
     assert off == total
     return ModelSpec(aev=aev, n_ensemble=n_ensemble, widths=widths, weights=out,
                      celu_alpha=celu_alpha)
+
+
+def make_dp_model(seed: int = 0, n_ensemble: int = 1, hidden=None, dp=None,
+                  celu_alpha: float = 0.1) -> ModelSpec:
+    """Random network set on the DeepPot-style descriptor (same networks,
+    480 inputs)."""
+    return make_model(seed, n_ensemble, hidden, dp if dp is not None else dp_params(), celu_alpha)
 
 
 def linear_readout_model(seed: int = 0, aev=None) -> ModelSpec:
