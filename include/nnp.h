@@ -102,6 +102,46 @@ typedef struct {
 int nnp_create(const nnp_model_desc *desc, nnp_model **out);
 void nnp_destroy(nnp_model *model);
 
+/* DeepPot-style local-frame descriptor (section "DeePMD Models"), a second
+ * model family behind the same entry points.  The neighbours of a centre
+ * within rc are grouped by species (ascending slot) and ordered nearest
+ * first; at most sel[s] of species s are kept, in slots
+ * sel[0] + ... + sel[s-1] + rank, and each kept neighbour fills four features
+ * {1/R, x/R, y/R, z/R}: (x, y, z) = (d . e_x, d . e_y, d . e_z) in the
+ * centre's local frame, e_x along the nearest neighbour a, e_y along the part
+ * of the second nearest b orthogonal to e_x, e_z = e_x x e_y (e_y = e_z = 0
+ * with a single neighbour or when b is collinear with a, |u|^2 <= 1e-12
+ * |d_b|^2).  Empty slots are zero; the descriptor length is 4 * sum(sel).
+ * The neighbour order and the cutoff test are decided in float64 from the
+ * caller's float32 coordinates: d = (r_j - r_i) + n L (n the lattice image
+ * relative to those coordinates), R^2 = (dx dx + dy dy) + dz dz, R^2 < rc^2,
+ * each operation rounded on its own; exact ties go to the smaller neighbour
+ * index within the system, then the smaller image (x, y, z).  No smoothing
+ * at the cutoff.  Neighbour lists reach rc + 1e-3 A (plus a pool's skin).
+ * This build runs n_species <= 7 and sum(sel) <= 256. */
+typedef struct {
+  int n_species;
+  float rc;        /* cutoff, Angstrom */
+  const int *sel;  /* HOST int[n_species], copied at creation */
+} nnp_dp_params;
+
+/* A DeepPot-style model: the descriptor and the same element networks as
+ * nnp_model_desc (widths[s][0] must be 4 * sum(sel)). */
+typedef struct {
+  nnp_dp_params dp;
+  int n_ensemble;
+  const int *n_layers;
+  const int *widths;
+  const float *weights;
+  float celu_alpha;
+  int precision;
+} nnp_dp_model_desc;
+
+/* Builds a DeepPot-style model on the current HIP device; the handle works
+ * with every entry point below (energies, forces, virials, pair lists,
+ * persistent lists, descriptor export, serving). */
+int nnp_create_dp(const nnp_dp_model_desc *desc, nnp_model **out);
+
 /* Pre-sizes the library workspace (the paper's bounded up-front buffer,
  * section "Massive Parallelism within Tinker-HP") for calls of up to
  * max_atoms atoms and max_systems systems, and sets the per-atom neighbour
@@ -206,8 +246,9 @@ int nnp_energy_forces_pairs(nnp_model *model, int64_t n_atoms, const float *coor
  * far (forced and skin-triggered). */
 int nnp_nlist_builds(nnp_nlist *list, void *stream, int64_t *builds);
 
-/* Same inputs; writes the AEV of every atom, DEVICE float32[N][aev_dim],
- * atom order.  For tests and inspection. */
+/* Same inputs; writes the descriptor (AEV, or the DeepPot-style
+ * environment) of every atom, DEVICE float32[N][nnp_aev_dim], atom order.
+ * For tests and inspection. */
 int nnp_debug_aev(nnp_model *model, int n_systems, const int64_t *batch_offsets,
                   const float *coords, const int32_t *species, const float *box,
                   float *aev_out, void *stream);
@@ -382,7 +423,8 @@ int nnp_bar(int64_t n0, const double *u, const double *lw0, int64_t n1, const do
  * *max_neighbors (nullable) receives the largest neighbour count seen. */
 int nnp_status(nnp_model *model, void *stream, int *max_neighbors);
 
-/* AEV length of the model (1008 for 7 species). */
+/* Descriptor length of the model: the AEV length (1008 for 7 species), or
+ * 4 * sum(sel) for a DeepPot-style model. */
 int nnp_aev_dim(const nnp_model *model);
 
 /* Message of the last failed call on this thread ("" if none). */

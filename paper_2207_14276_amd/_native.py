@@ -53,6 +53,20 @@ class nnp_model_desc(C.Structure):
                 ("precision", C.c_int)]
 
 
+class nnp_dp_params(C.Structure):
+    _fields_ = [("n_species", C.c_int), ("rc", C.c_float), ("sel", C.POINTER(C.c_int))]
+
+
+class nnp_dp_model_desc(C.Structure):
+    _fields_ = [("dp", nnp_dp_params),
+                ("n_ensemble", C.c_int),
+                ("n_layers", C.POINTER(C.c_int)),
+                ("widths", C.POINTER(C.c_int)),
+                ("weights", C.POINTER(C.c_float)),
+                ("celu_alpha", C.c_float),
+                ("precision", C.c_int)]
+
+
 class nnp_server_opts(C.Structure):
     _fields_ = [("slots", C.c_int64), ("nbr_capacity", C.c_int), ("skin", C.c_float),
                 ("max_batch_atoms", C.c_int64), ("max_active", C.c_int),
@@ -76,7 +90,7 @@ EXPORTS = ["nnp_create", "nnp_destroy", "nnp_reserve", "nnp_energy_forces", "nnp
            "nnp_debug_neighbors", "nnp_status", "nnp_aev_dim", "nnp_last_error",
            "nnp_set_timing", "nnp_stage_timings", "nnp_nlist_create", "nnp_nlist_destroy",
            "nnp_energy_forces_nlist", "nnp_nlist_builds", "nnp_autotune", "nnp_tuning",
-           "nnp_energy_forces_pairs", "nnp_bar",
+           "nnp_energy_forces_pairs", "nnp_bar", "nnp_create_dp",
            "nnp_server_create", "nnp_server_destroy", "nnp_server_clock", "nnp_server_submit",
            "nnp_server_step", "nnp_server_drain", "nnp_server_poll", "nnp_server_result",
            "nnp_server_stats",
@@ -98,6 +112,7 @@ def load():
     vp, i64p = C.c_void_p, C.POINTER(C.c_int64)
     fp = C.POINTER(C.c_float)
     lib.nnp_create.argtypes = [C.POINTER(nnp_model_desc), C.POINTER(C.c_void_p)]
+    lib.nnp_create_dp.argtypes = [C.POINTER(nnp_dp_model_desc), C.POINTER(C.c_void_p)]
     lib.nnp_destroy.argtypes = [vp]
     lib.nnp_destroy.restype = None
     lib.nnp_reserve.argtypes = [vp, C.c_int64, C.c_int, C.c_int]

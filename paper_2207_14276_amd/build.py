@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIBDIR = os.path.join(HERE, "lib")
 LIB = os.path.join(LIBDIR, "libnnp.so")
-SOURCES = ["api.hip", "nbr.hip", "aev.hip", "mlp.hip", "chain.hip", "server.hip", "bar.hip"]
+SOURCES = ["api.hip", "nbr.hip", "aev.hip", "mlp.hip", "chain.hip", "server.hip", "bar.hip", "deeppot.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -74,6 +74,7 @@ struct DevBuf {
 constexpr int kStages = 8;
 // Tunable launch shapes ("sites"): waves per workgroup of the AEV forward and
 // backward kernels, column-tile width of each dense-layer GEMM.
+enum { kDescAev = 0, kDescDp = 1 };  // descriptor kinds
 enum { kSiteAevFwd = 0, kSiteAevBwd = 1, kSiteGemmFwd = 2, kSiteGemmBwd = 10, kSiteGemmOut = 18,
        kSiteChain = 19, kTuneSites = 20 };
 constexpr int kMaxTimedCalls = 4096;  // timed calls held between two reads
@@ -96,7 +97,11 @@ struct nnp_model {
   int S = 0, M = 1, L = 1;
   int precision = NNP_FP32;
   float alpha = 0.1f;
-  AevConst aev{};
+  int kind = 0;                          // kDescAev or kDescDp
+  AevConst aev{};                        // descriptor of kind kDescAev
+  DpConst dp{};                          // descriptor of kind kDescDp
+  int D = 0;                             // descriptor length (the networks' input width)
+  float rc_desc = 0.f;                   // neighbour-list cutoff of the descriptor (no skin)
   std::vector<std::vector<int>> widths;  // [S][L+1]
   std::vector<int> ldH;                  // [L-1] max width of hidden layer l
   std::vector<LayerW> layers;            // [(M * S + s) * L + l]
@@ -112,7 +117,7 @@ struct nnp_model {
   // workspace
   DevBuf pos, sys_of, atom_cell, atom_slot, cell_count, cell_start, cell_atoms, nbr, nbr_cnt;
   DevBuf block_counts, bucket_off, bucket_cnt, perm, row_of_atom, G, dG, e_atom, W_atom, partial;
-  DevBuf sysdesc, chunk_sys, chunk_begin, sys_chunk_off, status, state, e_mem;
+  DevBuf sysdesc, chunk_sys, chunk_begin, sys_chunk_off, status, state, e_mem, dp_map;
   std::vector<DevBuf> H, Gd;
   // fused hidden-layer chain (bfloat16 models whose hidden widths allow it)
   bool chain = false;
@@ -177,7 +182,7 @@ extern "C" void nnp_destroy(nnp_model *m) {
                     &m->bucket_off, &m->bucket_cnt, &m->perm, &m->row_of_atom, &m->G, &m->dG,
                     &m->e_atom, &m->W_atom, &m->partial, &m->sysdesc, &m->chunk_sys,
                     &m->chunk_begin, &m->sys_chunk_off, &m->status, &m->state, &m->e_mem,
-                    &m->chain_nets};
+                    &m->chain_nets, &m->dp_map};
   for (DevBuf *b : bufs) b->release();
   for (auto &b : m->H) b.release();
   for (auto &b : m->Gd) b.release();
@@ -192,8 +197,20 @@ extern "C" void nnp_destroy(nnp_model *m) {
   delete m;
 }
 
-static int create_impl(const nnp_model_desc *d, nnp_model *m) {
-  const nnp_aev_params &a = d->aev;
+// Network half of a model description (shared by both descriptor kinds).
+struct NetArgs {
+  int n_ensemble;
+  const int *n_layers;
+  const int *widths;
+  const float *weights;
+  float celu_alpha;
+  int precision;
+};
+
+static int create_networks(const NetArgs *d, nnp_model *m);
+
+static int create_impl(const nnp_model_desc *dd, nnp_model *m) {
+  const nnp_aev_params &a = dd->aev;
   if (a.n_species < 1 || a.n_species > kMaxSpecies)
     return fail(NNP_EUNSUPPORTED, "n_species must be in 1..%d (got %d)", kMaxSpecies, a.n_species);
   if (a.n_shf_rad != kNShfRad || a.n_shf_ang != kNShfAng || a.n_shf_z != kNShfZ)
@@ -202,16 +219,8 @@ static int create_impl(const nnp_model_desc *d, nnp_model *m) {
   if (!(a.rc_rad > 0.f) || !(a.rc_ang > 0.f) || a.rc_ang > a.rc_rad)
     return fail(NNP_EUNSUPPORTED, "need 0 < rc_ang <= rc_rad");
   if (!(a.zeta >= 1.f)) return fail(NNP_EUNSUPPORTED, "zeta must be >= 1");
-  if (d->n_ensemble < 1) return fail(NNP_EINVAL, "n_ensemble must be >= 1");
-  if (d->n_ensemble > kMaxMembers) return fail(NNP_EUNSUPPORTED, "at most %d ensemble members", kMaxMembers);
-  if (!d->n_layers || !d->widths || !d->weights) return fail(NNP_EINVAL, "null network array");
-  if (d->precision != NNP_FP32 && d->precision != NNP_BF16) return fail(NNP_EINVAL, "bad precision");
-  if (!(d->celu_alpha > 0.f)) return fail(NNP_EINVAL, "celu_alpha must be > 0");
   const int S = a.n_species;
   m->S = S;
-  m->M = d->n_ensemble;
-  m->precision = d->precision;
-  m->alpha = d->celu_alpha;
   AevConst &c = m->aev;
   c.rc_r = a.rc_rad; c.eta_r = a.eta_rad; c.rc_a = a.rc_ang; c.eta_a = a.eta_ang;
   c.zeta = a.zeta; c.scale = a.radial_scale;
@@ -224,6 +233,55 @@ static int create_impl(const nnp_model_desc *d, nnp_model *m) {
   c.S = S;
   c.rad_len = S * kNShfRad;
   c.D = c.rad_len + S * (S + 1) / 2 * kAngBlock;
+  m->kind = kDescAev;
+  m->D = c.D;
+  m->rc_desc = a.rc_rad;
+  const NetArgs net{dd->n_ensemble, dd->n_layers, dd->widths, dd->weights, dd->celu_alpha, dd->precision};
+  return create_networks(&net, m);
+}
+
+static int create_dp_impl(const nnp_dp_model_desc *dd, nnp_model *m) {
+  const nnp_dp_params &p = dd->dp;
+  if (p.n_species < 1 || p.n_species > kMaxSpecies)
+    return fail(NNP_EUNSUPPORTED, "n_species must be in 1..%d (got %d)", kMaxSpecies, p.n_species);
+  if (!p.sel) return fail(NNP_EINVAL, "null sel array");
+  if (!(p.rc > 0.f) || !(p.rc < 1e3f)) return fail(NNP_EINVAL, "cutoff must be positive and finite");
+  DpConst &c = m->dp;
+  memset(&c, 0, sizeof c);
+  int slots = 0;
+  for (int s = 0; s < p.n_species; ++s) {
+    if (p.sel[s] < 0) return fail(NNP_EINVAL, "sel must be >= 0");
+    c.sel[s] = p.sel[s];
+    c.soff[s] = slots;
+    slots += p.sel[s];
+    if (slots > kDpMaxSlots) return fail(NNP_EUNSUPPORTED, "at most %d neighbour slots in total", kDpMaxSlots);
+  }
+  if (slots < 1) return fail(NNP_EINVAL, "sel must keep at least one neighbour");
+  c.S = p.n_species;
+  c.n_slots = slots;
+  c.D = 4 * slots;
+  c.ldm = (slots + 2 + 7) / 8 * 8;
+  c.rc2 = (double)p.rc * (double)p.rc;
+  m->S = p.n_species;
+  m->kind = kDescDp;
+  m->D = c.D;
+  // the lists reach 1e-3 A past the cutoff: every neighbour the float64
+  // cutoff test admits is in them whatever the float32 rounding
+  m->rc_desc = p.rc + 1e-3f;
+  const NetArgs net{dd->n_ensemble, dd->n_layers, dd->widths, dd->weights, dd->celu_alpha, dd->precision};
+  return create_networks(&net, m);
+}
+
+static int create_networks(const NetArgs *d, nnp_model *m) {
+  if (d->n_ensemble < 1) return fail(NNP_EINVAL, "n_ensemble must be >= 1");
+  if (d->n_ensemble > kMaxMembers) return fail(NNP_EUNSUPPORTED, "at most %d ensemble members", kMaxMembers);
+  if (!d->n_layers || !d->widths || !d->weights) return fail(NNP_EINVAL, "null network array");
+  if (d->precision != NNP_FP32 && d->precision != NNP_BF16) return fail(NNP_EINVAL, "bad precision");
+  if (!(d->celu_alpha > 0.f)) return fail(NNP_EINVAL, "celu_alpha must be > 0");
+  const int S = m->S;
+  m->M = d->n_ensemble;
+  m->precision = d->precision;
+  m->alpha = d->celu_alpha;
   const int L = d->n_layers[0];
   if (L < 1) return fail(NNP_EINVAL, "n_layers must be >= 1");
   if (L > 9) return fail(NNP_EUNSUPPORTED, "at most 9 layers per network");
@@ -241,10 +299,10 @@ static int create_impl(const nnp_model_desc *d, nnp_model *m) {
       m->widths[s][l] = w;
     }
   for (int s = 0; s < S; ++s) {
-    if (m->widths[s][0] != c.D) return fail(NNP_EINVAL, "first width must be the AEV length %d", c.D);
+    if (m->widths[s][0] != m->D) return fail(NNP_EINVAL, "first width must be the descriptor length %d", m->D);
     if (m->widths[s][L] != 1) return fail(NNP_EINVAL, "last width must be 1");
   }
-  m->ldG = (c.D + 31) / 32 * 32;
+  m->ldG = (m->D + 31) / 32 * 32;
   m->ldH.assign(std::max(L - 1, 0), 0);
   for (int l = 0; l + 1 < L; ++l)
     for (int s = 0; s < S; ++s) m->ldH[l] = std::max(m->ldH[l], m->widths[s][l + 1]);
@@ -379,7 +437,20 @@ extern "C" int nnp_create(const nnp_model_desc *d, nnp_model **out) {
   return NNP_OK;
 }
 
-extern "C" int nnp_aev_dim(const nnp_model *m) { return m ? m->aev.D : NNP_EINVAL; }
+extern "C" int nnp_create_dp(const nnp_dp_model_desc *d, nnp_model **out) {
+  if (!d || !out) return fail(NNP_EINVAL, "null argument");
+  *out = nullptr;
+  nnp_model *m = new nnp_model();
+  int rc = create_dp_impl(d, m);
+  if (rc != NNP_OK) {
+    nnp_destroy(m);
+    return rc;
+  }
+  *out = m;
+  return NNP_OK;
+}
+
+extern "C" int nnp_aev_dim(const nnp_model *m) { return m ? m->D : NNP_EINVAL; }
 
 // Buffers for a call of N atoms, S systems, C cells and n_chunks chunks.
 // Workspace of a call with N atoms, S systems, C cells and n_chunks
@@ -411,7 +482,8 @@ static int for_each_ws(nnp_model *m, int64_t N, int S, int64_t C, int n_chunks, 
   ENS(m->row_of_atom, N * 4);
   const int esz = m->precision == NNP_BF16 ? 2 : 4;  // activation element size
   ENS(m->G, rows * m->ldG * esz);
-  ENS(m->dG, rows * m->aev.D * 4);
+  ENS(m->dG, rows * m->D * 4);
+  if (m->kind == kDescDp) ENS(m->dp_map, N * (int64_t)m->dp.ldm * 2);
   ENS(m->e_atom, N * 4);
   if (m->chain) ENS(m->e_mem, rows * m->M * 4);
   ENS(m->W_atom, N * 36);
@@ -614,7 +686,7 @@ static int run(nnp_model *m, int n_sys, const int64_t *offs, const float *coords
       if (r[q].first < r[q - 1].second) return fail(NNP_EINVAL, "overlapping slot ranges");
   }
   const int cap = nl ? nl->cap : m->cap;
-  const float rc_list = m->aev.rc_r + (nl ? nl->skin : 0.f);
+  const float rc_list = m->rc_desc + (nl ? nl->skin : 0.f);
   const float rc_cell = rc_list * (1.0f + 1e-5f);
   std::vector<SysDesc> sd(n_sys);
   int64_t C = 0;
@@ -795,25 +867,34 @@ static int run(nnp_model *m, int n_sys, const int64_t *offs, const float *coords
   // atoms outside a caller's mask have no network: zero atomic energy
   if (pin.mask) launch_fill(m->e_atom.as<float>(), (size_t)N, 0.f, st);
   mark();
-  const int D = m->aev.D;
+  const int D = m->D;
   const bool bf16 = m->precision == NNP_BF16;
+  const bool dp = m->kind == kDescDp;
+  const bool want_grad = o.forces != nullptr;
+  // descriptor forward into rows of G (the AEV export: float32 rows of the
+  // dE/dG buffer, gathered back to atom order)
+  auto descriptor = [&](void *Gp, bool g_bf16, int ldg, uint16_t *map, int wpb) {
+    if (dp)
+      launch_dp_fwd(pos, coords, pool_state, m->sys_of.as<int>(), dsys, pool_nbr, pool_cnt, cap,
+                    m->row_of_atom.as<int>(), Gp, g_bf16, ldg, N, m->dp, map, wpb, st);
+    else
+      launch_aev_fwd(pos, m->sys_of.as<int>(), dsys, pool_nbr, pool_cnt, cap, m->row_of_atom.as<int>(), Gp,
+                     g_bf16, ldg, N, m->aev, wpb, st);
+  };
   if (mode == kAev) {
-    // float32 AEV into the (float32) dE/dG buffer, then back to atom order
-    launch_aev_fwd(pos, m->sys_of.as<int>(), dsys, pool_nbr, pool_cnt, cap,
-                   m->row_of_atom.as<int>(), m->dG.p, false, D, N, m->aev, 0, st);
+    descriptor(m->dG.p, false, D, nullptr, 0);
     launch_gather_rows(m->dG.as<float>(), D, m->row_of_atom.as<int>(), N, D, o.aev, st);
     HIP_TRY(hipGetLastError());
     return NNP_OK;
   }
   site_begin(kSiteAevFwd);
-  launch_aev_fwd(pos, m->sys_of.as<int>(), dsys, pool_nbr, pool_cnt, cap,
-                 m->row_of_atom.as<int>(), m->G.p, bf16, m->ldG, N, m->aev, m->tune_val[kSiteAevFwd], st);
+  descriptor(m->G.p, bf16, m->ldG, dp && want_grad ? m->dp_map.as<uint16_t>() : nullptr,
+             m->tune_val[kSiteAevFwd]);
   site_end(kSiteAevFwd);
   mark();
 
   // element networks: forward, output layer, backward to dE/dG; every launch
   // covers all species and all ensemble members of one layer index
-  const bool want_grad = o.forces != nullptr;
   const int row_tiles = rows / kTileM;
   const int L = m->L, M = m->M, S = m->S;
   auto common = [&](GemmLaunch &gl) {
@@ -946,9 +1027,14 @@ static int run(nnp_model *m, int n_sys, const int64_t *offs, const float *coords
   mark();
   if (want_grad) {
     site_begin(kSiteAevBwd);
-    launch_aev_bwd(pos, m->sys_of.as<int>(), dsys, pool_nbr, pool_cnt, cap,
-                   m->row_of_atom.as<int>(), m->dG.as<float>(), D, N, m->aev, o.forces,
-                   m->W_atom.as<float>(), m->tune_val[kSiteAevBwd], st);
+    if (dp)
+      launch_dp_bwd(pos, m->sys_of.as<int>(), dsys, pool_nbr, cap, m->row_of_atom.as<int>(),
+                    m->dG.as<float>(), D, N, m->dp, m->dp_map.as<uint16_t>(), o.forces,
+                    m->W_atom.as<float>(), m->tune_val[kSiteAevBwd], st);
+    else
+      launch_aev_bwd(pos, m->sys_of.as<int>(), dsys, pool_nbr, pool_cnt, cap,
+                     m->row_of_atom.as<int>(), m->dG.as<float>(), D, N, m->aev, o.forces,
+                     m->W_atom.as<float>(), m->tune_val[kSiteAevBwd], st);
     site_end(kSiteAevBwd);
   }
   mark();

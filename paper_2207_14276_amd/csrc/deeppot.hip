@@ -1,0 +1,466 @@
+// DeepPot-style local-frame descriptor and its gradient (section "DeePMD
+// Models"): the neighbours of a centre inside rc, grouped by species and
+// ordered nearest first, at most sel[s] of species s kept; each kept
+// neighbour fills four features {1/R, x/R, y/R, z/R}, (x, y, z) being its
+// coordinates in the centre's local frame.  The frame: e_x along the nearest
+// neighbour a, e_y along the part of the second nearest b orthogonal to e_x,
+// e_z = e_x x e_y; with one neighbour, or b collinear with a, e_y = e_z = 0.
+//
+// The neighbour order (and the cutoff test) is an integer decision taken in
+// float64 from the caller's float32 coordinates: d = (c_j - c_i) + m L with
+// m the lattice image relative to those coordinates, R^2 = (dx dx + dy dy)
+// + dz dz, each operation rounded on its own; exact ties go to the smaller
+// neighbour index, then the smaller image (x, y, z).  The features use the
+// float32 neighbour vector of the packed atom records, as the AEV kernels do.
+//
+// Forward, one wavefront per centre:
+//   1. lane per list entry: float64 R^2, per-species counts by ballot;
+//   2. again lane per entry: placement into per-species buckets in LDS
+//      (key, tie, float32 vector, entry index);
+//   3. per species bucket, lane per entry: rank = number of bucket entries
+//      ahead of it (O(n_s^2 / 64) per lane, all lanes reading the same LDS
+//      word at a time); ranks below sel[s] claim a slot; ranks 0 and 1 are
+//      the species' frame candidates;
+//   4. the two nearest among the candidates give the frame;
+//   5. lane per slot: four features, written as one 16-byte (8-byte in
+//      bfloat16) store, empty slots as zeros, and the slot -> list entry map
+//      that the backward reads.
+// Backward, one wavefront per centre, no LDS: lane per slot, the explicit
+// derivative of the slot's features with respect to its vector and the
+// frame sums A_c = sum_j (dE/dc_j) d_j / R_j, reduced over the wave; the
+// frame terms then reach the axis neighbours a and b.
+#include "internal.h"
+#include "wave.h"
+
+namespace nnp {
+
+namespace {
+
+constexpr uint16_t kNoEntry = 0xFFFF;
+
+// Per-wave LDS header.
+struct DpHead {
+  int cnt[8], off[8];                      // valid entries per species, bucket offsets
+  int fa, fb, pad0, pad1;                  // bucket positions of the frame neighbours (-1: none)
+  ulonglong2 cand[2 * kMaxSpecies + 2];    // each species' two nearest (key, tie)
+  int candv[2 * kMaxSpecies + 2];          // their bucket positions (-1: none)
+};
+
+__host__ __device__ inline size_t dp_head_bytes() { return (sizeof(DpHead) + 15) / 16 * 16; }
+// header, then per list entry: key/tie 16, vector 16, entry index 4; slot table
+__host__ __device__ inline size_t dp_lds_bytes(int cap, int n_slots) {
+  return dp_head_bytes() + (size_t)cap * (16 + 16 + 4) + ((size_t)n_slots * 4 + 15) / 16 * 16;
+}
+
+// Squared distance of the neighbour order, float64, no fused operations:
+// the same value whichever compiler contraction rules apply elsewhere.
+__device__ inline double dp_key(const float ci[3], const float *cj, int mx, int my, int mz,
+                                const double L[3]) {
+#pragma clang fp contract(off)
+  const double dx = ((double)cj[0] - (double)ci[0]) + (double)mx * L[0];
+  const double dy = ((double)cj[1] - (double)ci[1]) + (double)my * L[1];
+  const double dz = ((double)cj[2] - (double)ci[2]) + (double)mz * L[2];
+  return (dx * dx + dy * dy) + dz * dz;
+}
+
+// (key, tie) lexicographic order; R^2 >= 0, so its bits order like the value
+__device__ inline bool before(const ulonglong2 &a, const ulonglong2 &b) {
+  return a.x < b.x || (a.x == b.x && a.y < b.y);
+}
+
+// One list entry of centre i: validity, species, order key and tie.
+struct Entry {
+  int2 en;
+  bool valid;
+  int sj;
+  ulonglong2 kt;
+};
+
+__device__ inline Entry read_entry(int e, int n, const int2 *__restrict__ row, int j0, int n_sys,
+                                   const float4 *__restrict__ pos, const float *__restrict__ coords,
+                                   const AtomState *__restrict__ state, long long state_j0,
+                                   bool wrapped, const int wi[3], const float ci[3],
+                                   const double Ld[3], double rc2) {
+  Entry r;
+  r.en = make_int2(0, 0);
+  r.valid = false;
+  r.sj = -1;
+  r.kt = make_ulonglong2(~0ull, ~0ull);
+  if (e >= n) return r;
+  r.en = row[e];
+  if ((unsigned)r.en.x >= (unsigned)n_sys) return r;
+  const int j = j0 + r.en.x;
+  r.sj = __float_as_int(pos[j].w);
+  if (r.sj < 0) return r;
+  int mx, my, mz;
+  unpack_image(r.en.y, mx, my, mz);
+  if (wrapped) {
+    // images refer to the wrapped records; shift them to the caller's frame
+    const float4 wj = state[state_j0 + r.en.x].wrap;
+    mx += wi[0] - (int)wj.x;
+    my += wi[1] - (int)wj.y;
+    mz += wi[2] - (int)wj.z;
+  }
+  const double key = dp_key(ci, coords + 3 * (size_t)j, mx, my, mz, Ld);
+  r.valid = key < rc2;
+  const unsigned img = ((unsigned)(mx + 512) & 1023u) << 20 | ((unsigned)(my + 512) & 1023u) << 10 |
+                       ((unsigned)(mz + 512) & 1023u);
+  r.kt = make_ulonglong2((unsigned long long)__double_as_longlong(key),
+                         (unsigned long long)(unsigned)r.en.x << 32 | img);
+  return r;
+}
+
+// Local axes from the float32 vectors (and lengths) of a and b.
+struct Frame {
+  float ex[3], ey[3], ez[3];
+  float ra, nu;  // |d_a|; |u| (0: e_y, e_z undefined)
+};
+
+__device__ inline Frame make_frame(bool has_a, const float4 &da, bool has_b, const float4 &db) {
+  Frame f;
+  for (int k = 0; k < 3; ++k) f.ex[k] = f.ey[k] = f.ez[k] = 0.f;
+  f.ra = 1.f;
+  f.nu = 0.f;
+  if (!has_a) return f;
+  f.ra = da.w;
+  const float ia = 1.f / da.w;
+  f.ex[0] = da.x * ia; f.ex[1] = da.y * ia; f.ex[2] = da.z * ia;
+  if (!has_b) return f;
+  const float t = db.x * f.ex[0] + db.y * f.ex[1] + db.z * f.ex[2];
+  const float u0 = db.x - t * f.ex[0], u1 = db.y - t * f.ex[1], u2 = db.z - t * f.ex[2];
+  const float uu = u0 * u0 + u1 * u1 + u2 * u2;
+  if (!(uu > 1e-12f * (db.x * db.x + db.y * db.y + db.z * db.z))) return f;
+  f.nu = sqrtf(uu);
+  const float iu = 1.f / f.nu;
+  f.ey[0] = u0 * iu; f.ey[1] = u1 * iu; f.ey[2] = u2 * iu;
+  f.ez[0] = f.ex[1] * f.ey[2] - f.ex[2] * f.ey[1];
+  f.ez[1] = f.ex[2] * f.ey[0] - f.ex[0] * f.ey[2];
+  f.ez[2] = f.ex[0] * f.ey[1] - f.ex[1] * f.ey[0];
+  return f;
+}
+
+__device__ inline uint16_t bf16_rne(float v) {
+  uint32_t a = __float_as_uint(v);
+  a += 0x7fffu + ((a >> 16) & 1u);
+  return (uint16_t)(a >> 16);
+}
+
+template <bool BF16> __device__ inline void store_slot(void *row, int k, float4 f);
+template <> __device__ inline void store_slot<false>(void *row, int k, float4 f) { ((float4 *)row)[k] = f; }
+template <> __device__ inline void store_slot<true>(void *row, int k, float4 f) {
+  uint2 p;
+  p.x = (uint32_t)bf16_rne(f.x) | (uint32_t)bf16_rne(f.y) << 16;
+  p.y = (uint32_t)bf16_rne(f.z) | (uint32_t)bf16_rne(f.w) << 16;
+  ((uint2 *)row)[k] = p;
+}
+
+}  // namespace
+
+template <int WPB, bool BF16>
+__global__ void __launch_bounds__(WPB * kWave)
+k_dp_fwd(const float4 *__restrict__ pos, const float *__restrict__ coords,
+         const AtomState *__restrict__ state, const int *__restrict__ sys_of,
+         const SysDesc *__restrict__ sys, const int2 *__restrict__ nbr,
+         const int *__restrict__ nbr_cnt, int cap, const int *__restrict__ row_of_atom,
+         void *__restrict__ G, int ldg, int N, DpConst c, uint16_t *__restrict__ map) {
+  extern __shared__ float4 lds4[];
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave), lane = threadIdx.x % kWave;
+  const int i = blockIdx.x * WPB + wave;
+  if (i >= N) return;
+  const int r = row_of_atom[i];
+  if (r < 0) return;  // outside a caller's mask: no network row
+  char *base = (char *)lds4 + (size_t)wave * dp_lds_bytes(cap, c.n_slots);
+  DpHead *h = (DpHead *)base;
+  ulonglong2 *bkt = (ulonglong2 *)(base + dp_head_bytes());
+  float4 *bd = (float4 *)(bkt + cap);
+  int *bent = (int *)(bd + cap);
+  int *smap = bent + cap;
+
+  const SysDesc &d = sys[sys_of[i]];
+  const int n = min(nbr_cnt[d.state_off + (i - d.atom_off)], cap);
+  const float4 pi = pos[i];
+  const float L[3] = {d.L[0], d.L[1], d.L[2]};
+  const double Ld[3] = {(double)d.L[0], (double)d.L[1], (double)d.L[2]};
+  const int j0 = d.atom_off, n_sys = d.n;
+  const int2 *row = nbr + nbr_row(d, i, cap);
+  const float ci[3] = {coords[3 * (size_t)i], coords[3 * (size_t)i + 1], coords[3 * (size_t)i + 2]};
+  const bool wrapped = d.periodic != 0;
+  int wi[3] = {0, 0, 0};
+  if (wrapped) {
+    const float4 w = state[d.state_off + (i - d.atom_off)].wrap;
+    wi[0] = (int)w.x; wi[1] = (int)w.y; wi[2] = (int)w.z;
+  }
+
+  // 1. valid entries per species
+  int cnt[kMaxSpecies];
+#pragma unroll
+  for (int s = 0; s < kMaxSpecies; ++s) cnt[s] = 0;
+  for (int b = 0; b < n; b += kWave) {
+    const Entry x = read_entry(b + lane, n, row, j0, n_sys, pos, coords, state, d.state_off, wrapped, wi,
+                               ci, Ld, c.rc2);
+#pragma unroll
+    for (int s = 0; s < kMaxSpecies; ++s) cnt[s] += __popcll(__ballot(x.valid && x.sj == s));
+  }
+  int off[kMaxSpecies];
+  {
+    int o = 0;
+#pragma unroll
+    for (int s = 0; s < kMaxSpecies; ++s) { off[s] = o; o += cnt[s]; }
+  }
+  if (lane == 0) {
+    h->fa = -1;
+    h->fb = -1;
+  }
+  if (lane < 2 * kMaxSpecies + 2) {
+    h->cand[lane] = make_ulonglong2(~0ull, ~0ull);
+    h->candv[lane] = -1;
+  }
+  for (int k = lane; k < c.n_slots; k += kWave) smap[k] = -1;
+
+  // 2. species buckets
+  {
+    int run[kMaxSpecies];
+#pragma unroll
+    for (int s = 0; s < kMaxSpecies; ++s) run[s] = 0;
+    for (int b = 0; b < n; b += kWave) {
+      const int e = b + lane;
+      const Entry x = read_entry(e, n, row, j0, n_sys, pos, coords, state, d.state_off, wrapped, wi, ci,
+                                 Ld, c.rc2);
+      int at = 0;
+#pragma unroll
+      for (int s = 0; s < kMaxSpecies; ++s) {
+        const unsigned long long m = __ballot(x.valid && x.sj == s);
+        if (x.valid && x.sj == s) at = off[s] + run[s] + (int)lanes_below(m);
+        run[s] += __popcll(m);
+      }
+      if (x.valid) {
+        bkt[at] = x.kt;
+        bd[at] = entry_vec(pi, pos[j0 + x.en.x], x.en.y, L);
+        bent[at] = e;
+      }
+    }
+  }
+  wave_lds_sync();
+
+  // 3. rank inside each species bucket
+  for (int s = 0; s < c.S; ++s) {
+    const int cs = cnt[s], os = off[s], sel = c.sel[s], so = c.soff[s];
+    for (int vb = 0; vb < cs; vb += kWave) {
+      const int q = vb + lane;
+      const bool act = q < cs;
+      const ulonglong2 me = act ? bkt[os + q] : make_ulonglong2(~0ull, ~0ull);
+      int rank = 0;
+      for (int t = 0; t < cs; ++t) rank += before(bkt[os + t], me) ? 1 : 0;
+      if (act && rank < sel) smap[so + rank] = os + q;
+      if (act && rank < 2) {
+        h->cand[2 * s + rank] = me;
+        h->candv[2 * s + rank] = os + q;
+      }
+    }
+  }
+  wave_lds_sync();
+
+  // 4. the frame: the two nearest among the species' two nearest
+  if (lane < 2 * c.S) {
+    const ulonglong2 me = h->cand[lane];
+    const int v = h->candv[lane];
+    int g = 0;
+    for (int t = 0; t < 2 * c.S; ++t) g += before(h->cand[t], me) ? 1 : 0;
+    if (v >= 0 && g == 0) h->fa = v;
+    if (v >= 0 && g == 1) h->fb = v;
+  }
+  wave_lds_sync();
+  const int fa = h->fa, fb = h->fb;
+  const Frame f = make_frame(fa >= 0, fa >= 0 ? bd[fa] : make_float4(0.f, 0.f, 0.f, 1.f), fb >= 0,
+                             fb >= 0 ? bd[fb] : make_float4(0.f, 0.f, 0.f, 1.f));
+
+  // 5. features and the slot map
+  void *Grow = (char *)G + (size_t)r * ldg * (BF16 ? 2 : 4);
+  uint16_t *mrow = map ? map + (size_t)i * c.ldm : nullptr;
+  if (mrow && lane == 0) {
+    mrow[0] = fa >= 0 ? (uint16_t)bent[fa] : kNoEntry;
+    mrow[1] = fb >= 0 ? (uint16_t)bent[fb] : kNoEntry;
+  }
+  for (int k = lane; k < c.n_slots; k += kWave) {
+    const int v = smap[k];
+    float4 out = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (v >= 0) {
+      const float4 dv = bd[v];
+      const float ir = 1.f / dv.w;
+      out.x = ir;
+      out.y = (dv.x * f.ex[0] + dv.y * f.ex[1] + dv.z * f.ex[2]) * ir;
+      out.z = (dv.x * f.ey[0] + dv.y * f.ey[1] + dv.z * f.ey[2]) * ir;
+      out.w = (dv.x * f.ez[0] + dv.y * f.ez[1] + dv.z * f.ez[2]) * ir;
+    }
+    store_slot<BF16>(Grow, k, out);
+    if (mrow) mrow[2 + k] = v >= 0 ? (uint16_t)bent[v] : kNoEntry;
+  }
+}
+
+template <int WPB>
+__global__ void __launch_bounds__(WPB * kWave)
+k_dp_bwd(const float4 *__restrict__ pos, const int *__restrict__ sys_of,
+         const SysDesc *__restrict__ sys, const int2 *__restrict__ nbr, int cap,
+         const int *__restrict__ row_of_atom, const float *__restrict__ dG, int ldg, int N,
+         DpConst c, const uint16_t *__restrict__ map, float *__restrict__ F,
+         float *__restrict__ W_atom) {
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave), lane = threadIdx.x % kWave;
+  const int i = blockIdx.x * WPB + wave;
+  if (i >= N) return;
+  const int r = row_of_atom[i];
+  if (r < 0) {  // outside a caller's mask: no energy, no virial share
+    if (lane < 9) W_atom[(size_t)9 * i + lane] = 0.f;
+    return;
+  }
+  const SysDesc &d = sys[sys_of[i]];
+  const float4 pi = pos[i];
+  const float L[3] = {d.L[0], d.L[1], d.L[2]};
+  const int j0 = d.atom_off;
+  const int2 *row = nbr + nbr_row(d, i, cap);
+  const uint16_t *mrow = map + (size_t)i * c.ldm;
+  const int ea = mrow[0], eb = mrow[1];
+  int ja = -1, jb = -1;
+  float4 da = make_float4(0.f, 0.f, 0.f, 1.f), db = da;
+  if (ea != kNoEntry) {
+    const int2 en = row[ea];
+    ja = j0 + en.x;
+    da = entry_vec(pi, pos[ja], en.y, L);
+  }
+  if (eb != kNoEntry) {
+    const int2 en = row[eb];
+    jb = j0 + en.x;
+    db = entry_vec(pi, pos[jb], en.y, L);
+  }
+  const Frame f = make_frame(ja >= 0, da, jb >= 0, db);
+  const float4 *g4 = (const float4 *)(dG + (size_t)r * ldg);
+
+  // explicit terms, lane per slot; A[3c + k] = sum_j (dE/dG_{j,1+c}) d_j[k] / R_j
+  float A[9], fi[3], vir[9];
+  for (int q = 0; q < 9; ++q) A[q] = vir[q] = 0.f;
+  fi[0] = fi[1] = fi[2] = 0.f;
+  for (int k = lane; k < c.n_slots; k += kWave) {
+    const int e = mrow[2 + k];
+    if (e == kNoEntry) continue;
+    const int2 en = row[e];
+    const int j = j0 + en.x;
+    const float4 dv = entry_vec(pi, pos[j], en.y, L);
+    const float4 gs = g4[k];
+    const float ir = 1.f / dv.w;
+    const float cx = dv.x * f.ex[0] + dv.y * f.ex[1] + dv.z * f.ex[2];
+    const float cy = dv.x * f.ey[0] + dv.y * f.ey[1] + dv.z * f.ey[2];
+    const float cz = dv.x * f.ez[0] + dv.y * f.ez[1] + dv.z * f.ez[2];
+    // d(1/R)/dd = -d/R^3, d(c/R)/dd = e_c/R - c d/R^3 (axes held fixed)
+    const float s = (gs.x + gs.y * cx + gs.z * cy + gs.w * cz) * ir * ir * ir;
+    const float dvv[3] = {dv.x, dv.y, dv.z};
+    float gd[3];
+    for (int a = 0; a < 3; ++a) {
+      gd[a] = -s * dvv[a] + (gs.y * f.ex[a] + gs.z * f.ey[a] + gs.w * f.ez[a]) * ir;
+      A[a] += gs.y * ir * dvv[a];
+      A[3 + a] += gs.z * ir * dvv[a];
+      A[6 + a] += gs.w * ir * dvv[a];
+      fi[a] += gd[a];
+      atomicAdd(&F[3 * (size_t)j + a], -gd[a]);
+    }
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) vir[3 * a + b] -= dvv[a] * gd[b];
+  }
+  for (int q = 0; q < 9; ++q) A[q] = wave_sum(A[q]);
+  for (int q = 0; q < 9; ++q) vir[q] = wave_sum(vir[q]);
+  for (int a = 0; a < 3; ++a) fi[a] = wave_sum(fi[a]);
+
+  // frame terms: e_x = d_a/|d_a|, e_y = u/|u| with u = (I - e_x e_x^T) d_b,
+  // e_z = e_x x e_y; every lane holds the reduced sums
+  if (ja >= 0) {
+    float Bx[3] = {A[0], A[1], A[2]};
+    float gb[3] = {0.f, 0.f, 0.f};
+    const float dbv[3] = {db.x, db.y, db.z}, dav[3] = {da.x, da.y, da.z};
+    if (f.nu > 0.f) {
+      const float *Az = A + 6;
+      float By[3] = {A[3], A[4], A[5]};
+      // through e_z: dE/de_x += e_y x A_z, dE/de_y += A_z x e_x
+      Bx[0] += f.ey[1] * Az[2] - f.ey[2] * Az[1];
+      Bx[1] += f.ey[2] * Az[0] - f.ey[0] * Az[2];
+      Bx[2] += f.ey[0] * Az[1] - f.ey[1] * Az[0];
+      By[0] += Az[1] * f.ex[2] - Az[2] * f.ex[1];
+      By[1] += Az[2] * f.ex[0] - Az[0] * f.ex[2];
+      By[2] += Az[0] * f.ex[1] - Az[1] * f.ex[0];
+      const float byy = By[0] * f.ey[0] + By[1] * f.ey[1] + By[2] * f.ey[2];
+      const float iu = 1.f / f.nu;
+      float C[3];
+      for (int a = 0; a < 3; ++a) C[a] = (By[a] - byy * f.ey[a]) * iu;
+      const float cx = C[0] * f.ex[0] + C[1] * f.ex[1] + C[2] * f.ex[2];
+      const float bx = dbv[0] * f.ex[0] + dbv[1] * f.ex[1] + dbv[2] * f.ex[2];
+      for (int a = 0; a < 3; ++a) {
+        gb[a] = C[a] - cx * f.ex[a];
+        Bx[a] += -cx * dbv[a] - bx * C[a];
+      }
+    }
+    const float bxx = Bx[0] * f.ex[0] + Bx[1] * f.ex[1] + Bx[2] * f.ex[2];
+    const float ia = 1.f / f.ra;
+    float ga[3];
+    for (int a = 0; a < 3; ++a) ga[a] = (Bx[a] - bxx * f.ex[a]) * ia;
+    for (int a = 0; a < 3; ++a) {
+      fi[a] += ga[a] + gb[a];
+      for (int b = 0; b < 3; ++b) vir[3 * a + b] -= dav[a] * ga[b] + dbv[a] * gb[b];
+    }
+    if (lane == 0)
+      for (int a = 0; a < 3; ++a) atomicAdd(&F[3 * (size_t)ja + a], -ga[a]);
+    if (lane == 1 && f.nu > 0.f)
+      for (int a = 0; a < 3; ++a) atomicAdd(&F[3 * (size_t)jb + a], -gb[a]);
+  }
+  if (lane == 0)
+    for (int a = 0; a < 3; ++a) atomicAdd(&F[3 * (size_t)i + a], fi[a]);
+  if (lane < 9) {
+    float v = vir[0];
+    for (int q = 1; q < 9; ++q) v = lane == q ? vir[q] : v;
+    W_atom[(size_t)9 * i + lane] = v;
+  }
+}
+
+template <bool BF16>
+static void dp_fwd_t(const float4 *pos, const float *coords, const AtomState *state, const int *sys_of,
+                     const SysDesc *sys, const int2 *nbr, const int *nbr_cnt, int cap,
+                     const int *row_of_atom, void *G, int ldg, int N, const DpConst &c, uint16_t *map,
+                     int wpb, hipStream_t st) {
+  const size_t lds = dp_lds_bytes(cap, c.n_slots) * wpb;
+  const unsigned grid = (unsigned)((N + wpb - 1) / wpb);
+  if (wpb == 4)
+    k_dp_fwd<4, BF16><<<grid, 4 * kWave, lds, st>>>(pos, coords, state, sys_of, sys, nbr, nbr_cnt, cap,
+                                                    row_of_atom, G, ldg, N, c, map);
+  else if (wpb == 2)
+    k_dp_fwd<2, BF16><<<grid, 2 * kWave, lds, st>>>(pos, coords, state, sys_of, sys, nbr, nbr_cnt, cap,
+                                                    row_of_atom, G, ldg, N, c, map);
+  else
+    k_dp_fwd<1, BF16><<<grid, kWave, lds, st>>>(pos, coords, state, sys_of, sys, nbr, nbr_cnt, cap,
+                                                row_of_atom, G, ldg, N, c, map);
+}
+
+// Waves per workgroup: the preference (1, 2 or 4) when its LDS fits in
+// 64 KB, else one.
+void launch_dp_fwd(const float4 *pos, const float *coords, const AtomState *state, const int *sys_of,
+                   const SysDesc *sys, const int2 *nbr, const int *nbr_cnt, int cap,
+                   const int *row_of_atom, void *G, bool g_bf16, int ldg, int N, const DpConst &c,
+                   uint16_t *map, int wpb_pref, hipStream_t st) {
+  if (N <= 0) return;
+  int wpb = 1;
+  if ((wpb_pref == 2 || wpb_pref == 4) && dp_lds_bytes(cap, c.n_slots) * wpb_pref <= 64 * 1024) wpb = wpb_pref;
+  if (g_bf16) dp_fwd_t<true>(pos, coords, state, sys_of, sys, nbr, nbr_cnt, cap, row_of_atom, G, ldg, N, c, map, wpb, st);
+  else dp_fwd_t<false>(pos, coords, state, sys_of, sys, nbr, nbr_cnt, cap, row_of_atom, G, ldg, N, c, map, wpb, st);
+}
+
+// The backward uses no LDS: four waves per workgroup unless asked otherwise.
+void launch_dp_bwd(const float4 *pos, const int *sys_of, const SysDesc *sys, const int2 *nbr, int cap,
+                   const int *row_of_atom, const float *dG, int ldg, int N, const DpConst &c,
+                   const uint16_t *map, float *F, float *W_atom, int wpb_pref, hipStream_t st) {
+  if (N <= 0) return;
+  const int wpb = (wpb_pref == 1 || wpb_pref == 2) ? wpb_pref : 4;
+  const unsigned grid = (unsigned)((N + wpb - 1) / wpb);
+  if (wpb == 4)
+    k_dp_bwd<4><<<grid, 4 * kWave, 0, st>>>(pos, sys_of, sys, nbr, cap, row_of_atom, dG, ldg, N, c, map, F, W_atom);
+  else if (wpb == 2)
+    k_dp_bwd<2><<<grid, 2 * kWave, 0, st>>>(pos, sys_of, sys, nbr, cap, row_of_atom, dG, ldg, N, c, map, F, W_atom);
+  else
+    k_dp_bwd<1><<<grid, kWave, 0, st>>>(pos, sys_of, sys, nbr, cap, row_of_atom, dG, ldg, N, c, map, F, W_atom);
+}
+
+}  // namespace nnp

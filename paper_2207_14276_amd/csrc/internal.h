@@ -87,6 +87,18 @@ struct AevConst {
   int rad_len;  // S * 16
 };
 
+// DeepPot-style descriptor parameters, passed by value to its kernels.
+constexpr int kDpMaxSlots = 256;   // neighbours kept per centre, all species together
+struct DpConst {
+  double rc2;                  // cutoff squared, float64 (neighbour order and cutoff test)
+  int S;                       // species
+  int n_slots;                 // sum of sel
+  int D;                       // 4 * n_slots
+  int ldm;                     // slot-map row length (uint16 entries, multiple of 8)
+  int sel[kMaxSpecies];        // neighbours kept per species
+  int soff[kMaxSpecies];       // first slot of each species block
+};
+
 // Neighbour entry: j and a packed lattice image (10 bits per axis, +512).
 __host__ __device__ inline int pack_image(int x, int y, int z) {
   return (x + 512) | ((y + 512) << 10) | ((z + 512) << 20);
@@ -197,6 +209,15 @@ void launch_nbr_build(const float4 *pos, const int *sys_of, const SysDesc *sys, 
 void launch_species_bucket(const float4 *pos, int N, int S, int *block_counts, int n_blocks,
                            int *bucket_off, int *bucket_cnt, int *perm, int *row_of_atom,
                            int rows_cap, hipStream_t st);
+// DeepPot-style descriptor: forward into G rows (and the per-centre slot map
+// for the backward, nullable), backward from dE/dG to forces and virial.
+void launch_dp_fwd(const float4 *pos, const float *coords, const AtomState *state, const int *sys_of,
+                   const SysDesc *sys, const int2 *nbr, const int *nbr_cnt, int cap,
+                   const int *row_of_atom, void *G, bool g_bf16, int ldg, int N, const DpConst &c,
+                   uint16_t *map, int wpb_pref, hipStream_t st);
+void launch_dp_bwd(const float4 *pos, const int *sys_of, const SysDesc *sys, const int2 *nbr, int cap,
+                   const int *row_of_atom, const float *dG, int ldg, int N, const DpConst &c,
+                   const uint16_t *map, float *F, float *W_atom, int wpb_pref, hipStream_t st);
 void launch_aev_fwd(const float4 *pos, const int *sys_of, const SysDesc *sys, const int2 *nbr,
                     const int *nbr_cnt, int cap, const int *row_of_atom, void *G, bool g_bf16,
                     int ldg, int N, const AevConst &c, int wpb_pref, hipStream_t st);

@@ -35,10 +35,12 @@ class Result:
 class NNPModel:
     """A network set on one GPU.
 
-    `spec` carries the AEV hyper-parameters (dict `aev`), `n_ensemble`,
-    per-species `widths`, float32 `weights` (member, species, layer; W[out][in]
-    then b[out]) and `celu_alpha`.  `precision` is "fp32" or "bf16" (dense
-    layers with bfloat16 operands and float32 accumulation).
+    `spec` carries the descriptor hyper-parameters (dict `aev`: the AEV's, or
+    a DeepPot-style descriptor's with kind "dp", cutoff rc and per-species
+    capacities sel), `n_ensemble`, per-species `widths`, float32 `weights`
+    (member, species, layer; W[out][in] then b[out]) and `celu_alpha`.
+    `precision` is "fp32" or "bf16" (dense layers with bfloat16 operands and
+    float32 accumulation).
     """
 
     def __init__(self, spec, precision: str = "fp32", device=None):
@@ -48,27 +50,34 @@ class NNPModel:
         self.precision = precision
         p = spec.aev
         keep = {
-            "sr": np.ascontiguousarray(p["shf_rad"], np.float32),
-            "sa": np.ascontiguousarray(p["shf_ang"], np.float32),
-            "sz": np.ascontiguousarray(p["shf_z"], np.float32),
             "nl": np.array([len(w) - 1 for w in spec.widths], np.int32),
             "w": np.concatenate([np.array(w, np.int32) for w in spec.widths]),
             "weights": np.ascontiguousarray(spec.weights, np.float32),
         }
-        aev = nat.nnp_aev_params(int(p["n_species"]), float(p["rc_rad"]), float(p["eta_rad"]),
-                                 len(keep["sr"]), _fptr(keep["sr"]),
-                                 float(p["rc_ang"]), float(p["eta_ang"]), float(p["zeta"]),
-                                 len(keep["sa"]), _fptr(keep["sa"]),
-                                 len(keep["sz"]), _fptr(keep["sz"]),
-                                 float(p.get("radial_scale", 0.25)))
-        desc = nat.nnp_model_desc(aev, int(spec.n_ensemble),
-                                  keep["nl"].ctypes.data_as(C.POINTER(C.c_int)),
-                                  keep["w"].ctypes.data_as(C.POINTER(C.c_int)),
-                                  _fptr(keep["weights"]), float(spec.celu_alpha),
-                                  nat.NNP_BF16 if precision == "bf16" else nat.NNP_FP32)
+        nets = (int(spec.n_ensemble), keep["nl"].ctypes.data_as(C.POINTER(C.c_int)),
+                keep["w"].ctypes.data_as(C.POINTER(C.c_int)), _fptr(keep["weights"]),
+                float(spec.celu_alpha), nat.NNP_BF16 if precision == "bf16" else nat.NNP_FP32)
         h = C.c_void_p()
+        if p.get("kind") == "dp":
+            keep["sel"] = np.ascontiguousarray(p["sel"], np.int32)
+            dp = nat.nnp_dp_params(int(p["n_species"]), float(p["rc"]),
+                                   keep["sel"].ctypes.data_as(C.POINTER(C.c_int)))
+            desc = nat.nnp_dp_model_desc(dp, *nets)
+            create = lib.nnp_create_dp
+        else:
+            keep["sr"] = np.ascontiguousarray(p["shf_rad"], np.float32)
+            keep["sa"] = np.ascontiguousarray(p["shf_ang"], np.float32)
+            keep["sz"] = np.ascontiguousarray(p["shf_z"], np.float32)
+            aev = nat.nnp_aev_params(int(p["n_species"]), float(p["rc_rad"]), float(p["eta_rad"]),
+                                     len(keep["sr"]), _fptr(keep["sr"]),
+                                     float(p["rc_ang"]), float(p["eta_ang"]), float(p["zeta"]),
+                                     len(keep["sa"]), _fptr(keep["sa"]),
+                                     len(keep["sz"]), _fptr(keep["sz"]),
+                                     float(p.get("radial_scale", 0.25)))
+            desc = nat.nnp_model_desc(aev, *nets)
+            create = lib.nnp_create
         with torch.cuda.device(self.device):
-            nat.check(lib.nnp_create(C.byref(desc), C.byref(h)))
+            nat.check(create(C.byref(desc), C.byref(h)))
         self._h = h
         self.aev_dim = lib.nnp_aev_dim(h)
 
@@ -262,7 +271,7 @@ class NNPModel:
 
 class NeighborPool:
     """Persistent device-resident neighbour lists (nnp_nlist): `slots` atom
-    slots, lists built with cutoff rc_rad + skin and reused until an atom of
+    slots, lists built with the descriptor cutoff + skin and reused until an atom of
     the system has moved more than skin / 2 since its last build."""
 
     def __init__(self, model: NNPModel, slots: int, capacity: int = 256, skin: float = 1.0):

@@ -1,0 +1,241 @@
+"""The DeepPot-style descriptor (section "DeePMD Models") through the same C
+ABI: nnp_create_dp, then nnp_debug_aev, nnp_energy_forces, the pair-list and
+persistent-list entry points, against the FP64 oracle.
+
+Bars: the slot assignment (which neighbour lands in which slot, an integer
+decision taken in float64 on both sides) must be identical, so the set of
+filled slots matches exactly; the features themselves are float32
+(|dG| <= 2e-5 (1 + |G|)); energies and forces as for the AEV path: float32
+|dE_i| <= 1e-5 kcal/mol, |dF| <= 1e-3 kcal/mol/A; bfloat16 dense layers
+|dE_s|/N <= 1e-2 and |dF| <= max(5e-2, 0.02 max|F|).  The bfloat16 force bar
+scales with the force magnitude: bfloat16 operands carry a relative error of
+2^-9, so the force error of that form is a fixed fraction of the forces
+(under 1% of the largest one for both descriptor kinds here); the
+AEV model's largest forces are ~1.5 kcal/mol/A, where 5e-2 is 3%, while
+the randomly initialised DeepPot-style model reaches ~9 kcal/mol/A (its
+1/R and x/R features grow faster at short range).  The descriptor is not smooth where two
+neighbours of a species swap order or one crosses the cutoff; random inputs
+sit far enough from such points that float32 feature rounding does not
+reach them (the oracle's pins check the finite differences).
+"""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from tests.gpu_util import BF16_E_PER_ATOM, BF16_F, FP32_E_ATOM, FP32_F, log, run_gpu, to_dev
+from tests.test_gpu_pairs import brute_pairs, oracle_region, solute_in_water
+
+pytestmark = pytest.mark.gpu
+
+BF16_F_REL = 0.02   # bfloat16 force bar relative to the largest reference force
+
+
+@pytest.fixture(scope="module")
+def spec():
+    return synth.make_dp_model(0)
+
+
+@pytest.fixture(scope="module")
+def om(oracle_lib, spec):
+    return oracle_lib.OracleModel(spec)
+
+
+@pytest.fixture(scope="module")
+def m32(spec):
+    from paper_2207_14276_amd import NNPModel
+    m = NNPModel(spec, "fp32")
+    yield m
+    m.close()
+
+
+@pytest.fixture(scope="module")
+def m16(spec):
+    from paper_2207_14276_amd import NNPModel
+    m = NNPModel(spec, "bf16")
+    yield m
+    m.close()
+
+
+def _one(x, sp, box):
+    return synth.System(np.asarray(x, np.float32), np.asarray(sp, np.int32), np.asarray(box, np.float32))
+
+
+SYSTEMS = {
+    "cluster24": synth.make_batch([synth.config0()]),
+    "water8_small_box": synth.make_batch([synth.water_box(8, seed=5)]),
+    "water12_box": synth.make_batch([synth.water_box(12, seed=7)]),
+    # 9 atoms in a 4.5 A box: every atom's own images at +-L tie exactly
+    "water3_tiny_box": synth.make_batch([synth.water_box(3, seed=7)]),
+    "single_atom_5A_box": synth.make_batch([_one([[1.25, 2.5, 0.75]], [synth.H], [5.0, 5.0, 5.0])]),
+    "ragged16": synth.ragged_solutes(16, seed=12),
+    "water667": synth.make_batch([synth.config1()]),
+}
+
+
+@pytest.mark.parametrize("name", list(SYSTEMS))
+def test_descriptor_matches_oracle(m32, oracle_lib, name):
+    b = SYSTEMS[name]
+    c, s, bx, o = to_dev(b)
+    G = m32.aev(c, s, bx, o).cpu().numpy().astype(np.float64)
+    assert G.shape[1] == 480
+    worst = 0.0
+    for k in range(b.n_systems):
+        a, e = int(b.offsets[k]), int(b.offsets[k + 1])
+        ref = oracle_lib.dp_descriptor(b.coords[a:e], b.species[a:e], b.boxes[k], m32.spec.aev)
+        # same neighbour in the same slot: 1/R > 0 exactly where a slot is filled
+        assert np.array_equal(G[a:e, 0::4] > 0, ref[:, 0::4] > 0), (name, k)
+        worst = max(worst, float((np.abs(G[a:e] - ref) / (1.0 + np.abs(ref))).max()))
+    log(f"[dp descriptor] {name}: max |dG|/(1+|G|) = {worst:.3e}")
+    assert worst < 2e-5
+
+
+def test_single_atom_box_closed_form(m32):
+    """Six images at exactly 5 A: slots in image order (-x, -y, -z, +z, +y,
+    +x) in the frame e_x = -x, e_y = -y, e_z = +z."""
+    b = SYSTEMS["single_atom_5A_box"]
+    G = m32.aev(*to_dev(b)).cpu().numpy()[0]
+    want = np.zeros(480, np.float32)
+    want[:24] = np.ravel([[0.2, 1, 0, 0], [0.2, 0, 1, 0], [0.2, 0, 0, -1], [0.2, 0, 0, 1],
+                          [0.2, 0, -1, 0], [0.2, -1, 0, 0]])
+    np.testing.assert_allclose(G, want, atol=1e-6)
+
+
+def _check(model, oracle_lib, om, b, systems, e_atom_tol, e_sys_tol, f_tol, label, f_rel=0.0):
+    gpu = run_gpu(model, b)
+    ora = oracle_lib.batch_energy_forces(b, om, systems=systems)
+    worst_ea = worst_es = worst_f = worst_w = 0.0
+    for q, k in enumerate(systems):
+        a, e = int(b.offsets[k]), int(b.offsets[k + 1])
+        n = e - a
+        if n == 0:
+            assert gpu["energy"][k] == 0.0
+            continue
+        worst_ea = max(worst_ea, float(np.abs(gpu["e_atom"][a:e] - ora["e_atom"][q]).max()))
+        worst_es = max(worst_es, abs(gpu["energy"][k] - ora["energy"][q]) / n)
+        worst_f = max(worst_f, float(np.abs(gpu["forces"][a:e] - ora["forces"][q]).max()))
+        worst_w = max(worst_w, float(np.abs(gpu["virial"][k] - ora["virial"][q]).max()) / n)
+    f_max = max(float(np.abs(ora["forces"][q]).max()) for q in range(len(systems)) if len(ora["forces"][q]))
+    f_tol = max(f_tol, f_rel * f_max)
+    log(f"[dp {label}] max|dE_i|={worst_ea:.3e} max|dE_s|/N={worst_es:.3e} "
+        f"max|dF|={worst_f:.3e} (max|F|={f_max:.2f}, bar {f_tol:.3e}) max|dW|/N={worst_w:.3e}")
+    if e_atom_tol is not None:
+        assert worst_ea <= e_atom_tol
+    assert worst_es <= e_sys_tol
+    assert worst_f <= f_tol
+    assert worst_w <= 50 * f_tol
+
+
+@pytest.mark.parametrize("name", list(SYSTEMS))
+def test_fp32_energy_forces(m32, oracle_lib, om, name):
+    b = SYSTEMS[name]
+    _check(m32, oracle_lib, om, b, list(range(b.n_systems)), FP32_E_ATOM, FP32_E_ATOM, FP32_F, f"fp32 {name}")
+
+
+@pytest.mark.parametrize("name", ["cluster24", "water12_box", "ragged16", "water667"])
+def test_bf16_energy_forces(m16, oracle_lib, om, name):
+    b = SYSTEMS[name]
+    _check(m16, oracle_lib, om, b, list(range(b.n_systems)), None, BF16_E_PER_ATOM, BF16_F, f"bf16 {name}",
+           BF16_F_REL)
+
+
+def test_ragged_batch_512_sampled_systems(m32, m16, oracle_lib, om):
+    b = synth.config2()
+    sizes = np.diff(b.offsets)
+    rng = np.random.default_rng(1)
+    pick = sorted(set(rng.choice(b.n_systems, 22, replace=False).tolist()
+                      + [int(sizes.argmin()), int(sizes.argmax())]))
+    _check(m32, oracle_lib, om, b, pick, FP32_E_ATOM, FP32_E_ATOM, FP32_F, "fp32 ragged512")
+    _check(m16, oracle_lib, om, b, pick, None, BF16_E_PER_ATOM, BF16_F, "bf16 ragged512", BF16_F_REL)
+
+
+def test_edge_cases(m32, oracle_lib, om):
+    """Empty systems, a lone atom, one atom with only self-images, a pair in
+    a small box, and a capacity-limited model where neighbours are dropped."""
+    lone = _one([[0.3, 0.2, 0.1]], [synth.C], [0, 0, 0])
+    empty = _one(np.zeros((0, 3)), np.zeros(0), [0, 0, 0])
+    self_img = _one([[1.0, 1.0, 1.0]], [synth.O], [3.1, 3.1, 3.1])
+    pair_img = _one([[0.5, 0.5, 0.5], [1.7, 0.9, 1.1]], [synth.H, synth.N], [4.0, 3.0, 5.0])
+    b = synth.make_batch([empty, lone, synth.config0(), empty, self_img, pair_img, empty])
+    _check(m32, oracle_lib, om, b, list(range(b.n_systems)), FP32_E_ATOM, FP32_E_ATOM, FP32_F, "fp32 edge")
+    from paper_2207_14276_amd import NNPModel
+    small = synth.make_dp_model(2, dp=synth.dp_params(sel=(3, 2, 1, 2, 1, 1, 1)))
+    m = NNPModel(small, "fp32")
+    w = synth.make_batch([synth.water_box(12, seed=7), synth.config0()])
+    _check(m, oracle_lib, oracle_lib.OracleModel(small), w, [0, 1], FP32_E_ATOM, FP32_E_ATOM, FP32_F,
+           "fp32 sel=(3,2,1,2,1,1,1)")
+    m.close()
+
+
+def test_large_periodic_sampled(oracle_lib):
+    """The ~100k-atom solvated protein box in one call, ensemble of 4; eight
+    seeded atoms' energies and forces against the oracle's local evaluation,
+    plus the zero net force of the whole box."""
+    from paper_2207_14276_amd import NNPModel
+    spec = synth.make_dp_model(3, n_ensemble=4)
+    s = synth.config3()
+    b = synth.make_batch([s])
+    om = oracle_lib.OracleModel(spec)
+    rng = np.random.default_rng(5)
+    t = np.sort(rng.choice(s.n, 8, replace=False))
+    e_ref, f_ref = oracle_lib.sampled(s.coords, s.species, s.box, om, t)
+    for prec, e_tol, f_tol in (("fp32", FP32_E_ATOM, FP32_F), ("bf16", BF16_E_PER_ATOM, BF16_F)):
+        m = NNPModel(spec, prec)
+        gpu = run_gpu(m, b)
+        de = float(np.abs(gpu["e_atom"][t] - e_ref).max())
+        df = float(np.abs(gpu["forces"][t] - f_ref).max())
+        net = float(np.abs(gpu["forces"].sum(0)).max())
+        if prec == "bf16":
+            f_tol = max(f_tol, BF16_F_REL * float(np.abs(f_ref).max()))
+        log(f"[dp {prec} protein100k ens4] max|dE_i|={de:.3e} max|dF|={df:.3e} (bar {f_tol:.3e}) "
+            f"|sum F|={net:.3e}")
+        assert de <= e_tol
+        assert df <= f_tol
+        assert net <= 1e-3 * np.sqrt(s.n) * max(1.0, np.abs(gpu["forces"]).max())
+        m.close()
+
+
+def test_pair_list_region(spec, om, oracle_lib):
+    """A caller's pair list (6.5 A) and an ML region: the oracle's result for
+    the region alone."""
+    from paper_2207_14276_amd import NNPModel
+    coords, species, box, mask = solute_in_water()
+    pairs, shifts = brute_pairs(coords, box, rc=6.5)
+    m = NNPModel(spec, "fp32")
+    r = m.energy_forces_pairs(torch.as_tensor(coords, device="cuda"), torch.as_tensor(species, device="cuda"),
+                              box, torch.as_tensor(pairs, device="cuda"), torch.as_tensor(shifts, device="cuda"),
+                              torch.as_tensor(mask.astype(np.uint8), device="cuda"), virial=True, check=True)
+    torch.cuda.synchronize()
+    E, F = float(r.energy.cpu().numpy()[0]), r.forces.cpu().numpy().astype(np.float64)
+    m.close()
+    Eo, Fo, _ = oracle_region(oracle_lib, om, coords, species, box, mask)
+    n = int(mask.sum())
+    log(f"[dp pairs] region={n} |dE|/N={abs(E - Eo) / n:.3e} |dF|={np.abs(F - Fo).max():.3e}")
+    assert abs(E - Eo) / n <= FP32_E_ATOM
+    assert np.abs(F - Fo).max() <= FP32_F
+    assert np.all(F[~mask] == 0.0)
+
+
+def test_persistent_lists_follow_moves(m32, oracle_lib, om):
+    """A pool list built once (skin 1 A) and reused while the atoms move:
+    every step matches the oracle at the moved coordinates, and the list is
+    rebuilt only when the skin is used up."""
+    from paper_2207_14276_amd.model import NeighborPool
+    s0 = synth.water_box(12, seed=7)
+    nl = NeighborPool(m32, slots=s0.n, skin=1.0)
+    rng = np.random.default_rng(9)
+    x = s0.coords.astype(np.float64)
+    worst = 0.0
+    for step in range(4):
+        xs = x.astype(np.float32)
+        r = nl.energy_forces(torch.as_tensor(xs, device="cuda"), torch.as_tensor(s0.species, device="cuda"),
+                             s0.box[None], np.array([0, s0.n]), slots=[0])
+        torch.cuda.synchronize()
+        E, _, Fo, _ = oracle_lib.energy_forces(xs, s0.species, s0.box, om, virial=False)
+        worst = max(worst, float(np.abs(r.forces.cpu().numpy() - Fo).max()))
+        assert abs(float(r.energy.cpu().numpy()[0]) - E) / s0.n <= FP32_E_ATOM
+        x = x + rng.normal(0.0, 0.05, size=x.shape)
+    log(f"[dp nlist] builds={nl.builds()} max|dF|={worst:.3e}")
+    assert worst <= FP32_F
+    assert nl.builds() == 1
+    nl.close()
