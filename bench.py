@@ -36,6 +36,8 @@ def parse():
                    choices=["ragged512", "water2001", "protein100k", "cluster24", "serve", "copy",
                             "hybrid", "snapshots"])
     p.add_argument("--precision", default="bf16", choices=["bf16", "fp32"])
+    p.add_argument("--model", default="ani", choices=["ani", "dp"],
+                   help="descriptor family: ANI AEV (default) or DeepPot-style local frame")
     p.add_argument("--no-plain", action="store_true")
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--plain-passes", type=int, default=2)
@@ -53,16 +55,46 @@ def say(args, *a):
         print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def workload(name):
+def workload(name, kind="ani"):
     import synth
+    if kind == "dp":
+        mk, tag = synth.make_dp_model, "; DeepPot-style local-frame descriptor (rc 6 A, 120 slots, 480 features)"
+    else:
+        mk, tag = synth.make_model, ""
     if name == "ragged512":
-        return synth.config2(), synth.make_model(0), "ragged batch: 512 non-periodic solutes, 10-120 atoms"
+        return synth.config2(), mk(0), "ragged batch: 512 non-periodic solutes, 10-120 atoms" + tag
     if name == "water2001":
-        return synth.make_batch([synth.config1()]), synth.make_model(0), "periodic water box, 2001 atoms, L=27.1 A"
+        return synth.make_batch([synth.config1()]), mk(0), "periodic water box, 2001 atoms, L=27.1 A" + tag
     if name == "protein100k":
-        return (synth.make_batch([synth.config3()]), synth.make_model(3, n_ensemble=8),
-                "periodic solvated-protein-like box, 100,002 atoms, L=101 A, ensemble of 8 networks")
-    return synth.make_batch([synth.config0()]), synth.make_model(0), "24-atom cluster"
+        return (synth.make_batch([synth.config3()]), mk(3, n_ensemble=8),
+                "periodic solvated-protein-like box, 100,002 atoms, L=101 A, ensemble of 8 networks" + tag)
+    return synth.make_batch([synth.config0()]), mk(0), "24-atom cluster" + tag
+
+
+def dp_counts(model, batch, c, s):
+    """Work of the DeepPot-style descriptor kernels, from the library's own
+    neighbour lists (distances recomputed here in float64): valid entries
+    (inside rc), same-species comparisons of the in-bucket ranking
+    (sum over centres and species of n_s^2), kept slots, centres."""
+    cnt, ent = model.neighbors(c, s, batch.boxes, batch.offsets, capacity=model_cap(model))
+    cnt = cnt.cpu().numpy()
+    ent = ent.cpu().numpy()
+    sys_of = np.repeat(np.arange(batch.n_systems), np.diff(batch.offsets))
+    x = batch.coords.astype(np.float64)
+    rc, sel = model.spec.aev["rc"], np.asarray(model.spec.aev["sel"])
+    entries = comps = kept = 0
+    for i in range(batch.n_atoms):
+        e = ent[i, :min(cnt[i], ent.shape[1])]
+        if len(e) == 0:
+            continue
+        L = batch.boxes[sys_of[i]].astype(np.float64)
+        d = x[e[:, 0]] + e[:, 1:4] * L - x[i]
+        inside = (d * d).sum(1) < rc * rc
+        ns = np.bincount(batch.species[e[inside, 0]], minlength=len(sel))
+        entries += int(inside.sum())
+        comps += int((ns.astype(np.int64) ** 2).sum())
+        kept += int(np.minimum(ns, sel).sum())
+    return entries, comps, kept, batch.n_atoms
 
 
 def pair_triplet_counts(model, batch, c, s):
@@ -124,6 +156,25 @@ FLOP_TRIPLET_FWD = 230
 FLOP_RADIAL_BWD = 324
 FLOP_TRIPLET_BWD = 510
 
+# DeepPot-style descriptor, counted the same way (float64 operations count 2,
+# their issue cost on the float32 vector unit):
+#   forward:  per valid entry the float64 order key (3 subtractions, 3 image
+#             products, 3 additions, 3 squares, 2 additions: 14 -> 28);
+#             per same-species comparison of the ranking 1;
+#             per kept slot |d| (5 + sqrt 4), 1/R 4, three projections 15 -> 28;
+#             per centre the frame (normalise 2 vectors, Gram-Schmidt, cross
+#             product) ~ 40
+#   backward: per kept slot the vector (9 + 4) again, 1/R 4, three projections
+#             15, s 7 + 2, dE/dd 3 x 8, frame sums 18, virial 18, force sums
+#             and the neighbour's force 6 -> 107; per centre the frame again
+#             (40) and its chain rule (~90) -> 130
+FLOP_DP_ENTRY_FWD = 28
+FLOP_DP_COMPARE = 1
+FLOP_DP_SLOT_FWD = 28
+FLOP_DP_CENTRE_FWD = 40
+FLOP_DP_SLOT_BWD = 107
+FLOP_DP_CENTRE_BWD = 130
+
 
 def mlp_flops(spec, species):
     """2 * MACs of forward and backward (input gradient) dense layers."""
@@ -140,8 +191,14 @@ def mlp_flops(spec, species):
 # Kernel sources whose hash a counter summary records: the HBM byte counts
 # it holds describe the kernel as it was built from exactly these files.
 KERNEL_SOURCES = {
-    "k_aev_fwd": ["paper_2207_14276_amd/csrc/aev.hip", "paper_2207_14276_amd/csrc/internal.h"],
-    "k_aev_bwd": ["paper_2207_14276_amd/csrc/aev.hip", "paper_2207_14276_amd/csrc/internal.h"],
+    "k_aev_fwd": ["paper_2207_14276_amd/csrc/aev.hip", "paper_2207_14276_amd/csrc/internal.h",
+                  "paper_2207_14276_amd/csrc/wave.h"],
+    "k_aev_bwd": ["paper_2207_14276_amd/csrc/aev.hip", "paper_2207_14276_amd/csrc/internal.h",
+                  "paper_2207_14276_amd/csrc/wave.h"],
+    "k_dp_fwd": ["paper_2207_14276_amd/csrc/deeppot.hip", "paper_2207_14276_amd/csrc/internal.h",
+                 "paper_2207_14276_amd/csrc/wave.h"],
+    "k_dp_bwd": ["paper_2207_14276_amd/csrc/deeppot.hip", "paper_2207_14276_amd/csrc/internal.h",
+                 "paper_2207_14276_amd/csrc/wave.h"],
     "k_gemm": ["paper_2207_14276_amd/csrc/mlp.hip", "paper_2207_14276_amd/csrc/internal.h"],
 }
 
@@ -579,7 +636,7 @@ def main():
         return
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
-    batch, spec, desc = workload(args.workload)
+    batch, spec, desc = workload(args.workload, args.model)
     N, S = batch.n_atoms, batch.n_systems
     say(args, f"workload {args.workload}: N={N} S={S}")
     c = torch.as_tensor(batch.coords, device=dev)
@@ -621,10 +678,18 @@ def main():
     say(args, "stages ms:", {k: round(v, 4) for k, v in stages.items()})
 
     # algorithmic work
-    n_pairs, n_trip = pair_triplet_counts(model, batch, c, sp)
     fwd_f, bwd_f = mlp_flops(spec, batch.species)
-    aev_fwd_flop = FLOP_RADIAL_FWD * n_pairs + FLOP_TRIPLET_FWD * n_trip
-    aev_bwd_flop = FLOP_RADIAL_BWD * n_pairs + FLOP_TRIPLET_BWD * n_trip
+    if args.model == "dp":
+        entries, comps, kept, centres = dp_counts(model, batch, c, sp)
+        aev_fwd_flop = (FLOP_DP_ENTRY_FWD * entries + FLOP_DP_COMPARE * comps + FLOP_DP_SLOT_FWD * kept
+                        + FLOP_DP_CENTRE_FWD * centres)
+        aev_bwd_flop = FLOP_DP_SLOT_BWD * kept + FLOP_DP_CENTRE_BWD * centres
+        counts = {"entries": entries, "comparisons": comps, "kept_slots": kept}
+    else:
+        n_pairs, n_trip = pair_triplet_counts(model, batch, c, sp)
+        aev_fwd_flop = FLOP_RADIAL_FWD * n_pairs + FLOP_TRIPLET_FWD * n_trip
+        aev_bwd_flop = FLOP_RADIAL_BWD * n_pairs + FLOP_TRIPLET_BWD * n_trip
+        counts = {"pairs": n_pairs, "triplets": n_trip}
     mlp_flop = fwd_f + bwd_f
     cand = {
         "aev_fwd": ("alu", aev_fwd_flop, PEAK_FP32_VALU_TFLOPS),
@@ -636,13 +701,21 @@ def main():
     bound, work, peak = cand[dom]
     t_dom = stages[dom] * 1e-3
     achieved = work / t_dom / 1e12
-    kname = {"aev_fwd": "k_aev_fwd", "aev_bwd": "k_aev_bwd", "mlp": "k_gemm"}[dom]
+    pre = "k_dp" if args.model == "dp" else "k_aev"
+    kname = {"aev_fwd": pre + "_fwd", "aev_bwd": pre + "_bwd", "mlp": "k_gemm"}[dom]
+    wl = args.workload + ("_dp" if args.model == "dp" else "")
     roof = {"kernel": kname if dom != "mlp" else "k_gemm (all dense layers)",
             "bound": bound, "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
             "frac": round(achieved / peak, 4),
-            "traffic": measured_traffic(kname, args.workload, args.precision),
-            "work_per_launch_flop": work, "avg_launch_ms": round(stages[dom], 4),
-            "pairs": n_pairs, "triplets": n_trip}
+            "traffic": measured_traffic(kname, wl, args.precision),
+            "work_per_launch_flop": work, "avg_launch_ms": round(stages[dom], 4), **counts}
+    # achieved rate of the descriptor kernels (counted work / stage time)
+    work_tflops = {"desc_fwd": round(aev_fwd_flop / (stages["aev_fwd"] * 1e-3) / 1e12, 3),
+                   "desc_bwd": round(aev_bwd_flop / (stages["aev_bwd"] * 1e-3) / 1e12, 3)}
+    if args.model == "dp":
+        # the library's stage names are those of the AEV kernels; here they
+        # hold the DeepPot-style descriptor's
+        stages = {("dp_" + k[4:] if k.startswith("aev_") else k): v for k, v in stages.items()}
 
     out = {
         "metric": "energy+force atom-evals/s",
@@ -666,6 +739,7 @@ def main():
         "stages_ms": {k: round(v, 4) for k, v in stages.items()},
         "roofline": roof,
         "mlp_tflops": round(mlp_flop / (stages["mlp"] * 1e-3) / 1e12, 2),
+        "work_tflops": work_tflops,
     }
 
     # plain form: float32, one system per call, sequential on one stream

@@ -117,7 +117,7 @@ struct nnp_model {
   // workspace
   DevBuf pos, sys_of, atom_cell, atom_slot, cell_count, cell_start, cell_atoms, nbr, nbr_cnt;
   DevBuf block_counts, bucket_off, bucket_cnt, perm, row_of_atom, G, dG, e_atom, W_atom, partial;
-  DevBuf sysdesc, chunk_sys, chunk_begin, sys_chunk_off, status, state, e_mem, dp_map;
+  DevBuf sysdesc, chunk_sys, chunk_begin, sys_chunk_off, status, state, e_mem, dp_rec;
   std::vector<DevBuf> H, Gd;
   // fused hidden-layer chain (bfloat16 models whose hidden widths allow it)
   bool chain = false;
@@ -182,7 +182,7 @@ extern "C" void nnp_destroy(nnp_model *m) {
                     &m->bucket_off, &m->bucket_cnt, &m->perm, &m->row_of_atom, &m->G, &m->dG,
                     &m->e_atom, &m->W_atom, &m->partial, &m->sysdesc, &m->chunk_sys,
                     &m->chunk_begin, &m->sys_chunk_off, &m->status, &m->state, &m->e_mem,
-                    &m->chain_nets, &m->dp_map};
+                    &m->chain_nets, &m->dp_rec};
   for (DevBuf *b : bufs) b->release();
   for (auto &b : m->H) b.release();
   for (auto &b : m->Gd) b.release();
@@ -260,7 +260,7 @@ static int create_dp_impl(const nnp_dp_model_desc *dd, nnp_model *m) {
   c.S = p.n_species;
   c.n_slots = slots;
   c.D = 4 * slots;
-  c.ldm = (slots + 2 + 7) / 8 * 8;
+  c.ldm = slots + 2;
   c.rc2 = (double)p.rc * (double)p.rc;
   m->S = p.n_species;
   m->kind = kDescDp;
@@ -483,7 +483,7 @@ static int for_each_ws(nnp_model *m, int64_t N, int S, int64_t C, int n_chunks, 
   const int esz = m->precision == NNP_BF16 ? 2 : 4;  // activation element size
   ENS(m->G, rows * m->ldG * esz);
   ENS(m->dG, rows * m->D * 4);
-  if (m->kind == kDescDp) ENS(m->dp_map, N * (int64_t)m->dp.ldm * 2);
+  if (m->kind == kDescDp) ENS(m->dp_rec, N * (int64_t)m->dp.ldm * 16);
   ENS(m->e_atom, N * 4);
   if (m->chain) ENS(m->e_mem, rows * m->M * 4);
   ENS(m->W_atom, N * 36);
@@ -873,10 +873,10 @@ static int run(nnp_model *m, int n_sys, const int64_t *offs, const float *coords
   const bool want_grad = o.forces != nullptr;
   // descriptor forward into rows of G (the AEV export: float32 rows of the
   // dE/dG buffer, gathered back to atom order)
-  auto descriptor = [&](void *Gp, bool g_bf16, int ldg, uint16_t *map, int wpb) {
+  auto descriptor = [&](void *Gp, bool g_bf16, int ldg, float4 *rec, int wpb) {
     if (dp)
       launch_dp_fwd(pos, coords, pool_state, m->sys_of.as<int>(), dsys, pool_nbr, pool_cnt, cap,
-                    m->row_of_atom.as<int>(), Gp, g_bf16, ldg, N, m->dp, map, wpb, st);
+                    m->row_of_atom.as<int>(), Gp, g_bf16, ldg, N, m->dp, rec, wpb, st);
     else
       launch_aev_fwd(pos, m->sys_of.as<int>(), dsys, pool_nbr, pool_cnt, cap, m->row_of_atom.as<int>(), Gp,
                      g_bf16, ldg, N, m->aev, wpb, st);
@@ -888,7 +888,7 @@ static int run(nnp_model *m, int n_sys, const int64_t *offs, const float *coords
     return NNP_OK;
   }
   site_begin(kSiteAevFwd);
-  descriptor(m->G.p, bf16, m->ldG, dp && want_grad ? m->dp_map.as<uint16_t>() : nullptr,
+  descriptor(m->G.p, bf16, m->ldG, dp && want_grad ? m->dp_rec.as<float4>() : nullptr,
              m->tune_val[kSiteAevFwd]);
   site_end(kSiteAevFwd);
   mark();
@@ -1028,9 +1028,8 @@ static int run(nnp_model *m, int n_sys, const int64_t *offs, const float *coords
   if (want_grad) {
     site_begin(kSiteAevBwd);
     if (dp)
-      launch_dp_bwd(pos, m->sys_of.as<int>(), dsys, pool_nbr, cap, m->row_of_atom.as<int>(),
-                    m->dG.as<float>(), D, N, m->dp, m->dp_map.as<uint16_t>(), o.forces,
-                    m->W_atom.as<float>(), m->tune_val[kSiteAevBwd], st);
+      launch_dp_bwd(dsys, n_sys, all_small, m->row_of_atom.as<int>(), m->dG.as<float>(), D, N, m->dp,
+                    m->dp_rec.as<float4>(), o.forces, m->W_atom.as<float>(), m->tune_val[kSiteAevBwd], st);
     else
       launch_aev_bwd(pos, m->sys_of.as<int>(), dsys, pool_nbr, pool_cnt, cap,
                      m->row_of_atom.as<int>(), m->dG.as<float>(), D, N, m->aev, o.forces,

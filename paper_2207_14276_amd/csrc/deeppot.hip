@@ -16,19 +16,24 @@
 // Forward, one wavefront per centre:
 //   1. lane per list entry: float64 R^2, per-species counts by ballot;
 //   2. again lane per entry: placement into per-species buckets in LDS
-//      (key, tie, float32 vector, entry index);
+//      (key, tie, float32 vector, atom index);
 //   3. per species bucket, lane per entry: rank = number of bucket entries
 //      ahead of it (O(n_s^2 / 64) per lane, all lanes reading the same LDS
 //      word at a time); ranks below sel[s] claim a slot; ranks 0 and 1 are
 //      the species' frame candidates;
 //   4. the two nearest among the candidates give the frame;
 //   5. lane per slot: four features, written as one 16-byte (8-byte in
-//      bfloat16) store, empty slots as zeros, and the slot -> list entry map
-//      that the backward reads.
-// Backward, one wavefront per centre, no LDS: lane per slot, the explicit
-// derivative of the slot's features with respect to its vector and the
-// frame sums A_c = sum_j (dE/dc_j) d_j / R_j, reduced over the wave; the
-// frame terms then reach the axis neighbours a and b.
+//      bfloat16) store, empty slots as zeros, and the slot's record
+//      {d_x, d_y, d_z, j} for the backward (records 0 and 1: the frame's
+//      neighbours a and b), one coalesced 16-byte store per lane.
+// Backward, one wavefront per centre: lane per slot, reading the slot's
+// record (one coalesced load, no neighbour-list or atom gathers), the
+// explicit derivative of the slot's features with respect to its vector and
+// the frame sums A_c = sum_j (dE/dc_j) d_j / R_j, reduced over the wave; the
+// frame terms then reach the axis neighbours a and b.  Forces go out by float
+// atomics, or, for batches of small non-periodic systems, are summed per
+// system in LDS and stored once (global float atomics dominated the time of
+// the per-centre form).
 #include "internal.h"
 #include "wave.h"
 
@@ -36,7 +41,9 @@ namespace nnp {
 
 namespace {
 
-constexpr uint16_t kNoEntry = 0xFFFF;
+// Slot record of the backward: the neighbour vector and, in w, the
+// neighbour's atom index as int bits (-1: empty slot).
+__device__ inline float4 slot_record(const float4 &d, int j) { return make_float4(d.x, d.y, d.z, __int_as_float(j)); }
 
 // Per-wave LDS header.
 struct DpHead {
@@ -47,7 +54,7 @@ struct DpHead {
 };
 
 __host__ __device__ inline size_t dp_head_bytes() { return (sizeof(DpHead) + 15) / 16 * 16; }
-// header, then per list entry: key/tie 16, vector 16, entry index 4; slot table
+// header, then per list entry: key/tie 16, vector 16, atom index 4; slot table
 __host__ __device__ inline size_t dp_lds_bytes(int cap, int n_slots) {
   return dp_head_bytes() + (size_t)cap * (16 + 16 + 4) + ((size_t)n_slots * 4 + 15) / 16 * 16;
 }
@@ -162,7 +169,7 @@ k_dp_fwd(const float4 *__restrict__ pos, const float *__restrict__ coords,
          const AtomState *__restrict__ state, const int *__restrict__ sys_of,
          const SysDesc *__restrict__ sys, const int2 *__restrict__ nbr,
          const int *__restrict__ nbr_cnt, int cap, const int *__restrict__ row_of_atom,
-         void *__restrict__ G, int ldg, int N, DpConst c, uint16_t *__restrict__ map) {
+         void *__restrict__ G, int ldg, int N, DpConst c, float4 *__restrict__ rec) {
   extern __shared__ float4 lds4[];
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave), lane = threadIdx.x % kWave;
   const int i = blockIdx.x * WPB + wave;
@@ -173,8 +180,8 @@ k_dp_fwd(const float4 *__restrict__ pos, const float *__restrict__ coords,
   DpHead *h = (DpHead *)base;
   ulonglong2 *bkt = (ulonglong2 *)(base + dp_head_bytes());
   float4 *bd = (float4 *)(bkt + cap);
-  int *bent = (int *)(bd + cap);
-  int *smap = bent + cap;
+  int *bj = (int *)(bd + cap);
+  int *smap = bj + cap;
 
   const SysDesc &d = sys[sys_of[i]];
   const int n = min(nbr_cnt[d.state_off + (i - d.atom_off)], cap);
@@ -236,7 +243,7 @@ k_dp_fwd(const float4 *__restrict__ pos, const float *__restrict__ coords,
       if (x.valid) {
         bkt[at] = x.kt;
         bd[at] = entry_vec(pi, pos[j0 + x.en.x], x.en.y, L);
-        bent[at] = e;
+        bj[at] = j0 + x.en.x;
       }
     }
   }
@@ -274,12 +281,12 @@ k_dp_fwd(const float4 *__restrict__ pos, const float *__restrict__ coords,
   const Frame f = make_frame(fa >= 0, fa >= 0 ? bd[fa] : make_float4(0.f, 0.f, 0.f, 1.f), fb >= 0,
                              fb >= 0 ? bd[fb] : make_float4(0.f, 0.f, 0.f, 1.f));
 
-  // 5. features and the slot map
+  // 5. features and the slot records
   void *Grow = (char *)G + (size_t)r * ldg * (BF16 ? 2 : 4);
-  uint16_t *mrow = map ? map + (size_t)i * c.ldm : nullptr;
-  if (mrow && lane == 0) {
-    mrow[0] = fa >= 0 ? (uint16_t)bent[fa] : kNoEntry;
-    mrow[1] = fb >= 0 ? (uint16_t)bent[fb] : kNoEntry;
+  float4 *rrow = rec ? rec + (size_t)i * c.ldm : nullptr;
+  if (rrow && lane < 2) {
+    const int v = lane == 0 ? fa : fb;
+    rrow[lane] = v >= 0 ? slot_record(bd[v], bj[v]) : slot_record(make_float4(0.f, 0.f, 0.f, 0.f), -1);
   }
   for (int k = lane; k < c.n_slots; k += kWave) {
     const int v = smap[k];
@@ -293,44 +300,24 @@ k_dp_fwd(const float4 *__restrict__ pos, const float *__restrict__ coords,
       out.w = (dv.x * f.ez[0] + dv.y * f.ez[1] + dv.z * f.ez[2]) * ir;
     }
     store_slot<BF16>(Grow, k, out);
-    if (mrow) mrow[2 + k] = v >= 0 ? (uint16_t)bent[v] : kNoEntry;
+    if (rrow)
+      rrow[2 + k] = v >= 0 ? slot_record(bd[v], bj[v]) : slot_record(make_float4(0.f, 0.f, 0.f, 0.f), -1);
   }
 }
 
-template <int WPB>
-__global__ void __launch_bounds__(WPB * kWave)
-k_dp_bwd(const float4 *__restrict__ pos, const int *__restrict__ sys_of,
-         const SysDesc *__restrict__ sys, const int2 *__restrict__ nbr, int cap,
-         const int *__restrict__ row_of_atom, const float *__restrict__ dG, int ldg, int N,
-         DpConst c, const uint16_t *__restrict__ map, float *__restrict__ F,
-         float *__restrict__ W_atom) {
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave), lane = threadIdx.x % kWave;
-  const int i = blockIdx.x * WPB + wave;
-  if (i >= N) return;
-  const int r = row_of_atom[i];
-  if (r < 0) {  // outside a caller's mask: no energy, no virial share
-    if (lane < 9) W_atom[(size_t)9 * i + lane] = 0.f;
-    return;
-  }
-  const SysDesc &d = sys[sys_of[i]];
-  const float4 pi = pos[i];
-  const float L[3] = {d.L[0], d.L[1], d.L[2]};
-  const int j0 = d.atom_off;
-  const int2 *row = nbr + nbr_row(d, i, cap);
-  const uint16_t *mrow = map + (size_t)i * c.ldm;
-  const int ea = mrow[0], eb = mrow[1];
-  int ja = -1, jb = -1;
-  float4 da = make_float4(0.f, 0.f, 0.f, 1.f), db = da;
-  if (ea != kNoEntry) {
-    const int2 en = row[ea];
-    ja = j0 + en.x;
-    da = entry_vec(pi, pos[ja], en.y, L);
-  }
-  if (eb != kNoEntry) {
-    const int2 en = row[eb];
-    jb = j0 + en.x;
-    db = entry_vec(pi, pos[jb], en.y, L);
-  }
+// Backward of centre i (one wavefront, row r of dE/dG): the explicit terms
+// of its slots, the frame terms, and its virial share.  add(j, x, y, z) takes
+// a contribution to the force on atom j; every lane may call it.
+template <class Add>
+__device__ inline void dp_centre_bwd(int i, int lane, int r, const float *__restrict__ dG, int ldg,
+                                     const DpConst &c, const float4 *__restrict__ rec,
+                                     float *__restrict__ W_atom, Add &&add) {
+  const float4 *rrow = rec + (size_t)i * c.ldm;
+  const float4 ra = rrow[0], rb = rrow[1];
+  const int ja = __float_as_int(ra.w), jb = __float_as_int(rb.w);
+  float4 da = make_float4(ra.x, ra.y, ra.z, 1.f), db = make_float4(rb.x, rb.y, rb.z, 1.f);
+  if (ja >= 0) da.w = fast_sqrt(da.x * da.x + da.y * da.y + da.z * da.z);
+  if (jb >= 0) db.w = fast_sqrt(db.x * db.x + db.y * db.y + db.z * db.z);
   const Frame f = make_frame(ja >= 0, da, jb >= 0, db);
   const float4 *g4 = (const float4 *)(dG + (size_t)r * ldg);
 
@@ -339,19 +326,17 @@ k_dp_bwd(const float4 *__restrict__ pos, const int *__restrict__ sys_of,
   for (int q = 0; q < 9; ++q) A[q] = vir[q] = 0.f;
   fi[0] = fi[1] = fi[2] = 0.f;
   for (int k = lane; k < c.n_slots; k += kWave) {
-    const int e = mrow[2 + k];
-    if (e == kNoEntry) continue;
-    const int2 en = row[e];
-    const int j = j0 + en.x;
-    const float4 dv = entry_vec(pi, pos[j], en.y, L);
+    const float4 rk = rrow[2 + k];
+    const int j = __float_as_int(rk.w);
+    if (j < 0) continue;
     const float4 gs = g4[k];
-    const float ir = 1.f / dv.w;
-    const float cx = dv.x * f.ex[0] + dv.y * f.ex[1] + dv.z * f.ex[2];
-    const float cy = dv.x * f.ey[0] + dv.y * f.ey[1] + dv.z * f.ey[2];
-    const float cz = dv.x * f.ez[0] + dv.y * f.ez[1] + dv.z * f.ez[2];
+    const float dvv[3] = {rk.x, rk.y, rk.z};
+    const float ir = 1.f / fast_sqrt(rk.x * rk.x + rk.y * rk.y + rk.z * rk.z);
+    const float cx = rk.x * f.ex[0] + rk.y * f.ex[1] + rk.z * f.ex[2];
+    const float cy = rk.x * f.ey[0] + rk.y * f.ey[1] + rk.z * f.ey[2];
+    const float cz = rk.x * f.ez[0] + rk.y * f.ez[1] + rk.z * f.ez[2];
     // d(1/R)/dd = -d/R^3, d(c/R)/dd = e_c/R - c d/R^3 (axes held fixed)
     const float s = (gs.x + gs.y * cx + gs.z * cy + gs.w * cz) * ir * ir * ir;
-    const float dvv[3] = {dv.x, dv.y, dv.z};
     float gd[3];
     for (int a = 0; a < 3; ++a) {
       gd[a] = -s * dvv[a] + (gs.y * f.ex[a] + gs.z * f.ey[a] + gs.w * f.ez[a]) * ir;
@@ -359,8 +344,8 @@ k_dp_bwd(const float4 *__restrict__ pos, const int *__restrict__ sys_of,
       A[3 + a] += gs.z * ir * dvv[a];
       A[6 + a] += gs.w * ir * dvv[a];
       fi[a] += gd[a];
-      atomicAdd(&F[3 * (size_t)j + a], -gd[a]);
     }
+    add(j, -gd[0], -gd[1], -gd[2]);
     for (int a = 0; a < 3; ++a)
       for (int b = 0; b < 3; ++b) vir[3 * a + b] -= dvv[a] * gd[b];
   }
@@ -403,13 +388,10 @@ k_dp_bwd(const float4 *__restrict__ pos, const int *__restrict__ sys_of,
       fi[a] += ga[a] + gb[a];
       for (int b = 0; b < 3; ++b) vir[3 * a + b] -= dav[a] * ga[b] + dbv[a] * gb[b];
     }
-    if (lane == 0)
-      for (int a = 0; a < 3; ++a) atomicAdd(&F[3 * (size_t)ja + a], -ga[a]);
-    if (lane == 1 && f.nu > 0.f)
-      for (int a = 0; a < 3; ++a) atomicAdd(&F[3 * (size_t)jb + a], -gb[a]);
+    if (lane == 0) add(ja, -ga[0], -ga[1], -ga[2]);
+    if (lane == 1 && f.nu > 0.f) add(jb, -gb[0], -gb[1], -gb[2]);
   }
-  if (lane == 0)
-    for (int a = 0; a < 3; ++a) atomicAdd(&F[3 * (size_t)i + a], fi[a]);
+  if (lane == 2) add(i, fi[0], fi[1], fi[2]);
   if (lane < 9) {
     float v = vir[0];
     for (int q = 1; q < 9; ++q) v = lane == q ? vir[q] : v;
@@ -417,22 +399,75 @@ k_dp_bwd(const float4 *__restrict__ pos, const int *__restrict__ sys_of,
   }
 }
 
+// Any batch: one wavefront per centre, forces by float atomics.
+template <int WPB>
+__global__ void __launch_bounds__(WPB * kWave)
+k_dp_bwd(const int *__restrict__ row_of_atom, const float *__restrict__ dG, int ldg, int N, DpConst c,
+         const float4 *__restrict__ rec, float *__restrict__ F, float *__restrict__ W_atom) {
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave), lane = threadIdx.x % kWave;
+  const int i = blockIdx.x * WPB + wave;
+  if (i >= N) return;
+  const int r = row_of_atom[i];
+  if (r < 0) {  // outside a caller's mask: no energy, no virial share
+    if (lane < 9) W_atom[(size_t)9 * i + lane] = 0.f;
+    return;
+  }
+  dp_centre_bwd(i, lane, r, dG, ldg, c, rec, W_atom, [&](int j, float x, float y, float z) {
+    atomicAdd(&F[3 * (size_t)j], x);
+    atomicAdd(&F[3 * (size_t)j + 1], y);
+    atomicAdd(&F[3 * (size_t)j + 2], z);
+  });
+}
+
+// Batches of small non-periodic systems (every neighbour inside the centre's
+// own system): one workgroup per system, its waves taking the system's
+// centres in turn; the system's forces are summed in LDS (64-bit fixed
+// point, integer atomics) and stored once, with no global atomics.
+template <int WPB>
+__global__ void __launch_bounds__(WPB * kWave)
+k_dp_bwd_sys(const SysDesc *__restrict__ sys, const int *__restrict__ row_of_atom,
+             const float *__restrict__ dG, int ldg, DpConst c, const float4 *__restrict__ rec,
+             float *__restrict__ F, float *__restrict__ W_atom) {
+  __shared__ unsigned long long facc[3 * kSmallSystem];
+  const SysDesc &d = sys[blockIdx.x];
+  const int n = d.n, a0 = d.atom_off;
+  for (int t = threadIdx.x; t < 3 * n; t += WPB * kWave) facc[t] = 0ull;
+  __syncthreads();
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave), lane = threadIdx.x % kWave;
+  for (int il = wave; il < n; il += WPB) {
+    const int i = a0 + il;
+    const int r = row_of_atom[i];
+    if (r < 0) {
+      if (lane < 9) W_atom[(size_t)9 * i + lane] = 0.f;
+      continue;
+    }
+    dp_centre_bwd(i, lane, r, dG, ldg, c, rec, W_atom, [&](int j, float x, float y, float z) {
+      unsigned long long *p = facc + 3 * (j - a0);
+      atomicAdd(p, (unsigned long long)to_fix(x));
+      atomicAdd(p + 1, (unsigned long long)to_fix(y));
+      atomicAdd(p + 2, (unsigned long long)to_fix(z));
+    });
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < 3 * n; t += WPB * kWave) F[3 * (size_t)a0 + t] = from_fix((long long)facc[t]);
+}
+
 template <bool BF16>
 static void dp_fwd_t(const float4 *pos, const float *coords, const AtomState *state, const int *sys_of,
                      const SysDesc *sys, const int2 *nbr, const int *nbr_cnt, int cap,
-                     const int *row_of_atom, void *G, int ldg, int N, const DpConst &c, uint16_t *map,
+                     const int *row_of_atom, void *G, int ldg, int N, const DpConst &c, float4 *rec,
                      int wpb, hipStream_t st) {
   const size_t lds = dp_lds_bytes(cap, c.n_slots) * wpb;
   const unsigned grid = (unsigned)((N + wpb - 1) / wpb);
   if (wpb == 4)
     k_dp_fwd<4, BF16><<<grid, 4 * kWave, lds, st>>>(pos, coords, state, sys_of, sys, nbr, nbr_cnt, cap,
-                                                    row_of_atom, G, ldg, N, c, map);
+                                                    row_of_atom, G, ldg, N, c, rec);
   else if (wpb == 2)
     k_dp_fwd<2, BF16><<<grid, 2 * kWave, lds, st>>>(pos, coords, state, sys_of, sys, nbr, nbr_cnt, cap,
-                                                    row_of_atom, G, ldg, N, c, map);
+                                                    row_of_atom, G, ldg, N, c, rec);
   else
     k_dp_fwd<1, BF16><<<grid, kWave, lds, st>>>(pos, coords, state, sys_of, sys, nbr, nbr_cnt, cap,
-                                                row_of_atom, G, ldg, N, c, map);
+                                                row_of_atom, G, ldg, N, c, rec);
 }
 
 // Waves per workgroup: the preference (1, 2 or 4) when its LDS fits in
@@ -440,27 +475,34 @@ static void dp_fwd_t(const float4 *pos, const float *coords, const AtomState *st
 void launch_dp_fwd(const float4 *pos, const float *coords, const AtomState *state, const int *sys_of,
                    const SysDesc *sys, const int2 *nbr, const int *nbr_cnt, int cap,
                    const int *row_of_atom, void *G, bool g_bf16, int ldg, int N, const DpConst &c,
-                   uint16_t *map, int wpb_pref, hipStream_t st) {
+                   float4 *rec, int wpb_pref, hipStream_t st) {
   if (N <= 0) return;
   int wpb = 1;
   if ((wpb_pref == 2 || wpb_pref == 4) && dp_lds_bytes(cap, c.n_slots) * wpb_pref <= 64 * 1024) wpb = wpb_pref;
-  if (g_bf16) dp_fwd_t<true>(pos, coords, state, sys_of, sys, nbr, nbr_cnt, cap, row_of_atom, G, ldg, N, c, map, wpb, st);
-  else dp_fwd_t<false>(pos, coords, state, sys_of, sys, nbr, nbr_cnt, cap, row_of_atom, G, ldg, N, c, map, wpb, st);
+  if (g_bf16) dp_fwd_t<true>(pos, coords, state, sys_of, sys, nbr, nbr_cnt, cap, row_of_atom, G, ldg, N, c, rec, wpb, st);
+  else dp_fwd_t<false>(pos, coords, state, sys_of, sys, nbr, nbr_cnt, cap, row_of_atom, G, ldg, N, c, rec, wpb, st);
 }
 
-// The backward uses no LDS: four waves per workgroup unless asked otherwise.
-void launch_dp_bwd(const float4 *pos, const int *sys_of, const SysDesc *sys, const int2 *nbr, int cap,
-                   const int *row_of_atom, const float *dG, int ldg, int N, const DpConst &c,
-                   const uint16_t *map, float *F, float *W_atom, int wpb_pref, hipStream_t st) {
+// The per-centre backward uses no LDS: four waves per workgroup unless asked
+// otherwise.  With small_systems (every system non-periodic with at most
+// kSmallSystem atoms) the per-system form runs instead, eight waves per
+// system.
+void launch_dp_bwd(const SysDesc *sys, int n_sys, bool small_systems, const int *row_of_atom, const float *dG,
+                   int ldg, int N, const DpConst &c, const float4 *rec, float *F, float *W_atom, int wpb_pref,
+                   hipStream_t st) {
   if (N <= 0) return;
+  if (small_systems) {
+    k_dp_bwd_sys<8><<<n_sys, 8 * kWave, 0, st>>>(sys, row_of_atom, dG, ldg, c, rec, F, W_atom);
+    return;
+  }
   const int wpb = (wpb_pref == 1 || wpb_pref == 2) ? wpb_pref : 4;
   const unsigned grid = (unsigned)((N + wpb - 1) / wpb);
   if (wpb == 4)
-    k_dp_bwd<4><<<grid, 4 * kWave, 0, st>>>(pos, sys_of, sys, nbr, cap, row_of_atom, dG, ldg, N, c, map, F, W_atom);
+    k_dp_bwd<4><<<grid, 4 * kWave, 0, st>>>(row_of_atom, dG, ldg, N, c, rec, F, W_atom);
   else if (wpb == 2)
-    k_dp_bwd<2><<<grid, 2 * kWave, 0, st>>>(pos, sys_of, sys, nbr, cap, row_of_atom, dG, ldg, N, c, map, F, W_atom);
+    k_dp_bwd<2><<<grid, 2 * kWave, 0, st>>>(row_of_atom, dG, ldg, N, c, rec, F, W_atom);
   else
-    k_dp_bwd<1><<<grid, kWave, 0, st>>>(pos, sys_of, sys, nbr, cap, row_of_atom, dG, ldg, N, c, map, F, W_atom);
+    k_dp_bwd<1><<<grid, kWave, 0, st>>>(row_of_atom, dG, ldg, N, c, rec, F, W_atom);
 }
 
 }  // namespace nnp

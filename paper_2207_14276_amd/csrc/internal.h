@@ -94,7 +94,7 @@ struct DpConst {
   int S;                       // species
   int n_slots;                 // sum of sel
   int D;                       // 4 * n_slots
-  int ldm;                     // slot-map row length (uint16 entries, multiple of 8)
+  int ldm;                     // slot records per centre: n_slots + 2 (frame neighbours a, b first)
   int sel[kMaxSpecies];        // neighbours kept per species
   int soff[kMaxSpecies];       // first slot of each species block
 };
@@ -209,15 +209,16 @@ void launch_nbr_build(const float4 *pos, const int *sys_of, const SysDesc *sys, 
 void launch_species_bucket(const float4 *pos, int N, int S, int *block_counts, int n_blocks,
                            int *bucket_off, int *bucket_cnt, int *perm, int *row_of_atom,
                            int rows_cap, hipStream_t st);
-// DeepPot-style descriptor: forward into G rows (and the per-centre slot map
-// for the backward, nullable), backward from dE/dG to forces and virial.
+// DeepPot-style descriptor: forward into G rows (and the per-centre slot
+// records {d, j} for the backward, nullable), backward from dE/dG and the
+// records to forces and virial.
 void launch_dp_fwd(const float4 *pos, const float *coords, const AtomState *state, const int *sys_of,
                    const SysDesc *sys, const int2 *nbr, const int *nbr_cnt, int cap,
                    const int *row_of_atom, void *G, bool g_bf16, int ldg, int N, const DpConst &c,
-                   uint16_t *map, int wpb_pref, hipStream_t st);
-void launch_dp_bwd(const float4 *pos, const int *sys_of, const SysDesc *sys, const int2 *nbr, int cap,
-                   const int *row_of_atom, const float *dG, int ldg, int N, const DpConst &c,
-                   const uint16_t *map, float *F, float *W_atom, int wpb_pref, hipStream_t st);
+                   float4 *rec, int wpb_pref, hipStream_t st);
+void launch_dp_bwd(const SysDesc *sys, int n_sys, bool small_systems, const int *row_of_atom, const float *dG,
+                   int ldg, int N, const DpConst &c, const float4 *rec, float *F, float *W_atom, int wpb_pref,
+                   hipStream_t st);
 void launch_aev_fwd(const float4 *pos, const int *sys_of, const SysDesc *sys, const int2 *nbr,
                     const int *nbr_cnt, int cap, const int *row_of_atom, void *G, bool g_bf16,
                     int ldg, int N, const AevConst &c, int wpb_pref, hipStream_t st);
