@@ -199,6 +199,8 @@ KERNEL_SOURCES = {
                  "paper_2207_14276_amd/csrc/wave.h"],
     "k_dp_bwd": ["paper_2207_14276_amd/csrc/deeppot.hip", "paper_2207_14276_amd/csrc/internal.h",
                  "paper_2207_14276_amd/csrc/wave.h"],
+    "k_dp_bwd_sys": ["paper_2207_14276_amd/csrc/deeppot.hip", "paper_2207_14276_amd/csrc/internal.h",
+                     "paper_2207_14276_amd/csrc/wave.h"],
     "k_gemm": ["paper_2207_14276_amd/csrc/mlp.hip", "paper_2207_14276_amd/csrc/internal.h"],
 }
 
@@ -703,6 +705,9 @@ def main():
     achieved = work / t_dom / 1e12
     pre = "k_dp" if args.model == "dp" else "k_aev"
     kname = {"aev_fwd": pre + "_fwd", "aev_bwd": pre + "_bwd", "mlp": "k_gemm"}[dom]
+    small = bool(np.all(batch.boxes == 0)) and int(np.diff(batch.offsets).max()) <= 512
+    if kname == "k_dp_bwd" and small:
+        kname = "k_dp_bwd_sys"   # batches of small non-periodic systems: the per-system form
     wl = args.workload + ("_dp" if args.model == "dp" else "")
     roof = {"kernel": kname if dom != "mlp" else "k_gemm (all dense layers)",
             "bound": bound, "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
