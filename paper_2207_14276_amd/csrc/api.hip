@@ -1027,13 +1027,17 @@ static int run(nnp_model *m, int n_sys, const int64_t *offs, const float *coords
   mark();
   if (want_grad) {
     site_begin(kSiteAevBwd);
-    if (dp)
-      launch_dp_bwd(dsys, n_sys, all_small, m->row_of_atom.as<int>(), m->dG.as<float>(), D, N, m->dp,
+    if (dp) {
+      // cells exist for this call unless the pair list or the small-system scan replaced them
+      const bool cells = !pairs && !all_small;
+      launch_dp_bwd(dsys, n_sys, all_small, cells ? m->cell_start.as<int>() : nullptr,
+                    m->cell_atoms.as<int>(), (int)C, m->row_of_atom.as<int>(), m->dG.as<float>(), D, N, m->dp,
                     m->dp_rec.as<float4>(), o.forces, m->W_atom.as<float>(), m->tune_val[kSiteAevBwd], st);
-    else
+    } else {
       launch_aev_bwd(pos, m->sys_of.as<int>(), dsys, pool_nbr, pool_cnt, cap,
                      m->row_of_atom.as<int>(), m->dG.as<float>(), D, N, m->aev, o.forces,
                      m->W_atom.as<float>(), m->tune_val[kSiteAevBwd], st);
+    }
     site_end(kSiteAevBwd);
   }
   mark();

@@ -30,10 +30,12 @@
 // record (one coalesced load, no neighbour-list or atom gathers), the
 // explicit derivative of the slot's features with respect to its vector and
 // the frame sums A_c = sum_j (dE/dc_j) d_j / R_j, reduced over the wave; the
-// frame terms then reach the axis neighbours a and b.  Forces go out by float
-// atomics, or, for batches of small non-periodic systems, are summed per
-// system in LDS and stored once (global float atomics dominated the time of
-// the per-centre form).
+// frame terms then reach the axis neighbours a and b.  Global float atomics
+// dominated the time of that per-centre form, so forces are summed in LDS
+// first: per system for batches of small non-periodic systems (stored once,
+// no atomics), per cell of the cell grid otherwise (one set of atomics per
+// distinct atom and cell); the per-centre form with atomics remains for the
+// caller's pair lists.
 #include "internal.h"
 #include "wave.h"
 
@@ -483,16 +485,84 @@ void launch_dp_fwd(const float4 *pos, const float *coords, const AtomState *stat
   else dp_fwd_t<false>(pos, coords, state, sys_of, sys, nbr, nbr_cnt, cap, row_of_atom, G, ldg, N, c, rec, wpb, st);
 }
 
+// Systems on a cell grid: one workgroup per cell, its waves taking the cell's
+// centres in turn.  The centres of one cell share most of their neighbours,
+// so their force contributions are first summed in an LDS hash table keyed
+// by atom index (open addressing, 64-bit fixed-point sums) and each distinct
+// atom receives one set of float atomics per cell instead of one per
+// contribution.  A contribution that finds the table full goes straight to
+// global memory.
+constexpr int kMinCellGroups = 256;
+constexpr int kHashBits = 11;
+constexpr int kHashSlots = 1 << kHashBits;   // 2048 atoms; a cell's neighbourhood holds ~700
+
+template <int WPB>
+__global__ void __launch_bounds__(WPB * kWave)
+k_dp_bwd_cells(const int *__restrict__ cell_start, const int *__restrict__ cell_atoms,
+               const int *__restrict__ row_of_atom, const float *__restrict__ dG, int ldg, DpConst c,
+               const float4 *__restrict__ rec, float *__restrict__ F, float *__restrict__ W_atom) {
+  __shared__ int hkey[kHashSlots];
+  __shared__ unsigned long long hval[3 * kHashSlots];
+  const int b = cell_start[blockIdx.x], e = cell_start[blockIdx.x + 1];
+  if (b == e) return;  // the whole workgroup leaves together
+  for (int t = threadIdx.x; t < kHashSlots; t += WPB * kWave) {
+    hkey[t] = -1;
+    hval[3 * t] = hval[3 * t + 1] = hval[3 * t + 2] = 0ull;
+  }
+  __syncthreads();
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave), lane = threadIdx.x % kWave;
+  for (int p = b + wave; p < e; p += WPB) {
+    const int i = cell_atoms[p];
+    const int r = row_of_atom[i];
+    if (r < 0) {
+      if (lane < 9) W_atom[(size_t)9 * i + lane] = 0.f;
+      continue;
+    }
+    dp_centre_bwd(i, lane, r, dG, ldg, c, rec, W_atom, [&](int j, float x, float y, float z) {
+      unsigned h = ((unsigned)j * 2654435761u) >> (32 - kHashBits);
+      for (int probe = 0; probe < kHashSlots; ++probe) {
+        int k = hkey[h];
+        if (k == -1) k = atomicCAS(&hkey[h], -1, j);  // -1: this lane claimed the slot
+        if (k == -1 || k == j) {
+          atomicAdd(&hval[3 * h], (unsigned long long)to_fix(x));
+          atomicAdd(&hval[3 * h + 1], (unsigned long long)to_fix(y));
+          atomicAdd(&hval[3 * h + 2], (unsigned long long)to_fix(z));
+          return;
+        }
+        h = (h + 1) & (kHashSlots - 1);
+      }
+      atomicAdd(&F[3 * (size_t)j], x);
+      atomicAdd(&F[3 * (size_t)j + 1], y);
+      atomicAdd(&F[3 * (size_t)j + 2], z);
+    });
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < kHashSlots; t += WPB * kWave) {
+    const int j = hkey[t];
+    if (j < 0) continue;
+    atomicAdd(&F[3 * (size_t)j], from_fix((long long)hval[3 * t]));
+    atomicAdd(&F[3 * (size_t)j + 1], from_fix((long long)hval[3 * t + 1]));
+    atomicAdd(&F[3 * (size_t)j + 2], from_fix((long long)hval[3 * t + 2]));
+  }
+}
+
 // The per-centre backward uses no LDS: four waves per workgroup unless asked
 // otherwise.  With small_systems (every system non-periodic with at most
 // kSmallSystem atoms) the per-system form runs instead, eight waves per
-// system.
-void launch_dp_bwd(const SysDesc *sys, int n_sys, bool small_systems, const int *row_of_atom, const float *dG,
-                   int ldg, int N, const DpConst &c, const float4 *rec, float *F, float *W_atom, int wpb_pref,
-                   hipStream_t st) {
+// system; with a cell grid (cell_start non-null) of at least one cell per
+// compute unit the per-cell form, eight waves per cell (fewer cells leave
+// most of the chip idle: the 2,001-atom water box has 64).
+void launch_dp_bwd(const SysDesc *sys, int n_sys, bool small_systems, const int *cell_start,
+                   const int *cell_atoms, int n_cells, const int *row_of_atom, const float *dG, int ldg, int N,
+                   const DpConst &c, const float4 *rec, float *F, float *W_atom, int wpb_pref, hipStream_t st) {
   if (N <= 0) return;
   if (small_systems) {
     k_dp_bwd_sys<8><<<n_sys, 8 * kWave, 0, st>>>(sys, row_of_atom, dG, ldg, c, rec, F, W_atom);
+    return;
+  }
+  if (cell_start && n_cells >= kMinCellGroups) {
+    k_dp_bwd_cells<8><<<n_cells, 8 * kWave, 0, st>>>(cell_start, cell_atoms, row_of_atom, dG, ldg, c, rec, F,
+                                                     W_atom);
     return;
   }
   const int wpb = (wpb_pref == 1 || wpb_pref == 2) ? wpb_pref : 4;

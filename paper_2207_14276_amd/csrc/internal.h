@@ -216,9 +216,9 @@ void launch_dp_fwd(const float4 *pos, const float *coords, const AtomState *stat
                    const SysDesc *sys, const int2 *nbr, const int *nbr_cnt, int cap,
                    const int *row_of_atom, void *G, bool g_bf16, int ldg, int N, const DpConst &c,
                    float4 *rec, int wpb_pref, hipStream_t st);
-void launch_dp_bwd(const SysDesc *sys, int n_sys, bool small_systems, const int *row_of_atom, const float *dG,
-                   int ldg, int N, const DpConst &c, const float4 *rec, float *F, float *W_atom, int wpb_pref,
-                   hipStream_t st);
+void launch_dp_bwd(const SysDesc *sys, int n_sys, bool small_systems, const int *cell_start,
+                   const int *cell_atoms, int n_cells, const int *row_of_atom, const float *dG, int ldg, int N,
+                   const DpConst &c, const float4 *rec, float *F, float *W_atom, int wpb_pref, hipStream_t st);
 void launch_aev_fwd(const float4 *pos, const int *sys_of, const SysDesc *sys, const int2 *nbr,
                     const int *nbr_cnt, int cap, const int *row_of_atom, void *G, bool g_bf16,
                     int ldg, int N, const AevConst &c, int wpb_pref, hipStream_t st);
