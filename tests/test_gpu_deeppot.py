@@ -239,3 +239,31 @@ def test_persistent_lists_follow_moves(m32, oracle_lib, om):
     assert worst <= FP32_F
     assert nl.builds() == 1
     nl.close()
+
+
+def test_energy_only_equals_full(m16):
+    """Energy-only calls (no slot records, no backward) give the energies of
+    the energy+force call bit for bit, on the cell-grid and small-system
+    paths."""
+    for b in (synth.config2(), synth.make_batch([synth.config1()])):
+        c, s, bx, o = to_dev(b)
+        e0 = m16.energy_forces(c, s, bx, o, forces=False, check=True).energy.cpu().numpy()
+        e1 = m16.energy_forces(c, s, bx, o, forces=True, check=True).energy.cpu().numpy()
+        assert np.array_equal(e0, e1)
+
+
+def test_cell_grid_backward_sampled(m32, oracle_lib, om):
+    """A 7,500-atom water box (7^3 = 343 cells, enough for the per-cell
+    backward with its LDS hash): 24 seeded atoms' energies and forces
+    against the oracle's local evaluation."""
+    s = synth.water_box(2500, seed=11)
+    b = synth.make_batch([s])
+    gpu = run_gpu(m32, b)
+    rng = np.random.default_rng(11)
+    t = np.sort(rng.choice(s.n, 24, replace=False))
+    e_ref, f_ref = oracle_lib.sampled(s.coords, s.species, s.box, om, t)
+    de = float(np.abs(gpu["e_atom"][t] - e_ref).max())
+    df = float(np.abs(gpu["forces"][t] - f_ref).max())
+    log(f"[dp cells] L={s.box[0]:.2f} N={s.n} max|dE_i|={de:.3e} max|dF|={df:.3e}")
+    assert de <= FP32_E_ATOM
+    assert df <= FP32_F
