@@ -117,7 +117,7 @@ struct nnp_model {
   // workspace
   DevBuf pos, sys_of, atom_cell, atom_slot, cell_count, cell_start, cell_atoms, nbr, nbr_cnt;
   DevBuf block_counts, bucket_off, bucket_cnt, perm, row_of_atom, G, dG, e_atom, W_atom, partial;
-  DevBuf sysdesc, chunk_sys, chunk_begin, sys_chunk_off, status, state, e_mem, dp_rec;
+  DevBuf desc, status, state, e_mem, dp_rec;  // desc: the per-call descriptors (desc_layout)
   std::vector<DevBuf> H, Gd;
   // fused hidden-layer chain (bfloat16 models whose hidden widths allow it)
   bool chain = false;
@@ -180,8 +180,7 @@ extern "C" void nnp_destroy(nnp_model *m) {
   DevBuf *bufs[] = {&m->pos, &m->sys_of, &m->atom_cell, &m->atom_slot, &m->cell_count,
                     &m->cell_start, &m->cell_atoms, &m->nbr, &m->nbr_cnt, &m->block_counts,
                     &m->bucket_off, &m->bucket_cnt, &m->perm, &m->row_of_atom, &m->G, &m->dG,
-                    &m->e_atom, &m->W_atom, &m->partial, &m->sysdesc, &m->chunk_sys,
-                    &m->chunk_begin, &m->sys_chunk_off, &m->status, &m->state, &m->e_mem,
+                    &m->e_atom, &m->W_atom, &m->partial, &m->desc, &m->status, &m->state, &m->e_mem,
                     &m->chain_nets, &m->dp_rec};
   for (DevBuf *b : bufs) b->release();
   for (auto &b : m->H) b.release();
@@ -452,6 +451,20 @@ extern "C" int nnp_create_dp(const nnp_dp_model_desc *d, nnp_model **out) {
 
 extern "C" int nnp_aev_dim(const nnp_model *m) { return m ? m->D : NNP_EINVAL; }
 
+// Layout of the per-call descriptors, the same in pinned staging memory and
+// in the device buffer: SysDesc[S], chunk system[n_chunks], chunk first
+// atom[n_chunks], first chunk of each system[S + 1].
+struct DescLayout {
+  size_t sd, cs, cb, so, total;
+  DescLayout(int S, int n_chunks) {
+    sd = 0;
+    cs = sd + sizeof(SysDesc) * (size_t)S;
+    cb = cs + 4 * (size_t)n_chunks;
+    so = cb + 4 * (size_t)n_chunks;
+    total = so + 4 * (size_t)(S + 1);
+  }
+};
+
 // Buffers for a call of N atoms, S systems, C cells and n_chunks chunks.
 // Workspace of a call with N atoms, S systems, C cells and n_chunks
 // reduction chunks: f(buffer, bytes) is applied to every buffer (grow it, or
@@ -488,10 +501,7 @@ static int for_each_ws(nnp_model *m, int64_t N, int S, int64_t C, int n_chunks, 
   if (m->chain) ENS(m->e_mem, rows * m->M * 4);
   ENS(m->W_atom, N * 36);
   ENS(m->partial, (int64_t)n_chunks * 80 + 80);
-  ENS(m->sysdesc, (int64_t)S * sizeof(SysDesc));
-  ENS(m->chunk_sys, (int64_t)n_chunks * 4 + 4);
-  ENS(m->chunk_begin, (int64_t)n_chunks * 4 + 4);
-  ENS(m->sys_chunk_off, (int64_t)(S + 1) * 4);
+  ENS(m->desc, DescLayout(S, n_chunks).total);
   for (int l = 0; l + 1 < m->L; ++l) {
     ENS(m->H[l], rows * m->ldH[l] * m->M * esz);
     ENS(m->Gd[l], rows * m->ldH[l] * m->M * esz);
@@ -767,10 +777,10 @@ static int run(nnp_model *m, int n_sys, const int64_t *offs, const float *coords
     m->G_zeroed = m->G.bytes;
   }
 
-  // stage the per-call descriptors through pinned memory
-  size_t off_sd = 0, off_cs = off_sd + sizeof(SysDesc) * n_sys;
-  size_t off_cb = off_cs + 4 * (size_t)n_chunks, off_so = off_cb + 4 * (size_t)n_chunks;
-  size_t total = off_so + 4 * (size_t)(n_sys + 1);
+  // stage the per-call descriptors through pinned memory; one copy moves them
+  // all into the device buffer of the same layout
+  const DescLayout dl(n_sys, n_chunks);
+  const size_t off_sd = dl.sd, off_cs = dl.cs, off_cb = dl.cb, off_so = dl.so, total = dl.total;
   if (m->stage_pending) {
     HIP_TRY(hipEventSynchronize(m->stage_done));
     m->stage_pending = false;
@@ -789,12 +799,7 @@ static int run(nnp_model *m, int n_sys, const int64_t *offs, const float *coords
     memcpy(hs + off_cb, ch_begin.data(), 4 * (size_t)n_chunks);
   }
   memcpy(hs + off_so, sys_ch.data(), 4 * (size_t)(n_sys + 1));
-  HIP_TRY(hipMemcpyAsync(m->sysdesc.p, hs + off_sd, sizeof(SysDesc) * n_sys, hipMemcpyHostToDevice, st));
-  if (n_chunks) {
-    HIP_TRY(hipMemcpyAsync(m->chunk_sys.p, hs + off_cs, 4 * (size_t)n_chunks, hipMemcpyHostToDevice, st));
-    HIP_TRY(hipMemcpyAsync(m->chunk_begin.p, hs + off_cb, 4 * (size_t)n_chunks, hipMemcpyHostToDevice, st));
-  }
-  HIP_TRY(hipMemcpyAsync(m->sys_chunk_off.p, hs + off_so, 4 * (size_t)(n_sys + 1), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(m->desc.p, hs, total, hipMemcpyHostToDevice, st));
   HIP_TRY(hipEventRecord(m->stage_done, st));
   m->stage_pending = true;
 
@@ -819,7 +824,10 @@ static int run(nnp_model *m, int n_sys, const int64_t *offs, const float *coords
     if (tuning) (void)hipEventRecord(m->tune_ev[site][1], st);
   };
   mark();
-  SysDesc *dsys = m->sysdesc.as<SysDesc>();
+  SysDesc *dsys = (SysDesc *)(m->desc.as<char>() + off_sd);
+  const int *d_chunk_sys = (const int *)(m->desc.as<char>() + off_cs);
+  const int *d_chunk_begin = (const int *)(m->desc.as<char>() + off_cb);
+  const int *d_sys_chunk_off = (const int *)(m->desc.as<char>() + off_so);
   int *status = m->status.as<int>();
   float4 *pos = m->pos.as<float4>();
   int2 *pool_nbr = nl ? nl->nbr.as<int2>() : m->nbr.as<int2>();
@@ -865,7 +873,10 @@ static int run(nnp_model *m, int n_sys, const int64_t *offs, const float *coords
                         m->bucket_cnt.as<int>(), m->perm.as<int>(), m->row_of_atom.as<int>(), rows, st);
   if (mode == kFull && o.forces) launch_fill(o.forces, (size_t)3 * N, 0.f, st);
   // atoms outside a caller's mask have no network: zero atomic energy
-  if (pin.mask) launch_fill(m->e_atom.as<float>(), (size_t)N, 0.f, st);
+  // atomic energies go straight to the caller's buffer when one is given
+  // (every atom's entry is written each call), else to the workspace
+  float *e_atom = o.atom_energy ? o.atom_energy : m->e_atom.as<float>();
+  if (pin.mask) launch_fill(e_atom, (size_t)N, 0.f, st);
   mark();
   const int D = m->D;
   const bool bf16 = m->precision == NNP_BF16;
@@ -946,7 +957,7 @@ static int run(nnp_model *m, int n_sys, const int64_t *offs, const float *coords
     cl.inv_m = 1.0f / (float)M;
     cl.e_mem = m->e_mem.as<float>();
     cl.perm = m->perm.as<int>();
-    cl.e_atom = m->e_atom.as<float>();
+    cl.e_atom = e_atom;
     site_begin(kSiteChain);
     launch_chain(cl, L - 2, want_grad, rows, m->chain_lds, m->tune_val[kSiteChain] == 4 ? 4 : 8, st);
     site_end(kSiteChain);
@@ -969,7 +980,7 @@ static int run(nnp_model *m, int n_sys, const int64_t *offs, const float *coords
     el.bucket_off = m->bucket_off.as<int>();
     el.n_groups = S;
     el.n_members = M;
-    el.e_atom = m->e_atom.as<float>();
+    el.e_atom = e_atom;
     el.inv_m = 1.0f / (float)M;
     el.alpha = m->alpha;
     el.hidden = L >= 2;
@@ -1041,11 +1052,9 @@ static int run(nnp_model *m, int n_sys, const int64_t *offs, const float *coords
     site_end(kSiteAevBwd);
   }
   mark();
-  launch_reduce(m->e_atom.as<float>(), want_grad ? m->W_atom.as<float>() : nullptr, dsys, n_sys,
-                m->chunk_sys.as<int>(), m->chunk_begin.as<int>(), n_chunks, m->sys_chunk_off.as<int>(),
+  launch_reduce(e_atom, want_grad ? m->W_atom.as<float>() : nullptr, dsys, n_sys,
+                d_chunk_sys, d_chunk_begin, n_chunks, d_sys_chunk_off,
                 m->partial.as<double>(), o.energy, o.virial, st);
-  if (o.atom_energy && N > 0)
-    HIP_TRY(hipMemcpyAsync(o.atom_energy, m->e_atom.p, (size_t)N * 4, hipMemcpyDeviceToDevice, st));
   mark();
   if (ev) m->last_stages = stage - 1;
   HIP_TRY(hipGetLastError());
