@@ -389,7 +389,8 @@ int nnp_sched_info(nnp_sched *sched, int64_t *info);
  *                    the members' columns side by side in one tile space);
  *   site 10 + l      dense layer l input-gradient GEMM: width 64, 128 or 256;
  *   site 18          the dE/dG GEMM: width 64, 128 or 256;
- *   site 19          the fused hidden-layer chain: 4 or 8 waves per workgroup.
+ *   site 19          the fused hidden-layer chain: 4 or 8 waves per workgroup on
+ *                    32 rows, or 18: 8 waves on 64 rows (when twice the LDS fits).
  * The choices stay with the model for all later calls (no call changes any
  * result: tile shapes change no per-element arithmetic order); sites that did
  * not run keep their default (0).  Waits for the stream; allocates. */

@@ -121,6 +121,7 @@ struct nnp_model {
   std::vector<DevBuf> H, Gd;
   // fused hidden-layer chain (bfloat16 models whose hidden widths allow it)
   bool chain = false;
+  bool chain_rt2 = false;                // 64-row workgroups fit the LDS
   DevBuf chain_nets;                     // [member][species] ChainNet
   ChainLaunch chain_proto{};             // strides and LDS layout, filled at creation
   size_t chain_lds = 0;
@@ -414,6 +415,9 @@ static int create_networks(const NetArgs *d, nnp_model *m) {
       HIP_TRY(hipMemcpy(m->chain_nets.p, nets.data(), nets.size() * sizeof(ChainNet), hipMemcpyHostToDevice));
       m->chain = true;
       m->chain_lds = lds;
+      int max_lds = 0;
+      HIP_TRY(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, m->device));
+      m->chain_rt2 = 2 * lds <= (size_t)max_lds;
     }
   }
   HIP_TRY(hipEventCreateWithFlags(&m->stage_done, hipEventDisableTiming));
@@ -959,7 +963,10 @@ static int run(nnp_model *m, int n_sys, const int64_t *offs, const float *coords
     cl.perm = m->perm.as<int>();
     cl.e_atom = e_atom;
     site_begin(kSiteChain);
-    launch_chain(cl, L - 2, want_grad, rows, m->chain_lds, m->tune_val[kSiteChain] == 4 ? 4 : 8, st);
+    // tuned shape: 4 or 8 waves, plus 10 for 64-row workgroups
+    const int tv = m->tune_val[kSiteChain];
+    launch_chain(cl, L - 2, want_grad, rows, m->chain_lds, tv % 10 == 4 ? 4 : 8,
+                 tv >= 10 && m->chain_rt2 ? 2 : 1, st);
     site_end(kSiteChain);
   } else {
     EnergyLaunch el{};
@@ -1140,7 +1147,9 @@ extern "C" int nnp_autotune(nnp_model *m, int n_systems, const int64_t *offs, co
   // candidates: round r sets every GEMM site to kTn[r], both AEV sites to
   // kWpb[r] and the fused chain to kChainW[r] waves per workgroup
   constexpr int kRounds = 3, kReps = 3;
-  const int kTn[kRounds] = {64, 128, 256}, kWpb[kRounds] = {1, 2, 4}, kChainW[kRounds] = {8, 4, 8};
+  const int kTn[kRounds] = {64, 128, 256}, kWpb[kRounds] = {1, 2, 4};
+  // chain: 8 or 4 waves on 32 rows, 8 waves on 64 rows (+10) when the LDS allows
+  const int kChainW[kRounds] = {8, 4, m->chain_rt2 ? 18 : 8};
   double t[kTuneSites][kRounds] = {};
   bool hit[kTuneSites] = {};
   int rc = NNP_OK;
@@ -1168,7 +1177,9 @@ extern "C" int nnp_autotune(nnp_model *m, int n_systems, const int64_t *offs, co
     m->tune_val[q] = 0;
     if (!hit[q] || rc) continue;
     if (q == kSiteChain) {
-      m->tune_val[q] = std::min(t[q][0], t[q][2]) <= t[q][1] ? 8 : 4;
+      int best = 0;
+      for (int r = 1; r < kRounds; ++r) if (t[q][r] < t[q][best]) best = r;
+      m->tune_val[q] = kChainW[best];
     } else {
       int best = 0;
       for (int r = 1; r < kRounds; ++r) if (t[q][r] < t[q][best]) best = r;

@@ -5,7 +5,9 @@
 // layers of a network are narrow (<= 256 wide): run as separate GEMMs their
 // activations make several round trips through HBM.  Here one workgroup
 // takes 32 rows of one species bucket for one ensemble member and runs the
-// rest of the network on chip:
+// rest of the network on chip (or 64 rows, RT = 2, when the LDS allows: each
+// weight fragment loaded from L2 then feeds twice as many MFMAs, and weight
+// traffic from L2 is what bounds this kernel):
 //   forward   h_l = CELU(h_{l-1} W_l^T + b_l) for the hidden layers l >= 1,
 //             E = h_last . w_out + b_out, d_last = w_out * CELU'(h_last) / M;
 //   backward  d_{l-1} = (d_l W_l) * CELU'(h_{l-1}) down to d_0,
@@ -24,14 +26,16 @@ namespace nnp {
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float floatx4_t __attribute__((ext_vector_type(4)));
 
-__device__ inline uint16_t to_bf16(float f) {
-  uint32_t u = __float_as_uint(f);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
-}
+// float -> bfloat16, round to nearest even (one hardware conversion)
+__device__ inline uint16_t to_bf16(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
 __device__ inline float from_bf16(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
-__device__ inline float celu_f(float z, float alpha) { return z > 0.f ? z : alpha * expm1f(z / alpha); }
-__device__ inline float dcelu_h(float h, float alpha) { return h > 0.f ? 1.f : 1.f + h / alpha; }
+// CELU with the hardware exp2 (about 1 ulp; the result is rounded to
+// bfloat16 next), k_exp = log2(e) / alpha; CELU' from h = CELU(z) with
+// inv_alpha = 1 / alpha.
+__device__ inline float celu_f(float z, float alpha, float k_exp) {
+  return z > 0.f ? z : alpha * (__builtin_amdgcn_exp2f(z * k_exp) - 1.f);
+}
+__device__ inline float dcelu_h(float h, float inv_alpha) { return h > 0.f ? 1.f : 1.f + h * inv_alpha; }
 
 // Sum over aligned groups of 8 lanes (DPP), result in every lane of the group.
 __device__ inline float sum8_dpp(float v) {
@@ -41,15 +45,16 @@ __device__ inline float sum8_dpp(float v) {
   return v;
 }
 
-// C[32 x N] = A[32 x K] (LDS, bfloat16, row stride lda) . B^T with B[N][K]
-// (global, bfloat16, row stride ldb); K a multiple of 32 (<= 256), N of 16.
-// For every 16-column block owned by this wave, epi(cb, acc0, acc1) gets the
-// accumulators of rows 0-15 and 16-31: lane l holds column 16 cb + l % 16,
-// rows 4 (l / 16) + j (j = 0..3) of each half.
-template <int W, class Epi>
+// C[32 RT x N] = A[32 RT x K] (LDS, bfloat16, row stride lda) . B^T with
+// B[N][K] (global, bfloat16, row stride ldb); K a multiple of 32 (<= 256), N
+// of 16.  For every 16-column block owned by this wave, epi(cb, acc) gets the
+// accumulators of the 2 RT sixteen-row groups: lane l holds column
+// 16 cb + l % 16, rows 16 h + 4 (l / 16) + j (j = 0..3) in acc[h].
+template <int W, int RT, class Epi>
 __device__ inline void chain_gemm(const uint16_t *A, int lda, int K, const uint16_t *__restrict__ B, int ldb,
                                   int N, int wave, int lane, Epi &&epi) {
   constexpr int QM = 16 / W;                      // blocks per wave at N = 256
+  constexpr int HR = 2 * RT;                      // sixteen-row groups
   const int l16 = lane & 15, kq = lane >> 4;
   const int nkb = K / 32, ncb = N / 16;
   // this wave's blocks: wave + W q, q < nq (N <= 256: at most 16 / W).
@@ -58,9 +63,11 @@ __device__ inline void chain_gemm(const uint16_t *A, int lda, int K, const uint1
   // are loaded while the current step's MFMAs run.
   const int nq = ncb > wave ? (ncb - wave + W - 1) / W : 0;
   if (nq == 0) return;
-  floatx4_t acc[QM][2];
+  floatx4_t acc[QM][HR];
 #pragma unroll
-  for (int q = 0; q < QM; ++q) acc[q][0] = acc[q][1] = floatx4_t{0.f, 0.f, 0.f, 0.f};
+  for (int q = 0; q < QM; ++q)
+#pragma unroll
+    for (int h = 0; h < HR; ++h) acc[q][h] = floatx4_t{0.f, 0.f, 0.f, 0.f};
   const uint16_t *bp = B + (size_t)(wave * 16 + l16) * ldb + 8 * kq;
   const size_t bstep = (size_t)16 * W * ldb;      // W blocks of 16 rows
   uint4 bc[QM], bn[QM];
@@ -73,14 +80,16 @@ __device__ inline void chain_gemm(const uint16_t *A, int lda, int K, const uint1
       for (int q = 0; q < QM; ++q)
         if (q < nq) bn[q] = *(const uint4 *)(bp + q * bstep + (kb + 1) * 32);
     }
-    const bf16x8_t a0 = __builtin_bit_cast(bf16x8_t, *(const uint4 *)(A + l16 * lda + kb * 32 + 8 * kq));
-    const bf16x8_t a1 = __builtin_bit_cast(bf16x8_t, *(const uint4 *)(A + (16 + l16) * lda + kb * 32 + 8 * kq));
+    bf16x8_t a[HR];
+#pragma unroll
+    for (int h = 0; h < HR; ++h)
+      a[h] = __builtin_bit_cast(bf16x8_t, *(const uint4 *)(A + (16 * h + l16) * lda + kb * 32 + 8 * kq));
 #pragma unroll
     for (int q = 0; q < QM; ++q) {
       if (q < nq) {
         const bf16x8_t b = __builtin_bit_cast(bf16x8_t, bc[q]);
-        acc[q][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b, acc[q][0], 0, 0, 0);
-        acc[q][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b, acc[q][1], 0, 0, 0);
+#pragma unroll
+        for (int h = 0; h < HR; ++h) acc[q][h] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[h], b, acc[q][h], 0, 0, 0);
       }
     }
 #pragma unroll
@@ -88,11 +97,14 @@ __device__ inline void chain_gemm(const uint16_t *A, int lda, int K, const uint1
   }
 #pragma unroll
   for (int q = 0; q < QM; ++q)
-    if (q < nq) epi(wave + W * q, acc[q][0], acc[q][1]);
+    if (q < nq) epi(wave + W * q, acc[q]);
 }
 
-template <int NL, bool GRAD, int W>
+template <int NL, bool GRAD, int W, int RT>
 __global__ void __launch_bounds__(W * kWave) k_chain(ChainLaunch cl) {
+  constexpr int R = kChainRows * RT;   // rows of this workgroup
+  constexpr int HR = 2 * RT;
+  const float inv_alpha = 1.f / cl.alpha, k_exp = 1.4426950408889634f * inv_alpha;
   extern __shared__ uint4 chain_lds[];
   const int tid = threadIdx.x, wave = __builtin_amdgcn_readfirstlane(tid / kWave), lane = tid % kWave;
   const int l16 = lane & 15, kq = lane >> 4;
@@ -103,7 +115,7 @@ __global__ void __launch_bounds__(W * kWave) k_chain(ChainLaunch cl) {
   if (lb >= cl.n_blocks) return;
   const int n_rt = cl.n_blocks / cl.n_members;
   const int mb = lb / n_rt;
-  const int r0 = (lb % n_rt) * kChainRows;
+  const int r0 = (lb % n_rt) * R;
   int s = -1;
   for (int q = 0; q < cl.n_groups; ++q)
     if (r0 >= cl.bucket_off[q] && r0 < cl.bucket_off[q + 1]) s = q;
@@ -111,13 +123,13 @@ __global__ void __launch_bounds__(W * kWave) k_chain(ChainLaunch cl) {
   const ChainNet &net = cl.nets[mb * cl.n_groups + s];
   uint16_t *act[NL + 1];
 #pragma unroll
-  for (int l = 0; l <= NL; ++l) act[l] = (uint16_t *)((char *)chain_lds + cl.lds_off[l]);
+  for (int l = 0; l <= NL; ++l) act[l] = (uint16_t *)((char *)chain_lds + (size_t)cl.lds_off[l] * RT);
 
   // h_0 tile (this member's slice of the first layer's output) into LDS
   {
     const int w0 = net.width[0], cpr = w0 / 8;
     const uint16_t *src = cl.H0 + (size_t)r0 * cl.ldh + (size_t)mb * cl.h_member_stride;
-    for (int idx = tid; idx < kChainRows * cpr; idx += blockDim.x) {
+    for (int idx = tid; idx < R * cpr; idx += blockDim.x) {
       const int row = idx / cpr, ch = idx % cpr;
       *(uint4 *)(act[0] + row * cl.lds_ld[0] + ch * 8) = *(const uint4 *)(src + (size_t)row * cl.ldh + ch * 8);
     }
@@ -131,27 +143,27 @@ __global__ void __launch_bounds__(W * kWave) k_chain(ChainLaunch cl) {
     uint16_t *out = act[l];
     const int ldo = cl.lds_ld[l];
     if (l < NL) {
-      chain_gemm<W>(act[l - 1], cl.lds_ld[l - 1], K, net.W[l - 1], K, N, wave, lane,
-                 [&](int cb, floatx4_t a0, floatx4_t a1) {
+      chain_gemm<W, RT>(act[l - 1], cl.lds_ld[l - 1], K, net.W[l - 1], K, N, wave, lane,
+                 [&](int cb, const floatx4_t *acc) {
                    const int col = cb * 16 + l16;
                    const float bc = bias[col];
 #pragma unroll
-                   for (int j = 0; j < 4; ++j) {
-                     out[(4 * kq + j) * ldo + col] = to_bf16(celu_f(a0[j] + bc, cl.alpha));
-                     out[(16 + 4 * kq + j) * ldo + col] = to_bf16(celu_f(a1[j] + bc, cl.alpha));
-                   }
+                   for (int h = 0; h < HR; ++h)
+#pragma unroll
+                     for (int j = 0; j < 4; ++j)
+                       out[(16 * h + 4 * kq + j) * ldo + col] = to_bf16(celu_f(acc[h][j] + bc, cl.alpha, k_exp));
                  });
     } else {
       // last hidden layer: h_last (bfloat16) into its tile
-      chain_gemm<W>(act[l - 1], cl.lds_ld[l - 1], K, net.W[l - 1], K, N, wave, lane,
-                 [&](int cb, floatx4_t a0, floatx4_t a1) {
+      chain_gemm<W, RT>(act[l - 1], cl.lds_ld[l - 1], K, net.W[l - 1], K, N, wave, lane,
+                 [&](int cb, const floatx4_t *acc) {
                    const int col = cb * 16 + l16;
                    const float bc = bias[col];
 #pragma unroll
-                   for (int j = 0; j < 4; ++j) {
-                     out[(4 * kq + j) * ldo + col] = to_bf16(celu_f(a0[j] + bc, cl.alpha));
-                     out[(16 + 4 * kq + j) * ldo + col] = to_bf16(celu_f(a1[j] + bc, cl.alpha));
-                   }
+                   for (int h = 0; h < HR; ++h)
+#pragma unroll
+                     for (int j = 0; j < 4; ++j)
+                       out[(16 * h + 4 * kq + j) * ldo + col] = to_bf16(celu_f(acc[h][j] + bc, cl.alpha, k_exp));
                  });
     }
     __syncthreads();
@@ -164,8 +176,10 @@ __global__ void __launch_bounds__(W * kWave) k_chain(ChainLaunch cl) {
   {
     const int N = net.width[NL], nch = N / 8, ldo = cl.lds_ld[NL];
     uint16_t *hl = act[NL];
-    if (tid < kChainRows * 8) {
-      const int row = tid >> 3, seg = tid & 7;
+    // R * 8 is a multiple of the workgroup size: every group of eight lanes
+    // takes the loop's iterations together
+    for (int t8 = tid; t8 < R * 8; t8 += W * kWave) {
+      const int row = t8 >> 3, seg = t8 & 7;
       float e = 0.f;
       for (int ch = seg; ch < nch; ch += 8) {
         uint4 u = *(const uint4 *)(hl + row * ldo + ch * 8);
@@ -178,7 +192,7 @@ __global__ void __launch_bounds__(W * kWave) k_chain(ChainLaunch cl) {
         for (int k = 0; k < 8; ++k) {
           const float h = from_bf16(hv[k]);
           e += h * wv[k];
-          hv[k] = to_bf16(wv[k] * dcelu_h(h, cl.alpha) * cl.inv_m);
+          hv[k] = to_bf16(wv[k] * dcelu_h(h, inv_alpha) * cl.inv_m);
         }
         if (GRAD) *(uint4 *)(hl + row * ldo + ch * 8) = *(const uint4 *)hv;
       }
@@ -195,16 +209,16 @@ __global__ void __launch_bounds__(W * kWave) k_chain(ChainLaunch cl) {
     const int K = net.width[l], N = net.width[l - 1];
     uint16_t *hd = act[l - 1];
     const int ldo = cl.lds_ld[l - 1];
-    chain_gemm<W>(act[l], cl.lds_ld[l], K, net.Wt[l - 1], K, N, wave, lane,
-               [&](int cb, floatx4_t a0, floatx4_t a1) {
+    chain_gemm<W, RT>(act[l], cl.lds_ld[l], K, net.Wt[l - 1], K, N, wave, lane,
+               [&](int cb, const floatx4_t *acc) {
                  const int col = cb * 16 + l16;
 #pragma unroll
-                 for (int j = 0; j < 4; ++j) {
-                   uint16_t *p0 = hd + (4 * kq + j) * ldo + col;
-                   uint16_t *p1 = hd + (16 + 4 * kq + j) * ldo + col;
-                   *p0 = to_bf16(a0[j] * dcelu_h(from_bf16(*p0), cl.alpha));
-                   *p1 = to_bf16(a1[j] * dcelu_h(from_bf16(*p1), cl.alpha));
-                 }
+                 for (int h = 0; h < HR; ++h)
+#pragma unroll
+                   for (int j = 0; j < 4; ++j) {
+                     uint16_t *p = hd + (16 * h + 4 * kq + j) * ldo + col;
+                     *p = to_bf16(acc[h][j] * dcelu_h(from_bf16(*p), inv_alpha));
+                   }
                });
     __syncthreads();
   }
@@ -213,7 +227,7 @@ __global__ void __launch_bounds__(W * kWave) k_chain(ChainLaunch cl) {
   {
     const int w0 = net.width[0], cpr = w0 / 8;
     uint16_t *dst = cl.D0 + (size_t)r0 * cl.ldd + (size_t)mb * cl.d_member_stride;
-    for (int idx = tid; idx < kChainRows * cpr; idx += blockDim.x) {
+    for (int idx = tid; idx < R * cpr; idx += blockDim.x) {
       const int row = idx / cpr, ch = idx % cpr;
       *(uint4 *)(dst + (size_t)row * cl.ldd + ch * 8) = *(const uint4 *)(act[0] + row * cl.lds_ld[0] + ch * 8);
     }
@@ -234,30 +248,38 @@ __global__ void k_chain_mean(const float *__restrict__ e_mem, int M, const int *
   e_atom[atom] = e * inv_m;
 }
 
-template <int W>
+template <int W, int RT>
 static void chain_t(const ChainLaunch &cl, int n_hidden, bool grad, unsigned blocks, size_t lds_bytes,
                     hipStream_t st) {
   blocks = xcd_grid(blocks, cl.xcd_chunk);
   if (n_hidden == 1) {
-    if (grad) k_chain<1, true, W><<<blocks, W * kWave, lds_bytes, st>>>(cl);
-    else k_chain<1, false, W><<<blocks, W * kWave, lds_bytes, st>>>(cl);
+    if (grad) k_chain<1, true, W, RT><<<blocks, W * kWave, lds_bytes, st>>>(cl);
+    else k_chain<1, false, W, RT><<<blocks, W * kWave, lds_bytes, st>>>(cl);
   } else if (n_hidden == 2) {
-    if (grad) k_chain<2, true, W><<<blocks, W * kWave, lds_bytes, st>>>(cl);
-    else k_chain<2, false, W><<<blocks, W * kWave, lds_bytes, st>>>(cl);
+    if (grad) k_chain<2, true, W, RT><<<blocks, W * kWave, lds_bytes, st>>>(cl);
+    else k_chain<2, false, W, RT><<<blocks, W * kWave, lds_bytes, st>>>(cl);
   } else {
-    if (grad) k_chain<3, true, W><<<blocks, W * kWave, lds_bytes, st>>>(cl);
-    else k_chain<3, false, W><<<blocks, W * kWave, lds_bytes, st>>>(cl);
+    if (grad) k_chain<3, true, W, RT><<<blocks, W * kWave, lds_bytes, st>>>(cl);
+    else k_chain<3, false, W, RT><<<blocks, W * kWave, lds_bytes, st>>>(cl);
   }
 }
 
-void launch_chain(ChainLaunch cl, int n_hidden, bool grad, int rows, size_t lds_bytes, int waves,
+// lds_bytes: the activation tiles of 32 rows; rt = 2 takes 64 rows per
+// workgroup (twice the LDS), rt = 1 32.  rows is a multiple of 128.
+void launch_chain(ChainLaunch cl, int n_hidden, bool grad, int rows, size_t lds_bytes, int waves, int rt,
                   hipStream_t st) {
-  const unsigned blocks = (unsigned)(rows / kChainRows * cl.n_members);
+  const int R = kChainRows * (rt == 2 ? 2 : 1);
+  const unsigned blocks = (unsigned)(rows / R * cl.n_members);
   if (blocks == 0) return;
   cl.n_blocks = (int)blocks;
-  cl.xcd_chunk = 16;   // 512 rows of one network per chunk
-  if (waves == 4) chain_t<4>(cl, n_hidden, grad, blocks, lds_bytes, st);
-  else chain_t<8>(cl, n_hidden, grad, blocks, lds_bytes, st);
+  cl.xcd_chunk = 512 / R;   // 512 rows of one network per chunk
+  if (rt == 2) {
+    if (waves == 4) chain_t<4, 2>(cl, n_hidden, grad, blocks, 2 * lds_bytes, st);
+    else chain_t<8, 2>(cl, n_hidden, grad, blocks, 2 * lds_bytes, st);
+  } else {
+    if (waves == 4) chain_t<4, 1>(cl, n_hidden, grad, blocks, lds_bytes, st);
+    else chain_t<8, 1>(cl, n_hidden, grad, blocks, lds_bytes, st);
+  }
   k_chain_mean<<<(rows + 255) / 256, 256, 0, st>>>(cl.e_mem, cl.n_members, cl.perm, cl.bucket_off, cl.n_groups,
                                                     rows, cl.inv_m, cl.e_atom);
 }

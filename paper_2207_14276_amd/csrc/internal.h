@@ -229,7 +229,9 @@ void launch_aev_bwd(const float4 *pos, const int *sys_of, const SysDesc *sys, co
 // wpb_pref below: waves per workgroup 1, 2 or 4 when the LDS fits (else the default).
 void launch_gemm(int epi, bool bf16, GemmLaunch gl, int row_tiles, int max_n_out, int tn_pref, hipStream_t st);
 void launch_energy(const EnergyLaunch &el, bool bf16, int rows, hipStream_t st);
-void launch_chain(ChainLaunch cl, int n_hidden, bool grad, int rows, size_t lds_bytes, int waves,
+// waves per workgroup 4 or 8; rt = 2: 64 rows per workgroup (2 lds_bytes of
+// LDS), else 32
+void launch_chain(ChainLaunch cl, int n_hidden, bool grad, int rows, size_t lds_bytes, int waves, int rt,
                   hipStream_t st);
 void launch_fill(float *p, size_t n, float v, hipStream_t st);
 void launch_fill_i32(int *p, size_t n, int v, hipStream_t st);

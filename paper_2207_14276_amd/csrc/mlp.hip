@@ -27,10 +27,13 @@ namespace nnp {
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
-__device__ inline uint32_t bf16_bits_rne(float f) {
-  uint32_t u = __float_as_uint(f);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return u >> 16;
+// float -> bfloat16, round to nearest even (one hardware conversion; two
+// values per instruction when packed)
+typedef __bf16 bf16x2_hw __attribute__((ext_vector_type(2)));
+typedef float floatx2_hw __attribute__((ext_vector_type(2)));
+__device__ inline uint32_t bf16_bits_rne(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
+__device__ inline uint32_t bf16x2_bits_rne(float lo, float hi) {
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector((floatx2_hw){lo, hi}, bf16x2_hw));
 }
 __device__ inline float bf16_to_f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
@@ -46,14 +49,24 @@ template <> struct Op<true> {
   static __device__ inline void store(uint16_t *p, float v) { *p = (uint16_t)bf16_bits_rne(v); }
 };
 
-__device__ inline float celu(float z, float alpha) { return z > 0.f ? z : alpha * expm1f(z / alpha); }
+// CELU(z) = z for z > 0, else alpha (exp(z / alpha) - 1); inv_alpha = 1 / alpha.
+__device__ inline float celu(float z, float alpha, float inv_alpha) {
+  return z > 0.f ? z : alpha * expm1f(z * inv_alpha);
+}
+// The same with the hardware exp2 (about 1 ulp; the absolute error near
+// z = 0 stays ~1e-7 alpha) for outputs rounded to bfloat16 next; k_exp =
+// log2(e) / alpha.
+__device__ inline float celu_bf16(float z, float alpha, float k_exp) {
+  return z > 0.f ? z : alpha * (__builtin_amdgcn_exp2f(z * k_exp) - 1.f);
+}
 
 // CELU'(z) from h = CELU(z): 1 for h > 0, else exp(z / alpha) = 1 + h / alpha.
-__device__ inline float dcelu_from_h(float h, float alpha) { return h > 0.f ? 1.f : 1.f + h / alpha; }
+__device__ inline float dcelu_from_h(float h, float inv_alpha) { return h > 0.f ? 1.f : 1.f + h * inv_alpha; }
 
 
 template <int EPI, bool BF16, int TN>
 __global__ void __launch_bounds__(256) k_gemm(GemmLaunch gl) {
+  const float inv_alpha = 1.f / gl.alpha, k_exp = 1.4426950408889634f * inv_alpha;
   typedef typename Op<BF16>::T T;
   constexpr int TM = kTileM;
   constexpr int TK = BF16 ? 32 : 16;
@@ -209,12 +222,12 @@ __global__ void __launch_bounds__(256) k_gemm(GemmLaunch gl) {
         const float v = acc[bi][bj][i];
         if (EPI == kEpiFwd) {
           T *out = (T *)gl.C + (size_t)row * gl.ldc + (size_t)mb * gl.c_member_stride + col;
-          Op<BF16>::store(out, celu(v + bias, gl.alpha));
+          Op<BF16>::store(out, BF16 ? celu_bf16(v + bias, gl.alpha, k_exp) : celu(v + bias, gl.alpha, inv_alpha));
         } else if (EPI == kEpiBwd) {
           T *out = (T *)gl.C + (size_t)row * gl.ldc + (size_t)mb * gl.c_member_stride + col;
           const float h = Op<BF16>::load((const T *)gl.H + (size_t)row * gl.ldh +
                                          (size_t)mb * gl.h_member_stride + col);
-          Op<BF16>::store(out, v * dcelu_from_h(h, gl.alpha) * gl.scale);
+          Op<BF16>::store(out, v * dcelu_from_h(h, inv_alpha) * gl.scale);
         } else {
           float *out = (float *)gl.C + (size_t)row * gl.ldc + col;
           *out = v * gl.scale;
@@ -239,10 +252,10 @@ template <> struct Vec8<true> {
   }
   static __device__ inline void store(uint16_t *p, const float v[8]) {
     uint4 u;
-    u.x = bf16_bits_rne(v[0]) | (bf16_bits_rne(v[1]) << 16);
-    u.y = bf16_bits_rne(v[2]) | (bf16_bits_rne(v[3]) << 16);
-    u.z = bf16_bits_rne(v[4]) | (bf16_bits_rne(v[5]) << 16);
-    u.w = bf16_bits_rne(v[6]) | (bf16_bits_rne(v[7]) << 16);
+    u.x = bf16x2_bits_rne(v[0], v[1]);
+    u.y = bf16x2_bits_rne(v[2], v[3]);
+    u.z = bf16x2_bits_rne(v[4], v[5]);
+    u.w = bf16x2_bits_rne(v[6], v[7]);
     *(uint4 *)p = u;
   }
 };
@@ -290,6 +303,7 @@ __device__ inline void wait_chunks(int ahead) {
 template <int EPI, int TN, bool SPAN, int STAGES>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TN == 256 ? 2 : 1)))
 k_gemm_dl(GemmLaunch gl) {
+  const float inv_alpha = 1.f / gl.alpha, k_exp = 1.4426950408889634f * inv_alpha;
   typedef uint16_t T;
   constexpr int TM = kTileM;
   constexpr int TK = 32;
@@ -451,13 +465,13 @@ k_gemm_dl(GemmLaunch gl) {
           float b[8];
           Vec8<false>::load((SPAN ? gl.g[om * gl.n_groups + s].bias : grp.bias) + col, b);
 #pragma unroll
-          for (int e = 0; e < 8; ++e) v[e] = celu(v[e] + b[e], gl.alpha);
+          for (int e = 0; e < 8; ++e) v[e] = celu_bf16(v[e] + b[e], gl.alpha, k_exp);
           Vec8<true>::store((T *)gl.C + (size_t)row * gl.ldc + (size_t)om * gl.c_member_stride + col, v);
         } else if (EPI == kEpiBwd) {
           float h[8];
           Vec8<true>::load((const T *)gl.H + (size_t)row * gl.ldh + (size_t)mb * gl.h_member_stride + col, h);
 #pragma unroll
-          for (int e = 0; e < 8; ++e) v[e] = v[e] * dcelu_from_h(h[e], gl.alpha) * gl.scale;
+          for (int e = 0; e < 8; ++e) v[e] = v[e] * dcelu_from_h(h[e], inv_alpha) * gl.scale;
           Vec8<true>::store((T *)gl.C + (size_t)row * gl.ldc + (size_t)mb * gl.c_member_stride + col, v);
         } else {
 #pragma unroll
@@ -567,6 +581,7 @@ void launch_gemm(int epi, bool bf16, GemmLaunch gl, int row_tiles, int max_n_out
 // multiples of 8, so a lane's 8 inputs never straddle a member's slice.
 template <bool BF16>
 __global__ void __launch_bounds__(256) k_energy(EnergyLaunch el, int rows) {
+  const float inv_alpha = 1.f / el.alpha;
   typedef typename Op<BF16>::T T;
   const int half = threadIdx.x >> 5, l32 = threadIdx.x & 31;
   const int row = blockIdx.x * 8 + half;
@@ -593,7 +608,7 @@ __global__ void __launch_bounds__(256) k_energy(EnergyLaunch el, int rows) {
           if (el.hidden) {
             float gv[8];
 #pragma unroll
-            for (int q = 0; q < 8; ++q) gv[q] = wv[q] * dcelu_from_h(hv[q], el.alpha) * el.inv_m;
+            for (int q = 0; q < 8; ++q) gv[q] = wv[q] * dcelu_from_h(hv[q], inv_alpha) * el.inv_m;
             Vec8<BF16>::store((T *)el.Gout + (size_t)row * el.ldg + (size_t)m * el.g_member_stride + k0, gv);
           } else {
             // no hidden layer: dE/dG = mean of w, float32
