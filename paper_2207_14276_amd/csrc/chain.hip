@@ -29,6 +29,15 @@ typedef float floatx4_t __attribute__((ext_vector_type(4)));
 // float -> bfloat16, round to nearest even (one hardware conversion)
 __device__ inline uint16_t to_bf16(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
 __device__ inline float from_bf16(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+// four floats -> four bfloat16 (round to nearest even) in 8 bytes, first value lowest
+typedef __bf16 bf16x2_c __attribute__((ext_vector_type(2)));
+typedef float floatx2_c __attribute__((ext_vector_type(2)));
+__device__ inline uint2 pack4_bf16(float a, float b, float c, float d) {
+  uint2 r;
+  r.x = __builtin_bit_cast(uint32_t, __builtin_convertvector((floatx2_c){a, b}, bf16x2_c));
+  r.y = __builtin_bit_cast(uint32_t, __builtin_convertvector((floatx2_c){c, d}, bf16x2_c));
+  return r;
+}
 // CELU with the hardware exp2 (about 1 ulp; the result is rounded to
 // bfloat16 next), k_exp = log2(e) / alpha; CELU' from h = CELU(z) with
 // inv_alpha = 1 / alpha.
@@ -47,9 +56,12 @@ __device__ inline float sum8_dpp(float v) {
 
 // C[32 RT x N] = A[32 RT x K] (LDS, bfloat16, row stride lda) . B^T with
 // B[N][K] (global, bfloat16, row stride ldb); K a multiple of 32 (<= 256), N
-// of 16.  For every 16-column block owned by this wave, epi(cb, acc) gets the
-// accumulators of the 2 RT sixteen-row groups: lane l holds column
-// 16 cb + l % 16, rows 16 h + 4 (l / 16) + j (j = 0..3) in acc[h].
+// of 16.  Each product is formed transposed (weights as the MFMA's first
+// operand), so that a lane ends with four consecutive columns of one row:
+// for every 16-column block owned by this wave, epi(cb, acc) gets, in
+// acc[h][j], row 16 h + l % 16 and column 16 cb + 4 (l / 16) + j (j = 0..3)
+// of each of the 2 RT sixteen-row groups h; the epilogues then move four
+// bfloat16 values (8 bytes) per LDS access.
 template <int W, int RT, class Epi>
 __device__ inline void chain_gemm(const uint16_t *A, int lda, int K, const uint16_t *__restrict__ B, int ldb,
                                   int N, int wave, int lane, Epi &&epi) {
@@ -89,7 +101,7 @@ __device__ inline void chain_gemm(const uint16_t *A, int lda, int K, const uint1
       if (q < nq) {
         const bf16x8_t b = __builtin_bit_cast(bf16x8_t, bc[q]);
 #pragma unroll
-        for (int h = 0; h < HR; ++h) acc[q][h] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[h], b, acc[q][h], 0, 0, 0);
+        for (int h = 0; h < HR; ++h) acc[q][h] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b, a[h], acc[q][h], 0, 0, 0);
       }
     }
 #pragma unroll
@@ -145,25 +157,25 @@ __global__ void __launch_bounds__(W * kWave) k_chain(ChainLaunch cl) {
     if (l < NL) {
       chain_gemm<W, RT>(act[l - 1], cl.lds_ld[l - 1], K, net.W[l - 1], K, N, wave, lane,
                  [&](int cb, const floatx4_t *acc) {
-                   const int col = cb * 16 + l16;
-                   const float bc = bias[col];
+                   const int col = cb * 16 + 4 * kq;
+                   const float4 bc = *(const float4 *)(bias + col);
 #pragma unroll
                    for (int h = 0; h < HR; ++h)
-#pragma unroll
-                     for (int j = 0; j < 4; ++j)
-                       out[(16 * h + 4 * kq + j) * ldo + col] = to_bf16(celu_f(acc[h][j] + bc, cl.alpha, k_exp));
+                     *(uint2 *)(out + (16 * h + l16) * ldo + col) =
+                         pack4_bf16(celu_f(acc[h][0] + bc.x, cl.alpha, k_exp), celu_f(acc[h][1] + bc.y, cl.alpha, k_exp),
+                                    celu_f(acc[h][2] + bc.z, cl.alpha, k_exp), celu_f(acc[h][3] + bc.w, cl.alpha, k_exp));
                  });
     } else {
       // last hidden layer: h_last (bfloat16) into its tile
       chain_gemm<W, RT>(act[l - 1], cl.lds_ld[l - 1], K, net.W[l - 1], K, N, wave, lane,
                  [&](int cb, const floatx4_t *acc) {
-                   const int col = cb * 16 + l16;
-                   const float bc = bias[col];
+                   const int col = cb * 16 + 4 * kq;
+                   const float4 bc = *(const float4 *)(bias + col);
 #pragma unroll
                    for (int h = 0; h < HR; ++h)
-#pragma unroll
-                     for (int j = 0; j < 4; ++j)
-                       out[(16 * h + 4 * kq + j) * ldo + col] = to_bf16(celu_f(acc[h][j] + bc, cl.alpha, k_exp));
+                     *(uint2 *)(out + (16 * h + l16) * ldo + col) =
+                         pack4_bf16(celu_f(acc[h][0] + bc.x, cl.alpha, k_exp), celu_f(acc[h][1] + bc.y, cl.alpha, k_exp),
+                                    celu_f(acc[h][2] + bc.z, cl.alpha, k_exp), celu_f(acc[h][3] + bc.w, cl.alpha, k_exp));
                  });
     }
     __syncthreads();
@@ -211,14 +223,16 @@ __global__ void __launch_bounds__(W * kWave) k_chain(ChainLaunch cl) {
     const int ldo = cl.lds_ld[l - 1];
     chain_gemm<W, RT>(act[l], cl.lds_ld[l], K, net.Wt[l - 1], K, N, wave, lane,
                [&](int cb, const floatx4_t *acc) {
-                 const int col = cb * 16 + l16;
+                 const int col = cb * 16 + 4 * kq;
 #pragma unroll
-                 for (int h = 0; h < HR; ++h)
-#pragma unroll
-                   for (int j = 0; j < 4; ++j) {
-                     uint16_t *p = hd + (16 * h + 4 * kq + j) * ldo + col;
-                     *p = to_bf16(acc[h][j] * dcelu_h(from_bf16(*p), inv_alpha));
-                   }
+                 for (int h = 0; h < HR; ++h) {
+                   uint2 *p = (uint2 *)(hd + (16 * h + l16) * ldo + col);
+                   const uint2 hv = *p;
+                   *p = pack4_bf16(acc[h][0] * dcelu_h(__uint_as_float(hv.x << 16), inv_alpha),
+                                   acc[h][1] * dcelu_h(__uint_as_float(hv.x & 0xffff0000u), inv_alpha),
+                                   acc[h][2] * dcelu_h(__uint_as_float(hv.y << 16), inv_alpha),
+                                   acc[h][3] * dcelu_h(__uint_as_float(hv.y & 0xffff0000u), inv_alpha));
+                 }
                });
     __syncthreads();
   }
