@@ -839,7 +839,7 @@ static int run(nnp_model *m, int n_sys, const int64_t *offs, const float *coords
   AtomState *pool_state = nl ? nl->state.as<AtomState>() : m->state.as<AtomState>();
   if (nl) launch_skin_check(coords, dsys, n_sys, pool_state, 0.5f * nl->skin, nl->stats.as<int>(), st);
   launch_ingest(coords, species, pin.mask, dsys, n_sys, N, m->S, pos, m->sys_of.as<int>(), pool_state,
-                status, st);
+                status, mode == kFull ? o.forces : nullptr, st);
   mark();
   // every system small and without a box: a direct scan per system
   bool all_small = !pairs && N > 0;
@@ -875,7 +875,6 @@ static int run(nnp_model *m, int n_sys, const int64_t *offs, const float *coords
   const int rows = (N + kTileM - 1) / kTileM * kTileM + m->S * kTileM;
   launch_species_bucket(pos, N, m->S, m->block_counts.as<int>(), nblk, m->bucket_off.as<int>(),
                         m->bucket_cnt.as<int>(), m->perm.as<int>(), m->row_of_atom.as<int>(), rows, st);
-  if (mode == kFull && o.forces) launch_fill(o.forces, (size_t)3 * N, 0.f, st);
   // atoms outside a caller's mask have no network: zero atomic energy
   // atomic energies go straight to the caller's buffer when one is given
   // (every atom's entry is written each call), else to the workspace

@@ -186,9 +186,10 @@ struct EnergyLaunch {
 // ---- launchers (stream-ordered, no host sync)
 void launch_skin_check(const float *coords, SysDesc *sys, int n_sys, const AtomState *state,
                        float half_skin, int *stats, hipStream_t st);
+// zero_forces (nullable): the force output, cleared here for the backward
 void launch_ingest(const float *coords, const int *species, const unsigned char *mask,
                    const SysDesc *sys, int n_sys, int N, int S, float4 *pos, int *sys_of,
-                   AtomState *state, int *status, hipStream_t st);
+                   AtomState *state, int *status, float *zero_forces, hipStream_t st);
 constexpr int kSmallSystem = 512;   // largest non-periodic system of the small-system search
 void launch_nbr_small(const float4 *pos, const int *sys_of, const SysDesc *sys, int N, float rc_list,
                       int cap, int2 *nbr, int *nbr_cnt, int *status, hipStream_t st);

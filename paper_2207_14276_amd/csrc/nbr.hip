@@ -14,9 +14,16 @@ __global__ void k_ingest(const float *__restrict__ coords, const int *__restrict
                          const unsigned char *__restrict__ mask,
                          const SysDesc *__restrict__ sys, int n_sys, int N, int S,
                          float4 *__restrict__ pos, int *__restrict__ sys_of,
-                         AtomState *__restrict__ state, int *__restrict__ status) {
+                         AtomState *__restrict__ state, int *__restrict__ status,
+                         float *__restrict__ zero_forces) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= N) return;
+  // the force output starts from zero (the backward accumulates into it)
+  if (zero_forces) {
+    zero_forces[3 * (size_t)i] = 0.f;
+    zero_forces[3 * (size_t)i + 1] = 0.f;
+    zero_forces[3 * (size_t)i + 2] = 0.f;
+  }
   // system of atom i: last s with atom_off <= i (binary search)
   int lo = 0, hi = n_sys - 1;
   while (lo < hi) {
@@ -62,10 +69,10 @@ __global__ void k_ingest(const float *__restrict__ coords, const int *__restrict
 
 void launch_ingest(const float *coords, const int *species, const unsigned char *mask,
                    const SysDesc *sys, int n_sys, int N, int S, float4 *pos, int *sys_of,
-                   AtomState *state, int *status, hipStream_t st) {
+                   AtomState *state, int *status, float *zero_forces, hipStream_t st) {
   if (N <= 0) return;
   k_ingest<<<(N + 255) / 256, 256, 0, st>>>(coords, species, mask, sys, n_sys, N, S, pos, sys_of,
-                                            state, status);
+                                            state, status, zero_forces);
 }
 
 // One wave per system: a system that keeps its neighbour list is rebuilt
