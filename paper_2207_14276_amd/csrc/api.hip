@@ -770,6 +770,8 @@ static int run(nnp_model *m, int n_sys, const int64_t *offs, const float *coords
     }
   }
   sys_ch[n_sys] = (int)ch_sys.size();
+  bool one_chunk_each = true;
+  for (int s = 0; s < n_sys && one_chunk_each; ++s) one_chunk_each = sys_ch[s + 1] - sys_ch[s] == 1;
   const int n_chunks = (int)ch_sys.size();
   if (C > ((int64_t)1 << 28)) return fail(NNP_EUNSUPPORTED, "too many cells");
   int rc = ensure_ws(m, N, n_sys, C, n_chunks, nl != nullptr);
@@ -1059,7 +1061,7 @@ static int run(nnp_model *m, int n_sys, const int64_t *offs, const float *coords
   }
   mark();
   launch_reduce(e_atom, want_grad ? m->W_atom.as<float>() : nullptr, dsys, n_sys,
-                d_chunk_sys, d_chunk_begin, n_chunks, d_sys_chunk_off,
+                d_chunk_sys, d_chunk_begin, n_chunks, d_sys_chunk_off, one_chunk_each,
                 m->partial.as<double>(), o.energy, o.virial, st);
   mark();
   if (ev) m->last_stages = stage - 1;

@@ -209,7 +209,15 @@ __global__ void __launch_bounds__(W * kWave) k_chain(ChainLaunch cl) {
         if (GRAD) *(uint4 *)(hl + row * ldo + ch * 8) = *(const uint4 *)hv;
       }
       e = sum8_dpp(e);
-      if (seg == 0) cl.e_mem[(size_t)(r0 + row) * cl.n_members + mb] = e + net.b_out;
+      if (seg == 0) {
+        if (cl.n_members == 1) {
+          // a single network: the row's energy is the atomic energy
+          const int atom = cl.perm[r0 + row];
+          if (atom >= 0) cl.e_atom[atom] = e + net.b_out;
+        } else {
+          cl.e_mem[(size_t)(r0 + row) * cl.n_members + mb] = e + net.b_out;
+        }
+      }
     }
     __syncthreads();
   }
@@ -294,8 +302,9 @@ void launch_chain(ChainLaunch cl, int n_hidden, bool grad, int rows, size_t lds_
     if (waves == 4) chain_t<4, 1>(cl, n_hidden, grad, blocks, lds_bytes, st);
     else chain_t<8, 1>(cl, n_hidden, grad, blocks, lds_bytes, st);
   }
-  k_chain_mean<<<(rows + 255) / 256, 256, 0, st>>>(cl.e_mem, cl.n_members, cl.perm, cl.bucket_off, cl.n_groups,
-                                                    rows, cl.inv_m, cl.e_atom);
+  if (cl.n_members > 1)
+    k_chain_mean<<<(rows + 255) / 256, 256, 0, st>>>(cl.e_mem, cl.n_members, cl.perm, cl.bucket_off, cl.n_groups,
+                                                      rows, cl.inv_m, cl.e_atom);
 }
 
 }  // namespace nnp

@@ -238,7 +238,7 @@ void launch_fill(float *p, size_t n, float v, hipStream_t st);
 void launch_fill_i32(int *p, size_t n, int v, hipStream_t st);
 void launch_reduce(const float *e_atom, const float *W_atom, const SysDesc *sys, int n_sys,
                    const int *chunk_sys, const int *chunk_begin, int n_chunks,
-                   const int *sys_chunk_off, double *partial, double *energy, double *virial,
+                   const int *sys_chunk_off, bool one_chunk_each, double *partial, double *energy, double *virial,
                    hipStream_t st);
 void launch_gather_rows(const float *src, int ld, const int *row_of_atom, int N, int D,
                         float *dst, hipStream_t st);

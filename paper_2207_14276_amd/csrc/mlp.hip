@@ -641,7 +641,8 @@ constexpr int kChunk = 4096;
 __global__ void __launch_bounds__(256)
 k_reduce_partial(const float *__restrict__ e_atom, const float *__restrict__ W_atom,
                  const SysDesc *__restrict__ sys, const int *__restrict__ chunk_sys,
-                 const int *__restrict__ chunk_begin, double *__restrict__ partial) {
+                 const int *__restrict__ chunk_begin, double *__restrict__ partial,
+                 double *__restrict__ energy, double *__restrict__ virial) {
   __shared__ double red[10][256 / kWave];
   const int ch = blockIdx.x;
   const SysDesc &d = sys[chunk_sys[ch]];
@@ -664,7 +665,13 @@ k_reduce_partial(const float *__restrict__ e_atom, const float *__restrict__ W_a
   if (threadIdx.x < 10) {
     double v = 0.0;
     for (int w = 0; w < 256 / kWave; ++w) v += red[threadIdx.x][w];
-    partial[(size_t)10 * ch + threadIdx.x] = v;
+    if (energy) {
+      // one chunk per system (chunk ch is system ch): the sums are final
+      if (threadIdx.x == 0) energy[ch] = v;
+      else if (virial) virial[(size_t)9 * ch + threadIdx.x - 1] = v;
+    } else {
+      partial[(size_t)10 * ch + threadIdx.x] = v;
+    }
   }
 }
 
@@ -683,11 +690,15 @@ __global__ void k_reduce_final(const double *__restrict__ partial, const int *__
 
 void launch_reduce(const float *e_atom, const float *W_atom, const SysDesc *sys, int n_sys,
                    const int *chunk_sys, const int *chunk_begin, int n_chunks,
-                   const int *sys_chunk_off, double *partial, double *energy, double *virial,
-                   hipStream_t st) {
+                   const int *sys_chunk_off, bool one_chunk_each, double *partial, double *energy,
+                   double *virial, hipStream_t st) {
+  const bool direct = one_chunk_each && n_chunks == n_sys;
+  // every system exactly one chunk (chunk s is system s): the chunk sums are
+  // the system sums, no second pass
   if (n_chunks > 0)
-    k_reduce_partial<<<n_chunks, 256, 0, st>>>(e_atom, W_atom, sys, chunk_sys, chunk_begin, partial);
-  if (n_sys > 0)
+    k_reduce_partial<<<n_chunks, 256, 0, st>>>(e_atom, W_atom, sys, chunk_sys, chunk_begin, partial,
+                                               direct ? energy : nullptr, direct ? virial : nullptr);
+  if (n_sys > 0 && !direct)
     k_reduce_final<<<(n_sys + 127) / 128, 128, 0, st>>>(partial, sys_chunk_off, n_sys, energy, virial);
 }
 
