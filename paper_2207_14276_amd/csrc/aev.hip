@@ -766,13 +766,10 @@ void launch_aev_bwd(const float4 *pos, const int *sys_of, const SysDesc *sys, co
                     int N, const AevConst &c, float *F, float *W_atom, int wpb_pref, hipStream_t st) {
   if (N <= 0) return;
   const int wpb = waves_for_cap<true>(cap, wpb_pref);
-  // waves per SIMD the LDS allows (160 KB per compute unit, 4 SIMDs)
-  const size_t per_wg = wave_lds_bytes<true>(cap) * wpb;
-  const int lds_waves = (int)(160 * 1024 / per_wg) * wpb / 4;
-  if (lds_waves >= 6)
-    aev_bwd_t<6>(pos, sys_of, sys, nbr, nbr_cnt, cap, row_of_atom, dG, ldg, N, c, F, W_atom, wpb, st);
-  else
-    aev_bwd_t<0>(pos, sys_of, sys, nbr, nbr_cnt, cap, row_of_atom, dG, ldg, N, c, F, W_atom, wpb, st);
+  // no register bound: holding the kernel to 6 waves per SIMD (where the
+  // LDS allows 6) spilled and was 3% slower on the 100k-atom box than the
+  // unbounded allocation
+  aev_bwd_t<0>(pos, sys_of, sys, nbr, nbr_cnt, cap, row_of_atom, dG, ldg, N, c, F, W_atom, wpb, st);
 }
 
 }  // namespace nnp
