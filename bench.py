@@ -6,7 +6,9 @@ dense layers in bfloat16 (float32 accumulate).  Beside it the same batch is
 run the plain way: float32 dense layers, one system per call, sequentially
 on one stream.  One atom-eval = energy + forces of one atom.
 
-Prints one JSON line (see the measurement section of the design doc).
+Prints one JSON line: the metric, its value and unit, the timed steps, the
+per-stage times, the dominant kernel's roofline and the oracle's CPU
+baseline.
 """
 from __future__ import annotations
 
@@ -149,8 +151,9 @@ def model_cap(model):
 #                 per radial shift: Rbar - Rs, square, * eta, exp 4 = 7, x4 = 28;
 #                 fc_j fc_k 1; per (a, r) product and accumulate 2, x32 = 64
 #                                                               -> 230
-# The backward pass differentiates the same terms: radial 2x, triplet ~2.2x
-# (see the design doc), i.e. 324 and 510.
+# The backward pass differentiates the same terms: radial 2x (dE/dR of each
+# shift's Gaussian and cutoff), triplet ~2.2x (derivatives through cos, sin,
+# R_j, R_k and the cutoff product), i.e. 324 and 510.
 FLOP_RADIAL_FWD = 162
 FLOP_TRIPLET_FWD = 230
 FLOP_RADIAL_BWD = 324
@@ -615,8 +618,8 @@ def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this benchmark runs on one GPU only; the energy/force path "
-                          "is not sharded across GPUs in this build (see DESIGN.md)",
+        print(json.dumps({"error": "this benchmark runs on one GPU only: the energy/force path "
+                          "is not sharded across GPUs",
                           "n_gpus": args.gpus}))
         sys.exit(2)
 
