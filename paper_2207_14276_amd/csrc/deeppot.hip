@@ -14,9 +14,11 @@
 // float32 neighbour vector of the packed atom records, as the AEV kernels do.
 //
 // Forward, one wavefront per centre:
-//   1. lane per list entry: float64 R^2, per-species counts by ballot;
-//   2. again lane per entry: placement into per-species buckets in LDS
-//      (key, tie, float32 vector, atom index);
+//   1. lane per list entry: per-species counts of the list by ballot (the
+//      buckets' capacities);
+//   2. again lane per entry: the float64 R^2 and cutoff test, placement of
+//      the entries inside the cutoff into per-species buckets in LDS (key,
+//      tie, float32 vector, atom index);
 //   3. per species bucket, lane per entry: rank = number of bucket entries
 //      ahead of it (O(n_s^2 / 64) per lane, all lanes reading the same LDS
 //      word at a time); ranks below sel[s] claim a slot; ranks 0 and 1 are
@@ -200,15 +202,20 @@ k_dp_fwd(const float4 *__restrict__ pos, const float *__restrict__ coords,
     wi[0] = (int)w.x; wi[1] = (int)w.y; wi[2] = (int)w.z;
   }
 
-  // 1. valid entries per species
+  // 1. list entries per species: bucket capacities (the cutoff test in step 2
+  //    may drop some; buckets then keep unused space at their ends)
   int cnt[kMaxSpecies];
 #pragma unroll
   for (int s = 0; s < kMaxSpecies; ++s) cnt[s] = 0;
   for (int b = 0; b < n; b += kWave) {
-    const Entry x = read_entry(b + lane, n, row, j0, n_sys, pos, coords, state, d.state_off, wrapped, wi,
-                               ci, Ld, c.rc2);
+    const int e = b + lane;
+    int sj = -1;
+    if (e < n) {
+      const int2 en = row[e];
+      if ((unsigned)en.x < (unsigned)n_sys) sj = __float_as_int(pos[j0 + en.x].w);
+    }
 #pragma unroll
-    for (int s = 0; s < kMaxSpecies; ++s) cnt[s] += __popcll(__ballot(x.valid && x.sj == s));
+    for (int s = 0; s < kMaxSpecies; ++s) cnt[s] += __popcll(__ballot(sj == s));
   }
   int off[kMaxSpecies];
   {
@@ -248,6 +255,8 @@ k_dp_fwd(const float4 *__restrict__ pos, const float *__restrict__ coords,
         bj[at] = j0 + x.en.x;
       }
     }
+#pragma unroll
+    for (int s = 0; s < kMaxSpecies; ++s) cnt[s] = run[s];   // the entries inside the cutoff
   }
   wave_lds_sync();
 
