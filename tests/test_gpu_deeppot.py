@@ -267,3 +267,21 @@ def test_cell_grid_backward_sampled(m32, oracle_lib, om):
     log(f"[dp cells] L={s.box[0]:.2f} N={s.n} max|dE_i|={de:.3e} max|dF|={df:.3e}")
     assert de <= FP32_E_ATOM
     assert df <= FP32_F
+
+
+def test_served_through_the_native_server(m32, oracle_lib, om):
+    """The DeepPot model behind the continuous-batching server: every
+    request's last step matches the oracle at the coordinates evaluated."""
+    from tests.test_gpu_serving import _requests, _run
+    reqs = _requests(6, seed=7, nmin=20, nmax=200, steps=4)
+    rep, _ = _run(m32, reqs, spacing=0.001)
+    assert len(rep.results) == 6
+    worst_e = worst_f = 0.0
+    for rid in range(6):
+        res, r = rep.results[rid], reqs[rid]
+        E, _, F, _ = oracle_lib.energy_forces(res.coords, r.species, r.box, om, virial=False)
+        worst_e = max(worst_e, abs(float(res.energies[-1]) - E) / r.n_atoms)
+        worst_f = max(worst_f, float(np.abs(res.forces - F).max()))
+    log(f"[dp served] max|dE|/N={worst_e:.3e} max|dF|={worst_f:.3e}")
+    assert worst_e <= FP32_E_ATOM
+    assert worst_f <= FP32_F
