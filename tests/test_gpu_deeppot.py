@@ -285,3 +285,12 @@ def test_served_through_the_native_server(m32, oracle_lib, om):
     log(f"[dp served] max|dE|/N={worst_e:.3e} max|dF|={worst_f:.3e}")
     assert worst_e <= FP32_E_ATOM
     assert worst_f <= FP32_F
+
+
+def test_large_non_periodic_system(m32, oracle_lib, om):
+    """A 1,200-atom non-periodic solute: a bounding-box cell grid (hundreds
+    of reserved cells, few of them filled) through the per-cell backward."""
+    rng = np.random.default_rng(13)
+    s = synth.random_solute(rng, 1200, (1200 / 0.1) ** (1 / 3), synth.CONFIG2_PROBS)
+    b = synth.make_batch([s])
+    _check(m32, oracle_lib, om, b, [0], FP32_E_ATOM, FP32_E_ATOM, FP32_F, "fp32 solute1200")
