@@ -6,15 +6,19 @@
 // LDS with wave ballots.  Then
 //   radial:  lanes = 16 radial shifts x 4 neighbour slots, one species block
 //            at a time, reduced across the 4 slots with lane shuffles;
-//   angular (forward): one species-pair block at a time, in passes of 64
-//            neighbour pairs:
-//            (A) lane per pair: the pair geometry (cos and sin of the angle,
-//                cutoff product, the 4 radial Gaussians of the mean distance)
-//                is computed once and staged in a per-wave LDS scratch;
-//            (B) lanes = 8 angle shifts x 8 pairs: each lane evaluates the
-//                cosine power of its angle shift for a pair and accumulates
-//                the 4 radial-shift products; accumulators are reduced across
-//                the 8 pairs at the end of the block.
+//   angular (forward): the species-pair blocks in passes of 64 pair slots;
+//            a pass holds a 64-pair piece of a large block, or the rest of
+//            one block followed by whole smaller blocks, each padded to a
+//            multiple of 8 slots:
+//            (A) lane per slot: the pair geometry (cos and sin of the angle,
+//                the 4 radial Gaussians of the mean distance times the
+//                cutoff product) is computed once and staged in a per-wave
+//                LDS scratch;
+//            (B) lanes = 8 angle shifts x 8 slots, block by block: each lane
+//                evaluates the cosine power of its angle shift for a pair
+//                and accumulates the 4 radial-shift products; accumulators
+//                are reduced across the 8 slots once a block's last pair is
+//                done.
 //            Blocks without a pair are written as zeros directly.
 //   angular (backward): the pairs of all species-pair blocks form one
 //            stream, one pair per lane; a lane evaluates all 8 angle shifts
@@ -97,10 +101,11 @@ constexpr size_t kBlkTableBytes = (sizeof(PairBlock) * (kMaxBlocks + 1) + 15) / 
 
 struct WaveLds {
   Lists *ls;       // per-species counts and offsets (wave-uniform)
-  float4 *tGeo;    // pair scratch: cos, sin, fc_j fc_k, -      (forward)
-  float4 *tF2;     // pair scratch: radial Gaussians of Rbar     (forward)
+  float2 *tGeo;    // pair scratch: cos, sin                      (forward)
+  float4 *tF2;     // pair scratch: radial Gaussians of Rbar times
+                   // fc_j fc_k                                     (forward)
   PairBlock *blk;  // [kMaxBlocks + 1] pair-block table           (backward)
-  float4 *rD;      // radial: d vector and R
+  float4 *rD;      // radial: d vector and R (forward: d / R and R)
   float *rFc;      // radial: fc_rad(R)          (forward)
   float2 *rF2;     // fc(R) and fc'(R): radial cutoff, then (angular entries)
                    // the angular cutoff once the radial stage is done (backward)
@@ -119,7 +124,7 @@ struct WaveLds {
 template <bool BWD>
 __host__ __device__ inline size_t wave_lds_bytes(int cap) {
   return sizeof(Lists) + (BWD ? kBlkTableBytes + (size_t)cap * (16 + 24 + 4 + 4 + 4 + 4)
-                              : (size_t)kPairPass * 16 * 2 +
+                              : (size_t)kPairPass * (8 + 16) +
                                     (size_t)cap * (16 + 4 + 4 + 4));
 }
 
@@ -136,7 +141,7 @@ __device__ inline WaveLds carve(char *base, int cap) {
     w.rJ = (int *)p; p += (size_t)cap * 4;
     w.aIdx = (int *)p; p += (size_t)cap * 4;
   } else {
-    w.tGeo = (float4 *)p; p += (size_t)kPairPass * 16;
+    w.tGeo = (float2 *)p; p += (size_t)kPairPass * 8;
     w.tF2 = (float4 *)p; p += (size_t)kPairPass * 16;
     w.rD = (float4 *)p; p += (size_t)cap * 16;
     w.rFc = (float *)p; p += (size_t)cap * 4;
@@ -174,12 +179,16 @@ __device__ inline int build_blocks(int lane, const Lists &ls, int S, WaveLds &w,
 // Two species: q < n2 and every (x, y) occurs exactly once.
 // No branch depends on the block, so lanes of one pass in different blocks
 // do not diverge.
-__device__ inline void unrank(int u, const PairBlock &b, int &ax, int &ay) {
+__device__ inline void unrank(int u, int n1, int n2, float r1, float r2, int same, int ox, int oy,
+                              int &ax, int &ay) {
   int x, y;
-  const int q = fdivmod(u, b.n1, b.r1, x);
-  fdivmod(x + q + b.same, b.n2, b.r2, y);
-  ax = b.ox + x;
-  ay = b.oy + y;
+  const int q = fdivmod(u, n1, r1, x);
+  fdivmod(x + q + same, n2, r2, y);
+  ax = ox + x;
+  ay = oy + y;
+}
+__device__ inline void unrank(int u, const PairBlock &b, int &ax, int &ay) {
+  unrank(u, b.n1, b.n2, b.r1, b.r2, b.same, b.ox, b.oy, ax, ay);
 }
 
 // Pair t of the stream -> its block (searched from the wave-uniform block
@@ -278,8 +287,14 @@ __device__ inline void fill_lists(int lane, int n, const int2 *__restrict__ ent,
     if (inR) {
       float sn, cs;
       __sincosf(kr * d.w, &sn, &cs);
-      w.rD[q] = d;
-      if (!BWD) w.rFc[q] = 0.5f * cs + 0.5f;
+      if (BWD) {
+        w.rD[q] = d;
+      } else {
+        // the forward's pair geometry needs only the direction
+        const float ir = fast_rcp(d.w);
+        w.rD[q] = make_float4(d.x * ir, d.y * ir, d.z * ir, d.w);
+        w.rFc[q] = 0.5f * cs + 0.5f;
+      }
       if (BWD) {
         w.rF2[q] = make_float2(0.5f * cs + 0.5f, -0.5f * kr * sn);
         w.rJ[q] = j;
@@ -392,93 +407,157 @@ k_aev_fwd(const float4 *__restrict__ pos, const int *__restrict__ sys_of,
   // angular: G[rad_len + 32 p + 8 r + a] = sum over pairs {j, k} of
   //   2^(1-zeta) (1 + cos(theta - theta_a))^zeta exp(-eta (Rbar - Rs_r)^2) fc_j fc_k
   {
-    const int a = lane >> 3, t0 = lane & 7;  // 8 angle shifts x 8 pairs (pair fastest)
+    const int a = lane >> 3, t0 = lane & 7;  // phase B: 8 angle shifts x 8 pairs (pair fastest)
     const float cza = pick(c.cz, a), sza = pick(c.sz, a);
     const float pre = 1.0f - c.zeta;
     const float keta = -c.eta_a * 1.4426950408889634f;
+    // Lane b (< number of species pairs) describes species-pair block b, in
+    // the upper-triangle order of (sa, sb) that is also the feature order:
+    // its pair count and the unrank parameters of its two lists.
+    const int n_blk = c.S * (c.S + 1) / 2;
+    int bT = 0, bOxy = 0, bN12 = 0;
+    float bR1 = 1.f, bR2 = 1.f;
+    if (lane < n_blk) {
+      int sa = 0, rem = lane;
+#pragma unroll
+      for (int s = 0; s < kMaxSpecies - 1; ++s)
+        if (sa == s && rem >= c.S - s) { rem -= c.S - s; sa = s + 1; }
+      const int sb = sa + rem;
+      const int na = ls.cA[sa], nb = ls.cA[sb], oa = ls.oA[sa], ob = ls.oA[sb];
+      const bool same = sa == sb;
+      bT = same ? na * (na - 1) / 2 : na * nb;
+      const bool a_long = na >= nb;
+      const int n1 = max(na, nb), n2 = min(na, nb);
+      bOxy = (a_long ? oa : ob) | ((a_long ? ob : oa) << 16);
+      bN12 = n1 | (n2 << 16) | (same ? (int)0x80000000u : 0);
+      bR1 = fast_rcp((float)max(n1, 1));
+      bR2 = fast_rcp((float)max(n2, 1));
+    }
+    const unsigned long long nonempty = __ballot(bT > 0);
     // blocks without a pair of their two species are zero: written in one
     // pass of 16-byte stores over the angular part of the row
     {
-      unsigned long long nonempty = 0;  // up to 36 blocks
-      int q = 0;
-      for (int sa = 0; sa < c.S; ++sa)
-        for (int sb = sa; sb < c.S; ++sb, ++q) {
-          const int na = ls.cA[sa], nb = ls.cA[sb];
-          if ((sa == sb ? na * (na - 1) / 2 : na * nb) > 0) nonempty |= 1ull << q;
-        }
       constexpr int kChunksPerBlock = kAngBlock * (BF16 ? 2 : 4) / 16;
       uint4 *ang = (uint4 *)((char *)Grow + (size_t)c.rad_len * (BF16 ? 2 : 4));
-      for (int k = lane; k < q * kChunksPerBlock; k += kWave)
+      for (int k = lane; k < n_blk * kChunksPerBlock; k += kWave)
         if (!((nonempty >> (k / kChunksPerBlock)) & 1ull)) ang[k] = make_uint4(0u, 0u, 0u, 0u);
     }
-    int p = 0;
-    for (int sa = 0; sa < c.S; ++sa) {
-      for (int sb = sa; sb < c.S; ++sb, ++p) {
-        const int na = ls.cA[sa], nb = ls.cA[sb];
-        const int T = sa == sb ? na * (na - 1) / 2 : na * nb;
-        if (T == 0) continue;
-        const PairBlock blk = make_block(0, p, ls.oA[sa], ls.oA[sb], na, nb, sa == sb);
-        float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f, acc3 = 0.f;
-        for (int base = 0; base < T; base += kPairPass) {
-          // (A) lane per pair
-          {
-            const int t = base + lane;
-            const bool valid = t < T;
-            const int tt = valid ? t : T - 1;
-            int qj, qk;
-            unrank(tt, blk, qj, qk);
-            const float4 dj = w.rD[w.aIdx[qj]], dk = w.rD[w.aIdx[qk]];
-            const float dot = dj.x * dk.x + dj.y * dk.y + dj.z * dk.z;
-            const float cx = dj.y * dk.z - dj.z * dk.y;
-            const float cy = dj.z * dk.x - dj.x * dk.z;
-            const float cz = dj.x * dk.y - dj.y * dk.x;
-            const float cr = fast_sqrt(cx * cx + cy * cy + cz * cz);
-            const float inv = fast_rcp(dj.w * dk.w);
-            const float fcc = valid ? w.aFc[qj] * w.aFc[qk] : 0.f;
-            const float Rbar = 0.5f * (dj.w + dk.w);
-            const float u0 = Rbar - c.shf_a[0], u1 = Rbar - c.shf_a[1];
-            const float u2 = Rbar - c.shf_a[2], u3 = Rbar - c.shf_a[3];
-            w.tGeo[lane] = make_float4(dot * inv, cr * inv, fcc, 0.f);
-            w.tF2[lane] = make_float4(fast_exp2(keta * u0 * u0), fast_exp2(keta * u1 * u1),
-                                      fast_exp2(keta * u2 * u2), fast_exp2(keta * u3 * u3));
+    // Passes of 64 pair slots.  A block with more than 64 pairs left fills
+    // a pass on its own; otherwise the pass takes the rest of the block and
+    // then whole following blocks while they fit, each padded to a multiple
+    // of 8 slots, so that every group of 8 slots belongs to one block.
+    float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f, acc3 = 0.f;
+    unsigned long long pending = nonempty;
+    int u = 0;  // pairs of the first pending block done by earlier passes
+    while (pending) {
+      const int q = __builtin_ctzll(pending);
+      const int Tq = __builtin_amdgcn_readlane(bT, q);
+      // this lane's slot: block fields, pair index within the block, count
+      int l_oxy = __builtin_amdgcn_readlane(bOxy, q);
+      int l_n12 = __builtin_amdgcn_readlane(bN12, q);
+      float l_r1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(bR1), q));
+      float l_r2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(bR2), q));
+      int l_u = u + lane, l_T = Tq;
+      unsigned long long in_pass = 1ull << q;
+      const bool finish = Tq - u <= kPairPass;
+      int used = kPairPass;  // slots taken by the pass's blocks
+      if (finish) {
+        used = (Tq - u + 7) & ~7;
+        unsigned long long rest = pending & (pending - 1);
+        while (rest) {
+          const int q2 = __builtin_ctzll(rest);
+          const int T2 = __builtin_amdgcn_readlane(bT, q2);
+          const int g2 = (T2 + 7) & ~7;
+          if (used + g2 > kPairPass) break;
+          if (lane >= used) {
+            l_oxy = __builtin_amdgcn_readlane(bOxy, q2);
+            l_n12 = __builtin_amdgcn_readlane(bN12, q2);
+            l_r1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(bR1), q2));
+            l_r2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(bR2), q2));
+            l_u = lane - used;
+            l_T = T2;
           }
-          wave_lds_sync();
-          // (B) lanes = 8 angle shifts x 8 pairs.  Slots past the last pair
-          // hold a zero cutoff product (phase A), so they add nothing and need
-          // no test; groups of 8 pairs are taken two at a time.
-          const int groups = (min(kPairPass, T - base) + 7) >> 3;
-          int g8 = 0;
-          for (; g8 + 2 <= groups; g8 += 2) {
-            const int q0 = 8 * g8 + t0, q1 = q0 + 8;
-            const float4 geo0 = w.tGeo[q0], geo1 = w.tGeo[q1];
+          used += g2;
+          in_pass |= 1ull << q2;
+          rest &= rest - 1;
+        }
+      }
+      // (A) lane per pair slot; padding slots (and slots past the pass's
+      // blocks) repeat a valid pair with a zero cutoff product
+      {
+        const bool valid = lane < used && l_u < l_T;
+        const int tt = min(l_u, l_T - 1);
+        int qj, qk;
+        unrank(tt, l_n12 & 0xffff, (l_n12 >> 16) & 0x7fff, l_r1, l_r2, (l_n12 >> 31) & 1,
+               l_oxy & 0xffff, (l_oxy >> 16) & 0xffff, qj, qk);
+        const float4 dj = w.rD[w.aIdx[qj]], dk = w.rD[w.aIdx[qk]];  // unit vectors, R
+        const float cosv = dj.x * dk.x + dj.y * dk.y + dj.z * dk.z;
+        const float cx = dj.y * dk.z - dj.z * dk.y;
+        const float cy = dj.z * dk.x - dj.x * dk.z;
+        const float cz = dj.x * dk.y - dj.y * dk.x;
+        const float sinv = fast_sqrt(cx * cx + cy * cy + cz * cz);
+        const float fcc = valid ? w.aFc[qj] * w.aFc[qk] : 0.f;
+        const float Rbar = 0.5f * (dj.w + dk.w);
+        const float u0 = Rbar - c.shf_a[0], u1 = Rbar - c.shf_a[1];
+        const float u2 = Rbar - c.shf_a[2], u3 = Rbar - c.shf_a[3];
+        w.tGeo[lane] = make_float2(cosv, sinv);
+        w.tF2[lane] = make_float4(fcc * fast_exp2(keta * u0 * u0), fcc * fast_exp2(keta * u1 * u1),
+                                  fcc * fast_exp2(keta * u2 * u2), fcc * fast_exp2(keta * u3 * u3));
+      }
+      wave_lds_sync();
+      // (B) per block of the pass, its groups of 8 slots two at a time; a
+      // block's accumulators are reduced across the 8 pairs and stored once
+      // its last pair is done
+      {
+        int g = 0;  // first group of the block in the pass
+        unsigned long long blocks = in_pass;
+        while (blocks) {
+          const int k = __builtin_ctzll(blocks);
+          blocks &= blocks - 1;
+          const int Tk = __builtin_amdgcn_readlane(bT, k);
+          const int ng = k == q ? (finish ? (Tq - u + 7) >> 3 : kPairPass / 8) : (Tk + 7) >> 3;
+          const int gend = g + ng;
+          for (; g + 2 <= gend; g += 2) {
+            const int q0 = 8 * g + t0, q1 = q0 + 8;
+            const float2 geo0 = w.tGeo[q0], geo1 = w.tGeo[q1];
             const float4 f20 = w.tF2[q0], f21 = w.tF2[q1];
             const float x0 = fmaxf(1.0f + geo0.x * cza + geo0.y * sza, 0.f);
             const float x1 = fmaxf(1.0f + geo1.x * cza + geo1.y * sza, 0.f);
-            const float v0 = fast_exp2(c.zeta * fast_log2(x0) + pre) * geo0.z;
-            const float v1 = fast_exp2(c.zeta * fast_log2(x1) + pre) * geo1.z;
+            const float v0 = fast_exp2(c.zeta * fast_log2(x0) + pre);
+            const float v1 = fast_exp2(c.zeta * fast_log2(x1) + pre);
             acc0 += v0 * f20.x; acc0 += v1 * f21.x;
             acc1 += v0 * f20.y; acc1 += v1 * f21.y;
             acc2 += v0 * f20.z; acc2 += v1 * f21.z;
             acc3 += v0 * f20.w; acc3 += v1 * f21.w;
           }
-          if (g8 < groups) {
-            const int q = 8 * g8 + t0;
-            const float4 geo = w.tGeo[q];
-            const float4 f2 = w.tF2[q];
+          if (g < gend) {
+            const int q0 = 8 * g + t0;
+            const float2 geo = w.tGeo[q0];
+            const float4 f2 = w.tF2[q0];
             const float x = fmaxf(1.0f + geo.x * cza + geo.y * sza, 0.f);
-            const float v = fast_exp2(c.zeta * fast_log2(x) + pre) * geo.z;
+            const float v = fast_exp2(c.zeta * fast_log2(x) + pre);
             acc0 += v * f2.x; acc1 += v * f2.y; acc2 += v * f2.z; acc3 += v * f2.w;
+            ++g;
           }
-          wave_lds_sync();
+          if (k != q || finish) {
+            acc0 = sum8(acc0);
+            acc1 = sum8(acc1);
+            acc2 = sum8(acc2);
+            acc3 = sum8(acc3);
+            // feature [r][a] of block k from lane (a, t0 = r)
+            if (t0 < kNShfAng)
+              store1<BF16>(Grow, c.rad_len + k * kAngBlock + kNShfZ * t0 + a,
+                           t0 == 0 ? acc0 : t0 == 1 ? acc1 : t0 == 2 ? acc2 : acc3);
+            acc0 = acc1 = acc2 = acc3 = 0.f;
+          }
         }
-        acc0 = sum8(acc0);
-        acc1 = sum8(acc1);
-        acc2 = sum8(acc2);
-        acc3 = sum8(acc3);
-        // feature [r][a] of the block from lane (a, t0 = r)
-        if (t0 < kNShfAng)
-          store1<BF16>(Grow, c.rad_len + p * kAngBlock + kNShfZ * t0 + a,
-                       t0 == 0 ? acc0 : t0 == 1 ? acc1 : t0 == 2 ? acc2 : acc3);
+      }
+      wave_lds_sync();
+      if (finish) {
+        pending &= ~in_pass;
+        u = 0;
+      } else {
+        u += kPairPass;
       }
     }
   }
