@@ -540,14 +540,20 @@ k_aev_fwd(const float4 *__restrict__ pos, const int *__restrict__ sys_of,
             ++g;
           }
           if (k != q || finish) {
-            acc0 = sum8(acc0);
-            acc1 = sum8(acc1);
-            acc2 = sum8(acc2);
-            acc3 = sum8(acc3);
-            // feature [r][a] of block k from lane (a, t0 = r)
-            if (t0 < kNShfAng)
-              store1<BF16>(Grow, c.rad_len + k * kAngBlock + kNShfZ * t0 + a,
-                           t0 == 0 ? acc0 : t0 == 1 ? acc1 : t0 == 2 ? acc2 : acc3);
+            // sums over the 8 slot lanes of each angle shift, halving the
+            // values in flight at each step: the two quads of the 8 lanes
+            // swap halves (r 0, 1 stay low, r 2, 3 high), then the lane
+            // pairs of a quad, then neighbours add; lane t0 ends with
+            // r = 2 (t0 >> 2) + ((t0 >> 1) & 1)
+            const bool hi = t0 >= 4, b1 = (t0 >> 1) & 1;
+            const float A = (hi ? acc2 : acc0) + dpp<0x141>(hi ? acc0 : acc2);  // row_half_mirror
+            const float B = (hi ? acc3 : acc1) + dpp<0x141>(hi ? acc1 : acc3);
+            float C = (b1 ? B : A) + dpp<0x4E>(b1 ? A : B);                      // quad_perm [2,3,0,1]
+            C += dpp<0xB1>(C);                                                   // quad_perm [1,0,3,2]
+            if (!(t0 & 1)) {
+              const int r = 2 * (t0 >> 2) + ((t0 >> 1) & 1);
+              store1<BF16>(Grow, c.rad_len + k * kAngBlock + kNShfZ * r + a, C);
+            }
             acc0 = acc1 = acc2 = acc3 = 0.f;
           }
         }
