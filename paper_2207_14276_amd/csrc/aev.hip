@@ -106,7 +106,7 @@ struct WaveLds {
                    // fc_j fc_k                                     (forward)
   PairBlock *blk;  // [kMaxBlocks + 1] pair-block table           (backward)
   float4 *rD;      // radial: d vector and R (forward: d / R and R)
-  float *rFc;      // radial: fc_rad(R)          (forward)
+  float2 *rRF;     // radial: R and fc_rad(R)    (forward)
   float2 *rF2;     // fc(R) and fc'(R): radial cutoff, then (angular entries)
                    // the angular cutoff once the radial stage is done (backward)
   int *rJ;         // radial: neighbour index     (backward)
@@ -115,7 +115,7 @@ struct WaveLds {
   float *aFc;      // angular: fc_ang(R)          (forward)
 };
 
-// Per-wave LDS bytes (a multiple of 16).  Forward entry: rD 16, rFc 4,
+// Per-wave LDS bytes (a multiple of 16).  Forward entry: rD 16, rRF 8,
 // aIdx 4, aFc 4.  Backward entry: rD 16, rG 24, rF2 8, rJ 4, aIdx 4; the
 // backward reads the centre's dE/dG row from global memory (it stays in the
 // L1/L2 caches) and keeps the angular cutoff in the radial cutoff's slots,
@@ -125,7 +125,7 @@ template <bool BWD>
 __host__ __device__ inline size_t wave_lds_bytes(int cap) {
   return sizeof(Lists) + (BWD ? kBlkTableBytes + (size_t)cap * (16 + 24 + 4 + 4 + 4 + 4)
                               : (size_t)kPairPass * (8 + 16) +
-                                    (size_t)cap * (16 + 4 + 4 + 4));
+                                    (size_t)cap * (16 + 8 + 4 + 4));
 }
 
 template <bool BWD>
@@ -144,7 +144,7 @@ __device__ inline WaveLds carve(char *base, int cap) {
     w.tGeo = (float2 *)p; p += (size_t)kPairPass * 8;
     w.tF2 = (float4 *)p; p += (size_t)kPairPass * 16;
     w.rD = (float4 *)p; p += (size_t)cap * 16;
-    w.rFc = (float *)p; p += (size_t)cap * 4;
+    w.rRF = (float2 *)p; p += (size_t)cap * 8;
     w.aIdx = (int *)p; p += (size_t)cap * 4;
     w.aFc = (float *)p; p += (size_t)cap * 4;
   }
@@ -293,7 +293,7 @@ __device__ inline void fill_lists(int lane, int n, const int2 *__restrict__ ent,
         // the forward's pair geometry needs only the direction
         const float ir = fast_rcp(d.w);
         w.rD[q] = make_float4(d.x * ir, d.y * ir, d.z * ir, d.w);
-        w.rFc[q] = 0.5f * cs + 0.5f;
+        w.rRF[q] = make_float2(d.w, 0.5f * cs + 0.5f);
       }
       if (BWD) {
         w.rF2[q] = make_float2(0.5f * cs + 0.5f, -0.5f * kr * sn);
@@ -387,17 +387,18 @@ k_aev_fwd(const float4 *__restrict__ pos, const int *__restrict__ sys_of,
   {
     const int m = lane >> 2, slot = lane & 3;
     const float shf = pick(c.shf_r, m);
+    const float keta = -c.eta_r * 1.4426950408889634f;
     for (int s = 0; s < c.S; ++s) {
       float acc = 0.f;
       const int o = ls.oR[s];
       const int cnt = ls.cR[s];
+      // no branch per entry: slots past the end re-read the last entry
+      // and add it with a zero weight
       for (int e0 = 0; e0 < cnt; e0 += 4) {
         const int e = e0 + slot;
-        if (e < cnt) {
-          float R = w.rD[o + e].w;
-          float t = R - shf;
-          acc += fast_exp(-c.eta_r * t * t) * w.rFc[o + e];
-        }
+        const float2 rf = w.rRF[o + min(e, cnt - 1)];
+        const float t = rf.x - shf;
+        acc += fast_exp2(keta * t * t) * (e < cnt ? rf.y : 0.f);
       }
       acc = sum4(acc);
       if (slot == 0) store1<BF16>(Grow, s * kNShfRad + m, acc * c.scale);
