@@ -10,12 +10,22 @@ namespace nnp {
 // coordinates wrapped into [0, L) and the wrap and the caller's coordinates
 // recorded; a system that reuses its list applies the recorded wrap instead,
 // so neighbour vectors stay consistent with the stored lattice images.
+constexpr int kIngestLdsSystems = 1024;  // more systems: staging costs more than it saves
+
 __global__ void k_ingest(const float *__restrict__ coords, const int *__restrict__ species,
                          const unsigned char *__restrict__ mask,
                          const SysDesc *__restrict__ sys, int n_sys, int N, int S,
                          float4 *__restrict__ pos, int *__restrict__ sys_of,
                          AtomState *__restrict__ state, int *__restrict__ status,
                          float *__restrict__ zero_forces) {
+  // the systems' first atoms, staged in LDS when they fit: the search below
+  // then waits on LDS instead of on a chain of dependent global loads
+  __shared__ int s_off[kIngestLdsSystems];
+  const bool staged = n_sys <= kIngestLdsSystems;
+  if (staged) {
+    for (int k = threadIdx.x; k < n_sys; k += blockDim.x) s_off[k] = sys[k].atom_off;
+    __syncthreads();
+  }
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= N) return;
   // the force output starts from zero (the backward accumulates into it)
@@ -24,14 +34,15 @@ __global__ void k_ingest(const float *__restrict__ coords, const int *__restrict
     zero_forces[3 * (size_t)i + 1] = 0.f;
     zero_forces[3 * (size_t)i + 2] = 0.f;
   }
+  auto first_atom = [&](int k) { return staged ? s_off[k] : sys[k].atom_off; };
   // system of atom i: last s with atom_off <= i (binary search)
   int lo = 0, hi = n_sys - 1;
   while (lo < hi) {
     int mid = (lo + hi + 1) >> 1;
-    if (sys[mid].atom_off <= i) lo = mid; else hi = mid - 1;
+    if (first_atom(mid) <= i) lo = mid; else hi = mid - 1;
   }
   // skip empty systems that share the offset
-  while (lo + 1 < n_sys && sys[lo + 1].atom_off <= i) ++lo;
+  while (lo + 1 < n_sys && first_atom(lo + 1) <= i) ++lo;
   const SysDesc &d = sys[lo];
   const float cx = coords[3 * i], cy = coords[3 * i + 1], cz = coords[3 * i + 2];
   float x = cx, y = cy, z = cz;
@@ -575,21 +586,55 @@ k_species_count(const float4 *__restrict__ pos, int N, int S, int *__restrict__ 
 }
 
 // One workgroup: per-species exclusive scan over blocks, padded bucket
-// offsets, and -1 in the padding rows.
+// offsets, and -1 in the padding rows.  Blocks are taken 256 at a time, a
+// thread per block: the counts of all species load at once, wave scans by
+// shuffles, and the four waves' totals combine through LDS.
 __global__ void __launch_bounds__(256)
 k_species_scan(int *__restrict__ block_counts, int n_blocks, int S, int *__restrict__ bucket_off,
                int *__restrict__ bucket_cnt, int *__restrict__ perm) {
+  constexpr int kWaves = 256 / kWave;
+  __shared__ int wsum[kWaves][kMaxSpecies];
   __shared__ int tot[kMaxSpecies];
   __shared__ int off[kMaxSpecies + 1];
-  int t = threadIdx.x;
-  if (t < S) {
-    int run = 0;
-    for (int b = 0; b < n_blocks; ++b) {
-      int v = block_counts[b * kMaxSpecies + t];
-      block_counts[b * kMaxSpecies + t] = run;
-      run += v;
+  const int t = threadIdx.x, lane = t % kWave, wv = t / kWave;
+  int run[kMaxSpecies];  // totals of the earlier chunks (the same in every thread)
+#pragma unroll
+  for (int s = 0; s < kMaxSpecies; ++s) run[s] = 0;
+  for (int b0 = 0; b0 < n_blocks; b0 += 256) {
+    const int b = b0 + t;
+    const bool in = b < n_blocks;
+    int ex[kMaxSpecies];
+#pragma unroll
+    for (int s = 0; s < kMaxSpecies; ++s) {
+      const int v = in && s < S ? block_counts[b * kMaxSpecies + s] : 0;
+      int x = v;
+#pragma unroll
+      for (int d = 1; d < kWave; d <<= 1) {
+        const int y = __shfl_up(x, d);
+        if (lane >= d) x += y;
+      }
+      if (lane == kWave - 1) wsum[wv][s] = x;
+      ex[s] = x - v;
     }
-    tot[t] = run;
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < kMaxSpecies; ++s) {
+      int before = run[s], chunk = 0;
+#pragma unroll
+      for (int q = 0; q < kWaves; ++q) {
+        before += q < wv ? wsum[q][s] : 0;
+        chunk += wsum[q][s];
+      }
+      if (in && s < S) block_counts[b * kMaxSpecies + s] = before + ex[s];
+      run[s] += chunk;
+    }
+    __syncthreads();  // wsum is rewritten by the next chunk
+  }
+  if (t < S) {
+    int v = run[0];
+#pragma unroll
+    for (int s = 1; s < kMaxSpecies; ++s) v = t == s ? run[s] : v;
+    tot[t] = v;
   }
   __syncthreads();
   if (t == 0) {
