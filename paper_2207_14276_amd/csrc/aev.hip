@@ -106,26 +106,30 @@ struct WaveLds {
                    // fc_j fc_k                                     (forward)
   PairBlock *blk;  // [kMaxBlocks + 1] pair-block table           (backward)
   float4 *rD;      // radial: d vector and R (forward: d / R and R)
-  float2 *rRF;     // radial: R and fc_rad(R)    (forward)
+  float *rFc;      // radial: fc_rad(R)          (forward)
   float2 *rF2;     // fc(R) and fc'(R): radial cutoff, then (angular entries)
                    // the angular cutoff once the radial stage is done (backward)
   int *rJ;         // radial: neighbour index     (backward)
   long long *rG;   // radial: dE/dd accumulators, fixed point (backward, 3 per entry)
-  int *aIdx;       // angular: position in the radial arrays
+  int *aIdx;       // angular: position in the radial arrays  (backward)
+  unsigned short *aIdx16;  // the same, 16-bit       (forward)
   float *aFc;      // angular: fc_ang(R)          (forward)
 };
 
-// Per-wave LDS bytes (a multiple of 16).  Forward entry: rD 16, rRF 8,
-// aIdx 4, aFc 4.  Backward entry: rD 16, rG 24, rF2 8, rJ 4, aIdx 4; the
+// Per-wave LDS bytes (a multiple of 16).  Forward entry: rD 16, rFc 4,
+// aIdx16 2 (the array padded to 16 bytes), aFc 4: 4,992 bytes per wave at a
+// capacity of 128, so that 8 waves per SIMD fit.  Backward entry: rD 16, rG 24, rF2 8, rJ 4, aIdx 4; the
 // backward reads the centre's dE/dG row from global memory (it stays in the
 // L1/L2 caches) and keeps the angular cutoff in the radial cutoff's slots,
 // which keeps its LDS per wave near 8 KB (5 waves per SIMD at a capacity of
 // 128).
+__host__ __device__ inline size_t aidx16_bytes(int cap) { return ((size_t)cap * 2 + 15) / 16 * 16; }
+
 template <bool BWD>
 __host__ __device__ inline size_t wave_lds_bytes(int cap) {
   return sizeof(Lists) + (BWD ? kBlkTableBytes + (size_t)cap * (16 + 24 + 4 + 4 + 4 + 4)
                               : (size_t)kPairPass * (8 + 16) +
-                                    (size_t)cap * (16 + 8 + 4 + 4));
+                                    (size_t)cap * (16 + 4 + 4) + aidx16_bytes(cap));
 }
 
 template <bool BWD>
@@ -144,8 +148,8 @@ __device__ inline WaveLds carve(char *base, int cap) {
     w.tGeo = (float2 *)p; p += (size_t)kPairPass * 8;
     w.tF2 = (float4 *)p; p += (size_t)kPairPass * 16;
     w.rD = (float4 *)p; p += (size_t)cap * 16;
-    w.rRF = (float2 *)p; p += (size_t)cap * 8;
-    w.aIdx = (int *)p; p += (size_t)cap * 4;
+    w.rFc = (float *)p; p += (size_t)cap * 4;
+    w.aIdx16 = (unsigned short *)p; p += aidx16_bytes(cap);
     w.aFc = (float *)p; p += (size_t)cap * 4;
   }
   return w;
@@ -293,7 +297,7 @@ __device__ inline void fill_lists(int lane, int n, const int2 *__restrict__ ent,
         // the forward's pair geometry needs only the direction
         const float ir = fast_rcp(d.w);
         w.rD[q] = make_float4(d.x * ir, d.y * ir, d.z * ir, d.w);
-        w.rRF[q] = make_float2(d.w, 0.5f * cs + 0.5f);
+        w.rFc[q] = 0.5f * cs + 0.5f;
       }
       if (BWD) {
         w.rF2[q] = make_float2(0.5f * cs + 0.5f, -0.5f * kr * sn);
@@ -301,7 +305,8 @@ __device__ inline void fill_lists(int lane, int n, const int2 *__restrict__ ent,
       }
     }
     if (inA) {
-      w.aIdx[qa] = q;
+      if (BWD) w.aIdx[qa] = q;
+      else w.aIdx16[qa] = (unsigned short)q;
       if (!BWD) w.aFc[qa] = 0.5f * __cosf(ka * d.w) + 0.5f;
     }
   }
@@ -396,9 +401,9 @@ k_aev_fwd(const float4 *__restrict__ pos, const int *__restrict__ sys_of,
       // and add it with a zero weight
       for (int e0 = 0; e0 < cnt; e0 += 4) {
         const int e = e0 + slot;
-        const float2 rf = w.rRF[o + min(e, cnt - 1)];
-        const float t = rf.x - shf;
-        acc += fast_exp2(keta * t * t) * (e < cnt ? rf.y : 0.f);
+        const int q = o + min(e, cnt - 1);
+        const float t = w.rD[q].w - shf;
+        acc += fast_exp2(keta * t * t) * (e < cnt ? w.rFc[q] : 0.f);
       }
       acc = sum4(acc);
       if (slot == 0) store1<BF16>(Grow, s * kNShfRad + m, acc * c.scale);
@@ -491,7 +496,7 @@ k_aev_fwd(const float4 *__restrict__ pos, const int *__restrict__ sys_of,
         int qj, qk;
         unrank(tt, l_n12 & 0xffff, (l_n12 >> 16) & 0x7fff, l_r1, l_r2, (l_n12 >> 31) & 1,
                l_oxy & 0xffff, (l_oxy >> 16) & 0xffff, qj, qk);
-        const float4 dj = w.rD[w.aIdx[qj]], dk = w.rD[w.aIdx[qk]];  // unit vectors, R
+        const float4 dj = w.rD[w.aIdx16[qj]], dk = w.rD[w.aIdx16[qk]];  // unit vectors, R
         const float cosv = dj.x * dk.x + dj.y * dk.y + dj.z * dk.z;
         const float cx = dj.y * dk.z - dj.z * dk.y;
         const float cy = dj.z * dk.x - dj.x * dk.z;
