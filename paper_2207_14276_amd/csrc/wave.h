@@ -2,6 +2,7 @@
 #pragma once
 
 #include "internal.h"
+#include "fixed.h"
 
 namespace nnp {
 
@@ -60,19 +61,5 @@ __device__ inline void wave_lds_sync() {
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
-
-// Force-like accumulators in LDS are 64-bit fixed point with 2^-32 resolution:
-// integer LDS atomics are fast on this hardware where float LDS atomics are
-// not, and integer sums are exact and independent of the order of the adds.
-constexpr float kFix = 4294967296.0f;         // 2^32
-constexpr float kUnfix = 2.3283064365386963e-10f;  // 2^-32
-// floor(v * 2^32) as a 64-bit integer, built from its two 32-bit halves:
-// hi = floor(v), lo = (v - hi) * 2^32 in [0, 2^32) (both steps exact).
-__device__ inline long long to_fix(float v) {
-  const float hi = floorf(v);
-  const unsigned lo = (unsigned)((v - hi) * kFix);
-  return (long long)(((unsigned long long)(unsigned)(int)hi << 32) | lo);
-}
-__device__ inline float from_fix(long long v) { return (float)v * kUnfix; }
 
 }  // namespace nnp
