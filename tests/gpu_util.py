@@ -26,10 +26,10 @@ def to_dev(batch, device="cuda"):
             batch.boxes, batch.offsets)
 
 
-def run_gpu(model, batch, virial=True, forces=True):
+def run_gpu(model, batch, virial=True, forces=True, check=True):
     c, s, b, o = to_dev(batch)
     r = model.energy_forces(c, s, b, o, forces=forces, virial=virial and forces,
-                            atom_energy=True, check=True)
+                            atom_energy=True, check=check)
     torch.cuda.synchronize()
     out = {"energy": r.energy.cpu().numpy(), "e_atom": r.atom_energy.cpu().numpy().astype(np.float64)}
     if forces:
@@ -46,3 +46,23 @@ def compare_system(gpu, ora, k, batch, label, e_atom_tol, f_tol, e_sys_per_atom_
     de_sys = abs(gpu["energy"][k] - ora["energy"][k]) / max(n, 1)
     df = np.abs(gpu["forces"][a:e] - ora["forces"][k]).max() if n and "forces" in gpu else 0.0
     return de_atom, de_sys, df
+
+
+def virial_bound(coords, box, f_gpu, f_ref, rc=5.1):
+    """Bound on max |W_gpu - W_ref| of one system derived from its force
+    error.  Non-periodic: W = sum_k (r_k - c) (x) F_k for any centre c (the
+    pair terms d (x) dE/dd regroup per atom and the net force is zero), so
+    |dW_ab| <= sum_k |r_ka - c_a| |dF_kb|, plus float32 rounding of the
+    per-centre sums (2e-6 of the same sum over |F|).  Periodic: the lattice
+    images break that identity; each atom's share of W is a sum of pair terms
+    with lever arms below the cutoff, bounded by rc times its force error."""
+    x = np.asarray(coords, np.float64)
+    df = np.abs(np.asarray(f_gpu, np.float64) - np.asarray(f_ref, np.float64))
+    fr = np.abs(np.asarray(f_ref, np.float64))
+    if box is not None and np.all(np.asarray(box) > 0):
+        lever = np.full_like(x, rc)
+    else:
+        lever = np.abs(x - x.mean(0))
+    main = float((lever.T @ df).max())
+    slack = 2e-6 * float((lever.T @ fr).max()) + 1e-9 * len(x)
+    return main + slack

@@ -23,12 +23,21 @@ import pytest
 import torch
 
 import synth
-from tests.gpu_util import BF16_E_PER_ATOM, BF16_F, FP32_E_ATOM, FP32_F, log, run_gpu, to_dev
+from tests.gpu_util import (BF16_E_PER_ATOM, BF16_F, FP32_E_ATOM, FP32_F, log, run_gpu, to_dev,
+                            virial_bound)
 from tests.test_gpu_pairs import brute_pairs, oracle_region, solute_in_water
 
 pytestmark = pytest.mark.gpu
 
-BF16_F_REL = 0.02   # bfloat16 force bar relative to the largest reference force
+# bfloat16 dense layers round both operands of every product to 8 significant
+# bits (unit roundoff 2^-9 = 0.2%); the input gradient inherits that relative
+# error, so the force error scales with the forces.  This randomly
+# initialised model's forces reach ~26 kcal/mol/A on the ragged batch, where
+# the stated absolute bar (5e-2) is 0.2% of the largest force and is missed
+# (recorded as a miss; test_bf16_stated_force_bar_ragged512).  The cases
+# below assert the stated bar; the ragged batch asserts 0.5% of its largest
+# force, which catches regressions.
+BF16_F_REL = 0.005
 
 
 @pytest.fixture(scope="module")
@@ -102,9 +111,10 @@ def test_single_atom_box_closed_form(m32):
 
 
 def _check(model, oracle_lib, om, b, systems, e_atom_tol, e_sys_tol, f_tol, label, f_rel=0.0):
+    """Asserts the bars and returns (max |dF|, max |F|)."""
     gpu = run_gpu(model, b)
     ora = oracle_lib.batch_energy_forces(b, om, systems=systems)
-    worst_ea = worst_es = worst_f = worst_w = 0.0
+    worst_ea = worst_es = worst_f = worst_w = worst_wr = 0.0
     for q, k in enumerate(systems):
         a, e = int(b.offsets[k]), int(b.offsets[k + 1])
         n = e - a
@@ -114,16 +124,22 @@ def _check(model, oracle_lib, om, b, systems, e_atom_tol, e_sys_tol, f_tol, labe
         worst_ea = max(worst_ea, float(np.abs(gpu["e_atom"][a:e] - ora["e_atom"][q]).max()))
         worst_es = max(worst_es, abs(gpu["energy"][k] - ora["energy"][q]) / n)
         worst_f = max(worst_f, float(np.abs(gpu["forces"][a:e] - ora["forces"][q]).max()))
-        worst_w = max(worst_w, float(np.abs(gpu["virial"][k] - ora["virial"][q]).max()) / n)
+        dw = float(np.abs(gpu["virial"][k] - ora["virial"][q]).max())
+        worst_w = max(worst_w, dw / n)
+        worst_wr = max(worst_wr, dw / virial_bound(b.coords[a:e], b.boxes[k], gpu["forces"][a:e], ora["forces"][q],
+                                             rc=6.01))
     f_max = max(float(np.abs(ora["forces"][q]).max()) for q in range(len(systems)) if len(ora["forces"][q]))
     f_tol = max(f_tol, f_rel * f_max)
     log(f"[dp {label}] max|dE_i|={worst_ea:.3e} max|dE_s|/N={worst_es:.3e} "
-        f"max|dF|={worst_f:.3e} (max|F|={f_max:.2f}, bar {f_tol:.3e}) max|dW|/N={worst_w:.3e}")
+        f"max|dF|={worst_f:.3e} (max|F|={f_max:.2f}, bar {f_tol:.3e}) max|dW|/N={worst_w:.3e} "
+        f"max|dW|/bound={worst_wr:.3f}")
     if e_atom_tol is not None:
         assert worst_ea <= e_atom_tol
     assert worst_es <= e_sys_tol
     assert worst_f <= f_tol
-    assert worst_w <= 50 * f_tol
+    # the virial error follows from the force error (virial_bound)
+    assert worst_wr <= 1.0
+    return worst_f, f_max
 
 
 @pytest.mark.parametrize("name", list(SYSTEMS))
@@ -135,18 +151,39 @@ def test_fp32_energy_forces(m32, oracle_lib, om, name):
 @pytest.mark.parametrize("name", ["cluster24", "water12_box", "ragged16", "water667"])
 def test_bf16_energy_forces(m16, oracle_lib, om, name):
     b = SYSTEMS[name]
-    _check(m16, oracle_lib, om, b, list(range(b.n_systems)), None, BF16_E_PER_ATOM, BF16_F, f"bf16 {name}",
-           BF16_F_REL)
+    _check(m16, oracle_lib, om, b, list(range(b.n_systems)), None, BF16_E_PER_ATOM, BF16_F, f"bf16 {name}")
 
 
-def test_ragged_batch_512_sampled_systems(m32, m16, oracle_lib, om):
+def _ragged512_pick():
     b = synth.config2()
     sizes = np.diff(b.offsets)
     rng = np.random.default_rng(1)
     pick = sorted(set(rng.choice(b.n_systems, 22, replace=False).tolist()
                       + [int(sizes.argmin()), int(sizes.argmax())]))
+    return b, pick
+
+
+_RAGGED_BF16 = {}
+
+
+def test_ragged_batch_512_sampled_systems(m32, m16, oracle_lib, om):
+    b, pick = _ragged512_pick()
     _check(m32, oracle_lib, om, b, pick, FP32_E_ATOM, FP32_E_ATOM, FP32_F, "fp32 ragged512")
-    _check(m16, oracle_lib, om, b, pick, None, BF16_E_PER_ATOM, BF16_F, "bf16 ragged512", BF16_F_REL)
+    # the stated absolute force bar is missed here (see BF16_F_REL); energies
+    # meet theirs
+    df, fmax = _check(m16, oracle_lib, om, b, pick, None, BF16_E_PER_ATOM, 0.0, "bf16 ragged512", BF16_F_REL)
+    _RAGGED_BF16["df"] = df
+
+
+@pytest.mark.xfail(strict=True, reason="stated bfloat16 force bar (5e-2 kcal/mol/A) missed on the ragged "
+                                       "batch, where this model's forces reach ~26 kcal/mol/A")
+def test_bf16_stated_force_bar_ragged512(m16, oracle_lib, om):
+    df = _RAGGED_BF16.get("df")
+    if df is None:
+        b, pick = _ragged512_pick()
+        df, _ = _check(m16, oracle_lib, om, b, pick, None, BF16_E_PER_ATOM, 1e9, "bf16 ragged512")
+    log(f"[dp bf16 ragged512] max|dF|={df:.3e} against the stated bar {BF16_F:.1e}")
+    assert df <= BF16_F
 
 
 def test_edge_cases(m32, oracle_lib, om):
@@ -185,8 +222,6 @@ def test_large_periodic_sampled(oracle_lib):
         de = float(np.abs(gpu["e_atom"][t] - e_ref).max())
         df = float(np.abs(gpu["forces"][t] - f_ref).max())
         net = float(np.abs(gpu["forces"].sum(0)).max())
-        if prec == "bf16":
-            f_tol = max(f_tol, BF16_F_REL * float(np.abs(f_ref).max()))
         log(f"[dp {prec} protein100k ens4] max|dE_i|={de:.3e} max|dF|={df:.3e} (bar {f_tol:.3e}) "
             f"|sum F|={net:.3e}")
         assert de <= e_tol

@@ -12,7 +12,7 @@ import pytest
 import torch
 
 import synth
-from tests.gpu_util import FP32_E_ATOM, FP32_F, log
+from tests.gpu_util import BF16_E_PER_ATOM, BF16_F, FP32_E_ATOM, FP32_F, log
 
 pytestmark = pytest.mark.gpu
 
@@ -26,6 +26,12 @@ def spec():
 def m32(spec):
     from paper_2207_14276_amd import NNPModel
     return NNPModel(spec, "fp32")
+
+
+@pytest.fixture(scope="module")
+def m16(spec):
+    from paper_2207_14276_amd import NNPModel
+    return NNPModel(spec, "bf16")
 
 
 def _walk(batch, steps, sigma, seed):
@@ -115,18 +121,25 @@ def _run(model, reqs, spacing=0.0, **kw):
     return rep, stats
 
 
-def test_served_alone_equals_served_in_mix(m32, oracle_lib, spec):
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_served_alone_equals_served_in_mix(m32, m16, oracle_lib, spec, prec):
+    """Served in a changing mix or alone, a request gives the same walk, the
+    same energies and forces within float32 rounding of unordered force sums;
+    its last step matches the oracle at the tolerances of the precision form
+    the server runs (float32, or bfloat16 dense layers as benchmarked)."""
+    model = m32 if prec == "fp32" else m16
+    e_tol, f_tol = (FP32_E_ATOM, FP32_F) if prec == "fp32" else (BF16_E_PER_ATOM, BF16_F)
     reqs = _requests(10, seed=5)
     # staggered arrivals: the mix around the tracked requests changes every few steps
-    mixed, _ = _run(m32, reqs, spacing=0.002)
+    mixed, _ = _run(model, reqs, spacing=0.002)
     assert len(mixed.results) == 10
     for rid in (3, 6):
-        alone, _ = _run(m32, [reqs[rid]])
+        alone, _ = _run(model, [reqs[rid]])
         a, m = alone.results[0], mixed.results[rid]
         assert np.array_equal(a.coords, m.coords)        # the client's walk is the same
         de = float(np.abs(a.energies - m.energies).max())
         df = float(np.abs(a.forces - m.forces).max())
-        log(f"[alone-vs-mix rid={rid}] max|dE|={de:.3e} max|dF|={df:.3e}")
+        log(f"[alone-vs-mix {prec} rid={rid}] max|dE|={de:.3e} max|dF|={df:.3e}")
         assert de <= 1e-9 * reqs[rid].n_atoms + 1e-12
         assert df <= 1e-5
         # the last step's results match the oracle at the coordinates evaluated
@@ -134,9 +147,9 @@ def test_served_alone_equals_served_in_mix(m32, oracle_lib, spec):
         E, ea, F, _ = oracle_lib.energy_forces(a.coords, reqs[rid].species, reqs[rid].box, om)
         de = abs(float(a.energies[-1]) - E) / reqs[rid].n_atoms
         df = float(np.abs(a.forces - F).max())
-        log(f"[served vs oracle rid={rid}] |dE|/N={de:.3e} max|dF|={df:.3e}")
-        assert de <= FP32_E_ATOM
-        assert df <= FP32_F
+        log(f"[served vs oracle {prec} rid={rid}] |dE|/N={de:.3e} max|dF|={df:.3e}")
+        assert de <= e_tol
+        assert df <= f_tol
 
 
 def test_server_drains_a_burst(m32):
