@@ -52,6 +52,18 @@ def parse():
     return p.parse_args()
 
 
+def cpu_model() -> str:
+    """The host CPU's model name (first processor in /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def say(args, *a):
     if not args.quiet:
         print("[bench]", *a, file=sys.stderr, flush=True)
@@ -777,6 +789,30 @@ def main():
         out["speedup_vs_plain"] = round(value / (N / tplain), 2)
         say(args, f"plain fp32 per-system: {tplain * 1e3:.2f} ms/pass, {N / tplain:.3e} atom-evals/s")
 
+    # the same batched form with float32 dense layers: separates the gain of
+    # batching from that of the precision form
+    res32 = None
+    if args.precision == "bf16" and not args.no_plain:
+        m32 = NNPModel(spec, "fp32")
+        m32.reserve(N, S, cap)
+        m32.autotune(c, sp, batch.boxes, batch.offsets)
+        res32 = m32.energy_forces(c, sp, batch.boxes, batch.offsets, forces=True, virial=True,
+                                  atom_energy=True, check=True)
+        for _ in range(args.warmup):
+            m32.energy_forces(c, sp, batch.boxes, batch.offsets, out=res32)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            m32.energy_forces(c, sp, batch.boxes, batch.offsets, out=res32)
+        torch.cuda.synchronize()
+        w32 = time.perf_counter() - t0
+        m32.status()
+        out["batched_fp32"] = {"value": round(N * args.steps / w32, 1), "unit": "atom-evals/s",
+                               "ms_per_step": round(w32 / args.steps * 1e3, 4),
+                               "form": "batched, one call per step, float32 dense layers"}
+        out["speedup_bf16_vs_batched_fp32"] = round(value / (N * args.steps / w32), 2)
+        say(args, f"batched fp32: {w32 / args.steps * 1e3:.3f} ms/step, {N * args.steps / w32:.3e} atom-evals/s")
+
     # error of each form against the oracle on a seeded sample of systems
     if not args.no_cpu:
         import oracle
@@ -786,20 +822,26 @@ def main():
         if args.workload == "protein100k":
             tgt = np.sort(rng.choice(N, 8, replace=False))
             e_ref, f_ref = oracle.sampled(batch.coords, batch.species, batch.boxes[0], om, tgt)
-            f_err = float(np.abs(res.forces.cpu().numpy()[tgt] - f_ref).max())
-            e_err = float(np.abs(res.atom_energy.cpu().numpy()[tgt] - e_ref).max())
-            out["error_vs_oracle"] = {"sample": "8 atoms", "max_abs_dE_atom": e_err, "max_abs_dF": f_err}
+
+            def errors(r):
+                return {"sample": "8 atoms",
+                        "max_abs_dE_atom": float(np.abs(r.atom_energy.cpu().numpy()[tgt] - e_ref).max()),
+                        "max_abs_dF": float(np.abs(r.forces.cpu().numpy()[tgt] - f_ref).max())}
         else:
             ref = oracle.batch_energy_forces(batch, om, systems=pick)
-            F = res.forces.cpu().numpy()
-            E = res.energy.cpu().numpy()
-            fe, ee = 0.0, 0.0
-            for q, k in enumerate(pick):
-                a, e = int(batch.offsets[k]), int(batch.offsets[k + 1])
-                fe = max(fe, float(np.abs(F[a:e] - ref["forces"][q]).max()))
-                ee = max(ee, abs(E[k] - ref["energy"][q]) / (e - a))
-            out["error_vs_oracle"] = {"sample": f"{len(pick)} systems", "max_abs_dF": fe,
-                                      "max_abs_dE_per_atom": ee}
+
+            def errors(r):
+                F = r.forces.cpu().numpy()
+                E = r.energy.cpu().numpy()
+                fe, ee = 0.0, 0.0
+                for q, k in enumerate(pick):
+                    a, e = int(batch.offsets[k]), int(batch.offsets[k + 1])
+                    fe = max(fe, float(np.abs(F[a:e] - ref["forces"][q]).max()))
+                    ee = max(ee, abs(E[k] - ref["energy"][q]) / (e - a))
+                return {"sample": f"{len(pick)} systems", "max_abs_dF": fe, "max_abs_dE_per_atom": ee}
+        out["error_vs_oracle"] = errors(res)
+        if res32 is not None:
+            out["batched_fp32"]["error_vs_oracle"] = errors(res32)
 
         # CPU baseline: the oracle on a bounded sample of the same workload
         t_budget = args.cpu_seconds
@@ -823,7 +865,8 @@ def main():
             sample = f"{k} of {S} systems ({done_atoms} atoms), seeded order"
         out["cpu_baseline"] = {"value": round(cpu_rate, 2), "unit": "atom-evals/s",
                                "cores": oracle.threads(), "kind": "oracle", "sample": sample,
-                               "seconds": round(dt, 2)}
+                               "seconds": round(dt, 2), "cpu_model": cpu_model(),
+                               "host_cpus": os.cpu_count()}
         say(args, f"cpu oracle: {cpu_rate:.3e} atom-evals/s on {oracle.threads()} threads")
         # the same oracle on one core, on a smaller bounded sample
         prev = oracle.set_threads(1)

@@ -98,8 +98,12 @@ typedef struct {
   int precision;
 } nnp_model_desc;
 
-/* Builds a model on the current HIP device. *out receives the handle. */
-int nnp_create(const nnp_model_desc *desc, nnp_model **out);
+/* Builds a model on device hip_device (< 0: the calling thread's current
+ * HIP device); the caller's current device is left as it was.  *out receives
+ * the handle.  Every later call on the model runs on that device.  The
+ * weights are copied (section "A General Machine Learning Platform": the
+ * model is set up once, then fed positions every step). */
+int nnp_create(const nnp_model_desc *desc, int hip_device, nnp_model **out);
 void nnp_destroy(nnp_model *model);
 
 /* DeepPot-style local-frame descriptor (section "DeePMD Models"), a second
@@ -137,10 +141,11 @@ typedef struct {
   int precision;
 } nnp_dp_model_desc;
 
-/* Builds a DeepPot-style model on the current HIP device; the handle works
- * with every entry point below (energies, forces, virials, pair lists,
- * persistent lists, descriptor export, serving). */
-int nnp_create_dp(const nnp_dp_model_desc *desc, nnp_model **out);
+/* Builds a DeepPot-style model on device hip_device (< 0: the current one;
+ * as nnp_create); the handle works with every entry point below (energies,
+ * forces, virials, pair lists, persistent lists, descriptor export,
+ * serving). */
+int nnp_create_dp(const nnp_dp_model_desc *desc, int hip_device, nnp_model **out);
 
 /* Pre-sizes the library workspace (the paper's bounded up-front buffer,
  * section "Massive Parallelism within Tinker-HP") for calls of up to
@@ -149,7 +154,20 @@ int nnp_create_dp(const nnp_dp_model_desc *desc, nnp_model **out);
  * workspace grows on demand, which synchronizes the device. */
 int nnp_reserve(nnp_model *model, int64_t max_atoms, int max_systems, int nbr_capacity);
 
-/* Energy and forces of a batch of independent systems.
+/* Energy and forces of a batch of independent systems: per system the sum
+ * of the atomic energies of its atoms (section "Neural Network Potentials",
+ * energy-decomposition equation; with an ensemble, the mean over members,
+ * section "Neural Network Potentials"), each from the element network of its
+ * AEV (section "ANI models", radial and angular equations) over the atoms and
+ * periodic images within the cutoff (neighbour search: section "Massive
+ * Parallelism within Tinker-HP"), and the forces as the analytic negative
+ * gradient.  Positions go in and energies and forces come out as device
+ * addresses (section "A General Machine Learning Platform").
+ * The call only enqueues: it does not wait for the device, except when the
+ * workspace must grow (see nnp_reserve) or when the descriptors of 32
+ * earlier calls are still being copied (a ring of pinned staging slots).
+ * Calls on one model share its workspace: they must be on one stream, or
+ * ordered by the caller.
  *   n_systems      >= 1
  *   batch_offsets  HOST int64[n_systems + 1]; offsets[0] = 0, non-decreasing;
  *                  system s owns atoms [offsets[s], offsets[s+1]).

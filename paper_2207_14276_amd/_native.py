@@ -111,8 +111,8 @@ def load():
     lib = C.CDLL(LIB_PATH)
     vp, i64p = C.c_void_p, C.POINTER(C.c_int64)
     fp = C.POINTER(C.c_float)
-    lib.nnp_create.argtypes = [C.POINTER(nnp_model_desc), C.POINTER(C.c_void_p)]
-    lib.nnp_create_dp.argtypes = [C.POINTER(nnp_dp_model_desc), C.POINTER(C.c_void_p)]
+    lib.nnp_create.argtypes = [C.POINTER(nnp_model_desc), C.c_int, C.POINTER(C.c_void_p)]
+    lib.nnp_create_dp.argtypes = [C.POINTER(nnp_dp_model_desc), C.c_int, C.POINTER(C.c_void_p)]
     lib.nnp_destroy.argtypes = [vp]
     lib.nnp_destroy.restype = None
     lib.nnp_reserve.argtypes = [vp, C.c_int64, C.c_int, C.c_int]

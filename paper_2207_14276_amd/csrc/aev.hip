@@ -575,48 +575,94 @@ k_aev_fwd(const float4 *__restrict__ pos, const int *__restrict__ sys_of,
   }
 }
 
-// OCC: waves per SIMD the register allocation must allow (0: no bound).
-// With a small neighbour capacity the LDS leaves room for 6 waves per
-// SIMD; the kernel is then held to 80 registers so that they fit.
-template <int WPB, int OCC>
-__global__ void __launch_bounds__(WPB * kWave) __attribute__((amdgpu_waves_per_eu(OCC)))
-k_aev_bwd(const float4 *__restrict__ pos, const int *__restrict__ sys_of,
-          const SysDesc *__restrict__ sys, const int2 *__restrict__ nbr,
-          const int *__restrict__ nbr_cnt, int cap, const int *__restrict__ row_of_atom,
-          const float *__restrict__ dG, int ldg, int N, AevConst c, float *__restrict__ F,
-          float *__restrict__ W_atom) {
-  extern __shared__ float4 lds4[];
-  // the wave index is uniform across the wave: keep it (and the centre's
-  // index, descriptors and row pointers) in scalar registers
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave), lane = threadIdx.x % kWave;
-  const int i = blockIdx.x * WPB + wave;
+// Where the force contributions of a centre go.  Forces accumulate in 64-bit
+// fixed point (fixed.h) in the buffer Ffix[N][3], which the caller clears
+// first and converts to float32 afterwards: integer sums do not depend on the
+// order in which waves add into them, so forces come out the same bit for
+// bit whatever else the batch holds.
+//   SinkGlobal: device-scope integer atomics straight into Ffix;
+//   SinkSys:    an LDS table of one system's atoms (index j - atom_off),
+//               added into Ffix once per workgroup;
+//   SinkHash:   an LDS hash table keyed by atom index (open addressing,
+//               linear probing), added into Ffix once per workgroup; an atom
+//               that finds no free slot within kBwdProbe probes goes
+//               straight to Ffix.
+struct SinkGlobal {
+  unsigned long long *F;
+  __device__ inline void add(int j, long long x, long long y, long long z) const {
+    unsigned long long *p = F + 3 * (size_t)j;
+    atomicAdd(p, (unsigned long long)x);
+    atomicAdd(p + 1, (unsigned long long)y);
+    atomicAdd(p + 2, (unsigned long long)z);
+  }
+};
+struct SinkSys {
+  unsigned long long *tab;
+  int off;
+  __device__ inline void add(int j, long long x, long long y, long long z) const {
+    unsigned long long *p = tab + 3 * (j - off);
+    atomicAdd(p, (unsigned long long)x);
+    atomicAdd(p + 1, (unsigned long long)y);
+    atomicAdd(p + 2, (unsigned long long)z);
+  }
+};
+constexpr int kBwdHashBits = 9;
+constexpr int kBwdHash = 1 << kBwdHashBits;  // slots: a cell's neighbourhood holds ~300-450 atoms
+constexpr int kBwdProbe = 32;
+constexpr int kBwdMinCells = 512;  // cells of a grid for the per-cell form
+struct SinkHash {
+  int *key;
+  unsigned long long *val;
+  unsigned long long *F;
+  __device__ inline void add(int j, long long x, long long y, long long z) const {
+    unsigned h = ((unsigned)j * 2654435761u) >> (32 - kBwdHashBits);
+    for (int probe = 0; probe < kBwdProbe; ++probe) {
+      int k = key[h];
+      if (k == -1) k = atomicCAS(&key[h], -1, j);  // -1: this lane claimed the slot
+      if (k == -1 || k == j) {
+        unsigned long long *p = val + 3 * h;
+        atomicAdd(p, (unsigned long long)x);
+        atomicAdd(p + 1, (unsigned long long)y);
+        atomicAdd(p + 2, (unsigned long long)z);
+        return;
+      }
+      h = (h + 1) & (kBwdHash - 1);
+    }
+    SinkGlobal{F}.add(j, x, y, z);
+  }
+};
+
+// Backward of centre i by one wave (wave-uniform i; no workgroup barrier, so
+// waves of one workgroup may work on different centres): dE/dd of every
+// radial entry from the radial and angular terms, the centre's virial row
+// W_atom[i] = -sum d (x) dE/dd, and its force contributions through sink:
+// -dE/dd onto each neighbour, the sum of dE/dd onto the centre.
+template <class Sink>
+__device__ inline void bwd_centre(int i, int lane, const float4 *__restrict__ pos, const int *__restrict__ sys_of,
+                                  const SysDesc *__restrict__ sys, const int2 *__restrict__ nbr,
+                                  const int *__restrict__ nbr_cnt, int cap, const int *__restrict__ row_of_atom,
+                                  const float *__restrict__ dG, int ldg, const AevConst &c,
+                                  float *__restrict__ W_atom, WaveLds &w, const Sink &sink) {
   // an atom without a network row (outside a caller's mask) is skipped; its
   // virial share is zero
-  const bool has_row = i < N && row_of_atom[i] >= 0;
-  const bool live = has_row;
-  if (i < N && !has_row && lane < 9) W_atom[(size_t)9 * i + lane] = 0.f;
-  WaveLds w = carve<true>((char *)lds4 + wave * wave_lds_bytes<true>(cap), cap);
-  float4 pi = make_float4(0.f, 0.f, 0.f, 0.f);
-  float L[3] = {0.f, 0.f, 0.f};
-  int n = 0, j0 = 0, n_sys = 0;
-  const int2 *row = nbr;
-  if (live) {
-    const SysDesc &d = sys[sys_of[i]];
-    n_sys = d.n;
-    n = min(nbr_cnt[d.state_off + (i - d.atom_off)], cap);
-    pi = pos[i];
-    L[0] = d.L[0]; L[1] = d.L[1]; L[2] = d.L[2];
-    j0 = d.atom_off;
-    row = nbr + nbr_row(d, i, cap);
+  const int r_i = row_of_atom[i];
+  if (r_i < 0) {
+    if (lane < 9) W_atom[(size_t)9 * i + lane] = 0.f;
+    return;
   }
+  const SysDesc &d = sys[sys_of[i]];
+  const int n_sys = d.n;
+  const int n = min(nbr_cnt[d.state_off + (i - d.atom_off)], cap);
+  const float4 pi = pos[i];
+  const float L[3] = {d.L[0], d.L[1], d.L[2]};
+  const int j0 = d.atom_off;
+  const int2 *row = nbr + nbr_row(d, i, cap);
   fill_lists<true>(lane, n, row, j0, n_sys, pos, pi, L, c, w);
-  __syncthreads();
-  if (!live) return;
+  wave_lds_sync();
   const Lists &ls = *w.ls;
-  const float *g = dG + (size_t)row_of_atom[i] * ldg;
+  const float *g = dG + (size_t)r_i * ldg;
   int nR = 0;
   for (int s = 0; s < c.S; ++s) nR += ls.cR[s];
-
   // radial, lane per neighbour entry: with t_m = R - Rs_m and
   // e_m = exp(-eta t_m^2), dE/dR = scale (fc' sum_m g_m e_m - 2 eta fc
   // sum_m g_m e_m t_m), g being the dE/dG values of the entry's species.
@@ -770,36 +816,134 @@ k_aev_bwd(const float4 *__restrict__ pos, const int *__restrict__ sys_of,
     wave_lds_sync();
   }
 
-  // scatter: F_i += dE/dd, F_j -= dE/dd, per-centre virial -sum d (x) dE/dd
+  // scatter: -dE/dd onto each neighbour, the sum onto the centre (fixed
+  // point), per-centre virial -sum d (x) dE/dd
   {
     float fi0 = 0.f, fi1 = 0.f, fi2 = 0.f;
     float vir[9];
     for (int q = 0; q < 9; ++q) vir[q] = 0.f;
     for (int e = lane; e < nR; e += kWave) {
-      const float4 d = w.rD[e];
-      const float gx = from_fix(w.rG[3 * e]), gy = from_fix(w.rG[3 * e + 1]), gz = from_fix(w.rG[3 * e + 2]);
-      const int j = w.rJ[e];
+      const float4 dv = w.rD[e];
+      const long long q0 = w.rG[3 * e], q1 = w.rG[3 * e + 1], q2 = w.rG[3 * e + 2];
+      const float gx = from_fix(q0), gy = from_fix(q1), gz = from_fix(q2);
+      sink.add(w.rJ[e], -q0, -q1, -q2);
       fi0 += gx; fi1 += gy; fi2 += gz;
-      atomicAdd(&F[3 * j], -gx);
-      atomicAdd(&F[3 * j + 1], -gy);
-      atomicAdd(&F[3 * j + 2], -gz);
-      vir[0] -= d.x * gx; vir[1] -= d.x * gy; vir[2] -= d.x * gz;
-      vir[3] -= d.y * gx; vir[4] -= d.y * gy; vir[5] -= d.y * gz;
-      vir[6] -= d.z * gx; vir[7] -= d.z * gy; vir[8] -= d.z * gz;
+      vir[0] -= dv.x * gx; vir[1] -= dv.x * gy; vir[2] -= dv.x * gz;
+      vir[3] -= dv.y * gx; vir[4] -= dv.y * gy; vir[5] -= dv.y * gz;
+      vir[6] -= dv.z * gx; vir[7] -= dv.z * gy; vir[8] -= dv.z * gz;
     }
     fi0 = wave_sum(fi0);
     fi1 = wave_sum(fi1);
     fi2 = wave_sum(fi2);
     for (int q = 0; q < 9; ++q) vir[q] = wave_sum(vir[q]);
-    if (lane == 0) {
-      atomicAdd(&F[3 * i], fi0);
-      atomicAdd(&F[3 * i + 1], fi1);
-      atomicAdd(&F[3 * i + 2], fi2);
-    }
+    if (lane == 0) sink.add(i, to_fix(fi0), to_fix(fi1), to_fix(fi2));
     if (lane < 9) {
       float v = vir[0];
       for (int q = 1; q < 9; ++q) v = lane == q ? vir[q] : v;
       W_atom[(size_t)9 * i + lane] = v;
+    }
+  }
+  // the next centre of this wave rewrites the lists
+  wave_lds_sync();
+}
+
+// Per-centre form (caller pair lists, small cell grids): one wave per centre,
+// forces by device atomics.
+template <int WPB>
+__global__ void __launch_bounds__(WPB * kWave)
+k_aev_bwd(const float4 *__restrict__ pos, const int *__restrict__ sys_of,
+          const SysDesc *__restrict__ sys, const int2 *__restrict__ nbr,
+          const int *__restrict__ nbr_cnt, int cap, const int *__restrict__ row_of_atom,
+          const float *__restrict__ dG, int ldg, int N, AevConst c, unsigned long long *__restrict__ Ffix,
+          float *__restrict__ W_atom) {
+  extern __shared__ float4 lds4[];
+  // the wave index is uniform across the wave: keep it (and the centre's
+  // index, descriptors and row pointers) in scalar registers
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave), lane = threadIdx.x % kWave;
+  const int i = blockIdx.x * WPB + wave;
+  if (i >= N) return;
+  WaveLds w = carve<true>((char *)lds4 + wave * wave_lds_bytes<true>(cap), cap);
+  bwd_centre(i, lane, pos, sys_of, sys, nbr, nbr_cnt, cap, row_of_atom, dG, ldg, c, W_atom, w, SinkGlobal{Ffix});
+}
+
+// Next centre of a workgroup's group for the calling wave (an LDS counter:
+// waves that finish early take more centres).
+__device__ inline int next_centre(int *counter, int lane) {
+  int p = 0;
+  if (lane == 0) p = atomicAdd(counter, 1);
+  return __builtin_amdgcn_readfirstlane(p);
+}
+
+// Per-system form (batches of small non-periodic systems): a workgroup takes
+// a group of consecutive centres of one system (groups[b] = {first centre,
+// count}); the system's forces are summed in an LDS table and added into
+// Ffix once.
+template <int WPB>
+__global__ void __launch_bounds__(WPB * kWave) __attribute__((amdgpu_waves_per_eu(5)))
+k_aev_bwd_sys(const int2 *__restrict__ groups, const float4 *__restrict__ pos, const int *__restrict__ sys_of,
+              const SysDesc *__restrict__ sys, const int2 *__restrict__ nbr,
+              const int *__restrict__ nbr_cnt, int cap, const int *__restrict__ row_of_atom,
+              const float *__restrict__ dG, int ldg, AevConst c, unsigned long long *__restrict__ Ffix,
+              float *__restrict__ W_atom) {
+  extern __shared__ float4 lds4[];
+  __shared__ int counter;
+  const int2 gr = groups[blockIdx.x];
+  const SysDesc &d = sys[sys_of[gr.x]];
+  const int off = d.atom_off, n3 = 3 * d.n;
+  unsigned long long *tab = (unsigned long long *)((char *)lds4 + WPB * wave_lds_bytes<true>(cap));
+  for (int t = threadIdx.x; t < n3; t += WPB * kWave) tab[t] = 0ull;
+  if (threadIdx.x == 0) counter = 0;
+  __syncthreads();
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave), lane = threadIdx.x % kWave;
+  WaveLds w = carve<true>((char *)lds4 + wave * wave_lds_bytes<true>(cap), cap);
+  const SinkSys sink{tab, off};
+  for (int p = next_centre(&counter, lane); p < gr.y; p = next_centre(&counter, lane))
+    bwd_centre(gr.x + p, lane, pos, sys_of, sys, nbr, nbr_cnt, cap, row_of_atom, dG, ldg, c, W_atom, w, sink);
+  __syncthreads();
+  for (int t = threadIdx.x; t < n3; t += WPB * kWave) {
+    const unsigned long long v = tab[t];
+    if (v) atomicAdd(Ffix + 3 * (size_t)off + t, v);
+  }
+}
+
+// Per-cell form (cell grids): a workgroup takes the centres of one cell;
+// they share most of their neighbours, whose forces are summed in an LDS hash
+// table and added into Ffix once per cell.
+template <int WPB>
+__global__ void __launch_bounds__(WPB * kWave) __attribute__((amdgpu_waves_per_eu(5)))
+k_aev_bwd_cells(const int *__restrict__ cell_start, const int *__restrict__ cell_atoms,
+                const float4 *__restrict__ pos, const int *__restrict__ sys_of,
+                const SysDesc *__restrict__ sys, const int2 *__restrict__ nbr,
+                const int *__restrict__ nbr_cnt, int cap, const int *__restrict__ row_of_atom,
+                const float *__restrict__ dG, int ldg, AevConst c, unsigned long long *__restrict__ Ffix,
+                float *__restrict__ W_atom) {
+  extern __shared__ float4 lds4[];
+  __shared__ int counter;
+  const int b = cell_start[blockIdx.x], e = cell_start[blockIdx.x + 1];
+  if (b == e) return;  // the whole workgroup leaves together
+  char *tail = (char *)lds4 + WPB * wave_lds_bytes<true>(cap);
+  unsigned long long *hval = (unsigned long long *)tail;
+  int *hkey = (int *)(tail + 24 * kBwdHash);
+  for (int t = threadIdx.x; t < kBwdHash; t += WPB * kWave) {
+    hkey[t] = -1;
+    hval[3 * t] = hval[3 * t + 1] = hval[3 * t + 2] = 0ull;
+  }
+  if (threadIdx.x == 0) counter = 0;
+  __syncthreads();
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave), lane = threadIdx.x % kWave;
+  WaveLds w = carve<true>((char *)lds4 + wave * wave_lds_bytes<true>(cap), cap);
+  const SinkHash sink{hkey, hval, Ffix};
+  for (int p = next_centre(&counter, lane); b + p < e; p = next_centre(&counter, lane))
+    bwd_centre(cell_atoms[b + p], lane, pos, sys_of, sys, nbr, nbr_cnt, cap, row_of_atom, dG, ldg, c, W_atom, w,
+               sink);
+  __syncthreads();
+  for (int t = threadIdx.x; t < kBwdHash; t += WPB * kWave) {
+    const int j = hkey[t];
+    if (j < 0) continue;
+    unsigned long long *p = Ffix + 3 * (size_t)j;
+    for (int q = 0; q < 3; ++q) {
+      const unsigned long long v = hval[3 * t + q];
+      if (v) atomicAdd(p + q, v);
     }
   }
 }
@@ -838,29 +982,77 @@ void launch_aev_fwd(const float4 *pos, const int *sys_of, const SysDesc *sys, co
   else aev_fwd_t<false>(pos, sys_of, sys, nbr, nbr_cnt, cap, row_of_atom, G, ldg, N, c, wpb_pref, st);
 }
 
-template <int OCC>
-static void aev_bwd_t(const float4 *pos, const int *sys_of, const SysDesc *sys, const int2 *nbr,
-                      const int *nbr_cnt, int cap, const int *row_of_atom, const float *dG, int ldg,
-                      int N, const AevConst &c, float *F, float *W_atom, int wpb, hipStream_t st) {
-  size_t lds = wave_lds_bytes<true>(cap) * wpb;
-  unsigned grid = (unsigned)((N + wpb - 1) / wpb);
-  if (wpb == 4)
-    k_aev_bwd<4, OCC><<<grid, 4 * kWave, lds, st>>>(pos, sys_of, sys, nbr, nbr_cnt, cap, row_of_atom, dG, ldg, N, c, F, W_atom);
-  else if (wpb == 2)
-    k_aev_bwd<2, OCC><<<grid, 2 * kWave, lds, st>>>(pos, sys_of, sys, nbr, nbr_cnt, cap, row_of_atom, dG, ldg, N, c, F, W_atom);
-  else
-    k_aev_bwd<1, OCC><<<grid, kWave, lds, st>>>(pos, sys_of, sys, nbr, nbr_cnt, cap, row_of_atom, dG, ldg, N, c, F, W_atom);
+template <int WPB>
+static void aev_bwd_launch(int form, size_t lds, unsigned grid, const AevBwdGroups &gp, const float4 *pos,
+                           const int *sys_of, const SysDesc *sys, const int2 *nbr, const int *nbr_cnt, int cap,
+                           const int *row_of_atom, const float *dG, int ldg, int N, const AevConst &c,
+                           unsigned long long *Ffix, float *W_atom, hipStream_t st) {
+  if constexpr (WPB >= 4) {  // grouped forms run 4 to 8 waves per workgroup
+    if (form == 1) {
+      k_aev_bwd_sys<WPB><<<grid, WPB * kWave, lds, st>>>(gp.groups, pos, sys_of, sys, nbr, nbr_cnt, cap,
+                                                         row_of_atom, dG, ldg, c, Ffix, W_atom);
+      return;
+    }
+    if (form == 2) {
+      k_aev_bwd_cells<WPB><<<grid, WPB * kWave, lds, st>>>(gp.cell_start, gp.cell_atoms, pos, sys_of, sys, nbr,
+                                                           nbr_cnt, cap, row_of_atom, dG, ldg, c, Ffix, W_atom);
+      return;
+    }
+  }
+  k_aev_bwd<WPB><<<grid, WPB * kWave, lds, st>>>(pos, sys_of, sys, nbr, nbr_cnt, cap, row_of_atom, dG, ldg, N, c,
+                                                 Ffix, W_atom);
 }
 
+// Chooses the form: per system when the call is a batch of small
+// non-periodic systems (gp.groups), per cell on a grid of at least
+// kBwdMinCells cells (fewer would leave compute units idle), else per
+// centre.  Grouped forms run 8 waves per workgroup unless the tuned
+// preference is 4 or 6; the per-centre form takes the preference 1, 2 or 4.
 void launch_aev_bwd(const float4 *pos, const int *sys_of, const SysDesc *sys, const int2 *nbr,
                     const int *nbr_cnt, int cap, const int *row_of_atom, const float *dG, int ldg,
-                    int N, const AevConst &c, float *F, float *W_atom, int wpb_pref, hipStream_t st) {
+                    int N, const AevConst &c, unsigned long long *Ffix, float *W_atom, const AevBwdGroups &gp,
+                    int wpb_pref, size_t max_lds, hipStream_t st) {
   if (N <= 0) return;
+  const size_t per = wave_lds_bytes<true>(cap);
+  int form = 0;
+  size_t table = 0;
+  if (gp.groups && gp.n_groups > 0) {
+    form = 1;
+    table = ((size_t)gp.max_sys_atoms * 24 + 15) / 16 * 16;
+  } else if (gp.cell_start && gp.n_cells >= kBwdMinCells) {
+    form = 2;
+    table = (size_t)kBwdHash * 28;
+  }
+  if (form) {
+    int wpb = (wpb_pref == 4 || wpb_pref == 6) ? wpb_pref : 8;
+    while (wpb > 1 && per * wpb + table > max_lds) wpb = wpb == 8 ? 6 : wpb == 6 ? 4 : 1;
+    if (wpb > 1) {
+      const size_t lds = per * wpb + table;
+      const unsigned grid = (unsigned)(form == 1 ? gp.n_groups : gp.n_cells);
+      if (wpb == 8)
+        aev_bwd_launch<8>(form, lds, grid, gp, pos, sys_of, sys, nbr, nbr_cnt, cap, row_of_atom, dG, ldg, N, c,
+                          Ffix, W_atom, st);
+      else if (wpb == 6)
+        aev_bwd_launch<6>(form, lds, grid, gp, pos, sys_of, sys, nbr, nbr_cnt, cap, row_of_atom, dG, ldg, N, c,
+                          Ffix, W_atom, st);
+      else
+        aev_bwd_launch<4>(form, lds, grid, gp, pos, sys_of, sys, nbr, nbr_cnt, cap, row_of_atom, dG, ldg, N, c,
+                          Ffix, W_atom, st);
+      return;
+    }
+  }
   const int wpb = waves_for_cap<true>(cap, wpb_pref);
-  // no register bound: holding the kernel to 6 waves per SIMD (where the
-  // LDS allows 6) spilled and was 3% slower on the 100k-atom box than the
-  // unbounded allocation
-  aev_bwd_t<0>(pos, sys_of, sys, nbr, nbr_cnt, cap, row_of_atom, dG, ldg, N, c, F, W_atom, wpb, st);
+  const size_t lds = per * wpb;
+  const unsigned grid = (unsigned)((N + wpb - 1) / wpb);
+  if (wpb == 4)
+    aev_bwd_launch<4>(0, lds, grid, gp, pos, sys_of, sys, nbr, nbr_cnt, cap, row_of_atom, dG, ldg, N, c, Ffix,
+                      W_atom, st);
+  else if (wpb == 2)
+    aev_bwd_launch<2>(0, lds, grid, gp, pos, sys_of, sys, nbr, nbr_cnt, cap, row_of_atom, dG, ldg, N, c, Ffix,
+                      W_atom, st);
+  else
+    aev_bwd_launch<1>(0, lds, grid, gp, pos, sys_of, sys, nbr, nbr_cnt, cap, row_of_atom, dG, ldg, N, c, Ffix,
+                      W_atom, st);
 }
 
 }  // namespace nnp

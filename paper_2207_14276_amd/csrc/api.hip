@@ -83,6 +83,18 @@ const char *kStageNames[kStages] = {"ingest", "cells", "neighbours", "buckets",
 
 }  // namespace
 
+// Pinned staging of per-call descriptors.  A call copies its descriptors
+// from the next slot of the ring; it waits only when that slot's previous
+// copy (kStageSlots calls back) has not completed yet.
+constexpr int kStageSlots = 32;
+constexpr size_t kStageInitBytes = 16 * 1024;
+struct StageSlot {
+  void *p = nullptr;
+  size_t bytes = 0;
+  hipEvent_t done = nullptr;
+  bool pending = false;
+};
+
 struct LayerW {
   float *W = nullptr;       // [out][in] float32
   float *Wt = nullptr;      // [in][out] float32
@@ -118,6 +130,8 @@ struct nnp_model {
   DevBuf pos, sys_of, atom_cell, atom_slot, cell_count, cell_start, cell_atoms, nbr, nbr_cnt;
   DevBuf block_counts, bucket_off, bucket_cnt, perm, row_of_atom, G, dG, e_atom, W_atom, partial;
   DevBuf desc, status, state, e_mem, dp_rec;  // desc: the per-call descriptors (desc_layout)
+  DevBuf Ffix;                           // AEV models: forces in 64-bit fixed point [N][3]
+  size_t max_lds = 64 * 1024;            // LDS bytes one workgroup may use on this device
   std::vector<DevBuf> H, Gd;
   // fused hidden-layer chain (bfloat16 models whose hidden widths allow it)
   bool chain = false;
@@ -125,11 +139,10 @@ struct nnp_model {
   DevBuf chain_nets;                     // [member][species] ChainNet
   ChainLaunch chain_proto{};             // strides and LDS layout, filled at creation
   size_t chain_lds = 0;
-  // host staging (pinned) for per-call descriptors
-  void *stage = nullptr;
-  size_t stage_bytes = 0;
-  hipEvent_t stage_done = nullptr;
-  bool stage_pending = false;
+  // host staging (pinned) for per-call descriptors: a ring of slots, each
+  // reused once the copy that last read it has completed
+  StageSlot stage[kStageSlots];
+  int stage_next = 0;
   // tuned launch shapes (0: default) and the per-site events of a tuning run
   int tune_val[kTuneSites] = {};
   bool tuning = false;
@@ -182,12 +195,14 @@ extern "C" void nnp_destroy(nnp_model *m) {
                     &m->cell_start, &m->cell_atoms, &m->nbr, &m->nbr_cnt, &m->block_counts,
                     &m->bucket_off, &m->bucket_cnt, &m->perm, &m->row_of_atom, &m->G, &m->dG,
                     &m->e_atom, &m->W_atom, &m->partial, &m->desc, &m->status, &m->state, &m->e_mem,
-                    &m->chain_nets, &m->dp_rec};
+                    &m->chain_nets, &m->dp_rec, &m->Ffix};
   for (DevBuf *b : bufs) b->release();
   for (auto &b : m->H) b.release();
   for (auto &b : m->Gd) b.release();
-  if (m->stage) (void)hipHostFree(m->stage);
-  if (m->stage_done) (void)hipEventDestroy(m->stage_done);
+  for (StageSlot &ss : m->stage) {
+    if (ss.p) (void)hipHostFree(ss.p);
+    if (ss.done) (void)hipEventDestroy(ss.done);
+  }
   for (auto &set : m->evsets)
     for (auto &e : set)
       if (e) (void)hipEventDestroy(e);
@@ -310,6 +325,11 @@ static int create_networks(const NetArgs *d, nnp_model *m) {
   m->Gd.resize(std::max(L - 1, 0));
 
   HIP_TRY(hipGetDevice(&m->device));
+  {
+    int max_lds = 0;
+    HIP_TRY(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, m->device));
+    m->max_lds = (size_t)max_lds;
+  }
   m->layers.resize((size_t)m->M * S * L);
   const float *wp = d->weights;
   std::vector<float> tmp;
@@ -415,59 +435,75 @@ static int create_networks(const NetArgs *d, nnp_model *m) {
       HIP_TRY(hipMemcpy(m->chain_nets.p, nets.data(), nets.size() * sizeof(ChainNet), hipMemcpyHostToDevice));
       m->chain = true;
       m->chain_lds = lds;
-      int max_lds = 0;
-      HIP_TRY(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, m->device));
-      m->chain_rt2 = 2 * lds <= (size_t)max_lds;
+      m->chain_rt2 = 2 * lds <= m->max_lds;
     }
   }
-  HIP_TRY(hipEventCreateWithFlags(&m->stage_done, hipEventDisableTiming));
+  for (StageSlot &ss : m->stage) {
+    HIP_TRY(hipEventCreateWithFlags(&ss.done, hipEventDisableTiming | hipEventDisableSystemFence));
+    HIP_TRY(hipHostMalloc(&ss.p, kStageInitBytes, hipHostMallocDefault));
+    ss.bytes = kStageInitBytes;
+  }
   int rc = m->status.ensure(2 * sizeof(int));
   if (rc) return rc;
   HIP_TRY(hipMemset(m->status.p, 0, 2 * sizeof(int)));
   return NNP_OK;
 }
 
-extern "C" int nnp_create(const nnp_model_desc *d, nnp_model **out) {
+// Runs create on hip_device (< 0: the current device), restoring the
+// caller's current device afterwards.
+template <class Desc, class Impl>
+static int create_on(const Desc *d, int hip_device, nnp_model **out, Impl impl) {
   if (!d || !out) return fail(NNP_EINVAL, "null argument");
   *out = nullptr;
+  int prev = 0;
+  HIP_TRY(hipGetDevice(&prev));
+  if (hip_device >= 0) {
+    int n = 0;
+    HIP_TRY(hipGetDeviceCount(&n));
+    if (hip_device >= n) return fail(NNP_EINVAL, "hip_device %d: the node has %d devices", hip_device, n);
+    HIP_TRY(hipSetDevice(hip_device));
+  }
   nnp_model *m = new nnp_model();
-  int rc = create_impl(d, m);
+  int rc = impl(d, m);
   if (rc != NNP_OK) {
     nnp_destroy(m);
-    return rc;
+  } else {
+    *out = m;
   }
-  *out = m;
-  return NNP_OK;
+  (void)hipSetDevice(prev);
+  return rc;
 }
 
-extern "C" int nnp_create_dp(const nnp_dp_model_desc *d, nnp_model **out) {
-  if (!d || !out) return fail(NNP_EINVAL, "null argument");
-  *out = nullptr;
-  nnp_model *m = new nnp_model();
-  int rc = create_dp_impl(d, m);
-  if (rc != NNP_OK) {
-    nnp_destroy(m);
-    return rc;
-  }
-  *out = m;
-  return NNP_OK;
+extern "C" int nnp_create(const nnp_model_desc *d, int hip_device, nnp_model **out) {
+  return create_on(d, hip_device, out, create_impl);
+}
+
+extern "C" int nnp_create_dp(const nnp_dp_model_desc *d, int hip_device, nnp_model **out) {
+  return create_on(d, hip_device, out, create_dp_impl);
 }
 
 extern "C" int nnp_aev_dim(const nnp_model *m) { return m ? m->D : NNP_EINVAL; }
 
 // Layout of the per-call descriptors, the same in pinned staging memory and
 // in the device buffer: SysDesc[S], chunk system[n_chunks], chunk first
-// atom[n_chunks], first chunk of each system[S + 1].
+// atom[n_chunks], first chunk of each system[S + 1], backward centre groups
+// int2[n_groups] (8-byte aligned).
 struct DescLayout {
-  size_t sd, cs, cb, so, total;
-  DescLayout(int S, int n_chunks) {
+  size_t sd, cs, cb, so, gr, total;
+  DescLayout(int S, int n_chunks, int n_groups) {
     sd = 0;
     cs = sd + sizeof(SysDesc) * (size_t)S;
     cb = cs + 4 * (size_t)n_chunks;
     so = cb + 4 * (size_t)n_chunks;
-    total = so + 4 * (size_t)(S + 1);
+    gr = (so + 4 * (size_t)(S + 1) + 7) / 8 * 8;
+    total = gr + 8 * (size_t)n_groups;
   }
 };
+
+// Centres per group of the AEV backward's per-system form.
+constexpr int kBwdGroup = 16;
+// Groups of a call of small systems: at most this many per atom.
+static int64_t max_bwd_groups(int64_t N, int S) { return N / kBwdGroup + S + 1; }
 
 // Buffers for a call of N atoms, S systems, C cells and n_chunks chunks.
 // Workspace of a call with N atoms, S systems, C cells and n_chunks
@@ -505,7 +541,8 @@ static int for_each_ws(nnp_model *m, int64_t N, int S, int64_t C, int n_chunks, 
   if (m->chain) ENS(m->e_mem, rows * m->M * 4);
   ENS(m->W_atom, N * 36);
   ENS(m->partial, (int64_t)n_chunks * 80 + 80);
-  ENS(m->desc, DescLayout(S, n_chunks).total);
+  ENS(m->desc, DescLayout(S, n_chunks, (int)max_bwd_groups(N, S)).total);
+  if (m->kind == kDescAev) ENS(m->Ffix, N * 24);
   for (int l = 0; l + 1 < m->L; ++l) {
     ENS(m->H[l], rows * m->ldH[l] * m->M * esz);
     ENS(m->Gd[l], rows * m->ldH[l] * m->M * esz);
@@ -770,6 +807,24 @@ static int run(nnp_model *m, int n_sys, const int64_t *offs, const float *coords
     }
   }
   sys_ch[n_sys] = (int)ch_sys.size();
+  // every system small and without a box: a direct scan per system
+  bool all_small = !pairs && N > 0;
+  for (int s = 0; s < n_sys && all_small; ++s) all_small = !sd[s].periodic && sd[s].n <= kSmallSystem;
+  // centre groups of the AEV backward's per-system form: consecutive centres
+  // of one system, the systems in order of decreasing size (the costliest
+  // groups start first)
+  std::vector<int2> groups;
+  int max_sys_atoms = 0;
+  if (all_small && mode == kFull && o.forces && m->kind == kDescAev) {
+    std::vector<int> order(n_sys);
+    for (int s = 0; s < n_sys; ++s) order[s] = s;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return sd[a].n > sd[b].n; });
+    for (int s : order) {
+      max_sys_atoms = std::max(max_sys_atoms, sd[s].n);
+      for (int p = 0; p < sd[s].n; p += kBwdGroup)
+        groups.push_back(make_int2(sd[s].atom_off + p, std::min(kBwdGroup, sd[s].n - p)));
+    }
+  }
   bool one_chunk_each = true;
   for (int s = 0; s < n_sys && one_chunk_each; ++s) one_chunk_each = sys_ch[s + 1] - sys_ch[s] == 1;
   const int n_chunks = (int)ch_sys.size();
@@ -777,37 +832,43 @@ static int run(nnp_model *m, int n_sys, const int64_t *offs, const float *coords
   int rc = ensure_ws(m, N, n_sys, C, n_chunks, nl != nullptr);
   if (rc) return rc;
   if (m->G.bytes != m->G_zeroed) {
-    // a newly allocated G: clear it once so that the columns past the AEV
-    // length (never written) read as zeros in the first-layer GEMM
-    HIP_TRY(hipMemsetAsync(m->G.p, 0, m->G.bytes, st));
+    // a newly allocated G: clear it once (with the library's fill kernel) so
+    // that the columns past the AEV length (never written) read as zeros in
+    // the first-layer GEMM
+    launch_fill_i32(m->G.as<int>(), m->G.bytes / 4, 0, st);
     m->G_zeroed = m->G.bytes;
   }
 
   // stage the per-call descriptors through pinned memory; one copy moves them
   // all into the device buffer of the same layout
-  const DescLayout dl(n_sys, n_chunks);
+  const DescLayout dl(n_sys, n_chunks, (int)groups.size());
   const size_t off_sd = dl.sd, off_cs = dl.cs, off_cb = dl.cb, off_so = dl.so, total = dl.total;
-  if (m->stage_pending) {
-    HIP_TRY(hipEventSynchronize(m->stage_done));
-    m->stage_pending = false;
+  StageSlot &ss = m->stage[m->stage_next];
+  m->stage_next = (m->stage_next + 1) % kStageSlots;
+  if (ss.pending) {
+    // kStageSlots calls are in flight: wait for the oldest one's copy
+    HIP_TRY(hipEventSynchronize(ss.done));
+    ss.pending = false;
   }
-  if (total > m->stage_bytes) {
-    if (m->stage) HIP_TRY(hipHostFree(m->stage));
-    m->stage = nullptr;
+  if (total > ss.bytes) {
+    if (ss.p) HIP_TRY(hipHostFree(ss.p));
+    ss.p = nullptr;
+    ss.bytes = 0;
     size_t nb = total + total / 2 + 4096;
-    HIP_TRY(hipHostMalloc(&m->stage, nb, hipHostMallocDefault));
-    m->stage_bytes = nb;
+    HIP_TRY(hipHostMalloc(&ss.p, nb, hipHostMallocDefault));
+    ss.bytes = nb;
   }
-  char *hs = (char *)m->stage;
+  char *hs = (char *)ss.p;
   memcpy(hs + off_sd, sd.data(), sizeof(SysDesc) * n_sys);
   if (n_chunks) {
     memcpy(hs + off_cs, ch_sys.data(), 4 * (size_t)n_chunks);
     memcpy(hs + off_cb, ch_begin.data(), 4 * (size_t)n_chunks);
   }
   memcpy(hs + off_so, sys_ch.data(), 4 * (size_t)(n_sys + 1));
+  if (!groups.empty()) memcpy(hs + dl.gr, groups.data(), 8 * groups.size());
   HIP_TRY(hipMemcpyAsync(m->desc.p, hs, total, hipMemcpyHostToDevice, st));
-  HIP_TRY(hipEventRecord(m->stage_done, st));
-  m->stage_pending = true;
+  HIP_TRY(hipEventRecord(ss.done, st));
+  ss.pending = true;
 
   int stage = 0;
   hipEvent_t *ev = nullptr;
@@ -840,12 +901,13 @@ static int run(nnp_model *m, int n_sys, const int64_t *offs, const float *coords
   int *pool_cnt = nl ? nl->cnt.as<int>() : m->nbr_cnt.as<int>();
   AtomState *pool_state = nl ? nl->state.as<AtomState>() : m->state.as<AtomState>();
   if (nl) launch_skin_check(coords, dsys, n_sys, pool_state, 0.5f * nl->skin, nl->stats.as<int>(), st);
+  // AEV models accumulate forces in fixed point (converted by the reduction),
+  // DeepPot-style models in float32 straight in the output
+  const bool fix_forces = mode == kFull && o.forces && m->kind == kDescAev;
+  unsigned long long *Ffix = fix_forces ? m->Ffix.as<unsigned long long>() : nullptr;
   launch_ingest(coords, species, pin.mask, dsys, n_sys, N, m->S, pos, m->sys_of.as<int>(), pool_state,
-                status, mode == kFull ? o.forces : nullptr, st);
+                status, mode == kFull && !fix_forces ? o.forces : nullptr, Ffix, st);
   mark();
-  // every system small and without a box: a direct scan per system
-  bool all_small = !pairs && N > 0;
-  for (int s = 0; s < n_sys && all_small; ++s) all_small = !sd[s].periodic && sd[s].n <= kSmallSystem;
   if (pairs) {
     // the caller's list replaces the cell search (stage "cells" stays empty)
     mark();
@@ -1053,16 +1115,26 @@ static int run(nnp_model *m, int n_sys, const int64_t *offs, const float *coords
                     m->cell_atoms.as<int>(), (int)C, m->row_of_atom.as<int>(), m->dG.as<float>(), D, N, m->dp,
                     m->dp_rec.as<float4>(), o.forces, m->W_atom.as<float>(), m->tune_val[kSiteAevBwd], st);
     } else {
+      AevBwdGroups gp;
+      if (!groups.empty()) {
+        gp.groups = (const int2 *)(m->desc.as<char>() + dl.gr);
+        gp.n_groups = (int)groups.size();
+        gp.max_sys_atoms = max_sys_atoms;
+      } else if (!pairs && !all_small) {
+        gp.cell_start = m->cell_start.as<int>();
+        gp.cell_atoms = m->cell_atoms.as<int>();
+        gp.n_cells = (int)C;
+      }
       launch_aev_bwd(pos, m->sys_of.as<int>(), dsys, pool_nbr, pool_cnt, cap,
-                     m->row_of_atom.as<int>(), m->dG.as<float>(), D, N, m->aev, o.forces,
-                     m->W_atom.as<float>(), m->tune_val[kSiteAevBwd], st);
+                     m->row_of_atom.as<int>(), m->dG.as<float>(), D, N, m->aev, Ffix,
+                     m->W_atom.as<float>(), gp, m->tune_val[kSiteAevBwd], m->max_lds, st);
     }
     site_end(kSiteAevBwd);
   }
   mark();
   launch_reduce(e_atom, want_grad ? m->W_atom.as<float>() : nullptr, dsys, n_sys,
                 d_chunk_sys, d_chunk_begin, n_chunks, d_sys_chunk_off, one_chunk_each,
-                m->partial.as<double>(), o.energy, o.virial, st);
+                m->partial.as<double>(), o.energy, o.virial, Ffix, o.forces, st);
   mark();
   if (ev) m->last_stages = stage - 1;
   HIP_TRY(hipGetLastError());

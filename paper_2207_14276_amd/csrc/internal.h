@@ -187,9 +187,11 @@ struct EnergyLaunch {
 void launch_skin_check(const float *coords, SysDesc *sys, int n_sys, const AtomState *state,
                        float half_skin, int *stats, hipStream_t st);
 // zero_forces (nullable): the force output, cleared here for the backward
+// zero_fix (nullable): the fixed-point force accumulators, cleared here
 void launch_ingest(const float *coords, const int *species, const unsigned char *mask,
                    const SysDesc *sys, int n_sys, int N, int S, float4 *pos, int *sys_of,
-                   AtomState *state, int *status, float *zero_forces, hipStream_t st);
+                   AtomState *state, int *status, float *zero_forces, unsigned long long *zero_fix,
+                   hipStream_t st);
 constexpr int kSmallSystem = 512;   // largest non-periodic system of the small-system search
 void launch_nbr_small(const float4 *pos, const int *sys_of, const SysDesc *sys, int N, float rc_list,
                       int cap, int2 *nbr, int *nbr_cnt, int *status, hipStream_t st);
@@ -223,9 +225,21 @@ void launch_dp_bwd(const SysDesc *sys, int n_sys, bool small_systems, const int 
 void launch_aev_fwd(const float4 *pos, const int *sys_of, const SysDesc *sys, const int2 *nbr,
                     const int *nbr_cnt, int cap, const int *row_of_atom, void *G, bool g_bf16,
                     int ldg, int N, const AevConst &c, int wpb_pref, hipStream_t st);
+// How the AEV backward groups its centres (at most one of the two forms):
+// groups[n_groups] = {first centre, count} of consecutive centres of one
+// small non-periodic system (max_sys_atoms: the largest such system), or the
+// cell grid of the call.  Neither: one wave per centre.
+struct AevBwdGroups {
+  const int2 *groups = nullptr;
+  int n_groups = 0, max_sys_atoms = 0;
+  const int *cell_start = nullptr, *cell_atoms = nullptr;
+  int n_cells = 0;
+};
+// Forces go into Ffix [N][3] (64-bit fixed point, cleared by the caller).
 void launch_aev_bwd(const float4 *pos, const int *sys_of, const SysDesc *sys, const int2 *nbr,
                     const int *nbr_cnt, int cap, const int *row_of_atom, const float *dG,
-                    int ldg, int N, const AevConst &c, float *F, float *W_atom, int wpb_pref, hipStream_t st);
+                    int ldg, int N, const AevConst &c, unsigned long long *Ffix, float *W_atom,
+                    const AevBwdGroups &gp, int wpb_pref, size_t max_lds, hipStream_t st);
 // tn_pref: column-tile width 64 or 128 (anything else: the width heuristic);
 // wpb_pref below: waves per workgroup 1, 2 or 4 when the LDS fits (else the default).
 void launch_gemm(int epi, bool bf16, GemmLaunch gl, int row_tiles, int max_n_out, int tn_pref, hipStream_t st);
@@ -236,10 +250,11 @@ void launch_chain(ChainLaunch cl, int n_hidden, bool grad, int rows, size_t lds_
                   hipStream_t st);
 void launch_fill(float *p, size_t n, float v, hipStream_t st);
 void launch_fill_i32(int *p, size_t n, int v, hipStream_t st);
+// Ffix (nullable): fixed-point forces, converted into F [N][3] float32 here
 void launch_reduce(const float *e_atom, const float *W_atom, const SysDesc *sys, int n_sys,
                    const int *chunk_sys, const int *chunk_begin, int n_chunks,
                    const int *sys_chunk_off, bool one_chunk_each, double *partial, double *energy, double *virial,
-                   hipStream_t st);
+                   const unsigned long long *Ffix, float *F, hipStream_t st);
 void launch_gather_rows(const float *src, int ld, const int *row_of_atom, int N, int D,
                         float *dst, hipStream_t st);
 void launch_export_nbr(const int2 *nbr, const int *nbr_cnt, int cap, const SysDesc *sys,

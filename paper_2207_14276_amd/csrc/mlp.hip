@@ -19,6 +19,7 @@
 // LDS.  Blocks are renumbered so that consecutive logical blocks (which share
 // an A row tile) run on the same XCD and hit the same L2.
 #include "internal.h"
+#include "fixed.h"
 
 #include <algorithm>
 
@@ -642,7 +643,8 @@ __global__ void __launch_bounds__(256)
 k_reduce_partial(const float *__restrict__ e_atom, const float *__restrict__ W_atom,
                  const SysDesc *__restrict__ sys, const int *__restrict__ chunk_sys,
                  const int *__restrict__ chunk_begin, double *__restrict__ partial,
-                 double *__restrict__ energy, double *__restrict__ virial) {
+                 double *__restrict__ energy, double *__restrict__ virial,
+                 const unsigned long long *__restrict__ Ffix, float *__restrict__ F) {
   __shared__ double red[10][256 / kWave];
   const int ch = blockIdx.x;
   const SysDesc &d = sys[chunk_sys[ch]];
@@ -655,6 +657,9 @@ k_reduce_partial(const float *__restrict__ e_atom, const float *__restrict__ W_a
     if (W_atom)
       for (int q = 0; q < 9; ++q) acc[1 + q] += (double)W_atom[(size_t)9 * i + q];
   }
+  // fixed-point forces of the chunk's atoms to float32
+  if (Ffix)
+    for (int t = 3 * b + threadIdx.x; t < 3 * e; t += blockDim.x) F[t] = from_fix((long long)Ffix[t]);
   const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
   for (int q = 0; q < 10; ++q) {
     double v = acc[q];
@@ -691,13 +696,13 @@ __global__ void k_reduce_final(const double *__restrict__ partial, const int *__
 void launch_reduce(const float *e_atom, const float *W_atom, const SysDesc *sys, int n_sys,
                    const int *chunk_sys, const int *chunk_begin, int n_chunks,
                    const int *sys_chunk_off, bool one_chunk_each, double *partial, double *energy,
-                   double *virial, hipStream_t st) {
+                   double *virial, const unsigned long long *Ffix, float *F, hipStream_t st) {
   const bool direct = one_chunk_each && n_chunks == n_sys;
   // every system exactly one chunk (chunk s is system s): the chunk sums are
   // the system sums, no second pass
   if (n_chunks > 0)
     k_reduce_partial<<<n_chunks, 256, 0, st>>>(e_atom, W_atom, sys, chunk_sys, chunk_begin, partial,
-                                               direct ? energy : nullptr, direct ? virial : nullptr);
+                                               direct ? energy : nullptr, direct ? virial : nullptr, Ffix, F);
   if (n_sys > 0 && !direct)
     k_reduce_final<<<(n_sys + 127) / 128, 128, 0, st>>>(partial, sys_chunk_off, n_sys, energy, virial);
 }

@@ -17,7 +17,7 @@ __global__ void k_ingest(const float *__restrict__ coords, const int *__restrict
                          const SysDesc *__restrict__ sys, int n_sys, int N, int S,
                          float4 *__restrict__ pos, int *__restrict__ sys_of,
                          AtomState *__restrict__ state, int *__restrict__ status,
-                         float *__restrict__ zero_forces) {
+                         float *__restrict__ zero_forces, unsigned long long *__restrict__ zero_fix) {
   // the systems' first atoms, staged in LDS when they fit: the search below
   // then waits on LDS instead of on a chain of dependent global loads
   __shared__ int s_off[kIngestLdsSystems];
@@ -33,6 +33,11 @@ __global__ void k_ingest(const float *__restrict__ coords, const int *__restrict
     zero_forces[3 * (size_t)i] = 0.f;
     zero_forces[3 * (size_t)i + 1] = 0.f;
     zero_forces[3 * (size_t)i + 2] = 0.f;
+  }
+  if (zero_fix) {
+    zero_fix[3 * (size_t)i] = 0ull;
+    zero_fix[3 * (size_t)i + 1] = 0ull;
+    zero_fix[3 * (size_t)i + 2] = 0ull;
   }
   auto first_atom = [&](int k) { return staged ? s_off[k] : sys[k].atom_off; };
   // system of atom i: last s with atom_off <= i (binary search)
@@ -80,10 +85,11 @@ __global__ void k_ingest(const float *__restrict__ coords, const int *__restrict
 
 void launch_ingest(const float *coords, const int *species, const unsigned char *mask,
                    const SysDesc *sys, int n_sys, int N, int S, float4 *pos, int *sys_of,
-                   AtomState *state, int *status, float *zero_forces, hipStream_t st) {
+                   AtomState *state, int *status, float *zero_forces, unsigned long long *zero_fix,
+                   hipStream_t st) {
   if (N <= 0) return;
   k_ingest<<<(N + 255) / 256, 256, 0, st>>>(coords, species, mask, sys, n_sys, N, S, pos, sys_of,
-                                            state, status, zero_forces);
+                                            state, status, zero_forces, zero_fix);
 }
 
 // One wave per system: a system that keeps its neighbour list is rebuilt

@@ -76,8 +76,7 @@ class NNPModel:
                                      float(p.get("radial_scale", 0.25)))
             desc = nat.nnp_model_desc(aev, *nets)
             create = lib.nnp_create
-        with torch.cuda.device(self.device):
-            nat.check(create(C.byref(desc), C.byref(h)))
+        nat.check(create(C.byref(desc), int(self.device.index), C.byref(h)))
         self._h = h
         self.aev_dim = lib.nnp_aev_dim(h)
 

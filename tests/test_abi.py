@@ -42,7 +42,8 @@ def test_null_model_is_rejected_without_a_device():
 def test_null_descriptor_is_rejected():
     lib = nat.load()
     h = C.c_void_p()
-    assert lib.nnp_create(None, C.byref(h)) == nat.NNP_EINVAL
+    assert lib.nnp_create(None, -1, C.byref(h)) == nat.NNP_EINVAL
+    assert lib.nnp_create_dp(None, 0, C.byref(h)) == nat.NNP_EINVAL
     assert nat.last_error() != ""
 
 

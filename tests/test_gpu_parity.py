@@ -12,7 +12,8 @@ import pytest
 import torch
 
 import synth
-from tests.gpu_util import (BF16_E_PER_ATOM, BF16_F, FP32_E_ATOM, FP32_F, log, run_gpu, to_dev)
+from tests.gpu_util import (BF16_E_PER_ATOM, BF16_F, FP32_E_ATOM, FP32_F, log, run_gpu, to_dev,
+                            virial_bound)
 
 pytestmark = pytest.mark.gpu
 
@@ -135,6 +136,7 @@ def _check_energy_forces(model, oracle_lib, om, b, systems, e_atom_tol, e_sys_to
     gpu = run_gpu(model, b)
     ora = oracle_lib.batch_energy_forces(b, om, systems=systems)
     worst_ea = worst_es = worst_f = worst_w = 0.0
+    worst_wr = 0.0   # virial error as a fraction of its derived bound
     for q, k in enumerate(systems):
         a, e = int(b.offsets[k]), int(b.offsets[k + 1])
         n = e - a
@@ -144,16 +146,18 @@ def _check_energy_forces(model, oracle_lib, om, b, systems, e_atom_tol, e_sys_to
         worst_ea = max(worst_ea, float(np.abs(gpu["e_atom"][a:e] - ora["e_atom"][q]).max()))
         worst_es = max(worst_es, abs(gpu["energy"][k] - ora["energy"][q]) / n)
         worst_f = max(worst_f, float(np.abs(gpu["forces"][a:e] - ora["forces"][q]).max()))
-        worst_w = max(worst_w, float(np.abs(gpu["virial"][k] - ora["virial"][q]).max()) / n)
+        dw = float(np.abs(gpu["virial"][k] - ora["virial"][q]).max())
+        worst_w = max(worst_w, dw / n)
+        bound = virial_bound(b.coords[a:e], b.boxes[k], gpu["forces"][a:e], ora["forces"][q])
+        worst_wr = max(worst_wr, dw / bound)
     log(f"[{label}] max|dE_i|={worst_ea:.3e} max|dE_s|/N={worst_es:.3e} "
-        f"max|dF|={worst_f:.3e} max|dW|/N={worst_w:.3e}")
+        f"max|dF|={worst_f:.3e} max|dW|/N={worst_w:.3e} max|dW|/bound={worst_wr:.3f}")
     if e_atom_tol is not None:
         assert worst_ea <= e_atom_tol
     assert worst_es <= e_sys_tol
     assert worst_f <= f_tol
-    # the virial is a sum of d (x) dE/dd terms; per atom it carries the force
-    # error times a neighbour distance (< 5.1 A) times O(10) terms
-    assert worst_w <= 50 * f_tol
+    # the virial error follows from the force error (virial_bound)
+    assert worst_wr <= 1.0
     return gpu, ora
 
 
@@ -267,45 +271,80 @@ def _sampled64(oracle_lib, om, x64, s, targets):
     return e, f
 
 
+def _protein_box_samples(s, n_protein=30000, per_group=16, seed=3):
+    """Seeded atoms of the solvated-protein box in three groups: protein
+    interior (more than 6 A inside the sphere), the protein/water interface
+    (half protein atoms within 2.5 A of the sphere's surface, half waters
+    within 4 A outside it) and bulk water (more than 8 A outside it)."""
+    L = s.box.astype(np.float64)
+    x = s.coords.astype(np.float64)
+    r = np.linalg.norm(x - L / 2, axis=1)
+    R = np.linalg.norm(x[:n_protein] - L / 2, axis=1).max()
+    idx = np.arange(s.n)
+    rng = np.random.default_rng(seed)
+    draw = lambda v, k: np.sort(rng.choice(v, k, replace=False))
+    h = per_group // 2
+    return {"interior": draw(idx[(idx < n_protein) & (r < R - 6.0)], per_group),
+            "interface": np.concatenate([draw(idx[(idx < n_protein) & (r > R - 2.5)], h),
+                                         draw(idx[(idx >= n_protein) & (r < R + 4.0)], per_group - h)]),
+            "water": draw(idx[(idx >= n_protein) & (r > R + 8.0)], per_group)}
+
+
 def test_large_periodic_ensemble_sampled(oracle_lib):
     """~100k-atom periodic box with an ensemble of 8 networks, at full size in
-    one call; atomic energies and forces of 12 seeded atoms against the
-    oracle's local evaluation, plus the zero net force of the whole box."""
+    one call; atomic energies and forces of 48 seeded atoms (16 in the
+    protein's interior, 16 at the protein/water interface, 16 in bulk water)
+    against the oracle's local evaluation, plus the zero net force of the
+    whole box."""
     from paper_2207_14276_amd import NNPModel
     spec = synth.make_model(3, n_ensemble=8)
     s = synth.config3()
     b = synth.make_batch([s])
     om = oracle_lib.OracleModel(spec)
-    rng = np.random.default_rng(3)
-    t = np.sort(rng.choice(s.n, 12, replace=False))
+    groups = _protein_box_samples(s)
+    t = np.concatenate(list(groups.values()))
     e_ref, f_ref = oracle_lib.sampled(s.coords, s.species, s.box, om, t)
     for prec, e_tol, f_tol in (("fp32", FP32_E_ATOM, FP32_F), ("bf16", BF16_E_PER_ATOM, BF16_F)):
         m = NNPModel(spec, prec)
         gpu = run_gpu(m, b)
-        de = float(np.abs(gpu["e_atom"][t] - e_ref).max())
-        df = float(np.abs(gpu["forces"][t] - f_ref).max())
+        de_all = np.abs(gpu["e_atom"][t] - e_ref)
+        df_all = np.abs(gpu["forces"][t] - f_ref).max(1)
         net = float(np.abs(gpu["forces"].sum(0)).max())
-        log(f"[{prec} protein100k ens8] max|dE_i|={de:.3e} max|dF|={df:.3e} |sum F|={net:.3e}")
-        assert de <= e_tol
-        assert df <= f_tol
+        k = 0
+        for g, v in groups.items():
+            log(f"[{prec} protein100k ens8 {g}: {len(v)} atoms] max|dE_i|={de_all[k:k + len(v)].max():.3e} "
+                f"max|dF|={df_all[k:k + len(v)].max():.3e}")
+            k += len(v)
+        log(f"[{prec} protein100k ens8] |sum F|={net:.3e}")
+        assert float(de_all.max()) <= e_tol
+        assert float(df_all.max()) <= f_tol
         assert net <= 1e-3 * np.sqrt(s.n) * max(1.0, np.abs(gpu["forces"]).max())
         m.close()
 
 
-def test_batch_alone_vs_mix(m32):
-    """Each system gives the same result alone and inside a ragged batch."""
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_batch_alone_vs_mix(m32, m16, prec):
+    """Each system gives the same result alone and inside a ragged batch, bit
+    for bit: a row's dense-layer results do not depend on its tile, the AEV
+    backward's force sums are integer (fixed point), and the energy
+    reduction has a fixed order.  Also across repeated calls."""
+    model = m32 if prec == "fp32" else m16
     b = synth.ragged_solutes(24, seed=33)
-    mix = run_gpu(m32, b)
-    worst_e = worst_f = 0.0
+    mix = run_gpu(model, b)
+    again = run_gpu(model, b)
+    assert np.array_equal(mix["forces"], again["forces"])
+    assert np.array_equal(mix["energy"], again["energy"])
     for k in range(0, 24, 5):
         one = synth.make_batch([b.systems[k]])
-        alone = run_gpu(m32, one)
+        alone = run_gpu(model, one)
         a, e = int(b.offsets[k]), int(b.offsets[k + 1])
-        worst_e = max(worst_e, abs(alone["energy"][0] - mix["energy"][k]))
-        worst_f = max(worst_f, float(np.abs(alone["forces"] - mix["forces"][a:e]).max()))
-    log(f"[alone-vs-mix] max|dE|={worst_e:.3e} max|dF|={worst_f:.3e}")
-    assert worst_e <= 1e-9
-    assert worst_f <= 1e-5
+        de = abs(alone["energy"][0] - mix["energy"][k])
+        df = float(np.abs(alone["forces"] - mix["forces"][a:e]).max())
+        dw = float(np.abs(alone["virial"][0] - mix["virial"][k]).max())
+        log(f"[alone-vs-mix {prec} system {k}] |dE|={de:.3e} max|dF|={df:.3e} max|dW|={dw:.3e}")
+        assert de == 0.0
+        assert df == 0.0
+        assert dw == 0.0
 
 
 def test_edge_cases(m32, oracle_lib, om):
@@ -385,3 +424,35 @@ def test_autotune_changes_no_result(oracle_lib):
         assert np.array_equal(r1.energy.cpu().numpy(), e0)
         assert float(np.abs(r1.forces.cpu().numpy() - f0).max()) <= 1e-5
         m.close()
+
+
+def test_calls_only_enqueue(spec):
+    """nnp_energy_forces enqueues its work and returns: 64 back-to-back calls
+    on the 512-solute batch come back to the host well before the device has
+    finished them (a call waits only once 32 earlier calls' descriptor copies
+    are still in flight), and every call gives the first call's energies."""
+    from paper_2207_14276_amd import NNPModel
+    m = NNPModel(spec, "bf16")
+    b = synth.config2()
+    c, s, bx, o = to_dev(b)
+    m.reserve(b.n_atoms, b.n_systems, 160)
+    r0 = m.energy_forces(c, s, bx, o, check=True)
+    e0 = r0.energy.clone()
+    res = [m.energy_forces(c, s, bx, o) for _ in range(4)]  # outputs allocated before timing
+    torch.cuda.synchronize()
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    import time
+    start.record()
+    t0 = time.perf_counter()
+    for k in range(64):
+        m.energy_forces(c, s, bx, o, out=res[k % 4])
+    t_host = time.perf_counter() - t0
+    end.record()
+    torch.cuda.synchronize()
+    t_dev = start.elapsed_time(end) * 1e-3
+    m.status()
+    log(f"[enqueue] 64 calls: host {t_host * 1e3:.2f} ms, device {t_dev * 1e3:.2f} ms")
+    assert t_host < 0.9 * t_dev
+    for r in res:
+        assert torch.equal(r.energy, e0)
+    m.close()
