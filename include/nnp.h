@@ -345,14 +345,20 @@ void nnp_server_destroy(nnp_server *server);
 /* Seconds on the server's monotonic clock (0 at creation). */
 double nnp_server_clock(const nnp_server *server);
 /* Queues a request; t_arrival on the server clock (< 0: now).  *id receives
- * its handle (ids count up from 0).  NNP_EINVAL if it can never run. */
+ * its handle (ids count up from 0).  NNP_EINVAL if it can never run,
+ * NNP_ESPECIES if a species index is outside the model. */
 int nnp_server_submit(nnp_server *server, const nnp_request *req, double t_arrival, int64_t *id);
 /* Admits, launches one iteration on `stream` if any request is in flight,
  * and files the results of completed iterations (waiting while two are in
  * flight).  *pending (nullable) = requests queued or in flight plus
  * iterations not yet filed; 0 means everything submitted is finished.
- * A device flag (neighbour capacity, bad species) makes this and every later
- * step fail with NNP_ECAPACITY / NNP_ESPECIES. */
+ * A request whose neighbour list overflows the pool's capacity (on any
+ * build) stops alone: it is reported finished by nnp_server_poll and
+ * nnp_server_result returns NNP_ECAPACITY for it (naming the count), while
+ * every other request goes on unaffected (section "Massive Parallelism
+ * within Tinker-HP": buffers are bounded up front, and a request that does
+ * not fit must not bring the run down).  Species are checked when a request
+ * is submitted (NNP_ESPECIES). */
 int nnp_server_step(nnp_server *server, void *stream, int64_t *pending);
 /* Waits for every launched iteration and files its results. */
 int nnp_server_drain(nnp_server *server);
@@ -363,7 +369,9 @@ int nnp_server_poll(nnp_server *server, int64_t *ids, int max, int *n);
  * float32[n_atoms][3] of the last step (coordinates evaluated, kcal/mol/A),
  * times HOST float64[3] = arrival, admission, completion (server clock; the
  * completion time is when the host saw the last step's results).  Releases
- * the request's record: a second call fails with NNP_EINVAL. */
+ * the request's record: a second call fails with NNP_EINVAL.  For a request
+ * that stopped on a neighbour overflow it fills only times (completion =
+ * when the overflow was seen) and returns NNP_ECAPACITY. */
 int nnp_server_result(nnp_server *server, int64_t id, double *energies, float *coords, float *forces,
                       double *times);
 int nnp_server_stats(nnp_server *server, nnp_server_counters *out);
@@ -379,6 +387,9 @@ int nnp_server_stats(nnp_server *server, nnp_server_counters *out);
  *            flight and frees its slots.
  *   complete results of one launched step of id are back at time `now`;
  *            *finished = 1 when it was the last.
+ *   fail     stops an admitted, unfinished request at time `now` (its
+ *            evaluation failed): it leaves the flight, frees its slots and
+ *            counts as finished; NNP_EINVAL otherwise.
  *   job      times[3] = arrival, admission, completion (-1 = not yet), first
  *            slot and steps completed of a known request.
  *   info     info[6] = queued, in flight, atoms in flight, free slots,
@@ -391,6 +402,7 @@ int nnp_sched_admit(nnp_sched *sched, double now, int64_t *ids, int64_t *slots, 
 int nnp_sched_launch(nnp_sched *sched, int64_t *ids, int64_t *slots, int32_t *n_atoms, int32_t *steps,
                      int max, int *n);
 int nnp_sched_complete(nnp_sched *sched, int64_t id, double now, int *finished);
+int nnp_sched_fail(nnp_sched *sched, int64_t id, double now);
 int nnp_sched_job(nnp_sched *sched, int64_t id, double *times, int64_t *slot, int32_t *steps_done);
 int nnp_sched_info(nnp_sched *sched, int64_t *info);
 

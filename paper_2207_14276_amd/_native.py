@@ -95,7 +95,8 @@ EXPORTS = ["nnp_create", "nnp_destroy", "nnp_reserve", "nnp_energy_forces", "nnp
            "nnp_server_step", "nnp_server_drain", "nnp_server_poll", "nnp_server_result",
            "nnp_server_stats",
            "nnp_sched_create", "nnp_sched_destroy", "nnp_sched_submit", "nnp_sched_admit",
-           "nnp_sched_launch", "nnp_sched_complete", "nnp_sched_job", "nnp_sched_info"]
+           "nnp_sched_launch", "nnp_sched_complete", "nnp_sched_job", "nnp_sched_info",
+           "nnp_sched_fail"]
 
 _lib = None
 
@@ -155,6 +156,7 @@ def load():
     lib.nnp_sched_admit.argtypes = [vp, C.c_double, i64p, i64p, C.c_int, ip]
     lib.nnp_sched_launch.argtypes = [vp, i64p, i64p, i32p, i32p, C.c_int, ip]
     lib.nnp_sched_complete.argtypes = [vp, C.c_int64, C.c_double, ip]
+    lib.nnp_sched_fail.argtypes = [vp, C.c_int64, C.c_double]
     lib.nnp_sched_job.argtypes = [vp, C.c_int64, dp, i64p, i32p]
     lib.nnp_sched_info.argtypes = [vp, i64p]
     _lib = lib

@@ -604,6 +604,7 @@ int model_reserve_pooled(nnp_model *m, int64_t max_atoms, int max_systems) {
 const int *model_status_word(const nnp_model *m) { return m->status.as<int>(); }
 int model_device(const nnp_model *m) { return m->device; }
 int model_precision(const nnp_model *m) { return m->precision; }
+int model_species(const nnp_model *m) { return m->S; }
 
 }  // namespace nnp
 
@@ -1333,3 +1334,7 @@ extern "C" int nnp_energy_forces_nlist(nnp_model *m, nnp_nlist *nl, int n_system
   lp.rebuild = rebuild;
   return run(m, n_systems, offs, coords, species, box, o, (hipStream_t)stream, kFull, lp);
 }
+
+namespace nnp {
+const int *nlist_counts(const nnp_nlist *nl) { return nl->cnt.as<int>(); }
+}  // namespace nnp

@@ -6,6 +6,7 @@
 #include <stdint.h>
 
 struct nnp_model;
+struct nnp_nlist;
 
 namespace nnp {
 
@@ -18,6 +19,9 @@ int model_reserve_pooled(nnp_model *m, int64_t max_atoms, int max_systems);
 const int *model_status_word(const nnp_model *m);
 int model_device(const nnp_model *m);
 int model_precision(const nnp_model *m);
+int model_species(const nnp_model *m);
+// Per-slot neighbour counts of a pool (kept past the capacity on overflow).
+const int *nlist_counts(const nnp_nlist *nl);
 
 constexpr int kWave = 64;
 constexpr int kMaxSpecies = 7;

@@ -15,6 +15,7 @@
 // GPU.
 #pragma once
 
+#include <algorithm>
 #include <cstdint>
 #include <cstddef>
 #include <deque>
@@ -83,6 +84,7 @@ struct Job {
   int64_t slot = -1;
   int launched = 0;   // steps enqueued
   int completed = 0;  // steps whose results are back
+  bool failed = false;  // stopped early (fail); finished, without results
 };
 
 // One request's part in a launched iteration.
@@ -173,6 +175,27 @@ class Scheduler {
       return true;
     }
     return false;
+  }
+
+  // Stops a request early (its evaluation failed): it leaves the active set,
+  // its slots are free for later admissions (as after its last step, work on
+  // one stream runs in order) and it counts as finished.  Its steps already
+  // launched stay counted.  false if it is unknown, queued or already
+  // finished.
+  bool fail(int64_t id, double now) {
+    auto f = jobs_.find(id);
+    if (f == jobs_.end()) return false;
+    Job &j = f->second;
+    if (j.t_admitted < 0 || j.failed || j.completed == j.n_steps) return false;
+    auto a = std::find(active_.begin(), active_.end(), id);
+    if (a != active_.end()) {
+      active_.erase(a);
+      alloc_.release(j.slot, j.n_atoms);
+      active_atoms_ -= j.n_atoms;
+    }
+    j.failed = true;
+    j.t_done = now;
+    return true;
   }
 
   // Forgets a finished request (its record was handed out).

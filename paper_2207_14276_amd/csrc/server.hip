@@ -118,6 +118,27 @@ __global__ void k_walk(const ServeSys *__restrict__ sys, int n_sys, float *__res
   sx[3 * g + 2] += d.sigma * m2 * cosf(twopi * u4);
 }
 
+// Largest neighbour count of each request's atoms in the list pool (counts
+// are kept past the capacity, so an overflowing list shows here), one
+// workgroup per request.
+__global__ void __launch_bounds__(256) k_req_max_count(const ServeSys *__restrict__ sys,
+                                                       const int *__restrict__ counts, int *__restrict__ out) {
+  __shared__ int red[256 / 64];
+  const ServeSys d = sys[blockIdx.x];
+  int mx = 0;
+  for (int a = threadIdx.x; a < d.n; a += blockDim.x) mx = max(mx, counts[d.slot + a]);
+  for (int o = 32; o >= 1; o >>= 1) mx = max(mx, __shfl_xor(mx, o));
+  if (threadIdx.x % 64 == 0) red[threadIdx.x / 64] = mx;
+  __syncthreads();
+  if (threadIdx.x == 0) out[blockIdx.x] = max(max(red[0], red[1]), max(red[2], red[3]));
+}
+
+// Clears the model's device flags before an iteration (a kernel, not a
+// memset: the iteration stays free of memset nodes).
+__global__ void k_clear_flags(int *status) {
+  if (threadIdx.x < 2) status[threadIdx.x] = 0;
+}
+
 // ------------------------------------------------------------------ host
 
 double now_s() {
@@ -174,18 +195,21 @@ struct Request {
   std::vector<int32_t> species;  // (freed once uploaded)
   std::vector<double> energy;    // per step
   std::vector<float> last_coords, last_forces;
+  int error = NNP_OK;            // NNP_ECAPACITY: stopped, its list overflowed
+  int max_count = 0;             // the neighbour count that overflowed
 };
 
 // Host side of one launched iteration (a ring of these backs the pipeline).
 struct Iteration {
   Pinned up;    // uploads of admitted requests, then the ServeSys table
-  Pinned out;   // status word, energies [S], then coords and forces [N][3] if wanted
+  Pinned out;   // status word, energies [S], largest neighbour counts [S], then coords and
+                // forces [N][3] if wanted
   hipEvent_t done = nullptr;
   bool busy = false;
   std::vector<LaunchItem> items;
   std::vector<int64_t> offs;
   bool want_xf = false;
-  size_t off_energy = 0, off_x = 0, off_f = 0;
+  size_t off_energy = 0, off_cnt = 0, off_x = 0, off_f = 0;
 };
 
 constexpr int kDepth = 2;   // iterations in flight
@@ -207,12 +231,14 @@ struct nnp_server {
   std::unique_ptr<Scheduler> sched;
   DevMem store_x, store_s;          // [slots][3] f32, [slots] i32
   DevMem bx, bs, bf, be, bsys;      // batch coords, species, forces, energies, ServeSys table
+  DevMem bcnt;                      // largest neighbour count per request [max_active]
   std::unordered_map<int64_t, Request> reqs;
   Iteration ring[kRing];
   std::deque<int> inflight;         // ring indices, oldest first
   int next_ring = 0;
   int64_t next_id = 0;
-  int sticky = NNP_OK;              // first device flag seen (capacity, species)
+  int n_species = 0;
+  int sticky = NNP_OK;              // an unexpected device flag (species checked at submission)
   int64_t max_batch_seen = 0;
   std::vector<int64_t> ready;       // finished, not yet handed out
 };
@@ -235,14 +261,24 @@ int retire_one(nnp_server *s, bool block) {
   const double t = server_clock(s);
   const char *o = (const char *)it.out.p;
   const int status = *(const int *)o;
-  if (status && s->sticky == NNP_OK)
-    s->sticky = (status & kStatOverflow) ? NNP_ECAPACITY : NNP_ESPECIES;
+  // a neighbour overflow is a request's own failure (below); anything else
+  // should not happen (species are checked at submission)
+  if ((status & ~kStatOverflow) && s->sticky == NNP_OK) s->sticky = NNP_ESPECIES;
   const double *E = (const double *)(o + it.off_energy);
+  const int *cnt = (const int *)(o + it.off_cnt);
   const float *X = (const float *)(o + it.off_x);
   const float *F = (const float *)(o + it.off_f);
   for (size_t q = 0; q < it.items.size(); ++q) {
     const LaunchItem &li = it.items[q];
     Request &r = s->reqs[li.id];
+    if (r.error) continue;  // stopped in an earlier iteration: this step's results are void
+    if (cnt[q] > s->cap) {
+      // this request's list overflowed: it stops alone, the others go on
+      r.error = NNP_ECAPACITY;
+      r.max_count = cnt[q];
+      if (s->sched->fail(li.id, t)) s->ready.push_back(li.id);
+      continue;
+    }
     r.energy[li.step] = E[q];
     if (li.last) {
       const size_t a = (size_t)it.offs[q] * 3, n3 = (size_t)li.n_atoms * 3;
@@ -328,6 +364,7 @@ int launch_iteration(nnp_server *s, hipStream_t st, bool *launched) {
   HIP_TRY(hipMemcpyAsync(s->bsys.p, tab, sizeof(ServeSys) * (size_t)S, hipMemcpyHostToDevice, st));
   const int tpb = 256;
   const unsigned grid = (unsigned)((N + tpb - 1) / tpb);
+  k_clear_flags<<<1, 64, 0, st>>>(const_cast<int *>(model_status_word(s->model)));
   k_gather<<<grid, tpb, 0, st>>>(s->bsys.as<ServeSys>(), S, s->store_x.as<float>(), s->store_s.as<int>(),
                                  s->bx.as<float>(), s->bs.as<int>(), (int)N);
   HIP_TRY(hipGetLastError());
@@ -335,18 +372,21 @@ int launch_iteration(nnp_server *s, hipStream_t st, bool *launched) {
                                s->bx.as<float>(), s->bs.as<int32_t>(), boxes.data(), s->be.as<double>(),
                                s->bf.as<float>(), nullptr, nullptr, st);
   if (rc) return rc;
+  k_req_max_count<<<S, 256, 0, st>>>(s->bsys.as<ServeSys>(), nlist_counts(s->list), s->bcnt.as<int>());
   k_walk<<<grid, tpb, 0, st>>>(s->bsys.as<ServeSys>(), S, s->store_x.as<float>(), (int)N);
   HIP_TRY(hipGetLastError());
 
   // results back to the host
   it.off_energy = 16;
-  it.off_x = (it.off_energy + 8 * (size_t)S + 255) / 256 * 256;
+  it.off_cnt = it.off_energy + 8 * (size_t)S;
+  it.off_x = (it.off_cnt + 4 * (size_t)S + 255) / 256 * 256;
   it.off_f = it.off_x + 12 * (size_t)N;
   rc = it.out.ensure(want_xf ? it.off_f + 12 * (size_t)N : it.off_x);
   if (rc) return rc;
   char *o = (char *)it.out.p;
   HIP_TRY(hipMemcpyAsync(o, model_status_word(s->model), sizeof(int), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipMemcpyAsync(o + it.off_energy, s->be.p, 8 * (size_t)S, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(o + it.off_cnt, s->bcnt.p, 4 * (size_t)S, hipMemcpyDeviceToHost, st));
   if (want_xf) {
     HIP_TRY(hipMemcpyAsync(o + it.off_x, s->bx.p, 12 * (size_t)N, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipMemcpyAsync(o + it.off_f, s->bf.p, 12 * (size_t)N, hipMemcpyDeviceToHost, st));
@@ -417,8 +457,10 @@ extern "C" int nnp_server_create(nnp_model *m, const nnp_server_opts *o, nnp_ser
   if ((rc = s->store_x.alloc((size_t)o->slots * 12)) || (rc = s->store_s.alloc((size_t)o->slots * 4)) ||
       (rc = s->bx.alloc((size_t)lo * 12)) || (rc = s->bs.alloc((size_t)lo * 4)) ||
       (rc = s->bf.alloc((size_t)lo * 12)) || (rc = s->be.alloc((size_t)o->max_active * 8)) ||
-      (rc = s->bsys.alloc((size_t)o->max_active * sizeof(ServeSys))))
+      (rc = s->bsys.alloc((size_t)o->max_active * sizeof(ServeSys))) ||
+      (rc = s->bcnt.alloc((size_t)o->max_active * 4)))
     return rc;
+  s->n_species = model_species(m);
   if ((rc = nnp_nlist_create(m, o->slots, cap, o->skin, &s->list))) return rc;
   if ((rc = model_reserve_pooled(m, lo, o->max_active))) {
     nnp_nlist_destroy(s->list);
@@ -445,6 +487,9 @@ extern "C" void nnp_server_destroy(nnp_server *s) {
       (void)hipEventDestroy(it.done);
     }
   if (s->list) nnp_nlist_destroy(s->list);
+  // flags raised by requests that failed alone are the server's business:
+  // leave the model's flags clear for its next user
+  (void)hipMemset(const_cast<int *>(model_status_word(s->model)), 0, 2 * sizeof(int));
   delete s;
 }
 
@@ -456,6 +501,10 @@ extern "C" int nnp_server_submit(nnp_server *s, const nnp_request *r, double t_a
     return fail(NNP_EINVAL, "bad request");
   for (int a = 0; a < 3; ++a)
     if (!(r->box[a] >= 0.f)) return fail(NNP_EINVAL, "negative box length");
+  for (int a = 0; a < r->n_atoms; ++a)
+    if (r->species[a] < 0 || r->species[a] >= s->n_species)
+      return fail(NNP_ESPECIES, "atom %d: species %d outside the model's %d", a, (int)r->species[a],
+                  s->n_species);
   const int64_t rid = s->next_id;
   const double ta = t_arrival >= 0.0 ? t_arrival : server_clock(s);
   if (!s->sched->submit(rid, r->n_atoms, r->n_steps, ta))
@@ -477,7 +526,7 @@ extern "C" int nnp_server_submit(nnp_server *s, const nnp_request *r, double t_a
 
 extern "C" int nnp_server_step(nnp_server *s, void *stream, int64_t *pending) {
   if (!s) return fail(NNP_EINVAL, "null server");
-  if (s->sticky) return fail(s->sticky, "a device flag was raised (neighbour capacity or species)");
+  if (s->sticky) return fail(s->sticky, "an unexpected device flag was raised");
   HIP_TRY(hipSetDevice(s->device));
   hipStream_t st = (hipStream_t)stream;
   int rc = retire_ready(s);
@@ -491,7 +540,7 @@ extern "C" int nnp_server_step(nnp_server *s, void *stream, int64_t *pending) {
   }
   if ((rc = retire_ready(s))) return rc;
   if (pending) *pending = s->sched->queued() + s->sched->active() + (int64_t)s->inflight.size();
-  return s->sticky ? fail(s->sticky, "a device flag was raised (neighbour capacity or species)") : NNP_OK;
+  return s->sticky ? fail(s->sticky, "an unexpected device flag was raised") : NNP_OK;
 }
 
 extern "C" int nnp_server_drain(nnp_server *s) {
@@ -500,7 +549,7 @@ extern "C" int nnp_server_drain(nnp_server *s) {
     int rc = retire_one(s, true);
     if (rc) return rc;
   }
-  return s->sticky ? fail(s->sticky, "a device flag was raised (neighbour capacity or species)") : NNP_OK;
+  return s->sticky ? fail(s->sticky, "an unexpected device flag was raised") : NNP_OK;
 }
 
 extern "C" int nnp_server_poll(nnp_server *s, int64_t *ids, int max, int *n) {
@@ -517,9 +566,22 @@ extern "C" int nnp_server_result(nnp_server *s, int64_t id, double *energies, fl
   if (!s) return fail(NNP_EINVAL, "null server");
   const Job *j = s->sched->job(id);
   auto f = s->reqs.find(id);
-  if (!j || f == s->reqs.end() || j->completed < j->n_steps)
+  if (!j || f == s->reqs.end() || (j->completed < j->n_steps && !j->failed))
     return fail(NNP_EINVAL, "request %lld is not finished or was already collected", (long long)id);
   const Request &r = f->second;
+  if (r.error) {
+    if (times) {
+      times[0] = j->t_arrival;
+      times[1] = j->t_admitted;
+      times[2] = j->t_done;
+    }
+    const int err = r.error, mx = r.max_count, steps = j->completed;
+    s->reqs.erase(f);
+    s->sched->forget(id);
+    s->ready.erase(std::remove(s->ready.begin(), s->ready.end(), id), s->ready.end());
+    return fail(err, "request %lld stopped after %d steps: a neighbour list of %d entries overflowed the "
+                     "capacity of %d", (long long)id, steps, mx, s->cap);
+  }
   if (energies) memcpy(energies, r.energy.data(), 8 * r.energy.size());
   if (coords) memcpy(coords, r.last_coords.data(), 4 * r.last_coords.size());
   if (forces) memcpy(forces, r.last_forces.data(), 4 * r.last_forces.size());
@@ -611,6 +673,12 @@ extern "C" int nnp_sched_complete(nnp_sched *q, int64_t id, double now, int *fin
   if (!j || j->completed >= j->launched) return fail(NNP_EINVAL, "request %lld has no step in flight", (long long)id);
   const bool fin = q->s.complete(id, now);
   if (finished) *finished = fin ? 1 : 0;
+  return NNP_OK;
+}
+
+extern "C" int nnp_sched_fail(nnp_sched *q, int64_t id, double now) {
+  if (!q) return fail(NNP_EINVAL, "null scheduler");
+  if (!q->s.fail(id, now)) return fail(NNP_EINVAL, "request %lld is not admitted and unfinished", (long long)id);
   return NNP_OK;
 }
 

@@ -66,6 +66,10 @@ class Scheduler:
         nat.check(self._lib.nnp_sched_complete(self._h, int(rid), float(now), C.byref(fin)))
         return bool(fin.value)
 
+    def fail(self, rid: int, now: float):
+        """Stops an admitted, unfinished request (its evaluation failed)."""
+        nat.check(self._lib.nnp_sched_fail(self._h, int(rid), float(now)))
+
     def job(self, rid: int) -> dict:
         t = (C.c_double * 3)()
         slot = C.c_int64()
@@ -104,6 +108,8 @@ class Result:
     arrival: float
     admitted: float
     done: float
+    error: int = 0            # NNP_ECAPACITY: the request stopped alone (neighbour overflow)
+    message: str = ""
 
     @property
     def latency(self) -> float:
@@ -199,9 +205,13 @@ class Server:
         t = np.empty(3, np.float64)
         dp = C.POINTER(C.c_double)
         fp = C.POINTER(C.c_float)
-        nat.check(self._lib.nnp_server_result(self._h, int(rid), e.ctypes.data_as(dp),
-                                              x.ctypes.data_as(fp), f.ctypes.data_as(fp),
-                                              t.ctypes.data_as(dp)))
+        rc = self._lib.nnp_server_result(self._h, int(rid), e.ctypes.data_as(dp), x.ctypes.data_as(fp),
+                                         f.ctypes.data_as(fp), t.ctypes.data_as(dp))
+        if rc == nat.NNP_ECAPACITY:
+            # this request stopped alone; the server and the other requests go on
+            return Result(rid, np.zeros(0), np.zeros((0, 3), np.float32), np.zeros((0, 3), np.float32),
+                          float(t[0]), float(t[1]), float(t[2]), rc, nat.last_error())
+        nat.check(rc)
         return Result(rid, e, x, f, float(t[0]), float(t[1]), float(t[2]))
 
     def stats(self) -> ServerStats:

@@ -225,3 +225,27 @@ def test_replay_joins_arrivals_into_running_batch(monkeypatch):
     assert fake.batches[3] == [0, 1, 2]
     assert sorted(rep.results) == [0, 1, 2]
     assert rep.wall == pytest.approx(max(r.done for r in rep.results.values()))
+
+
+def test_failed_request_stops_alone():
+    """A request that fails mid-flight leaves the flight and frees its slots
+    for the queue; the others run all their steps; a failed or queued
+    request cannot be failed (again)."""
+    s = Scheduler(slots=100, max_batch_atoms=100)
+    for rid, n in enumerate([40, 30, 30, 50]):
+        s.submit(rid, n, 4, 0.0)
+    assert [r for r, _ in s.admit(0.0)] == [0, 1, 2]
+    with pytest.raises(NNPError):
+        s.fail(3, 0.5)               # still queued
+    s.launch()
+    s.fail(1, 1.0)                   # stops after one launched step
+    with pytest.raises(NNPError):
+        s.fail(1, 1.5)
+    assert s.info()["active"] == 2 and s.info()["free_slots"] == 30
+    assert s.admit(1.0) == []        # 50 atoms: the 30 freed slots are not enough
+    for _ in range(3):
+        items = s.launch()
+        assert sorted(it[0] for it in items) == [0, 2]
+    assert s.info()["free_slots"] == 100
+    assert [r for r, _ in s.admit(2.0)] == [3]
+    assert s.job(1)["done"] == 1.0
