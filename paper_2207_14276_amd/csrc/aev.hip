@@ -610,6 +610,7 @@ constexpr int kBwdHashBits = 9;
 constexpr int kBwdHash = 1 << kBwdHashBits;  // slots: a cell's neighbourhood holds ~300-450 atoms
 constexpr int kBwdProbe = 32;
 constexpr int kBwdMinCells = 512;  // cells of a grid for the per-cell form
+constexpr size_t kBwdStaticLds = 64;  // bytes kept for static LDS of the grouped forms
 struct SinkHash {
   int *key;
   unsigned long long *val;
@@ -1024,8 +1025,10 @@ void launch_aev_bwd(const float4 *pos, const int *sys_of, const SysDesc *sys, co
     table = (size_t)kBwdHash * 28;
   }
   if (form) {
+    // kBwdStaticLds: the kernels' static LDS (the centre counter) comes on
+    // top of the dynamic allocation
     int wpb = (wpb_pref == 4 || wpb_pref == 6) ? wpb_pref : 8;
-    while (wpb > 1 && per * wpb + table > max_lds) wpb = wpb == 8 ? 6 : wpb == 6 ? 4 : 1;
+    while (wpb > 1 && per * wpb + table + kBwdStaticLds > max_lds) wpb = wpb == 8 ? 6 : wpb == 6 ? 4 : 1;
     if (wpb > 1) {
       const size_t lds = per * wpb + table;
       const unsigned grid = (unsigned)(form == 1 ? gp.n_groups : gp.n_cells);

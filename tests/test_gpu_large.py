@@ -69,7 +69,7 @@ def _compare(label, n, e, ea, f, w, ref, coords, e_tol_atom, e_tol_sys, f_tol):
             assert de_atom <= e_tol_atom
     if w is not None:
         dw = float(np.abs(w - ref["W"]).max())
-        bound = virial_bound(coords, None, f, ref["F"])
+        bound = virial_bound(coords, None, f, ref["F"], w_ref=ref["W"])
         msg += f" max|dW|={dw:.3e} (bound {bound:.3e})"
         assert dw <= bound
     log(msg)

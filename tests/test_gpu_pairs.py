@@ -107,7 +107,7 @@ def test_region_matches_oracle(spec, om, oracle_lib, prec):
     n = int(mask.sum())
     de, df = abs(E - Eo) / n, float(np.abs(F - Fo).max())
     dw = float(np.abs(W - Wo).max())
-    bound = virial_bound(coords, box, F, Fo)
+    bound = virial_bound(coords, box, F, Fo, w_ref=Wo)
     log(f"[pairs {prec}] atoms={len(coords)} region={n} pairs={len(pairs)} |dE|/N={de:.3e} "
         f"|dF|={df:.3e} |dW|/N={dw / n:.3e} |dW|/bound={dw / bound:.3f}")
     e_tol, f_tol = (FP32_E_ATOM, FP32_F) if prec == "fp32" else (BF16_E_PER_ATOM, BF16_F)
@@ -177,7 +177,7 @@ def test_non_periodic_solute_without_shifts(spec, om, oracle_lib):
     Eo, _, Fo, Wo = oracle_lib.energy_forces(sys_.coords, sys_.species, box, om)
     assert abs(E - Eo) / len(sys_.species) <= FP32_E_ATOM
     assert np.abs(F - Fo).max() <= FP32_F
-    assert np.abs(W - Wo).max() <= virial_bound(sys_.coords, box, F, Fo)
+    assert np.abs(W - Wo).max() <= virial_bound(sys_.coords, box, F, Fo, w_ref=Wo)
 
 
 def test_bad_lists_are_reported(spec):

@@ -148,7 +148,8 @@ def _check_energy_forces(model, oracle_lib, om, b, systems, e_atom_tol, e_sys_to
         worst_f = max(worst_f, float(np.abs(gpu["forces"][a:e] - ora["forces"][q]).max()))
         dw = float(np.abs(gpu["virial"][k] - ora["virial"][q]).max())
         worst_w = max(worst_w, dw / n)
-        bound = virial_bound(b.coords[a:e], b.boxes[k], gpu["forces"][a:e], ora["forces"][q])
+        bound = virial_bound(b.coords[a:e], b.boxes[k], gpu["forces"][a:e], ora["forces"][q],
+                             w_ref=ora["virial"][q])
         worst_wr = max(worst_wr, dw / bound)
     log(f"[{label}] max|dE_i|={worst_ea:.3e} max|dE_s|/N={worst_es:.3e} "
         f"max|dF|={worst_f:.3e} max|dW|/N={worst_w:.3e} max|dW|/bound={worst_wr:.3f}")
