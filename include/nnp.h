@@ -194,6 +194,30 @@ int nnp_energy_forces(nnp_model *model, int n_systems, const int64_t *batch_offs
                       double *energy, float *forces, double *virial, float *atom_energy,
                       void *stream);
 
+/* nnp_energy_forces without any allocation, for callers that cannot
+ * allocate device memory: code under stream capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  Same arguments, results and errors as
+ * nnp_energy_forces; the call's whole workspace (atom records, cells,
+ * neighbour rows, AEV and activation rows, force accumulators, descriptors)
+ * comes from a fixed 64 MiB device array that the library holds on every
+ * device it runs on until the process ends, and the descriptors go through
+ * the model's existing pinned staging slots.  It calls no hipMalloc,
+ * hipFree or other allocating routine.
+ *   Limits: a call whose workspace exceeds the 64 MiB (with the ANI-2x
+ *   widths and the default capacity of 256 neighbours, roughly 4,000 atoms
+ *   in float32 and 6,000 in bfloat16; the message gives the bytes needed),
+ *   or whose descriptors exceed a 128 KiB staging slot (about 1,400
+ *   systems), is refused with NNP_EUNSUPPORTED before anything is
+ *   enqueued.
+ *   Sharing: every call on a device, on any model, uses that device's one
+ *   array; calls that overlap on a device (other streams, other threads)
+ *   race and give undefined results.  Each call clears what must start at
+ *   zero; nothing of an earlier call's contents is used. */
+int nnp_energy_forces_noalloc(nnp_model *model, int n_systems, const int64_t *batch_offsets,
+                              const float *coords, const int32_t *species, const float *box,
+                              double *energy, float *forces, double *virial, float *atom_energy,
+                              void *stream);
+
 /* Persistent neighbour lists (device-resident state for repeated calls on
  * slowly moving systems, e.g. successive MD steps).  A pool holds `slots`
  * atom slots; each system of a call occupies a caller-chosen range of slots

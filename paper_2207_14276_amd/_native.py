@@ -87,6 +87,7 @@ class nnp_server_counters(C.Structure):
 
 
 EXPORTS = ["nnp_create", "nnp_destroy", "nnp_reserve", "nnp_energy_forces", "nnp_debug_aev",
+           "nnp_energy_forces_noalloc",
            "nnp_debug_neighbors", "nnp_status", "nnp_aev_dim", "nnp_last_error",
            "nnp_set_timing", "nnp_stage_timings", "nnp_nlist_create", "nnp_nlist_destroy",
            "nnp_energy_forces_nlist", "nnp_nlist_builds", "nnp_autotune", "nnp_tuning",
@@ -118,6 +119,7 @@ def load():
     lib.nnp_destroy.restype = None
     lib.nnp_reserve.argtypes = [vp, C.c_int64, C.c_int, C.c_int]
     lib.nnp_energy_forces.argtypes = [vp, C.c_int, i64p, vp, vp, fp, vp, vp, vp, vp, vp]
+    lib.nnp_energy_forces_noalloc.argtypes = [vp, C.c_int, i64p, vp, vp, fp, vp, vp, vp, vp, vp]
     lib.nnp_debug_aev.argtypes = [vp, C.c_int, i64p, vp, vp, fp, vp, vp]
     lib.nnp_debug_neighbors.argtypes = [vp, C.c_int, i64p, vp, vp, fp, vp, vp, C.c_int, vp]
     lib.nnp_status.argtypes = [vp, vp, C.POINTER(C.c_int)]

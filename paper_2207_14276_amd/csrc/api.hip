@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -87,7 +88,7 @@ const char *kStageNames[kStages] = {"ingest", "cells", "neighbours", "buckets",
 // from the next slot of the ring; it waits only when that slot's previous
 // copy (kStageSlots calls back) has not completed yet.
 constexpr int kStageSlots = 32;
-constexpr size_t kStageInitBytes = 16 * 1024;
+constexpr size_t kStageInitBytes = 128 * 1024;  // ~1,400 systems' descriptors
 struct StageSlot {
   void *p = nullptr;
   size_t bytes = 0;
@@ -449,6 +450,8 @@ static int create_networks(const NetArgs *d, nnp_model *m) {
   return NNP_OK;
 }
 
+static int scratch_init(int dev);
+
 // Runs create on hip_device (< 0: the current device), restoring the
 // caller's current device afterwards.
 template <class Desc, class Impl>
@@ -465,6 +468,7 @@ static int create_on(const Desc *d, int hip_device, nnp_model **out, Impl impl) 
   }
   nnp_model *m = new nnp_model();
   int rc = impl(d, m);
+  if (rc == NNP_OK) rc = scratch_init(m->device);
   if (rc != NNP_OK) {
     nnp_destroy(m);
   } else {
@@ -553,6 +557,80 @@ static int for_each_ws(nnp_model *m, int64_t N, int S, int64_t C, int n_chunks, 
 
 static int ensure_ws(nnp_model *m, int64_t N, int S, int64_t C, int n_chunks, bool pooled = false) {
   return for_each_ws(m, N, S, C, n_chunks, pooled, [](DevBuf &b, size_t n) { return b.ensure(n); });
+}
+
+// Fixed device scratch of the allocation-free entry point
+// (nnp_energy_forces_noalloc): the whole per-call workspace of one call, on
+// every device the library runs on, held until the process ends.  Host code
+// uses the address hipGetSymbolAddress returns for the current device (the
+// array's name is only a host-side handle), looked up once per device when a
+// model is created there.
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+constexpr int kScratchDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+static std::mutex g_scratch_mu;
+static char *g_scratch_ptr[kScratchDevices];
+
+// Looks up this device's copy of scratch (the device must be current).
+static int scratch_init(int dev) {
+  if (dev < 0 || dev >= kScratchDevices)
+    return fail(NNP_EUNSUPPORTED, "device %d: the fixed scratch covers devices 0..%d", dev, kScratchDevices - 1);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[dev]) return NNP_OK;
+  void *p = nullptr;
+  HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+  g_scratch_ptr[dev] = (char *)p;
+  return NNP_OK;
+}
+
+static char *scratch_base(int dev) {
+  if (dev < 0 || dev >= kScratchDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return g_scratch_ptr[dev];
+}
+
+// The model's workspace buffers pointed into the fixed scratch for one call;
+// the model's own buffers come back when the guard goes out of scope.
+struct ScratchViews {
+  nnp_model *m = nullptr;
+  std::vector<std::pair<DevBuf *, DevBuf>> saved;
+  size_t g_zeroed = 0;
+  ~ScratchViews() {
+    for (auto &sv : saved) *sv.first = sv.second;
+    if (m) m->G_zeroed = g_zeroed;
+  }
+};
+
+static size_t scratch_round(size_t n) { return (n + 255) / 256 * 256; }
+
+// Carves the workspace of a call (N atoms, S systems, C cells, n_chunks
+// chunks, lists of the model's own capacity) out of the fixed scratch, or
+// refuses the call when it does not fit; nothing is enqueued either way.
+static int carve_scratch(nnp_model *m, int64_t N, int S, int64_t C, int n_chunks, ScratchViews &v) {
+  char *base = scratch_base(m->device);
+  if (!base) return fail(NNP_EDEVICE, "no fixed scratch address for device %d", m->device);
+  size_t need = 0;
+  for_each_ws(m, N, S, C, n_chunks, false, [&](DevBuf &, size_t n) {
+    need += scratch_round(n);
+    return 0;
+  });
+  if (need > kScratchBytes)
+    return fail(NNP_EUNSUPPORTED, "the call needs %zu bytes of workspace; the fixed scratch holds %zu", need,
+                kScratchBytes);
+  v.m = m;
+  v.g_zeroed = m->G_zeroed;
+  size_t off = 0;
+  for_each_ws(m, N, S, C, n_chunks, false, [&](DevBuf &b, size_t n) {
+    v.saved.push_back({&b, b});
+    b.p = base + off;
+    b.bytes = n;
+    off += scratch_round(n);
+    return 0;
+  });
+  // whatever an earlier call left there: the AEV rows' padding columns are
+  // cleared in this call
+  m->G_zeroed = (size_t)-1;
+  return NNP_OK;
 }
 
 // Cells and reduction chunks reserved for up to max_atoms atoms in
@@ -680,6 +758,8 @@ struct CallOut {
   int *nb_counts = nullptr;
   int *nb_entries = nullptr;
   int nb_cap = 0;
+  // the workspace comes from the fixed device scratch (nothing is allocated)
+  bool no_alloc = false;
 };
 
 // Where a call's neighbour lists live: the model's own per-call pool (every
@@ -830,7 +910,19 @@ static int run(nnp_model *m, int n_sys, const int64_t *offs, const float *coords
   for (int s = 0; s < n_sys && one_chunk_each; ++s) one_chunk_each = sys_ch[s + 1] - sys_ch[s] == 1;
   const int n_chunks = (int)ch_sys.size();
   if (C > ((int64_t)1 << 28)) return fail(NNP_EUNSUPPORTED, "too many cells");
-  int rc = ensure_ws(m, N, n_sys, C, n_chunks, nl != nullptr);
+  ScratchViews views;
+  int rc;
+  if (o.no_alloc) {
+    if (nl || pairs || mode != kFull) return fail(NNP_EINVAL, "the fixed scratch serves plain full calls only");
+    // the descriptors must fit the staging slots as they are
+    const size_t need = DescLayout(n_sys, n_chunks, (int)groups.size()).total;
+    if (need > m->stage[m->stage_next].bytes)
+      return fail(NNP_EUNSUPPORTED, "the call's descriptors (%zu bytes) exceed the %zu-byte staging slot", need,
+                  m->stage[m->stage_next].bytes);
+    rc = carve_scratch(m, N, n_sys, C, n_chunks, views);
+  } else {
+    rc = ensure_ws(m, N, n_sys, C, n_chunks, nl != nullptr);
+  }
   if (rc) return rc;
   if (m->G.bytes != m->G_zeroed) {
     // a newly allocated G: clear it once (with the library's fill kernel) so
@@ -1150,6 +1242,18 @@ extern "C" int nnp_energy_forces(nnp_model *m, int n_systems, const int64_t *off
   o.forces = forces;
   o.virial = virial;
   o.atom_energy = atom_energy;
+  return run(m, n_systems, offs, coords, species, box, o, (hipStream_t)stream, kFull);
+}
+
+extern "C" int nnp_energy_forces_noalloc(nnp_model *m, int n_systems, const int64_t *offs, const float *coords,
+                                         const int32_t *species, const float *box, double *energy,
+                                         float *forces, double *virial, float *atom_energy, void *stream) {
+  CallOut o;
+  o.energy = energy;
+  o.forces = forces;
+  o.virial = virial;
+  o.atom_energy = atom_energy;
+  o.no_alloc = true;
   return run(m, n_systems, offs, coords, species, box, o, (hipStream_t)stream, kFull);
 }
 
