@@ -45,10 +45,12 @@ def parse():
     p.add_argument("--plain-passes", type=int, default=2)
     p.add_argument("--cpu-seconds", type=float, default=15.0)
     p.add_argument("--quiet", action="store_true")
-    p.add_argument("--requests", type=int, default=200, help="serving: requests in the trace")
+    p.add_argument("--requests", type=int, default=4000, help="serving: requests in the trace")
     p.add_argument("--rate", type=float, default=2000.0, help="serving: Poisson arrival rate (1/s)")
     p.add_argument("--req-steps", type=int, default=50, help="serving: steps per request")
-    p.add_argument("--plain-requests", type=int, default=12, help="serving: sample for the plain path")
+    p.add_argument("--plain-requests", type=int, default=48, help="serving: sample for the plain path")
+    p.add_argument("--graphs", default="both", choices=["on", "off", "both"],
+                   help="serving: iterations replayed from recorded graphs, launched directly, or both")
     return p.parse_args()
 
 
@@ -151,6 +153,28 @@ def model_cap(model):
     return getattr(model, "_bench_cap", 256)
 
 
+def model_cutoff(spec):
+    """Neighbour cutoff of a model (the larger descriptor cutoff)."""
+    a = spec.aev if isinstance(spec.aev, dict) else vars(spec.aev)
+    return max(float(a.get(k, 0.0)) for k in ("rc_rad", "rc_ang", "rc"))
+
+
+def cell_count(batch, rc):
+    """Cells of the library's grid for a call on this batch: per periodic
+    system floor(L / rc) per axis (at least 1, at most 1,024), a quarter of
+    the atom count for a non-periodic bounding-box grid."""
+    total = 0
+    for k in range(batch.n_systems):
+        n = int(batch.offsets[k + 1] - batch.offsets[k])
+        b = np.asarray(batch.boxes[k], np.float64)
+        if np.all(b > 0):
+            nc = [min(1024, max(1, int(np.floor(x / (rc * (1 + 1e-5)))))) for x in b]
+            total += nc[0] * nc[1] * nc[2]
+        else:
+            total += max(1, n // 4)
+    return total
+
+
 # Algorithmic work of the AEV stages, counted from the formulas (flops of the
 # float32 vector unit; a transcendental (exp, log, sin/cos, sqrt, reciprocal)
 # counts 4, its issue cost relative to an add or multiply):
@@ -209,7 +233,11 @@ KERNEL_SOURCES = {
     "k_aev_fwd": ["paper_2207_14276_amd/csrc/aev.hip", "paper_2207_14276_amd/csrc/internal.h",
                   "paper_2207_14276_amd/csrc/wave.h"],
     "k_aev_bwd": ["paper_2207_14276_amd/csrc/aev.hip", "paper_2207_14276_amd/csrc/internal.h",
-                  "paper_2207_14276_amd/csrc/wave.h"],
+                  "paper_2207_14276_amd/csrc/wave.h", "paper_2207_14276_amd/csrc/fixed.h"],
+    "k_aev_bwd_sys": ["paper_2207_14276_amd/csrc/aev.hip", "paper_2207_14276_amd/csrc/internal.h",
+                      "paper_2207_14276_amd/csrc/wave.h", "paper_2207_14276_amd/csrc/fixed.h"],
+    "k_aev_bwd_cells": ["paper_2207_14276_amd/csrc/aev.hip", "paper_2207_14276_amd/csrc/internal.h",
+                        "paper_2207_14276_amd/csrc/wave.h", "paper_2207_14276_amd/csrc/fixed.h"],
     "k_dp_fwd": ["paper_2207_14276_amd/csrc/deeppot.hip", "paper_2207_14276_amd/csrc/internal.h",
                  "paper_2207_14276_amd/csrc/wave.h"],
     "k_dp_bwd": ["paper_2207_14276_amd/csrc/deeppot.hip", "paper_2207_14276_amd/csrc/internal.h",
@@ -295,20 +323,41 @@ def serve_bench(args):
         return [(r.arrival, Request(r.system.coords, r.system.species, r.system.box,
                                     args.req_steps, 0.01, seed=r.seed)) for r in trace]
 
-    # warm-up on a few requests (kernel loading, first-touch of the workspace)
-    srv = Server(model, slots=slots, capacity=cap, skin=1.0)
-    replay(srv, [(0.0, q) for _, q in reqs()[:8]])
-    srv.close()
-    torch.cuda.synchronize()
-
-    srv = Server(model, slots=slots, capacity=cap, skin=1.0)
-    say(args, "serving")
-    rep = replay(srv, reqs())
-    st = srv.stats()
-    srv.close()
     skip = len(trace) // 10
-    lat = rep.latencies(skip=skip) * 1e3
-    value = st.atom_evals / rep.wall
+
+    def serve(use_graphs):
+        # warm-up on a few requests (kernel loading, first-touch of the
+        # workspace), then the trace on a fresh server
+        srv = Server(model, slots=slots, capacity=cap, skin=1.0, use_graphs=use_graphs)
+        replay(srv, [(0.0, q) for _, q in reqs()[:8]])
+        srv.close()
+        torch.cuda.synchronize()
+        srv = Server(model, slots=slots, capacity=cap, skin=1.0, use_graphs=use_graphs)
+        say(args, f"serving ({'graphs' if use_graphs else 'direct launches'})")
+        rep = replay(srv, reqs())
+        st = srv.stats()
+        srv.close()
+        lat = rep.latencies(skip=skip) * 1e3
+        failed = sum(1 for r in rep.results.values() if r.error)
+        return {"value": st.atom_evals / rep.wall, "rep": rep, "st": st, "lat": lat, "failed": failed}
+
+    runs = {}
+    if args.graphs in ("on", "both"):
+        runs["graphs"] = serve(True)
+    if args.graphs in ("off", "both"):
+        runs["direct"] = serve(False)
+    head = runs.get("graphs") or runs["direct"]
+    rep, st, lat, value = head["rep"], head["st"], head["lat"], head["value"]
+
+    def summary(r):
+        st_ = r["st"]
+        return {"value": round(r["value"], 1), "unit": "atom-evals/s",
+                "latency_ms": {"p50": round(float(np.percentile(r["lat"], 50)), 3),
+                               "p99": round(float(np.percentile(r["lat"], 99)), 3)},
+                "iterations": int(st_.iterations),
+                "host_us_per_iteration": round(st_.host_launch_s / max(st_.iterations, 1) * 1e6, 1),
+                "graphs_recorded": int(st_.graph_captures), "graph_replays": int(st_.graph_replays),
+                "wall_s": round(r["rep"].wall, 3), "failed_requests": r["failed"]}
 
     # plain: float32, one request at a time, one step per call, fresh lists
     plain = NNPModel(spec, "fp32")
@@ -357,7 +406,9 @@ def serve_bench(args):
                    "mean_atoms": round(float(sizes.mean()), 1),
                    "offered_atom_evals_per_s": round(offered, 1),
                    "form": "native continuous batching, persistent lists (1 A skin), "
-                           "two iterations in flight",
+                           "two iterations in flight, "
+                           + ("iterations replayed from graphs recorded per capacity bucket"
+                              if "graphs" in runs else "kernels launched directly"),
                    "parallelism": "single GPU"},
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3),
                        "p99": round(float(np.percentile(lat, 99)), 3),
@@ -366,6 +417,7 @@ def serve_bench(args):
         "server": {"iterations": st.iterations, "atom_evals": st.atom_evals,
                    "max_batch_seen": st.max_batch_seen, "batch_budget": st.max_batch_atoms,
                    "device_bytes": st.device_bytes, "neighbour_list_builds": st.list_builds},
+        "forms": {k: summary(v) for k, v in runs.items()},
         "plain_fp32_sequential": {"value": round(plain_rate, 1), "unit": "atom-evals/s",
                                   "sample": f"{len(pick)} requests x {args.req_steps} steps",
                                   "service_ms_p50": round(float(np.percentile(p_lat, 50)), 3),
@@ -723,6 +775,14 @@ def main():
     small = bool(np.all(batch.boxes == 0)) and int(np.diff(batch.offsets).max()) <= 512
     if kname == "k_dp_bwd" and small:
         kname = "k_dp_bwd_sys"   # batches of small non-periodic systems: the per-system form
+    if kname == "k_aev_bwd" and tuned.get("aev_bwd_waves", 0) not in (1, 2):
+        # the form the library picks (unless tuned to a wave per centre): per
+        # system for batches of small non-periodic systems, per cell on grids
+        # of at least 512 cells
+        if small:
+            kname = "k_aev_bwd_sys"
+        elif cell_count(batch, model_cutoff(spec)) >= 512:
+            kname = "k_aev_bwd_cells"
     wl = args.workload + ("_dp" if args.model == "dp" else "")
     roof = {"kernel": kname if dom != "mlp" else "k_gemm (all dense layers)",
             "bound": bound, "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",

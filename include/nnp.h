@@ -328,6 +328,17 @@ int nnp_debug_neighbors(nnp_model *model, int n_systems, const int64_t *batch_of
  * beyond the budget and the slots).  Requests that do not fit wait in the
  * queue; a request larger than the pool or the batch budget is refused.
  * The server uses the model exclusively while it lives (same host thread).
+ *
+ * Graphs (use_graphs = 1): an iteration's kernels (gather, list update,
+ * descriptor, dense layers, backward, reductions, client move) are recorded
+ * once per capacity bucket into a HIP graph on a stream of the server's own
+ * and replayed on the caller's stream for every later iteration whose atom
+ * and request counts round up to the same bucket (the next of 2^k, 1.25,
+ * 1.5 and 1.75 times 2^k): grids are sized for the bucket and the kernels
+ * read the iteration's own sizes from its descriptors, uploaded before the
+ * replay.  Graphs hold no memset or allocation nodes.  The workspace is
+ * reserved for the bucket of the batch budget; the 48 most recently used
+ * graphs are kept.  Models of the DeepPot-style descriptor launch directly.
  * ---------------------------------------------------------------------- */
 typedef struct nnp_server nnp_server;
 
@@ -338,6 +349,9 @@ typedef struct {
   int64_t max_batch_atoms;  /* atoms per iteration at most, 0 = memory-bound */
   int max_active;           /* requests in flight at most, >= 1 */
   uint64_t hbm_budget;      /* device bytes granted to the server, 0 = 90% of free */
+  int use_graphs;           /* 1: each iteration's kernels are recorded once per
+                             * capacity bucket as a HIP graph and replayed (see
+                             * below); 0: launched one by one */
 } nnp_server_opts;
 
 typedef struct {
@@ -358,6 +372,9 @@ typedef struct {
   int64_t max_batch_seen;   /* largest iteration so far */
   uint64_t device_bytes;    /* device memory granted at creation (estimate) */
   int64_t list_builds;      /* neighbour lists built (waits for the device) */
+  int64_t graph_captures;   /* iterations recorded as a new graph */
+  int64_t graph_replays;    /* iterations launched as a graph (recorded ones included) */
+  double host_launch_s;     /* host time spent admitting, staging and enqueuing iterations */
 } nnp_server_counters;
 
 /* NNP_ENOMEM when the slots or a batch of one atom do not fit the budget;

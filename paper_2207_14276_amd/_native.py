@@ -70,7 +70,7 @@ class nnp_dp_model_desc(C.Structure):
 class nnp_server_opts(C.Structure):
     _fields_ = [("slots", C.c_int64), ("nbr_capacity", C.c_int), ("skin", C.c_float),
                 ("max_batch_atoms", C.c_int64), ("max_active", C.c_int),
-                ("hbm_budget", C.c_uint64)]
+                ("hbm_budget", C.c_uint64), ("use_graphs", C.c_int)]
 
 
 class nnp_request(C.Structure):
@@ -83,7 +83,8 @@ class nnp_server_counters(C.Structure):
     _fields_ = [("iterations", C.c_int64), ("atom_evals", C.c_int64), ("queued", C.c_int64),
                 ("active", C.c_int64), ("max_batch_atoms", C.c_int64),
                 ("max_batch_seen", C.c_int64), ("device_bytes", C.c_uint64),
-                ("list_builds", C.c_int64)]
+                ("list_builds", C.c_int64), ("graph_captures", C.c_int64),
+                ("graph_replays", C.c_int64), ("host_launch_s", C.c_double)]
 
 
 EXPORTS = ["nnp_create", "nnp_destroy", "nnp_reserve", "nnp_energy_forces", "nnp_debug_aev",

@@ -359,8 +359,9 @@ __global__ void __launch_bounds__(WPB * kWave)
 k_aev_fwd(const float4 *__restrict__ pos, const int *__restrict__ sys_of,
           const SysDesc *__restrict__ sys, const int2 *__restrict__ nbr,
           const int *__restrict__ nbr_cnt, int cap, const int *__restrict__ row_of_atom,
-          void *__restrict__ G, int ldg, int N, AevConst c) {
+          void *__restrict__ G, int ldg, Live N_, AevConst c) {
   extern __shared__ float4 lds4[];
+  const int N = N_.get();
   // the wave index is uniform across the wave: keep it (and the centre's
   // index, descriptors and row pointers) in scalar registers
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave), lane = threadIdx.x % kWave;
@@ -855,14 +856,14 @@ __global__ void __launch_bounds__(WPB * kWave)
 k_aev_bwd(const float4 *__restrict__ pos, const int *__restrict__ sys_of,
           const SysDesc *__restrict__ sys, const int2 *__restrict__ nbr,
           const int *__restrict__ nbr_cnt, int cap, const int *__restrict__ row_of_atom,
-          const float *__restrict__ dG, int ldg, int N, AevConst c, unsigned long long *__restrict__ Ffix,
+          const float *__restrict__ dG, int ldg, Live N, AevConst c, unsigned long long *__restrict__ Ffix,
           float *__restrict__ W_atom) {
   extern __shared__ float4 lds4[];
   // the wave index is uniform across the wave: keep it (and the centre's
   // index, descriptors and row pointers) in scalar registers
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave), lane = threadIdx.x % kWave;
   const int i = blockIdx.x * WPB + wave;
-  if (i >= N) return;
+  if (i >= N.get()) return;
   WaveLds w = carve<true>((char *)lds4 + wave * wave_lds_bytes<true>(cap), cap);
   bwd_centre(i, lane, pos, sys_of, sys, nbr, nbr_cnt, cap, row_of_atom, dG, ldg, c, W_atom, w, SinkGlobal{Ffix});
 }
@@ -885,9 +886,10 @@ k_aev_bwd_sys(const int2 *__restrict__ groups, const float4 *__restrict__ pos, c
               const SysDesc *__restrict__ sys, const int2 *__restrict__ nbr,
               const int *__restrict__ nbr_cnt, int cap, const int *__restrict__ row_of_atom,
               const float *__restrict__ dG, int ldg, AevConst c, unsigned long long *__restrict__ Ffix,
-              float *__restrict__ W_atom) {
+              float *__restrict__ W_atom, Live n_groups) {
   extern __shared__ float4 lds4[];
   __shared__ int counter;
+  if ((int)blockIdx.x >= n_groups.get()) return;  // the whole workgroup leaves together
   const int2 gr = groups[blockIdx.x];
   const SysDesc &d = sys[sys_of[gr.x]];
   const int off = d.atom_off, n3 = 3 * d.n;
@@ -917,9 +919,10 @@ k_aev_bwd_cells(const int *__restrict__ cell_start, const int *__restrict__ cell
                 const SysDesc *__restrict__ sys, const int2 *__restrict__ nbr,
                 const int *__restrict__ nbr_cnt, int cap, const int *__restrict__ row_of_atom,
                 const float *__restrict__ dG, int ldg, AevConst c, unsigned long long *__restrict__ Ffix,
-                float *__restrict__ W_atom) {
+                float *__restrict__ W_atom, Live n_cells) {
   extern __shared__ float4 lds4[];
   __shared__ int counter;
+  if ((int)blockIdx.x >= n_cells.get()) return;  // the whole workgroup leaves together
   const int b = cell_start[blockIdx.x], e = cell_start[blockIdx.x + 1];
   if (b == e) return;  // the whole workgroup leaves together
   char *tail = (char *)lds4 + WPB * wave_lds_bytes<true>(cap);
@@ -962,11 +965,11 @@ static int waves_for_cap(int cap, int pref) {
 
 template <bool BF16>
 static void aev_fwd_t(const float4 *pos, const int *sys_of, const SysDesc *sys, const int2 *nbr,
-                      const int *nbr_cnt, int cap, const int *row_of_atom, void *G, int ldg, int N,
+                      const int *nbr_cnt, int cap, const int *row_of_atom, void *G, int ldg, Live N,
                       const AevConst &c, int wpb_pref, hipStream_t st) {
   int wpb = waves_for_cap<false>(cap, wpb_pref);
   size_t lds = wave_lds_bytes<false>(cap) * wpb;
-  unsigned grid = (unsigned)((N + wpb - 1) / wpb);
+  unsigned grid = (unsigned)((N.v + wpb - 1) / wpb);
   if (wpb == 4)
     k_aev_fwd<4, BF16><<<grid, 4 * kWave, lds, st>>>(pos, sys_of, sys, nbr, nbr_cnt, cap, row_of_atom, G, ldg, N, c);
   else if (wpb == 2)
@@ -977,8 +980,8 @@ static void aev_fwd_t(const float4 *pos, const int *sys_of, const SysDesc *sys, 
 
 void launch_aev_fwd(const float4 *pos, const int *sys_of, const SysDesc *sys, const int2 *nbr,
                     const int *nbr_cnt, int cap, const int *row_of_atom, void *G, bool g_bf16,
-                    int ldg, int N, const AevConst &c, int wpb_pref, hipStream_t st) {
-  if (N <= 0) return;
+                    int ldg, Live N, const AevConst &c, int wpb_pref, hipStream_t st) {
+  if (N.v <= 0) return;
   if (g_bf16) aev_fwd_t<true>(pos, sys_of, sys, nbr, nbr_cnt, cap, row_of_atom, G, ldg, N, c, wpb_pref, st);
   else aev_fwd_t<false>(pos, sys_of, sys, nbr, nbr_cnt, cap, row_of_atom, G, ldg, N, c, wpb_pref, st);
 }
@@ -986,67 +989,81 @@ void launch_aev_fwd(const float4 *pos, const int *sys_of, const SysDesc *sys, co
 template <int WPB>
 static void aev_bwd_launch(int form, size_t lds, unsigned grid, const AevBwdGroups &gp, const float4 *pos,
                            const int *sys_of, const SysDesc *sys, const int2 *nbr, const int *nbr_cnt, int cap,
-                           const int *row_of_atom, const float *dG, int ldg, int N, const AevConst &c,
+                           const int *row_of_atom, const float *dG, int ldg, Live N, const AevConst &c,
                            unsigned long long *Ffix, float *W_atom, hipStream_t st) {
-  if constexpr (WPB >= 4) {  // grouped forms run 4 to 8 waves per workgroup
+  if constexpr (WPB >= 4) {  // grouped forms run 4 to 10 waves per workgroup
     if (form == 1) {
       k_aev_bwd_sys<WPB><<<grid, WPB * kWave, lds, st>>>(gp.groups, pos, sys_of, sys, nbr, nbr_cnt, cap,
-                                                         row_of_atom, dG, ldg, c, Ffix, W_atom);
+                                                         row_of_atom, dG, ldg, c, Ffix, W_atom,
+                                                         Live(gp.n_groups, gp.live_groups));
       return;
     }
     if (form == 2) {
       k_aev_bwd_cells<WPB><<<grid, WPB * kWave, lds, st>>>(gp.cell_start, gp.cell_atoms, pos, sys_of, sys, nbr,
-                                                           nbr_cnt, cap, row_of_atom, dG, ldg, c, Ffix, W_atom);
+                                                           nbr_cnt, cap, row_of_atom, dG, ldg, c, Ffix, W_atom,
+                                                           Live(gp.n_cells, gp.live_cells));
       return;
     }
   }
-  k_aev_bwd<WPB><<<grid, WPB * kWave, lds, st>>>(pos, sys_of, sys, nbr, nbr_cnt, cap, row_of_atom, dG, ldg, N, c,
-                                                 Ffix, W_atom);
+  if constexpr (WPB <= 4)
+    k_aev_bwd<WPB><<<grid, WPB * kWave, lds, st>>>(pos, sys_of, sys, nbr, nbr_cnt, cap, row_of_atom, dG, ldg, N, c,
+                                                   Ffix, W_atom);
 }
 
-// Chooses the form: per system when the call is a batch of small
+// Chooses the form.  wpb_pref 1 or 2: one wave per centre, forces straight
+// into Ffix by device atomics, that many waves per workgroup.  Otherwise a
+// grouped form when the call has one: per system for a batch of small
 // non-periodic systems (gp.groups), per cell on a grid of at least
-// kBwdMinCells cells (fewer would leave compute units idle), else per
-// centre.  Grouped forms run 8 waves per workgroup unless the tuned
-// preference is 4 or 6; the per-centre form takes the preference 1, 2 or 4.
+// kBwdMinCells cells (fewer would leave compute units idle), with wpb_pref
+// waves per workgroup (4, 5, 6, 8 or 10; default kBwdWaves), fewer when the
+// LDS does not hold them.  Without a grouped form: one wave per centre.
+constexpr int kBwdWaves = 8;
 void launch_aev_bwd(const float4 *pos, const int *sys_of, const SysDesc *sys, const int2 *nbr,
                     const int *nbr_cnt, int cap, const int *row_of_atom, const float *dG, int ldg,
-                    int N, const AevConst &c, unsigned long long *Ffix, float *W_atom, const AevBwdGroups &gp,
+                    Live N, const AevConst &c, unsigned long long *Ffix, float *W_atom, const AevBwdGroups &gp,
                     int wpb_pref, size_t max_lds, hipStream_t st) {
-  if (N <= 0) return;
+  if (N.v <= 0) return;
   const size_t per = wave_lds_bytes<true>(cap);
   int form = 0;
   size_t table = 0;
-  if (gp.groups && gp.n_groups > 0) {
-    form = 1;
-    table = ((size_t)gp.max_sys_atoms * 24 + 15) / 16 * 16;
-  } else if (gp.cell_start && gp.n_cells >= kBwdMinCells) {
-    form = 2;
-    table = (size_t)kBwdHash * 28;
+  if (wpb_pref != 1 && wpb_pref != 2) {
+    if (gp.groups && gp.n_groups > 0) {
+      form = 1;
+      table = ((size_t)gp.max_sys_atoms * 24 + 15) / 16 * 16;
+    } else if (gp.cell_start && gp.n_cells >= kBwdMinCells) {
+      form = 2;
+      table = (size_t)kBwdHash * 28;
+    }
   }
   if (form) {
     // kBwdStaticLds: the kernels' static LDS (the centre counter) comes on
     // top of the dynamic allocation
-    int wpb = (wpb_pref == 4 || wpb_pref == 6) ? wpb_pref : 8;
-    while (wpb > 1 && per * wpb + table + kBwdStaticLds > max_lds) wpb = wpb == 8 ? 6 : wpb == 6 ? 4 : 1;
-    if (wpb > 1) {
+    int wpb = (wpb_pref == 4 || wpb_pref == 5 || wpb_pref == 6 || wpb_pref == 8 || wpb_pref == 10) ? wpb_pref
+                                                                                                   : kBwdWaves;
+    auto fits = [&](int w) { return per * w + table + kBwdStaticLds <= max_lds; };
+    while (wpb >= 4 && !fits(wpb)) wpb = wpb == 10 ? 8 : wpb == 8 ? 6 : wpb - 1;
+    if (wpb >= 4) {
       const size_t lds = per * wpb + table;
       const unsigned grid = (unsigned)(form == 1 ? gp.n_groups : gp.n_cells);
-      if (wpb == 8)
-        aev_bwd_launch<8>(form, lds, grid, gp, pos, sys_of, sys, nbr, nbr_cnt, cap, row_of_atom, dG, ldg, N, c,
-                          Ffix, W_atom, st);
-      else if (wpb == 6)
-        aev_bwd_launch<6>(form, lds, grid, gp, pos, sys_of, sys, nbr, nbr_cnt, cap, row_of_atom, dG, ldg, N, c,
-                          Ffix, W_atom, st);
-      else
-        aev_bwd_launch<4>(form, lds, grid, gp, pos, sys_of, sys, nbr, nbr_cnt, cap, row_of_atom, dG, ldg, N, c,
-                          Ffix, W_atom, st);
-      return;
+#define NNP_BWD_CASE(W)                                                                                     \
+  case W:                                                                                                   \
+    aev_bwd_launch<W>(form, lds, grid, gp, pos, sys_of, sys, nbr, nbr_cnt, cap, row_of_atom, dG, ldg, N, c, \
+                      Ffix, W_atom, st);                                                                    \
+    return;
+      switch (wpb) {
+        NNP_BWD_CASE(4)
+        NNP_BWD_CASE(5)
+        NNP_BWD_CASE(6)
+        NNP_BWD_CASE(8)
+        NNP_BWD_CASE(10)
+        default: break;
+      }
+#undef NNP_BWD_CASE
     }
   }
   const int wpb = waves_for_cap<true>(cap, wpb_pref);
   const size_t lds = per * wpb;
-  const unsigned grid = (unsigned)((N + wpb - 1) / wpb);
+  const unsigned grid = (unsigned)((N.v + wpb - 1) / wpb);
   if (wpb == 4)
     aev_bwd_launch<4>(0, lds, grid, gp, pos, sys_of, sys, nbr, nbr_cnt, cap, row_of_atom, dG, ldg, N, c, Ffix,
                       W_atom, st);

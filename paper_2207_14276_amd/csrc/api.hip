@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <initializer_list>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -126,6 +127,7 @@ struct nnp_model {
   int ldG = 0;                           // row stride of the AEV buffer G: the AEV length
                                          // rounded up to 32; columns past it stay zero
   size_t G_zeroed = 0;                   // bytes of G cleared since its last growth
+  unsigned long long ws_gen = 0;         // counts workspace reallocations (recorded graphs hold its addresses)
 
   // workspace
   DevBuf pos, sys_of, atom_cell, atom_slot, cell_count, cell_start, cell_atoms, nbr, nbr_cnt;
@@ -441,7 +443,8 @@ static int create_networks(const NetArgs *d, nnp_model *m) {
   }
   for (StageSlot &ss : m->stage) {
     HIP_TRY(hipEventCreateWithFlags(&ss.done, hipEventDisableTiming | hipEventDisableSystemFence));
-    HIP_TRY(hipHostMalloc(&ss.p, kStageInitBytes, hipHostMallocDefault));
+    // coherent: the copy kernel reads it straight from host memory
+    HIP_TRY(hipHostMalloc(&ss.p, kStageInitBytes, hipHostMallocCoherent));
     ss.bytes = kStageInitBytes;
   }
   int rc = m->status.ensure(2 * sizeof(int));
@@ -489,23 +492,23 @@ extern "C" int nnp_create_dp(const nnp_dp_model_desc *d, int hip_device, nnp_mod
 extern "C" int nnp_aev_dim(const nnp_model *m) { return m ? m->D : NNP_EINVAL; }
 
 // Layout of the per-call descriptors, the same in pinned staging memory and
-// in the device buffer: SysDesc[S], chunk system[n_chunks], chunk first
+// in the device buffer: CallSizes, SysDesc[S], chunk system[n_chunks], chunk first
 // atom[n_chunks], first chunk of each system[S + 1], backward centre groups
 // int2[n_groups] (8-byte aligned).
 struct DescLayout {
   size_t sd, cs, cb, so, gr, total;
   DescLayout(int S, int n_chunks, int n_groups) {
-    sd = 0;
+    sd = sizeof(CallSizes);  // the call's sizes come first
     cs = sd + sizeof(SysDesc) * (size_t)S;
     cb = cs + 4 * (size_t)n_chunks;
     so = cb + 4 * (size_t)n_chunks;
     gr = (so + 4 * (size_t)(S + 1) + 7) / 8 * 8;
-    total = gr + 8 * (size_t)n_groups;
+    total = (gr + 8 * (size_t)n_groups + 15) / 16 * 16;  // moved in 16-byte units
   }
 };
 
 // Centres per group of the AEV backward's per-system form.
-constexpr int kBwdGroup = 16;
+constexpr int kBwdGroup = 20;
 // Groups of a call of small systems: at most this many per atom.
 static int64_t max_bwd_groups(int64_t N, int S) { return N / kBwdGroup + S + 1; }
 
@@ -556,8 +559,57 @@ static int for_each_ws(nnp_model *m, int64_t N, int S, int64_t C, int n_chunks, 
 }
 
 static int ensure_ws(nnp_model *m, int64_t N, int S, int64_t C, int n_chunks, bool pooled = false) {
-  return for_each_ws(m, N, S, C, n_chunks, pooled, [](DevBuf &b, size_t n) { return b.ensure(n); });
+  return for_each_ws(m, N, S, C, n_chunks, pooled, [m](DevBuf &b, size_t n) {
+    const void *before = b.p;
+    const int rc = b.ensure(n);
+    if (b.p != before) ++m->ws_gen;
+    return rc;
+  });
 }
+
+// Capacity buckets of graph replay: the smallest of 2^k, 1.25, 1.5 and 1.75
+// times 2^k (at least 64) that holds v; a call's launches are sized for its
+// bucket (at most 25% above the call).
+static int64_t bucket_up(int64_t v) {
+  int64_t b = 64;
+  while (b < v) b *= 2;
+  if (b > 64) {
+    const int64_t h = b / 2;
+    for (int q = 1; q <= 3; ++q)
+      if (h + q * (h / 4) >= v) return h + q * (h / 4);
+  }
+  return b;
+}
+
+// Recorded launch sequences, by everything their launches were recorded
+// with: the launch sizes, the call's form and every address a kernel takes.
+struct GraphKey {
+  int64_t n_launch, s_launch, c_launch, g_launch;
+  int all_small, cap;
+  const void *ptr[12];
+  unsigned long long ws_gen;
+  bool operator==(const GraphKey &o) const { return memcmp(this, &o, sizeof o) == 0; }
+};
+constexpr size_t kMaxGraphs = 48;
+
+namespace nnp {
+struct GraphCache {
+  struct Entry {
+    GraphKey key;
+    hipGraphExec_t exec;
+    unsigned long long used;
+  };
+  std::vector<Entry> entries;
+  unsigned long long clock = 0;
+};
+GraphCache *graph_cache_create() { return new GraphCache(); }
+int64_t launch_bucket(int64_t v) { return bucket_up(v); }
+void graph_cache_destroy(GraphCache *gc) {
+  if (!gc) return;
+  for (auto &e : gc->entries) (void)hipGraphExecDestroy(e.exec);
+  delete gc;
+}
+}  // namespace nnp
 
 // Fixed device scratch of the allocation-free entry point
 // (nnp_energy_forces_noalloc): the whole per-call workspace of one call, on
@@ -686,24 +738,44 @@ int model_species(const nnp_model *m) { return m->S; }
 
 }  // namespace nnp
 
+// Appends one event set for a timed call.
+static int add_evset(nnp_model *m) {
+  std::array<hipEvent_t, kStages + 1> set{};
+  // timing only: no system-scope fence at each record (the times are read
+  // after the stream has completed)
+  for (auto &e : set) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
+  m->evsets.push_back(set);
+  return NNP_OK;
+}
+
+// Sets for this many timed calls are created when timing is switched on, so
+// that the timed calls themselves create none (event creation can stall the
+// host for milliseconds when the runtime grows its signal pool).
+constexpr int kTimedSetsAhead = 64;
+
 extern "C" int nnp_set_timing(nnp_model *m, int enable) {
   if (!m) return fail(NNP_EINVAL, "null model");
   m->timing = enable != 0;
   m->ev_used = 0;
   m->last_stages = 0;
+  if (m->timing) {
+    HIP_TRY(hipSetDevice(m->device));
+    while ((int)m->evsets.size() < kTimedSetsAhead) {
+      int rc = add_evset(m);
+      if (rc) return rc;
+    }
+  }
   return NNP_OK;
 }
 
-// Event set for the next timed call (created on first use, then reused).
+// Event set for the next timed call (created on first use past the sets
+// made ahead, then reused).
 static int next_evset(nnp_model *m, hipEvent_t **out) {
   *out = nullptr;
   if (m->ev_used >= kMaxTimedCalls) return NNP_OK;  // beyond the limit: untimed
   if (m->ev_used == (int)m->evsets.size()) {
-    std::array<hipEvent_t, kStages + 1> set{};
-    // timing only: no system-scope fence at each record (the times are read
-    // after the stream has completed)
-    for (auto &e : set) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
-    m->evsets.push_back(set);
+    int rc = add_evset(m);
+    if (rc) return rc;
   }
   *out = m->evsets[m->ev_used++].data();
   return NNP_OK;
@@ -780,9 +852,70 @@ struct PairIn {
   int half = 1;                     // 1: each unordered pair once; 0: each direction
 };
 
+// Launches the recorded sequence of a call's launches on stream st,
+// recording it first (record(cs): the launches, issued on the capture
+// stream cs) when no graph was recorded with the same key.  The least
+// recently used graph makes room when the cache is full.
+template <class Record>
+static int replay(nnp_model *m, GraphRun *gr, hipStream_t st, int64_t n_l, int64_t s_l, int64_t c_l,
+                  int64_t g_l, bool all_small, int cap, std::initializer_list<const void *> ptrs,
+                  Record &&record) {
+  GraphCache *gc = gr->cache;
+  if (!gc || !gr->capture_stream) return fail(NNP_EINVAL, "graph replay needs a cache and a capture stream");
+  GraphKey k;
+  memset(&k, 0, sizeof k);
+  k.n_launch = n_l;
+  k.s_launch = s_l;
+  k.c_launch = c_l;
+  k.g_launch = g_l;
+  k.all_small = all_small ? 1 : 0;
+  k.cap = cap;
+  int q = 0;
+  for (const void *p : ptrs)
+    if (q < (int)(sizeof k.ptr / sizeof k.ptr[0])) k.ptr[q++] = p;
+  k.ws_gen = m->ws_gen;
+  GraphCache::Entry *hit = nullptr;
+  for (auto &e : gc->entries)
+    if (e.key == k) {
+      hit = &e;
+      break;
+    }
+  if (!hit) {
+    if (gc->entries.size() >= kMaxGraphs) {
+      // the graph leaving may still run on st
+      HIP_TRY(hipStreamSynchronize(st));
+      auto lru = std::min_element(gc->entries.begin(), gc->entries.end(),
+                                  [](const GraphCache::Entry &a, const GraphCache::Entry &b) { return a.used < b.used; });
+      (void)hipGraphExecDestroy(lru->exec);
+      gc->entries.erase(lru);
+    }
+    hipStream_t cs = gr->capture_stream;
+    HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    const int rc = record(cs);
+    hipGraph_t g = nullptr;
+    const hipError_t ec = hipStreamEndCapture(cs, &g);
+    if (rc) {
+      if (ec == hipSuccess && g) (void)hipGraphDestroy(g);
+      return rc;
+    }
+    if (ec != hipSuccess) return fail(NNP_EDEVICE, "hipStreamEndCapture failed: %s", hipGetErrorString(ec));
+    hipGraphExec_t ex = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ei != hipSuccess) return fail(NNP_EDEVICE, "hipGraphInstantiate failed: %s", hipGetErrorString(ei));
+    gc->entries.push_back({k, ex, 0});
+    hit = &gc->entries.back();
+    ++gr->captures;
+  }
+  hit->used = ++gc->clock;
+  HIP_TRY(hipGraphLaunch(hit->exec, st));
+  ++gr->replays;
+  return NNP_OK;
+}
+
 static int run(nnp_model *m, int n_sys, const int64_t *offs, const float *coords,
                const int32_t *species, const float *box, const CallOut &o, hipStream_t st, Mode mode,
-               const ListPool &lp = ListPool(), const PairIn &pin = PairIn()) {
+               const ListPool &lp = ListPool(), const PairIn &pin = PairIn(), GraphRun *gr = nullptr) {
   if (!m) return fail(NNP_EINVAL, "null model");
   if (n_sys < 1) return fail(NNP_EINVAL, "n_systems must be >= 1");
   if (!offs || !box) return fail(NNP_EINVAL, "null host array (batch_offsets / box)");
@@ -910,6 +1043,30 @@ static int run(nnp_model *m, int n_sys, const int64_t *offs, const float *coords
   for (int s = 0; s < n_sys && one_chunk_each; ++s) one_chunk_each = sys_ch[s + 1] - sys_ch[s] == 1;
   const int n_chunks = (int)ch_sys.size();
   if (C > ((int64_t)1 << 28)) return fail(NNP_EUNSUPPORTED, "too many cells");
+  // Graph replay (a caller's recorded launch sequences, persistent lists,
+  // AEV models): every launch is sized for the call's capacity bucket and
+  // the kernels read the call's own sizes from its descriptors.  Otherwise
+  // the launch sizes are the call's.
+  const bool graph = gr && gr->use_graph && m->kind == kDescAev && mode == kFull && nl && !pairs &&
+                     !m->timing && !m->tuning && !o.no_alloc && N > 0;
+  int N_l = N, S_l = n_sys, chunks_l = n_chunks, groups_l = (int)groups.size();
+  int64_t C_l = C;
+  if (graph) {
+    N_l = (int)bucket_up(N);
+    S_l = (int)bucket_up(n_sys);
+    // cells: a quarter of the atoms plus one per system bounds the grids of
+    // solutes (n/4 cells each) and of boxes at liquid density; sparser boxes
+    // take a bucket of their own
+    const int64_t c_typ = (int64_t)N_l / 4 + S_l;
+    C_l = C <= c_typ ? c_typ : bucket_up(C);
+    chunks_l = N_l / 4096 + S_l + 1;
+    if (!groups.empty()) {
+      groups_l = (int)max_bwd_groups(N_l, S_l);
+      max_sys_atoms = kSmallSystem;
+    }
+    if ((int64_t)N_l > ((int64_t)1 << 28) || C_l > ((int64_t)1 << 28))
+      return fail(NNP_EUNSUPPORTED, "too many atoms or cells for a recorded launch");
+  }
   ScratchViews views;
   int rc;
   if (o.no_alloc) {
@@ -921,7 +1078,7 @@ static int run(nnp_model *m, int n_sys, const int64_t *offs, const float *coords
                   m->stage[m->stage_next].bytes);
     rc = carve_scratch(m, N, n_sys, C, n_chunks, views);
   } else {
-    rc = ensure_ws(m, N, n_sys, C, n_chunks, nl != nullptr);
+    rc = ensure_ws(m, N_l, S_l, C_l, chunks_l, nl != nullptr);
   }
   if (rc) return rc;
   if (m->G.bytes != m->G_zeroed) {
@@ -934,7 +1091,7 @@ static int run(nnp_model *m, int n_sys, const int64_t *offs, const float *coords
 
   // stage the per-call descriptors through pinned memory; one copy moves them
   // all into the device buffer of the same layout
-  const DescLayout dl(n_sys, n_chunks, (int)groups.size());
+  const DescLayout dl(S_l, chunks_l, groups_l);
   const size_t off_sd = dl.sd, off_cs = dl.cs, off_cb = dl.cb, off_so = dl.so, total = dl.total;
   StageSlot &ss = m->stage[m->stage_next];
   m->stage_next = (m->stage_next + 1) % kStageSlots;
@@ -947,11 +1104,19 @@ static int run(nnp_model *m, int n_sys, const int64_t *offs, const float *coords
     if (ss.p) HIP_TRY(hipHostFree(ss.p));
     ss.p = nullptr;
     ss.bytes = 0;
-    size_t nb = total + total / 2 + 4096;
-    HIP_TRY(hipHostMalloc(&ss.p, nb, hipHostMallocDefault));
+    size_t nb = (total + total / 2 + 4096 + 15) / 16 * 16;
+    HIP_TRY(hipHostMalloc(&ss.p, nb, hipHostMallocCoherent));
     ss.bytes = nb;
   }
   char *hs = (char *)ss.p;
+  CallSizes csz;
+  memset(&csz, 0, sizeof csz);
+  csz.N = N;
+  csz.n_sys = n_sys;
+  csz.n_cells = (int)C;
+  csz.n_chunks = n_chunks;
+  csz.n_groups = (int)groups.size();
+  memcpy(hs, &csz, sizeof csz);
   memcpy(hs + off_sd, sd.data(), sizeof(SysDesc) * n_sys);
   if (n_chunks) {
     memcpy(hs + off_cs, ch_sys.data(), 4 * (size_t)n_chunks);
@@ -959,279 +1124,309 @@ static int run(nnp_model *m, int n_sys, const int64_t *offs, const float *coords
   }
   memcpy(hs + off_so, sys_ch.data(), 4 * (size_t)(n_sys + 1));
   if (!groups.empty()) memcpy(hs + dl.gr, groups.data(), 8 * groups.size());
-  HIP_TRY(hipMemcpyAsync(m->desc.p, hs, total, hipMemcpyHostToDevice, st));
+  launch_copy_from_host(hs, m->desc.p, total, st);
   HIP_TRY(hipEventRecord(ss.done, st));
   ss.pending = true;
 
-  int stage = 0;
-  hipEvent_t *ev = nullptr;
-  if (m->timing && mode == kFull) {
-    rc = next_evset(m, &ev);
-    if (rc) return rc;
-  }
-  auto mark = [&]() {
-    if (ev) (void)hipEventRecord(ev[stage++], st);
-  };
-  // per-site events while tuning (every site launches at most once per call)
-  const bool tuning = m->tuning && mode == kFull;
-  auto site_begin = [&](int site) {
-    if (tuning) {
-      (void)hipEventRecord(m->tune_ev[site][0], st);
-      m->tune_hit[site] = true;
+  // the call's sizes on the device (read by recorded launches)
+  const CallSizes *live = (const CallSizes *)m->desc.p;
+  const Live lN = graph ? Live(N_l, &live->N) : Live(N);
+  const Live lS = graph ? Live(S_l, &live->n_sys) : Live(n_sys);
+  const Live lC = graph ? Live((int)C_l, &live->n_cells) : Live((int)C);
+  const Live lChunks = graph ? Live(chunks_l, &live->n_chunks) : Live(n_chunks);
+  // every launch of the call, on stream st
+  auto enqueue = [&](hipStream_t st) -> int {
+    int stage = 0;
+    hipEvent_t *ev = nullptr;
+    if (m->timing && mode == kFull) {
+      rc = next_evset(m, &ev);
+      if (rc) return rc;
     }
-  };
-  auto site_end = [&](int site) {
-    if (tuning) (void)hipEventRecord(m->tune_ev[site][1], st);
-  };
-  mark();
-  SysDesc *dsys = (SysDesc *)(m->desc.as<char>() + off_sd);
-  const int *d_chunk_sys = (const int *)(m->desc.as<char>() + off_cs);
-  const int *d_chunk_begin = (const int *)(m->desc.as<char>() + off_cb);
-  const int *d_sys_chunk_off = (const int *)(m->desc.as<char>() + off_so);
-  int *status = m->status.as<int>();
-  float4 *pos = m->pos.as<float4>();
-  int2 *pool_nbr = nl ? nl->nbr.as<int2>() : m->nbr.as<int2>();
-  int *pool_cnt = nl ? nl->cnt.as<int>() : m->nbr_cnt.as<int>();
-  AtomState *pool_state = nl ? nl->state.as<AtomState>() : m->state.as<AtomState>();
-  if (nl) launch_skin_check(coords, dsys, n_sys, pool_state, 0.5f * nl->skin, nl->stats.as<int>(), st);
-  // AEV models accumulate forces in fixed point (converted by the reduction),
-  // DeepPot-style models in float32 straight in the output
-  const bool fix_forces = mode == kFull && o.forces && m->kind == kDescAev;
-  unsigned long long *Ffix = fix_forces ? m->Ffix.as<unsigned long long>() : nullptr;
-  launch_ingest(coords, species, pin.mask, dsys, n_sys, N, m->S, pos, m->sys_of.as<int>(), pool_state,
-                status, mode == kFull && !fix_forces ? o.forces : nullptr, Ffix, st);
-  mark();
-  if (pairs) {
-    // the caller's list replaces the cell search (stage "cells" stays empty)
+    auto mark = [&]() {
+      if (ev) (void)hipEventRecord(ev[stage++], st);
+    };
+    // per-site events while tuning (every site launches at most once per call)
+    const bool tuning = m->tuning && mode == kFull;
+    auto site_begin = [&](int site) {
+      if (tuning) {
+        (void)hipEventRecord(m->tune_ev[site][0], st);
+        m->tune_hit[site] = true;
+      }
+    };
+    auto site_end = [&](int site) {
+      if (tuning) (void)hipEventRecord(m->tune_ev[site][1], st);
+    };
     mark();
-    launch_pairs_to_rows(pin.pairs, pin.shifts, pin.n, pin.half, pin.mask, pos, N, sd[0].L, rc_list, cap,
-                         pool_nbr, pool_cnt, status, st);
-  } else if (all_small) {
+    SysDesc *dsys = (SysDesc *)(m->desc.as<char>() + off_sd);
+    const int *d_chunk_sys = (const int *)(m->desc.as<char>() + off_cs);
+    const int *d_chunk_begin = (const int *)(m->desc.as<char>() + off_cb);
+    const int *d_sys_chunk_off = (const int *)(m->desc.as<char>() + off_so);
+    int *status = m->status.as<int>();
+    float4 *pos = m->pos.as<float4>();
+    int2 *pool_nbr = nl ? nl->nbr.as<int2>() : m->nbr.as<int2>();
+    int *pool_cnt = nl ? nl->cnt.as<int>() : m->nbr_cnt.as<int>();
+    AtomState *pool_state = nl ? nl->state.as<AtomState>() : m->state.as<AtomState>();
+    if (nl) launch_skin_check(coords, dsys, lS, pool_state, 0.5f * nl->skin, nl->stats.as<int>(), st);
+    // AEV models accumulate forces in fixed point (converted by the reduction),
+    // DeepPot-style models in float32 straight in the output
+    const bool fix_forces = mode == kFull && o.forces && m->kind == kDescAev;
+    unsigned long long *Ffix = fix_forces ? m->Ffix.as<unsigned long long>() : nullptr;
+    launch_ingest(coords, species, pin.mask, dsys, lS, lN, m->S, pos, m->sys_of.as<int>(), pool_state,
+                  status, mode == kFull && !fix_forces ? o.forces : nullptr, Ffix, st);
     mark();
-    launch_nbr_small(pos, m->sys_of.as<int>(), dsys, N, rc_list, cap, pool_nbr, pool_cnt, status, st);
-  } else {
-    launch_grid(dsys, n_sys, pos, m->cell_count.as<int>(), rc_list, st);
-    launch_cell_count(pos, m->sys_of.as<int>(), dsys, N, m->cell_count.as<int>(), m->atom_cell.as<int>(),
-                      m->atom_slot.as<int>(), st);
-    launch_scan(m->cell_count.as<int>(), m->cell_start.as<int>(), (int)C, st);
-    launch_cell_scatter(m->atom_cell.as<int>(), m->atom_slot.as<int>(), m->cell_start.as<int>(), N,
-                        m->cell_atoms.as<int>(), st);
-    launch_cell_sort(m->cell_start.as<int>(), (int)C, m->cell_atoms.as<int>(), st);
+    if (pairs) {
+      // the caller's list replaces the cell search (stage "cells" stays empty)
+      mark();
+      launch_pairs_to_rows(pin.pairs, pin.shifts, pin.n, pin.half, pin.mask, pos, N, sd[0].L, rc_list, cap,
+                           pool_nbr, pool_cnt, status, st);
+    } else if (all_small) {
+      mark();
+      launch_nbr_small(pos, m->sys_of.as<int>(), dsys, lN, rc_list, cap, pool_nbr, pool_cnt, status, st);
+    } else {
+      launch_grid(dsys, lS, pos, m->cell_count.as<int>(), rc_list, st);
+      launch_cell_count(pos, m->sys_of.as<int>(), dsys, lN, m->cell_count.as<int>(), m->atom_cell.as<int>(),
+                        m->atom_slot.as<int>(), st);
+      launch_scan(m->cell_count.as<int>(), m->cell_start.as<int>(), lC, st);
+      launch_cell_scatter(m->atom_cell.as<int>(), m->atom_slot.as<int>(), m->cell_start.as<int>(), lN,
+                          m->cell_atoms.as<int>(), st);
+      launch_cell_sort(m->cell_start.as<int>(), lC, m->cell_atoms.as<int>(), st);
+      mark();
+      launch_nbr_build(pos, m->sys_of.as<int>(), dsys, lS, (int)C_l, m->cell_start.as<int>(),
+                       m->cell_atoms.as<int>(), lN, rc_list, cap, pool_nbr, pool_cnt, status, st);
+    }
+    if (mode == kNbr) {
+      launch_export_nbr(pool_nbr, pool_cnt, cap, dsys, m->sys_of.as<int>(), N, o.nb_counts,
+                        o.nb_entries, o.nb_cap, st);
+      HIP_TRY(hipGetLastError());
+      return NNP_OK;
+    }
     mark();
-    launch_nbr_build(pos, m->sys_of.as<int>(), dsys, n_sys, (int)C, m->cell_start.as<int>(),
-                     m->cell_atoms.as<int>(), N, rc_list, cap, pool_nbr, pool_cnt, status, st);
-  }
-  if (mode == kNbr) {
-    launch_export_nbr(pool_nbr, pool_cnt, cap, dsys, m->sys_of.as<int>(), N, o.nb_counts,
-                      o.nb_entries, o.nb_cap, st);
-    HIP_TRY(hipGetLastError());
-    return NNP_OK;
-  }
-  mark();
-  const int nblk = (N + 1023) / 1024;
-  const int rows = (N + kTileM - 1) / kTileM * kTileM + m->S * kTileM;
-  launch_species_bucket(pos, N, m->S, m->block_counts.as<int>(), nblk, m->bucket_off.as<int>(),
-                        m->bucket_cnt.as<int>(), m->perm.as<int>(), m->row_of_atom.as<int>(), rows, st);
-  // atoms outside a caller's mask have no network: zero atomic energy
-  // atomic energies go straight to the caller's buffer when one is given
-  // (every atom's entry is written each call), else to the workspace
-  float *e_atom = o.atom_energy ? o.atom_energy : m->e_atom.as<float>();
-  if (pin.mask) launch_fill(e_atom, (size_t)N, 0.f, st);
-  mark();
-  const int D = m->D;
-  const bool bf16 = m->precision == NNP_BF16;
-  const bool dp = m->kind == kDescDp;
-  const bool want_grad = o.forces != nullptr;
-  // descriptor forward into rows of G (the AEV export: float32 rows of the
-  // dE/dG buffer, gathered back to atom order)
-  auto descriptor = [&](void *Gp, bool g_bf16, int ldg, float4 *rec, int wpb) {
-    if (dp)
-      launch_dp_fwd(pos, coords, pool_state, m->sys_of.as<int>(), dsys, pool_nbr, pool_cnt, cap,
-                    m->row_of_atom.as<int>(), Gp, g_bf16, ldg, N, m->dp, rec, wpb, st);
-    else
-      launch_aev_fwd(pos, m->sys_of.as<int>(), dsys, pool_nbr, pool_cnt, cap, m->row_of_atom.as<int>(), Gp,
-                     g_bf16, ldg, N, m->aev, wpb, st);
-  };
-  if (mode == kAev) {
-    descriptor(m->dG.p, false, D, nullptr, 0);
-    launch_gather_rows(m->dG.as<float>(), D, m->row_of_atom.as<int>(), N, D, o.aev, st);
-    HIP_TRY(hipGetLastError());
-    return NNP_OK;
-  }
-  site_begin(kSiteAevFwd);
-  descriptor(m->G.p, bf16, m->ldG, dp && want_grad ? m->dp_rec.as<float4>() : nullptr,
-             m->tune_val[kSiteAevFwd]);
-  site_end(kSiteAevFwd);
-  mark();
+    const int nblk = (N_l + 1023) / 1024;
+    const int rows = (N_l + kTileM - 1) / kTileM * kTileM + m->S * kTileM;
+    launch_species_bucket(pos, lN, m->S, m->block_counts.as<int>(), nblk, m->bucket_off.as<int>(),
+                          m->bucket_cnt.as<int>(), m->perm.as<int>(), m->row_of_atom.as<int>(), rows, st);
+    // atoms outside a caller's mask have no network: zero atomic energy
+    // atomic energies go straight to the caller's buffer when one is given
+    // (every atom's entry is written each call), else to the workspace
+    float *e_atom = o.atom_energy ? o.atom_energy : m->e_atom.as<float>();
+    if (pin.mask) launch_fill(e_atom, (size_t)N, 0.f, st);
+    mark();
+    const int D = m->D;
+    const bool bf16 = m->precision == NNP_BF16;
+    const bool dp = m->kind == kDescDp;
+    const bool want_grad = o.forces != nullptr;
+    // descriptor forward into rows of G (the AEV export: float32 rows of the
+    // dE/dG buffer, gathered back to atom order)
+    auto descriptor = [&](void *Gp, bool g_bf16, int ldg, float4 *rec, int wpb) {
+      if (dp)
+        launch_dp_fwd(pos, coords, pool_state, m->sys_of.as<int>(), dsys, pool_nbr, pool_cnt, cap,
+                      m->row_of_atom.as<int>(), Gp, g_bf16, ldg, N, m->dp, rec, wpb, st);
+      else
+        launch_aev_fwd(pos, m->sys_of.as<int>(), dsys, pool_nbr, pool_cnt, cap, m->row_of_atom.as<int>(), Gp,
+                       g_bf16, ldg, lN, m->aev, wpb, st);
+    };
+    if (mode == kAev) {
+      descriptor(m->dG.p, false, D, nullptr, 0);
+      launch_gather_rows(m->dG.as<float>(), D, m->row_of_atom.as<int>(), N, D, o.aev, st);
+      HIP_TRY(hipGetLastError());
+      return NNP_OK;
+    }
+    site_begin(kSiteAevFwd);
+    descriptor(m->G.p, bf16, m->ldG, dp && want_grad ? m->dp_rec.as<float4>() : nullptr,
+               m->tune_val[kSiteAevFwd]);
+    site_end(kSiteAevFwd);
+    mark();
 
-  // element networks: forward, output layer, backward to dE/dG; every launch
-  // covers all species and all ensemble members of one layer index
-  const int row_tiles = rows / kTileM;
-  const int L = m->L, M = m->M, S = m->S;
-  auto common = [&](GemmLaunch &gl) {
-    gl.bucket_off = m->bucket_off.as<int>();
-    gl.n_groups = S;
-    gl.alpha = m->alpha;
-    gl.scale = 1.f;
-    gl.n_members = M;
-    gl.n_seg = 1;
-  };
-  // with the fused chain only the first layer runs as a separate GEMM
-  const bool use_chain = m->chain && bf16;
-  for (int l = 0; l + 1 < (use_chain ? 2 : L); ++l) {
-    GemmLaunch gl{};
-    common(gl);
-    gl.A = l == 0 ? m->G.p : m->H[l - 1].p;
-    gl.lda = l == 0 ? m->ldG : M * m->ldH[l - 1];
-    gl.a_member_stride = l == 0 ? 0 : m->ldH[l - 1];
-    gl.C = m->H[l].p;
-    gl.ldc = M * m->ldH[l];
-    gl.c_member_stride = m->ldH[l];
-    for (int mb = 0; mb < M; ++mb)
-      for (int s = 0; s < S; ++s) {
-        LayerW &lw = m->layer(mb, s, l);
-        GemmGroup &g = gl.g[mb * S + s];
-        g.B = bf16 ? (const void *)lw.Wb : (const void *)lw.W;
-        g.bias = lw.b;
-        g.n_out = lw.n_out;
-        g.K = lw.n_in;
-        if (l == 0 && bf16) g.K = g.ldb = m->ldG;  // zero-padded columns on both sides
-      }
-    site_begin(kSiteGemmFwd + l);
-    launch_gemm(kEpiFwd, bf16, gl, row_tiles, m->ldH[l], m->tune_val[kSiteGemmFwd + l], st);
-    site_end(kSiteGemmFwd + l);
-  }
-  if (use_chain) {
-    ChainLaunch cl = m->chain_proto;
-    cl.H0 = (const uint16_t *)m->H[0].p;
-    cl.ldh = M * m->ldH[0];
-    cl.h_member_stride = m->ldH[0];
-    cl.D0 = (uint16_t *)m->Gd[0].p;
-    cl.ldd = M * m->ldH[0];
-    cl.d_member_stride = m->ldH[0];
-    cl.nets = m->chain_nets.as<ChainNet>();
-    cl.bucket_off = m->bucket_off.as<int>();
-    cl.n_groups = S;
-    cl.n_members = M;
-    cl.alpha = m->alpha;
-    cl.inv_m = 1.0f / (float)M;
-    cl.e_mem = m->e_mem.as<float>();
-    cl.perm = m->perm.as<int>();
-    cl.e_atom = e_atom;
-    site_begin(kSiteChain);
-    // tuned shape: 4 or 8 waves, plus 10 for 64-row workgroups
-    const int tv = m->tune_val[kSiteChain];
-    launch_chain(cl, L - 2, want_grad, rows, m->chain_lds, tv % 10 == 4 ? 4 : 8,
-                 tv >= 10 && m->chain_rt2 ? 2 : 1, st);
-    site_end(kSiteChain);
-  } else {
-    EnergyLaunch el{};
-    el.Hin = L >= 2 ? m->H[L - 2].p : m->G.p;
-    el.ldh = L >= 2 ? M * m->ldH[L - 2] : m->ldG;
-    el.h_member_stride = L >= 2 ? m->ldH[L - 2] : 0;
-    el.Gout = L >= 2 ? m->Gd[L - 2].p : m->dG.p;
-    el.ldg = L >= 2 ? M * m->ldH[L - 2] : D;
-    el.g_member_stride = L >= 2 ? m->ldH[L - 2] : 0;
-    for (int mb = 0; mb < M; ++mb)
-      for (int s = 0; s < S; ++s) {
-        LayerW &lw = m->layer(mb, s, L - 1);
-        el.w[mb * S + s] = lw.W;
-        el.b[mb * S + s] = lw.b;
-        el.K[s] = lw.n_in;
-      }
-    el.perm = m->perm.as<int>();
-    el.bucket_off = m->bucket_off.as<int>();
-    el.n_groups = S;
-    el.n_members = M;
-    el.e_atom = e_atom;
-    el.inv_m = 1.0f / (float)M;
-    el.alpha = m->alpha;
-    el.hidden = L >= 2;
-    el.want_grad = want_grad;
-    // the no-hidden-layer form reads float32 AEVs and writes float32 dE/dG
-    launch_energy(el, bf16, rows, st);
-  }
-  if (want_grad) {
-    for (int l = L - 2; l >= 1 && !use_chain; --l) {
+    // element networks: forward, output layer, backward to dE/dG; every launch
+    // covers all species and all ensemble members of one layer index
+    const int row_tiles = rows / kTileM;
+    const int L = m->L, M = m->M, S = m->S;
+    auto common = [&](GemmLaunch &gl) {
+      gl.bucket_off = m->bucket_off.as<int>();
+      gl.n_groups = S;
+      gl.alpha = m->alpha;
+      gl.scale = 1.f;
+      gl.n_members = M;
+      gl.n_seg = 1;
+    };
+    // with the fused chain only the first layer runs as a separate GEMM
+    const bool use_chain = m->chain && bf16;
+    for (int l = 0; l + 1 < (use_chain ? 2 : L); ++l) {
       GemmLaunch gl{};
       common(gl);
-      gl.A = m->Gd[l].p;
-      gl.lda = M * m->ldH[l];
-      gl.a_member_stride = m->ldH[l];
-      gl.C = m->Gd[l - 1].p;
-      gl.ldc = M * m->ldH[l - 1];
-      gl.c_member_stride = m->ldH[l - 1];
-      gl.H = m->H[l - 1].p;
-      gl.ldh = M * m->ldH[l - 1];
-      gl.h_member_stride = m->ldH[l - 1];
+      gl.A = l == 0 ? m->G.p : m->H[l - 1].p;
+      gl.lda = l == 0 ? m->ldG : M * m->ldH[l - 1];
+      gl.a_member_stride = l == 0 ? 0 : m->ldH[l - 1];
+      gl.C = m->H[l].p;
+      gl.ldc = M * m->ldH[l];
+      gl.c_member_stride = m->ldH[l];
       for (int mb = 0; mb < M; ++mb)
         for (int s = 0; s < S; ++s) {
           LayerW &lw = m->layer(mb, s, l);
           GemmGroup &g = gl.g[mb * S + s];
-          g.B = bf16 ? (const void *)lw.Wtb : (const void *)lw.Wt;
-          g.n_out = lw.n_in;
-          g.K = lw.n_out;
+          g.B = bf16 ? (const void *)lw.Wb : (const void *)lw.W;
+          g.bias = lw.b;
+          g.n_out = lw.n_out;
+          g.K = lw.n_in;
+          if (l == 0 && bf16) g.K = g.ldb = m->ldG;  // zero-padded columns on both sides
         }
-      site_begin(kSiteGemmBwd + l);
-      launch_gemm(kEpiBwd, bf16, gl, row_tiles, m->ldH[l - 1], m->tune_val[kSiteGemmBwd + l], st);
-      site_end(kSiteGemmBwd + l);
+      site_begin(kSiteGemmFwd + l);
+      launch_gemm(kEpiFwd, bf16, gl, row_tiles, m->ldH[l], m->tune_val[kSiteGemmFwd + l], st);
+      site_end(kSiteGemmFwd + l);
     }
-    if (L >= 2) {
-      // dE/dG = sum over members of delta_0^m W_0^m: members are K segments
-      GemmLaunch gl{};
-      common(gl);
-      gl.n_members = 1;
-      gl.n_seg = M;
-      gl.A = m->Gd[0].p;
-      gl.lda = M * m->ldH[0];
-      gl.a_seg_stride = m->ldH[0];
-      gl.C = m->dG.p;
-      gl.ldc = D;
-      for (int s = 0; s < S; ++s) {
-        GemmGroup &g = gl.g[s];
-        g.B = bf16 ? (const void *)m->Wdg_b[s] : (const void *)m->Wdg[s];
-        g.n_out = D;
-        g.K = m->widths[s][1];
-      }
-      site_begin(kSiteGemmOut);
-      launch_gemm(kEpiOut, bf16, gl, row_tiles, D, m->tune_val[kSiteGemmOut], st);
-      site_end(kSiteGemmOut);
-    }
-  }
-  mark();
-  if (want_grad) {
-    site_begin(kSiteAevBwd);
-    if (dp) {
-      // cells exist for this call unless the pair list or the small-system scan replaced them
-      const bool cells = !pairs && !all_small;
-      launch_dp_bwd(dsys, n_sys, all_small, cells ? m->cell_start.as<int>() : nullptr,
-                    m->cell_atoms.as<int>(), (int)C, m->row_of_atom.as<int>(), m->dG.as<float>(), D, N, m->dp,
-                    m->dp_rec.as<float4>(), o.forces, m->W_atom.as<float>(), m->tune_val[kSiteAevBwd], st);
+    if (use_chain) {
+      ChainLaunch cl = m->chain_proto;
+      cl.H0 = (const uint16_t *)m->H[0].p;
+      cl.ldh = M * m->ldH[0];
+      cl.h_member_stride = m->ldH[0];
+      cl.D0 = (uint16_t *)m->Gd[0].p;
+      cl.ldd = M * m->ldH[0];
+      cl.d_member_stride = m->ldH[0];
+      cl.nets = m->chain_nets.as<ChainNet>();
+      cl.bucket_off = m->bucket_off.as<int>();
+      cl.n_groups = S;
+      cl.n_members = M;
+      cl.alpha = m->alpha;
+      cl.inv_m = 1.0f / (float)M;
+      cl.e_mem = m->e_mem.as<float>();
+      cl.perm = m->perm.as<int>();
+      cl.e_atom = e_atom;
+      site_begin(kSiteChain);
+      // tuned shape: 4 or 8 waves, plus 10 for 64-row workgroups
+      const int tv = m->tune_val[kSiteChain];
+      launch_chain(cl, L - 2, want_grad, rows, m->chain_lds, tv % 10 == 4 ? 4 : 8,
+                   tv >= 10 && m->chain_rt2 ? 2 : 1, st);
+      site_end(kSiteChain);
     } else {
-      AevBwdGroups gp;
-      if (!groups.empty()) {
-        gp.groups = (const int2 *)(m->desc.as<char>() + dl.gr);
-        gp.n_groups = (int)groups.size();
-        gp.max_sys_atoms = max_sys_atoms;
-      } else if (!pairs && !all_small) {
-        gp.cell_start = m->cell_start.as<int>();
-        gp.cell_atoms = m->cell_atoms.as<int>();
-        gp.n_cells = (int)C;
-      }
-      launch_aev_bwd(pos, m->sys_of.as<int>(), dsys, pool_nbr, pool_cnt, cap,
-                     m->row_of_atom.as<int>(), m->dG.as<float>(), D, N, m->aev, Ffix,
-                     m->W_atom.as<float>(), gp, m->tune_val[kSiteAevBwd], m->max_lds, st);
+      EnergyLaunch el{};
+      el.Hin = L >= 2 ? m->H[L - 2].p : m->G.p;
+      el.ldh = L >= 2 ? M * m->ldH[L - 2] : m->ldG;
+      el.h_member_stride = L >= 2 ? m->ldH[L - 2] : 0;
+      el.Gout = L >= 2 ? m->Gd[L - 2].p : m->dG.p;
+      el.ldg = L >= 2 ? M * m->ldH[L - 2] : D;
+      el.g_member_stride = L >= 2 ? m->ldH[L - 2] : 0;
+      for (int mb = 0; mb < M; ++mb)
+        for (int s = 0; s < S; ++s) {
+          LayerW &lw = m->layer(mb, s, L - 1);
+          el.w[mb * S + s] = lw.W;
+          el.b[mb * S + s] = lw.b;
+          el.K[s] = lw.n_in;
+        }
+      el.perm = m->perm.as<int>();
+      el.bucket_off = m->bucket_off.as<int>();
+      el.n_groups = S;
+      el.n_members = M;
+      el.e_atom = e_atom;
+      el.inv_m = 1.0f / (float)M;
+      el.alpha = m->alpha;
+      el.hidden = L >= 2;
+      el.want_grad = want_grad;
+      // the no-hidden-layer form reads float32 AEVs and writes float32 dE/dG
+      launch_energy(el, bf16, rows, st);
     }
-    site_end(kSiteAevBwd);
+    if (want_grad) {
+      for (int l = L - 2; l >= 1 && !use_chain; --l) {
+        GemmLaunch gl{};
+        common(gl);
+        gl.A = m->Gd[l].p;
+        gl.lda = M * m->ldH[l];
+        gl.a_member_stride = m->ldH[l];
+        gl.C = m->Gd[l - 1].p;
+        gl.ldc = M * m->ldH[l - 1];
+        gl.c_member_stride = m->ldH[l - 1];
+        gl.H = m->H[l - 1].p;
+        gl.ldh = M * m->ldH[l - 1];
+        gl.h_member_stride = m->ldH[l - 1];
+        for (int mb = 0; mb < M; ++mb)
+          for (int s = 0; s < S; ++s) {
+            LayerW &lw = m->layer(mb, s, l);
+            GemmGroup &g = gl.g[mb * S + s];
+            g.B = bf16 ? (const void *)lw.Wtb : (const void *)lw.Wt;
+            g.n_out = lw.n_in;
+            g.K = lw.n_out;
+          }
+        site_begin(kSiteGemmBwd + l);
+        launch_gemm(kEpiBwd, bf16, gl, row_tiles, m->ldH[l - 1], m->tune_val[kSiteGemmBwd + l], st);
+        site_end(kSiteGemmBwd + l);
+      }
+      if (L >= 2) {
+        // dE/dG = sum over members of delta_0^m W_0^m: members are K segments
+        GemmLaunch gl{};
+        common(gl);
+        gl.n_members = 1;
+        gl.n_seg = M;
+        gl.A = m->Gd[0].p;
+        gl.lda = M * m->ldH[0];
+        gl.a_seg_stride = m->ldH[0];
+        gl.C = m->dG.p;
+        gl.ldc = D;
+        for (int s = 0; s < S; ++s) {
+          GemmGroup &g = gl.g[s];
+          g.B = bf16 ? (const void *)m->Wdg_b[s] : (const void *)m->Wdg[s];
+          g.n_out = D;
+          g.K = m->widths[s][1];
+        }
+        site_begin(kSiteGemmOut);
+        launch_gemm(kEpiOut, bf16, gl, row_tiles, D, m->tune_val[kSiteGemmOut], st);
+        site_end(kSiteGemmOut);
+      }
+    }
+    mark();
+    if (want_grad) {
+      site_begin(kSiteAevBwd);
+      if (dp) {
+        // cells exist for this call unless the pair list or the small-system scan replaced them
+        const bool cells = !pairs && !all_small;
+        launch_dp_bwd(dsys, n_sys, all_small, cells ? m->cell_start.as<int>() : nullptr,
+                      m->cell_atoms.as<int>(), (int)C, m->row_of_atom.as<int>(), m->dG.as<float>(), D, N, m->dp,
+                      m->dp_rec.as<float4>(), o.forces, m->W_atom.as<float>(), m->tune_val[kSiteAevBwd], st);
+      } else {
+        AevBwdGroups gp;
+        if (!groups.empty()) {
+          gp.groups = (const int2 *)(m->desc.as<char>() + dl.gr);
+          gp.n_groups = groups_l;
+          gp.max_sys_atoms = max_sys_atoms;
+          if (graph) gp.live_groups = &live->n_groups;
+        } else if (!pairs && !all_small) {
+          gp.cell_start = m->cell_start.as<int>();
+          gp.cell_atoms = m->cell_atoms.as<int>();
+          gp.n_cells = (int)C_l;
+          if (graph) gp.live_cells = &live->n_cells;
+        }
+        launch_aev_bwd(pos, m->sys_of.as<int>(), dsys, pool_nbr, pool_cnt, cap,
+                       m->row_of_atom.as<int>(), m->dG.as<float>(), D, lN, m->aev, Ffix,
+                       m->W_atom.as<float>(), gp, m->tune_val[kSiteAevBwd], m->max_lds, st);
+      }
+      site_end(kSiteAevBwd);
+    }
+    mark();
+    launch_reduce(e_atom, want_grad ? m->W_atom.as<float>() : nullptr, dsys, lS,
+                  d_chunk_sys, d_chunk_begin, lChunks, d_sys_chunk_off,
+                  !graph && one_chunk_each && n_chunks == n_sys,
+                  m->partial.as<double>(), o.energy, o.virial, Ffix, o.forces, st);
+    mark();
+    if (ev) m->last_stages = stage - 1;
+    HIP_TRY(hipGetLastError());
+    return NNP_OK;
+  };
+  if (!graph) {
+    if (gr && gr->pre) gr->pre(gr->ctx, st, N, n_sys, nullptr);
+    int rc2 = enqueue(st);
+    if (rc2) return rc2;
+    if (gr && gr->post) gr->post(gr->ctx, st, N, n_sys, nullptr);
+    HIP_TRY(hipGetLastError());
+    return NNP_OK;
   }
-  mark();
-  launch_reduce(e_atom, want_grad ? m->W_atom.as<float>() : nullptr, dsys, n_sys,
-                d_chunk_sys, d_chunk_begin, n_chunks, d_sys_chunk_off, one_chunk_each,
-                m->partial.as<double>(), o.energy, o.virial, Ffix, o.forces, st);
-  mark();
-  if (ev) m->last_stages = stage - 1;
-  HIP_TRY(hipGetLastError());
-  return NNP_OK;
+  return replay(m, gr, st, N_l, S_l, C_l, groups_l, all_small, cap,
+                {coords, species, o.energy, o.forces, o.virial, o.atom_energy, nl, (const void *)gr->pre,
+                 (const void *)gr->post, gr->ctx, m->desc.p, nullptr},
+                [&](hipStream_t cs) -> int {
+                  if (gr->pre) gr->pre(gr->ctx, cs, N_l, S_l, live);
+                  int rc2 = enqueue(cs);
+                  if (rc2) return rc2;
+                  if (gr->post) gr->post(gr->ctx, cs, N_l, S_l, live);
+                  return NNP_OK;
+                });
 }
 
 extern "C" int nnp_energy_forces(nnp_model *m, int n_systems, const int64_t *offs, const float *coords,
@@ -1322,18 +1517,21 @@ extern "C" int nnp_autotune(nnp_model *m, int n_systems, const int64_t *offs, co
   CallOut o;
   o.energy = energy;
   o.forces = forces;
-  // candidates: round r sets every GEMM site to kTn[r], both AEV sites to
-  // kWpb[r] and the fused chain to kChainW[r] waves per workgroup
-  constexpr int kRounds = 3, kReps = 3;
-  const int kTn[kRounds] = {64, 128, 256}, kWpb[kRounds] = {1, 2, 4};
+  // candidates: round r sets every GEMM site to kTn[r], the AEV forward to
+  // kWpb[r] waves per workgroup, the AEV backward to kBwd[r] (1: a wave per
+  // centre with device atomics; 5, 4, 8: a grouped form with that many
+  // waves) and the fused chain to kChainW[r] waves per workgroup
+  constexpr int kRounds = 4, kReps = 3;
+  const int kTn[kRounds] = {64, 128, 256, 128}, kWpb[kRounds] = {1, 2, 4, 2};
+  const int kBwd[kRounds] = {1, 5, 4, 8};
   // chain: 8 or 4 waves on 32 rows, 8 waves on 64 rows (+10) when the LDS allows
-  const int kChainW[kRounds] = {8, 4, m->chain_rt2 ? 18 : 8};
+  const int kChainW[kRounds] = {8, 4, m->chain_rt2 ? 18 : 8, 8};
   double t[kTuneSites][kRounds] = {};
   bool hit[kTuneSites] = {};
   int rc = NNP_OK;
   for (int r = 0; r < kRounds && rc == NNP_OK; ++r) {
     for (int q = 0; q < kTuneSites; ++q)
-      m->tune_val[q] = q < kSiteGemmFwd ? kWpb[r] : q == kSiteChain ? kChainW[r] : kTn[r];
+      m->tune_val[q] = q == kSiteAevBwd ? kBwd[r] : q < kSiteGemmFwd ? kWpb[r] : q == kSiteChain ? kChainW[r] : kTn[r];
     rc = run(m, n_systems, offs, coords, species, box, o, st, kFull);  // warm-up
     for (int k = 0; k < kReps && rc == NNP_OK; ++k) {
       m->tuning = true;
@@ -1361,7 +1559,7 @@ extern "C" int nnp_autotune(nnp_model *m, int n_systems, const int64_t *offs, co
     } else {
       int best = 0;
       for (int r = 1; r < kRounds; ++r) if (t[q][r] < t[q][best]) best = r;
-      m->tune_val[q] = q < kSiteGemmFwd ? kWpb[best] : kTn[best];
+      m->tune_val[q] = q == kSiteAevBwd ? kBwd[best] : q < kSiteGemmFwd ? kWpb[best] : kTn[best];
     }
   }
   (void)hipFree(energy);
@@ -1421,6 +1619,25 @@ extern "C" int nnp_nlist_builds(nnp_nlist *nl, void *stream, int64_t *builds) {
   *builds = h;
   return NNP_OK;
 }
+
+namespace nnp {
+int run_nlist(nnp_model *m, nnp_nlist *nl, int n_systems, const int64_t *offs, const int64_t *slots,
+              const int32_t *rebuild, const float *coords, const int32_t *species, const float *box,
+              double *energy, float *forces, double *virial, float *atom_energy, hipStream_t st,
+              GraphRun *gr) {
+  if (!nl) return fail(NNP_EINVAL, "null neighbour-list pool");
+  CallOut o;
+  o.energy = energy;
+  o.forces = forces;
+  o.virial = virial;
+  o.atom_energy = atom_energy;
+  ListPool lp;
+  lp.nl = nl;
+  lp.slots = slots;
+  lp.rebuild = rebuild;
+  return run(m, n_systems, offs, coords, species, box, o, st, kFull, lp, PairIn(), gr);
+}
+}  // namespace nnp
 
 extern "C" int nnp_energy_forces_nlist(nnp_model *m, nnp_nlist *nl, int n_systems, const int64_t *offs,
                                        const int64_t *slots, const int32_t *rebuild, const float *coords,

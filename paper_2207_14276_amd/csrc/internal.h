@@ -23,6 +23,49 @@ int model_species(const nnp_model *m);
 // Per-slot neighbour counts of a pool (kept past the capacity on overflow).
 const int *nlist_counts(const nnp_nlist *nl);
 
+struct CallSizes;
+// Graph replay of calls on persistent lists (serving).  A call's launches
+// are recorded once per capacity bucket (its atom and system counts rounded
+// up to the bucket, which sizes every grid) into a HIP graph together with
+// the caller's own kernels before and after them, and replayed for every
+// later call in the bucket: the kernels read the call's own sizes from its
+// descriptors (uploaded before the replay).  pre/post get the launch sizes
+// and the device address of the live sizes (null when launched directly).
+struct GraphCache;
+GraphCache *graph_cache_create();
+void graph_cache_destroy(GraphCache *gc);
+struct GraphRun {
+  void (*pre)(void *ctx, hipStream_t st, int n_launch, int s_launch, const CallSizes *live) = nullptr;
+  void (*post)(void *ctx, hipStream_t st, int n_launch, int s_launch, const CallSizes *live) = nullptr;
+  void *ctx = nullptr;
+  GraphCache *cache = nullptr;
+  hipStream_t capture_stream = nullptr;  // a stream of the caller's own (capture is not allowed on the null stream)
+  bool use_graph = true;                 // false: the same launches, issued directly with the exact sizes
+  long long captures = 0, replays = 0;   // counted here
+};
+// The capacity bucket of a size (what recorded launches are sized for).
+int64_t launch_bucket(int64_t v);
+int run_nlist(nnp_model *m, nnp_nlist *nl, int n_systems, const int64_t *offs, const int64_t *slots,
+              const int32_t *rebuild, const float *coords, const int32_t *species, const float *box,
+              double *energy, float *forces, double *virial, float *atom_energy, hipStream_t st,
+              GraphRun *gr);
+
+// A launch size: the value itself or, for launches recorded once and
+// replayed for calls of other sizes (a graph per capacity bucket, its grids
+// sized for the bucket), the device address where every call leaves its own
+// value.  Kernels read it once on entry; blocks past the live size leave.
+struct Live {
+  int v;
+  const int *p;
+  __host__ __device__ Live(int v_ = 0, const int *p_ = nullptr) : v(v_), p(p_) {}
+  __device__ __forceinline__ int get() const { return p ? *p : v; }
+};
+
+// Sizes of a call, the first bytes of its device descriptors.
+struct CallSizes {
+  int N, n_sys, n_cells, n_chunks, n_groups, pad[3];
+};
+
 constexpr int kWave = 64;
 constexpr int kMaxSpecies = 7;
 constexpr int kNShfRad = 16;
@@ -188,32 +231,32 @@ struct EnergyLaunch {
 };
 
 // ---- launchers (stream-ordered, no host sync)
-void launch_skin_check(const float *coords, SysDesc *sys, int n_sys, const AtomState *state,
+void launch_skin_check(const float *coords, SysDesc *sys, Live n_sys, const AtomState *state,
                        float half_skin, int *stats, hipStream_t st);
 // zero_forces (nullable): the force output, cleared here for the backward
 // zero_fix (nullable): the fixed-point force accumulators, cleared here
 void launch_ingest(const float *coords, const int *species, const unsigned char *mask,
-                   const SysDesc *sys, int n_sys, int N, int S, float4 *pos, int *sys_of,
+                   const SysDesc *sys, Live n_sys, Live N, int S, float4 *pos, int *sys_of,
                    AtomState *state, int *status, float *zero_forces, unsigned long long *zero_fix,
                    hipStream_t st);
 constexpr int kSmallSystem = 512;   // largest non-periodic system of the small-system search
-void launch_nbr_small(const float4 *pos, const int *sys_of, const SysDesc *sys, int N, float rc_list,
+void launch_nbr_small(const float4 *pos, const int *sys_of, const SysDesc *sys, Live N, float rc_list,
                       int cap, int2 *nbr, int *nbr_cnt, int *status, hipStream_t st);
 void launch_pairs_to_rows(const int *pairs, const int *shifts, long long n_pairs, int half,
                           const unsigned char *mask, const float4 *pos, int N, const float L[3],
                           float rc, int cap, int2 *nbr, int *nbr_cnt, int *status, hipStream_t st);
-void launch_grid(SysDesc *sys, int n_sys, const float4 *pos, int *cell_count, float rc_list,
+void launch_grid(SysDesc *sys, Live n_sys, const float4 *pos, int *cell_count, float rc_list,
                  hipStream_t st);
-void launch_cell_count(const float4 *pos, const int *sys_of, const SysDesc *sys, int N,
+void launch_cell_count(const float4 *pos, const int *sys_of, const SysDesc *sys, Live N,
                        int *cell_count, int *atom_cell, int *atom_slot, hipStream_t st);
-void launch_scan(const int *in, int *out, int n, hipStream_t st);
+void launch_scan(const int *in, int *out, Live n, hipStream_t st);
 void launch_cell_scatter(const int *atom_cell, const int *atom_slot, const int *cell_start,
-                         int N, int *cell_atoms, hipStream_t st);
-void launch_cell_sort(const int *cell_start, int n_cells, int *cell_atoms, hipStream_t st);
-void launch_nbr_build(const float4 *pos, const int *sys_of, const SysDesc *sys, int n_sys, int n_cells,
-                      const int *cell_start, const int *cell_atoms, int N, float rc_list, int cap,
+                         Live N, int *cell_atoms, hipStream_t st);
+void launch_cell_sort(const int *cell_start, Live n_cells, int *cell_atoms, hipStream_t st);
+void launch_nbr_build(const float4 *pos, const int *sys_of, const SysDesc *sys, Live n_sys, int n_cells,
+                      const int *cell_start, const int *cell_atoms, Live N, float rc_list, int cap,
                       int2 *nbr, int *nbr_cnt, int *status, hipStream_t st);
-void launch_species_bucket(const float4 *pos, int N, int S, int *block_counts, int n_blocks,
+void launch_species_bucket(const float4 *pos, Live N, int S, int *block_counts, int n_blocks,
                            int *bucket_off, int *bucket_cnt, int *perm, int *row_of_atom,
                            int rows_cap, hipStream_t st);
 // DeepPot-style descriptor: forward into G rows (and the per-centre slot
@@ -228,21 +271,24 @@ void launch_dp_bwd(const SysDesc *sys, int n_sys, bool small_systems, const int 
                    const DpConst &c, const float4 *rec, float *F, float *W_atom, int wpb_pref, hipStream_t st);
 void launch_aev_fwd(const float4 *pos, const int *sys_of, const SysDesc *sys, const int2 *nbr,
                     const int *nbr_cnt, int cap, const int *row_of_atom, void *G, bool g_bf16,
-                    int ldg, int N, const AevConst &c, int wpb_pref, hipStream_t st);
+                    int ldg, Live N, const AevConst &c, int wpb_pref, hipStream_t st);
 // How the AEV backward groups its centres (at most one of the two forms):
 // groups[n_groups] = {first centre, count} of consecutive centres of one
 // small non-periodic system (max_sys_atoms: the largest such system), or the
-// cell grid of the call.  Neither: one wave per centre.
+// cell grid of the call.  Neither: one wave per centre.  Launches sized for
+// more groups or cells than a call has read the live counts from live_*
+// (nullable).
 struct AevBwdGroups {
   const int2 *groups = nullptr;
   int n_groups = 0, max_sys_atoms = 0;
   const int *cell_start = nullptr, *cell_atoms = nullptr;
   int n_cells = 0;
+  const int *live_groups = nullptr, *live_cells = nullptr;
 };
 // Forces go into Ffix [N][3] (64-bit fixed point, cleared by the caller).
 void launch_aev_bwd(const float4 *pos, const int *sys_of, const SysDesc *sys, const int2 *nbr,
                     const int *nbr_cnt, int cap, const int *row_of_atom, const float *dG,
-                    int ldg, int N, const AevConst &c, unsigned long long *Ffix, float *W_atom,
+                    int ldg, Live N, const AevConst &c, unsigned long long *Ffix, float *W_atom,
                     const AevBwdGroups &gp, int wpb_pref, size_t max_lds, hipStream_t st);
 // tn_pref: column-tile width 64 or 128 (anything else: the width heuristic);
 // wpb_pref below: waves per workgroup 1, 2 or 4 when the LDS fits (else the default).
@@ -252,12 +298,16 @@ void launch_energy(const EnergyLaunch &el, bool bf16, int rows, hipStream_t st);
 // LDS), else 32
 void launch_chain(ChainLaunch cl, int n_hidden, bool grad, int rows, size_t lds_bytes, int waves, int rt,
                   hipStream_t st);
+// src: host memory the device reads directly (coherent pinned); bytes are
+// rounded up to 16 on both sides
+void launch_copy_from_host(const void *src, void *dst, size_t bytes, hipStream_t st);
 void launch_fill(float *p, size_t n, float v, hipStream_t st);
 void launch_fill_i32(int *p, size_t n, int v, hipStream_t st);
-// Ffix (nullable): fixed-point forces, converted into F [N][3] float32 here
-void launch_reduce(const float *e_atom, const float *W_atom, const SysDesc *sys, int n_sys,
-                   const int *chunk_sys, const int *chunk_begin, int n_chunks,
-                   const int *sys_chunk_off, bool one_chunk_each, double *partial, double *energy, double *virial,
+// Ffix (nullable): fixed-point forces, converted into F [N][3] float32 here.
+// direct: chunk s is system s for every system (one pass, no partials).
+void launch_reduce(const float *e_atom, const float *W_atom, const SysDesc *sys, Live n_sys,
+                   const int *chunk_sys, const int *chunk_begin, Live n_chunks,
+                   const int *sys_chunk_off, bool direct, double *partial, double *energy, double *virial,
                    const unsigned long long *Ffix, float *F, hipStream_t st);
 void launch_gather_rows(const float *src, int ld, const int *row_of_atom, int N, int D,
                         float *dst, hipStream_t st);

@@ -644,9 +644,10 @@ k_reduce_partial(const float *__restrict__ e_atom, const float *__restrict__ W_a
                  const SysDesc *__restrict__ sys, const int *__restrict__ chunk_sys,
                  const int *__restrict__ chunk_begin, double *__restrict__ partial,
                  double *__restrict__ energy, double *__restrict__ virial,
-                 const unsigned long long *__restrict__ Ffix, float *__restrict__ F) {
+                 const unsigned long long *__restrict__ Ffix, float *__restrict__ F, Live n_chunks) {
   __shared__ double red[10][256 / kWave];
   const int ch = blockIdx.x;
+  if (ch >= n_chunks.get()) return;  // the whole workgroup
   const SysDesc &d = sys[chunk_sys[ch]];
   const int b = chunk_begin[ch];
   const int e = min(b + kChunk, d.atom_off + d.n);
@@ -681,9 +682,9 @@ k_reduce_partial(const float *__restrict__ e_atom, const float *__restrict__ W_a
 }
 
 __global__ void k_reduce_final(const double *__restrict__ partial, const int *__restrict__ sys_chunk_off,
-                               int n_sys, double *__restrict__ energy, double *__restrict__ virial) {
+                               Live n_sys, double *__restrict__ energy, double *__restrict__ virial) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= n_sys) return;
+  if (s >= n_sys.get()) return;
   double acc[10];
   for (int q = 0; q < 10; ++q) acc[q] = 0.0;
   for (int ch = sys_chunk_off[s]; ch < sys_chunk_off[s + 1]; ++ch)
@@ -693,18 +694,18 @@ __global__ void k_reduce_final(const double *__restrict__ partial, const int *__
     for (int q = 0; q < 9; ++q) virial[(size_t)9 * s + q] = acc[1 + q];
 }
 
-void launch_reduce(const float *e_atom, const float *W_atom, const SysDesc *sys, int n_sys,
-                   const int *chunk_sys, const int *chunk_begin, int n_chunks,
-                   const int *sys_chunk_off, bool one_chunk_each, double *partial, double *energy,
+void launch_reduce(const float *e_atom, const float *W_atom, const SysDesc *sys, Live n_sys,
+                   const int *chunk_sys, const int *chunk_begin, Live n_chunks,
+                   const int *sys_chunk_off, bool direct, double *partial, double *energy,
                    double *virial, const unsigned long long *Ffix, float *F, hipStream_t st) {
-  const bool direct = one_chunk_each && n_chunks == n_sys;
-  // every system exactly one chunk (chunk s is system s): the chunk sums are
-  // the system sums, no second pass
-  if (n_chunks > 0)
-    k_reduce_partial<<<n_chunks, 256, 0, st>>>(e_atom, W_atom, sys, chunk_sys, chunk_begin, partial,
-                                               direct ? energy : nullptr, direct ? virial : nullptr, Ffix, F);
-  if (n_sys > 0 && !direct)
-    k_reduce_final<<<(n_sys + 127) / 128, 128, 0, st>>>(partial, sys_chunk_off, n_sys, energy, virial);
+  // direct: every system exactly one chunk (chunk s is system s), the chunk
+  // sums are the system sums, no second pass
+  if (n_chunks.v > 0)
+    k_reduce_partial<<<n_chunks.v, 256, 0, st>>>(e_atom, W_atom, sys, chunk_sys, chunk_begin, partial,
+                                                 direct ? energy : nullptr, direct ? virial : nullptr, Ffix, F,
+                                                 n_chunks);
+  if (n_sys.v > 0 && !direct)
+    k_reduce_final<<<(n_sys.v + 127) / 128, 128, 0, st>>>(partial, sys_chunk_off, n_sys, energy, virial);
 }
 
 }  // namespace nnp

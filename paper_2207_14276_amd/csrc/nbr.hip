@@ -14,10 +14,11 @@ constexpr int kIngestLdsSystems = 1024;  // more systems: staging costs more tha
 
 __global__ void k_ingest(const float *__restrict__ coords, const int *__restrict__ species,
                          const unsigned char *__restrict__ mask,
-                         const SysDesc *__restrict__ sys, int n_sys, int N, int S,
+                         const SysDesc *__restrict__ sys, Live n_sys_, Live N_, int S,
                          float4 *__restrict__ pos, int *__restrict__ sys_of,
                          AtomState *__restrict__ state, int *__restrict__ status,
                          float *__restrict__ zero_forces, unsigned long long *__restrict__ zero_fix) {
+  const int n_sys = n_sys_.get(), N = N_.get();
   // the systems' first atoms, staged in LDS when they fit: the search below
   // then waits on LDS instead of on a chain of dependent global loads
   __shared__ int s_off[kIngestLdsSystems];
@@ -84,22 +85,22 @@ __global__ void k_ingest(const float *__restrict__ coords, const int *__restrict
 }
 
 void launch_ingest(const float *coords, const int *species, const unsigned char *mask,
-                   const SysDesc *sys, int n_sys, int N, int S, float4 *pos, int *sys_of,
+                   const SysDesc *sys, Live n_sys, Live N, int S, float4 *pos, int *sys_of,
                    AtomState *state, int *status, float *zero_forces, unsigned long long *zero_fix,
                    hipStream_t st) {
-  if (N <= 0) return;
-  k_ingest<<<(N + 255) / 256, 256, 0, st>>>(coords, species, mask, sys, n_sys, N, S, pos, sys_of,
+  if (N.v <= 0) return;
+  k_ingest<<<(N.v + 255) / 256, 256, 0, st>>>(coords, species, mask, sys, n_sys, N, S, pos, sys_of,
                                             state, status, zero_forces, zero_fix);
 }
 
 // One wave per system: a system that keeps its neighbour list is rebuilt
 // once any atom has moved more than half the skin since the last build
 // (then no pair can have entered the cutoff unseen).  stats[0] counts builds.
-__global__ void k_skin_check(const float *__restrict__ coords, SysDesc *__restrict__ sys, int n_sys,
+__global__ void k_skin_check(const float *__restrict__ coords, SysDesc *__restrict__ sys, Live n_sys,
                              const AtomState *__restrict__ state, float half_skin,
                              int *__restrict__ stats) {
   const int s = blockIdx.x;
-  if (s >= n_sys) return;
+  if (s >= n_sys.get()) return;
   const int lane = threadIdx.x;
   const SysDesc d = sys[s];
   int rebuild = d.rebuild;
@@ -120,20 +121,20 @@ __global__ void k_skin_check(const float *__restrict__ coords, SysDesc *__restri
   }
 }
 
-void launch_skin_check(const float *coords, SysDesc *sys, int n_sys, const AtomState *state,
+void launch_skin_check(const float *coords, SysDesc *sys, Live n_sys, const AtomState *state,
                        float half_skin, int *stats, hipStream_t st) {
-  if (n_sys <= 0) return;
-  k_skin_check<<<n_sys, kWave, 0, st>>>(coords, sys, n_sys, state, half_skin, stats);
+  if (n_sys.v <= 0) return;
+  k_skin_check<<<n_sys.v, kWave, 0, st>>>(coords, sys, n_sys, state, half_skin, stats);
 }
 
 // -------------------------------------------------------------- cell grids
 // One wave per system.  Periodic: the host already set nc/edge.  Non-periodic:
 // cells of edge >= rc_list over the bounding box, at most cell_cap cells.
 // Also clears the system's cell counters.
-__global__ void k_grid(SysDesc *__restrict__ sys, int n_sys, const float4 *__restrict__ pos,
+__global__ void k_grid(SysDesc *__restrict__ sys, Live n_sys, const float4 *__restrict__ pos,
                        int *__restrict__ cell_count, float rc_list) {
   int s = blockIdx.x;
-  if (s >= n_sys) return;
+  if (s >= n_sys.get()) return;
   int lane = threadIdx.x;
   SysDesc d = sys[s];
   if (!d.periodic) {
@@ -177,10 +178,10 @@ __global__ void k_grid(SysDesc *__restrict__ sys, int n_sys, const float4 *__res
   for (int c = lane; c < d.cell_cap; c += kWave) cell_count[d.cell_off + c] = 0;
 }
 
-void launch_grid(SysDesc *sys, int n_sys, const float4 *pos, int *cell_count, float rc_list,
+void launch_grid(SysDesc *sys, Live n_sys, const float4 *pos, int *cell_count, float rc_list,
                  hipStream_t st) {
-  if (n_sys <= 0) return;
-  k_grid<<<n_sys, kWave, 0, st>>>(sys, n_sys, pos, cell_count, rc_list);
+  if (n_sys.v <= 0) return;
+  k_grid<<<n_sys.v, kWave, 0, st>>>(sys, n_sys, pos, cell_count, rc_list);
 }
 
 __device__ inline int cell_coord(float x, float o, float e, int nc) {
@@ -189,10 +190,10 @@ __device__ inline int cell_coord(float x, float o, float e, int nc) {
 }
 
 __global__ void k_cell_count(const float4 *__restrict__ pos, const int *__restrict__ sys_of,
-                             const SysDesc *__restrict__ sys, int N, int *__restrict__ cell_count,
+                             const SysDesc *__restrict__ sys, Live N, int *__restrict__ cell_count,
                              int *__restrict__ atom_cell, int *__restrict__ atom_slot) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= N) return;
+  if (i >= N.get()) return;
   const SysDesc &d = sys[sys_of[i]];
   float4 p = pos[i];
   int cx = cell_coord(p.x, d.origin[0], d.edge[0], d.nc[0]);
@@ -203,17 +204,18 @@ __global__ void k_cell_count(const float4 *__restrict__ pos, const int *__restri
   atom_slot[i] = atomicAdd(&cell_count[c], 1);
 }
 
-void launch_cell_count(const float4 *pos, const int *sys_of, const SysDesc *sys, int N,
+void launch_cell_count(const float4 *pos, const int *sys_of, const SysDesc *sys, Live N,
                        int *cell_count, int *atom_cell, int *atom_slot, hipStream_t st) {
-  if (N <= 0) return;
-  k_cell_count<<<(N + 255) / 256, 256, 0, st>>>(pos, sys_of, sys, N, cell_count, atom_cell,
+  if (N.v <= 0) return;
+  k_cell_count<<<(N.v + 255) / 256, 256, 0, st>>>(pos, sys_of, sys, N, cell_count, atom_cell,
                                                 atom_slot);
 }
 
 // Exclusive prefix sum, out[0..n]: one workgroup of 1024 threads walks the
 // array in coalesced 1024-element steps, carrying the running total.
 __global__ void __launch_bounds__(1024) k_scan(const int *__restrict__ in, int *__restrict__ out,
-                                               int n) {
+                                               Live n_) {
+  const int n = n_.get();
   __shared__ int wsum[1024 / kWave];
   __shared__ int carry_s;
   const int t = threadIdx.x, lane = t % kWave, w = t / kWave;
@@ -238,22 +240,22 @@ __global__ void __launch_bounds__(1024) k_scan(const int *__restrict__ in, int *
   if (t == 0) out[n] = carry_s;
 }
 
-void launch_scan(const int *in, int *out, int n, hipStream_t st) {
+void launch_scan(const int *in, int *out, Live n, hipStream_t st) {
   k_scan<<<1, 1024, 0, st>>>(in, out, n);
 }
 
 __global__ void k_cell_scatter(const int *__restrict__ atom_cell, const int *__restrict__ atom_slot,
-                               const int *__restrict__ cell_start, int N,
+                               const int *__restrict__ cell_start, Live N,
                                int *__restrict__ cell_atoms) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= N) return;
+  if (i >= N.get()) return;
   cell_atoms[cell_start[atom_cell[i]] + atom_slot[i]] = i;
 }
 
-void launch_cell_scatter(const int *atom_cell, const int *atom_slot, const int *cell_start, int N,
+void launch_cell_scatter(const int *atom_cell, const int *atom_slot, const int *cell_start, Live N,
                          int *cell_atoms, hipStream_t st) {
-  if (N <= 0) return;
-  k_cell_scatter<<<(N + 255) / 256, 256, 0, st>>>(atom_cell, atom_slot, cell_start, N,
+  if (N.v <= 0) return;
+  k_cell_scatter<<<(N.v + 255) / 256, 256, 0, st>>>(atom_cell, atom_slot, cell_start, N,
                                                   cell_atoms);
 }
 
@@ -262,10 +264,11 @@ void launch_cell_scatter(const int *atom_cell, const int *atom_slot, const int *
 // rank sort in LDS; cells above kSortMax atoms keep their arrival order.
 constexpr int kSortMax = 2048;
 
-__global__ void __launch_bounds__(256) k_cell_sort(const int *__restrict__ cell_start, int n_cells,
+__global__ void __launch_bounds__(256) k_cell_sort(const int *__restrict__ cell_start, Live n_cells,
                                                    int *__restrict__ cell_atoms) {
   __shared__ int buf[kSortMax];
   const int c = blockIdx.x;
+  if (c >= n_cells.get()) return;
   const int b = cell_start[c], n = cell_start[c + 1] - b;
   if (n <= 1 || n > kSortMax) return;
   for (int k = threadIdx.x; k < n; k += blockDim.x) buf[k] = cell_atoms[b + k];
@@ -278,9 +281,9 @@ __global__ void __launch_bounds__(256) k_cell_sort(const int *__restrict__ cell_
   }
 }
 
-void launch_cell_sort(const int *cell_start, int n_cells, int *cell_atoms, hipStream_t st) {
-  if (n_cells <= 0) return;
-  k_cell_sort<<<n_cells, 256, 0, st>>>(cell_start, n_cells, cell_atoms);
+void launch_cell_sort(const int *cell_start, Live n_cells, int *cell_atoms, hipStream_t st) {
+  if (n_cells.v <= 0) return;
+  k_cell_sort<<<n_cells.v, 256, 0, st>>>(cell_start, n_cells, cell_atoms);
 }
 
 // ----------------------------------------------------------- neighbour list
@@ -304,11 +307,11 @@ __device__ inline void wrap_cell(int u, int nc, bool periodic, int &w, int &shif
 __global__ void __launch_bounds__(256)
 k_nbr_build(const float4 *__restrict__ pos, const int *__restrict__ sys_of,
             const SysDesc *__restrict__ sys, const int *__restrict__ cell_start,
-            const int *__restrict__ cell_atoms, int N, float rc_list, int cap,
+            const int *__restrict__ cell_atoms, Live N, float rc_list, int cap,
             int2 *__restrict__ nbr, int *__restrict__ nbr_cnt, int *__restrict__ status) {
   const int lane = threadIdx.x % kWave;
   const int i = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
-  if (i >= N) return;
+  if (i >= N.get()) return;
   const SysDesc d = sys[sys_of[i]];
   if (!d.rebuild) return;
   const float4 p = pos[i];
@@ -377,7 +380,7 @@ constexpr int kCandChunk = 1024;  // candidates staged at a time
 constexpr int kHomeChunk = 256;   // atoms of the home cell handled at a time
 
 __global__ void __launch_bounds__(256)
-k_nbr_cell(const float4 *__restrict__ pos, const SysDesc *__restrict__ sys, int n_sys,
+k_nbr_cell(const float4 *__restrict__ pos, const SysDesc *__restrict__ sys, Live n_sys_,
            const int *__restrict__ cell_start, const int *__restrict__ cell_atoms, float rc_list,
            int cap, int2 *__restrict__ nbr, int *__restrict__ nbr_cnt, int *__restrict__ status) {
   __shared__ float4 cpos[kCandChunk];   // candidate r_j (w: j as int bits)
@@ -387,7 +390,9 @@ k_nbr_cell(const float4 *__restrict__ pos, const SysDesc *__restrict__ sys, int 
   __shared__ int hidx[kHomeChunk], hcnt[kHomeChunk];
   const int tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
   const int cell = blockIdx.x;
-  // the system owning this cell: last s with cell_off <= cell
+  const int n_sys = n_sys_.get();
+  // the system owning this cell: last s with cell_off <= cell (cells past the
+  // last system's range leave below)
   int lo = 0, hi = n_sys - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
@@ -516,11 +521,11 @@ k_nbr_cell(const float4 *__restrict__ pos, const SysDesc *__restrict__ sys, int 
 // increasing j.
 __global__ void __launch_bounds__(256)
 k_nbr_small(const float4 *__restrict__ pos, const int *__restrict__ sys_of,
-            const SysDesc *__restrict__ sys, int N, float rc_list, int cap,
+            const SysDesc *__restrict__ sys, Live N, float rc_list, int cap,
             int2 *__restrict__ nbr, int *__restrict__ nbr_cnt, int *__restrict__ status) {
   const int lane = threadIdx.x % kWave;
   const int i = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
-  if (i >= N) return;
+  if (i >= N.get()) return;
   const SysDesc d = sys[sys_of[i]];
   if (!d.rebuild) return;
   const float4 p = pos[i];
@@ -550,24 +555,25 @@ k_nbr_small(const float4 *__restrict__ pos, const int *__restrict__ sys_of,
   }
 }
 
-void launch_nbr_small(const float4 *pos, const int *sys_of, const SysDesc *sys, int N, float rc_list,
+void launch_nbr_small(const float4 *pos, const int *sys_of, const SysDesc *sys, Live N, float rc_list,
                       int cap, int2 *nbr, int *nbr_cnt, int *status, hipStream_t st) {
-  if (N <= 0) return;
-  k_nbr_small<<<(N + 3) / 4, 256, 0, st>>>(pos, sys_of, sys, N, rc_list, cap, nbr, nbr_cnt, status);
+  if (N.v <= 0) return;
+  k_nbr_small<<<(N.v + 3) / 4, 256, 0, st>>>(pos, sys_of, sys, N, rc_list, cap, nbr, nbr_cnt, status);
 }
 
-void launch_nbr_build(const float4 *pos, const int *sys_of, const SysDesc *sys, int n_sys, int n_cells,
-                      const int *cell_start, const int *cell_atoms, int N, float rc_list, int cap,
+void launch_nbr_build(const float4 *pos, const int *sys_of, const SysDesc *sys, Live n_sys, int n_cells,
+                      const int *cell_start, const int *cell_atoms, Live N, float rc_list, int cap,
                       int2 *nbr, int *nbr_cnt, int *status, hipStream_t st) {
-  if (N <= 0) return;
+  if (N.v <= 0) return;
   // staging a cell's stencil pays off once cells hold several atoms (dense
   // boxes); sparse grids of small solutes are faster with a wave per atom
-  if (n_cells > 0 && N >= 8 * (long long)n_cells) {
+  // (decided on the launch sizes)
+  if (n_cells > 0 && N.v >= 8 * (long long)n_cells) {
     k_nbr_cell<<<n_cells, 256, 0, st>>>(pos, sys, n_sys, cell_start, cell_atoms, rc_list, cap, nbr,
                                         nbr_cnt, status);
     return;
   }
-  k_nbr_build<<<(N + 3) / 4, 256, 0, st>>>(pos, sys_of, sys, cell_start, cell_atoms, N, rc_list,
+  k_nbr_build<<<(N.v + 3) / 4, 256, 0, st>>>(pos, sys_of, sys, cell_start, cell_atoms, N, rc_list,
                                            cap, nbr, nbr_cnt, status);
 }
 
@@ -578,8 +584,9 @@ void launch_nbr_build(const float4 *pos, const int *sys_of, const SysDesc *sys, 
 constexpr int kBucketBlock = 1024;
 
 __global__ void __launch_bounds__(kBucketBlock)
-k_species_count(const float4 *__restrict__ pos, int N, int S, int *__restrict__ block_counts) {
+k_species_count(const float4 *__restrict__ pos, Live N_, int S, int *__restrict__ block_counts) {
   __shared__ int cnt[kMaxSpecies];
+  const int N = N_.get();
   if (threadIdx.x < kMaxSpecies) cnt[threadIdx.x] = 0;
   __syncthreads();
   int i = blockIdx.x * kBucketBlock + threadIdx.x;
@@ -659,9 +666,10 @@ k_species_scan(int *__restrict__ block_counts, int n_blocks, int S, int *__restr
 }
 
 __global__ void __launch_bounds__(kBucketBlock)
-k_species_scatter(const float4 *__restrict__ pos, int N, const int *__restrict__ block_base,
+k_species_scatter(const float4 *__restrict__ pos, Live N_, const int *__restrict__ block_base,
                   const int *__restrict__ bucket_off, int *__restrict__ perm,
                   int *__restrict__ row_of_atom) {
+  const int N = N_.get();
   __shared__ int wave_cnt[kBucketBlock / kWave][kMaxSpecies];
   int i = blockIdx.x * kBucketBlock + threadIdx.x;
   int w = threadIdx.x / kWave;
@@ -686,19 +694,37 @@ k_species_scatter(const float4 *__restrict__ pos, int N, const int *__restrict__
   }
 }
 
-void launch_species_bucket(const float4 *pos, int N, int S, int *block_counts, int n_blocks,
+void launch_species_bucket(const float4 *pos, Live N, int S, int *block_counts, int n_blocks,
                            int *bucket_off, int *bucket_cnt, int *perm, int *row_of_atom,
                            int rows_cap, hipStream_t st) {
   (void)rows_cap;
-  if (N > 0) k_species_count<<<n_blocks, kBucketBlock, 0, st>>>(pos, N, S, block_counts);
-  k_species_scan<<<1, 256, 0, st>>>(block_counts, N > 0 ? n_blocks : 0, S, bucket_off,
+  // blocks past the live atoms (launches sized for more) count zeros
+  if (N.v > 0) k_species_count<<<n_blocks, kBucketBlock, 0, st>>>(pos, N, S, block_counts);
+  k_species_scan<<<1, 256, 0, st>>>(block_counts, N.v > 0 ? n_blocks : 0, S, bucket_off,
                                     bucket_cnt, perm);
-  if (N > 0)
+  if (N.v > 0)
     k_species_scatter<<<n_blocks, kBucketBlock, 0, st>>>(pos, N, block_counts, bucket_off, perm,
                                                          row_of_atom);
 }
 
 // ----------------------------------------------------------------- utilities
+// Copies bytes (rounded up to 16) from host memory mapped for the device
+// (coherent pinned staging) into device memory with a kernel on the
+// stream's own queue: the per-call descriptors reach the device without a
+// copy-engine hand-off (about 25 us of latency per call).
+__global__ void __launch_bounds__(256) k_copy16(const uint4 *__restrict__ src, uint4 *__restrict__ dst,
+                                                size_t n16) {
+  for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n16; k += (size_t)gridDim.x * blockDim.x)
+    dst[k] = src[k];
+}
+
+void launch_copy_from_host(const void *src, void *dst, size_t bytes, hipStream_t st) {
+  const size_t n16 = (bytes + 15) / 16;
+  if (n16 == 0) return;
+  const size_t blocks = (n16 + 255) / 256;
+  k_copy16<<<(unsigned)(blocks < 256 ? blocks : 256), 256, 0, st>>>((const uint4 *)src, (uint4 *)dst, n16);
+}
+
 __global__ void k_fill(float *__restrict__ p, size_t n, float v) {
   size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   size_t stride = (size_t)gridDim.x * blockDim.x;

@@ -80,12 +80,12 @@ __device__ inline int find_sys(const ServeSys *sys, int n_sys, int i) {
 }
 
 // Batch coordinates and species from the store.
-__global__ void k_gather(const ServeSys *__restrict__ sys, int n_sys, const float *__restrict__ sx,
+__global__ void k_gather(const ServeSys *__restrict__ sys, Live n_sys, const float *__restrict__ sx,
                          const int *__restrict__ ss, float *__restrict__ bx, int *__restrict__ bs,
-                         int N) {
+                         Live N) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= N) return;
-  const ServeSys d = sys[find_sys(sys, n_sys, i)];
+  if (i >= N.get()) return;
+  const ServeSys d = sys[find_sys(sys, n_sys.get(), i)];
   const long long g = d.slot + (i - d.off);
   bx[3 * (size_t)i] = sx[3 * g];
   bx[3 * (size_t)i + 1] = sx[3 * g + 1];
@@ -96,10 +96,10 @@ __global__ void k_gather(const ServeSys *__restrict__ sys, int n_sys, const floa
 // The client's move after step `step`: x += sigma * z with z ~ N(0, 1) from
 // Philox (counter = (local atom, step + 1, 0, 0), key = seed) and the
 // Box-Muller transform (three of its four normals are used).
-__global__ void k_walk(const ServeSys *__restrict__ sys, int n_sys, float *__restrict__ sx, int N) {
+__global__ void k_walk(const ServeSys *__restrict__ sys, Live n_sys, float *__restrict__ sx, Live N) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= N) return;
-  const ServeSys d = sys[find_sys(sys, n_sys, i)];
+  if (i >= N.get()) return;
+  const ServeSys d = sys[find_sys(sys, n_sys.get(), i)];
   if (!d.move) return;
   const int a = i - d.off;
   const uint4 r = philox4x32_10(make_uint4((unsigned)a, (unsigned)(d.step + 1), 0u, 0u),
@@ -122,8 +122,10 @@ __global__ void k_walk(const ServeSys *__restrict__ sys, int n_sys, float *__res
 // are kept past the capacity, so an overflowing list shows here), one
 // workgroup per request.
 __global__ void __launch_bounds__(256) k_req_max_count(const ServeSys *__restrict__ sys,
-                                                       const int *__restrict__ counts, int *__restrict__ out) {
+                                                       const int *__restrict__ counts, int *__restrict__ out,
+                                                       Live n_sys) {
   __shared__ int red[256 / 64];
+  if ((int)blockIdx.x >= n_sys.get()) return;  // the whole workgroup
   const ServeSys d = sys[blockIdx.x];
   int mx = 0;
   for (int a = threadIdx.x; a < d.n; a += blockDim.x) mx = max(mx, counts[d.slot + a]);
@@ -241,6 +243,10 @@ struct nnp_server {
   int sticky = NNP_OK;              // an unexpected device flag (species checked at submission)
   int64_t max_batch_seen = 0;
   std::vector<int64_t> ready;       // finished, not yet handed out
+  // iterations as recorded graphs: the cache, the recording stream, counters
+  GraphRun gr;
+  hipStream_t cap_stream = nullptr;
+  double host_s = 0.0;              // host time in launch_iteration
 };
 
 namespace {
@@ -302,8 +308,38 @@ int retire_ready(nnp_server *s) {
   return NNP_OK;
 }
 
-// Admits what fits and launches one iteration if any request is in flight.
+// The server's launches before and after the evaluation of an iteration,
+// sized for n_l atoms and s_l requests; live (when recorded): the device
+// address of the iteration's own sizes.
+void serve_pre(void *ctx, hipStream_t st, int n_l, int s_l, const CallSizes *live) {
+  nnp_server *s = (nnp_server *)ctx;
+  const Live N(n_l, live ? &live->N : nullptr), S(s_l, live ? &live->n_sys : nullptr);
+  k_clear_flags<<<1, 64, 0, st>>>(const_cast<int *>(model_status_word(s->model)));
+  k_gather<<<(unsigned)((n_l + 255) / 256), 256, 0, st>>>(s->bsys.as<ServeSys>(), S, s->store_x.as<float>(),
+                                                          s->store_s.as<int>(), s->bx.as<float>(),
+                                                          s->bs.as<int>(), N);
+}
+
+void serve_post(void *ctx, hipStream_t st, int n_l, int s_l, const CallSizes *live) {
+  nnp_server *s = (nnp_server *)ctx;
+  const Live N(n_l, live ? &live->N : nullptr), S(s_l, live ? &live->n_sys : nullptr);
+  k_req_max_count<<<(unsigned)s_l, 256, 0, st>>>(s->bsys.as<ServeSys>(), nlist_counts(s->list),
+                                                 s->bcnt.as<int>(), S);
+  k_walk<<<(unsigned)((n_l + 255) / 256), 256, 0, st>>>(s->bsys.as<ServeSys>(), S, s->store_x.as<float>(), N);
+}
+
+int launch_iteration_impl(nnp_server *s, hipStream_t st, bool *launched);
+
+// Admits what fits and launches one iteration if any request is in flight
+// (host time counted).
 int launch_iteration(nnp_server *s, hipStream_t st, bool *launched) {
+  const double t0 = now_s();
+  const int rc = launch_iteration_impl(s, st, launched);
+  s->host_s += now_s() - t0;
+  return rc;
+}
+
+int launch_iteration_impl(nnp_server *s, hipStream_t st, bool *launched) {
   *launched = false;
   const double t = server_clock(s);
   std::vector<int64_t> admitted = s->sched->admit(t);
@@ -362,19 +398,13 @@ int launch_iteration(nnp_server *s, hipStream_t st, bool *launched) {
   const int64_t N = it.offs[S];
   s->max_batch_seen = std::max(s->max_batch_seen, N);
   HIP_TRY(hipMemcpyAsync(s->bsys.p, tab, sizeof(ServeSys) * (size_t)S, hipMemcpyHostToDevice, st));
-  const int tpb = 256;
-  const unsigned grid = (unsigned)((N + tpb - 1) / tpb);
-  k_clear_flags<<<1, 64, 0, st>>>(const_cast<int *>(model_status_word(s->model)));
-  k_gather<<<grid, tpb, 0, st>>>(s->bsys.as<ServeSys>(), S, s->store_x.as<float>(), s->store_s.as<int>(),
-                                 s->bx.as<float>(), s->bs.as<int>(), (int)N);
-  HIP_TRY(hipGetLastError());
-  rc = nnp_energy_forces_nlist(s->model, s->list, S, it.offs.data(), slots.data(), rebuild.data(),
-                               s->bx.as<float>(), s->bs.as<int32_t>(), boxes.data(), s->be.as<double>(),
-                               s->bf.as<float>(), nullptr, nullptr, st);
+  // the evaluation with the server's kernels before (flags, gather) and
+  // after (overflow counts, the client's move), as one recorded graph per
+  // capacity bucket or launched directly
+  rc = run_nlist(s->model, s->list, S, it.offs.data(), slots.data(), rebuild.data(), s->bx.as<float>(),
+                 s->bs.as<int32_t>(), boxes.data(), s->be.as<double>(), s->bf.as<float>(), nullptr, nullptr, st,
+                 &s->gr);
   if (rc) return rc;
-  k_req_max_count<<<S, 256, 0, st>>>(s->bsys.as<ServeSys>(), nlist_counts(s->list), s->bcnt.as<int>());
-  k_walk<<<grid, tpb, 0, st>>>(s->bsys.as<ServeSys>(), S, s->store_x.as<float>(), (int)N);
-  HIP_TRY(hipGetLastError());
 
   // results back to the host
   it.off_energy = 16;
@@ -426,8 +456,13 @@ extern "C" int nnp_server_create(nnp_model *m, const nnp_server_opts *o, nnp_ser
     return fail(NNP_ENOMEM, "%lld slots need %llu bytes; the budget is %llu", (long long)o->slots,
                 (unsigned long long)fixed, (unsigned long long)budget);
   // the largest per-iteration atom count whose batch buffers and workspace fit
+  // recorded iterations size their launches for the capacity bucket of
+  // their atom and request counts: the workspace is reserved for the buckets
+  const bool graphs = o->use_graphs != 0;
+  auto ws_atoms = [&](int64_t n) { return graphs ? launch_bucket(n) : n; };
+  const int ws_sys = graphs ? (int)launch_bucket(o->max_active) : o->max_active;
   auto need = [&](int64_t n) {
-    return fixed + 28ull * (uint64_t)n + model_workspace_bytes(m, n, o->max_active, true);
+    return fixed + 28ull * (uint64_t)n + model_workspace_bytes(m, ws_atoms(n), ws_sys, true);
   };
   int64_t hi = o->max_batch_atoms > 0 ? o->max_batch_atoms : o->slots;
   hi = std::min<int64_t>(hi, o->slots);
@@ -462,10 +497,25 @@ extern "C" int nnp_server_create(nnp_model *m, const nnp_server_opts *o, nnp_ser
     return rc;
   s->n_species = model_species(m);
   if ((rc = nnp_nlist_create(m, o->slots, cap, o->skin, &s->list))) return rc;
-  if ((rc = model_reserve_pooled(m, lo, o->max_active))) {
+  if ((rc = model_reserve_pooled(m, ws_atoms(lo), ws_sys))) {
     nnp_nlist_destroy(s->list);
     s->list = nullptr;
     return rc;
+  }
+  s->gr.pre = serve_pre;
+  s->gr.post = serve_post;
+  s->gr.ctx = s.get();
+  s->gr.use_graph = graphs;
+  if (graphs) {
+    s->gr.cache = graph_cache_create();
+    // recording needs a stream other than the null stream (default priority)
+    hipError_t e = hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+      s->cap_stream = nullptr;
+      nnp_server_destroy(s.release());
+      return fail(NNP_EDEVICE, "hipStreamCreate: %s", hipGetErrorString(e));
+    }
+    s->gr.capture_stream = s->cap_stream;
   }
   for (auto &it : s->ring) {
     hipError_t e = hipEventCreateWithFlags(&it.done, hipEventDisableTiming);
@@ -487,6 +537,8 @@ extern "C" void nnp_server_destroy(nnp_server *s) {
       (void)hipEventDestroy(it.done);
     }
   if (s->list) nnp_nlist_destroy(s->list);
+  graph_cache_destroy(s->gr.cache);
+  if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
   // flags raised by requests that failed alone are the server's business:
   // leave the model's flags clear for its next user
   (void)hipMemset(const_cast<int *>(model_status_word(s->model)), 0, 2 * sizeof(int));
@@ -606,6 +658,9 @@ extern "C" int nnp_server_stats(nnp_server *s, nnp_server_counters *out) {
   out->max_batch_seen = s->max_batch_seen;
   out->device_bytes = s->granted;
   out->list_builds = 0;
+  out->graph_captures = s->gr.captures;
+  out->graph_replays = s->gr.replays;
+  out->host_launch_s = s->host_s;
   if (s->list) {
     int rc = nnp_nlist_builds(s->list, nullptr, &out->list_builds);
     if (rc) return rc;

@@ -126,21 +126,27 @@ class ServerStats:
     max_batch_seen: int
     device_bytes: int
     list_builds: int
+    graph_captures: int
+    graph_replays: int
+    host_launch_s: float
 
 
 class Server:
     """The library's continuous-batching server on one model (which it then
     uses exclusively).  `hbm_budget` bytes of device memory (0 = 90% of what
-    is free) bound the per-iteration batch; see nnp_server_create."""
+    is free) bound the per-iteration batch; see nnp_server_create.
+    `use_graphs`: replay each iteration's kernels from a HIP graph recorded
+    once per capacity bucket (else launch them one by one)."""
 
     def __init__(self, model, slots: int, capacity: int = 256, skin: float = 1.0,
-                 max_batch_atoms: int = 0, max_active: int = 4096, hbm_budget: int = 0):
+                 max_batch_atoms: int = 0, max_active: int = 4096, hbm_budget: int = 0,
+                 use_graphs: bool = True):
         import torch
         self.torch = torch
         self.model = model
         self._lib = nat.load()
         opts = nat.nnp_server_opts(int(slots), int(capacity), float(skin), int(max_batch_atoms),
-                                   int(max_active), int(hbm_budget))
+                                   int(max_active), int(hbm_budget), 1 if use_graphs else 0)
         h = C.c_void_p()
         with torch.cuda.device(model.device):
             nat.check(self._lib.nnp_server_create(model.handle, C.byref(opts), C.byref(h)))
@@ -217,7 +223,7 @@ class Server:
     def stats(self) -> ServerStats:
         c = nat.nnp_server_counters()
         nat.check(self._lib.nnp_server_stats(self._h, C.byref(c)))
-        return ServerStats(*[int(getattr(c, f)) for f, _ in nat.nnp_server_counters._fields_])
+        return ServerStats(*[getattr(c, f) for f, _ in nat.nnp_server_counters._fields_])
 
 
 @dataclass

@@ -285,3 +285,30 @@ def test_bad_species_refused_at_submission(m32):
         srv.submit(Request(s.coords, sp, s.box, 2, 0.01, seed=1))
     srv.close()
     m32.status()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_graph_replay_equals_direct_launches(m32, m16, prec):
+    """The same requests served with every iteration replayed from a graph
+    recorded once per capacity bucket, and with every kernel launched
+    directly: identical walks, energies and forces, bit for bit (results do
+    not depend on the mix, so the two runs' different batching does not
+    matter); most iterations replay a graph recorded earlier."""
+    model = m32 if prec == "fp32" else m16
+    reqs = _requests(16, seed=21, nmin=20, nmax=900, steps=8)
+    g, sg = _run(model, reqs, spacing=0.001, use_graphs=True)
+    d, sd = _run(model, reqs, spacing=0.001, use_graphs=False)
+    log(f"[graphs {prec}] iterations {sg.iterations} (direct run: {sd.iterations}), "
+        f"graphs recorded {sg.graph_captures}, replays {sg.graph_replays}; host time per iteration "
+        f"{sg.host_launch_s / max(sg.iterations, 1) * 1e6:.0f} us with graphs, "
+        f"{sd.host_launch_s / max(sd.iterations, 1) * 1e6:.0f} us direct")
+    assert len(g.results) == len(d.results) == len(reqs)
+    for rid in range(len(reqs)):
+        a, b = g.results[rid], d.results[rid]
+        assert a.error == 0 and b.error == 0
+        assert np.array_equal(a.coords, b.coords)
+        assert np.array_equal(a.energies, b.energies)
+        assert np.array_equal(a.forces, b.forces)
+    assert sg.graph_replays == sg.iterations
+    assert 1 <= sg.graph_captures < sg.iterations
+    assert sd.graph_replays == 0 and sd.graph_captures == 0
