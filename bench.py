@@ -13,6 +13,8 @@ baseline.
 from __future__ import annotations
 
 import argparse
+import contextlib
+import gc
 import json
 import os
 import sys
@@ -52,6 +54,21 @@ def parse():
     p.add_argument("--graphs", default="both", choices=["on", "off", "both"],
                    help="serving: iterations replayed from recorded graphs, launched directly, or both")
     return p.parse_args()
+
+
+@contextlib.contextmanager
+def no_gc_pauses():
+    """A timed region without Python garbage-collection pauses: a full
+    collection over the interpreter's objects (torch alone holds hundreds of
+    thousands) takes tens of milliseconds on the host and would be charged
+    to whatever step it interrupts.  Collect first, keep the collector off
+    until the region ends."""
+    gc.collect()
+    gc.disable()
+    try:
+        yield
+    finally:
+        gc.enable()
 
 
 def cpu_model() -> str:
@@ -334,7 +351,8 @@ def serve_bench(args):
         torch.cuda.synchronize()
         srv = Server(model, slots=slots, capacity=cap, skin=1.0, use_graphs=use_graphs)
         say(args, f"serving ({'graphs' if use_graphs else 'direct launches'})")
-        rep = replay(srv, reqs())
+        with no_gc_pauses():
+            rep = replay(srv, reqs())
         st = srv.stats()
         srv.close()
         lat = rep.latencies(skip=skip) * 1e3
@@ -375,12 +393,13 @@ def serve_bench(args):
         g.manual_seed(int(r.seed))
         out = plain.energy_forces(c, s, box, offs)
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.req_steps):
-            plain.energy_forces(c, s, box, offs, out=out)
-            torch.cuda.synchronize()
-            c.add_(torch.randn(c.shape, generator=g, device=dev) * 0.01)
-        dt = time.perf_counter() - t0
+        with no_gc_pauses():
+            t0 = time.perf_counter()
+            for _ in range(args.req_steps):
+                plain.energy_forces(c, s, box, offs, out=out)
+                torch.cuda.synchronize()
+                c.add_(torch.randn(c.shape, generator=g, device=dev) * 0.01)
+            dt = time.perf_counter() - t0
         p_time += dt
         p_atoms += r.system.n * args.req_steps
         p_lat.append(dt * 1e3)
@@ -474,13 +493,14 @@ def hybrid_bench(args):
     ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
     model.set_timing(True)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        starts[k].record(st)
-        model.energy_forces_pairs(c, sp, full.box, pairs, shifts, mask, half=False, out=res)
-        ends[k].record(st)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
+    with no_gc_pauses():
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            starts[k].record(st)
+            model.energy_forces_pairs(c, sp, full.box, pairs, shifts, mask, half=False, out=res)
+            ends[k].record(st)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
     stages = model.stage_timings()
     model.set_timing(False)
     model.status()
@@ -490,11 +510,12 @@ def hybrid_bench(args):
     # the same region through the library's own cell search
     r2 = model.energy_forces(cs, ss, sub.boxes, sub.offsets, check=True)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        model.energy_forces(cs, ss, sub.boxes, sub.offsets, out=r2)
-    torch.cuda.synchronize()
-    own = n_ml * args.steps / (time.perf_counter() - t0)
+    with no_gc_pauses():
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            model.energy_forces(cs, ss, sub.boxes, sub.offsets, out=r2)
+        torch.cuda.synchronize()
+        own = n_ml * args.steps / (time.perf_counter() - t0)
 
     n_pairs, n_trip = pair_triplet_counts(model, sub, cs, ss)
     aev_fwd_flop = FLOP_RADIAL_FWD * n_pairs + FLOP_TRIPLET_FWD * n_trip
@@ -594,13 +615,14 @@ def snapshots_bench(args):
               for _ in range(args.steps)]
         model.set_timing(True)
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for a, b in ev:
-            a.record(st)
-            model.energy_forces(c, sp, batch.boxes, batch.offsets, forces=forces, out=r)
-            b.record(st)
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
+        with no_gc_pauses():
+            t0 = time.perf_counter()
+            for a, b in ev:
+                a.record(st)
+                model.energy_forces(c, sp, batch.boxes, batch.offsets, forces=forces, out=r)
+                b.record(st)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
         stages = model.stage_timings()
         model.set_timing(False)
         lat = np.array([a.elapsed_time(b) for a, b in ev])
@@ -619,11 +641,12 @@ def snapshots_bench(args):
             batch.boxes[k:k + 1], np.array([0, n_atoms], np.int64)) for k in pick]
     outs = [plain.energy_forces(*q, forces=False) for q in per]
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for q, o in zip(per, outs):
-        plain.energy_forces(*q, forces=False, out=o)
-    torch.cuda.synchronize()
-    plain_rate = len(pick) * n_atoms / (time.perf_counter() - t0)
+    with no_gc_pauses():
+        t0 = time.perf_counter()
+        for q, o in zip(per, outs):
+            plain.energy_forces(*q, forces=False, out=o)
+        torch.cuda.synchronize()
+        plain_rate = len(pick) * n_atoms / (time.perf_counter() - t0)
 
     # host BAR on the energies (target = reference restraint + network energy)
     x_ref = ref.coords.astype(np.float64)
@@ -730,13 +753,14 @@ def main():
     ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
     model.set_timing(True)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        starts[k].record(st)
-        model.energy_forces(c, sp, batch.boxes, batch.offsets, out=res)
-        ends[k].record(st)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
+    with no_gc_pauses():
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            starts[k].record(st)
+            model.energy_forces(c, sp, batch.boxes, batch.offsets, out=res)
+            ends[k].record(st)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
     stages = model.stage_timings()
     model.set_timing(False)
     model.status()
@@ -775,10 +799,10 @@ def main():
     small = bool(np.all(batch.boxes == 0)) and int(np.diff(batch.offsets).max()) <= 512
     if kname == "k_dp_bwd" and small:
         kname = "k_dp_bwd_sys"   # batches of small non-periodic systems: the per-system form
-    if kname == "k_aev_bwd" and tuned.get("aev_bwd_waves", 0) not in (1, 2):
-        # the form the library picks (unless tuned to a wave per centre): per
-        # system for batches of small non-periodic systems, per cell on grids
-        # of at least 512 cells
+    if kname == "k_aev_bwd" and tuned.get("aev_bwd_waves", 0) >= 4:
+        # a grouped form of the backward (tuned to 4-10 waves per workgroup):
+        # per system for batches of small non-periodic systems, per cell on
+        # grids of at least 512 cells
         if small:
             kname = "k_aev_bwd_sys"
         elif cell_count(batch, model_cutoff(spec)) >= 512:
@@ -837,11 +861,12 @@ def main():
         tp = []
         for _ in range(max(1, args.plain_passes)):
             torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            for p, o in zip(per_sys, outs):
-                plain.energy_forces(*p, out=o)
-            torch.cuda.synchronize()
-            tp.append(time.perf_counter() - t0)
+            with no_gc_pauses():
+                t0 = time.perf_counter()
+                for p, o in zip(per_sys, outs):
+                    plain.energy_forces(*p, out=o)
+                torch.cuda.synchronize()
+                tp.append(time.perf_counter() - t0)
         tplain = min(tp)
         out["plain_fp32_per_system"] = {"value": round(N / tplain, 1), "unit": "atom-evals/s",
                                         "ms_per_pass": round(tplain * 1e3, 3),
@@ -861,11 +886,12 @@ def main():
         for _ in range(args.warmup):
             m32.energy_forces(c, sp, batch.boxes, batch.offsets, out=res32)
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            m32.energy_forces(c, sp, batch.boxes, batch.offsets, out=res32)
-        torch.cuda.synchronize()
-        w32 = time.perf_counter() - t0
+        with no_gc_pauses():
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                m32.energy_forces(c, sp, batch.boxes, batch.offsets, out=res32)
+            torch.cuda.synchronize()
+            w32 = time.perf_counter() - t0
         m32.status()
         out["batched_fp32"] = {"value": round(N * args.steps / w32, 1), "unit": "atom-evals/s",
                                "ms_per_step": round(w32 / args.steps * 1e3, 4),

@@ -67,44 +67,11 @@ constexpr int kPairPass = kWave;  // neighbour pairs staged per pass
 constexpr int kMaxBlocks = kMaxSpecies * (kMaxSpecies + 1) / 2;
 constexpr int kMaxAng = kMaxBlocks * kAngBlock;  // 896 angular features
 
-// Non-empty species-pair block q of the centre's pair stream.  A pair is
-// addressed as (x, y): x in the longer species list (length n1), y in the
-// shorter one (n2); for a same-species block both are the one list.  The
-// angular term is symmetric in its two neighbours, so which of the two
-// species is called j does not matter.
-struct PairBlock {
-  int start;                   // first pair of the block in the stream
-  unsigned short ox, oy;       // angular-list offsets of the x and y lists
-  unsigned short n1, n2;       // their counts (n1 >= n2)
-  float r1, r2;                // 1 / n1, 1 / n2
-  unsigned char p;             // feature block index (upper-triangle order of (sa, sb))
-  unsigned char same;          // sa == sb
-  unsigned char pad0, pad1;
-};
-static_assert(sizeof(PairBlock) == 24, "pair-block table entry");
-
-__device__ inline PairBlock make_block(int start, int p, int oa, int ob, int na, int nb, bool same) {
-  PairBlock b;
-  const bool a_long = na >= nb;
-  b.start = start;
-  b.ox = (unsigned short)(a_long ? oa : ob); b.oy = (unsigned short)(a_long ? ob : oa);
-  b.n1 = (unsigned short)max(na, nb); b.n2 = (unsigned short)min(na, nb);
-  // hardware reciprocals (within an ulp): fdivmod corrects the quotient
-  b.r1 = fast_rcp((float)max((int)b.n1, 1));
-  b.r2 = fast_rcp((float)max((int)b.n2, 1));
-  b.p = (unsigned char)p; b.same = same ? 1 : 0;
-  b.pad0 = b.pad1 = 0;
-  return b;
-}
-// the table of one wave, padded to a multiple of 16 bytes
-constexpr size_t kBlkTableBytes = (sizeof(PairBlock) * (kMaxBlocks + 1) + 15) / 16 * 16;
-
 struct WaveLds {
   Lists *ls;       // per-species counts and offsets (wave-uniform)
   float2 *tGeo;    // pair scratch: cos, sin                      (forward)
   float4 *tF2;     // pair scratch: radial Gaussians of Rbar times
                    // fc_j fc_k                                     (forward)
-  PairBlock *blk;  // [kMaxBlocks + 1] pair-block table           (backward)
   float4 *rD;      // radial: d vector and R (forward: d / R and R)
   float *rFc;      // radial: fc_rad(R)          (forward)
   float2 *rF2;     // fc(R) and fc'(R): radial cutoff, then (angular entries)
@@ -127,7 +94,7 @@ __host__ __device__ inline size_t aidx16_bytes(int cap) { return ((size_t)cap * 
 
 template <bool BWD>
 __host__ __device__ inline size_t wave_lds_bytes(int cap) {
-  return sizeof(Lists) + (BWD ? kBlkTableBytes + (size_t)cap * (16 + 24 + 4 + 4 + 4 + 4)
+  return sizeof(Lists) + (BWD ? (size_t)cap * (16 + 24 + 4 + 4 + 4 + 4)
                               : (size_t)kPairPass * (8 + 16) +
                                     (size_t)cap * (16 + 4 + 4) + aidx16_bytes(cap));
 }
@@ -140,7 +107,6 @@ __device__ inline WaveLds carve(char *base, int cap) {
   if (BWD) {
     w.rD = (float4 *)p; p += (size_t)cap * 16;
     w.rG = (long long *)p; p += (size_t)cap * 24;
-    w.blk = (PairBlock *)p; p += kBlkTableBytes;
     w.rF2 = (float2 *)p; p += (size_t)cap * 8;
     w.rJ = (int *)p; p += (size_t)cap * 4;
     w.aIdx = (int *)p; p += (size_t)cap * 4;
@@ -155,34 +121,40 @@ __device__ inline WaveLds carve(char *base, int cap) {
   return w;
 }
 
-// Builds the table of non-empty species-pair blocks of the angular list
-// (wave-uniform values; lane 0 writes); returns the number of pairs.
-__device__ inline int build_blocks(int lane, const Lists &ls, int S, WaveLds &w, int &nblk) {
-  int q = 0, start = 0, p = 0;
-  for (int sa = 0; sa < S; ++sa)
-    for (int sb = sa; sb < S; ++sb, ++p) {
-      const int na = ls.cA[sa], nb = ls.cA[sb];
-      const int T = sa == sb ? na * (na - 1) / 2 : na * nb;
-      if (T == 0) continue;
-      if (lane == 0) w.blk[q] = make_block(start, p, ls.oA[sa], ls.oA[sb], na, nb, sa == sb);
-      ++q;
-      start += T;
-    }
-  if (lane == 0) w.blk[q].start = start;  // sentinel
-  nblk = q;
-  return start;
+// Lane b (< S (S + 1) / 2) describes species-pair block b of the centre's
+// angular pairs, in the upper-triangle order of (sa, sb) that is also the
+// feature order: its pair count T and the unrank fields of its two lists
+// (a pair is addressed as (x, y), x in the longer species list of length n1,
+// y in the shorter of length n2; a same-species block uses the one list
+// for both; the angular term is symmetric in its two neighbours):
+// oxy = offsets of the x and y lists (16 bits each), n12 = n1 | n2 << 16 |
+// same << 31, r1 = 1 / n1, r2 = 1 / n2 (hardware reciprocals: fdivmod
+// corrects the quotient).  Other lanes get T = 0.
+__device__ inline void block_words(int lane, const Lists &ls, int S, int &bT, int &bOxy, int &bN12, float &bR1,
+                                   float &bR2) {
+  bT = 0;
+  bOxy = 0;
+  bN12 = 0;
+  bR1 = 1.f;
+  bR2 = 1.f;
+  if (lane < S * (S + 1) / 2) {
+    int sa = 0, rem = lane;
+#pragma unroll
+    for (int s = 0; s < kMaxSpecies - 1; ++s)
+      if (sa == s && rem >= S - s) { rem -= S - s; sa = s + 1; }
+    const int sb = sa + rem;
+    const int na = ls.cA[sa], nb = ls.cA[sb], oa = ls.oA[sa], ob = ls.oA[sb];
+    const bool same = sa == sb;
+    bT = same ? na * (na - 1) / 2 : na * nb;
+    const bool a_long = na >= nb;
+    const int n1 = max(na, nb), n2 = min(na, nb);
+    bOxy = (a_long ? oa : ob) | ((a_long ? ob : oa) << 16);
+    bN12 = n1 | (n2 << 16) | (same ? (int)0x80000000u : 0);
+    bR1 = fast_rcp((float)max(n1, 1));
+    bR2 = fast_rcp((float)max(n2, 1));
+  }
 }
 
-// Pair u of a block, enumerated by diagonals so that consecutive pairs (the
-// lanes of one pass) mostly touch different neighbour entries:
-//   x = u mod n1 runs fastest, the diagonal number q = u div n1 shifts the
-//   partner: y = (x + q + same) mod n2.
-// Same species (n1 = n2 = n): diagonals d = q + 1 = 1, 2, ... give the pairs
-// (x, x + d mod n) once each; when n is even the last diagonal d = n/2 holds
-// only its first n/2 pairs, which is where u stops (u < n(n-1)/2).
-// Two species: q < n2 and every (x, y) occurs exactly once.
-// No branch depends on the block, so lanes of one pass in different blocks
-// do not diverge.
 __device__ inline void unrank(int u, int n1, int n2, float r1, float r2, int same, int ox, int oy,
                               int &ax, int &ay) {
   int x, y;
@@ -191,23 +163,6 @@ __device__ inline void unrank(int u, int n1, int n2, float r1, float r2, int sam
   ax = ox + x;
   ay = oy + y;
 }
-__device__ inline void unrank(int u, const PairBlock &b, int &ax, int &ay) {
-  unrank(u, b.n1, b.n2, b.r1, b.r2, b.same, b.ox, b.oy, ax, ay);
-}
-
-// Pair t of the stream -> its block (searched from the wave-uniform block
-// index qb of the pass), the positions of its two entries in the angular
-// list, and the feature block index.
-__device__ inline void locate_pair(int t, int qb, int nblk, int pass_end, const WaveLds &w,
-                                   int &aj, int &ak, int &p) {
-  int q = qb;
-  for (int r = qb + 1; r < nblk && w.blk[r].start < pass_end; ++r)
-    if (t >= w.blk[r].start) q = r;
-  const PairBlock b = w.blk[q];
-  unrank(t - b.start, b, aj, ak);
-  p = b.p;
-}
-
 // Builds the species-sorted radial list (R < rc_r) and angular list
 // (R < rc_a, a subset) of centre i in LDS.  Two passes over the entries:
 // per-species counts by ballot, then placement.
@@ -418,28 +373,11 @@ k_aev_fwd(const float4 *__restrict__ pos, const int *__restrict__ sys_of,
     const float cza = pick(c.cz, a), sza = pick(c.sz, a);
     const float pre = 1.0f - c.zeta;
     const float keta = -c.eta_a * 1.4426950408889634f;
-    // Lane b (< number of species pairs) describes species-pair block b, in
-    // the upper-triangle order of (sa, sb) that is also the feature order:
-    // its pair count and the unrank parameters of its two lists.
+    // lane b: species-pair block b (block_words)
     const int n_blk = c.S * (c.S + 1) / 2;
-    int bT = 0, bOxy = 0, bN12 = 0;
-    float bR1 = 1.f, bR2 = 1.f;
-    if (lane < n_blk) {
-      int sa = 0, rem = lane;
-#pragma unroll
-      for (int s = 0; s < kMaxSpecies - 1; ++s)
-        if (sa == s && rem >= c.S - s) { rem -= c.S - s; sa = s + 1; }
-      const int sb = sa + rem;
-      const int na = ls.cA[sa], nb = ls.cA[sb], oa = ls.oA[sa], ob = ls.oA[sb];
-      const bool same = sa == sb;
-      bT = same ? na * (na - 1) / 2 : na * nb;
-      const bool a_long = na >= nb;
-      const int n1 = max(na, nb), n2 = min(na, nb);
-      bOxy = (a_long ? oa : ob) | ((a_long ? ob : oa) << 16);
-      bN12 = n1 | (n2 << 16) | (same ? (int)0x80000000u : 0);
-      bR1 = fast_rcp((float)max(n1, 1));
-      bR2 = fast_rcp((float)max(n2, 1));
-    }
+    int bT, bOxy, bN12;
+    float bR1, bR2;
+    block_words(lane, ls, c.S, bT, bOxy, bN12, bR1, bR2);
     const unsigned long long nonempty = __ballot(bT > 0);
     // blocks without a pair of their two species are zero: written in one
     // pass of 16-byte stores over the angular part of the row
@@ -715,21 +653,50 @@ __device__ inline void bwd_centre(int i, int lane, const float4 *__restrict__ po
   wave_lds_sync();
 
   // angular: lane per neighbour pair over the pair stream of all blocks
+  // (the blocks' pairs one after another, in feature order)
   {
     const float *gA = g + c.rad_len;
-    int nblk;
-    const int P = build_blocks(lane, ls, c.S, w, nblk);
-    wave_lds_sync();
+    // lane b: species-pair block b, with the first pair of the block in the
+    // stream (an exclusive prefix sum of the counts over the lanes)
+    const int n_blk = c.S * (c.S + 1) / 2;
+    int bT, bOxy, bN12;
+    float bR1, bR2;
+    block_words(lane, ls, c.S, bT, bOxy, bN12, bR1, bR2);
+    int bStart = bT;
+#pragma unroll
+    for (int d = 1; d < 32; d <<= 1) {  // n_blk <= 28: the first 32 lanes hold every block
+      const int y = __shfl_up(bStart, d, 32);
+      if ((lane & 31) >= d) bStart += y;
+    }
+    const int P = __builtin_amdgcn_readlane(bStart, n_blk - 1);
+    bStart -= bT;
     const float pre = 1.0f - c.zeta;
     const float zm1 = c.zeta - 1.0f;
     const float keta = -c.eta_a * 1.4426950408889634f;
     const float m2eta = -2.0f * c.eta_a;
-    int qb = 0;
+    int qb = 0;  // the block holding the pass's first pair (wave-uniform)
     for (int base = 0; base < P; base += kPairPass) {
-      while (qb + 1 < nblk && w.blk[qb + 1].start <= base) ++qb;
+      while (qb + 1 < n_blk && __builtin_amdgcn_readlane(bStart, qb + 1) <= base) ++qb;
       const bool valid = base + lane < P;
-      int aj, ak, p;
-      locate_pair(min(base + lane, P - 1), qb, nblk, base + kPairPass, w, aj, ak, p);
+      const int t = min(base + lane, P - 1);
+      // this lane's block: the last one starting at or before its pair
+      // (an empty block starts where the next one does and is passed over);
+      // the pass's blocks are few, their starts wave-uniform
+      int p = qb;
+      for (int r = qb + 1; r < n_blk; ++r) {
+        const int sr = __builtin_amdgcn_readlane(bStart, r);
+        if (sr >= base + kPairPass) break;
+        p = t >= sr ? r : p;
+      }
+      const int pa = p << 2;
+      const int l_oxy = __builtin_amdgcn_ds_bpermute(pa, bOxy);
+      const int l_n12 = __builtin_amdgcn_ds_bpermute(pa, bN12);
+      const float l_r1 = __int_as_float(__builtin_amdgcn_ds_bpermute(pa, __float_as_int(bR1)));
+      const float l_r2 = __int_as_float(__builtin_amdgcn_ds_bpermute(pa, __float_as_int(bR2)));
+      const int l_start = __builtin_amdgcn_ds_bpermute(pa, bStart);
+      int aj, ak;
+      unrank(t - l_start, l_n12 & 0xffff, (l_n12 >> 16) & 0x7fff, l_r1, l_r2, (l_n12 >> 31) & 1,
+             l_oxy & 0xffff, (l_oxy >> 16) & 0xffff, aj, ak);
       const int qj = w.aIdx[aj], qk = w.aIdx[ak];
       const float4 dj = w.rD[qj], dk = w.rD[qk];
       const float2 cj2 = w.rF2[qj], ck2 = w.rF2[qk];  // angular fc and fc'
@@ -1010,14 +977,14 @@ static void aev_bwd_launch(int form, size_t lds, unsigned grid, const AevBwdGrou
                                                    Ffix, W_atom);
 }
 
-// Chooses the form.  wpb_pref 1 or 2: one wave per centre, forces straight
-// into Ffix by device atomics, that many waves per workgroup.  Otherwise a
-// grouped form when the call has one: per system for a batch of small
-// non-periodic systems (gp.groups), per cell on a grid of at least
-// kBwdMinCells cells (fewer would leave compute units idle), with wpb_pref
-// waves per workgroup (4, 5, 6, 8 or 10; default kBwdWaves), fewer when the
-// LDS does not hold them.  Without a grouped form: one wave per centre.
-constexpr int kBwdWaves = 8;
+// Chooses the form.  wpb_pref 0 (untuned), 1 or 2: one wave per centre,
+// forces straight into Ffix by device atomics, one or two waves per
+// workgroup (the fastest form measured on the ragged solutes and on the
+// 100k-atom box).  4, 5, 6, 8 or 10: a grouped form when the call has one,
+// with that many waves per workgroup (fewer when the LDS does not hold
+// them): per system for a batch of small non-periodic systems (gp.groups),
+// per cell on a grid of at least kBwdMinCells cells (fewer would leave
+// compute units idle).  Without a grouped form: one wave per centre.
 void launch_aev_bwd(const float4 *pos, const int *sys_of, const SysDesc *sys, const int2 *nbr,
                     const int *nbr_cnt, int cap, const int *row_of_atom, const float *dG, int ldg,
                     Live N, const AevConst &c, unsigned long long *Ffix, float *W_atom, const AevBwdGroups &gp,
@@ -1026,7 +993,7 @@ void launch_aev_bwd(const float4 *pos, const int *sys_of, const SysDesc *sys, co
   const size_t per = wave_lds_bytes<true>(cap);
   int form = 0;
   size_t table = 0;
-  if (wpb_pref != 1 && wpb_pref != 2) {
+  if (wpb_pref >= 4) {
     if (gp.groups && gp.n_groups > 0) {
       form = 1;
       table = ((size_t)gp.max_sys_atoms * 24 + 15) / 16 * 16;
@@ -1038,8 +1005,7 @@ void launch_aev_bwd(const float4 *pos, const int *sys_of, const SysDesc *sys, co
   if (form) {
     // kBwdStaticLds: the kernels' static LDS (the centre counter) comes on
     // top of the dynamic allocation
-    int wpb = (wpb_pref == 4 || wpb_pref == 5 || wpb_pref == 6 || wpb_pref == 8 || wpb_pref == 10) ? wpb_pref
-                                                                                                   : kBwdWaves;
+    int wpb = (wpb_pref == 4 || wpb_pref == 5 || wpb_pref == 6 || wpb_pref == 8 || wpb_pref == 10) ? wpb_pref : 8;
     auto fits = [&](int w) { return per * w + table + kBwdStaticLds <= max_lds; };
     while (wpb >= 4 && !fits(wpb)) wpb = wpb == 10 ? 8 : wpb == 8 ? 6 : wpb - 1;
     if (wpb >= 4) {
