@@ -238,7 +238,12 @@ void nnp_nlist_destroy(nnp_nlist *list);
  *            overlap (NNP_EINVAL otherwise).
  *   rebuild  HOST int32[n_systems] or NULL: nonzero forces a fresh list for
  *            that system (set it the first time a system uses its slots, or
- *            after its atoms were renumbered). */
+ *            after its atoms were renumbered).
+ * The pool records, per system (by its first slot), the box, the list
+ * cutoff (the model's cutoff + skin) and the atom count its rows were built
+ * for; a call that differs in any of them rebuilds that system's rows, so a
+ * pool can be shared by models of different cutoffs and by systems whose box
+ * changes.  Renumbered atoms are not detected: use rebuild. */
 int nnp_energy_forces_nlist(nnp_model *model, nnp_nlist *list, int n_systems,
                             const int64_t *batch_offsets, const int64_t *slots,
                             const int32_t *rebuild, const float *coords, const int32_t *species,

@@ -26,9 +26,9 @@
 //            centre's row, which stays in the L1/L2 caches), recomputes the
 //            angular cutoff of both legs, differentiates through cos, sin,
 //            R_j and R_k, and accumulates dE/dd_j and dE/dd_k per neighbour
-//            entry in LDS (64-bit fixed point, integer atomics).  Forces are
-//            then scattered with float atomics.
-// The backward keeps its LDS per wave near 8 KB (5 waves per SIMD at a
+//            entry in the wave's LDS (float64 atomics, in a fixed order).
+//            Forces then go to the accumulators in 64-bit fixed point.
+// The backward keeps its LDS per wave under 7 KB (5 waves per SIMD at a
 // neighbour capacity of 128): the kernel is latency-bound, so occupancy
 // matters more than avoiding recomputation.
 #include "internal.h"
@@ -77,7 +77,7 @@ struct WaveLds {
   float2 *rF2;     // fc(R) and fc'(R): radial cutoff, then (angular entries)
                    // the angular cutoff once the radial stage is done (backward)
   int *rJ;         // radial: neighbour index     (backward)
-  long long *rG;   // radial: dE/dd accumulators, fixed point (backward, 3 per entry)
+  double *rG;      // radial: dE/dd accumulators, float64 (backward, 3 per entry)
   int *aIdx;       // angular: position in the radial arrays  (backward)
   unsigned short *aIdx16;  // the same, 16-bit       (forward)
   float *aFc;      // angular: fc_ang(R)          (forward)
@@ -106,7 +106,7 @@ __device__ inline WaveLds carve(char *base, int cap) {
   w.ls = (Lists *)p; p += sizeof(Lists);
   if (BWD) {
     w.rD = (float4 *)p; p += (size_t)cap * 16;
-    w.rG = (long long *)p; p += (size_t)cap * 24;
+    w.rG = (double *)p; p += (size_t)cap * 24;
     w.rF2 = (float2 *)p; p += (size_t)cap * 8;
     w.rJ = (int *)p; p += (size_t)cap * 4;
     w.aIdx = (int *)p; p += (size_t)cap * 4;
@@ -631,8 +631,8 @@ __device__ inline void bwd_centre(int i, int lane, const float4 *__restrict__ po
       }
       const float dEdR = c.scale * (fc.y * A - 2.0f * c.eta_r * fc.x * B);
       const float q = dEdR * fast_rcp(d.w);
-      long long *gg = w.rG + 3 * e;
-      gg[0] = to_fix(q * d.x); gg[1] = to_fix(q * d.y); gg[2] = to_fix(q * d.z);
+      double *gg = w.rG + 3 * e;
+      gg[0] = (double)(q * d.x); gg[1] = (double)(q * d.y); gg[2] = (double)(q * d.z);
     }
   }
   wave_lds_sync();
@@ -772,14 +772,17 @@ __device__ inline void bwd_centre(int i, int lane, const float4 *__restrict__ po
         const float ck = (dRk - cs * invk) * invk;
         const float sjj = ak_ * dk.w * dk.w, sjk = -ak_ * dot;
         const float skk = ak_ * dj.w * dj.w, skj = -ak_ * dot;
-        unsigned long long *gj = (unsigned long long *)(w.rG + 3 * qj);
-        unsigned long long *gk = (unsigned long long *)(w.rG + 3 * qk);
-        atomicAdd(gj + 0, (unsigned long long)to_fix(aj_ * dk.x + sjj * dj.x + sjk * dk.x + cj * dj.x));
-        atomicAdd(gj + 1, (unsigned long long)to_fix(aj_ * dk.y + sjj * dj.y + sjk * dk.y + cj * dj.y));
-        atomicAdd(gj + 2, (unsigned long long)to_fix(aj_ * dk.z + sjj * dj.z + sjk * dk.z + cj * dj.z));
-        atomicAdd(gk + 0, (unsigned long long)to_fix(aj_ * dj.x + skk * dk.x + skj * dj.x + ck * dk.x));
-        atomicAdd(gk + 1, (unsigned long long)to_fix(aj_ * dj.y + skk * dk.y + skj * dj.y + ck * dk.y));
-        atomicAdd(gk + 2, (unsigned long long)to_fix(aj_ * dj.z + skk * dk.z + skj * dj.z + ck * dk.z));
+        // float64 LDS atomics: the wave's own region, so the adds to an
+        // entry happen in one fixed order (program order, then lane order
+        // within an instruction) and the sums are the same on every call
+        double *gj = w.rG + 3 * qj;
+        double *gk = w.rG + 3 * qk;
+        atomicAdd(gj + 0, (double)(aj_ * dk.x + sjj * dj.x + sjk * dk.x + cj * dj.x));
+        atomicAdd(gj + 1, (double)(aj_ * dk.y + sjj * dj.y + sjk * dk.y + cj * dj.y));
+        atomicAdd(gj + 2, (double)(aj_ * dk.z + sjj * dj.z + sjk * dk.z + cj * dj.z));
+        atomicAdd(gk + 0, (double)(aj_ * dj.x + skk * dk.x + skj * dj.x + ck * dk.x));
+        atomicAdd(gk + 1, (double)(aj_ * dj.y + skk * dk.y + skj * dj.y + ck * dk.y));
+        atomicAdd(gk + 2, (double)(aj_ * dj.z + skk * dk.z + skj * dj.z + ck * dk.z));
       }
     }
     wave_lds_sync();
@@ -793,9 +796,8 @@ __device__ inline void bwd_centre(int i, int lane, const float4 *__restrict__ po
     for (int q = 0; q < 9; ++q) vir[q] = 0.f;
     for (int e = lane; e < nR; e += kWave) {
       const float4 dv = w.rD[e];
-      const long long q0 = w.rG[3 * e], q1 = w.rG[3 * e + 1], q2 = w.rG[3 * e + 2];
-      const float gx = from_fix(q0), gy = from_fix(q1), gz = from_fix(q2);
-      sink.add(w.rJ[e], -q0, -q1, -q2);
+      const float gx = (float)w.rG[3 * e], gy = (float)w.rG[3 * e + 1], gz = (float)w.rG[3 * e + 2];
+      sink.add(w.rJ[e], -to_fix(gx), -to_fix(gy), -to_fix(gz));
       fi0 += gx; fi1 += gy; fi2 += gz;
       vir[0] -= dv.x * gx; vir[1] -= dv.x * gy; vir[2] -= dv.x * gz;
       vir[3] -= dv.y * gx; vir[4] -= dv.y * gy; vir[5] -= dv.y * gz;

@@ -10,6 +10,7 @@
 #include <initializer_list>
 #include <mutex>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "../../include/nnp.h"
@@ -169,6 +170,16 @@ struct nnp_nlist {
   int cap = 0;
   float skin = 0.f;
   DevBuf nbr, cnt, state, stats;
+  // what each system's rows were last built for, by its first slot: box
+  // lengths, list cutoff (model cutoff + skin) and atom count.  A call whose
+  // system differs in any of them (another model's cutoff, a changed box, a
+  // new system in the slots) rebuilds that system's rows.
+  struct Built {
+    float L[3];
+    float rc_list;
+    int n;
+  };
+  std::unordered_map<int64_t, Built> built;
 };
 
 static void round_bf16_host(const float *src, uint16_t *dst, size_t n) {
@@ -954,6 +965,10 @@ static int run(nnp_model *m, int n_sys, const int64_t *offs, const float *coords
   const float rc_list = m->rc_desc + (nl ? nl->skin : 0.f);
   const float rc_cell = rc_list * (1.0f + 1e-5f);
   std::vector<SysDesc> sd(n_sys);
+  std::vector<std::pair<int64_t, nnp_nlist::Built>> built_now;
+  auto record_builds = [&]() {
+    for (auto &bn : built_now) nl->built[bn.first] = bn.second;
+  };
   int64_t C = 0;
   std::vector<int> ch_sys, ch_begin, sys_ch(n_sys + 1);
   for (int s = 0; s < n_sys; ++s) {
@@ -988,6 +1003,12 @@ static int run(nnp_model *m, int n_sys, const int64_t *offs, const float *coords
       d.state_off = lp.slots[s];
       d.list_off = lp.slots[s] * (int64_t)cap;
       d.rebuild = lp.rebuild ? (lp.rebuild[s] != 0) : 0;
+      const auto it = nl->built.find(lp.slots[s]);
+      const nnp_nlist::Built now = {{b[0], b[1], b[2]}, rc_list, d.n};
+      if (it == nl->built.end() || memcmp(&it->second, &now, sizeof now) != 0) {
+        d.rebuild = 1;
+        built_now.push_back({lp.slots[s], now});  // recorded once the call is enqueued
+      }
     } else {
       d.state_off = offs[s];
       d.list_off = offs[s] * (int64_t)cap;
@@ -1415,9 +1436,10 @@ static int run(nnp_model *m, int n_sys, const int64_t *offs, const float *coords
     if (rc2) return rc2;
     if (gr && gr->post) gr->post(gr->ctx, st, N, n_sys, nullptr);
     HIP_TRY(hipGetLastError());
+    if (nl) record_builds();
     return NNP_OK;
   }
-  return replay(m, gr, st, N_l, S_l, C_l, groups_l, all_small, cap,
+  const int rc_replay = replay(m, gr, st, N_l, S_l, C_l, groups_l, all_small, cap,
                 {coords, species, o.energy, o.forces, o.virial, o.atom_energy, nl, (const void *)gr->pre,
                  (const void *)gr->post, gr->ctx, m->desc.p, nullptr},
                 [&](hipStream_t cs) -> int {
@@ -1427,6 +1449,8 @@ static int run(nnp_model *m, int n_sys, const int64_t *offs, const float *coords
                   if (gr->post) gr->post(gr->ctx, cs, N_l, S_l, live);
                   return NNP_OK;
                 });
+  if (rc_replay == NNP_OK) record_builds();
+  return rc_replay;
 }
 
 extern "C" int nnp_energy_forces(nnp_model *m, int n_systems, const int64_t *offs, const float *coords,

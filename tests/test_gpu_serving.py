@@ -77,6 +77,44 @@ def test_pool_lists_match_fresh_lists(m32, sigma, expect_rebuilds):
     m32.status()
 
 
+def test_pool_rows_follow_cutoff_box_and_size(m32):
+    """A pool records what each system's rows were built for (box, list
+    cutoff = model cutoff + skin, atom count): the same slots used by a model
+    of a larger cutoff, or with the box changed, or by a system of another
+    size, rebuild instead of reusing rows built for the old one.  Each result
+    matches a fresh list's at the pool tolerances."""
+    from paper_2207_14276_amd import NeighborPool, NNPModel
+    dp = NNPModel(synth.make_dp_model(0), "fp32")  # cutoff 6.0 A (the ANI model's: 5.1 A)
+    pool = NeighborPool(m32, slots=600, capacity=320, skin=0.5)
+
+    def check(model, system, rebuild, expect_build):
+        b = synth.make_batch([system])
+        c = torch.as_tensor(b.coords, device="cuda")
+        sp = torch.as_tensor(b.species, device="cuda")
+        before = pool.builds()
+        pool.model = model
+        r = pool.energy_forces(c, sp, b.boxes, b.offsets, [0], [rebuild])
+        ref = model.energy_forces(c, sp, b.boxes, b.offsets, check=True)
+        torch.cuda.synchronize()
+        de = float((r.energy - ref.energy).abs().max()) / system.n
+        df = float((r.forces - ref.forces).abs().max())
+        log(f"[pool record] n={system.n} box={system.box[0]:.2f} builds +{pool.builds() - before} "
+            f"|dE|/N={de:.2e} |dF|={df:.2e}")
+        assert pool.builds() == before + (1 if expect_build else 0)
+        assert de <= 1e-6 and df <= 1e-5
+
+    w = synth.water_box(60, seed=3)
+    check(m32, w, 1, True)                       # first use of the slots
+    check(m32, w, 0, False)                      # unchanged: the rows are reused
+    check(dp, w, 0, True)                        # larger cutoff: rebuilt
+    scaled = synth.System(w.coords * 1.04, w.species, w.box * 1.04)
+    check(dp, scaled, 0, True)                   # box changed: rebuilt
+    check(m32, synth.water_box(50, seed=4), 0, True)  # another system in the slots: rebuilt
+    pool.model = m32
+    pool.close()
+    dp.close()
+
+
 def test_pool_rejects_bad_slot_ranges(m32):
     from paper_2207_14276_amd import NeighborPool, NNPError
     b = _systems()
