@@ -82,15 +82,20 @@ __device__ inline void chain_gemm(const uint16_t *A, int lda, int K, const uint1
     for (int h = 0; h < HR; ++h) acc[q][h] = floatx4_t{0.f, 0.f, 0.f, 0.f};
   const uint16_t *bp = B + (size_t)(wave * 16 + l16) * ldb + 8 * kq;
   const size_t bstep = (size_t)16 * W * ldb;      // W blocks of 16 rows
-  uint4 bc[QM], bn[QM];
+  // B fragments of K steps kb (bc), kb + 1 (bn) and kb + 2 (bnn): the loads
+  // (L2 hits) are issued two steps ahead of their MFMAs
+  uint4 bc[QM], bn[QM], bnn[QM];
 #pragma unroll
   for (int q = 0; q < QM; ++q)
-    if (q < nq) bc[q] = *(const uint4 *)(bp + q * bstep);
+    if (q < nq) {
+      bc[q] = *(const uint4 *)(bp + q * bstep);
+      if (nkb > 1) bn[q] = *(const uint4 *)(bp + q * bstep + 32);
+    }
   for (int kb = 0; kb < nkb; ++kb) {
-    if (kb + 1 < nkb) {
+    if (kb + 2 < nkb) {
 #pragma unroll
       for (int q = 0; q < QM; ++q)
-        if (q < nq) bn[q] = *(const uint4 *)(bp + q * bstep + (kb + 1) * 32);
+        if (q < nq) bnn[q] = *(const uint4 *)(bp + q * bstep + (kb + 2) * 32);
     }
     bf16x8_t a[HR];
 #pragma unroll
@@ -105,7 +110,10 @@ __device__ inline void chain_gemm(const uint16_t *A, int lda, int K, const uint1
       }
     }
 #pragma unroll
-    for (int q = 0; q < QM; ++q) bc[q] = bn[q];
+    for (int q = 0; q < QM; ++q) {
+      bc[q] = bn[q];
+      bn[q] = bnn[q];
+    }
   }
 #pragma unroll
   for (int q = 0; q < QM; ++q)
