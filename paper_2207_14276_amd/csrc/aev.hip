@@ -72,7 +72,7 @@ struct WaveLds {
   float2 *tGeo;    // pair scratch: cos, sin                      (forward)
   float4 *tF2;     // pair scratch: radial Gaussians of Rbar times
                    // fc_j fc_k                                     (forward)
-  float4 *rD;      // radial: d vector and R (forward: d / R and R)
+  float4 *rD;      // radial: unit vector d / R and R
   float *rFc;      // radial: fc_rad(R)          (forward)
   float2 *rF2;     // fc(R) and fc'(R): radial cutoff, then (angular entries)
                    // the angular cutoff once the radial stage is done (backward)
@@ -125,17 +125,15 @@ __device__ inline WaveLds carve(char *base, int cap) {
 // angular pairs, in the upper-triangle order of (sa, sb) that is also the
 // feature order: its pair count T and the unrank fields of its two lists
 // (a pair is addressed as (x, y), x in the longer species list of length n1,
-// y in the shorter of length n2; a same-species block uses the one list
-// for both; the angular term is symmetric in its two neighbours):
-// oxy = offsets of the x and y lists (16 bits each), n12 = n1 | n2 << 16 |
-// same << 31, r1 = 1 / n1, r2 = 1 / n2 (hardware reciprocals: fdivmod
-// corrects the quotient).  Other lanes get T = 0.
-__device__ inline void block_words(int lane, const Lists &ls, int S, int &bT, int &bOxy, int &bN12, float &bR1,
-                                   float &bR2) {
+// y in the shorter of length n2; a same-species block uses the one list for
+// both; the angular term is symmetric in its two neighbours): oxy = offsets
+// of the x and y lists (16 bits each), ns = n1 | n2 << 16 | same << 31,
+// r2 = 1 / n2 (a hardware reciprocal: fdivmod corrects the quotient).
+// Other lanes get T = 0.
+__device__ inline void block_words(int lane, const Lists &ls, int S, int &bT, int &bOxy, int &bNs, float &bR2) {
   bT = 0;
   bOxy = 0;
-  bN12 = 0;
-  bR1 = 1.f;
+  bNs = 0;
   bR2 = 1.f;
   if (lane < S * (S + 1) / 2) {
     int sa = 0, rem = lane;
@@ -149,19 +147,27 @@ __device__ inline void block_words(int lane, const Lists &ls, int S, int &bT, in
     const bool a_long = na >= nb;
     const int n1 = max(na, nb), n2 = min(na, nb);
     bOxy = (a_long ? oa : ob) | ((a_long ? ob : oa) << 16);
-    bN12 = n1 | (n2 << 16) | (same ? (int)0x80000000u : 0);
-    bR1 = fast_rcp((float)max(n1, 1));
+    bNs = n1 | (n2 << 16) | (same ? (int)0x80000000u : 0);
     bR2 = fast_rcp((float)max(n2, 1));
   }
 }
 
-__device__ inline void unrank(int u, int n1, int n2, float r1, float r2, int same, int ox, int oy,
-                              int &ax, int &ay) {
-  int x, y;
-  const int q = fdivmod(u, n1, r1, x);
-  fdivmod(x + q + same, n2, r2, y);
-  ax = ox + x;
-  ay = oy + y;
+// List positions (ax, ay) of pair u of a block (ns and r2 as in
+// block_words), with u = q n2 + y.  Two species: x = (y + q) mod n1, q < n1.
+// One species of n entries (n1 = n2 = n): q < n / 2 and the pair is
+// {y, (y + q + 1) mod n}, q + 1 being its distance around the list, so that
+// every unordered pair comes once (for even n the last row q = n / 2 - 1
+// holds only y < n / 2).  Either way y + q (+ 1) < 2 n1, and neighbouring
+// lanes take different entries of both lists (their LDS adds to an entry's
+// accumulators do not pile up on one address).
+__device__ inline void unrank(int u, int ns, float r2, int oxy, int &ax, int &ay) {
+  const int n1 = ns & 0xffff, n2 = (ns >> 16) & 0x7fff;
+  int y;
+  const int q = fdivmod(u, n2, r2, y);
+  int x = y + q + (ns < 0 ? 1 : 0);
+  x = x >= n1 ? x - n1 : x;
+  ax = (oxy & 0xffff) + x;
+  ay = ((oxy >> 16) & 0xffff) + y;
 }
 // Builds the species-sorted radial list (R < rc_r) and angular list
 // (R < rc_a, a subset) of centre i in LDS.  Two passes over the entries:
@@ -246,17 +252,14 @@ __device__ inline void fill_lists(int lane, int n, const int2 *__restrict__ ent,
     if (inR) {
       float sn, cs;
       __sincosf(kr * d.w, &sn, &cs);
-      if (BWD) {
-        w.rD[q] = d;
-      } else {
-        // the forward's pair geometry needs only the direction
-        const float ir = fast_rcp(d.w);
-        w.rD[q] = make_float4(d.x * ir, d.y * ir, d.z * ir, d.w);
-        w.rFc[q] = 0.5f * cs + 0.5f;
-      }
+      // the pair geometry and the gradients need only the direction and R
+      const float ir = fast_rcp(d.w);
+      w.rD[q] = make_float4(d.x * ir, d.y * ir, d.z * ir, d.w);
       if (BWD) {
         w.rF2[q] = make_float2(0.5f * cs + 0.5f, -0.5f * kr * sn);
         w.rJ[q] = j;
+      } else {
+        w.rFc[q] = 0.5f * cs + 0.5f;
       }
     }
     if (inA) {
@@ -375,9 +378,9 @@ k_aev_fwd(const float4 *__restrict__ pos, const int *__restrict__ sys_of,
     const float keta = -c.eta_a * 1.4426950408889634f;
     // lane b: species-pair block b (block_words)
     const int n_blk = c.S * (c.S + 1) / 2;
-    int bT, bOxy, bN12;
-    float bR1, bR2;
-    block_words(lane, ls, c.S, bT, bOxy, bN12, bR1, bR2);
+    int bT, bOxy, bNs;
+    float bR2;
+    block_words(lane, ls, c.S, bT, bOxy, bNs, bR2);
     const unsigned long long nonempty = __ballot(bT > 0);
     // blocks without a pair of their two species are zero: written in one
     // pass of 16-byte stores over the angular part of the row
@@ -399,8 +402,7 @@ k_aev_fwd(const float4 *__restrict__ pos, const int *__restrict__ sys_of,
       const int Tq = __builtin_amdgcn_readlane(bT, q);
       // this lane's slot: block fields, pair index within the block, count
       int l_oxy = __builtin_amdgcn_readlane(bOxy, q);
-      int l_n12 = __builtin_amdgcn_readlane(bN12, q);
-      float l_r1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(bR1), q));
+      int l_ns = __builtin_amdgcn_readlane(bNs, q);
       float l_r2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(bR2), q));
       int l_u = u + lane, l_T = Tq;
       unsigned long long in_pass = 1ull << q;
@@ -416,8 +418,7 @@ k_aev_fwd(const float4 *__restrict__ pos, const int *__restrict__ sys_of,
           if (used + g2 > kPairPass) break;
           if (lane >= used) {
             l_oxy = __builtin_amdgcn_readlane(bOxy, q2);
-            l_n12 = __builtin_amdgcn_readlane(bN12, q2);
-            l_r1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(bR1), q2));
+            l_ns = __builtin_amdgcn_readlane(bNs, q2);
             l_r2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(bR2), q2));
             l_u = lane - used;
             l_T = T2;
@@ -433,8 +434,7 @@ k_aev_fwd(const float4 *__restrict__ pos, const int *__restrict__ sys_of,
         const bool valid = lane < used && l_u < l_T;
         const int tt = min(l_u, l_T - 1);
         int qj, qk;
-        unrank(tt, l_n12 & 0xffff, (l_n12 >> 16) & 0x7fff, l_r1, l_r2, (l_n12 >> 31) & 1,
-               l_oxy & 0xffff, (l_oxy >> 16) & 0xffff, qj, qk);
+        unrank(tt, l_ns, l_r2, l_oxy, qj, qk);
         const float4 dj = w.rD[w.aIdx16[qj]], dk = w.rD[w.aIdx16[qk]];  // unit vectors, R
         const float cosv = dj.x * dk.x + dj.y * dk.y + dj.z * dk.z;
         const float cx = dj.y * dk.z - dj.z * dk.y;
@@ -605,8 +605,9 @@ __device__ inline void bwd_centre(int i, int lane, const float4 *__restrict__ po
   for (int s = 0; s < c.S; ++s) nR += ls.cR[s];
   // radial, lane per neighbour entry: with t_m = R - Rs_m and
   // e_m = exp(-eta t_m^2), dE/dR = scale (fc' sum_m g_m e_m - 2 eta fc
-  // sum_m g_m e_m t_m), g being the dE/dG values of the entry's species.
-  // This stage is the first writer of the dE/dd accumulators.
+  // sum_m g_m e_m t_m), g being the dE/dG values of the entry's species;
+  // dE/dd = dE/dR d / R.  This stage is the first writer of the dE/dd
+  // accumulators.
   {
     const float keta = -c.eta_r * 1.4426950408889634f;
     for (int e = lane; e < nR; e += kWave) {
@@ -630,9 +631,8 @@ __device__ inline void bwd_centre(int i, int lane, const float4 *__restrict__ po
         }
       }
       const float dEdR = c.scale * (fc.y * A - 2.0f * c.eta_r * fc.x * B);
-      const float q = dEdR * fast_rcp(d.w);
       double *gg = w.rG + 3 * e;
-      gg[0] = (double)(q * d.x); gg[1] = (double)(q * d.y); gg[2] = (double)(q * d.z);
+      gg[0] = (double)(dEdR * d.x); gg[1] = (double)(dEdR * d.y); gg[2] = (double)(dEdR * d.z);
     }
   }
   wave_lds_sync();
@@ -659,9 +659,9 @@ __device__ inline void bwd_centre(int i, int lane, const float4 *__restrict__ po
     // lane b: species-pair block b, with the first pair of the block in the
     // stream (an exclusive prefix sum of the counts over the lanes)
     const int n_blk = c.S * (c.S + 1) / 2;
-    int bT, bOxy, bN12;
-    float bR1, bR2;
-    block_words(lane, ls, c.S, bT, bOxy, bN12, bR1, bR2);
+    int bT, bOxy, bNs;
+    float bR2;
+    block_words(lane, ls, c.S, bT, bOxy, bNs, bR2);
     int bStart = bT;
 #pragma unroll
     for (int d = 1; d < 32; d <<= 1) {  // n_blk <= 28: the first 32 lanes hold every block
@@ -690,24 +690,19 @@ __device__ inline void bwd_centre(int i, int lane, const float4 *__restrict__ po
       }
       const int pa = p << 2;
       const int l_oxy = __builtin_amdgcn_ds_bpermute(pa, bOxy);
-      const int l_n12 = __builtin_amdgcn_ds_bpermute(pa, bN12);
-      const float l_r1 = __int_as_float(__builtin_amdgcn_ds_bpermute(pa, __float_as_int(bR1)));
+      const int l_ns = __builtin_amdgcn_ds_bpermute(pa, bNs);
       const float l_r2 = __int_as_float(__builtin_amdgcn_ds_bpermute(pa, __float_as_int(bR2)));
       const int l_start = __builtin_amdgcn_ds_bpermute(pa, bStart);
       int aj, ak;
-      unrank(t - l_start, l_n12 & 0xffff, (l_n12 >> 16) & 0x7fff, l_r1, l_r2, (l_n12 >> 31) & 1,
-             l_oxy & 0xffff, (l_oxy >> 16) & 0xffff, aj, ak);
+      unrank(t - l_start, l_ns, l_r2, l_oxy, aj, ak);
       const int qj = w.aIdx[aj], qk = w.aIdx[ak];
-      const float4 dj = w.rD[qj], dk = w.rD[qk];
+      const float4 dj = w.rD[qj], dk = w.rD[qk];      // unit vectors u, v and R
       const float2 cj2 = w.rF2[qj], ck2 = w.rF2[qk];  // angular fc and fc'
-      const float dot = dj.x * dk.x + dj.y * dk.y + dj.z * dk.z;
+      const float cosv = dj.x * dk.x + dj.y * dk.y + dj.z * dk.z;
       const float cx = dj.y * dk.z - dj.z * dk.y;
       const float cy = dj.z * dk.x - dj.x * dk.z;
       const float cz = dj.x * dk.y - dj.y * dk.x;
-      const float cr = fast_sqrt(cx * cx + cy * cy + cz * cz);
-      const float invj = fast_rcp(dj.w), invk = fast_rcp(dk.w);
-      const float invRR = invj * invk;
-      const float cosv = dot * invRR, sinv = cr * invRR;
+      const float sinv = fast_sqrt(cx * cx + cy * cy + cz * cz);
       const float Rbar = 0.5f * (dj.w + dk.w);
       float f2[kNShfAng], ur[kNShfAng];
 #pragma unroll
@@ -763,26 +758,26 @@ __device__ inline void bwd_centre(int i, int lane, const float4 *__restrict__ po
         dbar *= 0.5f * m2eta * fcc;  // via Rbar, for each of R_j and R_k
         const float dRj = dbar + dfc * cj2.y * fk;
         const float dRk = dbar + dfc * fj * ck2.y;
-        const float inv_cr = cr > 1e-12f * dj.w * dk.w ? fast_rcp(cr) : 0.f;
-        const float aj_ = dcos * invRR, ak_ = dsin * inv_cr * invRR;
-        // d cos / d dj = dk / RR - cos dj / Rj^2 ; d sin / d dj =
-        // (Rk^2 dj - dot dk) / (|dj x dk| RR) - sin dj / Rj^2
-        const float cs = dcos * cosv + dsin * sinv;
-        const float cj = (dRj - cs * invj) * invj;
-        const float ck = (dRk - cs * invk) * invk;
-        const float sjj = ak_ * dk.w * dk.w, sjk = -ak_ * dot;
-        const float skk = ak_ * dj.w * dj.w, skj = -ak_ * dot;
+        // with c = cos, s = sin of the angle and u, v the unit vectors of
+        // the legs j, k: d c / d dj = (v - c u) / Rj and d s / d dj =
+        // -(c / s) (v - c u) / Rj (likewise for dk with u and v swapped),
+        // so dE/d dj = bj v + (dE/dRj - bj c) u with bj = (dE/dc -
+        // dE/ds c / s) / Rj.  Where s vanishes (collinear legs) the sine's
+        // term is dropped.
+        const float beta = dcos - (sinv > 1e-12f ? dsin * cosv * fast_rcp(sinv) : 0.f);
+        const float bj = beta * fast_rcp(dj.w), bk = beta * fast_rcp(dk.w);
+        const float uj = dRj - bj * cosv, uk = dRk - bk * cosv;
         // float64 LDS atomics: the wave's own region, so the adds to an
         // entry happen in one fixed order (program order, then lane order
         // within an instruction) and the sums are the same on every call
         double *gj = w.rG + 3 * qj;
         double *gk = w.rG + 3 * qk;
-        atomicAdd(gj + 0, (double)(aj_ * dk.x + sjj * dj.x + sjk * dk.x + cj * dj.x));
-        atomicAdd(gj + 1, (double)(aj_ * dk.y + sjj * dj.y + sjk * dk.y + cj * dj.y));
-        atomicAdd(gj + 2, (double)(aj_ * dk.z + sjj * dj.z + sjk * dk.z + cj * dj.z));
-        atomicAdd(gk + 0, (double)(aj_ * dj.x + skk * dk.x + skj * dj.x + ck * dk.x));
-        atomicAdd(gk + 1, (double)(aj_ * dj.y + skk * dk.y + skj * dj.y + ck * dk.y));
-        atomicAdd(gk + 2, (double)(aj_ * dj.z + skk * dk.z + skj * dj.z + ck * dk.z));
+        atomicAdd(gj + 0, (double)(bj * dk.x + uj * dj.x));
+        atomicAdd(gj + 1, (double)(bj * dk.y + uj * dj.y));
+        atomicAdd(gj + 2, (double)(bj * dk.z + uj * dj.z));
+        atomicAdd(gk + 0, (double)(bk * dj.x + uk * dk.x));
+        atomicAdd(gk + 1, (double)(bk * dj.y + uk * dk.y));
+        atomicAdd(gk + 2, (double)(bk * dj.z + uk * dk.z));
       }
     }
     wave_lds_sync();
@@ -795,7 +790,8 @@ __device__ inline void bwd_centre(int i, int lane, const float4 *__restrict__ po
     float vir[9];
     for (int q = 0; q < 9; ++q) vir[q] = 0.f;
     for (int e = lane; e < nR; e += kWave) {
-      const float4 dv = w.rD[e];
+      const float4 ur = w.rD[e];  // unit vector and R
+      const float4 dv = make_float4(ur.x * ur.w, ur.y * ur.w, ur.z * ur.w, ur.w);
       const float gx = (float)w.rG[3 * e], gy = (float)w.rG[3 * e + 1], gz = (float)w.rG[3 * e + 2];
       sink.add(w.rJ[e], -to_fix(gx), -to_fix(gy), -to_fix(gz));
       fi0 += gx; fi1 += gy; fi2 += gz;
