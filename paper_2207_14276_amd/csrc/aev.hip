@@ -28,9 +28,10 @@
 //            R_j and R_k, and accumulates dE/dd_j and dE/dd_k per neighbour
 //            entry in the wave's LDS (float64 atomics, in a fixed order).
 //            Forces then go to the accumulators in 64-bit fixed point.
-// The backward keeps its LDS per wave under 7 KB (5 waves per SIMD at a
-// neighbour capacity of 128): the kernel is latency-bound, so occupancy
-// matters more than avoiding recomputation.
+// The backward keeps its LDS per wave near 7 KB (5 waves per SIMD at a
+// neighbour capacity of 128) by recomputing the angular cutoffs and reading
+// dE/dG from cache; its VALU issue, not memory, sets its time, so every
+// instruction saved in the per-pair loop counts.
 #include "internal.h"
 #include "wave.h"
 
@@ -373,8 +374,9 @@ k_aev_fwd(const float4 *__restrict__ pos, const int *__restrict__ sys_of,
   //   2^(1-zeta) (1 + cos(theta - theta_a))^zeta exp(-eta (Rbar - Rs_r)^2) fc_j fc_k
   {
     const int a = lane >> 3, t0 = lane & 7;  // phase B: 8 angle shifts x 8 pairs (pair fastest)
-    const float cza = pick(c.cz, a), sza = pick(c.sz, a);
-    const float pre = 1.0f - c.zeta;
+    // y = (1 + cos(theta - theta_a)) / 2 in [0, 1] (clamped by its own FMA),
+    // so that 2^(1-zeta) (1 + cos)^zeta = 2 y^zeta = 2^(zeta log2 y + 1)
+    const float hcz = pick(c.hcz, a), hsz = pick(c.hsz, a);
     const float keta = -c.eta_a * 1.4426950408889634f;
     // lane b: species-pair block b (block_words)
     const int n_blk = c.S * (c.S + 1) / 2;
@@ -466,10 +468,10 @@ k_aev_fwd(const float4 *__restrict__ pos, const int *__restrict__ sys_of,
             const int q0 = 8 * g + t0, q1 = q0 + 8;
             const float2 geo0 = w.tGeo[q0], geo1 = w.tGeo[q1];
             const float4 f20 = w.tF2[q0], f21 = w.tF2[q1];
-            const float x0 = fmaxf(1.0f + geo0.x * cza + geo0.y * sza, 0.f);
-            const float x1 = fmaxf(1.0f + geo1.x * cza + geo1.y * sza, 0.f);
-            const float v0 = fast_exp2(c.zeta * fast_log2(x0) + pre);
-            const float v1 = fast_exp2(c.zeta * fast_log2(x1) + pre);
+            const float y0 = __builtin_amdgcn_fmed3f(fmaf(geo0.x, hcz, fmaf(geo0.y, hsz, 0.5f)), 0.f, 1.f);
+            const float y1 = __builtin_amdgcn_fmed3f(fmaf(geo1.x, hcz, fmaf(geo1.y, hsz, 0.5f)), 0.f, 1.f);
+            const float v0 = fast_exp2(c.zeta * fast_log2(y0) + 1.0f);
+            const float v1 = fast_exp2(c.zeta * fast_log2(y1) + 1.0f);
             acc0 += v0 * f20.x; acc0 += v1 * f21.x;
             acc1 += v0 * f20.y; acc1 += v1 * f21.y;
             acc2 += v0 * f20.z; acc2 += v1 * f21.z;
@@ -479,8 +481,8 @@ k_aev_fwd(const float4 *__restrict__ pos, const int *__restrict__ sys_of,
             const int q0 = 8 * g + t0;
             const float2 geo = w.tGeo[q0];
             const float4 f2 = w.tF2[q0];
-            const float x = fmaxf(1.0f + geo.x * cza + geo.y * sza, 0.f);
-            const float v = fast_exp2(c.zeta * fast_log2(x) + pre);
+            const float y = __builtin_amdgcn_fmed3f(fmaf(geo.x, hcz, fmaf(geo.y, hsz, 0.5f)), 0.f, 1.f);
+            const float v = fast_exp2(c.zeta * fast_log2(y) + 1.0f);
             acc0 += v * f2.x; acc1 += v * f2.y; acc2 += v * f2.z; acc3 += v * f2.w;
             ++g;
           }
@@ -670,7 +672,6 @@ __device__ inline void bwd_centre(int i, int lane, const float4 *__restrict__ po
     }
     const int P = __builtin_amdgcn_readlane(bStart, n_blk - 1);
     bStart -= bT;
-    const float pre = 1.0f - c.zeta;
     const float zm1 = c.zeta - 1.0f;
     const float keta = -c.eta_a * 1.4426950408889634f;
     const float m2eta = -2.0f * c.eta_a;
@@ -729,17 +730,18 @@ __device__ inline void bwd_centre(int i, int lane, const float4 *__restrict__ po
 #pragma unroll
         for (int aa = 0; aa < 4; ++aa) {
           const int a = 4 * h + aa;
-          const float x = fmaxf(1.0f + cosv * c.cz[a] + sinv * c.sz[a], 0.f);
-          const float p1 = fast_exp2(zm1 * fast_log2(x) + pre);
+          // y = x / 2 in [0, 1] (clamped by its own FMA); p1 = y^(zeta-1)
+          const float y = __builtin_amdgcn_fmed3f(fmaf(cosv, c.hcz[a], fmaf(sinv, c.hsz[a], 0.5f)), 0.f, 1.f);
+          const float p1 = fast_exp2(zm1 * fast_log2(y));
           float A = gq[0][aa] * f2[0];
 #pragma unroll
           for (int r = 1; r < kNShfAng; ++r) A += gq[r][aa] * f2[r];
           const float s1 = p1 * A;
-          dcos += s1 * c.cz[a];
-          dsin += s1 * c.sz[a];
-          const float f1 = p1 * x;
+          dcos += s1 * c.hcz[a];  // half of dE/dcos: doubled below
+          dsin += s1 * c.hsz[a];
+          const float f1h = p1 * y;  // f1 / 2: H holds half its value
 #pragma unroll
-          for (int r = 0; r < kNShfAng; ++r) H[r] += gq[r][aa] * f1;
+          for (int r = 0; r < kNShfAng; ++r) H[r] += gq[r][aa] * f1h;
         }
       }
       if (valid) {
@@ -752,10 +754,11 @@ __device__ inline void bwd_centre(int i, int lane, const float4 *__restrict__ po
         }
         const float fj = cj2.x, fk = ck2.x;
         const float fcc = fj * fk;
-        const float zf = c.zeta * fcc;
+        const float zf = 2.0f * c.zeta * fcc;  // the halved cos / sin constants
         dcos *= zf;
         dsin *= zf;
-        dbar *= 0.5f * m2eta * fcc;  // via Rbar, for each of R_j and R_k
+        dbar *= m2eta * fcc;  // via Rbar (dRbar/dR = 1/2, H halved), for each of R_j and R_k
+        dfc += dfc;           // H halved
         const float dRj = dbar + dfc * cj2.y * fk;
         const float dRk = dbar + dfc * fj * ck2.y;
         // with c = cos, s = sin of the angle and u, v the unit vectors of
@@ -846,7 +849,7 @@ __device__ inline int next_centre(int *counter, int lane) {
 // count}); the system's forces are summed in an LDS table and added into
 // Ffix once.
 template <int WPB>
-__global__ void __launch_bounds__(WPB * kWave) __attribute__((amdgpu_waves_per_eu(5)))
+__global__ void __launch_bounds__(WPB * kWave)
 k_aev_bwd_sys(const int2 *__restrict__ groups, const float4 *__restrict__ pos, const int *__restrict__ sys_of,
               const SysDesc *__restrict__ sys, const int2 *__restrict__ nbr,
               const int *__restrict__ nbr_cnt, int cap, const int *__restrict__ row_of_atom,
@@ -878,7 +881,7 @@ k_aev_bwd_sys(const int2 *__restrict__ groups, const float4 *__restrict__ pos, c
 // they share most of their neighbours, whose forces are summed in an LDS hash
 // table and added into Ffix once per cell.
 template <int WPB>
-__global__ void __launch_bounds__(WPB * kWave) __attribute__((amdgpu_waves_per_eu(5)))
+__global__ void __launch_bounds__(WPB * kWave)
 k_aev_bwd_cells(const int *__restrict__ cell_start, const int *__restrict__ cell_atoms,
                 const float4 *__restrict__ pos, const int *__restrict__ sys_of,
                 const SysDesc *__restrict__ sys, const int2 *__restrict__ nbr,

@@ -256,8 +256,8 @@ static int create_impl(const nnp_model_desc *dd, nnp_model *m) {
   for (int k = 0; k < kNShfRad; ++k) c.shf_r[k] = a.shf_rad[k];
   for (int k = 0; k < kNShfAng; ++k) c.shf_a[k] = a.shf_ang[k];
   for (int k = 0; k < kNShfZ; ++k) {
-    c.cz[k] = (float)std::cos((double)a.shf_z[k]);
-    c.sz[k] = (float)std::sin((double)a.shf_z[k]);
+    c.hcz[k] = (float)(0.5 * std::cos((double)a.shf_z[k]));
+    c.hsz[k] = (float)(0.5 * std::sin((double)a.shf_z[k]));
   }
   c.S = S;
   c.rad_len = S * kNShfRad;

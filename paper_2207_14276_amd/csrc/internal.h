@@ -128,7 +128,7 @@ struct AevConst {
   float rc_r, eta_r, rc_a, eta_a, zeta, scale;
   float shf_r[kNShfRad];
   float shf_a[kNShfAng];
-  float cz[kNShfZ], sz[kNShfZ];  // cos / sin of the angle shifts
+  float hcz[kNShfZ], hsz[kNShfZ];  // halved cos / sin of the angle shifts
   int S;        // species
   int D;        // AEV length
   int rad_len;  // S * 16
