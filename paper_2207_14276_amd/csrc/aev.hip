@@ -675,16 +675,23 @@ __device__ inline void bwd_centre(int i, int lane, const float4 *__restrict__ po
     const float zm1 = c.zeta - 1.0f;
     const float keta = -c.eta_a * 1.4426950408889634f;
     const float m2eta = -2.0f * c.eta_a;
-    int qb = 0;  // the block holding the pass's first pair (wave-uniform)
+    // the non-empty block holding the pass's first pair (wave-uniform);
+    // the block searches visit non-empty blocks only
+    const unsigned long long nonempty = __ballot(bT > 0);
+    int qb = nonempty ? __builtin_ctzll(nonempty) : 0;
     for (int base = 0; base < P; base += kPairPass) {
-      while (qb + 1 < n_blk && __builtin_amdgcn_readlane(bStart, qb + 1) <= base) ++qb;
+      for (unsigned long long m = nonempty & (~0ull << (qb + 1)); m; m &= m - 1) {
+        const int r = __builtin_ctzll(m);
+        if (__builtin_amdgcn_readlane(bStart, r) > base) break;
+        qb = r;
+      }
       const bool valid = base + lane < P;
       const int t = min(base + lane, P - 1);
-      // this lane's block: the last one starting at or before its pair
-      // (an empty block starts where the next one does and is passed over);
-      // the pass's blocks are few, their starts wave-uniform
+      // this lane's block: the last non-empty one starting at or before its
+      // pair; the pass's blocks are few, their starts wave-uniform
       int p = qb;
-      for (int r = qb + 1; r < n_blk; ++r) {
+      for (unsigned long long m = nonempty & (~0ull << (qb + 1)); m; m &= m - 1) {
+        const int r = __builtin_ctzll(m);
         const int sr = __builtin_amdgcn_readlane(bStart, r);
         if (sr >= base + kPairPass) break;
         p = t >= sr ? r : p;
