@@ -170,34 +170,63 @@ __device__ inline void unrank(int u, int ns, float r2, int oxy, int &ax, int &ay
   ax = (oxy & 0xffff) + x;
   ay = ((oxy >> 16) & 0xffff) + y;
 }
+// One neighbour entry of a centre: the atom (index within the system's
+// records at j0), its species and the vector d (R in w); false for an entry
+// past the row or whose stored atom index is not below n_sys (a reused list
+// applied to a different system), which is never dereferenced.
+__device__ __attribute__((always_inline)) inline bool load_entry(int e, int n, const int2 *__restrict__ ent, int j0, int n_sys,
+                                  const float4 *__restrict__ pos, const float4 &pi, const float L[3],
+                                  int &sj, int &j, float4 &d) {
+  int2 en = make_int2(0, 0);
+  if (e < n) en = ent[e];
+  const bool v = e < n && (unsigned)en.x < (unsigned)n_sys;
+  sj = -1;
+  j = 0;
+  d = make_float4(0.f, 0.f, 0.f, 1e30f);
+  if (v) {
+    j = j0 + en.x;
+    const float4 pj = pos[j];
+    d = entry_vec(pi, pj, en.y, L);
+    sj = __float_as_int(pj.w);
+  }
+  return v;
+}
+
 // Builds the species-sorted radial list (R < rc_r) and angular list
 // (R < rc_a, a subset) of centre i in LDS.  Two passes over the entries:
-// per-species counts by ballot, then placement.
-// Entries whose stored atom index is not below n_sys (a reused list applied
-// to a different system) are skipped, never dereferenced.  Per-species tallies
-// live in registers (loops over the species slots are fully unrolled) and the
-// wave-uniform result is published in LDS.
+// per-species counts by ballot, then placement.  Rows of up to 128 entries
+// (the common case) are loaded once and kept in registers for both passes;
+// longer rows are loaded again.  Per-species tallies live in registers
+// (loops over the species slots are fully unrolled; species without an
+// entry in a chunk are skipped) and the wave-uniform result is published
+// in LDS.
 template <bool BWD>
 __device__ inline void fill_lists(int lane, int n, const int2 *__restrict__ ent, int j0, int n_sys,
                                   const float4 *__restrict__ pos, const float4 &pi,
                                   const float L[3], const AevConst &c, WaveLds &w) {
   const int S = c.S;
+  const bool cached = n <= 2 * kWave;  // wave-uniform
+  int sj0 = -1, sj1 = -1, jj0 = 0, jj1 = 0;
+  float4 d0 = make_float4(0.f, 0.f, 0.f, 1e30f), d1 = d0;
+  if (cached) {
+    load_entry(lane, n, ent, j0, n_sys, pos, pi, L, sj0, jj0, d0);
+    if (n > kWave) load_entry(kWave + lane, n, ent, j0, n_sys, pos, pi, L, sj1, jj1, d1);
+  }
   int cR[kMaxSpecies], cA[kMaxSpecies];
 #pragma unroll
   for (int s = 0; s < kMaxSpecies; ++s) { cR[s] = 0; cA[s] = 0; }
   for (int b = 0; b < n; b += kWave) {
-    int e = b + lane;
-    int2 en = make_int2(0, 0);
-    if (e < n) en = ent[e];
-    bool v = e < n && (unsigned)en.x < (unsigned)n_sys;
-    int sj = -1;
-    float R = 1e30f;
-    if (v) {
-      float4 pj = pos[j0 + en.x];
-      R = entry_vec(pi, pj, en.y, L).w;
-      sj = __float_as_int(pj.w);
+    int sj, j;
+    float4 d;
+    if (cached) {  // the entry of this lane in the chunk starting at b
+      const bool first = b == 0;
+      sj = first ? sj0 : sj1;
+      j = first ? jj0 : jj1;
+      d = first ? d0 : d1;
+    } else {
+      load_entry(b + lane, n, ent, j0, n_sys, pos, pi, L, sj, j, d);
     }
-    bool inR = v && R < c.rc_r, inA = v && R < c.rc_a;
+    const bool inR = sj >= 0 && d.w < c.rc_r, inA = sj >= 0 && d.w < c.rc_a;
 #pragma unroll
     for (int s = 0; s < kMaxSpecies; ++s) {
       cR[s] += __popcll(__ballot(inR && sj == s));
@@ -223,26 +252,25 @@ __device__ inline void fill_lists(int lane, int n, const int2 *__restrict__ ent,
   const float kr = kPi / c.rc_r, ka = kPi / c.rc_a;
   (void)ka;
   for (int b = 0; b < n; b += kWave) {
-    int e = b + lane;
-    int2 en = make_int2(0, 0);
-    if (e < n) en = ent[e];
-    bool v = e < n && (unsigned)en.x < (unsigned)n_sys;
-    int sj = -1, j = 0;
-    float4 d = make_float4(0.f, 0.f, 0.f, 1e30f);
-    if (v) {
-      j = j0 + en.x;
-      float4 pj = pos[j];
-      d = entry_vec(pi, pj, en.y, L);
-      sj = __float_as_int(pj.w);
+    int sj, j;
+    float4 d;
+    if (cached) {  // the entry of this lane in the chunk starting at b
+      const bool first = b == 0;
+      sj = first ? sj0 : sj1;
+      j = first ? jj0 : jj1;
+      d = first ? d0 : d1;
+    } else {
+      load_entry(b + lane, n, ent, j0, n_sys, pos, pi, L, sj, j, d);
     }
-    bool inR = v && d.w < c.rc_r, inA = v && d.w < c.rc_a;
+    const bool inR = sj >= 0 && d.w < c.rc_r, inA = sj >= 0 && d.w < c.rc_a;
     // slots of this lane's entry in the two lists (selects per species;
     // the stores below are then issued once, not once per species)
     int q = 0, qa = 0;
 #pragma unroll
     for (int s = 0; s < kMaxSpecies; ++s) {
-      unsigned long long mR = __ballot(inR && sj == s);
-      unsigned long long mA = __ballot(inA && sj == s);
+      const unsigned long long mR = __ballot(inR && sj == s);
+      if (!mR) continue;  // (the angular list is a subset of the radial one)
+      const unsigned long long mA = __ballot(inA && sj == s);
       if (sj == s) {
         q = pR[s] + (int)lanes_below(mR);
         qa = pA[s] + (int)lanes_below(mA);
@@ -798,6 +826,7 @@ __device__ inline void bwd_centre(int i, int lane, const float4 *__restrict__ po
   {
     float fi0 = 0.f, fi1 = 0.f, fi2 = 0.f;
     float vir[9];
+#pragma unroll
     for (int q = 0; q < 9; ++q) vir[q] = 0.f;
     for (int e = lane; e < nR; e += kWave) {
       const float4 ur = w.rD[e];  // unit vector and R
@@ -812,10 +841,12 @@ __device__ inline void bwd_centre(int i, int lane, const float4 *__restrict__ po
     fi0 = wave_sum(fi0);
     fi1 = wave_sum(fi1);
     fi2 = wave_sum(fi2);
+#pragma unroll
     for (int q = 0; q < 9; ++q) vir[q] = wave_sum(vir[q]);
     if (lane == 0) sink.add(i, to_fix(fi0), to_fix(fi1), to_fix(fi2));
     if (lane < 9) {
       float v = vir[0];
+#pragma unroll
       for (int q = 1; q < 9; ++q) v = lane == q ? vir[q] : v;
       W_atom[(size_t)9 * i + lane] = v;
     }

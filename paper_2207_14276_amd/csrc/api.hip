@@ -1550,14 +1550,22 @@ extern "C" int nnp_autotune(nnp_model *m, int n_systems, const int64_t *offs, co
   const int kBwd[kRounds] = {1, 5, 4, 8};
   // chain: 8 or 4 waves on 32 rows, 8 waves on 64 rows (+10) when the LDS allows
   const int kChainW[kRounds] = {8, 4, m->chain_rt2 ? 18 : 8, 8};
-  double t[kTuneSites][kRounds] = {};
+  // Every candidate runs once untimed, then the rounds take turns kReps
+  // times (so that clock and cache warm-up do not favour a late round), and
+  // each candidate keeps its fastest time.
+  double t[kTuneSites][kRounds];
+  for (auto &row : t)
+    for (double &x : row) x = 1e30;
   bool hit[kTuneSites] = {};
   int rc = NNP_OK;
-  for (int r = 0; r < kRounds && rc == NNP_OK; ++r) {
-    for (int q = 0; q < kTuneSites; ++q)
-      m->tune_val[q] = q == kSiteAevBwd ? kBwd[r] : q < kSiteGemmFwd ? kWpb[r] : q == kSiteChain ? kChainW[r] : kTn[r];
-    rc = run(m, n_systems, offs, coords, species, box, o, st, kFull);  // warm-up
-    for (int k = 0; k < kReps && rc == NNP_OK; ++k) {
+  for (int k = -1; k < kReps && rc == NNP_OK; ++k) {
+    for (int r = 0; r < kRounds && rc == NNP_OK; ++r) {
+      for (int q = 0; q < kTuneSites; ++q)
+        m->tune_val[q] = q == kSiteAevBwd ? kBwd[r] : q < kSiteGemmFwd ? kWpb[r] : q == kSiteChain ? kChainW[r] : kTn[r];
+      if (k < 0) {  // warm-up
+        rc = run(m, n_systems, offs, coords, species, box, o, st, kFull);
+        continue;
+      }
       m->tuning = true;
       for (bool &h : m->tune_hit) h = false;
       rc = run(m, n_systems, offs, coords, species, box, o, st, kFull);
@@ -1567,12 +1575,13 @@ extern "C" int nnp_autotune(nnp_model *m, int n_systems, const int64_t *offs, co
       for (int q = 0; q < kTuneSites; ++q)
         if (m->tune_hit[q]) {
           float ms = 0.f;
-          if (hipEventElapsedTime(&ms, m->tune_ev[q][0], m->tune_ev[q][1]) == hipSuccess) t[q][r] += ms;
+          if (hipEventElapsedTime(&ms, m->tune_ev[q][0], m->tune_ev[q][1]) == hipSuccess) t[q][r] = std::min(t[q][r], (double)ms);
           hit[q] = true;
         }
     }
   }
-  // the fastest candidate of each site that ran (GEMM widths: best of the two 64 rounds)
+  // the fastest candidate of each site that ran (a value tried in two rounds
+  // keeps the faster of them)
   for (int q = 0; q < kTuneSites; ++q) {
     m->tune_val[q] = 0;
     if (!hit[q] || rc) continue;
