@@ -458,8 +458,12 @@ int nnp_sched_info(nnp_sched *sched, int64_t *info);
  * forces computed into the call's own scratch) once per candidate round and
  * keeps, for every tunable launch ("site"), the fastest candidate measured
  * with HIP events on `stream`:
- *   site 0, 1        AEV forward / backward: waves per workgroup 1, 2 or 4
- *                    (candidates whose LDS does not fit are skipped);
+ *   site 0           AEV forward: waves per workgroup 1, 2 or 4 (candidates
+ *                    whose LDS does not fit are skipped);
+ *   site 1           AEV backward: 1 wave per centre (forces by device
+ *                    atomics), or 4, 5 or 8 waves per workgroup summing the
+ *                    forces of a system (batches of small non-periodic
+ *                    systems) or of a cell (cell grids) in LDS first;
  *   site 2 + l       dense layer l forward GEMM: column-tile width 64, 128
  *                    or 256 (256: for a layer whose members share the input,
  *                    the members' columns side by side in one tile space);

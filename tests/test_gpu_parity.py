@@ -418,7 +418,8 @@ def test_autotune_changes_no_result(oracle_lib):
         tuned = m.autotune(c, sp, bx, o)
         log(f"[autotune {prec}] {tuned}")
         assert tuned, "no site was tuned"
-        allowed = lambda k: (1, 2, 4) if k.startswith("aev") else (4, 8, 18) if k == "chain_waves" else (64, 128, 256)
+        allowed = lambda k: ((1, 2, 4) if k == "aev_fwd_waves" else (1, 2, 4, 5, 8) if k == "aev_bwd_waves"
+                             else (4, 8, 18) if k == "chain_waves" else (64, 128, 256))
         for k, v in tuned.items():
             assert v in allowed(k), (k, v)
         r1 = m.energy_forces(c, sp, bx, o, check=True)
