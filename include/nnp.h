@@ -455,9 +455,10 @@ int nnp_sched_info(nnp_sched *sched, int64_t *info);
 /* Tile-shape tuning for a representative batch (section "Massive Parallelism
  * within Tinker-HP" reports the kernel time split that makes these choices
  * matter).  Runs the batch (inputs as for nnp_energy_forces, energies and
- * forces computed into the call's own scratch) once per candidate round and
- * keeps, for every tunable launch ("site"), the fastest candidate measured
- * with HIP events on `stream`:
+ * forces computed into the call's own scratch) with each candidate round's
+ * shapes, the rounds taking turns six times (the first untimed), and keeps,
+ * for every tunable launch ("site"), the candidate with the fastest of its
+ * times measured with HIP events on `stream`:
  *   site 0           AEV forward: waves per workgroup 1, 2 or 4 (candidates
  *                    whose LDS does not fit are skipped);
  *   site 1           AEV backward: 1 wave per centre (forces by device

@@ -1545,7 +1545,7 @@ extern "C" int nnp_autotune(nnp_model *m, int n_systems, const int64_t *offs, co
   // kWpb[r] waves per workgroup, the AEV backward to kBwd[r] (1: a wave per
   // centre with device atomics; 5, 4, 8: a grouped form with that many
   // waves) and the fused chain to kChainW[r] waves per workgroup
-  constexpr int kRounds = 4, kReps = 3;
+  constexpr int kRounds = 4, kReps = 5;
   const int kTn[kRounds] = {64, 128, 256, 128}, kWpb[kRounds] = {1, 2, 4, 2};
   const int kBwd[kRounds] = {1, 5, 4, 8};
   // chain: 8 or 4 waves on 32 rows, 8 waves on 64 rows (+10) when the LDS allows
