@@ -86,11 +86,11 @@ struct WaveLds {
 
 // Per-wave LDS bytes (a multiple of 16).  Forward entry: rD 16, rFc 4,
 // aIdx16 2 (the array padded to 16 bytes), aFc 4: 4,992 bytes per wave at a
-// capacity of 128, so that 8 waves per SIMD fit.  Backward entry: rD 16, rG 24, rF2 8, rJ 4, aIdx 4; the
-// backward reads the centre's dE/dG row from global memory (it stays in the
-// L1/L2 caches) and keeps the angular cutoff in the radial cutoff's slots,
-// which keeps its LDS per wave near 8 KB (5 waves per SIMD at a capacity of
-// 128).
+// capacity of 128, so that 8 waves per SIMD fit.  Backward entry: rD 16,
+// rG 24, rF2 8, rJ 4, aIdx 4; the backward reads the centre's dE/dG row from
+// global memory (it stays in the L1/L2 caches) and keeps the angular cutoff
+// in the radial cutoff's slots: 7,296 bytes per wave at a capacity of 128
+// (5 waves per SIMD).
 __host__ __device__ inline size_t aidx16_bytes(int cap) { return ((size_t)cap * 2 + 15) / 16 * 16; }
 
 template <bool BWD>
