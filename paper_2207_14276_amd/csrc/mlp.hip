@@ -434,6 +434,21 @@ k_gemm_dl(GemmLaunch gl) {
   // moves 8 consecutive elements (16-byte bfloat16 rows, 2 x 16-byte float32
   // rows).  Output widths are multiples of 8: an 8-column chunk is either
   // wholly inside n_out or wholly outside.
+  if constexpr (EPI == kEpiOut) {
+    // float32 output: straight from the accumulators, whose layout already
+    // gives each half-wave 32 consecutive columns (128 bytes) of one row
+#pragma unroll
+    for (int bi = 0; bi < BM; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < BN; ++bj) {
+        const int col = c0 + wc * WN + bj * 32 + l32;
+        if (col >= n_cols) continue;
+        float *out = (float *)gl.C + (size_t)(r0 + wr * WM + bi * 32 + 4 * hi) * gl.ldc + col;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) out[(size_t)(8 * (i / 4) + (i % 4)) * gl.ldc] = acc[bi][bj][i] * gl.scale;
+      }
+    return;
+  }
   constexpr int EP_LD = 36;                     // floats per LDS row (16-byte aligned)
   __syncthreads();                              // every wave is done with the operand tiles
   float *ep = (float *)smem + wave * 32 * EP_LD;
