@@ -170,13 +170,15 @@ __device__ inline void unrank(int u, int ns, float r2, int oxy, int &ax, int &ay
   ax = (oxy & 0xffff) + x;
   ay = ((oxy >> 16) & 0xffff) + y;
 }
+
 // One neighbour entry of a centre: the atom (index within the system's
 // records at j0), its species and the vector d (R in w); false for an entry
 // past the row or whose stored atom index is not below n_sys (a reused list
 // applied to a different system), which is never dereferenced.
-__device__ __attribute__((always_inline)) inline bool load_entry(int e, int n, const int2 *__restrict__ ent, int j0, int n_sys,
-                                  const float4 *__restrict__ pos, const float4 &pi, const float L[3],
-                                  int &sj, int &j, float4 &d) {
+__device__ __attribute__((always_inline)) inline bool load_entry(int e, int n, const int2 *__restrict__ ent,
+                                                                 int j0, int n_sys, const float4 *__restrict__ pos,
+                                                                 const float4 &pi, const float L[3], int &sj, int &j,
+                                                                 float4 &d) {
   int2 en = make_int2(0, 0);
   if (e < n) en = ent[e];
   const bool v = e < n && (unsigned)en.x < (unsigned)n_sys;
