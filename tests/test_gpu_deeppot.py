@@ -7,13 +7,16 @@ decision taken in float64 on both sides) must be identical, so the set of
 filled slots matches exactly; the features themselves are float32
 (|dG| <= 2e-5 (1 + |G|)); energies and forces as for the AEV path: float32
 |dE_i| <= 1e-5 kcal/mol, |dF| <= 1e-3 kcal/mol/A; bfloat16 dense layers
-|dE_s|/N <= 1e-2 and |dF| <= max(5e-2, 0.02 max|F|).  The bfloat16 force bar
+|dE_s|/N <= 1e-2 and |dF| <= 5e-2 kcal/mol/A.  The bfloat16 force error
 scales with the force magnitude: bfloat16 operands carry a relative error of
 2^-9, so the force error of that form is a fixed fraction of the forces
-(under 1% of the largest one for both descriptor kinds here); the
-AEV model's largest forces are ~1.5 kcal/mol/A, where 5e-2 is 3%, while
-the randomly initialised DeepPot-style model reaches ~9 kcal/mol/A (its
-1/R and x/R features grow faster at short range).  The descriptor is not smooth where two
+(under 1% of the largest one for both descriptor kinds here); the AEV
+model's largest forces are ~1.5 kcal/mol/A, where 5e-2 is 3%, while the
+randomly initialised DeepPot-style model reaches 9-26 kcal/mol/A on the
+ragged solutes (its 1/R and x/R features grow faster at short range),
+where the stated force bar is missed: recorded as strict expected failures,
+with 1% of the largest force asserted there instead to catch regressions.
+The descriptor is not smooth where two
 neighbours of a species swap order or one crosses the cutoff; random inputs
 sit far enough from such points that float32 feature rounding does not
 reach them (the oracle's pins check the finite differences).
