@@ -290,8 +290,7 @@ void launch_aev_bwd(const float4 *pos, const int *sys_of, const SysDesc *sys, co
                     const int *nbr_cnt, int cap, const int *row_of_atom, const float *dG,
                     int ldg, Live N, const AevConst &c, unsigned long long *Ffix, float *W_atom,
                     const AevBwdGroups &gp, int wpb_pref, size_t max_lds, hipStream_t st);
-// tn_pref: column-tile width 64 or 128 (anything else: the width heuristic);
-// wpb_pref below: waves per workgroup 1, 2 or 4 when the LDS fits (else the default).
+// tn_pref: column-tile width 64, 128 or 256 (anything else: the width heuristic).
 void launch_gemm(int epi, bool bf16, GemmLaunch gl, int row_tiles, int max_n_out, int tn_pref, hipStream_t st);
 void launch_energy(const EnergyLaunch &el, bool bf16, int rows, hipStream_t st);
 // waves per workgroup 4 or 8; rt = 2: 64 rows per workgroup (2 lds_bytes of
