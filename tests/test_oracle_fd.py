@@ -135,3 +135,34 @@ def test_sampled_equals_whole_system(oracle_lib):
         e, f = oracle_lib.sampled(s.coords, s.species, s.box, om, t)
         np.testing.assert_allclose(e, ea[t], rtol=1e-13, atol=1e-15)
         np.testing.assert_allclose(f, F[t], rtol=1e-11, atol=1e-13)
+
+
+def test_collinear_triplet_force_is_the_central_difference(oracle_lib):
+    """At an exactly collinear triplet the sine of the angle, |d_j x d_k| /
+    (R_j R_k), has a kink, and the oracle takes its derivative as zero there
+    (the reading of the gradient at collinear triplets).  That is exactly the
+    central difference of the energy: the one-sided slopes of |sin| across
+    the line are opposite and cancel.  The case is not trivial: the one-sided
+    slopes across the line differ."""
+    om = oracle_lib.OracleModel(synth.make_model(0))
+    # C at the origin between an H and an O on the x axis: theta = pi
+    x = np.array([[0.0, 0.0, 0.0], [1.25, 0.0, 0.0], [-1.125, 0.0, 0.0]])
+    sp = np.array([1, 0, 3], np.int32)
+    box = np.zeros(3, np.float32)
+    E0, _, F, _ = oracle_lib.energy_forces(x.astype(np.float32), sp, box, om)
+    h = 1e-5
+    for i in range(3):
+        for a in range(3):
+            e = []
+            for sgn in (+1, -1):
+                y = x.copy()
+                y[i, a] += sgn * h
+                e.append(_energy64(oracle_lib, om, y, sp, box)[0])
+            assert F[i, a] == pytest.approx(-(e[0] - e[1]) / (2 * h), abs=1e-7), (i, a)
+    # across the line (the centre moved along y) the one-sided slopes differ
+    up, down = x.copy(), x.copy()
+    up[0, 1] += h
+    down[0, 1] -= h
+    s_up = (_energy64(oracle_lib, om, up, sp, box)[0] - E0) / h
+    s_down = (E0 - _energy64(oracle_lib, om, down, sp, box)[0]) / h
+    assert abs(s_up - s_down) > 1e-4
