@@ -343,12 +343,27 @@ template <> __device__ inline void store1<true>(void *row, int k, float v) {
 }
 template <> __device__ inline void store1<false>(void *row, int k, float v) { ((float *)row)[k] = v; }
 
+// Bit p of x (p < 32) to bits 2 p and 2 p + 1.
+__device__ inline unsigned long long spread_pairs(unsigned long long x) {
+  x &= 0xffffffffull;
+  x = (x | (x << 16)) & 0x0000ffff0000ffffull;
+  x = (x | (x << 8)) & 0x00ff00ff00ff00ffull;
+  x = (x | (x << 4)) & 0x0f0f0f0f0f0f0f0full;
+  x = (x | (x << 2)) & 0x3333333333333333ull;
+  x = (x | (x << 1)) & 0x5555555555555555ull;
+  return x | (x << 1);
+}
+// The row mask's halves: a radial block is one 16-column half, an angular
+// block two, and all of them fit in 64 bits.
+static_assert(kNShfRad == 16 && kAngBlock == 32, "row mask halves");
+static_assert(kMaxSpecies + kMaxSpecies * (kMaxSpecies + 1) <= 64, "row mask width");
+
 template <int WPB, bool BF16>
 __global__ void __launch_bounds__(WPB * kWave)
 k_aev_fwd(const float4 *__restrict__ pos, const int *__restrict__ sys_of,
           const SysDesc *__restrict__ sys, const int2 *__restrict__ nbr,
           const int *__restrict__ nbr_cnt, int cap, const int *__restrict__ row_of_atom,
-          void *__restrict__ G, int ldg, Live N_, AevConst c) {
+          void *__restrict__ G, int ldg, unsigned long long *__restrict__ row_mask, Live N_, AevConst c) {
   extern __shared__ float4 lds4[];
   const int N = N_.get();
   // the wave index is uniform across the wave: keep it (and the centre's
@@ -375,7 +390,8 @@ k_aev_fwd(const float4 *__restrict__ pos, const int *__restrict__ sys_of,
   __syncthreads();
   if (!live) return;
   const Lists &ls = *w.ls;
-  void *Grow = (char *)G + (size_t)row_of_atom[i] * ldg * (BF16 ? 2 : 4);
+  const int r_i = row_of_atom[i];
+  void *Grow = (char *)G + (size_t)r_i * ldg * (BF16 ? 2 : 4);
 
   // radial: G[16 s + m] = scale * sum_j exp(-eta (R - Rs_m)^2) fc(R)
   // lanes = 16 shifts x 4 neighbour slots (slot fastest)
@@ -414,6 +430,12 @@ k_aev_fwd(const float4 *__restrict__ pos, const int *__restrict__ sys_of,
     float bR2;
     block_words(lane, ls, c.S, bT, bOxy, bNs, bR2);
     const unsigned long long nonempty = __ballot(bT > 0);
+    // the row's record of its possibly non-zero halves: radial species with
+    // an entry, species pairs with a pair
+    if (row_mask) {
+      const unsigned long long radial = __ballot(lane < c.S && ls.cR[min(lane, kMaxSpecies - 1)] > 0);
+      if (lane == 0) row_mask[r_i] = radial | spread_pairs(nonempty) << c.S;
+    }
     // blocks without a pair of their two species are zero: written in one
     // pass of 16-byte stores over the angular part of the row
     {
@@ -973,25 +995,31 @@ static int waves_for_cap(int cap, int pref) {
 
 template <bool BF16>
 static void aev_fwd_t(const float4 *pos, const int *sys_of, const SysDesc *sys, const int2 *nbr,
-                      const int *nbr_cnt, int cap, const int *row_of_atom, void *G, int ldg, Live N,
-                      const AevConst &c, int wpb_pref, hipStream_t st) {
+                      const int *nbr_cnt, int cap, const int *row_of_atom, void *G, int ldg,
+                      unsigned long long *row_mask, Live N, const AevConst &c, int wpb_pref, hipStream_t st) {
   int wpb = waves_for_cap<false>(cap, wpb_pref);
   size_t lds = wave_lds_bytes<false>(cap) * wpb;
   unsigned grid = (unsigned)((N.v + wpb - 1) / wpb);
   if (wpb == 4)
-    k_aev_fwd<4, BF16><<<grid, 4 * kWave, lds, st>>>(pos, sys_of, sys, nbr, nbr_cnt, cap, row_of_atom, G, ldg, N, c);
+    k_aev_fwd<4, BF16><<<grid, 4 * kWave, lds, st>>>(pos, sys_of, sys, nbr, nbr_cnt, cap, row_of_atom, G, ldg,
+                                                     row_mask, N, c);
   else if (wpb == 2)
-    k_aev_fwd<2, BF16><<<grid, 2 * kWave, lds, st>>>(pos, sys_of, sys, nbr, nbr_cnt, cap, row_of_atom, G, ldg, N, c);
+    k_aev_fwd<2, BF16><<<grid, 2 * kWave, lds, st>>>(pos, sys_of, sys, nbr, nbr_cnt, cap, row_of_atom, G, ldg,
+                                                     row_mask, N, c);
   else
-    k_aev_fwd<1, BF16><<<grid, kWave, lds, st>>>(pos, sys_of, sys, nbr, nbr_cnt, cap, row_of_atom, G, ldg, N, c);
+    k_aev_fwd<1, BF16><<<grid, kWave, lds, st>>>(pos, sys_of, sys, nbr, nbr_cnt, cap, row_of_atom, G, ldg,
+                                                 row_mask, N, c);
 }
 
 void launch_aev_fwd(const float4 *pos, const int *sys_of, const SysDesc *sys, const int2 *nbr,
                     const int *nbr_cnt, int cap, const int *row_of_atom, void *G, bool g_bf16,
-                    int ldg, Live N, const AevConst &c, int wpb_pref, hipStream_t st) {
+                    int ldg, Live N, const AevConst &c, unsigned long long *row_mask, int wpb_pref,
+                    hipStream_t st) {
   if (N.v <= 0) return;
-  if (g_bf16) aev_fwd_t<true>(pos, sys_of, sys, nbr, nbr_cnt, cap, row_of_atom, G, ldg, N, c, wpb_pref, st);
-  else aev_fwd_t<false>(pos, sys_of, sys, nbr, nbr_cnt, cap, row_of_atom, G, ldg, N, c, wpb_pref, st);
+  if (g_bf16)
+    aev_fwd_t<true>(pos, sys_of, sys, nbr, nbr_cnt, cap, row_of_atom, G, ldg, row_mask, N, c, wpb_pref, st);
+  else
+    aev_fwd_t<false>(pos, sys_of, sys, nbr, nbr_cnt, cap, row_of_atom, G, ldg, row_mask, N, c, wpb_pref, st);
 }
 
 template <int WPB>

@@ -135,6 +135,7 @@ struct nnp_model {
   DevBuf block_counts, bucket_off, bucket_cnt, perm, row_of_atom, G, dG, e_atom, W_atom, partial;
   DevBuf desc, status, state, e_mem, dp_rec;  // desc: the per-call descriptors (desc_layout)
   DevBuf Ffix;                           // AEV models: forces in 64-bit fixed point [N][3]
+  DevBuf gmask;                          // AEV models: per G row, its possibly non-zero 16-column halves
   size_t max_lds = 64 * 1024;            // LDS bytes one workgroup may use on this device
   std::vector<DevBuf> H, Gd;
   // fused hidden-layer chain (bfloat16 models whose hidden widths allow it)
@@ -209,7 +210,7 @@ extern "C" void nnp_destroy(nnp_model *m) {
                     &m->cell_start, &m->cell_atoms, &m->nbr, &m->nbr_cnt, &m->block_counts,
                     &m->bucket_off, &m->bucket_cnt, &m->perm, &m->row_of_atom, &m->G, &m->dG,
                     &m->e_atom, &m->W_atom, &m->partial, &m->desc, &m->status, &m->state, &m->e_mem,
-                    &m->chain_nets, &m->dp_rec, &m->Ffix};
+                    &m->chain_nets, &m->dp_rec, &m->Ffix, &m->gmask};
   for (DevBuf *b : bufs) b->release();
   for (auto &b : m->H) b.release();
   for (auto &b : m->Gd) b.release();
@@ -561,6 +562,7 @@ static int for_each_ws(nnp_model *m, int64_t N, int S, int64_t C, int n_chunks, 
   ENS(m->partial, (int64_t)n_chunks * 80 + 80);
   ENS(m->desc, DescLayout(S, n_chunks, (int)max_bwd_groups(N, S)).total);
   if (m->kind == kDescAev) ENS(m->Ffix, N * 24);
+  if (m->kind == kDescAev) ENS(m->gmask, rows * 8);
   for (int l = 0; l + 1 < m->L; ++l) {
     ENS(m->H[l], rows * m->ldH[l] * m->M * esz);
     ENS(m->Gd[l], rows * m->ldH[l] * m->M * esz);
@@ -1226,6 +1228,10 @@ static int run(nnp_model *m, int n_sys, const int64_t *offs, const float *coords
     const int rows = (N_l + kTileM - 1) / kTileM * kTileM + m->S * kTileM;
     launch_species_bucket(pos, lN, m->S, m->block_counts.as<int>(), nblk, m->bucket_off.as<int>(),
                           m->bucket_cnt.as<int>(), m->perm.as<int>(), m->row_of_atom.as<int>(), rows, st);
+    // AEV models: the forward records per row the column halves it may have
+    // non-zero, and the first layer and the dE/dG product skip what no row
+    // of a tile has
+    unsigned long long *gmask = m->kind == kDescDp ? nullptr : m->gmask.as<unsigned long long>();
     // atoms outside a caller's mask have no network: zero atomic energy
     // atomic energies go straight to the caller's buffer when one is given
     // (every atom's entry is written each call), else to the workspace
@@ -1238,22 +1244,22 @@ static int run(nnp_model *m, int n_sys, const int64_t *offs, const float *coords
     const bool want_grad = o.forces != nullptr;
     // descriptor forward into rows of G (the AEV export: float32 rows of the
     // dE/dG buffer, gathered back to atom order)
-    auto descriptor = [&](void *Gp, bool g_bf16, int ldg, float4 *rec, int wpb) {
+    auto descriptor = [&](void *Gp, bool g_bf16, int ldg, float4 *rec, unsigned long long *tm, int wpb) {
       if (dp)
         launch_dp_fwd(pos, coords, pool_state, m->sys_of.as<int>(), dsys, pool_nbr, pool_cnt, cap,
                       m->row_of_atom.as<int>(), Gp, g_bf16, ldg, N, m->dp, rec, wpb, st);
       else
         launch_aev_fwd(pos, m->sys_of.as<int>(), dsys, pool_nbr, pool_cnt, cap, m->row_of_atom.as<int>(), Gp,
-                       g_bf16, ldg, lN, m->aev, wpb, st);
+                       g_bf16, ldg, lN, m->aev, tm, wpb, st);
     };
     if (mode == kAev) {
-      descriptor(m->dG.p, false, D, nullptr, 0);
+      descriptor(m->dG.p, false, D, nullptr, nullptr, 0);
       launch_gather_rows(m->dG.as<float>(), D, m->row_of_atom.as<int>(), N, D, o.aev, st);
       HIP_TRY(hipGetLastError());
       return NNP_OK;
     }
     site_begin(kSiteAevFwd);
-    descriptor(m->G.p, bf16, m->ldG, dp && want_grad ? m->dp_rec.as<float4>() : nullptr,
+    descriptor(m->G.p, bf16, m->ldG, dp && want_grad ? m->dp_rec.as<float4>() : nullptr, gmask,
                m->tune_val[kSiteAevFwd]);
     site_end(kSiteAevFwd);
     mark();
@@ -1281,6 +1287,10 @@ static int run(nnp_model *m, int n_sys, const int64_t *offs, const float *coords
       gl.C = m->H[l].p;
       gl.ldc = M * m->ldH[l];
       gl.c_member_stride = m->ldH[l];
+      if (l == 0) {
+        gl.row_mask = gmask;
+        gl.bucket_cnt = m->bucket_cnt.as<int>();
+      }
       for (int mb = 0; mb < M; ++mb)
         for (int s = 0; s < S; ++s) {
           LayerW &lw = m->layer(mb, s, l);
@@ -1381,6 +1391,8 @@ static int run(nnp_model *m, int n_sys, const int64_t *offs, const float *coords
         gl.a_seg_stride = m->ldH[0];
         gl.C = m->dG.p;
         gl.ldc = D;
+        gl.row_mask = gmask;
+        gl.bucket_cnt = m->bucket_cnt.as<int>();
         for (int s = 0; s < S; ++s) {
           GemmGroup &g = gl.g[s];
           g.B = bf16 ? (const void *)m->Wdg_b[s] : (const void *)m->Wdg[s];

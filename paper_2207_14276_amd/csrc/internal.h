@@ -176,6 +176,15 @@ struct GemmLaunch {
   const void *H; int ldh;      // backward: layer input activations for CELU'
   int h_member_stride;
   const int *bucket_off;       // [n_groups + 1] padded row offsets (device)
+  // Nullable: per row, bit h set when columns [16 h, 16 h + 16) of the AEV
+  // row may be non-zero (the AEV forward's record of the real rows, the
+  // first bucket_cnt rows of each bucket).  With it the direct-to-LDS kernel
+  // skips the zero work of its row tile: first layer (A = the AEVs, one K
+  // segment): K halves no row has; dE/dG output: column halves no row has,
+  // not stored (their readers read a row's own halves only), and no MFMAs
+  // for a wave whose columns are all such.
+  const unsigned long long *row_mask;
+  const int *bucket_cnt;       // [n_groups] real rows per bucket (with row_mask)
   int n_groups;                // species
   int n_members;               // grid dimension over ensemble members
   int n_seg;                   // K segments summed into one output
@@ -269,9 +278,13 @@ void launch_dp_fwd(const float4 *pos, const float *coords, const AtomState *stat
 void launch_dp_bwd(const SysDesc *sys, int n_sys, bool small_systems, const int *cell_start,
                    const int *cell_atoms, int n_cells, const int *row_of_atom, const float *dG, int ldg, int N,
                    const DpConst &c, const float4 *rec, float *F, float *W_atom, int wpb_pref, hipStream_t st);
+// row_mask (nullable): per G row, the 16-column halves that may be non-zero
+// (radial species s: half s; angular species pair p: halves S + 2 p and
+// S + 2 p + 1); every other half of the row is written as zeros.
 void launch_aev_fwd(const float4 *pos, const int *sys_of, const SysDesc *sys, const int2 *nbr,
                     const int *nbr_cnt, int cap, const int *row_of_atom, void *G, bool g_bf16,
-                    int ldg, Live N, const AevConst &c, int wpb_pref, hipStream_t st);
+                    int ldg, Live N, const AevConst &c, unsigned long long *row_mask, int wpb_pref,
+                    hipStream_t st);
 // How the AEV backward groups its centres (at most one of the two forms):
 // groups[n_groups] = {first centre, count} of consecutive centres of one
 // small non-periodic system (max_sys_atoms: the largest such system), or the

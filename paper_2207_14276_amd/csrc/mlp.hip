@@ -20,6 +20,7 @@
 // an A row tile) run on the same XCD and hit the same L2.
 #include "internal.h"
 #include "fixed.h"
+#include "wave.h"
 
 #include <algorithm>
 
@@ -298,6 +299,16 @@ __device__ inline void wait_chunks(int ahead) {
   else __builtin_amdgcn_s_waitcnt(vm_imm(0));
 }
 
+// Bits 0, 2, 4, ... of x gathered into bits 0, 1, 2, ...
+__device__ inline unsigned long long even_bits(unsigned long long x) {
+  x &= 0x5555555555555555ull;
+  x = (x | (x >> 1)) & 0x3333333333333333ull;
+  x = (x | (x >> 2)) & 0x0f0f0f0f0f0f0f0full;
+  x = (x | (x >> 4)) & 0x00ff00ff00ff00ffull;
+  x = (x | (x >> 8)) & 0x0000ffff0000ffffull;
+  return (x | (x >> 16)) & 0x00000000ffffffffull;
+}
+
 // 256-wide tiles hold 128 accumulator registers per lane; the kernel is
 // held to 256 registers in all so that two workgroups share a compute unit.
 // STAGES: depth of the operand ring; loads run STAGES - 1 chunks ahead.
@@ -308,7 +319,7 @@ k_gemm_dl(GemmLaunch gl) {
   typedef uint16_t T;
   constexpr int TM = kTileM;
   constexpr int TK = 32;
-  static_assert(STAGES >= 3 && STAGES <= 5, "ring depth");
+  static_assert(STAGES == 3, "ring depth: the first two chunks are issued unconditionally");
   constexpr int WM = TN == 64 ? 32 : 64;
   constexpr int WN = TN == 256 ? 128 : 64;
   constexpr int WAVES_N = TN / WN;
@@ -328,9 +339,14 @@ k_gemm_dl(GemmLaunch gl) {
   const int mb = SPAN ? 0 : (lb / n_ct) % gl.n_members;
   const int rt = SPAN ? lb / n_ct : lb / (n_ct * gl.n_members);
   const int r0 = rt * TM;
-  int s = -1;
+  // the row tile's species bucket, and (with row records) where its real
+  // rows end
+  int s = -1, real_end = 0;
   for (int q = 0; q < gl.n_groups; ++q)
-    if (r0 >= gl.bucket_off[q] && r0 < gl.bucket_off[q + 1]) s = q;
+    if (r0 >= gl.bucket_off[q] && r0 < gl.bucket_off[q + 1]) {
+      s = q;
+      if (gl.row_mask) real_end = gl.bucket_off[q] + gl.bucket_cnt[q];
+    }
   if (s < 0) return;
   const GemmGroup grp = gl.g[mb * gl.n_groups + s];
   const int n_cols = SPAN ? grp.n_out * gl.n_members : grp.n_out;
@@ -339,7 +355,6 @@ k_gemm_dl(GemmLaunch gl) {
   const int K = grp.K;
   const int nseg = gl.n_seg;
   const int nk = K / TK;
-  const int total = nk * nseg;
 
   const int tid = threadIdx.x, wave = __builtin_amdgcn_readfirstlane(tid / kWave), lane = tid % kWave;
   const int l32 = lane & 31, hi = lane >> 5;
@@ -389,13 +404,77 @@ k_gemm_dl(GemmLaunch gl) {
 #pragma unroll
     for (int j = 0; j < BN; ++j) acc[i][j] = floatx16{};
 
+  // The AEV halves (16 columns) that some row of the tile may have
+  // non-zero (wave-uniform; all without the record).  First layer: after
+  // the first chunks, a K chunk (halves 2c, 2c + 1) is loaded only if one
+  // of its halves is live, and a half's MFMAs run only if it is; the
+  // skipped products are zero for every row.  dE/dG: a column half no row
+  // has is read by no one and is not stored; a wave whose columns are all
+  // such runs no MFMAs.  Each wave loads the tile's row records (1 KB, two
+  // per lane) like the operands, ahead of chunk 0, into its own slots of the
+  // ring's last stage, which chunk 2 fills only after the records are read.
+  constexpr bool kMaskK = EPI == kEpiFwd, kMaskN = EPI == kEpiOut;
+  const bool masked = gl.row_mask != nullptr && (kMaskN || (kMaskK && nseg == 1 && nk <= 32));
+  static_assert(TM == 2 * kWave && A_SLOTS >= 256, "two row records per lane, in the wave's A slots");
+  if (masked)
+    __builtin_amdgcn_global_load_lds((const void *)(gl.row_mask + r0 + 2 * lane),
+                                     (__attribute__((address_space(3))) void *)&smem[STAGES - 1][wave * kWave],
+                                     16, 0, 0);
+  // the first chunks go out in order (every call has at least STAGES - 1)
+  const int n_pro = STAGES - 1;
 #pragma unroll
-  for (int q = 0; q < STAGES - 1; ++q)
-    if (q < total) issue(q, q);
+  for (int q = 0; q < STAGES - 1; ++q) issue(q, q);
+  unsigned long long live_h = ~0ull;
+  // live K chunks after the first ones, in order (first layer, masked: one
+  // segment of at most 32 chunks), set with live_h
+  unsigned long long kc_issue = 0, kc_comp = 0;
+  int total = kMaskK && masked ? n_pro : nk * nseg;  // masked first layer: until live_h is known
+  // chunk of the k-th issue (called for k = 0, 1, 2, ... in turn)
+  auto chunk_at = [&](int k) {
+    if (!(kMaskK && masked) || k < n_pro) return k;
+    const int cc = __builtin_ctzll(kc_issue);
+    kc_issue &= kc_issue - 1;
+    return cc;
+  };
+  bool wave_live = true;  // whether any column half of this wave is live (dE/dG)
+  bool some_dead = false;  // whether a column half of the tile is not (dE/dG)
+
   for (int c = 0; c < total; ++c) {
     // this wave's loads of chunk c are done once at most those of the
     // chunks issued after it remain
     wait_chunks<LOADS, STAGES - 2>(min(total - 1 - c, STAGES - 2));
+    if (masked && c == 0) {
+      // this wave's own record load preceded its chunk 0 loads, waited for
+      // above (no barrier needed); the read waits for itself (a plain LDS
+      // read here would make the compiler wait for every load in flight)
+      uint4 r;
+      const unsigned ra =
+          (unsigned)(uintptr_t)(__attribute__((address_space(3))) uint4 *)&smem[STAGES - 1][wave * kWave + lane];
+      asm volatile("ds_read_b128 %0, %1\n\ts_waitcnt lgkmcnt(0)" : "=v"(r) : "v"(ra) : "memory");
+      // records past the bucket's real rows are not the forward's
+      const int real = real_end - r0 - 2 * lane;
+      const unsigned h_lo = (real > 0 ? r.x : 0u) | (real > 1 ? r.z : 0u);
+      const unsigned h_hi = (real > 0 ? r.y : 0u) | (real > 1 ? r.w : 0u);
+      live_h = ((unsigned long long)wave_or(h_hi) << 32) | wave_or(h_lo);
+      if (kMaskN) {
+        // a column tile without a live half: nothing to compute or store
+        // (every wave leaves here; the operand loads in flight land in this
+        // workgroup's LDS first)
+        const unsigned long long tile_h = (live_h >> (c0 / 16)) & ((1ull << (TN / 16 - 1) << 1) - 1);
+        if (tile_h == 0) {
+          __builtin_amdgcn_s_waitcnt(vm_imm(0));
+          return;
+        }
+        // every half of the column tile live: stores without the check
+        some_dead = tile_h != ((1ull << (TN / 16 - 1) << 1) - 1);
+        wave_live = ((live_h >> ((c0 + wc * WN) / 16)) & ((1ull << (WN / 16 - 1) << 1) - 1)) != 0;
+      } else {
+        kc_issue = even_bits(live_h | (live_h >> 1)) & (nk >= 64 ? ~0ull : (1ull << nk) - 1) &
+                   ~((1ull << n_pro) - 1);
+        kc_comp = kc_issue;
+        total = n_pro + __builtin_popcountll(kc_issue);
+      }
+    }
     // a plain barrier: LDS is coherent within the workgroup, every wave has
     // waited for its own part of chunk c above, and its reads of the stage
     // overwritten next were consumed (by MFMAs) before it got here; a full
@@ -403,11 +482,23 @@ k_gemm_dl(GemmLaunch gl) {
     __builtin_amdgcn_s_barrier();
     // stage (c + STAGES - 1) % STAGES was last read for chunk c - 1, which
     // every wave has finished (barrier above)
-    if (c + STAGES - 1 < total) issue(c + STAGES - 1, (c + STAGES - 1) % STAGES);
+    if (c + STAGES - 1 < total) issue(chunk_at(c + STAGES - 1), (c + STAGES - 1) % STAGES);
     const uint4 *As = smem[c % STAGES];
     const uint4 *Bs = As + A_SLOTS;
+    // live halves of this chunk (first layer, masked)
+    unsigned halves = 3u;
+    if (kMaskK && masked) {
+      int cc = c;
+      if (c >= n_pro) {
+        cc = __builtin_ctzll(kc_comp);
+        kc_comp &= kc_comp - 1;
+      }
+      halves = (unsigned)(live_h >> (2 * cc)) & 3u;
+    }
+    if (!wave_live) continue;
 #pragma unroll
     for (int kk = 0; kk < TK; kk += 16) {
+      if (!((halves >> (kk / 16)) & 1u)) continue;
       const int ch = kk / 8 + hi;
       bf16x8 a[BM], b[BN];
 #pragma unroll
@@ -442,7 +533,7 @@ k_gemm_dl(GemmLaunch gl) {
 #pragma unroll
       for (int bj = 0; bj < BN; ++bj) {
         const int col = c0 + wc * WN + bj * 32 + l32;
-        if (col >= n_cols) continue;
+        if (col >= n_cols || (some_dead && !((live_h >> (col / 16)) & 1ull))) continue;
         float *out = (float *)gl.C + (size_t)(r0 + wr * WM + bi * 32 + 4 * hi) * gl.ldc + col;
 #pragma unroll
         for (int i = 0; i < 16; ++i) out[(size_t)(8 * (i / 4) + (i % 4)) * gl.ldc] = acc[bi][bj][i] * gl.scale;
@@ -542,7 +633,9 @@ static bool gemm_span_uniform(const GemmLaunch &gl) {
 }
 
 // Whether every K chunk of 32 elements and every operand row start is
-// 16-byte aligned and inside its row, as the direct-to-LDS kernel needs.
+// 16-byte aligned and inside its row, and every output sums at least two
+// chunks (the first two are loaded unconditionally), as the direct-to-LDS
+// kernel needs.
 static bool gemm_k32(const GemmLaunch &gl) {
   auto m32 = [](long long v) { return v % 32 == 0; };
   if (!m32(gl.lda) || !m32(gl.a_member_stride) || !m32(gl.a_seg_stride)) return false;
@@ -550,7 +643,7 @@ static bool gemm_k32(const GemmLaunch &gl) {
     const GemmGroup &g = gl.g[q];
     if (!g.B) continue;
     const long long ldb = g.ldb ? g.ldb : (long long)g.K * gl.n_seg;
-    if (!m32(g.K) || !m32(ldb) || g.K < 32) return false;
+    if (!m32(g.K) || !m32(ldb) || g.K * gl.n_seg < 64) return false;
   }
   return true;
 }

@@ -53,6 +53,20 @@ __device__ inline float wave_sum(float v) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
 }
 
+// OR over the whole wave, returned in every lane (the steps of wave_sum)
+template <int CTRL, int ROWS = 0xF> __device__ inline unsigned dpp_u(unsigned v) {
+  return (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROWS, 0xF, false);
+}
+__device__ inline unsigned wave_or(unsigned v) {
+  v |= dpp_u<0xB1>(v);
+  v |= dpp_u<0x4E>(v);
+  v |= dpp_u<0x141>(v);
+  v |= dpp_u<0x140>(v);
+  v |= dpp_u<0x142, 0xA>(v);
+  v |= dpp_u<0x143, 0xC>(v);
+  return (unsigned)__builtin_amdgcn_readlane((int)v, 63);
+}
+
 // Orders this wave's LDS writes before its later LDS reads by other lanes
 // (LDS requests of one wave are served in order; this only stops the
 // compiler from moving accesses across it).
