@@ -363,13 +363,15 @@ __global__ void __launch_bounds__(WPB * kWave)
 k_aev_fwd(const float4 *__restrict__ pos, const int *__restrict__ sys_of,
           const SysDesc *__restrict__ sys, const int2 *__restrict__ nbr,
           const int *__restrict__ nbr_cnt, int cap, const int *__restrict__ row_of_atom,
-          void *__restrict__ G, int ldg, unsigned long long *__restrict__ row_mask, Live N_, AevConst c) {
+          void *__restrict__ G, int ldg, unsigned long long *__restrict__ row_mask,
+          const int *__restrict__ wave_atom, Live N_, AevConst c) {
   extern __shared__ float4 lds4[];
   const int N = N_.get();
   // the wave index is uniform across the wave: keep it (and the centre's
   // index, descriptors and row pointers) in scalar registers
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave), lane = threadIdx.x % kWave;
-  const int i = blockIdx.x * WPB + wave;
+  const int wv = blockIdx.x * WPB + wave;
+  const int i = wave_atom && wv < N ? __builtin_amdgcn_readfirstlane(wave_atom[wv]) : wv;
   // an atom without a network row (outside a caller's mask) is skipped
   const bool live = i < N && row_of_atom[i] >= 0;
   WaveLds w = carve<false>((char *)lds4 + wave * wave_lds_bytes<false>(cap), cap);
@@ -572,7 +574,11 @@ k_aev_fwd(const float4 *__restrict__ pos, const int *__restrict__ sys_of,
 // fixed point (fixed.h) in the buffer Ffix[N][3], which the caller clears
 // first and converts to float32 afterwards: integer sums do not depend on the
 // order in which waves add into them, so forces come out the same bit for
-// bit whatever else the batch holds.
+// bit whatever else the batch holds.  Atom j of system d accumulates in slot
+// j + fix_shift(d) = d.order_off + (j - d.atom_off): the systems in the
+// order their centres are launched, so that the waves running together add
+// into neighbouring slots (scattered slots made these device atomics
+// several times slower).
 //   SinkGlobal: device-scope integer atomics straight into Ffix;
 //   SinkSys:    an LDS table of one system's atoms (index j - atom_off),
 //               added into Ffix once per workgroup;
@@ -582,8 +588,9 @@ k_aev_fwd(const float4 *__restrict__ pos, const int *__restrict__ sys_of,
 //               straight to Ffix.
 struct SinkGlobal {
   unsigned long long *F;
+  int shift;  // fix_shift of the system
   __device__ inline void add(int j, long long x, long long y, long long z) const {
-    unsigned long long *p = F + 3 * (size_t)j;
+    unsigned long long *p = F + 3 * (size_t)(j + shift);
     atomicAdd(p, (unsigned long long)x);
     atomicAdd(p + 1, (unsigned long long)y);
     atomicAdd(p + 2, (unsigned long long)z);
@@ -608,6 +615,7 @@ struct SinkHash {
   int *key;
   unsigned long long *val;
   unsigned long long *F;
+  int shift;  // fix_shift of the system
   __device__ inline void add(int j, long long x, long long y, long long z) const {
     unsigned h = ((unsigned)j * 2654435761u) >> (32 - kBwdHashBits);
     for (int probe = 0; probe < kBwdProbe; ++probe) {
@@ -622,7 +630,7 @@ struct SinkHash {
       }
       h = (h + 1) & (kBwdHash - 1);
     }
-    SinkGlobal{F}.add(j, x, y, z);
+    SinkGlobal{F, shift}.add(j, x, y, z);
   }
 };
 
@@ -887,15 +895,19 @@ k_aev_bwd(const float4 *__restrict__ pos, const int *__restrict__ sys_of,
           const SysDesc *__restrict__ sys, const int2 *__restrict__ nbr,
           const int *__restrict__ nbr_cnt, int cap, const int *__restrict__ row_of_atom,
           const float *__restrict__ dG, int ldg, Live N, AevConst c, unsigned long long *__restrict__ Ffix,
-          float *__restrict__ W_atom) {
+          float *__restrict__ W_atom, const int *__restrict__ wave_atom) {
   extern __shared__ float4 lds4[];
   // the wave index is uniform across the wave: keep it (and the centre's
   // index, descriptors and row pointers) in scalar registers
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave), lane = threadIdx.x % kWave;
-  const int i = blockIdx.x * WPB + wave;
-  if (i >= N.get()) return;
+  const int wv = blockIdx.x * WPB + wave;
+  if (wv >= N.get()) return;
+  // the centre of this wave (the costliest systems' centres first)
+  const int i = wave_atom ? __builtin_amdgcn_readfirstlane(wave_atom[wv]) : wv;
   WaveLds w = carve<true>((char *)lds4 + wave * wave_lds_bytes<true>(cap), cap);
-  bwd_centre(i, lane, pos, sys_of, sys, nbr, nbr_cnt, cap, row_of_atom, dG, ldg, c, W_atom, w, SinkGlobal{Ffix});
+  const SysDesc &d = sys[sys_of[i]];
+  bwd_centre(i, lane, pos, sys_of, sys, nbr, nbr_cnt, cap, row_of_atom, dG, ldg, c, W_atom, w,
+             SinkGlobal{Ffix, fix_shift(d)});
 }
 
 // Next centre of a workgroup's group for the calling wave (an LDS counter:
@@ -935,7 +947,7 @@ k_aev_bwd_sys(const int2 *__restrict__ groups, const float4 *__restrict__ pos, c
   __syncthreads();
   for (int t = threadIdx.x; t < n3; t += WPB * kWave) {
     const unsigned long long v = tab[t];
-    if (v) atomicAdd(Ffix + 3 * (size_t)off + t, v);
+    if (v) atomicAdd(Ffix + 3 * (size_t)d.order_off + t, v);
   }
 }
 
@@ -966,7 +978,9 @@ k_aev_bwd_cells(const int *__restrict__ cell_start, const int *__restrict__ cell
   __syncthreads();
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave), lane = threadIdx.x % kWave;
   WaveLds w = carve<true>((char *)lds4 + wave * wave_lds_bytes<true>(cap), cap);
-  const SinkHash sink{hkey, hval, Ffix};
+  // a cell's centres and their neighbours belong to one system
+  const int shift = fix_shift(sys[sys_of[cell_atoms[b]]]);
+  const SinkHash sink{hkey, hval, Ffix, shift};
   for (int p = next_centre(&counter, lane); b + p < e; p = next_centre(&counter, lane))
     bwd_centre(cell_atoms[b + p], lane, pos, sys_of, sys, nbr, nbr_cnt, cap, row_of_atom, dG, ldg, c, W_atom, w,
                sink);
@@ -974,7 +988,7 @@ k_aev_bwd_cells(const int *__restrict__ cell_start, const int *__restrict__ cell
   for (int t = threadIdx.x; t < kBwdHash; t += WPB * kWave) {
     const int j = hkey[t];
     if (j < 0) continue;
-    unsigned long long *p = Ffix + 3 * (size_t)j;
+    unsigned long long *p = Ffix + 3 * (size_t)(j + shift);
     for (int q = 0; q < 3; ++q) {
       const unsigned long long v = hval[3 * t + q];
       if (v) atomicAdd(p + q, v);
@@ -996,30 +1010,33 @@ static int waves_for_cap(int cap, int pref) {
 template <bool BF16>
 static void aev_fwd_t(const float4 *pos, const int *sys_of, const SysDesc *sys, const int2 *nbr,
                       const int *nbr_cnt, int cap, const int *row_of_atom, void *G, int ldg,
-                      unsigned long long *row_mask, Live N, const AevConst &c, int wpb_pref, hipStream_t st) {
+                      unsigned long long *row_mask, const int *wave_atom, Live N, const AevConst &c, int wpb_pref,
+                      hipStream_t st) {
   int wpb = waves_for_cap<false>(cap, wpb_pref);
   size_t lds = wave_lds_bytes<false>(cap) * wpb;
   unsigned grid = (unsigned)((N.v + wpb - 1) / wpb);
   if (wpb == 4)
     k_aev_fwd<4, BF16><<<grid, 4 * kWave, lds, st>>>(pos, sys_of, sys, nbr, nbr_cnt, cap, row_of_atom, G, ldg,
-                                                     row_mask, N, c);
+                                                     row_mask, wave_atom, N, c);
   else if (wpb == 2)
     k_aev_fwd<2, BF16><<<grid, 2 * kWave, lds, st>>>(pos, sys_of, sys, nbr, nbr_cnt, cap, row_of_atom, G, ldg,
-                                                     row_mask, N, c);
+                                                     row_mask, wave_atom, N, c);
   else
     k_aev_fwd<1, BF16><<<grid, kWave, lds, st>>>(pos, sys_of, sys, nbr, nbr_cnt, cap, row_of_atom, G, ldg,
-                                                 row_mask, N, c);
+                                                 row_mask, wave_atom, N, c);
 }
 
 void launch_aev_fwd(const float4 *pos, const int *sys_of, const SysDesc *sys, const int2 *nbr,
                     const int *nbr_cnt, int cap, const int *row_of_atom, void *G, bool g_bf16,
-                    int ldg, Live N, const AevConst &c, unsigned long long *row_mask, int wpb_pref,
-                    hipStream_t st) {
+                    int ldg, Live N, const AevConst &c, unsigned long long *row_mask, const int *wave_atom,
+                    int wpb_pref, hipStream_t st) {
   if (N.v <= 0) return;
   if (g_bf16)
-    aev_fwd_t<true>(pos, sys_of, sys, nbr, nbr_cnt, cap, row_of_atom, G, ldg, row_mask, N, c, wpb_pref, st);
+    aev_fwd_t<true>(pos, sys_of, sys, nbr, nbr_cnt, cap, row_of_atom, G, ldg, row_mask, wave_atom, N, c, wpb_pref,
+                    st);
   else
-    aev_fwd_t<false>(pos, sys_of, sys, nbr, nbr_cnt, cap, row_of_atom, G, ldg, row_mask, N, c, wpb_pref, st);
+    aev_fwd_t<false>(pos, sys_of, sys, nbr, nbr_cnt, cap, row_of_atom, G, ldg, row_mask, wave_atom, N, c, wpb_pref,
+                     st);
 }
 
 template <int WPB>
@@ -1043,7 +1060,7 @@ static void aev_bwd_launch(int form, size_t lds, unsigned grid, const AevBwdGrou
   }
   if constexpr (WPB <= 4)
     k_aev_bwd<WPB><<<grid, WPB * kWave, lds, st>>>(pos, sys_of, sys, nbr, nbr_cnt, cap, row_of_atom, dG, ldg, N, c,
-                                                   Ffix, W_atom);
+                                                   Ffix, W_atom, gp.wave_atom);
 }
 
 // Chooses the form.  wpb_pref 0 (untuned), 1 or 2: one wave per centre,

@@ -136,6 +136,7 @@ struct nnp_model {
   DevBuf desc, status, state, e_mem, dp_rec;  // desc: the per-call descriptors (desc_layout)
   DevBuf Ffix;                           // AEV models: forces in 64-bit fixed point [N][3]
   DevBuf gmask;                          // AEV models: per G row, its possibly non-zero 16-column halves
+  DevBuf wave_atom;                      // AEV models: centre of each wave of the per-centre kernels
   size_t max_lds = 64 * 1024;            // LDS bytes one workgroup may use on this device
   std::vector<DevBuf> H, Gd;
   // fused hidden-layer chain (bfloat16 models whose hidden widths allow it)
@@ -210,7 +211,7 @@ extern "C" void nnp_destroy(nnp_model *m) {
                     &m->cell_start, &m->cell_atoms, &m->nbr, &m->nbr_cnt, &m->block_counts,
                     &m->bucket_off, &m->bucket_cnt, &m->perm, &m->row_of_atom, &m->G, &m->dG,
                     &m->e_atom, &m->W_atom, &m->partial, &m->desc, &m->status, &m->state, &m->e_mem,
-                    &m->chain_nets, &m->dp_rec, &m->Ffix, &m->gmask};
+                    &m->chain_nets, &m->dp_rec, &m->Ffix, &m->gmask, &m->wave_atom};
   for (DevBuf *b : bufs) b->release();
   for (auto &b : m->H) b.release();
   for (auto &b : m->Gd) b.release();
@@ -563,6 +564,7 @@ static int for_each_ws(nnp_model *m, int64_t N, int S, int64_t C, int n_chunks, 
   ENS(m->desc, DescLayout(S, n_chunks, (int)max_bwd_groups(N, S)).total);
   if (m->kind == kDescAev) ENS(m->Ffix, N * 24);
   if (m->kind == kDescAev) ENS(m->gmask, rows * 8);
+  if (m->kind == kDescAev) ENS(m->wave_atom, N * 4);
   for (int l = 0; l + 1 < m->L; ++l) {
     ENS(m->H[l], rows * m->ldH[l] * m->M * esz);
     ENS(m->Gd[l], rows * m->ldH[l] * m->M * esz);
@@ -1044,6 +1046,19 @@ static int run(nnp_model *m, int n_sys, const int64_t *offs, const float *coords
     }
   }
   sys_ch[n_sys] = (int)ch_sys.size();
+  // the AEV kernels' one-wave-per-centre launches take the systems in order
+  // of decreasing size, so that the costliest centres do not start last and
+  // leave the compute units idle behind them
+  {
+    std::vector<int> order(n_sys);
+    for (int s = 0; s < n_sys; ++s) order[s] = s;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return sd[a].n > sd[b].n; });
+    int next = 0;
+    for (int s : order) {
+      sd[s].order_off = next;
+      next += sd[s].n;
+    }
+  }
   // every system small and without a box: a direct scan per system
   bool all_small = !pairs && N > 0;
   for (int s = 0; s < n_sys && all_small; ++s) all_small = !sd[s].periodic && sd[s].n <= kSmallSystem;
@@ -1194,8 +1209,10 @@ static int run(nnp_model *m, int n_sys, const int64_t *offs, const float *coords
     // DeepPot-style models in float32 straight in the output
     const bool fix_forces = mode == kFull && o.forces && m->kind == kDescAev;
     unsigned long long *Ffix = fix_forces ? m->Ffix.as<unsigned long long>() : nullptr;
+    // the launch order of the AEV kernels' centres, for calls of several systems
+    int *wave_atom = m->kind == kDescAev && n_sys > 1 && !pairs ? m->wave_atom.as<int>() : nullptr;
     launch_ingest(coords, species, pin.mask, dsys, lS, lN, m->S, pos, m->sys_of.as<int>(), pool_state,
-                  status, mode == kFull && !fix_forces ? o.forces : nullptr, Ffix, st);
+                  status, mode == kFull && !fix_forces ? o.forces : nullptr, Ffix, wave_atom, st);
     mark();
     if (pairs) {
       // the caller's list replaces the cell search (stage "cells" stays empty)
@@ -1226,7 +1243,7 @@ static int run(nnp_model *m, int n_sys, const int64_t *offs, const float *coords
     mark();
     const int nblk = (N_l + 1023) / 1024;
     const int rows = (N_l + kTileM - 1) / kTileM * kTileM + m->S * kTileM;
-    launch_species_bucket(pos, lN, m->S, m->block_counts.as<int>(), nblk, m->bucket_off.as<int>(),
+    launch_species_bucket(pos, wave_atom, lN, m->S, m->block_counts.as<int>(), nblk, m->bucket_off.as<int>(),
                           m->bucket_cnt.as<int>(), m->perm.as<int>(), m->row_of_atom.as<int>(), rows, st);
     // AEV models: the forward records per row the column halves it may have
     // non-zero, and the first layer and the dE/dG product skip what no row
@@ -1250,7 +1267,7 @@ static int run(nnp_model *m, int n_sys, const int64_t *offs, const float *coords
                       m->row_of_atom.as<int>(), Gp, g_bf16, ldg, N, m->dp, rec, wpb, st);
       else
         launch_aev_fwd(pos, m->sys_of.as<int>(), dsys, pool_nbr, pool_cnt, cap, m->row_of_atom.as<int>(), Gp,
-                       g_bf16, ldg, lN, m->aev, tm, wpb, st);
+                       g_bf16, ldg, lN, m->aev, tm, wave_atom, wpb, st);
     };
     if (mode == kAev) {
       descriptor(m->dG.p, false, D, nullptr, nullptr, 0);
@@ -1415,6 +1432,7 @@ static int run(nnp_model *m, int n_sys, const int64_t *offs, const float *coords
                       m->dp_rec.as<float4>(), o.forces, m->W_atom.as<float>(), m->tune_val[kSiteAevBwd], st);
       } else {
         AevBwdGroups gp;
+        gp.wave_atom = wave_atom;
         if (!groups.empty()) {
           gp.groups = (const int2 *)(m->desc.as<char>() + dl.gr);
           gp.n_groups = groups_l;

@@ -107,9 +107,15 @@ struct SysDesc {
   float edge[3];
   int nc[3];
   int rebuild;       // nonzero: build this system's neighbour list in this call
+  int order_off;     // first wave of this system's centres in the AEV kernels'
+                     // launch order (systems by decreasing size)
   long long list_off;   // first neighbour row of the system in the list pool
   long long state_off;  // first per-atom state slot (reference position, wrap)
 };
+
+// Offset from atom index to its slot in the fixed-point force accumulators
+// (the launch order of the systems: slot = order_off + local index).
+__host__ __device__ inline int fix_shift(const SysDesc &d) { return d.order_off - d.atom_off; }
 
 // Persistent per-atom state of a neighbour list: the caller's coordinates at
 // the last build (w unused) and the periodic wrap applied then (in box units).
@@ -244,10 +250,11 @@ void launch_skin_check(const float *coords, SysDesc *sys, Live n_sys, const Atom
                        float half_skin, int *stats, hipStream_t st);
 // zero_forces (nullable): the force output, cleared here for the backward
 // zero_fix (nullable): the fixed-point force accumulators, cleared here
+// wave_atom (nullable): gets, at order_off + k, the k-th atom of each system.
 void launch_ingest(const float *coords, const int *species, const unsigned char *mask,
                    const SysDesc *sys, Live n_sys, Live N, int S, float4 *pos, int *sys_of,
                    AtomState *state, int *status, float *zero_forces, unsigned long long *zero_fix,
-                   hipStream_t st);
+                   int *wave_atom, hipStream_t st);
 constexpr int kSmallSystem = 512;   // largest non-periodic system of the small-system search
 void launch_nbr_small(const float4 *pos, const int *sys_of, const SysDesc *sys, Live N, float rc_list,
                       int cap, int2 *nbr, int *nbr_cnt, int *status, hipStream_t st);
@@ -265,8 +272,11 @@ void launch_cell_sort(const int *cell_start, Live n_cells, int *cell_atoms, hipS
 void launch_nbr_build(const float4 *pos, const int *sys_of, const SysDesc *sys, Live n_sys, int n_cells,
                       const int *cell_start, const int *cell_atoms, Live N, float rc_list, int cap,
                       int2 *nbr, int *nbr_cnt, int *status, hipStream_t st);
-void launch_species_bucket(const float4 *pos, Live N, int S, int *block_counts, int n_blocks,
-                           int *bucket_off, int *bucket_cnt, int *perm, int *row_of_atom,
+// Rows of each species bucket follow the atoms in wave_atom's order (the AEV
+// kernels' launch order: centres running together read neighbouring rows),
+// or the atom order without it.
+void launch_species_bucket(const float4 *pos, const int *wave_atom, Live N, int S, int *block_counts,
+                           int n_blocks, int *bucket_off, int *bucket_cnt, int *perm, int *row_of_atom,
                            int rows_cap, hipStream_t st);
 // DeepPot-style descriptor: forward into G rows (and the per-centre slot
 // records {d, j} for the backward, nullable), backward from dE/dG and the
@@ -281,10 +291,12 @@ void launch_dp_bwd(const SysDesc *sys, int n_sys, bool small_systems, const int 
 // row_mask (nullable): per G row, the 16-column halves that may be non-zero
 // (radial species s: half s; angular species pair p: halves S + 2 p and
 // S + 2 p + 1); every other half of the row is written as zeros.
+// wave_atom (nullable): the centre of wave w (the ingest's launch order, the
+// costliest systems first, so that no long centre starts last); else w.
 void launch_aev_fwd(const float4 *pos, const int *sys_of, const SysDesc *sys, const int2 *nbr,
                     const int *nbr_cnt, int cap, const int *row_of_atom, void *G, bool g_bf16,
-                    int ldg, Live N, const AevConst &c, unsigned long long *row_mask, int wpb_pref,
-                    hipStream_t st);
+                    int ldg, Live N, const AevConst &c, unsigned long long *row_mask, const int *wave_atom,
+                    int wpb_pref, hipStream_t st);
 // How the AEV backward groups its centres (at most one of the two forms):
 // groups[n_groups] = {first centre, count} of consecutive centres of one
 // small non-periodic system (max_sys_atoms: the largest such system), or the
@@ -297,6 +309,7 @@ struct AevBwdGroups {
   const int *cell_start = nullptr, *cell_atoms = nullptr;
   int n_cells = 0;
   const int *live_groups = nullptr, *live_cells = nullptr;
+  const int *wave_atom = nullptr;  // one wave per centre: the centre of wave w (nullable: w)
 };
 // Forces go into Ffix [N][3] (64-bit fixed point, cleared by the caller).
 void launch_aev_bwd(const float4 *pos, const int *sys_of, const SysDesc *sys, const int2 *nbr,

@@ -766,9 +766,11 @@ k_reduce_partial(const float *__restrict__ e_atom, const float *__restrict__ W_a
     if (W_atom)
       for (int q = 0; q < 9; ++q) acc[1 + q] += (double)W_atom[(size_t)9 * i + q];
   }
-  // fixed-point forces of the chunk's atoms to float32
-  if (Ffix)
-    for (int t = 3 * b + threadIdx.x; t < 3 * e; t += blockDim.x) F[t] = from_fix((long long)Ffix[t]);
+  // fixed-point forces of the chunk's atoms (slots in launch order) to float32
+  if (Ffix) {
+    const int s3 = 3 * fix_shift(d);
+    for (int t = 3 * b + threadIdx.x; t < 3 * e; t += blockDim.x) F[t] = from_fix((long long)Ffix[t + s3]);
+  }
   const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
   for (int q = 0; q < 10; ++q) {
     double v = acc[q];

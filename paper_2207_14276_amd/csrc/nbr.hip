@@ -17,7 +17,8 @@ __global__ void k_ingest(const float *__restrict__ coords, const int *__restrict
                          const SysDesc *__restrict__ sys, Live n_sys_, Live N_, int S,
                          float4 *__restrict__ pos, int *__restrict__ sys_of,
                          AtomState *__restrict__ state, int *__restrict__ status,
-                         float *__restrict__ zero_forces, unsigned long long *__restrict__ zero_fix) {
+                         float *__restrict__ zero_forces, unsigned long long *__restrict__ zero_fix,
+                         int *__restrict__ wave_atom) {
   const int n_sys = n_sys_.get(), N = N_.get();
   // the systems' first atoms, staged in LDS when they fit: the search below
   // then waits on LDS instead of on a chain of dependent global loads
@@ -50,6 +51,7 @@ __global__ void k_ingest(const float *__restrict__ coords, const int *__restrict
   // skip empty systems that share the offset
   while (lo + 1 < n_sys && first_atom(lo + 1) <= i) ++lo;
   const SysDesc &d = sys[lo];
+  if (wave_atom) wave_atom[d.order_off + (i - d.atom_off)] = i;
   const float cx = coords[3 * i], cy = coords[3 * i + 1], cz = coords[3 * i + 2];
   float x = cx, y = cy, z = cz;
   AtomState &a = state[d.state_off + (i - d.atom_off)];
@@ -87,10 +89,10 @@ __global__ void k_ingest(const float *__restrict__ coords, const int *__restrict
 void launch_ingest(const float *coords, const int *species, const unsigned char *mask,
                    const SysDesc *sys, Live n_sys, Live N, int S, float4 *pos, int *sys_of,
                    AtomState *state, int *status, float *zero_forces, unsigned long long *zero_fix,
-                   hipStream_t st) {
+                   int *wave_atom, hipStream_t st) {
   if (N.v <= 0) return;
   k_ingest<<<(N.v + 255) / 256, 256, 0, st>>>(coords, species, mask, sys, n_sys, N, S, pos, sys_of,
-                                            state, status, zero_forces, zero_fix);
+                                            state, status, zero_forces, zero_fix, wave_atom);
 }
 
 // One wave per system: a system that keeps its neighbour list is rebuilt
@@ -584,13 +586,15 @@ void launch_nbr_build(const float4 *pos, const int *sys_of, const SysDesc *sys, 
 constexpr int kBucketBlock = 1024;
 
 __global__ void __launch_bounds__(kBucketBlock)
-k_species_count(const float4 *__restrict__ pos, Live N_, int S, int *__restrict__ block_counts) {
+k_species_count(const float4 *__restrict__ pos, const int *__restrict__ wave_atom, Live N_, int S,
+                int *__restrict__ block_counts) {
   __shared__ int cnt[kMaxSpecies];
   const int N = N_.get();
   if (threadIdx.x < kMaxSpecies) cnt[threadIdx.x] = 0;
   __syncthreads();
-  int i = blockIdx.x * kBucketBlock + threadIdx.x;
-  if (i < N) {
+  const int w = blockIdx.x * kBucketBlock + threadIdx.x;
+  if (w < N) {
+    const int i = wave_atom ? wave_atom[w] : w;
     const int s = __float_as_int(pos[i].w);
     if (s >= 0) atomicAdd(&cnt[s], 1);   // slot -1: outside the caller's mask
   }
@@ -666,14 +670,15 @@ k_species_scan(int *__restrict__ block_counts, int n_blocks, int S, int *__restr
 }
 
 __global__ void __launch_bounds__(kBucketBlock)
-k_species_scatter(const float4 *__restrict__ pos, Live N_, const int *__restrict__ block_base,
-                  const int *__restrict__ bucket_off, int *__restrict__ perm,
+k_species_scatter(const float4 *__restrict__ pos, const int *__restrict__ wave_atom, Live N_,
+                  const int *__restrict__ block_base, const int *__restrict__ bucket_off, int *__restrict__ perm,
                   int *__restrict__ row_of_atom) {
   const int N = N_.get();
   __shared__ int wave_cnt[kBucketBlock / kWave][kMaxSpecies];
-  int i = blockIdx.x * kBucketBlock + threadIdx.x;
+  const int t = blockIdx.x * kBucketBlock + threadIdx.x;
+  const int i = wave_atom && t < N ? wave_atom[t] : t;
   int w = threadIdx.x / kWave;
-  int s = i < N ? __float_as_int(pos[i].w) : -1;
+  int s = t < N ? __float_as_int(pos[i].w) : -1;
   int rank_in_wave = 0;
   for (int q = 0; q < kMaxSpecies; ++q) {
     unsigned long long m = __ballot(s == q);
@@ -689,21 +694,21 @@ k_species_scatter(const float4 *__restrict__ pos, Live N_, const int *__restrict
     int row = bucket_off[s] + block_base[blockIdx.x * kMaxSpecies + s] + before + rank_in_wave;
     perm[row] = i;
     row_of_atom[i] = row;
-  } else if (i < N) {
+  } else if (t < N) {
     row_of_atom[i] = -1;   // no network row: the AEV kernels skip the atom
   }
 }
 
-void launch_species_bucket(const float4 *pos, Live N, int S, int *block_counts, int n_blocks,
-                           int *bucket_off, int *bucket_cnt, int *perm, int *row_of_atom,
+void launch_species_bucket(const float4 *pos, const int *wave_atom, Live N, int S, int *block_counts,
+                           int n_blocks, int *bucket_off, int *bucket_cnt, int *perm, int *row_of_atom,
                            int rows_cap, hipStream_t st) {
   (void)rows_cap;
   // blocks past the live atoms (launches sized for more) count zeros
-  if (N.v > 0) k_species_count<<<n_blocks, kBucketBlock, 0, st>>>(pos, N, S, block_counts);
+  if (N.v > 0) k_species_count<<<n_blocks, kBucketBlock, 0, st>>>(pos, wave_atom, N, S, block_counts);
   k_species_scan<<<1, 256, 0, st>>>(block_counts, N.v > 0 ? n_blocks : 0, S, bucket_off,
                                     bucket_cnt, perm);
   if (N.v > 0)
-    k_species_scatter<<<n_blocks, kBucketBlock, 0, st>>>(pos, N, block_counts, bucket_off, perm,
+    k_species_scatter<<<n_blocks, kBucketBlock, 0, st>>>(pos, wave_atom, N, block_counts, bucket_off, perm,
                                                          row_of_atom);
 }
 
