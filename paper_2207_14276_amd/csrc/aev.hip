@@ -174,14 +174,18 @@ __device__ inline void unrank(int u, int ns, float r2, int oxy, int &ax, int &ay
 // One neighbour entry of a centre: the atom (index within the system's
 // records at j0), its species and the vector d (R in w); false for an entry
 // past the row or whose stored atom index is not below n_sys (a reused list
-// applied to a different system), which is never dereferenced.
+// applied to a different system), which is never dereferenced.  self >= 0:
+// no list; entry e is the system's atom e (n = n_sys), the centre (local
+// index self) excluded.
 __device__ __attribute__((always_inline)) inline bool load_entry(int e, int n, const int2 *__restrict__ ent,
-                                                                 int j0, int n_sys, const float4 *__restrict__ pos,
+                                                                 int self, int j0, int n_sys,
+                                                                 const float4 *__restrict__ pos,
                                                                  const float4 &pi, const float L[3], int &sj, int &j,
                                                                  float4 &d) {
   int2 en = make_int2(0, 0);
-  if (e < n) en = ent[e];
-  const bool v = e < n && (unsigned)en.x < (unsigned)n_sys;
+  if (self >= 0) en = make_int2(e, pack_image(0, 0, 0));
+  else if (e < n) en = ent[e];
+  const bool v = e < n && (unsigned)en.x < (unsigned)n_sys && en.x != self;
   sj = -1;
   j = 0;
   d = make_float4(0.f, 0.f, 0.f, 1e30f);
@@ -195,7 +199,9 @@ __device__ __attribute__((always_inline)) inline bool load_entry(int e, int n, c
 }
 
 // Builds the species-sorted radial list (R < rc_r) and angular list
-// (R < rc_a, a subset) of centre i in LDS.  Two passes over the entries:
+// (R < rc_a, a subset) of centre i in LDS from its neighbour row, or (self
+// >= 0) from all atoms of its system, keeping those a list would hold (R^2
+// below rc_r^2 as the list build tests it).  Two passes over the entries:
 // per-species counts by ballot, then placement.  Rows of up to 128 entries
 // (the common case) are loaded once and kept in registers for both passes;
 // longer rows are loaded again.  Per-species tallies live in registers
@@ -203,16 +209,17 @@ __device__ __attribute__((always_inline)) inline bool load_entry(int e, int n, c
 // entry in a chunk are skipped) and the wave-uniform result is published
 // in LDS.
 template <bool BWD>
-__device__ inline void fill_lists(int lane, int n, const int2 *__restrict__ ent, int j0, int n_sys,
+__device__ inline void fill_lists(int lane, int n, const int2 *__restrict__ ent, int self, int j0, int n_sys,
                                   const float4 *__restrict__ pos, const float4 &pi,
                                   const float L[3], const AevConst &c, WaveLds &w) {
   const int S = c.S;
   const bool cached = n <= 2 * kWave;  // wave-uniform
+  const float rc2 = c.rc_r * c.rc_r;
   int sj0 = -1, sj1 = -1, jj0 = 0, jj1 = 0;
   float4 d0 = make_float4(0.f, 0.f, 0.f, 1e30f), d1 = d0;
   if (cached) {
-    load_entry(lane, n, ent, j0, n_sys, pos, pi, L, sj0, jj0, d0);
-    if (n > kWave) load_entry(kWave + lane, n, ent, j0, n_sys, pos, pi, L, sj1, jj1, d1);
+    load_entry(lane, n, ent, self, j0, n_sys, pos, pi, L, sj0, jj0, d0);
+    if (n > kWave) load_entry(kWave + lane, n, ent, self, j0, n_sys, pos, pi, L, sj1, jj1, d1);
   }
   int cR[kMaxSpecies], cA[kMaxSpecies];
 #pragma unroll
@@ -226,9 +233,10 @@ __device__ inline void fill_lists(int lane, int n, const int2 *__restrict__ ent,
       j = first ? jj0 : jj1;
       d = first ? d0 : d1;
     } else {
-      load_entry(b + lane, n, ent, j0, n_sys, pos, pi, L, sj, j, d);
+      load_entry(b + lane, n, ent, self, j0, n_sys, pos, pi, L, sj, j, d);
     }
-    const bool inR = sj >= 0 && d.w < c.rc_r, inA = sj >= 0 && d.w < c.rc_a;
+    const bool inR = sj >= 0 && d.w < c.rc_r && (self < 0 || d.x * d.x + d.y * d.y + d.z * d.z < rc2),
+               inA = inR && d.w < c.rc_a;
 #pragma unroll
     for (int s = 0; s < kMaxSpecies; ++s) {
       cR[s] += __popcll(__ballot(inR && sj == s));
@@ -262,9 +270,10 @@ __device__ inline void fill_lists(int lane, int n, const int2 *__restrict__ ent,
       j = first ? jj0 : jj1;
       d = first ? d0 : d1;
     } else {
-      load_entry(b + lane, n, ent, j0, n_sys, pos, pi, L, sj, j, d);
+      load_entry(b + lane, n, ent, self, j0, n_sys, pos, pi, L, sj, j, d);
     }
-    const bool inR = sj >= 0 && d.w < c.rc_r, inA = sj >= 0 && d.w < c.rc_a;
+    const bool inR = sj >= 0 && d.w < c.rc_r && (self < 0 || d.x * d.x + d.y * d.y + d.z * d.z < rc2),
+               inA = inR && d.w < c.rc_a;
     // slots of this lane's entry in the two lists (selects per species;
     // the stores below are then issued once, not once per species)
     int q = 0, qa = 0;
@@ -364,7 +373,7 @@ k_aev_fwd(const float4 *__restrict__ pos, const int *__restrict__ sys_of,
           const SysDesc *__restrict__ sys, const int2 *__restrict__ nbr,
           const int *__restrict__ nbr_cnt, int cap, const int *__restrict__ row_of_atom,
           void *__restrict__ G, int ldg, unsigned long long *__restrict__ row_mask,
-          const int *__restrict__ wave_atom, Live N_, AevConst c) {
+          const int *__restrict__ wave_atom, int *__restrict__ status, Live N_, AevConst c) {
   extern __shared__ float4 lds4[];
   const int N = N_.get();
   // the wave index is uniform across the wave: keep it (and the centre's
@@ -377,21 +386,34 @@ k_aev_fwd(const float4 *__restrict__ pos, const int *__restrict__ sys_of,
   WaveLds w = carve<false>((char *)lds4 + wave * wave_lds_bytes<false>(cap), cap);
   float4 pi = make_float4(0.f, 0.f, 0.f, 0.f);
   float L[3] = {0.f, 0.f, 0.f};
-  int n = 0, j0 = 0, n_sys = 0;
+  int n = 0, j0 = 0, n_sys = 0, self = -1;
   const int2 *row = nbr;
   if (live) {
     const SysDesc &d = sys[sys_of[i]];
     n_sys = d.n;
-    n = min(nbr_cnt[d.state_off + (i - d.atom_off)], cap);
     pi = pos[i];
     L[0] = d.L[0]; L[1] = d.L[1]; L[2] = d.L[2];
     j0 = d.atom_off;
-    row = nbr + nbr_row(d, i, cap);
+    if (nbr) {
+      n = min(nbr_cnt[d.state_off + (i - d.atom_off)], cap);
+      row = nbr + nbr_row(d, i, cap);
+    } else {
+      n = n_sys;  // no list: the system's atoms
+      self = i - d.atom_off;
+    }
   }
-  fill_lists<false>(lane, n, row, j0, n_sys, pos, pi, L, c, w);
+  fill_lists<false>(lane, n, row, self, j0, n_sys, pos, pi, L, c, w);
   __syncthreads();
   if (!live) return;
   const Lists &ls = *w.ls;
+  // without a list, the largest neighbour count (what the list build
+  // records) goes to status[1]: the current value is read here and compared
+  // at the end, so that the wave does not wait for it
+  int nb_cnt = 0, nb_max = 0;
+  if (status) {
+    for (int s = 0; s < c.S; ++s) nb_cnt += ls.cR[s];
+    nb_max = __hip_atomic_load(status + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
   const int r_i = row_of_atom[i];
   void *Grow = (char *)G + (size_t)r_i * ldg * (BF16 ? 2 : 4);
 
@@ -568,6 +590,7 @@ k_aev_fwd(const float4 *__restrict__ pos, const int *__restrict__ sys_of,
       }
     }
   }
+  if (status && lane == 0 && nb_cnt > nb_max) atomicMax(status + 1, nb_cnt);
 }
 
 // Where the force contributions of a centre go.  Forces accumulate in 64-bit
@@ -654,12 +677,14 @@ __device__ inline void bwd_centre(int i, int lane, const float4 *__restrict__ po
   }
   const SysDesc &d = sys[sys_of[i]];
   const int n_sys = d.n;
-  const int n = min(nbr_cnt[d.state_off + (i - d.atom_off)], cap);
+  // no list (nbr null): the system's atoms
+  const int n = nbr ? min(nbr_cnt[d.state_off + (i - d.atom_off)], cap) : n_sys;
+  const int self = nbr ? -1 : i - d.atom_off;
   const float4 pi = pos[i];
   const float L[3] = {d.L[0], d.L[1], d.L[2]};
   const int j0 = d.atom_off;
-  const int2 *row = nbr + nbr_row(d, i, cap);
-  fill_lists<true>(lane, n, row, j0, n_sys, pos, pi, L, c, w);
+  const int2 *row = nbr ? nbr + nbr_row(d, i, cap) : nbr;
+  fill_lists<true>(lane, n, row, self, j0, n_sys, pos, pi, L, c, w);
   wave_lds_sync();
   const Lists &ls = *w.ls;
   const float *g = dG + (size_t)r_i * ldg;
@@ -1010,33 +1035,33 @@ static int waves_for_cap(int cap, int pref) {
 template <bool BF16>
 static void aev_fwd_t(const float4 *pos, const int *sys_of, const SysDesc *sys, const int2 *nbr,
                       const int *nbr_cnt, int cap, const int *row_of_atom, void *G, int ldg,
-                      unsigned long long *row_mask, const int *wave_atom, Live N, const AevConst &c, int wpb_pref,
-                      hipStream_t st) {
+                      unsigned long long *row_mask, const int *wave_atom, int *status, Live N, const AevConst &c,
+                      int wpb_pref, hipStream_t st) {
   int wpb = waves_for_cap<false>(cap, wpb_pref);
   size_t lds = wave_lds_bytes<false>(cap) * wpb;
   unsigned grid = (unsigned)((N.v + wpb - 1) / wpb);
   if (wpb == 4)
     k_aev_fwd<4, BF16><<<grid, 4 * kWave, lds, st>>>(pos, sys_of, sys, nbr, nbr_cnt, cap, row_of_atom, G, ldg,
-                                                     row_mask, wave_atom, N, c);
+                                                     row_mask, wave_atom, status, N, c);
   else if (wpb == 2)
     k_aev_fwd<2, BF16><<<grid, 2 * kWave, lds, st>>>(pos, sys_of, sys, nbr, nbr_cnt, cap, row_of_atom, G, ldg,
-                                                     row_mask, wave_atom, N, c);
+                                                     row_mask, wave_atom, status, N, c);
   else
     k_aev_fwd<1, BF16><<<grid, kWave, lds, st>>>(pos, sys_of, sys, nbr, nbr_cnt, cap, row_of_atom, G, ldg,
-                                                 row_mask, wave_atom, N, c);
+                                                 row_mask, wave_atom, status, N, c);
 }
 
 void launch_aev_fwd(const float4 *pos, const int *sys_of, const SysDesc *sys, const int2 *nbr,
                     const int *nbr_cnt, int cap, const int *row_of_atom, void *G, bool g_bf16,
                     int ldg, Live N, const AevConst &c, unsigned long long *row_mask, const int *wave_atom,
-                    int wpb_pref, hipStream_t st) {
+                    int *status, int wpb_pref, hipStream_t st) {
   if (N.v <= 0) return;
   if (g_bf16)
-    aev_fwd_t<true>(pos, sys_of, sys, nbr, nbr_cnt, cap, row_of_atom, G, ldg, row_mask, wave_atom, N, c, wpb_pref,
-                    st);
+    aev_fwd_t<true>(pos, sys_of, sys, nbr, nbr_cnt, cap, row_of_atom, G, ldg, row_mask, wave_atom, status, N, c,
+                    wpb_pref, st);
   else
-    aev_fwd_t<false>(pos, sys_of, sys, nbr, nbr_cnt, cap, row_of_atom, G, ldg, row_mask, wave_atom, N, c, wpb_pref,
-                     st);
+    aev_fwd_t<false>(pos, sys_of, sys, nbr, nbr_cnt, cap, row_of_atom, G, ldg, row_mask, wave_atom, status, N, c,
+                     wpb_pref, st);
 }
 
 template <int WPB>

@@ -1062,6 +1062,12 @@ static int run(nnp_model *m, int n_sys, const int64_t *offs, const float *coords
   // every system small and without a box: a direct scan per system
   bool all_small = !pairs && N > 0;
   for (int s = 0; s < n_sys && all_small; ++s) all_small = !sd[s].periodic && sd[s].n <= kSmallSystem;
+  // and without a persistent list, no system larger than the capacity
+  // allows (cap neighbours): the AEV kernels scan each centre's system
+  // themselves, and no neighbour list is built
+  int max_n = 0;
+  for (int s = 0; s < n_sys; ++s) max_n = std::max(max_n, sd[s].n);
+  const bool direct = all_small && !nl && m->kind == kDescAev && mode != kNbr && max_n - 1 <= cap;
   // centre groups of the AEV backward's per-system form: consecutive centres
   // of one system, the systems in order of decreasing size (the costliest
   // groups start first)
@@ -1221,7 +1227,8 @@ static int run(nnp_model *m, int n_sys, const int64_t *offs, const float *coords
                            pool_nbr, pool_cnt, status, st);
     } else if (all_small) {
       mark();
-      launch_nbr_small(pos, m->sys_of.as<int>(), dsys, lN, rc_list, cap, pool_nbr, pool_cnt, status, st);
+      if (!direct)
+        launch_nbr_small(pos, m->sys_of.as<int>(), dsys, lN, rc_list, cap, pool_nbr, pool_cnt, status, st);
     } else {
       launch_grid(dsys, lS, pos, m->cell_count.as<int>(), rc_list, st);
       launch_cell_count(pos, m->sys_of.as<int>(), dsys, lN, m->cell_count.as<int>(), m->atom_cell.as<int>(),
@@ -1266,8 +1273,9 @@ static int run(nnp_model *m, int n_sys, const int64_t *offs, const float *coords
         launch_dp_fwd(pos, coords, pool_state, m->sys_of.as<int>(), dsys, pool_nbr, pool_cnt, cap,
                       m->row_of_atom.as<int>(), Gp, g_bf16, ldg, N, m->dp, rec, wpb, st);
       else
-        launch_aev_fwd(pos, m->sys_of.as<int>(), dsys, pool_nbr, pool_cnt, cap, m->row_of_atom.as<int>(), Gp,
-                       g_bf16, ldg, lN, m->aev, tm, wave_atom, wpb, st);
+        launch_aev_fwd(pos, m->sys_of.as<int>(), dsys, direct ? nullptr : pool_nbr, pool_cnt, cap,
+                       m->row_of_atom.as<int>(), Gp, g_bf16, ldg, lN, m->aev, tm, wave_atom,
+                       direct ? status : nullptr, wpb, st);
     };
     if (mode == kAev) {
       descriptor(m->dG.p, false, D, nullptr, nullptr, 0);
@@ -1444,7 +1452,7 @@ static int run(nnp_model *m, int n_sys, const int64_t *offs, const float *coords
           gp.n_cells = (int)C_l;
           if (graph) gp.live_cells = &live->n_cells;
         }
-        launch_aev_bwd(pos, m->sys_of.as<int>(), dsys, pool_nbr, pool_cnt, cap,
+        launch_aev_bwd(pos, m->sys_of.as<int>(), dsys, direct ? nullptr : pool_nbr, pool_cnt, cap,
                        m->row_of_atom.as<int>(), m->dG.as<float>(), D, lN, m->aev, Ffix,
                        m->W_atom.as<float>(), gp, m->tune_val[kSiteAevBwd], m->max_lds, st);
       }

@@ -293,10 +293,13 @@ void launch_dp_bwd(const SysDesc *sys, int n_sys, bool small_systems, const int 
 // S + 2 p + 1); every other half of the row is written as zeros.
 // wave_atom (nullable): the centre of wave w (the ingest's launch order, the
 // costliest systems first, so that no long centre starts last); else w.
+// nbr null: no neighbour list; each centre takes the atoms of its system
+// (small non-periodic systems of at most cap + 1 atoms) and records its
+// neighbour count as the list build would, largest in status[1] (nullable).
 void launch_aev_fwd(const float4 *pos, const int *sys_of, const SysDesc *sys, const int2 *nbr,
                     const int *nbr_cnt, int cap, const int *row_of_atom, void *G, bool g_bf16,
                     int ldg, Live N, const AevConst &c, unsigned long long *row_mask, const int *wave_atom,
-                    int wpb_pref, hipStream_t st);
+                    int *status, int wpb_pref, hipStream_t st);
 // How the AEV backward groups its centres (at most one of the two forms):
 // groups[n_groups] = {first centre, count} of consecutive centres of one
 // small non-periodic system (max_sys_atoms: the largest such system), or the
@@ -312,6 +315,7 @@ struct AevBwdGroups {
   const int *wave_atom = nullptr;  // one wave per centre: the centre of wave w (nullable: w)
 };
 // Forces go into Ffix [N][3] (64-bit fixed point, cleared by the caller).
+// nbr null: no neighbour list (as for launch_aev_fwd).
 void launch_aev_bwd(const float4 *pos, const int *sys_of, const SysDesc *sys, const int2 *nbr,
                     const int *nbr_cnt, int cap, const int *row_of_atom, const float *dG,
                     int ldg, Live N, const AevConst &c, unsigned long long *Ffix, float *W_atom,
