@@ -699,12 +699,83 @@ k_species_scatter(const float4 *__restrict__ pos, const int *__restrict__ wave_a
   }
 }
 
+// Calls of at most kPlaceBlocks bucketing blocks skip the scan kernel: each
+// scatter workgroup sums the per-block counts itself (one count per thread,
+// LDS atomics) into the species totals and its own offsets, and workgroup 0
+// publishes the bucket offsets and clears the padding rows.
+constexpr int kPlaceBlocks = 128;
+
+__global__ void __launch_bounds__(kBucketBlock)
+k_species_place(const float4 *__restrict__ pos, const int *__restrict__ wave_atom, Live N_,
+                const int *__restrict__ block_counts, int n_blocks, int S, int *__restrict__ bucket_off,
+                int *__restrict__ bucket_cnt, int *__restrict__ perm, int *__restrict__ row_of_atom) {
+  const int N = N_.get();
+  __shared__ int tot[kMaxSpecies], before_blk[kMaxSpecies], off[kMaxSpecies + 1];
+  __shared__ int wave_cnt[kBucketBlock / kWave][kMaxSpecies];
+  if (threadIdx.x < kMaxSpecies) {
+    tot[threadIdx.x] = 0;
+    before_blk[threadIdx.x] = 0;
+  }
+  __syncthreads();
+  // the counts of every block: species totals and this block's base
+  for (int k = threadIdx.x; k < n_blocks * kMaxSpecies; k += blockDim.x) {
+    const int b = k / kMaxSpecies, sp = k - b * kMaxSpecies;
+    const int c = block_counts[k];
+    if (c) {
+      atomicAdd(&tot[sp], c);
+      if (b < (int)blockIdx.x) atomicAdd(&before_blk[sp], c);
+    }
+  }
+  const int t = blockIdx.x * kBucketBlock + threadIdx.x;
+  const int i = wave_atom && t < N ? wave_atom[t] : t;
+  const int w = threadIdx.x / kWave;
+  const int s = t < N ? __float_as_int(pos[i].w) : -1;
+  int rank_in_wave = 0;
+  for (int q = 0; q < kMaxSpecies; ++q) {
+    unsigned long long m = __ballot(s == q);
+    if (s == q)
+      rank_in_wave = __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
+                                               __builtin_amdgcn_mbcnt_lo((unsigned)m, 0));
+    if ((threadIdx.x & (kWave - 1)) == 0) wave_cnt[w][q] = __popcll(m);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int o = 0;
+    for (int q = 0; q < S; ++q) {
+      off[q] = o;
+      o += (tot[q] + kTileM - 1) / kTileM * kTileM;
+    }
+    off[S] = o;
+  }
+  __syncthreads();
+  if (blockIdx.x == 0) {
+    if (threadIdx.x <= S) bucket_off[threadIdx.x] = off[threadIdx.x];
+    if (threadIdx.x < S) bucket_cnt[threadIdx.x] = tot[threadIdx.x];
+    for (int q = 0; q < S; ++q)
+      for (int r = off[q] + tot[q] + threadIdx.x; r < off[q + 1]; r += blockDim.x) perm[r] = -1;
+  }
+  if (s >= 0) {
+    int before = 0;
+    for (int v = 0; v < w; ++v) before += wave_cnt[v][s];
+    const int row = off[s] + before_blk[s] + before + rank_in_wave;
+    perm[row] = i;
+    row_of_atom[i] = row;
+  } else if (t < N) {
+    row_of_atom[i] = -1;   // no network row: the AEV kernels skip the atom
+  }
+}
+
 void launch_species_bucket(const float4 *pos, const int *wave_atom, Live N, int S, int *block_counts,
                            int n_blocks, int *bucket_off, int *bucket_cnt, int *perm, int *row_of_atom,
                            int rows_cap, hipStream_t st) {
   (void)rows_cap;
   // blocks past the live atoms (launches sized for more) count zeros
   if (N.v > 0) k_species_count<<<n_blocks, kBucketBlock, 0, st>>>(pos, wave_atom, N, S, block_counts);
+  if (N.v > 0 && n_blocks <= kPlaceBlocks) {
+    k_species_place<<<n_blocks, kBucketBlock, 0, st>>>(pos, wave_atom, N, block_counts, n_blocks, S, bucket_off,
+                                                       bucket_cnt, perm, row_of_atom);
+    return;
+  }
   k_species_scan<<<1, 256, 0, st>>>(block_counts, N.v > 0 ? n_blocks : 0, S, bucket_off,
                                     bucket_cnt, perm);
   if (N.v > 0)
