@@ -516,11 +516,15 @@ const char *nnp_last_error(void);
  * nnp_set_timing(model, 1) turns it on and clears what was recorded; every
  * later nnp_energy_forces / nnp_energy_forces_nlist call records one set of
  * stage-boundary events (up to 4096 calls between two reads; calls beyond
- * that are not timed).  nnp_stage_timings waits for the last recorded call,
- * writes up to n stage durations in ms, each the mean over the calls recorded
- * since the previous read, with the stage names (static strings), clears the
- * record and returns the number of stages (0 when nothing was recorded).
- * The recording adds no wait to the calls themselves. */
+ * that are not timed).  nnp_set_timing(model, 2 + s) records only the two
+ * events around stage s (each event costs a few microseconds of device time,
+ * so timing one stage disturbs the calls least); 0 turns timing off; other
+ * values give NNP_EINVAL.  nnp_stage_timings waits for the last recorded
+ * call, writes up to n stage durations in ms, each the mean over the calls
+ * recorded since the previous read (-1 for stages not recorded), with the
+ * stage names (static strings), clears the record and returns the number of
+ * stages (0 when nothing was recorded).  The recording adds no wait to the
+ * calls themselves. */
 int nnp_set_timing(nnp_model *model, int enable);
 int nnp_stage_timings(nnp_model *model, float *ms_out, const char **names_out, int n);
 

@@ -156,6 +156,7 @@ struct nnp_model {
   hipEvent_t tune_ev[kTuneSites][2] = {};
   // timing: one set of stage-boundary events per timed call, kept until read
   bool timing = false;
+  int timed_stage = -1;  // >= 0: only this stage's two boundary events are recorded
   std::vector<std::array<hipEvent_t, kStages + 1>> evsets;
   int ev_used = 0;       // sets recorded since the last read
   int last_stages = 0;
@@ -770,7 +771,9 @@ constexpr int kTimedSetsAhead = 64;
 
 extern "C" int nnp_set_timing(nnp_model *m, int enable) {
   if (!m) return fail(NNP_EINVAL, "null model");
+  if (enable < 0 || enable >= 2 + kStages) return fail(NNP_EINVAL, "timing mode %d: 0, 1 or 2 + a stage index", enable);
   m->timing = enable != 0;
+  m->timed_stage = enable >= 2 ? enable - 2 : -1;
   m->ev_used = 0;
   m->last_stages = 0;
   if (m->timing) {
@@ -801,8 +804,15 @@ extern "C" int nnp_stage_timings(nnp_model *m, float *ms, const char **names, in
   if (!m->timing || m->last_stages == 0 || m->ev_used == 0) return 0;
   const int k = std::min(n, m->last_stages);
   const int used = m->ev_used;
-  HIP_TRY(hipEventSynchronize(m->evsets[used - 1][m->last_stages]));
+  const int ts = m->timed_stage;
+  if (ts >= m->last_stages) return fail(NNP_EINVAL, "the timed stage is past the calls' stages");
+  HIP_TRY(hipEventSynchronize(m->evsets[used - 1][ts >= 0 ? ts + 1 : m->last_stages]));
   for (int q = 0; q < k; ++q) {
+    if (names) names[q] = kStageNames[q];
+    if (ts >= 0 && q != ts) {  // not recorded
+      if (ms) ms[q] = -1.f;
+      continue;
+    }
     double acc = 0.0;
     for (int c = 0; c < used; ++c) {
       float t = 0.f;
@@ -810,7 +820,6 @@ extern "C" int nnp_stage_timings(nnp_model *m, float *ms, const char **names, in
       acc += t;
     }
     if (ms) ms[q] = (float)(acc / used);
-    if (names) names[q] = kStageNames[q];
   }
   m->ev_used = 0;
   return k;
@@ -1186,8 +1195,14 @@ static int run(nnp_model *m, int n_sys, const int64_t *offs, const float *coords
       rc = next_evset(m, &ev);
       if (rc) return rc;
     }
+    // stage boundary b: recorded when every stage is timed, or when b opens
+    // or closes the one timed stage
     auto mark = [&]() {
-      if (ev) (void)hipEventRecord(ev[stage++], st);
+      if (ev) {
+        const int ts = m->timed_stage;
+        if (ts < 0 || stage == ts || stage == ts + 1) (void)hipEventRecord(ev[stage], st);
+        ++stage;
+      }
     };
     // per-site events while tuning (every site launches at most once per call)
     const bool tuning = m->tuning && mode == kFull;

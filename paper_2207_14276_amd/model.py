@@ -258,14 +258,19 @@ class NNPModel:
                 _stream_handle(self.device)))
         return cnt, ent
 
-    def set_timing(self, on: bool = True):
-        nat.check(nat.load().nnp_set_timing(self._h, 1 if on else 0))
+    STAGES = ("ingest", "cells", "neighbours", "buckets", "aev_fwd", "mlp", "aev_bwd", "reduce")
+
+    def set_timing(self, on: bool = True, stage: str = None):
+        """Stage timing on (every stage, or only `stage`, by its name) or off."""
+        mode = 0 if not on else (1 if stage is None else 2 + self.STAGES.index(stage))
+        nat.check(nat.load().nnp_set_timing(self._h, mode))
 
     def stage_timings(self) -> dict:
+        """Mean ms per recorded call of each recorded stage."""
         ms = (C.c_float * 16)()
         names = (C.c_char_p * 16)()
         k = nat.check(nat.load().nnp_stage_timings(self._h, ms, names, 16))
-        return {names[q].decode(): float(ms[q]) for q in range(k)}
+        return {names[q].decode(): float(ms[q]) for q in range(k) if ms[q] >= 0.0}
 
 
 class NeighborPool:

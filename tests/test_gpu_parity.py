@@ -369,6 +369,25 @@ def test_system_order_changes_no_result(m32, m16, prec):
     log(f"[system order {prec}] 40 systems permuted: energies, forces and virials equal bit for bit")
 
 
+def test_stage_timing_modes(m16):
+    """Stage timing: every stage boundary, or only the two events around one
+    stage (the others reported as not recorded); results unchanged."""
+    b = synth.ragged_solutes(12, seed=7)
+    ref = run_gpu(m16, b)
+    m16.set_timing(True)
+    got = run_gpu(m16, b)
+    all_stages = m16.stage_timings()
+    m16.set_timing(True, stage="aev_bwd")
+    run_gpu(m16, b)
+    run_gpu(m16, b)
+    one = m16.stage_timings()
+    m16.set_timing(False)
+    log(f"[timing] all stages {all_stages}; aev_bwd alone {one}")
+    assert list(all_stages) == list(m16.STAGES) and all(v >= 0.0 for v in all_stages.values())
+    assert list(one) == ["aev_bwd"] and one["aev_bwd"] > 0.0
+    assert np.array_equal(got["forces"], ref["forces"])
+
+
 def test_edge_cases(m32, oracle_lib, om):
     """Empty systems, single atoms (no neighbours), one atom alone in a
     periodic box (self-images only), in one ragged batch."""
