@@ -1,9 +1,12 @@
 // Atomic environment vectors and their gradient (section "ANI models":
 // cosine cutoff, radial and angular symmetry functions).
 //
-// One wavefront per centre atom.  The centre's neighbour entries are
-// re-derived from the packed atom records and sorted by neighbour species into
-// LDS with wave ballots.  Then
+// One wavefront per centre atom; for calls of several systems the waves take
+// the centres of the largest systems first (wave_atom), so that no costly
+// centre starts last.  The centre's neighbour entries (its list row, or for
+// small systems without a list the atoms of its system) are re-derived from
+// the packed atom records and sorted by neighbour species into LDS with wave
+// ballots.  Then
 //   radial:  lanes = 16 radial shifts x 4 neighbour slots, one species block
 //            at a time, reduced across the 4 slots with lane shuffles;
 //   angular (forward): the species-pair blocks in passes of 64 pair slots;
